@@ -1,0 +1,245 @@
+"""ctypes binding of the FP64 CPU oracle.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is a plain, slow, double-precision
+implementation of the matrix element method integration written from the
+paper (Schouten, DeAbreu, Stelzer, CPC 2014) and from the published
+methods it relies on (VEGAS, Philox).  It shares no code with the HIP
+library.  Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline
+leg may import it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+KIND_DY = 1
+KIND_TT = 2
+KIND_GENZ = 3
+NBINS = 64
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "sqrt_s", "m_t", "w_t", "m_w", "w_w", "alpha", "alpha_s", "g_fermi",
+        "sigma_k", "tf_sigma", "r_lo", "r_hi", "m_lo", "m_hi")]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("I", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("chi2dof", ctypes.c_double), ("n_iter_used", ctypes.c_int)]
+
+
+def dy_params(**kw):
+    """Drell-Yan configuration: sqrt(S) = 13 TeV, alpha = 1/137, 5% TF,
+    r window [1 - 5 sigma, 1 + 5 sigma], truth window 60-120 GeV."""
+    p = dict(sqrt_s=13000.0, m_t=172.5, w_t=1.4, m_w=80.4, w_w=2.1,
+             alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
+             sigma_k=20.0, tf_sigma=0.05, r_lo=0.75, r_hi=1.25,
+             m_lo=60.0, m_hi=120.0)
+    p.update(kw)
+    return Params(**p)
+
+
+def tt_params(**kw):
+    """ttbar dilepton configuration: t (172.5, 1.4), W (80.4, 2.1), b-jet
+    Gaussian TF 15 %, r window [0.25, 1.75], recoil sigma 20 GeV."""
+    p = dict(sqrt_s=13000.0, m_t=172.5, w_t=1.4, m_w=80.4, w_w=2.1,
+             alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
+             sigma_k=20.0, tf_sigma=0.15, r_lo=0.25, r_hi=1.75,
+             m_lo=0.0, m_hi=0.0)
+    p.update(kw)
+    return Params(**p)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            _build.build()
+        _LIB = ctypes.CDLL(path)
+        _declare(_LIB)
+    return _LIB
+
+
+def _declare(L):
+    D, I, U32, U64, I64, P = (ctypes.c_double, ctypes.c_int, ctypes.c_uint32,
+                              ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p)
+    sig = {
+        "or_philox4x32_10": (None, [P, P, P]),
+        "or_uniforms": (None, [U64, U32, U32, U32, U32, I, P]),
+        "or_vegas_map": (D, [P, I, P, P, P]),
+        "or_vegas_uniform_grid": (None, [P, I]),
+        "or_vegas_refine_dim": (None, [P, D, P]),
+        "or_xf_u": (D, [D]), "or_xf_d": (D, [D]), "or_xf_qbar": (D, [D]), "or_xf_g": (D, [D]),
+        "or_dy_integrand": (D, [P, P, P]),
+        "or_qq_mumu_me2": (D, [P, P, P, P, D, D]),
+        "or_dy_sigma_2d": (D, [P, I]),
+        "or_dy_sigma_tau": (D, [P, I]),
+        "or_tt_integrand": (D, [P, P, I, P, P]),
+        "or_solve_dilepton": (I, [P, P, P, P, D, D, D, D, D, D, P, P, P]),
+        "or_dilepton_residual": (None, [P, P, P, P, P, P, P]),
+        "or_tt_me2_gg": (D, [P, P, P, P]),
+        "or_tt_me2_qq": (D, [P, P, P, P]),
+        "or_gg_ttbar_prod": (D, [D, P, P, P, P]),
+        "or_qq_ttbar_prod": (D, [D, P, P, P, P]),
+        "or_gg_ttbar_ward": (D, [D, P, P, P, P]),
+        "or_top_decay_spinsum": (D, [D, P, P, P, P]),
+        "or_integrate_one": (None, [I, P, P, I, U64, U32, I64, I, D, P, P, P, P]),
+        "or_vegas_iteration": (None, [I, P, P, I, U64, U32, U32, I64, P, P, P, P]),
+        "or_weight_at": (D, [I, P, P, I, P, P]),
+        "or_integrate_events": (None, [I, P, P, I, I, U64, I64, I, D, D, P, P, P]),
+        "or_dims": (I, [I]), "or_nperm": (I, [I]),
+        "or_bw_map": (D, [D, D, D, D, D, P]),
+        "or_gauss_tf": (D, [D, D, D]),
+        "or_genz_integrand": (D, [P]),
+        "or_genz_exact": (D, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniforms(seed, k, it, event, perm, D):
+    u = np.zeros(D)
+    lib().or_uniforms(seed, k, it, event, perm, D, _ptr(u))
+    return u
+
+
+def uniform_grid(D):
+    g = np.zeros((D, NBINS + 1))
+    lib().or_vegas_uniform_grid(_ptr(g), D)
+    return g
+
+
+def vegas_map(grid, u):
+    grid = _f64(grid)
+    u = _f64(u)
+    D = grid.shape[0]
+    x = np.zeros(D)
+    bins = np.zeros(D, dtype=np.int32)
+    jac = lib().or_vegas_map(_ptr(grid), D, _ptr(u), _ptr(x), _ptr(bins))
+    return x, jac, bins
+
+
+def refine_dim(d, alpha, edges):
+    d = _f64(d)
+    e = _f64(edges).copy()
+    lib().or_vegas_refine_dim(_ptr(d), alpha, _ptr(e))
+    return e
+
+
+def dy_integrand(p, ev, x):
+    ev = _f64(ev)
+    x = _f64(x)
+    return lib().or_dy_integrand(ctypes.byref(p), _ptr(ev), _ptr(x))
+
+
+def tt_integrand(p, ev, perm, x):
+    ev = _f64(ev)
+    x = _f64(x)
+    ns = ctypes.c_int(0)
+    v = lib().or_tt_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
+    return v, ns.value
+
+
+def solve_dilepton(b, bb, lp, lm, met, q2):
+    b, bb, lp, lm = (_f64(a) for a in (b, bb, lp, lm))
+    nu = np.zeros(16)
+    nub = np.zeros(16)
+    det = np.zeros(4)
+    n = lib().or_solve_dilepton(_ptr(b), _ptr(bb), _ptr(lp), _ptr(lm), met[0], met[1],
+                                q2[0], q2[1], q2[2], q2[3], _ptr(nu), _ptr(nub), _ptr(det))
+    return nu[:4 * n].reshape(n, 4), nub[:4 * n].reshape(n, 4), det[:n]
+
+
+def dilepton_q2(b, bb, lp, lm, nu, nub):
+    arrs = [_f64(a) for a in (b, bb, lp, lm, nu, nub)]
+    out = np.zeros(4)
+    lib().or_dilepton_residual(*[_ptr(a) for a in arrs], _ptr(out))
+    return out
+
+
+def integrate_one(kind, p, ev, perm, seed, event_index, n_points, n_iter,
+                  alpha=1.5, grid=None):
+    ev = _f64(ev)
+    D = lib().or_dims(kind)
+    Is = np.zeros(n_iter)
+    Vs = np.zeros(n_iter)
+    g = None if grid is None else _f64(grid).copy()
+    r = Result()
+    lib().or_integrate_one(kind, ctypes.byref(p), _ptr(ev), perm, seed, event_index,
+                           n_points, n_iter, alpha, None if g is None else _ptr(g),
+                           _ptr(Is), _ptr(Vs), ctypes.byref(r))
+    return r, Is, Vs, g
+
+
+def vegas_iteration(kind, p, ev, perm, seed, event_index, it, n_points, grid):
+    ev = _f64(ev)
+    grid = _f64(grid)
+    D = grid.shape[0]
+    s1 = ctypes.c_double()
+    s2 = ctypes.c_double()
+    bins = np.zeros((D, NBINS))
+    lib().or_vegas_iteration(kind, ctypes.byref(p), _ptr(ev), perm, seed, event_index, it,
+                             n_points, _ptr(grid), ctypes.byref(s1), ctypes.byref(s2),
+                             _ptr(bins))
+    return s1.value, s2.value, bins
+
+
+def weight_at(kind, p, ev, perm, grid, u):
+    ev, grid, u = _f64(ev), _f64(grid), _f64(u)
+    return lib().or_weight_at(kind, ctypes.byref(p), _ptr(ev), perm, _ptr(grid), _ptr(u))
+
+
+def integrate_events(kind, p, events, seed, n_points, n_iter, alpha=1.5, sigma_norm=0.0):
+    ev = _f64(events)
+    n_events, n_obj = ev.shape[0], ev.shape[1]
+    P = np.zeros(n_events)
+    err = np.zeros(n_events)
+    st = np.zeros(n_events, dtype=np.int32)
+    lib().or_integrate_events(kind, ctypes.byref(p), _ptr(ev), n_events, n_obj, seed,
+                              n_points, n_iter, alpha, sigma_norm, _ptr(P), _ptr(err), _ptr(st))
+    return P, err, st
+
+
+def _vec(a):
+    return _f64(a)
+
+
+def call4(name, *args):
+    """call a function taking (double, p, p, p, p) or (p, p, p, p)"""
+    conv = []
+    keep = []
+    for a in args:
+        if isinstance(a, (float, int)):
+            conv.append(float(a))
+        elif isinstance(a, Params):
+            conv.append(ctypes.byref(a))
+        else:
+            arr = _f64(a)
+            keep.append(arr)
+            conv.append(_ptr(arr))
+    return getattr(lib(), name)(*conv)

@@ -1,0 +1,133 @@
+/*
+ * Oracle: the per-integral VEGAS loop and the per-event result.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Sec. 2: S_N = V (1/N) sum f(x_i) and its error V sigma_f / sqrt(N), with
+ * sigma_f read as the standard deviation (the printed bracket defines the
+ * variance).  Iterations are combined by inverse-variance weighting, the
+ * first one (uniform grid) discarded.  Sec. 3 / Sec. 4: the event density
+ * averages the integrals over the jet-parton assignments.
+ */
+#include "oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static double integrand(int kind, const or_params* p, const double* ev, int perm, const double* x)
+{
+  if (kind == OR_KIND_DY) return or_dy_integrand(p, ev, x);
+  if (kind == OR_KIND_GENZ) return or_genz_integrand(x);
+  return or_tt_integrand(p, ev, perm, x, NULL);
+}
+
+double or_weight_at(int kind, const or_params* p, const double* ev, int perm,
+                    const double* grid, const double* u)
+{
+  int D = or_dims(kind);
+  double x[16];
+  double jac = or_vegas_map(grid, D, u, x, NULL);
+  return integrand(kind, p, ev, perm, x) * jac;
+}
+
+void or_vegas_iteration(int kind, const or_params* p, const double* ev, int perm,
+                        uint64_t seed, uint32_t event_index, uint32_t iter,
+                        int64_t n_points, const double* grid,
+                        double* s1_out, double* s2_out, double* bins)
+{
+  int D = or_dims(kind);
+  double s1 = 0.0, s2 = 0.0;
+  memset(bins, 0, sizeof(double) * D * OR_NBINS);
+  for (int64_t k = 0; k < n_points; ++k) {
+    double u[16], x[16];
+    int bi[16];
+    or_uniforms(seed, (uint32_t)k, iter, event_index, (uint32_t)perm, D, u);
+    double jac = or_vegas_map(grid, D, u, x, bi);
+    double w = integrand(kind, p, ev, perm, x) * jac;
+    s1 += w;
+    s2 += w * w;
+    for (int d = 0; d < D; ++d) bins[d * OR_NBINS + bi[d]] += w * w;
+  }
+  *s1_out = s1;
+  *s2_out = s2;
+}
+
+void or_integrate_one(int kind, const or_params* p, const double* ev, int perm,
+                      uint64_t seed, uint32_t event_index, int64_t n_points,
+                      int n_iter, double alpha, double* grid_io,
+                      double* iter_I, double* iter_var, or_result* res)
+{
+  int D = or_dims(kind);
+  double* grid = (double*)malloc(sizeof(double) * D * (OR_NBINS + 1));
+  double* bins = (double*)malloc(sizeof(double) * D * OR_NBINS);
+  if (grid_io) memcpy(grid, grid_io, sizeof(double) * D * (OR_NBINS + 1));
+  else or_vegas_uniform_grid(grid, D);
+  double wsum = 0.0, wIsum = 0.0;
+  double* Is = (double*)malloc(sizeof(double) * (n_iter > 0 ? n_iter : 1));
+  double* Vs = (double*)malloc(sizeof(double) * (n_iter > 0 ? n_iter : 1));
+  for (int j = 0; j < n_iter; ++j) {
+    double s1, s2;
+    or_vegas_iteration(kind, p, ev, perm, seed, event_index, (uint32_t)j, n_points, grid, &s1, &s2, bins);
+    double N = (double)n_points;
+    double I = s1 / N;
+    double var = (s2 / N - I * I) / (N - 1.0);
+    if (var < 0.0) var = 0.0;
+    Is[j] = I; Vs[j] = var;
+    if (iter_I) iter_I[j] = I;
+    if (iter_var) iter_var[j] = var;
+    if (j >= 1 && var > 0.0) { wsum += 1.0 / var; wIsum += I / var; }
+    for (int d = 0; d < D; ++d)
+      or_vegas_refine_dim(bins + d * OR_NBINS, alpha, grid + d * (OR_NBINS + 1));
+  }
+  res->n_iter_used = n_iter;
+  if (wsum > 0.0) {
+    res->I = wIsum / wsum;
+    res->sigma = sqrt(1.0 / wsum);
+    double chi2 = 0.0;
+    int n = 0;
+    for (int j = 1; j < n_iter; ++j)
+      if (Vs[j] > 0.0) { chi2 += (Is[j] - res->I) * (Is[j] - res->I) / Vs[j]; ++n; }
+    res->chi2dof = n > 1 ? chi2 / (n - 1) : 0.0;
+  } else {
+    /* no iteration with a positive variance: every weight was equal (in
+     * practice, all zero) */
+    double m = 0.0;
+    int n = 0;
+    for (int j = 1; j < n_iter; ++j) { m += Is[j]; ++n; }
+    res->I = n ? m / n : (n_iter ? Is[0] : 0.0);
+    res->sigma = 0.0;
+    res->chi2dof = 0.0;
+  }
+  if (grid_io) memcpy(grid_io, grid, sizeof(double) * D * (OR_NBINS + 1));
+  free(grid); free(bins); free(Is); free(Vs);
+}
+
+void or_integrate_events(int kind, const or_params* p, const double* events,
+                         int n_events, int n_obj, uint64_t seed, int64_t n_points,
+                         int n_iter, double alpha, double sigma_norm,
+                         double* P, double* err, int32_t* status)
+{
+  int np = or_nperm(kind);
+  int64_t per = (n_points + np - 1) / np;   /* points per permutation */
+  int n_int = n_events * np;
+  or_result* r = (or_result*)malloc(sizeof(or_result) * (n_int > 0 ? n_int : 1));
+  #pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < n_int; ++i) {
+    int e = i / np, perm = i % np;
+    or_integrate_one(kind, p, events + (size_t)e * n_obj * 4, perm, seed, (uint32_t)e,
+                     per, n_iter, alpha, NULL, NULL, NULL, &r[i]);
+  }
+  double norm = sigma_norm > 0.0 ? 1.0 / sigma_norm : 1.0;
+  for (int e = 0; e < n_events; ++e) {
+    double s = 0.0, v = 0.0;
+    int bad = 0;
+    for (int k = 0; k < np; ++k) {
+      s += r[e * np + k].I;
+      v += r[e * np + k].sigma * r[e * np + k].sigma;
+      if (!isfinite(r[e * np + k].I)) bad = 1;
+    }
+    P[e] = norm * s / np;
+    err[e] = norm * sqrt(v) / np;
+    status[e] = bad ? 3 : (s == 0.0 ? 1 : 0);
+  }
+  free(r);
+}

@@ -1,0 +1,543 @@
+/*
+ * Oracle: phase-space maps, constraint solves and the two integrands.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Drell-Yan: Eq. mem_def with the n-body phase space below it, the TF
+ * convolution of Eq. 3 and a Gaussian momentum TF (Sec. 1).
+ * ttbar dilepton: Eq. integrand of Sec. 3 with the change of variables to
+ * the top and W propagator virtualities, Eq. dilepsolv, and the per-point
+ * missing transverse momentum of Sec. 4 (extended by a transverse recoil).
+ */
+#include "oracle.h"
+#include <math.h>
+#include <string.h>
+
+static double mdot(const double* a, const double* b)
+{
+  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+static double norm3(const double* p) { return sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]); }
+
+/* -------------------------------------------------------- toy densities -- */
+double or_xf_u(double x) { return 2.0 * sqrt(x) * pow(1.0 - x, 3); }
+double or_xf_d(double x) { return sqrt(x) * pow(1.0 - x, 4); }
+double or_xf_qbar(double x) { return 0.2 * pow(1.0 - x, 7); }
+double or_xf_g(double x) { return 3.0 * pow(1.0 - x, 5); }
+
+double or_gauss_tf(double meas, double truth, double rel_sigma)
+{
+  double s = rel_sigma * truth;
+  double z = (meas - truth) / s;
+  return exp(-0.5 * z * z) / (sqrt(2.0 * M_PI) * s);
+}
+
+/* ----------------------------------------------------------- Drell-Yan -- */
+/* Collins-Soper polar angle of the mu- in the pair rest frame */
+static double cos_cs(const double* m1, const double* m2)
+{
+  double P[4];
+  for (int i = 0; i < 4; ++i) P[i] = m1[i] + m2[i];
+  double M2 = mdot(P, P), pt2 = P[1] * P[1] + P[2] * P[2];
+  double p1p = (m1[0] + m1[3]) / sqrt(2.0), p1m = (m1[0] - m1[3]) / sqrt(2.0);
+  double p2p = (m2[0] + m2[3]) / sqrt(2.0), p2m = (m2[0] - m2[3]) / sqrt(2.0);
+  return 2.0 * (p1p * p2m - p1m * p2p) / (sqrt(M2) * sqrt(M2 + pt2));
+}
+
+double or_dy_integrand(const or_params* p, const double* ev, const double* x)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  double mu[2][4];
+  double factor = 1.0;
+  for (int k = 0; k < 2; ++k) {
+    const double* m = ev + 4 * k;
+    double pm = norm3(m);
+    double r = p->r_lo + x[k] * (p->r_hi - p->r_lo);
+    double pt = pm / r;                      /* true |p| */
+    double jac = (p->r_hi - p->r_lo) * pm / (r * r);
+    for (int i = 1; i < 4; ++i) mu[k][i] = m[i] / pm * pt;
+    mu[k][0] = pt;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    /* d^3p/((2pi)^3 2E) with delta functions on the direction:
+     * p^2 sin(theta) dp / (2E), times the TF (the (2pi) powers are
+     * collected below) */
+    factor *= pt * pt * sin_th / (2.0 * pt) * or_gauss_tf(pm, pt, p->tf_sigma) * jac;
+  }
+  double P[4];
+  for (int i = 0; i < 4; ++i) P[i] = mu[0][i] + mu[1][i];
+  double M2 = mdot(P, P);
+  if (M2 <= 0.0) return 0.0;
+  double M = sqrt(M2);
+  if (M < p->m_lo || M > p->m_hi) return 0.0;
+  double x1 = (P[0] + P[3]) / p->sqrt_s, x2 = (P[0] - P[3]) / p->sqrt_s;
+  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
+  double c = cos_cs(mu[0], mu[1]);
+  double e2 = 4.0 * M_PI * p->alpha;
+  double me_unit = e2 * e2 * (1.0 + c * c) / 3.0;   /* for Q_q^2 = 1 */
+  double fu1 = or_xf_u(x1) / x1, fd1 = or_xf_d(x1) / x1, fq1 = or_xf_qbar(x1) / x1;
+  double fu2 = or_xf_u(x2) / x2, fd2 = or_xf_d(x2) / x2, fq2 = or_xf_qbar(x2) / x2;
+  double lum = 4.0 / 9.0 * (fu1 * fq2 + fq1 * fu2) + 1.0 / 9.0 * (fd1 * fq2 + fq1 * fd2);
+  double shat = x1 * x2 * S;
+  double flux = 1.0 / (2.0 * shat);
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 2.0);
+  return two_pi_pow * (2.0 / S) * lum * me_unit * flux * factor;
+}
+
+/* Gauss-Legendre nodes on [-1,1] by Newton on the Legendre recurrence */
+static void gauss_legendre(int n, double* xs, double* ws)
+{
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int j = 0; j < n; ++j) { double p2 = p1; p1 = p0; p0 = ((2.0 * j + 1.0) * z * p1 - j * p2) / (j + 1.0); }
+      pp = n * (z * p0 - p1) / (z * z - 1.0);
+      double dz = p0 / pp;
+      z -= dz;
+      if (fabs(dz) < 1e-15) break;
+    }
+    xs[i] = z;
+    ws[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+static double dy_lumi_sigma(const or_params* p, double x1, double x2)
+{
+  double fu1 = or_xf_u(x1) / x1, fd1 = or_xf_d(x1) / x1, fq1 = or_xf_qbar(x1) / x1;
+  double fu2 = or_xf_u(x2) / x2, fd2 = or_xf_d(x2) / x2, fq2 = or_xf_qbar(x2) / x2;
+  double lum = 4.0 / 9.0 * (fu1 * fq2 + fq1 * fu2) + 1.0 / 9.0 * (fd1 * fq2 + fq1 * fd2);
+  double shat = x1 * x2 * p->sqrt_s * p->sqrt_s;
+  /* partonic sigma(q qbar -> mu mu) for unit charge, colour averaged:
+   * 4 pi alpha^2 / (3 shat) / 3 */
+  return lum * 4.0 * M_PI * p->alpha * p->alpha / (9.0 * shat);
+}
+
+double or_dy_sigma_2d(const or_params* p, int nodes)
+{
+  /* integrate over (ln tau, y) with x1 = sqrt(tau) e^y, x2 = sqrt(tau) e^-y,
+   * dx1 dx2 = tau d(ln tau) dy */
+  double xs[4096], ws[4096];
+  if (nodes > 4096) nodes = 4096;
+  gauss_legendre(nodes, xs, ws);
+  double S = p->sqrt_s * p->sqrt_s;
+  double lt0 = log(p->m_lo * p->m_lo / S), lt1 = log(p->m_hi * p->m_hi / S);
+  double total = 0.0;
+  for (int i = 0; i < nodes; ++i) {
+    double lt = 0.5 * (lt1 - lt0) * xs[i] + 0.5 * (lt1 + lt0);
+    double tau = exp(lt);
+    double ymax = -0.5 * lt;
+    double inner = 0.0;
+    for (int j = 0; j < nodes; ++j) {
+      double y = ymax * xs[j];
+      double x1 = sqrt(tau) * exp(y), x2 = sqrt(tau) * exp(-y);
+      if (x1 >= 1.0 || x2 >= 1.0) continue;
+      inner += ws[j] * ymax * dy_lumi_sigma(p, x1, x2);
+    }
+    total += ws[i] * 0.5 * (lt1 - lt0) * tau * inner;
+  }
+  return total;
+}
+
+double or_dy_sigma_tau(const or_params* p, int nodes)
+{
+  /* sigma = int dtau/tau * tau * L(tau) sigmahat, L(tau) = int_tau^1 dx/x f(x) f(tau/x);
+   * substitute x = tau^v, v in (0,1): dx/x = -ln(tau) dv */
+  double xs[4096], ws[4096];
+  if (nodes > 4096) nodes = 4096;
+  gauss_legendre(nodes, xs, ws);
+  double S = p->sqrt_s * p->sqrt_s;
+  double lt0 = log(p->m_lo * p->m_lo / S), lt1 = log(p->m_hi * p->m_hi / S);
+  double total = 0.0;
+  for (int i = 0; i < nodes; ++i) {
+    double lt = 0.5 * (lt1 - lt0) * xs[i] + 0.5 * (lt1 + lt0);
+    double tau = exp(lt);
+    double lum = 0.0;
+    for (int j = 0; j < nodes; ++j) {
+      double v = 0.5 * xs[j] + 0.5;
+      double x1 = exp(v * lt), x2 = tau / x1;
+      double f = 4.0 / 9.0 * (or_xf_u(x1) * or_xf_qbar(x2) + or_xf_qbar(x1) * or_xf_u(x2))
+               + 1.0 / 9.0 * (or_xf_d(x1) * or_xf_qbar(x2) + or_xf_qbar(x1) * or_xf_d(x2));
+      /* f_a(x1) f_b(x2) = xf_a xf_b / (x1 x2) = xf xf / tau;  dx1/x1 = -lt dv */
+      lum += 0.5 * ws[j] * (-lt) * f / tau;
+    }
+    double shat = tau * S;
+    total += ws[i] * 0.5 * (lt1 - lt0) * tau * lum * 4.0 * M_PI * p->alpha * p->alpha / (9.0 * shat);
+  }
+  return total;
+}
+
+/* ------------------------------------------------- dilepton solutions --- */
+/* Polynomial helpers, coefficients in ascending order. */
+static double peval(const double* c, int n, double x)
+{
+  double r = c[n];
+  for (int i = n - 1; i >= 0; --i) r = r * x + c[i];
+  return r;
+}
+
+/* Real roots of a polynomial of degree n <= 4, found by isolating each
+ * root between consecutive real roots of the derivative (where the
+ * polynomial is monotone) and bisecting to the last representable bit.
+ * Returns the count; roots ascending. */
+static int real_roots(const double* c_in, int n, double* roots)
+{
+  double c[5];
+  memcpy(c, c_in, sizeof(double) * (n + 1));
+  while (n > 0 && c[n] == 0.0) --n;
+  if (n == 0) return 0;
+  if (n == 1) { roots[0] = -c[0] / c[1]; return 1; }
+  double dc[4] = {0, 0, 0, 0};
+  for (int i = 1; i <= n; ++i) dc[i - 1] = i * c[i];
+  double crit[4];
+  int nc = real_roots(dc, n - 1, crit);
+  double bound = 0.0;
+  for (int i = 0; i < n; ++i) bound = fmax(bound, fabs(c[i] / c[n]));
+  bound = 1.0 + bound;
+  double pts[6];
+  int np = 0;
+  pts[np++] = -bound;
+  for (int i = 0; i < nc; ++i) if (crit[i] > -bound && crit[i] < bound) pts[np++] = crit[i];
+  pts[np++] = bound;
+  int nr = 0;
+  for (int i = 0; i + 1 < np; ++i) {
+    double lo = pts[i], hi = pts[i + 1];
+    double flo = peval(c, n, lo), fhi = peval(c, n, hi);
+    if (flo == 0.0) {                       /* exact root at the left end */
+      if (nr == 0 || roots[nr - 1] != lo) roots[nr++] = lo;
+      continue;
+    }
+    if (fhi == 0.0) {                       /* recorded as the next left end */
+      if (i + 2 == np) roots[nr++] = hi;
+      continue;
+    }
+    if ((flo < 0) == (fhi < 0)) continue;   /* monotone, no sign change */
+    for (int it = 0; it < 2000; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      double fm = peval(c, n, mid);
+      if (fm == 0.0) { lo = hi = mid; break; }
+      if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else { hi = mid; }
+    }
+    roots[nr++] = 0.5 * (lo + hi);
+  }
+  return nr;
+}
+
+/* Linear part of the neutrino constraints for one top: with E = |p|,
+ * 2 l.nu = q2w and 2 b.nu = q2t - q2w - 2 b.l give E and p_z as affine
+ * functions of (p_x, p_y): E = e0 + e1 px + e2 py, pz = z0 + z1 px + z2 py. */
+static int nu_affine(const double* b, const double* l, double q2w, double q2t,
+                     double e[3], double z[3])
+{
+  double h1 = 0.5 * q2w;
+  double h2 = 0.5 * (q2t - q2w - 2.0 * mdot(b, l));
+  double det = -l[0] * b[3] + l[3] * b[0];
+  if (det == 0.0) return 0;
+  e[0] = (-b[3] * h1 + l[3] * h2) / det;
+  e[1] = (-b[3] * l[1] + l[3] * b[1]) / det;
+  e[2] = (-b[3] * l[2] + l[3] * b[2]) / det;
+  z[0] = (l[0] * h2 - b[0] * h1) / det;
+  z[1] = (l[0] * b[1] - b[0] * l[1]) / det;
+  z[2] = (l[0] * b[2] - b[0] * l[2]) / det;
+  return 1;
+}
+
+/* conic coefficients {xx, xy, yy, x, y, 1} of E^2 - px^2 - py^2 - pz^2 = 0 */
+static void conic_of(const double e[3], const double z[3], double c[6])
+{
+  c[0] = e[1] * e[1] - 1.0 - z[1] * z[1];
+  c[1] = 2.0 * (e[1] * e[2] - z[1] * z[2]);
+  c[2] = e[2] * e[2] - 1.0 - z[2] * z[2];
+  c[3] = 2.0 * (e[0] * e[1] - z[0] * z[1]);
+  c[4] = 2.0 * (e[0] * e[2] - z[0] * z[2]);
+  c[5] = e[0] * e[0] - z[0] * z[0];
+}
+
+static void residuals(const double* b, const double* bb, const double* lp, const double* lm,
+                      double mx, double my, const double v[4], double F[4], double Jm[16])
+{
+  double nu[4], nb[4];
+  nu[1] = v[0]; nu[2] = v[1]; nu[3] = v[2];
+  nb[1] = mx - v[0]; nb[2] = my - v[1]; nb[3] = v[3];
+  nu[0] = norm3(nu); nb[0] = norm3(nb);
+  double wt[4], wtb[4];
+  for (int i = 0; i < 4; ++i) { wt[i] = b[i] + lp[i]; wtb[i] = bb[i] + lm[i]; }
+  /* F = (q2_W+, q2_t, q2_W-, q2_tbar) at (nu, nubar) */
+  F[0] = 2.0 * mdot(lp, nu);
+  F[1] = mdot(wt, wt) + 2.0 * mdot(wt, nu);
+  F[2] = 2.0 * mdot(lm, nb);
+  F[3] = mdot(wtb, wtb) + 2.0 * mdot(wtb, nb);
+  if (!Jm) return;
+  /* d(a.nu)/d(nu_i) = a_E nu_i / E - a_i ;  nubar_x,y = met - nu_x,y */
+  for (int i = 0; i < 3; ++i) {
+    double dl = lp[0] * nu[i + 1] / nu[0] - lp[i + 1];
+    double dw = wt[0] * nu[i + 1] / nu[0] - wt[i + 1];
+    Jm[0 * 4 + i] = 2.0 * dl;
+    Jm[1 * 4 + i] = 2.0 * dw;
+  }
+  Jm[0 * 4 + 3] = 0.0;
+  Jm[1 * 4 + 3] = 0.0;
+  double dlm[3], dwm[3];
+  for (int i = 0; i < 3; ++i) {
+    dlm[i] = 2.0 * (lm[0] * nb[i + 1] / nb[0] - lm[i + 1]);
+    dwm[i] = 2.0 * (wtb[0] * nb[i + 1] / nb[0] - wtb[i + 1]);
+  }
+  Jm[2 * 4 + 0] = -dlm[0]; Jm[2 * 4 + 1] = -dlm[1]; Jm[2 * 4 + 2] = 0.0; Jm[2 * 4 + 3] = dlm[2];
+  Jm[3 * 4 + 0] = -dwm[0]; Jm[3 * 4 + 1] = -dwm[1]; Jm[3 * 4 + 2] = 0.0; Jm[3 * 4 + 3] = dwm[2];
+}
+
+/* Gaussian elimination with partial pivoting; returns det and, if rhs is
+ * given, solves A x = rhs in place. */
+static double lu_det_solve(double A_in[16], double* rhs)
+{
+  double A[16];
+  memcpy(A, A_in, sizeof(A));
+  double det = 1.0;
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r) if (fabs(A[r * 4 + c]) > fabs(A[piv * 4 + c])) piv = r;
+    if (A[piv * 4 + c] == 0.0) return 0.0;
+    if (piv != c) {
+      for (int k = 0; k < 4; ++k) { double t = A[c * 4 + k]; A[c * 4 + k] = A[piv * 4 + k]; A[piv * 4 + k] = t; }
+      if (rhs) { double t = rhs[c]; rhs[c] = rhs[piv]; rhs[piv] = t; }
+      det = -det;
+    }
+    det *= A[c * 4 + c];
+    for (int r = c + 1; r < 4; ++r) {
+      double f = A[r * 4 + c] / A[c * 4 + c];
+      for (int k = c; k < 4; ++k) A[r * 4 + k] -= f * A[c * 4 + k];
+      if (rhs) rhs[r] -= f * rhs[c];
+    }
+  }
+  if (rhs)
+    for (int r = 3; r >= 0; --r) {
+      double s = rhs[r];
+      for (int k = r + 1; k < 4; ++k) s -= A[r * 4 + k] * rhs[k];
+      rhs[r] = s / A[r * 4 + r];
+    }
+  return det;
+}
+
+void or_dilepton_residual(const double* b, const double* bb, const double* lp,
+                          const double* lm, const double* nu, const double* nub,
+                          double* q2)
+{
+  double wt[4], wtb[4], wp[4], wm[4];
+  for (int i = 0; i < 4; ++i) {
+    wp[i] = lp[i] + nu[i]; wm[i] = lm[i] + nub[i];
+    wt[i] = wp[i] + b[i]; wtb[i] = wm[i] + bb[i];
+  }
+  q2[0] = mdot(wp, wp); q2[1] = mdot(wt, wt); q2[2] = mdot(wm, wm); q2[3] = mdot(wtb, wtb);
+}
+
+int or_solve_dilepton(const double* b_in, const double* bb_in, const double* lp_in,
+                      const double* lm_in, double metx, double mety,
+                      double q2wp, double q2t, double q2wm, double q2tb,
+                      double* nu_out, double* nub_out, double* detj_out)
+{
+  /* work in units of lam so that all polynomial coefficients are O(1) */
+  double lam = 0.25 * (b_in[0] + bb_in[0] + lp_in[0] + lm_in[0]);
+  double b[4], bb[4], lp[4], lm[4];
+  for (int i = 0; i < 4; ++i) { b[i] = b_in[i] / lam; bb[i] = bb_in[i] / lam; lp[i] = lp_in[i] / lam; lm[i] = lm_in[i] / lam; }
+  double mx = metx / lam, my = mety / lam, l2 = lam * lam;
+  double qwp = q2wp / l2, qt = q2t / l2, qwm = q2wm / l2, qtb = q2tb / l2;
+
+  double e1[3], z1[3], e2[3], z2[3];
+  if (!nu_affine(b, lp, qwp, qt, e1, z1)) return 0;
+  if (!nu_affine(bb, lm, qwm, qtb, e2, z2)) return 0;
+  double c1[6], cb[6], c2[6];
+  conic_of(e1, z1, c1);
+  conic_of(e2, z2, cb);
+  /* the nubar conic in (nubar_x, nubar_y) -> in (nu_x, nu_y) */
+  c2[0] = cb[0]; c2[1] = cb[1]; c2[2] = cb[2];
+  c2[3] = -2.0 * mx * cb[0] - my * cb[1] - cb[3];
+  c2[4] = -2.0 * my * cb[2] - mx * cb[1] - cb[4];
+  c2[5] = cb[0] * mx * mx + cb[1] * mx * my + cb[2] * my * my + cb[3] * mx + cb[4] * my + cb[5];
+  /* each conic as A py^2 + B(px) py + C(px); resultant in py */
+  double A1 = c1[2], A2 = c2[2];
+  double B1[2] = {c1[4], c1[1]}, B2[2] = {c2[4], c2[1]};
+  double C1[3] = {c1[5], c1[3], c1[0]}, C2[3] = {c2[5], c2[3], c2[0]};
+  double P[3], Q[2], R[4] = {0, 0, 0, 0};
+  for (int i = 0; i < 3; ++i) P[i] = A1 * C2[i] - A2 * C1[i];
+  for (int i = 0; i < 2; ++i) Q[i] = A1 * B2[i] - A2 * B1[i];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) R[i + j] += B1[i] * C2[j] - B2[i] * C1[j];
+  double res[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) res[i + j] += P[i] * P[j];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 4; ++j) if (i + j <= 4) res[i + j] -= Q[i] * R[j];
+  double roots[4];
+  int nr = real_roots(res, 4, roots);
+  int ns = 0;
+  for (int k = 0; k < nr; ++k) {
+    double px = roots[k];
+    double q = Q[0] + Q[1] * px;
+    double py;
+    double pval = P[0] + P[1] * px + P[2] * px * px;
+    if (fabs(q) > 1e-12 * (fabs(Q[0]) + fabs(Q[1] * px)) && q != 0.0) {
+      py = -pval / q;
+    } else {
+      /* degenerate elimination: take the root of conic 1 that best
+       * satisfies conic 2 */
+      double a = A1, bq = B1[0] + B1[1] * px, cq = C1[0] + C1[1] * px + C1[2] * px * px;
+      double disc = bq * bq - 4 * a * cq;
+      if (disc < 0 || a == 0.0) continue;
+      double y1 = (-bq + sqrt(disc)) / (2 * a), y2 = (-bq - sqrt(disc)) / (2 * a);
+      double r1 = fabs(c2[0] * px * px + c2[1] * px * y1 + c2[2] * y1 * y1 + c2[3] * px + c2[4] * y1 + c2[5]);
+      double r2 = fabs(c2[0] * px * px + c2[1] * px * y2 + c2[2] * y2 * y2 + c2[3] * px + c2[4] * y2 + c2[5]);
+      py = r1 < r2 ? y1 : y2;
+    }
+    double E1 = e1[0] + e1[1] * px + e1[2] * py;
+    double pz1 = z1[0] + z1[1] * px + z1[2] * py;
+    double pbx = mx - px, pby = my - py;
+    double E2 = e2[0] + e2[1] * pbx + e2[2] * pby;
+    double pz2 = z2[0] + z2[1] * pbx + z2[2] * pby;
+    if (!(E1 > 0.0 && E2 > 0.0)) continue;
+    double v[4] = {px, py, pz1, pz2};
+    double target[4] = {qwp, qt, qwm, qtb};
+    double F[4], Jm[16];
+    for (int it = 0; it < 2; ++it) {
+      residuals(b, bb, lp, lm, mx, my, v, F, Jm);
+      double rhs[4];
+      for (int i = 0; i < 4; ++i) rhs[i] = F[i] - target[i];
+      if (lu_det_solve(Jm, rhs) == 0.0) break;
+      for (int i = 0; i < 4; ++i) v[i] -= rhs[i];
+    }
+    residuals(b, bb, lp, lm, mx, my, v, F, Jm);
+    double worst = 0.0;
+    for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs(F[i] - target[i]) / fabs(target[i]));
+    if (!(worst < 1e-6)) continue;
+    double det = lu_det_solve(Jm, NULL);
+    if (det == 0.0) continue;
+    double* nu = nu_out + 4 * ns;
+    double* nb = nub_out + 4 * ns;
+    nu[1] = v[0] * lam; nu[2] = v[1] * lam; nu[3] = v[2] * lam;
+    nb[1] = (mx - v[0]) * lam; nb[2] = (my - v[1]) * lam; nb[3] = v[3] * lam;
+    nu[0] = norm3(nu); nb[0] = norm3(nb);
+    /* the Jacobian has dimension GeV^4 (q2 per momentum) */
+    detj_out[ns] = det * lam * lam * lam * lam;
+    ++ns;
+  }
+  return ns;
+}
+
+/* ------------------------------------------------------ ttbar dilepton -- */
+/* Breit-Wigner (tan) map of x onto q2 in [lo, hi]; returns the Jacobian */
+double or_bw_map(double x, double m, double w, double lo, double hi, double* q2)
+{
+  double mw = m * w;
+  double t0 = atan((lo - m * m) / mw), t1 = atan((hi - m * m) / mw);
+  double th = t0 + x * (t1 - t0);
+  *q2 = m * m + mw * tan(th);
+  double d = *q2 - m * m;
+  return (t1 - t0) * (d * d + mw * mw) / mw;
+}
+
+/* transverse boost that removes the total transverse momentum P_T */
+static void boost_transverse(const double* P, const double* in, double* out)
+{
+  double bx = P[1] / P[0], by = P[2] / P[0];
+  double b2 = bx * bx + by * by;
+  double g = 1.0 / sqrt(1.0 - b2);
+  double bp = bx * in[1] + by * in[2];
+  double g2 = b2 > 0.0 ? (g - 1.0) / b2 : 0.0;
+  out[0] = g * (in[0] - bp);
+  out[1] = in[1] + g2 * bp * bx - g * bx * in[0];
+  out[2] = in[2] + g2 * bp * by - g * by * in[0];
+  out[3] = in[3];
+}
+
+int or_dims(int kind) { return kind == OR_KIND_DY ? 2 : (kind == OR_KIND_GENZ ? 4 : 8); }
+int or_nperm(int kind) { return kind == OR_KIND_TT ? 2 : 1; }
+
+double or_genz_integrand(const double* x)
+{
+  double f = 1.0;
+  for (int d = 0; d < 4; ++d) {
+    double c = 0.3 + 0.1 * d, a = 20.0;
+    f *= a / (1.0 + a * a * (x[d] - c) * (x[d] - c));
+  }
+  return f;
+}
+
+double or_genz_exact(void)
+{
+  double v = 1.0;
+  for (int d = 0; d < 4; ++d) {
+    double c = 0.3 + 0.1 * d, a = 20.0;
+    v *= atan(a * (1.0 - c)) + atan(a * c);
+  }
+  return v;
+}
+
+double or_tt_integrand(const or_params* p, const double* ev, int perm,
+                       const double* x, int* nsol_out)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  const double* jet[2] = {ev + (perm ? 4 : 0), ev + (perm ? 0 : 4)};
+  const double* lp = ev + 8;
+  const double* lm = ev + 12;
+  if (nsol_out) *nsol_out = 0;
+  /* jet energies through r = E_meas / E_true, directions fixed */
+  double bq[2][4];
+  double jetf = 1.0;
+  for (int k = 0; k < 2; ++k) {
+    const double* m = jet[k];
+    double em = m[0], pm = norm3(m);
+    double r = p->r_lo + x[k] * (p->r_hi - p->r_lo);
+    double E = em / r;
+    double jac = (p->r_hi - p->r_lo) * em / (r * r);
+    bq[k][0] = E;
+    for (int i = 1; i < 4; ++i) bq[k][i] = m[i] / pm * E;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    /* E^2 sin(theta) dE T(E_meas | E) / (2E), massless partons */
+    jetf *= E * E * sin_th * or_gauss_tf(em, E, p->tf_sigma) / (2.0 * E) * jac;
+  }
+  double q2t, q2tb, q2wp, q2wm;
+  double jbw = or_bw_map(x[2], p->m_t, p->w_t, 0.0, S, &q2t)
+             * or_bw_map(x[3], p->m_t, p->w_t, 0.0, S, &q2tb)
+             * or_bw_map(x[4], p->m_w, p->w_w, 0.0, S, &q2wp)
+             * or_bw_map(x[5], p->m_w, p->w_w, 0.0, S, &q2wm);
+  /* recoil k_T drawn from its Gaussian prior: the prior density times the
+   * Jacobian of this (Box-Muller) map is one */
+  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[6]));
+  double phi = 2.0 * M_PI * x[7];
+  double kx = rho * cos(phi), ky = rho * sin(phi);
+  /* missing transverse momentum at this point (Sec. 4), shifted by k_T */
+  double metx = kx - (bq[0][1] + bq[1][1] + lp[1] + lm[1]);
+  double mety = ky - (bq[0][2] + bq[1][2] + lp[2] + lm[2]);
+  double nu[16], nub[16], detj[4];
+  int ns = or_solve_dilepton(bq[0], bq[1], lp, lm, metx, mety, q2wp, q2t, q2wm, q2tb, nu, nub, detj);
+  if (nsol_out) *nsol_out = ns;
+  double sum = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const double* v = nu + 4 * s;
+    const double* vb = nub + 4 * s;
+    double lab[6][4];
+    memcpy(lab[0], bq[0], sizeof(lab[0])); memcpy(lab[1], lp, sizeof(lab[1]));
+    memcpy(lab[2], v, sizeof(lab[2]));     memcpy(lab[3], bq[1], sizeof(lab[3]));
+    memcpy(lab[4], lm, sizeof(lab[4]));    memcpy(lab[5], vb, sizeof(lab[5]));
+    double P[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 6; ++k) for (int i = 0; i < 4; ++i) P[i] += lab[k][i];
+    double hard[24];
+    for (int k = 0; k < 6; ++k) boost_transverse(P, lab[k], hard + 4 * k);
+    double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+    double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
+    double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+    double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
+    double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
+    double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
+    double me = g1 * g2 * or_tt_me2_gg(p, k1, k2, hard)
+              + q1 * qb2 * or_tt_me2_qq(p, k1, k2, hard)
+              + qb1 * q2 * or_tt_me2_qq(p, k2, k1, hard);
+    double shat = x1 * x2 * S;
+    double f = (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat)
+             / fabs(detj[s]) / (2.0 * v[0] * 2.0 * vb[0]);
+    sum += f;
+  }
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
+  double lep = 1.0 / (2.0 * lp[0] * 2.0 * lm[0]);
+  return sum * two_pi_pow * lep * jetf * jbw;
+}

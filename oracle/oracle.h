@@ -1,0 +1,166 @@
+/*
+ * Oracle for the matrix element method (MEM) integration path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, double-precision CPU
+ * implementation of what the GPU library computes.  It shares no code,
+ * header, table or constant generator with the HIP library; only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  Every function cites the passage of Schouten, DeAbreu & Stelzer,
+ * "Accelerated Matrix Element Method with Parallel Computing" (CPC 2014)
+ * that it follows, or names the published method it writes out.
+ *
+ * Conventions (fixed here, stated once):
+ *   metric (+,-,-,-); four-vectors are double[4] = {E, px, py, pz};
+ *   Dirac representation for gamma matrices; sums over spins use complete
+ *   bases of Dirac spinors, sums over gluon polarisations use the two
+ *   linear transverse polarisations.
+ */
+#ifndef MEM_ORACLE_H
+#define MEM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ RNG -- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its
+ * published definition: 10 rounds of two 32x32->64 multiplications with a
+ * Weyl-sequence key schedule. */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The point stream of the MC estimator (Sec. 2, Eq. for S_N): uniform
+ * u in [0,1)^D for point k of iteration `iter` of integral (event, perm).
+ * Dimension pair (2b, 2b+1) comes from one Philox call with counter
+ * {k, iter, event, perm*16 + b}; each 64-bit half (w0<<32|w1, w2<<32|w3)
+ * is shifted right by 11 and scaled by 2^-53. */
+void or_uniforms(uint64_t seed, uint32_t k, uint32_t iter, uint32_t event,
+                 uint32_t perm, int D, double* u);
+
+/* ---------------------------------------------------------------- VEGAS -- */
+#define OR_NBINS 64
+/* Lepage's VEGAS map (J. Comput. Phys. 27 (1978) 192): grid holds D rows of
+ * 65 edges.  Returns the Jacobian, writes x. */
+double or_vegas_map(const double* grid, int D, const double* u, double* x, int* bins);
+void   or_vegas_uniform_grid(double* grid, int D);
+/* damped rebinning of one dimension from its per-bin sums of w^2 */
+void   or_vegas_refine_dim(const double* d_in, double alpha, double* edges);
+
+/* -------------------------------------------------------------- physics -- */
+typedef struct {
+  double sqrt_s;
+  double m_t, w_t, m_w, w_w;
+  double alpha;        /* QED coupling (Drell-Yan) */
+  double alpha_s;      /* strong coupling, fixed */
+  double g_fermi;      /* G_F in GeV^-2 */
+  double sigma_k;      /* Gaussian width of each component of the recoil k_T */
+  double tf_sigma;     /* relative width of the Gaussian energy TF */
+  double r_lo, r_hi;   /* integration window of r = E_meas / E_true */
+  double m_lo, m_hi;   /* Drell-Yan truth window on m_mumu */
+} or_params;
+
+/* toy parton densities x*f(x) of the configuration, and the gluon choice */
+double or_xf_u(double x);
+double or_xf_d(double x);
+double or_xf_qbar(double x);
+double or_xf_g(double x);
+
+/* Drell-Yan qqbar -> gamma* -> mu mu, integrand over the two true |p|
+ * (Eq. mem_def + Eq. 3 with a Gaussian momentum TF). ev = mu-, mu+ as
+ * 2 x {E,px,py,pz}.  x in [0,1]^2.  No VEGAS Jacobian. */
+double or_dy_integrand(const or_params* p, const double* ev, const double* x);
+/* spin- and colour-averaged |M|^2 for q qbar -> mu- mu+ computed from
+ * explicit Dirac spinors and gamma matrices (p1 = quark, p2 = antiquark,
+ * p3 = mu-, p4 = mu+), charges in units of e. */
+double or_qq_mumu_me2(const double* p1, const double* p2, const double* p3,
+                      const double* p4, double Qq, double alpha);
+/* LO sigma(q qbar -> gamma* -> mu mu) in the window [m_lo, m_hi] by 2D
+ * Gauss-Legendre quadrature over (x1, x2); in GeV^-2. */
+double or_dy_sigma_2d(const or_params* p, int nodes);
+/* the same as a 1D integral over tau of the parton luminosity */
+double or_dy_sigma_tau(const or_params* p, int nodes);
+
+/* ttbar dilepton (Eqs. integrand and dilepsolv).  ev = b-jet 0, b-jet 1,
+ * l+, l- as 4 x {E,px,py,pz}.  perm 0: jet 0 is the b (from t), perm 1:
+ * swapped.  x in [0,1]^8.  Writes the number of accepted neutrino
+ * solutions when nsol != 0. */
+double or_tt_integrand(const or_params* p, const double* ev, int perm,
+                       const double* x, int* nsol);
+
+/* Building blocks exposed for tests. */
+/* all real (nu, nubar) solutions of Eq. dilepsolv; returns the count (<= 4),
+ * writes nu[4*i], nub[4*i] and the 4x4 Jacobian determinant of
+ * (q2_W+, q2_t, q2_W-, q2_tbar) w.r.t. (nu_x, nu_y, nu_z, nubar_z). */
+int or_solve_dilepton(const double* b, const double* bb, const double* lp,
+                      const double* lm, double metx, double mety,
+                      double q2wp, double q2t, double q2wm, double q2tb,
+                      double* nu, double* nub, double* detj);
+/* residuals of Eq. dilepsolv at (nu, nubar) */
+void or_dilepton_residual(const double* b, const double* bb, const double* lp,
+                          const double* lm, const double* nu, const double* nub,
+                          double* q2_out /* wp, t, wm, tb */);
+/* |M|^2 summed over all spins and colours (no averaging, no couplings), for
+ * gg -> t tbar -> b l+ nu bbar l- nubar.  k1, k2 gluons along +z, -z.
+ * mom = b, l+, nu, bbar, l-, nubar. Includes the four Breit-Wigner
+ * propagators.  Returns the colour/spin sum times g_s^4 g_W^8/16 / (avg). */
+double or_tt_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom);
+double or_tt_me2_qq(const or_params* p, const double* kq, const double* kqb, const double* mom);
+/* on-shell production only, spin/colour averaged, couplings g_s = 1 */
+double or_gg_ttbar_prod(double mt, const double* k1, const double* k2,
+                        const double* pt, const double* ptb);
+double or_qq_ttbar_prod(double mt, const double* k1, const double* k2,
+                        const double* pt, const double* ptb);
+/* Ward test: replace gluon 1's polarisation by its momentum; returns the
+ * largest |amplitude| over spins and the other gluon's polarisation */
+double or_gg_ttbar_ward(double mt, const double* k1, const double* k2,
+                        const double* pt, const double* ptb);
+/* t -> b l+ nu, summed over all spins, without couplings or W propagator */
+double or_top_decay_spinsum(double mt, const double* pt, const double* b,
+                            const double* lp, const double* nu);
+
+/* pieces of the tt map exposed for tests */
+double or_bw_map(double x, double m, double w, double lo, double hi, double* q2);
+double or_gauss_tf(double meas, double truth, double rel_sigma);
+/* Genz product-peak test integrand on [0,1]^4 (kind OR_KIND_GENZ):
+ * prod_d a / (1 + a^2 (x_d - c_d)^2), a = 20, c_d = 0.3 + 0.1 d */
+double or_genz_integrand(const double* x);
+double or_genz_exact(void);
+
+/* -------------------------------------------------------------- driver -- */
+enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3 };
+typedef struct {
+  double I, sigma;          /* combined estimate over iterations >= 2 */
+  double chi2dof;
+  int    n_iter_used;
+} or_result;
+/* Full VEGAS integration of one (event, permutation) integral.  iter_I and
+ * iter_var (may be NULL) receive I_j, sigma_j^2 of every iteration.
+ * grid_io (may be NULL): if non-NULL it is the starting grid and receives
+ * the final grid. */
+void or_integrate_one(int kind, const or_params* p, const double* ev, int perm,
+                      uint64_t seed, uint32_t event_index, int64_t n_points,
+                      int n_iter, double alpha, double* grid_io,
+                      double* iter_I, double* iter_var, or_result* res);
+/* one VEGAS iteration with a given grid; returns sum w, sum w^2 and the
+ * per-(dim,bin) sums of w^2 (D x 64) */
+void or_vegas_iteration(int kind, const or_params* p, const double* ev, int perm,
+                        uint64_t seed, uint32_t event_index, uint32_t iter,
+                        int64_t n_points, const double* grid,
+                        double* s1, double* s2, double* bins);
+/* integrand value at u (maps through the grid, multiplies the Jacobian) */
+double or_weight_at(int kind, const or_params* p, const double* ev, int perm,
+                    const double* grid, const double* u);
+/* P and its error per event (Eq. mem_def with the permutation average),
+ * events laid out [n_events][n_obj][4]; OpenMP over integrals. */
+void or_integrate_events(int kind, const or_params* p, const double* events,
+                         int n_events, int n_obj, uint64_t seed, int64_t n_points,
+                         int n_iter, double alpha, double sigma_norm,
+                         double* P, double* err, int32_t* status);
+int or_dims(int kind);
+int or_nperm(int kind);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

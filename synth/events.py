@@ -1,0 +1,161 @@
+"""Seeded synthetic collision events for the matrix element method.
+
+This module is the only piece shared by the oracle side and the GPU side:
+it draws input events and holds none of the method's arithmetic (no matrix
+element, parton density, transfer-function density or phase-space weight).
+Events are produced by sampling production and decay kinematics directly
+(Breit-Wigner masses, isotropic two-body decays, a Gaussian transverse
+recoil) and smearing energies with the detector resolution, so their shapes
+match the processes of the paper's benchmark (Sec. 3 and 4) without being
+weighted by any |M|^2.
+
+Layouts: `obs` is float64 [n_events, n_obj, 4] with rows (E, px, py, pz).
+  Drell-Yan:       mu-, mu+
+  ttbar dilepton:  jet_a, jet_b, l+, l-    (b/bbar order random)
+"""
+import numpy as np
+
+SQRT_S = 13000.0
+M_T, W_T = 172.5, 1.4
+M_W, W_W = 80.4, 2.1
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.Philox(key=seed))
+
+
+def _bw(rng, n, m, w, lo, hi):
+    """Breit-Wigner (Cauchy) masses truncated to [lo, hi] by inverse CDF."""
+    a0 = np.arctan((lo - m) / (0.5 * w))
+    a1 = np.arctan((hi - m) / (0.5 * w))
+    return m + 0.5 * w * np.tan(a0 + rng.random(n) * (a1 - a0))
+
+
+def _iso(rng, n):
+    c = 2.0 * rng.random(n) - 1.0
+    s = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+    phi = 2.0 * np.pi * rng.random(n)
+    return np.stack([s * np.cos(phi), s * np.sin(phi), c], axis=-1)
+
+
+def _two_body(M, m1, m2, nhat):
+    """momenta of a two-body decay at rest; returns p1, p2 as (n,4)"""
+    p = np.sqrt(np.maximum(0.0, (M * M - (m1 + m2) ** 2) * (M * M - (m1 - m2) ** 2))) / (2.0 * M)
+    e1 = np.sqrt(p * p + m1 * m1)
+    e2 = np.sqrt(p * p + m2 * m2)
+    v1 = np.concatenate([e1[:, None], p[:, None] * nhat], axis=1)
+    v2 = np.concatenate([e2[:, None], -p[:, None] * nhat], axis=1)
+    return v1, v2
+
+
+def _boost(p, P):
+    """boost four-vectors p (n,4) from the rest frame of P (n,4) to the lab"""
+    M = np.sqrt(np.maximum(P[:, 0] ** 2 - np.sum(P[:, 1:] ** 2, axis=1), 1e-300))
+    b = P[:, 1:] / P[:, :1]
+    b2 = np.sum(b * b, axis=1)
+    g = P[:, 0] / M
+    bp = np.sum(b * p[:, 1:], axis=1)
+    g2 = np.where(b2 > 0, (g - 1.0) / np.where(b2 > 0, b2, 1.0), 0.0)
+    E = g * (p[:, 0] + bp)
+    vec = p[:, 1:] + (g2 * bp + g * p[:, 0])[:, None] * b
+    return np.concatenate([E[:, None], vec], axis=1)
+
+
+def _massless(E, direction_from):
+    n = direction_from[:, 1:] / np.linalg.norm(direction_from[:, 1:], axis=1, keepdims=True)
+    return np.concatenate([E[:, None], E[:, None] * n], axis=1)
+
+
+def _smear(rng, E, rel):
+    """E (1 + rel z), redrawn while non-positive (the resolution model)"""
+    out = E * (1.0 + rel * rng.standard_normal(E.shape))
+    bad = out <= 0.0
+    while np.any(bad):
+        out[bad] = E[bad] * (1.0 + rel * rng.standard_normal(int(bad.sum())))
+        bad = out <= 0.0
+    return out
+
+
+def drell_yan(n_events, seed, m_lo=60.0, m_hi=120.0, rel_sigma=0.05):
+    """q qbar -> gamma* -> mu- mu+ at sqrt(S) = 13 TeV.  The pair mass has a
+    falling m^-3 shape in [m_lo, m_hi], the pair rapidity is uniform inside
+    |y| < 2.5 (and the kinematic limit), the decay angle follows 1 + cos^2,
+    and each muon |p| is smeared by a Gaussian of relative width rel_sigma
+    with its direction kept."""
+    rng = _rng(seed)
+    u = rng.random(n_events)
+    m = 1.0 / np.sqrt(m_lo ** -2 + u * (m_hi ** -2 - m_lo ** -2))
+    ymax = np.minimum(2.5, np.log(SQRT_S / m))
+    y = (2.0 * rng.random(n_events) - 1.0) * ymax
+    cth = np.empty(n_events)
+    filled = 0
+    while filled < n_events:
+        c = 2.0 * rng.random(2 * n_events) - 1.0
+        keep = c[rng.random(2 * n_events) * 2.0 < 1.0 + c * c]
+        take = min(len(keep), n_events - filled)
+        cth[filled:filled + take] = keep[:take]
+        filled += take
+    phi = 2.0 * np.pi * rng.random(n_events)
+    s = np.sqrt(1.0 - cth * cth)
+    nhat = np.stack([s * np.cos(phi), s * np.sin(phi), cth], axis=1)
+    mu1, mu2 = _two_body(m, np.zeros(n_events), np.zeros(n_events), nhat)
+    P = np.stack([m * np.cosh(y), np.zeros(n_events), np.zeros(n_events), m * np.sinh(y)], axis=1)
+    mu1 = _boost(mu1, P)
+    mu2 = _boost(mu2, P)
+    truth = np.stack([mu1, mu2], axis=1)
+    obs = np.empty_like(truth)
+    for k in range(2):
+        pm = _smear(rng, truth[:, k, 0], rel_sigma)
+        obs[:, k] = _massless(pm, truth[:, k])
+    return {"obs": obs, "truth": truth, "m": m}
+
+
+def ttbar_dilepton(n_events, seed, rel_sigma=0.15, sigma_k=20.0):
+    """pp -> t tbar -> b l+ nu bbar l- nubar.  Top and W masses are
+    Breit-Wigner distributed, sqrt(shat) rises from threshold with a
+    Gamma(2, 80 GeV) excess, the pair rapidity is Gaussian (width 1) within
+    the kinematic limit, all decays are isotropic, the system receives a
+    Gaussian transverse recoil k_T (sigma_k per component), b-jet energies
+    are smeared by rel_sigma, leptons are exact, and the two b-jets are
+    stored in random order."""
+    rng = _rng(seed)
+    n = n_events
+    mt1 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mt2 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mw1 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mw2 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mtt = mt1 + mt2 + rng.gamma(2.0, 80.0, n)
+    ymax = np.log(SQRT_S / mtt)
+    y = np.clip(rng.standard_normal(n), -1.0, 1.0) * np.minimum(2.0, 0.9 * ymax)
+    t, tb = _two_body(mtt, mt1, mt2, _iso(rng, n))
+    b, wp = _two_body(mt1, np.zeros(n), mw1, _iso(rng, n))
+    bb, wm = _two_body(mt2, np.zeros(n), mw2, _iso(rng, n))
+    lp, nu = _two_body(mw1, np.zeros(n), np.zeros(n), _iso(rng, n))
+    lm, nub = _two_body(mw2, np.zeros(n), np.zeros(n), _iso(rng, n))
+    lp, nu = _boost(lp, wp), _boost(nu, wp)
+    lm, nub = _boost(lm, wm), _boost(nub, wm)
+    b, lp, nu = (_boost(v, t) for v in (b, lp, nu))
+    bb, lm, nub = (_boost(v, tb) for v in (bb, lm, nub))
+    # longitudinal boost of the pair, then the transverse recoil
+    k = sigma_k * rng.standard_normal((n, 2))
+    E_cm = np.sqrt(mtt ** 2 + np.sum(k * k, axis=1)) * np.cosh(y)
+    P = np.stack([E_cm, k[:, 0], k[:, 1], np.sqrt(mtt ** 2 + np.sum(k * k, axis=1)) * np.sinh(y)], axis=1)
+    parts = [_boost(v, P) for v in (b, lp, nu, bb, lm, nub)]
+    b, lp, nu, bb, lm, nub = parts
+    Eb = _smear(rng, b[:, 0], rel_sigma)
+    Ebb = _smear(rng, bb[:, 0], rel_sigma)
+    jb = _massless(Eb, b)
+    jbb = _massless(Ebb, bb)
+    swap = rng.random(n) < 0.5
+    j0 = np.where(swap[:, None], jbb, jb)
+    j1 = np.where(swap[:, None], jb, jbb)
+    obs = np.stack([j0, j1, lp, lm], axis=1)
+    truth = {"b": b, "bb": bb, "lp": lp, "lm": lm, "nu": nu, "nub": nub, "k": k,
+             "swap": swap, "mt1": mt1, "mt2": mt2, "mw1": mw1, "mw2": mw2}
+    return {"obs": obs, "truth": truth}
+
+
+def budgets(n_events, seed, lo=16384, hi=262144):
+    """per-event point budgets drawn uniformly from [lo, hi)"""
+    rng = _rng(seed)
+    return (lo + np.floor(rng.random(n_events) * (hi - lo))).astype(np.int64)

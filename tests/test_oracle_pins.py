@@ -1,0 +1,416 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: a
+library routine (rocRAND's Philox), textbook closed forms (Ellis-Stirling-
+Webber heavy-quark production, the V-A decay spin sum, e+e- -> mu+mu-),
+gauge invariance, symmetries, exact integrals and brute-force quadrature.
+"""
+import ctypes
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import events
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def mdot(a, b):
+    return a[0] * b[0] - a[1:] @ b[1:]
+
+
+# ----------------------------------------------------------------- RNG ----
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand(tmp_path):
+    """Philox4x32-10 equals rocRAND's engine word for word (host run)."""
+    exe = tmp_path / "philox_ref"
+    subprocess.run(["hipcc", "-O1", os.path.join(HERE, "golden", "rocrand_philox_ref.cpp"),
+                    "-o", str(exe)], check=True, capture_output=True)
+    rng = np.random.default_rng(5)
+    rows = []
+    for _ in range(200):
+        rows.append((int(rng.integers(0, 2**63)), int(rng.integers(0, 2**32)),
+                     int(rng.integers(0, 64)), int(rng.integers(0, 2**20)), int(rng.integers(0, 400))))
+    rows.append((0, 0, 0, 0, 0))
+    # the reference maps the counter through a 64-bit offset 4*(k | iter<<32),
+    # so iter stays below 2^30 there
+    rows.append((2**64 - 1, 2**32 - 1, 2**30 - 1, 2**32 - 1, 2**32 - 1))
+    inp = "\n".join(" ".join(str(v) for v in r) for r in rows) + "\n"
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(v) for v in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
+    for r, want in zip(rows, ref):
+        seed, k, it, ev, sub = r
+        got = oracle.philox([k, it, ev, sub], [seed & 0xFFFFFFFF, seed >> 32])
+        assert np.array_equal(got.astype(np.uint64), want), r
+
+
+def test_uniforms_are_53bit_and_uniform():
+    u = np.array([oracle.uniforms(7, k, 0, 3, 0, 2) for k in range(20000)]).ravel()
+    assert np.all(u >= 0.0) and np.all(u < 1.0)
+    scaled = u * 2.0**53
+    assert np.all(scaled == np.floor(scaled))
+    hist, _ = np.histogram(u, bins=50, range=(0, 1))
+    expect = len(u) / 50
+    chi2 = np.sum((hist - expect) ** 2 / expect)
+    assert chi2 < 100.0  # 49 dof, p ~ 1e-5
+    from scipy import stats
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+
+
+def test_uniforms_word_layout():
+    """dims (2b, 2b+1) come from words (0,1) and (2,3) of counter block b"""
+    seed = 0x1407759512345
+    u = oracle.uniforms(seed, 11, 2, 5, 1, 5)
+    for b in range(3):
+        w = oracle.philox([11, 2, 5, 16 + b], [seed & 0xFFFFFFFF, seed >> 32]).astype(np.uint64)
+        hi = int((w[0] << np.uint64(32)) | w[1]) >> 11
+        assert u[2 * b] == hi * 2.0**-53
+        if 2 * b + 1 < 5:
+            lo = int((w[2] << np.uint64(32)) | w[3]) >> 11
+            assert u[2 * b + 1] == lo * 2.0**-53
+
+
+# --------------------------------------------------------------- VEGAS ----
+def test_uniform_grid_map_is_identity():
+    g = oracle.uniform_grid(3)
+    rng = np.random.default_rng(1)
+    for _ in range(100):
+        u = np.floor(rng.random(3) * 2**53) * 2.0**-53
+        x, jac, bins = oracle.vegas_map(g, u)
+        assert np.all(x == u) and jac == 1.0
+        assert np.all(bins == np.floor(u * 64))
+
+
+def test_map_monotone_and_jacobian():
+    rng = np.random.default_rng(2)
+    edges = np.concatenate([[0.0], np.sort(rng.random(63)), [1.0]])
+    g = edges[None, :]
+    us = np.sort(rng.random(2000))
+    xs = [oracle.vegas_map(g, [u])[0][0] for u in us]
+    assert np.all(np.diff(xs) >= 0)
+    for u in us[:50]:
+        x, jac, b = oracle.vegas_map(g, [u])
+        i = int(u * 64)
+        assert edges[i] <= x[0] <= edges[i + 1]
+        assert jac == 64 * (edges[i + 1] - edges[i])
+
+
+def test_refine_flat_keeps_uniform_and_peak_concentrates():
+    e = np.linspace(0, 1, 65)
+    assert np.allclose(oracle.refine_dim(np.ones(64), 1.5, e), e, atol=1e-15)
+    d = np.zeros(64)
+    d[20] = 1.0
+    new = oracle.refine_dim(d, 1.5, e)
+    assert new[0] == 0.0 and new[64] == 1.0
+    assert np.all(np.diff(new) > 0)
+    # smoothing spreads bin 20 over 19..21; those bins take most new bins
+    inside = np.sum((new[1:] <= e[22]) & (new[:-1] >= e[19]))
+    assert inside > 40
+    zero = oracle.refine_dim(np.zeros(64), 1.5, e)
+    assert np.array_equal(zero, e)
+
+
+def test_refine_matches_damped_rebinning_by_hand():
+    """one refinement step checked against the written-out Lepage rule"""
+    rng = np.random.default_rng(3)
+    d = rng.random(64) ** 3
+    e = np.concatenate([[0.0], np.sort(rng.random(63)), [1.0]])
+    s = np.empty(64)
+    s[0] = (d[0] + d[1]) / 2
+    s[1:-1] = (d[:-2] + d[1:-1] + d[2:]) / 3
+    s[-1] = (d[-2] + d[-1]) / 2
+    rho = s / s.sum()
+    m = ((1 - rho) / np.log(1 / rho)) ** 1.5
+    cum = np.concatenate([[0.0], np.cumsum(m)])
+    targets = cum[-1] * np.arange(1, 64) / 64
+    # inverse of the piecewise-linear cumulative importance
+    want = np.interp(targets, cum, e)
+    got = oracle.refine_dim(d, 1.5, e)
+    assert np.allclose(got[1:64], want, rtol=0, atol=1e-13)
+
+
+def test_vegas_genz_product_peak():
+    """VEGAS on a separable product peak: estimate within 3 sigma of the
+    exact integral, and the adapted error far below plain MC."""
+    exact = oracle.lib().or_genz_exact()
+    p = oracle.dy_params()
+    r, Is, Vs, _ = oracle.integrate_one(oracle.KIND_GENZ, p, np.zeros(4), 0, 99, 0, 20000, 8)
+    pull = (r.I - exact) / r.sigma
+    assert abs(pull) < 3.0, (r.I, exact, r.sigma)
+    assert r.sigma / exact < 0.2 * math.sqrt(Vs[0]) / exact
+
+
+def test_vegas_pull_distribution_genz():
+    exact = oracle.lib().or_genz_exact()
+    p = oracle.dy_params()
+    pulls = []
+    for seed in range(30):
+        r, _, _, _ = oracle.integrate_one(oracle.KIND_GENZ, p, np.zeros(4), 0, 1000 + seed, 0, 4000, 6)
+        pulls.append((r.I - exact) / r.sigma)
+    pulls = np.array(pulls)
+    assert abs(pulls.mean()) < 0.6 and 0.5 < pulls.std() < 1.6
+
+
+# ------------------------------------------------------------- physics ----
+def _on_shell_tt(rng, mt, rs):
+    k1 = np.array([rs / 2, 0, 0, rs / 2])
+    k2 = np.array([rs / 2, 0, 0, -rs / 2])
+    p = math.sqrt(rs * rs / 4 - mt * mt)
+    c = 2 * rng.random() - 1
+    ph = 2 * math.pi * rng.random()
+    sn = math.sqrt(1 - c * c)
+    pt = np.array([rs / 2, p * sn * math.cos(ph), p * sn * math.sin(ph), p * c])
+    ptb = np.array([rs / 2, -pt[1], -pt[2], -pt[3]])
+    return k1, k2, pt, ptb
+
+
+def test_heavy_quark_production_closed_forms():
+    """gg -> QQbar and qqbar -> QQbar spin/colour averaged |M|^2 / g^4
+    (Ellis-Stirling-Webber, tau_i = 2 p_i.p_3 / s, rho = 4 m^2 / s)"""
+    rng = np.random.default_rng(4)
+    mt = 172.5
+    for _ in range(20):
+        rs = 2 * mt + 2000 * rng.random()
+        k1, k2, pt, ptb = _on_shell_tt(rng, mt, rs)
+        s = rs * rs
+        t1, t2, rho = 2 * mdot(k1, pt) / s, 2 * mdot(k2, pt) / s, 4 * mt * mt / s
+        gg = (1 / (6 * t1 * t2) - 3 / 8) * (t1 * t1 + t2 * t2 + rho - rho * rho / (4 * t1 * t2))
+        qq = 4 / 9 * (t1 * t1 + t2 * t2 + rho / 2)
+        assert oracle.call4("or_gg_ttbar_prod", mt, k1, k2, pt, ptb) == pytest.approx(gg, rel=1e-12)
+        assert oracle.call4("or_qq_ttbar_prod", mt, k1, k2, pt, ptb) == pytest.approx(qq, rel=1e-12)
+
+
+def test_gg_ward_identity():
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        k1, k2, pt, ptb = _on_shell_tt(rng, 172.5, 400 + 1000 * rng.random())
+        assert oracle.call4("or_gg_ttbar_ward", 172.5, k1, k2, pt, ptb) < 1e-10
+
+
+def _massless(rng, scale=60.0):
+    v = rng.normal(size=3) * scale
+    return np.array([np.linalg.norm(v), *v])
+
+
+def test_top_decay_spin_sum():
+    """sum over spins of |ubar(b) J P_L u(t)|^2 = 16 (t.l)(b.nu) (V-A)"""
+    rng = np.random.default_rng(6)
+    for _ in range(10):
+        b, lp, nu = _massless(rng), _massless(rng), _massless(rng)
+        pt = b + lp + nu
+        m = math.sqrt(mdot(pt, pt))
+        v = oracle.call4("or_top_decay_spinsum", m, pt, b, lp, nu)
+        assert v == pytest.approx(16 * mdot(pt, lp) * mdot(b, nu), rel=1e-12)
+
+
+def test_qq_mumu_me_and_cross_section():
+    """|M|^2 = (4 pi alpha)^2 Q^2 (1 + cos^2)/3 and, by exact quadrature
+    over dPhi_2 = dOmega / (32 pi^2), sigma(e+e- -> mu+mu-) = 4 pi alpha^2/(3s)"""
+    a = 1 / 137.0
+    rs = 91.0
+    s = rs * rs
+    p1 = np.array([rs / 2, 0, 0, rs / 2])
+    p2 = np.array([rs / 2, 0, 0, -rs / 2])
+    xs, ws = np.polynomial.legendre.leggauss(6)
+    sig = 0.0
+    L = oracle.lib()
+    for c, w in zip(xs, ws):
+        sn = math.sqrt(1 - c * c)
+        p3 = np.array([rs / 2, rs / 2 * sn * 0.6, rs / 2 * sn * 0.8, rs / 2 * c])
+        p4 = np.array([rs / 2, -p3[1], -p3[2], -p3[3]])
+        args = [np.ascontiguousarray(v) for v in (p1, p2, p3, p4)]
+        me = L.or_qq_mumu_me2(*[oracle._ptr(v) for v in args], 1.0, a) * 3.0  # undo colour avg
+        assert me == pytest.approx((4 * math.pi * a) ** 2 * (1 + c * c), rel=1e-12)
+        sig += w * 2 * math.pi * me / (32 * math.pi**2) / (2 * s)
+    assert sig == pytest.approx(4 * math.pi * a * a / (3 * s), rel=1e-12)
+
+
+def _tt_point(rng):
+    """random 2->6 kinematics with gluons along the beam"""
+    parts = [_massless(rng, 70.0) for _ in range(6)]
+    P = sum(parts)
+    # transverse boost to zero pT, then read x1, x2 from E +- pz
+    bx, by = P[1] / P[0], P[2] / P[0]
+    b2 = bx * bx + by * by
+    g = 1 / math.sqrt(1 - b2)
+    out = []
+    for v in parts:
+        bp = bx * v[1] + by * v[2]
+        g2 = (g - 1) / b2
+        out.append(np.array([g * (v[0] - bp), v[1] + g2 * bp * bx - g * bx * v[0],
+                             v[2] + g2 * bp * by - g * by * v[0], v[3]]))
+    P = sum(out)
+    k1 = np.array([(P[0] + P[3]) / 2, 0, 0, (P[0] + P[3]) / 2])
+    k2 = np.array([(P[0] - P[3]) / 2, 0, 0, -(P[0] - P[3]) / 2])
+    return k1, k2, np.concatenate(out)
+
+
+def _zboost(v, eta):
+    ch, sh = math.cosh(eta), math.sinh(eta)
+    return np.array([ch * v[0] + sh * v[3], v[1], v[2], sh * v[0] + ch * v[3]])
+
+
+def _zrot(v, a):
+    c, s = math.cos(a), math.sin(a)
+    return np.array([v[0], c * v[1] - s * v[2], s * v[1] + c * v[2], v[3]])
+
+
+def test_full_me_invariance_and_cp():
+    """the 2->6 |M|^2 is unchanged by boosts along and rotations about the
+    beam, and by CP (particles <-> antiparticles, momenta reflected, the
+    two beams exchanged)"""
+    p = oracle.tt_params()
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        k1, k2, mom = _tt_point(rng)
+        m6 = mom.reshape(6, 4)
+        gg = oracle.call4("or_tt_me2_gg", p, k1, k2, mom)
+        qq = oracle.call4("or_tt_me2_qq", p, k1, k2, mom)
+        assert gg > 0 and qq > 0
+        eta, ang = rng.normal(), rng.random() * 6.28
+        tr = lambda v: _zrot(_zboost(v, eta), ang)
+        mom2 = np.concatenate([tr(v) for v in m6])
+        assert oracle.call4("or_tt_me2_gg", p, tr(k1), tr(k2), mom2) == pytest.approx(gg, rel=1e-9)
+        assert oracle.call4("or_tt_me2_qq", p, tr(k1), tr(k2), mom2) == pytest.approx(qq, rel=1e-9)
+        par = lambda v: np.array([v[0], -v[1], -v[2], -v[3]])
+        b, lp, nu, bb, lm, nub = m6
+        cp = np.concatenate([par(v) for v in (bb, lm, nub, b, lp, nu)])
+        assert oracle.call4("or_tt_me2_gg", p, par(k2), par(k1), cp) == pytest.approx(gg, rel=1e-9)
+        # qqbar: the quark becomes an antiquark; the beam it came from is reflected
+        assert oracle.call4("or_tt_me2_qq", p, par(k2), par(k1), cp) == pytest.approx(qq, rel=1e-9)
+
+
+def test_dilepton_solutions_round_trip():
+    """the generator's true (nu, nubar) is among the solutions of
+    Eq. dilepsolv for its own propagator virtualities and MET"""
+    d = events.ttbar_dilepton(40, 21)
+    t = d["truth"]
+    for i in range(40):
+        b, bb, lp, lm, nu, nub = (t[k][i] for k in ("b", "bb", "lp", "lm", "nu", "nub"))
+        q2 = oracle.dilepton_q2(b, bb, lp, lm, nu, nub)
+        met = nu[1:3] + nub[1:3]
+        sols, solsb, det = oracle.solve_dilepton(b, bb, lp, lm, met, q2)
+        assert len(sols) in (2, 4) or len(sols) >= 1
+        err = [max(np.max(np.abs(s - nu)), np.max(np.abs(sb - nub))) / nu[0] for s, sb in zip(sols, solsb)]
+        assert min(err) < 1e-9
+        for s, sb in zip(sols, solsb):
+            assert np.allclose(oracle.dilepton_q2(b, bb, lp, lm, s, sb), q2, rtol=1e-9)
+
+
+def test_dilepton_jacobian_finite_difference():
+    d = events.ttbar_dilepton(10, 22)
+    t = d["truth"]
+    for i in range(10):
+        b, bb, lp, lm, nu, nub = (t[k][i] for k in ("b", "bb", "lp", "lm", "nu", "nub"))
+        q2 = oracle.dilepton_q2(b, bb, lp, lm, nu, nub)
+        met = nu[1:3] + nub[1:3]
+        sols, solsb, det = oracle.solve_dilepton(b, bb, lp, lm, met, q2)
+        for s, sb, dj in zip(sols, solsb, det):
+            v0 = np.array([s[1], s[2], s[3], sb[3]])
+
+            def F(v):
+                n = np.array([0, v[0], v[1], v[2]])
+                n[0] = np.linalg.norm(n[1:])
+                m = np.array([0, met[0] - v[0], met[1] - v[1], v[3]])
+                m[0] = np.linalg.norm(m[1:])
+                return oracle.dilepton_q2(b, bb, lp, lm, n, m)
+
+            J = np.zeros((4, 4))
+            for j in range(4):
+                h = 1e-4 * max(1.0, abs(v0[j]))
+                e = np.zeros(4)
+                e[j] = h
+                J[:, j] = (F(v0 + e) - F(v0 - e)) / (2 * h)
+            assert np.linalg.det(J) == pytest.approx(dj, rel=1e-5)
+
+
+def test_bw_map_and_tf_normalisation():
+    """Jacobian x Breit-Wigner is the constant (theta1-theta0)/(M Gamma), and
+    the Gaussian TF integrates to one over the measured energy"""
+    L = oracle.lib()
+    m, w, lo, hi = 172.5, 1.4, 0.0, 13000.0**2
+    t0, t1 = math.atan((lo - m * m) / (m * w)), math.atan((hi - m * m) / (m * w))
+    for x in np.linspace(0.01, 0.99, 13):
+        q2 = ctypes.c_double()
+        jac = L.or_bw_map(float(x), m, w, lo, hi, ctypes.byref(q2))
+        bw = 1.0 / ((q2.value - m * m) ** 2 + m * m * w * w)
+        assert jac * bw == pytest.approx((t1 - t0) / (m * w), rel=1e-9)
+    from scipy import integrate
+    for truth, sig in ((50.0, 0.15), (300.0, 0.05)):
+        val, _ = integrate.quad(lambda e: L.or_gauss_tf(e, truth, sig), truth * (1 - 12 * sig), truth * (1 + 12 * sig), epsabs=0, epsrel=1e-12)
+        assert val == pytest.approx(1.0, abs=1e-10)
+
+
+def test_dy_sigma_two_ways():
+    p = oracle.dy_params()
+    L = oracle.lib()
+    a = L.or_dy_sigma_2d(ctypes.byref(p), 300)
+    b = L.or_dy_sigma_tau(ctypes.byref(p), 300)
+    assert a == pytest.approx(b, rel=1e-10)
+    assert a > 0
+
+
+def _dy_quadrature(p, ev, n=400):
+    """brute-force tensor Gauss-Legendre over the 2D unit square (the
+    integrand has a hard mass window, so use many nodes)"""
+    xs, ws = np.polynomial.legendre.leggauss(n)
+    xs = 0.5 * (xs + 1)
+    ws = 0.5 * ws
+    tot = 0.0
+    for x0, w0 in zip(xs, ws):
+        for x1, w1 in zip(xs, ws):
+            tot += w0 * w1 * oracle.dy_integrand(p, ev, [x0, x1])
+    return tot
+
+
+def test_dy_vegas_vs_quadrature():
+    """VEGAS estimate of the Drell-Yan integral within 3 sigma of brute-force
+    quadrature (pins the VEGAS driver on the real integrand)"""
+    p = oracle.dy_params()
+    d = events.drell_yan(3, 31)
+    for i in range(3):
+        ev = d["obs"][i]
+        q = _dy_quadrature(p, ev, 300)
+        r, _, _, _ = oracle.integrate_one(oracle.KIND_DY, p, ev, 0, 5, i, 4096, 10)
+        assert abs(r.I - q) < 3.5 * r.sigma + 1e-3 * q, (r.I, q, r.sigma)
+
+
+def tt_truth_x(p, obs, tr, i):
+    """invert the tt map at the generator's truth: r windows, BW tan maps and
+    the Box-Muller recoil map"""
+    S = p.sqrt_s ** 2
+    b, bb = tr["b"][i], tr["bb"][i]
+    jb, jbb = (obs[1], obs[0]) if tr["swap"][i] else (obs[0], obs[1])
+    perm = 1 if tr["swap"][i] else 0
+    x = np.zeros(8)
+    x[0] = (jb[0] / b[0] - p.r_lo) / (p.r_hi - p.r_lo)
+    x[1] = (jbb[0] / bb[0] - p.r_lo) / (p.r_hi - p.r_lo)
+    q2 = oracle.dilepton_q2(b, bb, tr["lp"][i], tr["lm"][i], tr["nu"][i], tr["nub"][i])
+    for j, (q, m, w) in enumerate(((q2[1], p.m_t, p.w_t), (q2[3], p.m_t, p.w_t),
+                                   (q2[0], p.m_w, p.w_w), (q2[2], p.m_w, p.w_w))):
+        t0, t1 = math.atan((0 - m * m) / (m * w)), math.atan((S - m * m) / (m * w))
+        x[2 + j] = (math.atan((q - m * m) / (m * w)) - t0) / (t1 - t0)
+    k = tr["k"][i]
+    x[6] = 1 - math.exp(-(k @ k) / (2 * p.sigma_k ** 2))
+    x[7] = (math.atan2(k[1], k[0]) / (2 * math.pi)) % 1.0
+    return x, perm
+
+
+def test_tt_integrand_positive_at_truth():
+    """at the truth point the map reproduces the event and one neutrino
+    solution exists; elsewhere the integrand is finite and non-negative"""
+    p = oracle.tt_params()
+    d = events.ttbar_dilepton(8, 41)
+    rng = np.random.default_rng(9)
+    for i in range(8):
+        ev = d["obs"][i]
+        x, perm = tt_truth_x(p, ev, d["truth"], i)
+        v, ns = oracle.tt_integrand(p, ev, perm, x)
+        assert ns >= 1 and v > 0
+        vals = np.array([oracle.tt_integrand(p, ev, rng.integers(2), rng.random(8))[0] for _ in range(100)])
+        assert np.all(np.isfinite(vals)) and np.all(vals >= 0)
