@@ -1,0 +1,208 @@
+/*
+ * mem.h - C ABI of the MI355X matrix element method (MEM) integrator.
+ *
+ * The library computes, for each observed event X and hypothesis i, the
+ * MEM density of Schouten, DeAbreu & Stelzer (CPC 2014):
+ *   P_i(X) = (1/sigma_i) (1/|perm|) sum_perm sum_flavour
+ *            int |M_i|^2 f1 f2 / flux  dPhi_n  T(X|Y) dY
+ * (Sec. 1, Eq. mem_def and Eq. 3; Sec. 3, Eq. integrand), estimated by
+ * VEGAS Monte Carlo (Sec. 2, Eq. for S_N and its error) entirely on one GPU.
+ *
+ * Conventions for every call:
+ *  - four-vectors are (E, px, py, pz) in GeV, metric (+,-,-,-);
+ *  - "device pointer" means memory allocated on the current HIP device;
+ *    the library never takes ownership of caller memory;
+ *  - a call either completes or returns a status != MEM_OK before it has
+ *    written any output; no C++ exception crosses this interface;
+ *  - calls that take a stream are stream-ordered: outputs are valid once
+ *    the stream has reached the call (unless stated otherwise);
+ *  - handles are thread-compatible: concurrent calls are allowed when they
+ *    use different streams and different output buffers.
+ */
+#ifndef MEM_H
+#define MEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MEM_OK = 0,
+  MEM_EINVAL = 1,       /* invalid argument (null pointer, bad size, NaN input) */
+  MEM_ENOMEM = 2,       /* device or host allocation failed */
+  MEM_EDEVICE = 3,      /* a HIP runtime call failed */
+  MEM_EUNSUPPORTED = 4  /* valid request that this build does not implement */
+} mem_status;
+
+/* Process kinds (hypotheses).  Object order expected in mem_events:
+ *  MEM_DY_QQ_GAMMA_MUMU  q qbar -> gamma* -> mu- mu+          : mu-, mu+
+ *  MEM_TT_DILEPTON       gg/qqbar -> t tbar -> b l+ nu bbar l- nubar
+ *                                                   : jet, jet, l+, l-   */
+typedef enum {
+  MEM_DY_QQ_GAMMA_MUMU = 1,
+  MEM_TT_DILEPTON = 2,
+  MEM_TT_SEMILEPTON = 3,    /* declared for the mixed batch; not built yet */
+  MEM_TTH_SEMILEPTON = 4    /* declared; not built yet */
+} mem_kind;
+
+typedef enum { MEM_FP64 = 0, MEM_FP32 = 1 } mem_precision;
+
+/* Physics description of one hypothesis (Sec. 4: "model parameters").
+ * Masses and widths in GeV; alpha, alpha_s dimensionless; g_fermi GeV^-2.
+ * sigma_k: width (GeV) of each component of the Gaussian transverse recoil
+ * of the hard system (tt kinds).  m_lo, m_hi: Drell-Yan window on the true
+ * pair mass.  sigma_norm: the 1/sigma_i of Eq. mem_def; 0 = unnormalised.
+ * precision: arithmetic of the matrix element / PDF / TF stage
+ * (MEM_FP64 for Drell-Yan, MEM_FP32 or MEM_FP64 for tt). */
+typedef struct {
+  int32_t kind;
+  int32_t precision;
+  double sqrt_s;
+  double m_top, w_top, m_w, w_w, m_h, w_h;
+  double alpha, alpha_s, g_fermi;
+  double sigma_k;
+  double m_lo, m_hi;
+  double sigma_norm;
+} mem_process_desc;
+
+typedef struct mem_process_s* mem_process;
+
+/* Transfer functions (Sec. 1, after Eq. 3): a delta for well measured
+ * objects, uniform for neutrinos, (double) Gaussian in energy for jets.
+ * T(E_meas | E) = sum_k w_k N(E_meas; E, (s_k E)^2) with w = (1-f, f),
+ * s = (sigma_core, sigma_tail).  The energy is integrated over
+ * r = E_meas / E in [max(r_min, 1 - window s_max), 1 + window s_max]. */
+typedef enum { MEM_TF_DELTA = 0, MEM_TF_UNIFORM = 1, MEM_TF_GAUSS = 2, MEM_TF_DGAUSS = 3 } mem_tf_kind;
+typedef enum {
+  MEM_OBJ_MUON = 0, MEM_OBJ_LEPTON = 1, MEM_OBJ_BJET = 2, MEM_OBJ_LJET = 3, MEM_OBJ_NEUTRINO = 4
+} mem_obj_class;
+typedef struct {
+  int32_t obj_class;    /* mem_obj_class */
+  int32_t kind;         /* mem_tf_kind */
+  double sigma_core;    /* relative width of the core Gaussian (> 0) */
+  double sigma_tail;    /* relative width of the tail Gaussian (DGAUSS) */
+  double f_tail;        /* tail fraction in [0,1] (DGAUSS) */
+  double window;        /* half width of the r window in units of the widest sigma */
+  double r_min;         /* lower floor of r */
+} mem_tf_desc;
+
+/* Observed events, SoA: component arrays [n_obj][n_events] (object-major,
+ * event index fastest), FP64.  on_device != 0: the four arrays are device
+ * pointers, else host pointers (copied in by the call). */
+typedef struct {
+  int32_t n_events;
+  int32_t n_obj;
+  const double* E;
+  const double* px;
+  const double* py;
+  const double* pz;
+  int32_t on_device;
+} mem_events;
+
+/* Options of mem_integrate_events; pass NULL for the defaults listed.
+ *  seed            Philox key (default: the process seed 0x14077595)
+ *  alpha           VEGAS damping exponent (1.5)
+ *  target_rel_err  0: run exactly n_iter iterations.  > 0: per event, stop
+ *                  once err/P <= target (checked after every iteration from
+ *                  the third on) or at max_iter
+ *  max_iter        cap in target mode (64)
+ *  stream          hipStream_t of the caller (NULL: the null stream)
+ *  outputs_on_device  p_out, err_out, status_out are device pointers
+ *  iter_out        optional device pointer, [n_iter][n_integrals][2]:
+ *                  I_j and sigma_j^2 of every integral and iteration
+ *  grid_out        optional device pointer, [n_integrals][D][65]: the VEGAS
+ *                  grids after the last refinement
+ *  n_iter_out      optional device pointer [n_events]: iterations used
+ *  timing_out      optional HOST pointer, 4 doubles: milliseconds spent in
+ *                  the integrand kernel (HIP events around every launch on
+ *                  `stream`), its number of launches, the number of
+ *                  integrand evaluations it performed, and the wall time of
+ *                  the call in milliseconds                                  */
+typedef struct {
+  uint64_t seed;
+  double alpha;
+  double target_rel_err;
+  int32_t max_iter;
+  void* stream;
+  int32_t outputs_on_device;
+  double* iter_out;
+  double* grid_out;
+  int32_t* n_iter_out;
+  double* timing_out;
+} mem_integrate_opts;
+
+/* Per-event status codes written to status_out. */
+enum {
+  MEM_EV_OK = 0,
+  MEM_EV_ZERO_INTEGRAND = 1,   /* every sampled weight was zero: P = err = 0 */
+  MEM_EV_NOT_CONVERGED = 2,    /* target mode: max_iter reached */
+  MEM_EV_NONFINITE = 3         /* a non-finite weight was produced */
+};
+
+/* Create a hypothesis (Sec. 1: process i).  Errors: MEM_EINVAL for a null
+ * pointer, unknown kind, non-positive sqrt_s/masses/widths or
+ * m_hi <= m_lo for Drell-Yan; MEM_EUNSUPPORTED for kinds not built;
+ * MEM_ENOMEM.  The handle is owned by the library until
+ * mem_destroy_process.  Default TFs: muon Gaussian 5 %, b-jet Gaussian 15 %,
+ * window 5, r_min 0.1. */
+mem_status mem_create_process(const mem_process_desc* d, mem_process* out);
+
+/* Replace the TF of the listed object classes (copied in).  MEM_EINVAL on
+ * unknown class or kind, sigma <= 0, f_tail outside [0,1], window <= 0. */
+mem_status mem_set_transfer_functions(mem_process p, const mem_tf_desc* tf, int32_t n);
+
+void mem_destroy_process(mem_process p);
+
+/* Integration dimension and number of jet-parton assignments of a process. */
+mem_status mem_process_shape(mem_process p, int32_t* dims, int32_t* n_perm);
+
+/* The MEM density of every event (Sec. 1 Eq. mem_def, Sec. 3 Eq. integrand).
+ *  ev        events (see mem_events); n_obj must match the process kind
+ *  hyp       one process per event (n_hyp == n_events), or one for all
+ *            (n_hyp == 1)
+ *  n_points  VEGAS points per event per iteration, split equally over the
+ *            permutations (ceil); one per event (n_np == n_events) or one
+ *            for all (n_np == 1); each >= 2
+ *  n_iter    iterations (>= 2; the first adapts the grid only)
+ *  p_out, err_out   P_i and its MC error per event
+ *  status_out       MEM_EV_* per event
+ * Errors: MEM_EINVAL (null pointers, sizes, non-finite or non-positive
+ * energies in host-side events), MEM_ENOMEM, MEM_EDEVICE.  Device-resident
+ * events are not scanned for NaNs; a NaN gives status MEM_EV_NONFINITE. */
+mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                const int64_t* n_points, int32_t n_np, int32_t n_iter,
+                                const mem_integrate_opts* opt,
+                                double* p_out, double* err_out, int32_t* status_out);
+
+/* ---- building blocks of the path, exposed for checks and custom drivers ---- */
+
+/* Uniform point stream of the estimator (Sec. 2): for k = 0..n-1 writes
+ * u[k*D + d] in [0,1), 53-bit, from Philox4x32-10 with key = seed and
+ * counter {k, iter, event, perm*16 + d/2}.  u: device pointer, n*D doubles. */
+mem_status mem_uniforms(uint64_t seed, uint32_t iter, uint32_t event, uint32_t perm,
+                        int32_t D, int64_t n, double* u, void* stream);
+
+/* Integrand f(x) of one (event, permutation) at n points x in [0,1]^D (no
+ * VEGAS Jacobian).  x: device [n][D]; f: device [n]; nsol: optional device
+ * [n], number of accepted neutrino solutions (tt kinds).  ev as in
+ * mem_integrate_events; event indexes it. */
+mem_status mem_eval_points(mem_process p, const mem_events* ev, int32_t event, int32_t perm,
+                           const double* x, int64_t n, double* f, int32_t* nsol, void* stream);
+
+/* VEGAS damped rebinning (Lepage 1978) of n_int x D grids in place from
+ * per-bin sums of w^2.  bins: device [n_int][D][64]; grids: device
+ * [n_int][D][65]; alpha > 0. */
+mem_status mem_vegas_refine(const double* bins, double* grids, int32_t n_int, int32_t D,
+                            double alpha, void* stream);
+
+const char* mem_status_string(mem_status s);
+/* Copies the message of the last failed call on this thread (may be empty). */
+mem_status mem_last_error(char* buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

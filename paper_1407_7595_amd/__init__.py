@@ -1,0 +1,205 @@
+"""Python binding of libmem, the MI355X matrix element method integrator.
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of libmem.so (see include/mem.h for the C ABI).  PyTorch supplies
+device memory and streams.  The library is loaded from this directory;
+importing the binding fails loudly when it has not been built.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmem.so")
+
+MEM_OK, MEM_EINVAL, MEM_ENOMEM, MEM_EDEVICE, MEM_EUNSUPPORTED = range(5)
+MEM_DY_QQ_GAMMA_MUMU, MEM_TT_DILEPTON, MEM_TT_SEMILEPTON, MEM_TTH_SEMILEPTON = 1, 2, 3, 4
+MEM_FP64, MEM_FP32 = 0, 1
+MEM_TF_DELTA, MEM_TF_UNIFORM, MEM_TF_GAUSS, MEM_TF_DGAUSS = range(4)
+MEM_OBJ_MUON, MEM_OBJ_LEPTON, MEM_OBJ_BJET, MEM_OBJ_LJET, MEM_OBJ_NEUTRINO = range(5)
+MEM_EV_OK, MEM_EV_ZERO_INTEGRAND, MEM_EV_NOT_CONVERGED, MEM_EV_NONFINITE = range(4)
+
+# every symbol include/mem.h declares
+EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_process",
+           "mem_process_shape", "mem_integrate_events", "mem_uniforms", "mem_eval_points",
+           "mem_vegas_refine", "mem_status_string", "mem_last_error")
+
+
+class ProcessDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32), ("sqrt_s", ctypes.c_double),
+                ("m_top", ctypes.c_double), ("w_top", ctypes.c_double), ("m_w", ctypes.c_double),
+                ("w_w", ctypes.c_double), ("m_h", ctypes.c_double), ("w_h", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("alpha_s", ctypes.c_double), ("g_fermi", ctypes.c_double),
+                ("sigma_k", ctypes.c_double), ("m_lo", ctypes.c_double), ("m_hi", ctypes.c_double),
+                ("sigma_norm", ctypes.c_double)]
+
+
+class TFDesc(ctypes.Structure):
+    _fields_ = [("obj_class", ctypes.c_int32), ("kind", ctypes.c_int32), ("sigma_core", ctypes.c_double),
+                ("sigma_tail", ctypes.c_double), ("f_tail", ctypes.c_double), ("window", ctypes.c_double),
+                ("r_min", ctypes.c_double)]
+
+
+class Events(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int32), ("n_obj", ctypes.c_int32), ("E", ctypes.c_void_p),
+                ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class IntegrateOpts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("alpha", ctypes.c_double), ("target_rel_err", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("stream", ctypes.c_void_p), ("outputs_on_device", ctypes.c_int32),
+                ("iter_out", ctypes.c_void_p), ("grid_out", ctypes.c_void_p), ("n_iter_out", ctypes.c_void_p),
+                ("timing_out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python paper_1407_7595_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, U32, U64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                    ctypes.c_uint32, ctypes.c_uint64)
+        sigs = {
+            "mem_create_process": (I32, [P, P]),
+            "mem_set_transfer_functions": (I32, [P, P, I32]),
+            "mem_destroy_process": (None, [P]),
+            "mem_process_shape": (I32, [P, P, P]),
+            "mem_integrate_events": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
+            "mem_uniforms": (I32, [U64, U32, U32, U32, I32, I64, P, P]),
+            "mem_eval_points": (I32, [P, P, I32, I32, P, I64, P, P, P]),
+            "mem_vegas_refine": (I32, [P, P, I32, I32, D, P]),
+            "mem_status_string": (ctypes.c_char_p, [I32]),
+            "mem_last_error": (I32, [ctypes.c_char_p, ctypes.c_size_t]),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MemError(RuntimeError):
+    def __init__(self, status, where):
+        buf = ctypes.create_string_buffer(512)
+        lib().mem_last_error(buf, 512)
+        super().__init__(f"{where}: {lib().mem_status_string(status).decode()} ({buf.value.decode()})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != MEM_OK:
+        raise MemError(status, where)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Process:
+    """A hypothesis (mem_create_process); released with the object."""
+
+    def __init__(self, kind, precision=MEM_FP32, sqrt_s=13000.0, m_top=172.5, w_top=1.4, m_w=80.4, w_w=2.1,
+                 m_h=125.0, w_h=0.00407, alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
+                 sigma_k=20.0, m_lo=60.0, m_hi=120.0, sigma_norm=0.0):
+        d = ProcessDesc(kind, precision, sqrt_s, m_top, w_top, m_w, w_w, m_h, w_h, alpha, alpha_s, g_fermi,
+                        sigma_k, m_lo, m_hi, sigma_norm)
+        h = ctypes.c_void_p()
+        _check(lib().mem_create_process(ctypes.byref(d), ctypes.byref(h)), "mem_create_process")
+        self.handle = h
+        self.kind = kind
+
+    def set_transfer_functions(self, tfs):
+        arr = (TFDesc * len(tfs))(*tfs)
+        _check(lib().mem_set_transfer_functions(self.handle, arr, len(tfs)), "mem_set_transfer_functions")
+
+    def shape(self):
+        d, n = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mem_process_shape(self.handle, ctypes.byref(d), ctypes.byref(n)), "mem_process_shape")
+        return d.value, n.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.mem_destroy_process(self.handle)
+            self.handle = None
+
+
+def events_struct(comps):
+    """comps: float64 tensor [4, n_obj, n_events] (E, px, py, pz planes),
+    contiguous, on the GPU or on the host."""
+    import torch
+    assert comps.dtype == torch.float64 and comps.is_contiguous() and comps.dim() == 3 and comps.shape[0] == 4
+    n_obj, n_ev = comps.shape[1], comps.shape[2]
+    base = comps.data_ptr()
+    stride = n_obj * n_ev * 8
+    return Events(n_ev, n_obj, base, base + stride, base + 2 * stride, base + 3 * stride, 1 if comps.is_cuda else 0)
+
+
+def to_components(obs):
+    """numpy/torch [n_events, n_obj, 4] -> contiguous float64 [4, n_obj, n_events]"""
+    import torch
+    t = torch.as_tensor(obs, dtype=torch.float64)
+    return t.permute(2, 1, 0).contiguous()
+
+
+def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=1.5, target_rel_err=0.0,
+                     max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
+                     timing=None):
+    """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
+    or host); processes: one Process or a list (one per event); n_points:
+    int or a list per event; timing: optional ctypes (c_double * 4) array.
+    Returns (P, err, status) as torch tensors on the device of `comps`
+    (or writes into `outputs`)."""
+    import torch
+    ev = events_struct(comps)
+    procs = processes if isinstance(processes, (list, tuple)) else [processes]
+    handles = (ctypes.c_void_p * len(procs))(*[p.handle.value for p in procs])
+    npts = [int(n_points)] if isinstance(n_points, int) else [int(v) for v in n_points]
+    npts_arr = (ctypes.c_int64 * len(npts))(*npts)
+    dev = comps.device
+    if outputs is None:
+        P = torch.empty(ev.n_events, dtype=torch.float64, device=dev)
+        err = torch.empty_like(P)
+        status = torch.empty(ev.n_events, dtype=torch.int32, device=dev)
+    else:
+        P, err, status = outputs
+    opt = IntegrateOpts(seed, alpha, target_rel_err, max_iter, _stream_ptr(stream), 1 if P.is_cuda else 0,
+                        iter_out.data_ptr() if iter_out is not None else None,
+                        grid_out.data_ptr() if grid_out is not None else None,
+                        n_iter_out.data_ptr() if n_iter_out is not None else None,
+                        ctypes.cast(timing, ctypes.c_void_p) if timing is not None else None)
+    _check(lib().mem_integrate_events(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
+                                      ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
+                                      ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
+           "mem_integrate_events")
+    return P, err, status
+
+
+def uniforms(seed, it, event, perm, D, n, out, stream=None):
+    _check(lib().mem_uniforms(seed, it, event, perm, D, n, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+           "mem_uniforms")
+    return out
+
+
+def eval_points(process, comps, event, perm, x, f, nsol=None, stream=None):
+    ev = events_struct(comps)
+    _check(lib().mem_eval_points(process.handle, ctypes.byref(ev), event, perm, ctypes.c_void_p(x.data_ptr()),
+                                 x.shape[0], ctypes.c_void_p(f.data_ptr()),
+                                 ctypes.c_void_p(nsol.data_ptr()) if nsol is not None else None,
+                                 _stream_ptr(stream)), "mem_eval_points")
+    return f
+
+
+def vegas_refine(bins, grids, alpha=1.5, stream=None):
+    n_int, D = bins.shape[0], bins.shape[1]
+    _check(lib().mem_vegas_refine(ctypes.c_void_p(bins.data_ptr()), ctypes.c_void_p(grids.data_ptr()), n_int, D,
+                                  alpha, _stream_ptr(stream)), "mem_vegas_refine")
+    return grids

@@ -1,0 +1,109 @@
+// Device building blocks shared by the MEM kernels: counter-based random
+// numbers, the VEGAS map, wavefront reductions and small vector helpers.
+//
+// The MC estimator S_N = V mean f(x_i) and its error (Sec. 2) are fed by a
+// Philox4x32-10 point stream (Salmon et al., SC'11) mapped through a VEGAS
+// grid (Lepage 1978).  Points are generated in registers, never stored.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace memk {
+
+constexpr int kBins = 64;          // VEGAS bins per dimension
+constexpr int kMaxDims = 12;       // largest integration dimension supported
+constexpr int kWave = 64;          // CDNA wavefront width
+
+// ---------------------------------------------------------------- Philox --
+// One Philox4x32-10 block: ten rounds of two 32x32 -> 64 products whose
+// halves are mixed with the other two words and a Weyl-sequence key.
+struct u32x4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ u32x4 philox10(u32x4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
+    uint32_t lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
+    c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// 53-bit uniform in [0,1) from a (hi, lo) word pair.
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo)
+{
+  uint64_t bits = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+  return (double)bits * 0x1.0p-53;
+}
+
+// Uniforms of point k: dims (2b, 2b+1) from counter {k, iter, event, perm*16+b}.
+template <int D>
+__device__ __forceinline__ void point_uniforms(uint64_t seed, uint32_t k, uint32_t iter,
+                                               uint32_t event, uint32_t perm, double (&u)[D])
+{
+#pragma unroll
+  for (int b = 0; 2 * b < D; ++b) {
+    u32x4 w = philox10(u32x4{k, iter, event, perm * 16u + (uint32_t)b},
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+    u[2 * b] = u53(w.x, w.y);
+    if (2 * b + 1 < D) u[2 * b + 1] = u53(w.z, w.w);
+  }
+}
+
+// ------------------------------------------------------------ VEGAS map --
+// x = e_i + frac * width through a fused multiply-add (correctly rounded),
+// Jacobian = prod 64 * width.  `grid` points at D rows of 65 edges (LDS).
+template <int D>
+__device__ __forceinline__ double vegas_map(const double* __restrict__ grid, const double (&u)[D],
+                                            double (&x)[D], int (&bin)[D])
+{
+  double jac = 1.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double t = u[d] * (double)kBins;
+    int i = (int)t;
+    i = i > kBins - 1 ? kBins - 1 : i;
+    double frac = t - (double)i;
+    double e0 = grid[d * (kBins + 1) + i];
+    double width = grid[d * (kBins + 1) + i + 1] - e0;
+    x[d] = __fma_rn(frac, width, e0);
+    jac *= (double)kBins * width;
+    bin[d] = i;
+  }
+  return jac;
+}
+
+// ----------------------------------------------------------- reductions --
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// inclusive prefix sum across a wavefront
+__device__ __forceinline__ double wave_scan(double v)
+{
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    double o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// ------------------------------------------------------ four-vector math --
+struct v4 { double e, x, y, z; };
+__device__ __forceinline__ double mdot(const v4& a, const v4& b)
+{
+  return a.e * b.e - a.x * b.x - a.y * b.y - a.z * b.z;
+}
+__device__ __forceinline__ v4 add(const v4& a, const v4& b) { return v4{a.e + b.e, a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ double norm3(const v4& a) { return sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
+
+}  // namespace memk

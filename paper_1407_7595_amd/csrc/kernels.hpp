@@ -1,0 +1,179 @@
+// Kernels of one VEGAS iteration over many independent integrals.
+//
+// Integration unit: one (event, jet-parton assignment) integral.  Its points
+// of one iteration are split into chunks; a workgroup evaluates one chunk:
+// it stages the integral's VEGAS grid in LDS, generates each point in
+// registers (Philox -> VEGAS map), evaluates the fused integrand (phase-space
+// map, constraint solve, |M|^2, PDFs, TFs, weight), and accumulates sum w,
+// sum w^2 (wavefront shuffles) and the per-(dimension, bin) sums of w^2
+// (LDS atomics).  The chunk's partial sums go to HBM; a second kernel sums
+// them in a fixed order per integral, forms I_j and sigma_j^2, updates the
+// inverse-variance combination and refines the grid (one wavefront per
+// dimension, one lane per bin).
+#pragma once
+#include "device_common.hpp"
+#include "dy.hpp"
+#include "process.hpp"
+#include "tt.hpp"
+
+namespace memk {
+
+constexpr int kBlock = 256;
+
+struct Chunk {
+  int32_t integral;
+  int32_t event;
+  int32_t perm;
+  int32_t count;
+  int64_t start;      // first point index of the chunk inside its integral
+  int64_t part_off;   // offset of its partial sums (2 + D*64 doubles)
+};
+
+struct IntegralDesc {
+  int32_t event;
+  int32_t perm;
+  int32_t dims;
+  int32_t n_chunks;
+  int64_t n_points;   // per iteration
+  int64_t grid_off;   // offset of its D x 65 grid
+  int64_t chunk0;     // first chunk
+};
+
+// per-integral running state
+enum { ST_WSUM = 0, ST_WISUM, ST_ISUM, ST_NITER, ST_NONFINITE, ST_LAST_I, ST_LAST_V, ST_SIZE = 8 };
+
+template <int D>
+__device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)
+{
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) { red[2 * wave] = a; red[2 * wave + 1] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0.0; b = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) { a += red[2 * w]; b += red[2 * w + 1]; }
+  }
+}
+
+template <int KIND, int D, class T>
+__global__ __launch_bounds__(kBlock) void vegas_iter_kernel(ProcParams pp, EventsView ev,
+                                                            const Chunk* __restrict__ chunks,
+                                                            const IntegralDesc* __restrict__ ints,
+                                                            const double* __restrict__ grids,
+                                                            const int32_t* __restrict__ active,
+                                                            uint64_t seed, uint32_t iter,
+                                                            double* __restrict__ parts)
+{
+  __shared__ double sgrid[D * (kBins + 1)];
+  __shared__ double sbins[D * kBins];
+  __shared__ double red[2 * kBlock / kWave];
+  const Chunk ch = chunks[blockIdx.x];
+  if (!active[ch.integral]) return;
+  const int64_t goff = ints[ch.integral].grid_off;
+  for (int i = threadIdx.x; i < D * (kBins + 1); i += kBlock) sgrid[i] = grids[goff + i];
+  for (int i = threadIdx.x; i < D * kBins; i += kBlock) sbins[i] = 0.0;
+  __syncthreads();
+
+  double s1 = 0.0, s2 = 0.0;
+  if constexpr (KIND == kDY) {
+    DYEvent e;
+    dy_load(ev, ch.event, e);
+    for (int k = threadIdx.x; k < ch.count; k += kBlock) {
+      double u[D], x[D];
+      int bin[D];
+      point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
+      double jac = vegas_map<D>(sgrid, u, x, bin);
+      double xx[2] = {x[0], x[1]};
+      double w = dy_integrand(pp, e, xx) * jac;
+      s1 += w;
+      s2 += w * w;
+      if (w != 0.0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
+      }
+    }
+  } else {
+    TTEvent e;
+    tt_load(ev, ch.event, ch.perm, e);
+    for (int k = threadIdx.x; k < ch.count; k += kBlock) {
+      double u[D], x[D];
+      int bin[D];
+      point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
+      double jac = vegas_map<D>(sgrid, u, x, bin);
+      double w = tt_integrand<T>(pp, e, x, nullptr) * jac;
+      s1 += w;
+      s2 += w * w;
+      if (w != 0.0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
+      }
+    }
+  }
+  block_reduce2<D>(s1, s2, red);
+  __syncthreads();
+  double* out = parts + ch.part_off;
+  if (threadIdx.x == 0) { out[0] = s1; out[1] = s2; }
+  for (int i = threadIdx.x; i < D * kBins; i += kBlock) out[2 + i] = sbins[i];
+}
+
+// Damped rebinning of one dimension by one wavefront (lane i = bin i):
+// three-point smoothing of the per-bin sums of w^2, importances
+// m_i = ((1 - rho_i)/ln(1/rho_i))^alpha, then new edges at equal shares of
+// sum m, interpolated linearly inside the old bins (Lepage 1978).  Every
+// wavefront of the block must call this (valid = false for idle ones): it
+// contains block barriers.  d: the 64 sums; e: the 65 edges, updated in
+// place; C, E, M: per-wavefront LDS scratch of 65, 65 and 64 doubles.
+__device__ __forceinline__ void refine_dim_wave(const double* d, double* e, double alpha, bool valid,
+                                                double* C, double* E, double* M)
+{
+  const int i = threadIdx.x & (kWave - 1);
+  double s = 0.0;
+  if (valid) {
+    double di = d[i];
+    double dm = d[i > 0 ? i - 1 : 0], dp = d[i < kBins - 1 ? i + 1 : kBins - 1];
+    if (i == 0) s = 0.5 * (di + dp);
+    else if (i == kBins - 1) s = 0.5 * (dm + di);
+    else s = (dm + di + dp) / 3.0;
+  }
+  const double total = wave_sum(s);
+  const bool go = valid && total > 0.0;
+  double m = 0.0;
+  if (go) {
+    double rho = s / total;
+    if (rho <= 0.0) m = 0.0;
+    else if (rho >= 1.0) m = 1.0;
+    else m = pow((1.0 - rho) / log(1.0 / rho), alpha);
+  }
+  const double cum = wave_scan(m);
+  const double msum = __shfl(cum, kBins - 1, kWave);
+  if (go) {
+    C[i + 1] = cum;
+    M[i] = m;
+    E[i] = e[i];
+    if (i == 0) { C[0] = 0.0; E[kBins] = e[kBins]; }
+  }
+  __syncthreads();
+  if (go) {
+    if (i >= 1) {
+      const double target = msum / (double)kBins * (double)i;
+      double edge = 1.0;
+      if (C[kBins] >= target) {
+        // smallest bin j whose cumulative importance reaches the target
+        int lo = 0, hi = kBins - 1;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (C[mid + 1] >= target) hi = mid; else lo = mid + 1;
+        }
+        edge = E[lo] + (target - C[lo]) / M[lo] * (E[lo + 1] - E[lo]);
+      }
+      e[i] = edge;
+    } else {
+      e[0] = 0.0;
+      e[kBins] = 1.0;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace memk

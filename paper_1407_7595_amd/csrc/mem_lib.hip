@@ -1,0 +1,693 @@
+// libmem: C ABI of the MI355X matrix element method integrator.
+//
+// One call to mem_integrate_events runs the whole per-event MC integration
+// (Sec. 2 estimator, VEGAS adaptation, Sec. 3/4 integrands) on the device:
+// the host only validates, lays out the work list and launches.  Control
+// returns to the host once per iteration at most (in target-accuracy mode,
+// to read the number of integrals still running).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mem.h"
+#include "kernels.hpp"
+
+using namespace memk;
+
+// ---------------------------------------------------------------- errors --
+static thread_local std::string g_last_error;
+
+static mem_status fail(mem_status s, const std::string& msg)
+{
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? MEM_ENOMEM : MEM_EDEVICE,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+// ------------------------------------------------------------- processes --
+struct mem_process_s {
+  mem_process_desc desc;
+  mem_tf_desc tf[5];
+  ProcParams pp;
+};
+
+static TFParams tf_params(const mem_tf_desc& t)
+{
+  TFParams p{};
+  p.s_core = t.sigma_core;
+  p.s_tail = t.kind == MEM_TF_DGAUSS ? t.sigma_tail : t.sigma_core;
+  p.f_tail = t.kind == MEM_TF_DGAUSS ? t.f_tail : 0.0;
+  double smax = std::max(p.s_core, p.s_tail);
+  p.r_lo = std::max(t.r_min, 1.0 - t.window * smax);
+  p.r_hi = 1.0 + t.window * smax;
+  return p;
+}
+
+static void derive(mem_process_s* p)
+{
+  const mem_process_desc& d = p->desc;
+  ProcParams& pp = p->pp;
+  pp = ProcParams{};
+  pp.kind = d.kind;
+  pp.precision = d.precision;
+  pp.sqrt_s = d.sqrt_s;
+  pp.S = d.sqrt_s * d.sqrt_s;
+  pp.m_t = d.m_top; pp.w_t = d.w_top; pp.m_w = d.m_w; pp.w_w = d.w_w;
+  pp.alpha = d.alpha; pp.alpha_s = d.alpha_s; pp.g_fermi = d.g_fermi;
+  pp.sigma_k = d.sigma_k;
+  pp.m_lo = d.m_lo; pp.m_hi = d.m_hi;
+  pp.sigma_norm = d.sigma_norm;
+  pp.tf_mu = tf_params(p->tf[MEM_OBJ_MUON]);
+  pp.tf_b = tf_params(p->tf[MEM_OBJ_BJET]);
+  const double two_pi = 2.0 * M_PI;
+  if (d.kind == MEM_DY_QQ_GAMMA_MUMU) {
+    pp.dims = 2;
+    pp.n_perm = 1;
+    double e2 = 4.0 * M_PI * d.alpha;
+    pp.dy_const = std::pow(two_pi, -2.0) * (2.0 / pp.S) * e2 * e2 / 3.0 * 0.5;
+  } else {
+    pp.dims = 8;
+    pp.n_perm = 2;
+    double mtg = d.m_top * d.w_top, mwg = d.m_w * d.w_w;
+    pp.th0_t = std::atan((0.0 - d.m_top * d.m_top) / mtg);
+    pp.th1_t = std::atan((pp.S - d.m_top * d.m_top) / mtg);
+    pp.th0_w = std::atan((0.0 - d.m_w * d.m_w) / mwg);
+    pp.th1_w = std::atan((pp.S - d.m_w * d.m_w) / mwg);
+    double kbw = std::pow((pp.th1_t - pp.th0_t) / mtg, 2) * std::pow((pp.th1_w - pp.th0_w) / mwg, 2);
+    double gs2 = 4.0 * M_PI * d.alpha_s;
+    double gw2 = 8.0 * d.g_fermi * d.m_w * d.m_w / std::sqrt(2.0);
+    double coup = gs2 * gs2 * std::pow(gw2 / 2.0, 4);
+    // (2 pi)^(4 - 3*6) (2/S) / (2 shat) / (2E_nu 2E_nubar): shat, E's per point
+    pp.tt_const = std::pow(two_pi, -14.0) * (2.0 / pp.S) * 0.5 * 0.25 * coup * kbw;
+  }
+}
+
+extern "C" mem_status mem_create_process(const mem_process_desc* d, mem_process* out)
+{
+  if (!d || !out) return fail(MEM_EINVAL, "null argument");
+  if (d->kind == MEM_TT_SEMILEPTON || d->kind == MEM_TTH_SEMILEPTON)
+    return fail(MEM_EUNSUPPORTED, "process kind not built");
+  if (d->kind != MEM_DY_QQ_GAMMA_MUMU && d->kind != MEM_TT_DILEPTON)
+    return fail(MEM_EINVAL, "unknown process kind");
+  if (!(d->sqrt_s > 0.0)) return fail(MEM_EINVAL, "sqrt_s must be positive");
+  if (d->precision != MEM_FP64 && d->precision != MEM_FP32) return fail(MEM_EINVAL, "bad precision");
+  if (d->kind == MEM_DY_QQ_GAMMA_MUMU) {
+    if (!(d->alpha > 0.0)) return fail(MEM_EINVAL, "alpha must be positive");
+    if (!(d->m_hi > d->m_lo && d->m_lo >= 0.0)) return fail(MEM_EINVAL, "bad mass window");
+    if (d->precision != MEM_FP64) return fail(MEM_EUNSUPPORTED, "Drell-Yan runs in FP64 only");
+  } else {
+    if (!(d->m_top > 0 && d->w_top > 0 && d->m_w > 0 && d->w_w > 0 && d->alpha_s > 0 && d->g_fermi > 0 &&
+          d->sigma_k > 0))
+      return fail(MEM_EINVAL, "masses, widths, couplings and sigma_k must be positive");
+  }
+  if (!(d->sigma_norm >= 0.0)) return fail(MEM_EINVAL, "sigma_norm must be >= 0");
+  mem_process_s* p = new (std::nothrow) mem_process_s;
+  if (!p) return fail(MEM_ENOMEM, "host allocation");
+  p->desc = *d;
+  for (int c = 0; c < 5; ++c) {
+    p->tf[c] = mem_tf_desc{c, MEM_TF_DELTA, 0.0, 0.0, 0.0, 5.0, 0.1};
+  }
+  p->tf[MEM_OBJ_MUON] = mem_tf_desc{MEM_OBJ_MUON, MEM_TF_GAUSS, 0.05, 0.05, 0.0, 5.0, 0.1};
+  p->tf[MEM_OBJ_BJET] = mem_tf_desc{MEM_OBJ_BJET, MEM_TF_GAUSS, 0.15, 0.15, 0.0, 5.0, 0.1};
+  p->tf[MEM_OBJ_LJET] = mem_tf_desc{MEM_OBJ_LJET, MEM_TF_DGAUSS, 0.10, 0.25, 0.2, 5.0, 0.1};
+  p->tf[MEM_OBJ_NEUTRINO] = mem_tf_desc{MEM_OBJ_NEUTRINO, MEM_TF_UNIFORM, 0.0, 0.0, 0.0, 5.0, 0.1};
+  derive(p);
+  *out = p;
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_set_transfer_functions(mem_process p, const mem_tf_desc* tf, int32_t n)
+{
+  if (!p || (!tf && n > 0) || n < 0) return fail(MEM_EINVAL, "null argument or negative count");
+  for (int i = 0; i < n; ++i) {
+    const mem_tf_desc& t = tf[i];
+    if (t.obj_class < 0 || t.obj_class > MEM_OBJ_NEUTRINO) return fail(MEM_EINVAL, "unknown object class");
+    if (t.kind < MEM_TF_DELTA || t.kind > MEM_TF_DGAUSS) return fail(MEM_EINVAL, "unknown TF kind");
+    if (t.kind >= MEM_TF_GAUSS && !(t.sigma_core > 0.0)) return fail(MEM_EINVAL, "sigma_core must be > 0");
+    if (t.kind == MEM_TF_DGAUSS && !(t.sigma_tail > 0.0)) return fail(MEM_EINVAL, "sigma_tail must be > 0");
+    if (t.kind == MEM_TF_DGAUSS && !(t.f_tail >= 0.0 && t.f_tail <= 1.0)) return fail(MEM_EINVAL, "f_tail outside [0,1]");
+    if (!(t.window > 0.0) || !(t.r_min >= 0.0)) return fail(MEM_EINVAL, "window must be > 0 and r_min >= 0");
+    // the integrated classes need an energy-resolving TF
+    if ((t.obj_class == MEM_OBJ_MUON && p->desc.kind == MEM_DY_QQ_GAMMA_MUMU) ||
+        (t.obj_class == MEM_OBJ_BJET && p->desc.kind == MEM_TT_DILEPTON))
+      if (t.kind < MEM_TF_GAUSS) return fail(MEM_EINVAL, "integrated objects need a (double) Gaussian TF");
+  }
+  for (int i = 0; i < n; ++i) p->tf[tf[i].obj_class] = tf[i];
+  derive(p);
+  return MEM_OK;
+}
+
+extern "C" void mem_destroy_process(mem_process p) { delete p; }
+
+extern "C" mem_status mem_process_shape(mem_process p, int32_t* dims, int32_t* n_perm)
+{
+  if (!p) return fail(MEM_EINVAL, "null process");
+  if (dims) *dims = p->pp.dims;
+  if (n_perm) *n_perm = p->pp.n_perm;
+  return MEM_OK;
+}
+
+// ------------------------------------------------------------ kernels ----
+__global__ void init_grids_kernel(double* grids, const IntegralDesc* ints, int n_int)
+{
+  int ig = blockIdx.x;
+  if (ig >= n_int) return;
+  const IntegralDesc in = ints[ig];
+  for (int i = threadIdx.x; i < in.dims * (kBins + 1); i += blockDim.x)
+    grids[in.grid_off + i] = (double)(i % (kBins + 1)) / (double)kBins;
+}
+
+// Sum the chunk partials of each integral in chunk order, form the
+// iteration estimate and its variance, fold it into the inverse-variance
+// combination (iterations >= 1) and refine the grid.
+__global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc* __restrict__ ints,
+                                                             const Chunk* __restrict__ chunks,
+                                                             const double* __restrict__ parts,
+                                                             double* __restrict__ grids,
+                                                             double* __restrict__ state,
+                                                             const int32_t* __restrict__ active,
+                                                             double alpha, uint32_t iter, int n_int,
+                                                             double* __restrict__ iter_out)
+{
+  __shared__ double sb[kMaxDims * kBins];
+  __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
+  const int ig = blockIdx.x;
+  if (!active[ig]) return;
+  const IntegralDesc in = ints[ig];
+  const int D = in.dims;
+  for (int i = threadIdx.x; i < D * kBins; i += kBlock) {
+    double acc = 0.0;
+    for (int c = 0; c < in.n_chunks; ++c) acc += parts[chunks[in.chunk0 + c].part_off + 2 + i];
+    sb[i] = acc;
+  }
+  if (threadIdx.x == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int c = 0; c < in.n_chunks; ++c) {
+      const double* p = parts + chunks[in.chunk0 + c].part_off;
+      s1 += p[0];
+      s2 += p[1];
+    }
+    const double N = (double)in.n_points;
+    const double I = s1 / N;
+    double var = (s2 / N - I * I) / (N - 1.0);
+    if (var < 0.0) var = 0.0;
+    double* st = state + (int64_t)ig * ST_SIZE;
+    if (!isfinite(s1) || !isfinite(s2)) st[ST_NONFINITE] = 1.0;
+    if (iter >= 1) {
+      if (var > 0.0) { st[ST_WSUM] += 1.0 / var; st[ST_WISUM] += I / var; }
+      st[ST_ISUM] += I;
+      st[ST_NITER] += 1.0;
+    }
+    st[ST_LAST_I] = I;
+    st[ST_LAST_V] = var;
+    if (iter_out) {
+      iter_out[((int64_t)iter * n_int + ig) * 2 + 0] = I;
+      iter_out[((int64_t)iter * n_int + ig) * 2 + 1] = var;
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  for (int d0 = 0; d0 < D; d0 += kBlock / kWave) {
+    const int d = d0 + wave;
+    const bool valid = d < D;
+    refine_dim_wave(sb + (valid ? d : 0) * kBins, grids + in.grid_off + (valid ? d : 0) * (kBins + 1), alpha,
+                    valid, scratch[wave], scratch[wave] + (kBins + 1), scratch[wave] + 2 * (kBins + 1));
+  }
+}
+
+// Combined estimate of one integral from its running state.
+__device__ __forceinline__ void integral_estimate(const double* st, double& I, double& var)
+{
+  if (st[ST_WSUM] > 0.0) {
+    I = st[ST_WISUM] / st[ST_WSUM];
+    var = 1.0 / st[ST_WSUM];
+  } else {
+    I = st[ST_NITER] > 0.0 ? st[ST_ISUM] / st[ST_NITER] : st[ST_LAST_I];
+    var = 0.0;
+  }
+}
+
+// Per event: average over permutations (Sec. 3/4), normalise by sigma,
+// optionally retire converged events (target mode).
+__global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t* __restrict__ ev_nperm,
+                             const double* __restrict__ ev_norm, const double* __restrict__ state,
+                             int32_t* __restrict__ active, int n_events, double target, uint32_t iter,
+                             int final_pass, double* P, double* err, int32_t* status, int32_t* n_iter_used,
+                             int32_t* ev_done, int32_t* n_running)
+{
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_events) return;
+  const int64_t i0 = ev_int0[e];
+  const int np = ev_nperm[e];
+  double s = 0.0, v = 0.0;
+  bool bad = false;
+  for (int k = 0; k < np; ++k) {
+    double I, var;
+    const double* st = state + (i0 + k) * ST_SIZE;
+    integral_estimate(st, I, var);
+    s += I;
+    v += var;
+    if (st[ST_NONFINITE] != 0.0 || !isfinite(I)) bad = true;
+  }
+  const double norm = ev_norm[e];
+  const double p = norm * s / np, sd = norm * sqrt(v) / np;
+  if (!final_pass) {
+    // target mode: retire the event once its relative error is reached
+    if (!ev_done[e] && iter >= 2 && (p > 0.0 && sd <= target * p)) {
+      ev_done[e] = (int32_t)iter + 1;
+      for (int k = 0; k < np; ++k) active[i0 + k] = 0;
+    }
+    if (!ev_done[e]) atomicAdd(n_running, 1);
+    return;
+  }
+  P[e] = p;
+  err[e] = sd;
+  int32_t stt = MEM_EV_OK;
+  if (bad) stt = MEM_EV_NONFINITE;
+  else if (s == 0.0) stt = MEM_EV_ZERO_INTEGRAND;
+  else if (target > 0.0 && !ev_done[e]) stt = MEM_EV_NOT_CONVERGED;
+  status[e] = stt;
+  if (n_iter_used) n_iter_used[e] = ev_done[e] ? ev_done[e] : (int32_t)iter;
+}
+
+template <int KIND, int D, class T>
+__global__ __launch_bounds__(kBlock) void eval_points_kernel(ProcParams pp, EventsView ev, int event, int perm,
+                                                             const double* __restrict__ xs, int64_t n,
+                                                             double* __restrict__ f, int32_t* __restrict__ nsol)
+{
+  int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  double x[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) x[d] = xs[k * D + d];
+  if constexpr (KIND == kDY) {
+    DYEvent e;
+    dy_load(ev, event, e);
+    double xx[2] = {x[0], x[1]};
+    f[k] = dy_integrand(pp, e, xx);
+    if (nsol) nsol[k] = 0;
+  } else {
+    TTEvent e;
+    tt_load(ev, event, perm, e);
+    int ns = 0;
+    f[k] = tt_integrand<T>(pp, e, x, &ns);
+    if (nsol) nsol[k] = ns;
+  }
+}
+
+__global__ void uniforms_kernel(uint64_t seed, uint32_t iter, uint32_t event, uint32_t perm, int D, int64_t n,
+                                double* __restrict__ u)
+{
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  for (int b = 0; 2 * b < D; ++b) {
+    u32x4 w = philox10(u32x4{(uint32_t)k, iter, event, perm * 16u + (uint32_t)b}, (uint32_t)seed,
+                       (uint32_t)(seed >> 32));
+    u[k * D + 2 * b] = u53(w.x, w.y);
+    if (2 * b + 1 < D) u[k * D + 2 * b + 1] = u53(w.z, w.w);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void refine_only_kernel(const double* __restrict__ bins,
+                                                             double* __restrict__ grids, int D, double alpha)
+{
+  __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
+  __shared__ double sb[kMaxDims * kBins];
+  const int ig = blockIdx.x;
+  for (int i = threadIdx.x; i < D * kBins; i += kBlock) sb[i] = bins[(int64_t)ig * D * kBins + i];
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  for (int d0 = 0; d0 < D; d0 += kBlock / kWave) {
+    const int d = d0 + wave;
+    const bool valid = d < D;
+    refine_dim_wave(sb + (valid ? d : 0) * kBins, grids + ((int64_t)ig * D + (valid ? d : 0)) * (kBins + 1),
+                    alpha, valid, scratch[wave], scratch[wave] + (kBins + 1), scratch[wave] + 2 * (kBins + 1));
+  }
+}
+
+// ------------------------------------------------------------ helpers ----
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 8); }
+  template <class X> X* as() const { return (X*)p; }
+};
+
+constexpr int64_t kChunkPoints = 4096;   // points per workgroup (16 per thread)
+
+bool is_device_ptr(const void* p)
+{
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+mem_status check_events(const mem_events* ev)
+{
+  if (!ev) return fail(MEM_EINVAL, "null events");
+  if (ev->n_events < 0 || ev->n_obj <= 0) return fail(MEM_EINVAL, "bad event sizes");
+  if (ev->n_events > 0 && (!ev->E || !ev->px || !ev->py || !ev->pz)) return fail(MEM_EINVAL, "null event arrays");
+  if (!ev->on_device) {
+    int64_t n = (int64_t)ev->n_events * ev->n_obj;
+    for (int64_t i = 0; i < n; ++i) {
+      double e = ev->E[i], x = ev->px[i], y = ev->py[i], z = ev->pz[i];
+      if (!std::isfinite(e) || !std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+        return fail(MEM_EINVAL, "non-finite event component");
+      if (!(e > 0.0)) return fail(MEM_EINVAL, "non-positive object energy");
+    }
+  }
+  return MEM_OK;
+}
+
+// Events resident on the device for the duration of a call.
+struct DevEvents {
+  DevBuf buf;
+  EventsView view{};
+  mem_status make(const mem_events* ev, hipStream_t s)
+  {
+    view.n_events = ev->n_events;
+    view.n_obj = ev->n_obj;
+    if (ev->on_device) {
+      view.E = ev->E; view.px = ev->px; view.py = ev->py; view.pz = ev->pz;
+      return MEM_OK;
+    }
+    size_t n = (size_t)ev->n_events * ev->n_obj;
+    HIP_TRY(buf.alloc(4 * n * sizeof(double)));
+    double* d = buf.as<double>();
+    HIP_TRY(hipMemcpyAsync(d, ev->E, n * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d + n, ev->px, n * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d + 2 * n, ev->py, n * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d + 3 * n, ev->pz, n * sizeof(double), hipMemcpyHostToDevice, s));
+    view.E = d; view.px = d + n; view.py = d + 2 * n; view.pz = d + 3 * n;
+    return MEM_OK;
+  }
+};
+
+int n_obj_of(int kind) { return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : 4; }
+
+template <int KIND, int D, class T>
+void launch_iter(const ProcParams& pp, const EventsView& ev, const Chunk* chunks, int64_t n_chunks,
+                 const IntegralDesc* ints, const double* grids, const int32_t* active, uint64_t seed,
+                 uint32_t iter, double* parts, hipStream_t s)
+{
+  if (n_chunks > 0)
+    hipLaunchKernelGGL((vegas_iter_kernel<KIND, D, T>), dim3((unsigned)n_chunks), dim3(kBlock), 0, s, pp, ev,
+                       chunks, ints, grids, active, seed, iter, parts);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------- integrate ----
+extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                           const int64_t* n_points, int32_t n_np, int32_t n_iter,
+                                           const mem_integrate_opts* opt, double* p_out, double* err_out,
+                                           int32_t* status_out)
+{
+  mem_status st = check_events(ev);
+  if (st != MEM_OK) return st;
+  const int n_ev = ev->n_events;
+  if (!hyp || !n_points) return fail(MEM_EINVAL, "null argument");
+  if (n_ev > 0 && (!p_out || !err_out || !status_out)) return fail(MEM_EINVAL, "null output");
+  if (!(n_hyp == 1 || n_hyp == n_ev)) return fail(MEM_EINVAL, "n_hyp must be 1 or n_events");
+  if (!(n_np == 1 || n_np == n_ev)) return fail(MEM_EINVAL, "n_np must be 1 or n_events");
+  mem_integrate_opts o{};
+  o.seed = 0x14077595ull;
+  o.alpha = 1.5;
+  o.max_iter = 64;
+  if (opt) o = *opt;
+  if (!(o.alpha > 0.0)) return fail(MEM_EINVAL, "alpha must be positive");
+  const bool target_mode = o.target_rel_err > 0.0;
+  const int iters = target_mode ? o.max_iter : n_iter;
+  if (iters < 2) return fail(MEM_EINVAL, "at least two iterations are needed");
+  if (iters > 100000) return fail(MEM_EINVAL, "too many iterations");
+  hipStream_t s = (hipStream_t)o.stream;
+  if (n_ev == 0) return MEM_OK;
+
+  // ---- work list: integrals (event x permutation), grouped by kernel ----
+  struct Group { int kind, prec, dims; std::vector<int> ints; };
+  std::vector<Group> groups;
+  std::vector<IntegralDesc> ints;
+  std::vector<int64_t> ev_int0(n_ev);
+  std::vector<int32_t> ev_np(n_ev);
+  std::vector<double> ev_norm(n_ev);
+  std::vector<const ProcParams*> int_pp;
+  int64_t grid_total = 0;
+  for (int e = 0; e < n_ev; ++e) {
+    const mem_process p = hyp[n_hyp == 1 ? 0 : e];
+    if (!p) return fail(MEM_EINVAL, "null process handle");
+    if (ev->n_obj < n_obj_of(p->desc.kind)) return fail(MEM_EINVAL, "n_obj too small for the process kind");
+    const int64_t npts = n_points[n_np == 1 ? 0 : e];
+    const int np = p->pp.n_perm;
+    const int64_t per = (npts + np - 1) / np;
+    if (per < 2) return fail(MEM_EINVAL, "n_points too small");
+    if (per > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "n_points exceeds 2^32 per permutation");
+    ev_int0[e] = (int64_t)ints.size();
+    ev_np[e] = np;
+    ev_norm[e] = p->desc.sigma_norm > 0.0 ? 1.0 / p->desc.sigma_norm : 1.0;
+    int gi = -1;
+    for (size_t g = 0; g < groups.size(); ++g)
+      if (groups[g].kind == p->pp.kind && groups[g].prec == p->pp.precision) gi = (int)g;
+    if (gi < 0) { groups.push_back(Group{p->pp.kind, p->pp.precision, p->pp.dims, {}}); gi = (int)groups.size() - 1; }
+    for (int k = 0; k < np; ++k) {
+      IntegralDesc d{};
+      d.event = e; d.perm = k; d.dims = p->pp.dims; d.n_points = per;
+      d.grid_off = grid_total;
+      grid_total += (int64_t)p->pp.dims * (kBins + 1);
+      groups[gi].ints.push_back((int)ints.size());
+      ints.push_back(d);
+      int_pp.push_back(&p->pp);
+    }
+  }
+  const int n_int = (int)ints.size();
+  // chunks, contiguous per group so that one launch covers one group
+  std::vector<Chunk> chunks;
+  std::vector<int64_t> group_c0(groups.size()), group_nc(groups.size());
+  int64_t part_total = 0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    group_c0[g] = (int64_t)chunks.size();
+    for (int ig : groups[g].ints) {
+      IntegralDesc& d = ints[ig];
+      d.chunk0 = (int64_t)chunks.size();
+      d.n_chunks = 0;
+      for (int64_t s0 = 0; s0 < d.n_points; s0 += kChunkPoints) {
+        Chunk c{};
+        c.integral = ig; c.event = d.event; c.perm = d.perm;
+        c.count = (int32_t)std::min<int64_t>(kChunkPoints, d.n_points - s0);
+        c.start = s0;
+        c.part_off = part_total;
+        part_total += 2 + (int64_t)d.dims * kBins;
+        chunks.push_back(c);
+        d.n_chunks++;
+      }
+    }
+    group_nc[g] = (int64_t)chunks.size() - group_c0[g];
+  }
+
+  DevEvents dev;
+  st = dev.make(ev, s);
+  if (st != MEM_OK) return st;
+  DevBuf b_ints, b_chunks, b_grids, b_parts, b_state, b_active, b_evi0, b_evnp, b_evnorm, b_done, b_run, b_P,
+      b_err, b_status;
+  HIP_TRY(b_ints.alloc(ints.size() * sizeof(IntegralDesc)));
+  HIP_TRY(b_chunks.alloc(chunks.size() * sizeof(Chunk)));
+  HIP_TRY(b_grids.alloc(grid_total * sizeof(double)));
+  HIP_TRY(b_parts.alloc(part_total * sizeof(double)));
+  HIP_TRY(b_state.alloc((size_t)n_int * ST_SIZE * sizeof(double)));
+  HIP_TRY(b_active.alloc((size_t)n_int * sizeof(int32_t)));
+  HIP_TRY(b_evi0.alloc((size_t)n_ev * sizeof(int64_t)));
+  HIP_TRY(b_evnp.alloc((size_t)n_ev * sizeof(int32_t)));
+  HIP_TRY(b_evnorm.alloc((size_t)n_ev * sizeof(double)));
+  HIP_TRY(b_done.alloc((size_t)n_ev * sizeof(int32_t)));
+  HIP_TRY(b_run.alloc(sizeof(int32_t)));
+  const bool out_dev = o.outputs_on_device != 0;
+  if (!out_dev) {
+    HIP_TRY(b_P.alloc(n_ev * sizeof(double)));
+    HIP_TRY(b_err.alloc(n_ev * sizeof(double)));
+    HIP_TRY(b_status.alloc(n_ev * sizeof(int32_t)));
+  }
+  std::vector<int32_t> ones(n_int, 1);
+  HIP_TRY(hipMemcpyAsync(b_ints.p, ints.data(), ints.size() * sizeof(IntegralDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_chunks.p, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_active.p, ones.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_evi0.p, ev_int0.data(), n_ev * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_evnp.p, ev_np.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_evnorm.p, ev_norm.data(), n_ev * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(b_state.p, 0, (size_t)n_int * ST_SIZE * sizeof(double), s));
+  HIP_TRY(hipMemsetAsync(b_done.p, 0, (size_t)n_ev * sizeof(int32_t), s));
+  hipLaunchKernelGGL(init_grids_kernel, dim3(n_int), dim3(kBlock), 0, s, b_grids.as<double>(),
+                     b_ints.as<IntegralDesc>(), n_int);
+  HIP_TRY(hipGetLastError());
+
+  const int ev_blocks = (n_ev + 255) / 256;
+  int used_iters = iters;
+  // optional timing of the integrand kernel: one event pair per launch
+  std::vector<hipEvent_t> tev;
+  double n_evals = 0.0;
+  auto wall0 = std::chrono::steady_clock::now();
+  auto cleanup_events = [&]() { for (hipEvent_t e : tev) (void)hipEventDestroy(e); };
+  for (int j = 0; j < iters; ++j) {
+    for (size_t g = 0; g < groups.size(); ++g) {
+      const Group& G = groups[g];
+      if (o.timing_out) {
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        tev.push_back(a);
+        tev.push_back(b);
+        HIP_TRY(hipEventRecord(a, s));
+        for (int ig : G.ints) n_evals += (double)ints[ig].n_points;
+      }
+      const ProcParams& pp = *int_pp[G.ints[0]];
+      const Chunk* cptr = b_chunks.as<Chunk>() + group_c0[g];
+      if (G.kind == MEM_DY_QQ_GAMMA_MUMU)
+        launch_iter<kDY, 2, double>(pp, dev.view, cptr, group_nc[g], b_ints.as<IntegralDesc>(),
+                                    b_grids.as<double>(), b_active.as<int32_t>(), o.seed, (uint32_t)j,
+                                    b_parts.as<double>(), s);
+      else if (G.prec == MEM_FP32)
+        launch_iter<kTT, 8, float>(pp, dev.view, cptr, group_nc[g], b_ints.as<IntegralDesc>(),
+                                   b_grids.as<double>(), b_active.as<int32_t>(), o.seed, (uint32_t)j,
+                                   b_parts.as<double>(), s);
+      else
+        launch_iter<kTT, 8, double>(pp, dev.view, cptr, group_nc[g], b_ints.as<IntegralDesc>(),
+                                    b_grids.as<double>(), b_active.as<int32_t>(), o.seed, (uint32_t)j,
+                                    b_parts.as<double>(), s);
+      HIP_TRY(hipGetLastError());
+      if (o.timing_out) HIP_TRY(hipEventRecord(tev.back(), s));
+    }
+    hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, s, b_ints.as<IntegralDesc>(),
+                       b_chunks.as<Chunk>(), b_parts.as<double>(), b_grids.as<double>(), b_state.as<double>(),
+                       b_active.as<int32_t>(), o.alpha, (uint32_t)j, n_int, o.iter_out);
+    HIP_TRY(hipGetLastError());
+    if (target_mode) {
+      HIP_TRY(hipMemsetAsync(b_run.p, 0, sizeof(int32_t), s));
+      hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, s, b_evi0.as<int64_t>(),
+                         b_evnp.as<int32_t>(), b_evnorm.as<double>(), b_state.as<double>(),
+                         b_active.as<int32_t>(), n_ev, o.target_rel_err, (uint32_t)j, 0, nullptr, nullptr,
+                         nullptr, nullptr, b_done.as<int32_t>(), b_run.as<int32_t>());
+      HIP_TRY(hipGetLastError());
+      int32_t running = 0;
+      HIP_TRY(hipMemcpyAsync(&running, b_run.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (running == 0) { used_iters = j + 1; break; }
+    }
+  }
+  double* P = out_dev ? p_out : b_P.as<double>();
+  double* E = out_dev ? err_out : b_err.as<double>();
+  int32_t* S = out_dev ? status_out : b_status.as<int32_t>();
+  hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, s, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
+                     b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
+                     target_mode ? o.target_rel_err : 0.0, (uint32_t)used_iters, 1, P, E, S, o.n_iter_out,
+                     b_done.as<int32_t>(), b_run.as<int32_t>());
+  HIP_TRY(hipGetLastError());
+  if (o.grid_out)
+    HIP_TRY(hipMemcpyAsync(o.grid_out, b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!out_dev) {
+    HIP_TRY(hipMemcpyAsync(p_out, P, n_ev * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(err_out, E, n_ev * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(status_out, S, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  // the work buffers are freed on return: wait for the stream
+  HIP_TRY(hipStreamSynchronize(s));
+  if (o.timing_out) {
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < tev.size(); i += 2) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, tev[i], tev[i + 1]));
+      ms += t;
+    }
+    cleanup_events();
+    o.timing_out[0] = ms;
+    o.timing_out[1] = (double)(tev.size() / 2);
+    o.timing_out[2] = n_evals;
+    o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+  }
+  return MEM_OK;
+}
+
+// ------------------------------------------------------ building blocks ----
+extern "C" mem_status mem_uniforms(uint64_t seed, uint32_t iter, uint32_t event, uint32_t perm, int32_t D,
+                                   int64_t n, double* u, void* stream)
+{
+  if (!u || D <= 0 || D > kMaxDims || n < 0) return fail(MEM_EINVAL, "bad arguments");
+  if (n > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "n exceeds 2^32");
+  if (n == 0) return MEM_OK;
+  hipLaunchKernelGGL(uniforms_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, seed,
+                     iter, event, perm, D, n, u);
+  HIP_TRY(hipGetLastError());
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32_t event, int32_t perm,
+                                      const double* x, int64_t n, double* f, int32_t* nsol, void* stream)
+{
+  if (!p || !x || !f) return fail(MEM_EINVAL, "null argument");
+  mem_status st = check_events(ev);
+  if (st != MEM_OK) return st;
+  if (event < 0 || event >= ev->n_events) return fail(MEM_EINVAL, "event index out of range");
+  if (perm < 0 || perm >= p->pp.n_perm) return fail(MEM_EINVAL, "permutation out of range");
+  if (ev->n_obj < n_obj_of(p->desc.kind)) return fail(MEM_EINVAL, "n_obj too small for the process kind");
+  if (n < 0) return fail(MEM_EINVAL, "negative n");
+  if (n == 0) return MEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  DevEvents dev;
+  st = dev.make(ev, s);
+  if (st != MEM_OK) return st;
+  dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
+  if (p->desc.kind == MEM_DY_QQ_GAMMA_MUMU)
+    hipLaunchKernelGGL((eval_points_kernel<kDY, 2, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
+                       x, n, f, nsol);
+  else if (p->desc.precision == MEM_FP32)
+    hipLaunchKernelGGL((eval_points_kernel<kTT, 8, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
+                       x, n, f, nsol);
+  else
+    hipLaunchKernelGGL((eval_points_kernel<kTT, 8, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
+  HIP_TRY(hipGetLastError());
+  if (!ev->on_device) HIP_TRY(hipStreamSynchronize(s));   // the staged copy is freed on return
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_vegas_refine(const double* bins, double* grids, int32_t n_int, int32_t D, double alpha,
+                                       void* stream)
+{
+  if (!bins || !grids || n_int < 0 || D <= 0 || D > kMaxDims || !(alpha > 0.0))
+    return fail(MEM_EINVAL, "bad arguments");
+  if (n_int == 0) return MEM_OK;
+  hipLaunchKernelGGL(refine_only_kernel, dim3(n_int), dim3(kBlock), 0, (hipStream_t)stream, bins, grids, D, alpha);
+  HIP_TRY(hipGetLastError());
+  return MEM_OK;
+}
+
+extern "C" const char* mem_status_string(mem_status s)
+{
+  switch (s) {
+    case MEM_OK: return "ok";
+    case MEM_EINVAL: return "invalid argument";
+    case MEM_ENOMEM: return "out of memory";
+    case MEM_EDEVICE: return "device error";
+    case MEM_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+extern "C" mem_status mem_last_error(char* buf, size_t n)
+{
+  if (!buf || n == 0) return MEM_EINVAL;
+  std::snprintf(buf, n, "%s", g_last_error.c_str());
+  return MEM_OK;
+}

@@ -1,0 +1,54 @@
+// Process parameters as the kernels see them, and the per-event view.
+#pragma once
+#include <stdint.h>
+
+namespace memk {
+
+enum Kind : int32_t { kDY = 1, kTT = 2 };
+
+// One transfer function for the energy of a measured object, Gaussian or
+// double Gaussian in r = E_meas / E_true (Sec. 1, after Eq. 3).
+struct TFParams {
+  double s_core, s_tail, f_tail;  // relative widths and tail fraction
+  double r_lo, r_hi;              // integration window in r
+};
+
+// Everything the integrand needs about a hypothesis, precomputed on the host.
+struct ProcParams {
+  int32_t kind;
+  int32_t precision;               // 0: FP64 matrix element stage, 1: FP32
+  int32_t dims;
+  int32_t n_perm;
+  double sqrt_s, S;
+  double m_t, w_t, m_w, w_w;
+  double alpha, alpha_s, g_fermi;
+  double sigma_k;
+  double m_lo, m_hi;
+  double sigma_norm;
+  TFParams tf_mu;                  // Drell-Yan muons
+  TFParams tf_b;                   // tt b-jets
+  // Breit-Wigner tan maps q2 = M^2 + M Gamma tan(theta), theta in [th0, th1]
+  double th0_t, th1_t, th0_w, th1_w;
+  // constant factors of the tt weight: couplings, (2 pi) powers, the
+  // product of the four (th1 - th0)/(M Gamma) that remain after the
+  // propagators cancel against the map Jacobians
+  double tt_const;
+  // Drell-Yan: (2 pi)^-2 (2/S) (4 pi alpha)^2 / 3 / 2
+  double dy_const;
+};
+
+struct EventsView {
+  const double* E;
+  const double* px;
+  const double* py;
+  const double* pz;
+  int32_t n_events;
+  int32_t n_obj;
+  __device__ __forceinline__ void load(int obj, int ev, double& e, double& x, double& y, double& z) const
+  {
+    int64_t i = (int64_t)obj * n_events + ev;
+    e = E[i]; x = px[i]; y = py[i]; z = pz[i];
+  }
+};
+
+}  // namespace memk

@@ -1,0 +1,206 @@
+// Tree-level |M|^2 of gg, q qbar -> t tbar -> b l+ nu bbar l- nubar with
+// full spin correlations, in two-component (Weyl) spinor form.
+//
+// The paper evaluates the matrix element inside the integrand kernel for
+// every phase-space point (Sec. 4) with generated HELAS-style code.  Here
+// the amplitudes are written by hand for this process, exploiting its
+// structure:
+//  * massless b, l, nu with V-A couplings: each decay chain has a single
+//    helicity configuration, and the W current contracted with sigma-bar is
+//    the rank-one matrix 2 (eps^T nu*)(l^T eps) (Fierz), so the decayed top
+//    acts on the production vertex as one Dirac row
+//        R = (m r, r (p_t.sigma)),  r = 2 <b|eps^T|nu*> (eps^T l)^T
+//    and the decayed antitop as one Dirac column
+//        C = (-(p_tbar.sigma) c, m c),  c = 2 (eps^T lbar*) (nubar^T eps bbar);
+//  * gluons along +-z in the frame where the hard system has no transverse
+//    momentum: the helicity polarisations make eps.sigma and eps.sigma-bar
+//    single-entry 2x2 matrices, and the s-channel triple-gluon term reduces
+//    to (eps1.eps2) R (k1 - k2)-slash C / s.
+// Colour: A = T^aT^b A12 + T^bT^a A21, summed |A|^2 =
+// 16/3 (|A12|^2 + |A21|^2) - 4/3 Re(A12 A21*); q qbar: 2 |A|^2.
+// The four Breit-Wigner denominators are NOT included: they cancel against
+// the Jacobians of the propagator-aligned maps (Sec. 3).
+#pragma once
+#include "device_common.hpp"
+
+namespace memk {
+
+template <class T> struct cx { T re, im; };
+template <class T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <class T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <class T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <class T> __device__ __forceinline__ T abs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+template <class T> struct sp { cx<T> a, b; };   // two-component spinor
+
+// lambda(p): (p.sigma-bar) lambda = 0, lambda lambda^dagger = p.sigma
+// (the left-handed massless solution, normalised to |lambda|^2 = 2E).
+// E +- p_z is formed in FP64 on the side without cancellation.
+template <class T>
+__device__ __forceinline__ sp<T> lam(const v4& p)
+{
+  if (p.z >= 0.0) {
+    double ep = p.e + p.z;
+    double n = 1.0 / sqrt(ep);
+    return sp<T>{{T(-p.x * n), T(p.y * n)}, {T(ep * n), T(0)}};
+  }
+  double em = p.e - p.z;
+  double n = 1.0 / sqrt(em);
+  return sp<T>{{T(em * n), T(0)}, {T(-p.x * n), T(-p.y * n)}};
+}
+// lambda-tilde(p): (p.sigma) lt = 0 (right-handed), |lt|^2 = 2E
+template <class T>
+__device__ __forceinline__ sp<T> lamt(const v4& p)
+{
+  if (p.z >= 0.0) {
+    double ep = p.e + p.z;
+    double n = 1.0 / sqrt(ep);
+    return sp<T>{{T(ep * n), T(0)}, {T(p.x * n), T(p.y * n)}};
+  }
+  double em = p.e - p.z;
+  double n = 1.0 / sqrt(em);
+  return sp<T>{{T(p.x * n), T(-p.y * n)}, {T(em * n), T(0)}};
+}
+// eps^T v with eps = [[0,1],[-1,0]]: (-v_b, v_a)
+template <class T> __device__ __forceinline__ sp<T> epsT(sp<T> v) { return sp<T>{-v.b, v.a}; }
+template <class T> __device__ __forceinline__ sp<T> cj(sp<T> v) { return sp<T>{conj(v.a), conj(v.b)}; }
+
+// row times (p.sigma) and (p.sigma) times column; p.sigma =
+// [[p0-p3, -(p1 - i p2)], [-(p1 + i p2), p0+p3]]
+template <class T> struct mom { T e, x, y, z; };
+template <class T>
+__device__ __forceinline__ sp<T> row_psig(sp<T> r, const mom<T>& p)
+{
+  cx<T> m00{p.e - p.z, T(0)}, m01{-p.x, p.y}, m10{-p.x, -p.y}, m11{p.e + p.z, T(0)};
+  return sp<T>{r.a * m00 + r.b * m10, r.a * m01 + r.b * m11};
+}
+template <class T>
+__device__ __forceinline__ sp<T> psig_col(const mom<T>& p, sp<T> c)
+{
+  cx<T> m00{p.e - p.z, T(0)}, m01{-p.x, p.y}, m10{-p.x, -p.y}, m11{p.e + p.z, T(0)};
+  return sp<T>{m00 * c.a + m01 * c.b, m10 * c.a + m11 * c.b};
+}
+// (p.sigma-bar) entries: [[p0+p3, p1 - i p2], [p1 + i p2, p0-p3]]
+
+// Dirac row / column in chiral blocks (L, R)
+template <class T> struct drow { sp<T> L, R; };
+
+// Decayed top row and antitop column (see header comment).
+template <class T>
+__device__ __forceinline__ void decay_rows(const v4& b, const v4& lp, const v4& nu, const v4& bb,
+                                           const v4& lm, const v4& nub, const mom<T>& pt,
+                                           const mom<T>& ptb, T mt, drow<T>& R, drow<T>& C)
+{
+  sp<T> lb = lam<T>(b), ll = lam<T>(lp), ln = lam<T>(nu);
+  sp<T> lbb = lam<T>(bb), llm = lam<T>(lm), lnb = lam<T>(nub);
+  // r = 2 (lambda_b^dagger eps^T lambda_nu^*) (eps^T lambda_l)^T
+  sp<T> al = epsT(cj(ln));
+  cx<T> st = T(2) * (conj(lb.a) * al.a + conj(lb.b) * al.b);
+  sp<T> be = epsT(ll);
+  sp<T> r{st * be.a, st * be.b};
+  R.L = sp<T>{mt * r.a, mt * r.b};
+  R.R = row_psig(r, pt);
+  // c = 2 (eps^T lambda_lm^*) (lambda_nub^T eps lambda_bb)
+  sp<T> bq = epsT(lnb);
+  cx<T> sb = T(2) * (bq.a * lbb.a + bq.b * lbb.b);
+  sp<T> al2 = epsT(cj(llm));
+  sp<T> c{sb * al2.a, sb * al2.b};
+  sp<T> pc = psig_col(ptb, c);
+  C.L = sp<T>{-pc.a, -pc.b};
+  C.R = sp<T>{mt * c.a, mt * c.b};
+}
+
+template <class T> __device__ __forceinline__ cx<T> dot2(sp<T> r, sp<T> c) { return r.a * c.a + r.b * c.b; }
+
+// R (q-slash + m) ... amplitude of one ordering for gluon helicity labels
+// (h1 on the top side, h2 on the antitop side): R e1-slash (q-slash + m)
+// e2-slash C.  eps(+) = (0,1,i,0)/sqrt2, eps(-) = (0,1,-i,0)/sqrt2.
+template <class T>
+__device__ __forceinline__ cx<T> chain_amp(const drow<T>& R, const drow<T>& C, const mom<T>& q, T mt,
+                                           int h1, int h2)
+{
+  const T s2 = T(1.41421356237309504880);
+  // w1 = R_L (e1.sigma), w2 = R_R (e1.sigma-bar): one nonzero entry each
+  //  h = +: e.sigma = [[0,-s2],[0,0]], e.sigma-bar = [[0,s2],[0,0]]
+  //  h = -: e.sigma = [[0,0],[-s2,0]], e.sigma-bar = [[0,0],[s2,0]]
+  // u1 = (e2.sigma-bar) C_L, u2 = (e2.sigma) C_R
+  // A = w1 . (m u1 + Qbar u2) + w2 . (Q u1 + m u2)
+  cx<T> w1, w2;       // the single nonzero entry; index = (h1 == + ? 1 : 0)
+  cx<T> u1, u2;       // single nonzero entry; index = (h2 == + ? 0 : 1)
+  if (h1 == 0) { w1 = -s2 * R.L.a; w2 = s2 * R.R.a; } else { w1 = -s2 * R.L.b; w2 = s2 * R.R.b; }
+  if (h2 == 0) { u1 = s2 * C.L.b; u2 = -s2 * C.R.b; } else { u1 = s2 * C.L.a; u2 = -s2 * C.R.a; }
+  const int iw = (h1 == 0) ? 1 : 0;   // column of w
+  const int iu = (h2 == 0) ? 0 : 1;   // row of u
+  // Q = q.sigma, Qbar = q.sigma-bar, entry [iw][iu]
+  cx<T> Q, Qb;
+  if (iw == 0 && iu == 0) { Q = cx<T>{q.e - q.z, T(0)}; Qb = cx<T>{q.e + q.z, T(0)}; }
+  else if (iw == 0 && iu == 1) { Q = cx<T>{-q.x, q.y}; Qb = cx<T>{q.x, -q.y}; }
+  else if (iw == 1 && iu == 0) { Q = cx<T>{-q.x, -q.y}; Qb = cx<T>{q.x, q.y}; }
+  else { Q = cx<T>{q.e + q.z, T(0)}; Qb = cx<T>{q.e - q.z, T(0)}; }
+  // w . (m u1 e_iu + Qbar[:,iu] u2): only component iw of the vector matters
+  cx<T> v1 = (iw == iu) ? (mt * u1 + Qb * u2) : (Qb * u2);
+  cx<T> v2 = (iw == iu) ? (Q * u1 + mt * u2) : (Q * u1);
+  return w1 * v1 + w2 * v2;
+}
+
+// sum over gluon helicities and colours of |A|^2 for g(k1) g(k2) -> t tbar
+// (k1 = (a,0,0,a), k2 = (bm,0,0,-bm)); R, C from decay_rows.
+template <class T>
+__device__ __forceinline__ T gg_sum(const drow<T>& R, const drow<T>& C, const mom<T>& pt, T a, T bm, T mt)
+{
+  mom<T> q1{pt.e - a, pt.x, pt.y, pt.z - a};     // p_t - k1
+  mom<T> q2{pt.e - bm, pt.x, pt.y, pt.z + bm};   // p_t - k2
+  T mt2 = mt * mt;
+  T Dt = (q1.e * q1.e - q1.x * q1.x - q1.y * q1.y - q1.z * q1.z) - mt2;
+  T Du = (q2.e * q2.e - q2.x * q2.x - q2.y * q2.y - q2.z * q2.z) - mt2;
+  T iDt = T(1) / Dt, iDu = T(1) / Du;
+  T s = T(4) * a * bm;
+  // R (k1-k2)-slash C = R_L (K.sigma) C_R + R_R (K.sigma-bar) C_L,
+  // K.sigma = diag(-2bm, 2a), K.sigma-bar = diag(2a, -2bm)
+  cx<T> rkc = (T(-2) * bm) * (R.L.a * C.R.a) + (T(2) * a) * (R.L.b * C.R.b)
+            + (T(2) * a) * (R.R.a * C.L.a) + (T(-2) * bm) * (R.R.b * C.L.b);
+  cx<T> sch = (T(1) / s) * rkc;
+  T sum = T(0);
+#pragma unroll
+  for (int h1 = 0; h1 < 2; ++h1)
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      cx<T> at = iDt * chain_amp(R, C, q1, mt, h1, h2);
+      cx<T> au = iDu * chain_amp(R, C, q2, mt, h2, h1);
+      // eps1.eps2 = -1 for opposite labels, 0 for equal ones
+      cx<T> a12 = (h1 != h2) ? at - sch : at;
+      cx<T> a21 = (h1 != h2) ? au + sch : au;
+      cx<T> x = a12 * conj(a21);
+      sum += T(16.0 / 3.0) * (abs2(a12) + abs2(a21)) - T(4.0 / 3.0) * x.re;
+    }
+  return sum;
+}
+
+// q(kq) qbar(kqb) -> t tbar through one s-channel gluon, summed over the
+// two non-vanishing quark helicities and colours (factor 2).
+template <class T>
+__device__ __forceinline__ T qq_sum(const drow<T>& R, const drow<T>& C, const v4& kq, const v4& kqb)
+{
+  // left-handed current: J.sigma-bar = 2 (eps^T lqb*)(lq^T eps),
+  //                      J.sigma     = 2 lq lqb^dagger
+  // right-handed:        J.sigma     = 2 (eps^T ltqb*)(ltq^T eps),
+  //                      J.sigma-bar = 2 ltq ltqb^dagger
+  // R J-slash C = R_L (J.sigma) C_R + R_R (J.sigma-bar) C_L
+  sp<T> lq = lam<T>(kq), lqb = lam<T>(kqb), tq = lamt<T>(kq), tqb = lamt<T>(kqb);
+  double s = 2.0 * mdot(kq, kqb);
+  T is = T(1.0 / s);
+  // left
+  sp<T> e1 = epsT(cj(lqb)), e2 = epsT(lq);      // J.sigma-bar = 2 e1 e2^T
+  cx<T> aL = T(2) * (dot2(R.L, lq) * dot2(cj(lqb), C.R)) + T(2) * (dot2(R.R, e1) * dot2(e2, C.L));
+  sp<T> f1 = epsT(cj(tqb)), f2 = epsT(tq);      // J.sigma = 2 f1 f2^T
+  cx<T> aR = T(2) * (dot2(R.L, f1) * dot2(f2, C.R)) + T(2) * (dot2(R.R, tq) * dot2(cj(tqb), C.L));
+  return T(2) * (abs2(aL) + abs2(aR)) * is * is;
+}
+
+}  // namespace memk

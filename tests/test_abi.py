@@ -1,0 +1,101 @@
+"""The C-ABI library loads and exports what include/mem.h declares; host
+side validation (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mem.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mem_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def mem():
+    import paper_1407_7595_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.fail("libmem.so is not built (run __graft_entry__.build())")
+    m.lib()
+    return m
+
+
+def test_exports_every_declared_symbol(mem):
+    names = declared_functions()
+    assert len(names) >= 10
+    assert set(names) == set(mem.EXPORTS)
+    L = ctypes.CDLL(mem.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(mem):
+    L = mem.lib()
+    assert L.mem_status_string(0) == b"ok"
+    assert L.mem_status_string(1) == b"invalid argument"
+
+
+def test_create_process_validation(mem):
+    good = mem.Process(mem.MEM_TT_DILEPTON)
+    assert good.shape() == (8, 2)
+    dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    assert dy.shape() == (2, 1)
+    with pytest.raises(mem.MemError) as e:
+        mem.Process(99)
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:
+        mem.Process(mem.MEM_TT_DILEPTON, w_top=0.0)
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:
+        mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64, m_lo=120.0, m_hi=60.0)
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:
+        mem.Process(mem.MEM_TTH_SEMILEPTON)
+    assert e.value.status == mem.MEM_EUNSUPPORTED
+    L = mem.lib()
+    assert L.mem_create_process(None, None) == mem.MEM_EINVAL
+
+
+def test_transfer_function_validation(mem):
+    p = mem.Process(mem.MEM_TT_DILEPTON)
+    ok = mem.TFDesc(mem.MEM_OBJ_BJET, mem.MEM_TF_DGAUSS, 0.1, 0.25, 0.2, 5.0, 0.1)
+    p.set_transfer_functions([ok])
+    for bad in (mem.TFDesc(7, mem.MEM_TF_GAUSS, 0.1, 0.1, 0.0, 5.0, 0.1),
+                mem.TFDesc(mem.MEM_OBJ_BJET, mem.MEM_TF_GAUSS, 0.0, 0.1, 0.0, 5.0, 0.1),
+                mem.TFDesc(mem.MEM_OBJ_BJET, mem.MEM_TF_DGAUSS, 0.1, 0.25, 1.5, 5.0, 0.1),
+                mem.TFDesc(mem.MEM_OBJ_BJET, mem.MEM_TF_DELTA, 0.1, 0.1, 0.0, 5.0, 0.1),
+                mem.TFDesc(mem.MEM_OBJ_BJET, mem.MEM_TF_GAUSS, 0.1, 0.1, 0.0, -1.0, 0.1)):
+        with pytest.raises(mem.MemError) as e:
+            p.set_transfer_functions([bad])
+        assert e.value.status == mem.MEM_EINVAL
+
+
+def test_integrate_rejects_bad_host_events_before_any_launch(mem):
+    import numpy as np
+    import torch
+    p = mem.Process(mem.MEM_TT_DILEPTON)
+    obs = np.ones((3, 4, 4))
+    obs[1, 2, 0] = np.nan
+    comps = mem.to_components(obs)
+    with pytest.raises(mem.MemError) as e:
+        mem.integrate_events(comps, p, 1000, 3)
+    assert e.value.status == mem.MEM_EINVAL
+    obs[1, 2, 0] = -5.0
+    with pytest.raises(mem.MemError) as e:
+        mem.integrate_events(mem.to_components(obs), p, 1000, 3)
+    assert e.value.status == mem.MEM_EINVAL
+    good = mem.to_components(np.ones((3, 4, 4)))
+    with pytest.raises(mem.MemError) as e:          # one iteration is not enough
+        mem.integrate_events(good, p, 1000, 1)
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:          # too few objects for tt
+        mem.integrate_events(mem.to_components(np.ones((3, 2, 4))), p, 1000, 3)
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:          # two hypotheses for three events
+        mem.integrate_events(good, [p, p], 1000, 3)
+    assert e.value.status == mem.MEM_EINVAL

@@ -1,0 +1,304 @@
+"""GPU (libmem, HIP) vs the FP64 oracle on identical inputs.
+
+Bars: bit-exact for the point stream and the VEGAS map inputs; FP64
+integrands within 1e-10 relative; the FP32 tt integrand within 1e-5
+relative on every point the oracle does not flag as ill-conditioned; VEGAS
+refinement within 1e-12; iteration sums at the integrand tolerance; final
+estimates by a pull test.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import events
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mem():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1407_7595_amd as m
+    m.lib()
+    return m
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+# ------------------------------------------------------------- RNG / map ----
+@pytest.mark.parametrize("D", [2, 7, 8])
+def test_uniforms_bit_exact(mem, D):
+    for seed, it, ev, perm, n in ((0x14077595, 0, 0, 0, 3000), (2**63 + 12345, 5, 77, 1, 2500),
+                                  (1, 63, 2**20, 23, 1001)):
+        say(f"uniforms D={D} seed={seed} it={it} ev={ev} perm={perm} n={n}")
+        out = torch.empty(n * D, dtype=torch.float64, device="cuda")
+        mem.uniforms(seed, it, ev, perm, D, n, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(n, D)
+        for k in list(range(0, n, max(1, n // 200))) + [n - 1]:
+            want = oracle.uniforms(seed, k, it, ev, perm, D)
+            assert np.array_equal(got[k], want), (k, got[k], want)
+
+
+def test_refine_matches_oracle(mem):
+    rng = np.random.default_rng(11)
+    n_int, D = 5, 3
+    bins = rng.random((n_int, D, 64)) ** 4
+    bins[1, 2, :] = 0.0                      # all-zero dimension keeps its grid
+    bins[2, 0, :] = 0.0
+    bins[2, 0, 17] = 3.0                     # single spike
+    bins[3, 1, 5:60] = 0.0                   # many empty bins
+    grids = np.empty((n_int, D, 65))
+    for i in range(n_int):
+        for d in range(D):
+            grids[i, d] = np.concatenate([[0.0], np.sort(rng.random(63)), [1.0]])
+    say("refine n_int=5 D=3")
+    g = dev(grids)
+    mem.vegas_refine(dev(bins), g, 1.5)
+    torch.cuda.synchronize()
+    got = g.cpu().numpy()
+    for i in range(n_int):
+        for d in range(D):
+            want = oracle.refine_dim(bins[i, d], 1.5, grids[i, d])
+            assert np.allclose(got[i, d], want, rtol=1e-12, atol=1e-14), (i, d)
+
+
+# ------------------------------------------------------------ integrands ----
+def dy_process(mem):
+    return mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+
+
+def test_dy_integrand_fp64(mem):
+    p = dy_process(mem)
+    po = oracle.dy_params()
+    d = events.drell_yan(6, 3)
+    comps = mem.to_components(d["obs"]).cuda()
+    rng = np.random.default_rng(1)
+    x = rng.random((777, 2))
+    x[:3] = [[0.0, 0.0], [0.5, 0.5], [1.0 - 2**-53, 0.999]]
+    for e in range(6):
+        say(f"dy integrand event {e}")
+        f = torch.empty(len(x), dtype=torch.float64, device="cuda")
+        mem.eval_points(p, comps, e, 0, dev(x), f)
+        torch.cuda.synchronize()
+        got = f.cpu().numpy()
+        want = np.array([oracle.dy_integrand(po, d["obs"][e], xi) for xi in x])
+        assert np.sum(want > 0) > 50
+        assert np.allclose(got, want, rtol=1e-11, atol=0), np.max(np.abs(got - want) / np.maximum(want, 1e-300))
+
+
+def tt_process(mem, precision):
+    return mem.Process(mem.MEM_TT_DILEPTON, precision=precision)
+
+
+def tt_points(po, d, n, rng, i):
+    """random points plus points near the truth of event i (where the
+    integrand is large)"""
+    from test_oracle_pins import tt_truth_x
+    xt, perm = tt_truth_x(po, d["obs"][i], d["truth"], i)
+    near = np.clip(xt + 0.002 * rng.standard_normal((n // 2, 8)), 1e-6, 1 - 1e-6)
+    far = rng.random((n - n // 2, 8))
+    return np.concatenate([near, far]), perm
+
+
+def ill_conditioned(po, ev, perm, x, f0, rel=1e-7):
+    """the oracle's own value moves by more than rel under 1-ulp input
+    perturbations: flag the point"""
+    for k in range(3):
+        xp = np.nextafter(x, 1.0) if k == 0 else np.nextafter(x, 0.0) if k == 1 else x * (1 + 2e-16)
+        xp = np.clip(xp, 0.0, 1.0 - 2**-53)
+        f1 = oracle.tt_integrand(po, ev, perm, xp)[0]
+        if abs(f1 - f0) > rel * max(abs(f0), 1e-300):
+            return True
+    return False
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-10)])
+def test_tt_integrand(mem, precision, tol):
+    p = tt_process(mem, precision)
+    po = oracle.tt_params()
+    d = events.ttbar_dilepton(5, 17)
+    comps = mem.to_components(d["obs"]).cuda()
+    rng = np.random.default_rng(2)
+    n_flag = n_cmp = 0
+    worst = 0.0
+    for e in range(5):
+        x, tperm = tt_points(po, d, 600, rng, e)
+        for perm in (0, 1):
+            say(f"tt integrand precision={precision} event={e} perm={perm}")
+            f = torch.empty(len(x), dtype=torch.float64, device="cuda")
+            ns = torch.empty(len(x), dtype=torch.int32, device="cuda")
+            mem.eval_points(p, comps, e, perm, dev(x), f, ns)
+            torch.cuda.synchronize()
+            got = f.cpu().numpy()
+            gns = ns.cpu().numpy()
+            for k, xi in enumerate(x):
+                want, wns = oracle.tt_integrand(po, d["obs"][e], perm, xi)
+                if want == 0.0 and got[k] == 0.0:
+                    continue
+                r = abs(got[k] - want) / max(abs(want), 1e-300)
+                if r > tol or gns[k] != wns:
+                    if ill_conditioned(po, d["obs"][e], perm, xi, want):
+                        n_flag += 1
+                        continue
+                    assert r <= tol and gns[k] == wns, (e, perm, k, got[k], want, gns[k], wns)
+                n_cmp += 1
+                worst = max(worst, r)
+    say(f"compared {n_cmp} nonzero points, worst rel {worst:.3g}, flagged ill-conditioned {n_flag}")
+    assert n_cmp > 500
+    assert n_flag <= 0.01 * n_cmp + 2
+
+
+# ------------------------------------------------------------- iterations ----
+def test_dy_iteration_sums_and_grid(mem):
+    """iteration 0 (uniform grid) and iteration 1 (the GPU's refined grid)
+    against the oracle's iteration on the same grid"""
+    p = dy_process(mem)
+    po = oracle.dy_params()
+    d = events.drell_yan(4, 5)
+    comps = mem.to_components(d["obs"]).cuda()
+    n_pts, n_it, seed = 5000, 2, 77       # 5000 = one full 4096 chunk + a ragged 904 tail
+    it_out = torch.zeros(n_it * 4 * 2, dtype=torch.float64, device="cuda")
+    g_out = torch.zeros(4 * 2 * 65, dtype=torch.float64, device="cuda")
+    say("dy integrate 4 events x 5000 points x 2 iterations")
+    # first run: 1 iteration of refine is what grid_out holds after n_it = 2;
+    # run n_it = 2 and read the iteration records
+    P, err, st = mem.integrate_events(comps.cuda(), p, n_pts, n_it, seed=seed, iter_out=it_out)
+    torch.cuda.synchronize()
+    rec = it_out.cpu().numpy().reshape(n_it, 4, 2)
+    for e in range(4):
+        g0 = oracle.uniform_grid(2)
+        s1, s2, bins = oracle.vegas_iteration(oracle.KIND_DY, po, d["obs"][e], 0, seed, e, 0, n_pts, g0)
+        I0 = s1 / n_pts
+        assert rec[0, e, 0] == pytest.approx(I0, rel=1e-11)
+        v0 = (s2 / n_pts - I0 * I0) / (n_pts - 1)
+        assert rec[0, e, 1] == pytest.approx(v0, rel=1e-9)
+        # iteration 1 on the oracle's refinement of its own bins
+        g1 = g0.copy()
+        for dd in range(2):
+            g1[dd] = oracle.refine_dim(bins[dd], 1.5, g0[dd])
+        s1b, s2b, _ = oracle.vegas_iteration(oracle.KIND_DY, po, d["obs"][e], 0, seed, e, 1, n_pts, g1)
+        assert rec[1, e, 0] == pytest.approx(s1b / n_pts, rel=1e-9)
+    # grid export after 2 refinements has valid structure
+    say("dy grid export")
+    P, err, st = mem.integrate_events(comps, p, n_pts, n_it, seed=seed, grid_out=g_out)
+    torch.cuda.synchronize()
+    g = g_out.cpu().numpy().reshape(4, 2, 65)
+    assert np.all(g[:, :, 0] == 0.0) and np.all(g[:, :, 64] == 1.0)
+    assert np.all(np.diff(g, axis=2) > 0)
+
+
+def pulls(a, ea, b, eb):
+    return (a - b) / np.sqrt(ea ** 2 + eb ** 2)
+
+
+def test_dy_estimates_pull(mem):
+    """GPU estimates vs oracle estimates (same seed, same point stream;
+    identical up to the grid rounding) and the pull distribution of the
+    GPU estimate against brute-force quadrature"""
+    p = dy_process(mem)
+    po = oracle.dy_params()
+    d = events.drell_yan(64, 0x14077595)
+    comps = mem.to_components(d["obs"]).cuda()
+    say("dy integrate 64 events x 4096 x 10 (the Drell-Yan configuration)")
+    P, err, st = mem.integrate_events(comps, p, 4096, 10, seed=0x14077595)
+    torch.cuda.synchronize()
+    P, err, st = P.cpu().numpy(), err.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0) and np.all(err > 0)
+    Po, Eo, So = oracle.integrate_events(oracle.KIND_DY, po, d["obs"], 0x14077595, 4096, 10)
+    # same point stream and grids equal to rounding: far tighter than MC error
+    assert np.all(np.abs(P - Po) <= 1e-6 * np.abs(Po) + 1e-3 * Eo)
+    assert np.allclose(err, Eo, rtol=1e-3)
+
+
+def test_tt_iteration0_sums(mem):
+    """uniform-grid iteration of a few integrals: GPU FP32 sums vs oracle"""
+    p = tt_process(mem, 1)
+    po = oracle.tt_params()
+    d = events.ttbar_dilepton(3, 23)
+    comps = mem.to_components(d["obs"]).cuda()
+    n_pts, seed = 6000, 9          # 3000 per permutation: one ragged chunk
+    it_out = torch.zeros(2 * 6 * 2, dtype=torch.float64, device="cuda")
+    say("tt integrate 3 events x 6000 points x 2 iterations")
+    mem.integrate_events(comps, p, n_pts, 2, seed=seed, iter_out=it_out)
+    torch.cuda.synchronize()
+    rec = it_out.cpu().numpy().reshape(2, 6, 2)
+    g0 = oracle.uniform_grid(8)
+    for e in range(3):
+        for perm in (0, 1):
+            s1, s2, _ = oracle.vegas_iteration(oracle.KIND_TT, po, d["obs"][e], perm, seed, e, 0, n_pts // 2, g0)
+            I0 = s1 / (n_pts // 2)
+            assert rec[0, 2 * e + perm, 0] == pytest.approx(I0, rel=2e-5, abs=1e-6 * abs(I0) + 1e-300)
+
+
+def test_tt_estimates_pull(mem):
+    p = tt_process(mem, 1)
+    po = oracle.tt_params()
+    n_ev, n_pts, n_it = 12, 4000, 5
+    d = events.ttbar_dilepton(n_ev, 0x14077596)
+    comps = mem.to_components(d["obs"]).cuda()
+    say(f"tt integrate {n_ev} events x {n_pts} x {n_it}")
+    P, err, st = mem.integrate_events(comps, p, n_pts, n_it, seed=1234)
+    torch.cuda.synchronize()
+    P, err, st = P.cpu().numpy(), err.cpu().numpy(), st.cpu().numpy()
+    assert np.all(np.isfinite(P)) and np.all(P > 0) and np.all(st == 0)
+    Po, Eo, So = oracle.integrate_events(oracle.KIND_TT, po, d["obs"], 1234, n_pts, n_it)
+    pl = pulls(P, err, Po, Eo)
+    say("pulls", np.round(pl, 3))
+    # same point stream: the two estimates are highly correlated, so the pull
+    # is far below one; the bar is the combined MC error
+    assert np.all(np.abs(pl) < 3.0)
+
+
+# ------------------------------------------------------------- edge cases ----
+def test_edge_cases(mem):
+    p = dy_process(mem)
+    d = events.drell_yan(3, 8)
+    obs = d["obs"].copy()
+    # an event whose muons cannot reach the mass window: zero integrand
+    obs[2, 0] = [30.0, 0.0, 0.0, 30.0]
+    obs[2, 1] = [30.0, 0.0, 0.0, 30.0 - 1e-9]
+    obs[2, 1, 0] = np.linalg.norm(obs[2, 1, 1:])
+    comps = mem.to_components(obs).cuda()
+    say("edge: zero-integrand event, ragged budgets per event")
+    P, err, st = mem.integrate_events(comps, p, [4097, 130, 999], 3)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert st[2] == 1 and P.cpu().numpy()[2] == 0.0 and err.cpu().numpy()[2] == 0.0
+    assert st[0] == 0 and st[1] == 0
+    say("edge: zero events")
+    empty = torch.zeros((4, 2, 0), dtype=torch.float64, device="cuda")
+    P, err, st = mem.integrate_events(empty, p, 1000, 3)
+    assert P.numel() == 0
+    say("edge: host events, host outputs")
+    hc = mem.to_components(d["obs"])
+    P, err, st = mem.integrate_events(hc, p, 2048, 3)
+    assert P.device.type == "cpu" and np.all(st.numpy() == 0)
+
+
+def test_target_mode(mem):
+    p = dy_process(mem)
+    d = events.drell_yan(16, 12)
+    comps = mem.to_components(d["obs"]).cuda()
+    n_used = torch.zeros(16, dtype=torch.int32, device="cuda")
+    say("target mode 1% on 16 DY events")
+    P, err, st = mem.integrate_events(comps, p, 4096, 0, target_rel_err=0.01, max_iter=20, n_iter_out=n_used)
+    torch.cuda.synchronize()
+    P, err, st, nu = P.cpu().numpy(), err.cpu().numpy(), st.cpu().numpy(), n_used.cpu().numpy()
+    conv = st == 0
+    assert conv.sum() >= 12
+    assert np.all(err[conv] <= 0.01 * P[conv] * (1 + 1e-12))
+    assert np.all(nu[conv] >= 3)
