@@ -32,10 +32,12 @@ MAX_ITER = 64
 SEED_EVENTS = 0x14077595 + 1
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 
-# Algorithmic FP32-equivalent FLOP per integrand evaluation of the ttbar
-# dilepton path (FP64 operations count twice), see the FLOP accounting in
-# the design notes; None until measured.
-FLOP_PER_EVAL = None
+# Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
+# FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
+# peak is half the FP32 one).  Counted by paper_1407_7595_amd/opcount.py on
+# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 2717.6 FP64 +
+# 1063.1 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
+FLOP_PER_EVAL = 2.0 * 2717.6 + 1063.1
 
 
 def log(*a):
@@ -80,6 +82,8 @@ def main():
     ap.add_argument("--events", type=int, default=N_EVENTS)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the integrals are independent, "
@@ -92,6 +96,13 @@ def main():
     from synth import events
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read and written")
+        del src, dst
     d = events.ttbar_dilepton(args.events, SEED_EVENTS)
     comps = mem.to_components(d["obs"]).cuda()
     proc = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
@@ -135,7 +146,7 @@ def main():
     st = S.cpu().numpy()
     nu = n_used.cpu().numpy()
     conv = float(np.mean(st == 0))
-    value = n_ev * args.steps / total
+    value = n_ev * args.steps / total if total > 0 else None
 
     roof = None
     if FLOP_PER_EVAL is not None and launches > 0:
@@ -150,7 +161,7 @@ def main():
         log(f"  {cpu}")
     out = {
         "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps if args.steps else None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"ttbar dilepton MEM, {n_ev} events, 8D VEGAS, {PTS} points/event/iteration "
                                f"to 1% per-event error (max {MAX_ITER} iterations)",
@@ -159,7 +170,7 @@ def main():
         "integrand_evals_per_s": evals_per_s,
         "fixed_budget": {"iterations": FIXED_ITERS, "seconds": fixed_s, "kernel_ms": kern_ms,
                          "median_rel_err": float(np.median(fixed_rel))},
-        "converged_fraction": conv, "median_iterations": float(np.median(nu)),
+        "converged_fraction": conv, "median_iterations": float(np.median(nu)) if args.steps else None,
         "flow_vs_vegas": None,
         "roofline": roof, "cpu_baseline": cpu,
     }

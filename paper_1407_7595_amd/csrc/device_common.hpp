@@ -5,7 +5,9 @@
 // Philox4x32-10 point stream (Salmon et al., SC'11) mapped through a VEGAS
 // grid (Lepage 1978).  Points are generated in registers, never stored.
 #pragma once
+#ifndef MEM_HOST_COUNT
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace memk {
@@ -78,6 +80,7 @@ __device__ __forceinline__ double vegas_map(const double* __restrict__ grid, con
 }
 
 // ----------------------------------------------------------- reductions --
+#ifndef MEM_HOST_COUNT
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -96,6 +99,8 @@ __device__ __forceinline__ double wave_scan(double v)
   }
   return v;
 }
+
+#endif  // MEM_HOST_COUNT
 
 // ------------------------------------------------------ four-vector math --
 struct v4 { double e, x, y, z; };
