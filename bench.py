@@ -35,9 +35,9 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 # Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
 # FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
 # peak is half the FP32 one).  Counted by paper_1407_7595_amd/opcount.py on
-# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 2717.6 FP64 +
-# 1063.1 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
-FLOP_PER_EVAL = 2.0 * 2717.6 + 1063.1
+# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 2368.7 FP64 +
+# 1065.3 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
+FLOP_PER_EVAL = 2.0 * 2368.7 + 1065.3
 
 
 def log(*a):

@@ -102,6 +102,22 @@ __device__ __forceinline__ double wave_scan(double v)
 
 #endif  // MEM_HOST_COUNT
 
+// FP64 reciprocal: hardware estimate refined by two Newton steps (full
+// double accuracy for normal operands, without the scaling and fix-up of
+// an IEEE division; 0 gives a non-finite result).
+__device__ __forceinline__ double fast_rcp(double d)
+{
+#ifdef MEM_HOST_COUNT
+  return 1.0 / d;
+#else
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __fma_rn(-d, r, 1.0);
+  r = __fma_rn(r, e, r);
+  e = __fma_rn(-d, r, 1.0);
+  return __fma_rn(r, e, r);
+#endif
+}
+
 // ------------------------------------------------------ four-vector math --
 struct v4 { double e, x, y, z; };
 __device__ __forceinline__ double mdot(const v4& a, const v4& b)

@@ -19,6 +19,9 @@
 namespace memk {
 
 constexpr int kBlock = 256;
+#ifndef MEM_TT_WAVES
+#define MEM_TT_WAVES 2
+#endif
 
 struct Chunk {
   int32_t integral;
@@ -57,7 +60,7 @@ __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)
 }
 
 template <int KIND, int D, class T>
-__global__ __launch_bounds__(kBlock) void vegas_iter_kernel(ProcParams pp, EventsView ev,
+__global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_iter_kernel(ProcParams pp, EventsView ev,
                                                             const Chunk* __restrict__ chunks,
                                                             const IntegralDesc* __restrict__ ints,
                                                             const double* __restrict__ grids,

@@ -69,6 +69,8 @@ inline CD::CD(const CF& f) : v(f.v) {}
   inline TY log(TY a) { g_t.trans[K]++; return TY(std::log(a.v)); }                              \
   inline TY tan(TY a) { g_t.trans[K]++; return TY(std::tan(a.v)); }                              \
   inline TY atan(TY a) { g_t.trans[K]++; return TY(std::atan(a.v)); }                            \
+  inline TY sin(TY a) { g_t.trans[K]++; return TY(std::sin(a.v)); }                              \
+  inline TY cos(TY a) { g_t.trans[K]++; return TY(std::cos(a.v)); }                              \
   inline TY pow(TY a, TY b) { g_t.trans[K]++; return TY(std::pow(a.v, b.v)); }                   \
   inline TY fabs(TY a) { return TY(std::fabs(a.v)); }                                            \
   inline TY fmax(TY a, TY b) { return TY(std::fmax(a.v, b.v)); }                                 \

@@ -106,19 +106,28 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
   const double q2wp = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[4] * (pp.th1_w - pp.th0_w));
   const double q2wm = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[5] * (pp.th1_w - pp.th0_w));
   const double rho = pp.sigma_k * sqrt(-2.0 * log(1.0 - x[6]));
-  double sphi, cphi;
-  sincos(2.0 * M_PI * x[7], &sphi, &cphi);
+  const double phi = 2.0 * M_PI * x[7];
+  const double sphi = sin(phi), cphi = cos(phi);
   const double metx = rho * cphi - (bq[0].x + bq[1].x + ev.lp.x + ev.lm.x);
   const double mety = rho * sphi - (bq[0].y + bq[1].y + ev.lp.y + ev.lm.y);
 
+  NuSet sols;
+  solve_dilepton(bq[0], bq[1], ev.lp, ev.lm, metx, mety, q2wp, q2t, q2wm, q2tb, sols);
+  const int ns = sols.n;
+
+  // matrix element stage: only the solutions are live here
   const T mt = T(pp.m_t);
+  const double isqs = 1.0 / pp.sqrt_s;
   double acc = 0.0;
-  int ns = solve_dilepton(bq[0], bq[1], ev.lp, ev.lm, metx, mety, q2wp, q2t, q2wm, q2tb,
-                          [&](const v4& nu, const v4& nb, double adet) {
+  for (int k = 0; k < ns; ++k) {
+    const NuSol sk = sols.get(k);
+    v4 nu{0.0, sk.nx, sk.ny, sk.nz}, nb{0.0, sk.bx, sk.by, sk.bz};
+    nu.e = norm3(nu);
+    nb.e = norm3(nb);
     v4 P = add(add(add(bq[0], bq[1]), add(ev.lp, ev.lm)), add(nu, nb));
     double Eh = sqrt(P.e * P.e - P.x * P.x - P.y * P.y);
-    double x1 = (Eh + P.z) / pp.sqrt_s, x2 = (Eh - P.z) / pp.sqrt_s;
-    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return;
+    double x1 = (Eh + P.z) * isqs, x2 = (Eh - P.z) * isqs;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
     TBoost B(P);
     v4 hb = B.apply64(bq[0]), hl = B.apply64(ev.lp), hn = B.apply64(nu);
     v4 hbb = B.apply64(bq[1]), hlm = B.apply64(ev.lm), hnb = B.apply64(nb);
@@ -138,8 +147,8 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
     T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
     T me = g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
     double shat = x1 * x2 * pp.S;
-    acc += (P.e / Eh) * (double)me / (shat * x1 * x2 * adet * nu.e * nb.e);
-  });
+    acc += (P.e / Eh) * (double)me / (shat * x1 * x2 * sk.adet * nu.e * nb.e);
+  }
   if (nsol_out) *nsol_out = ns;
   return acc * pp.tt_const * ev.lep_fac * (double)jetf;
 }

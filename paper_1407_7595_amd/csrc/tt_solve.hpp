@@ -45,7 +45,7 @@ __device__ __forceinline__ double bracketed_root(const double (&c)[N + 1], doubl
     horner_d<N>(c, x, f, df);
     if (f == 0.0) return x;
     if ((f < 0.0) == (flo < 0.0)) lo = x; else hi = x;
-    double xn = x - f / df;
+    double xn = x - f * fast_rcp(df);
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
     if (fabs(xn - x) <= 4e-16 * fabs(x) + 1e-300 || !(hi > lo)) return xn;
     x = xn;
@@ -53,66 +53,71 @@ __device__ __forceinline__ double bracketed_root(const double (&c)[N + 1], doubl
   return x;
 }
 
-// Real roots of a quartic (c4 != 0), ascending; returns the count.
-__device__ __forceinline__ int quartic_real_roots(const double (&c_in)[5], double (&root)[4])
+// Up to four doubles with a count; filled and read through select chains so
+// that the values stay in registers (no dynamically indexed arrays).
+struct Four {
+  double v0, v1, v2, v3;
+  int n;
+  __device__ __forceinline__ void put(double x)
+  {
+    v0 = n == 0 ? x : v0;
+    v1 = n == 1 ? x : v1;
+    v2 = n == 2 ? x : v2;
+    v3 = n >= 3 ? x : v3;
+    ++n;
+  }
+  __device__ __forceinline__ double get(int k) const { return k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : v3; }
+};
+
+// Roots of a polynomial in each of `NI` consecutive intervals of pts
+// (monotone on each), appended ascending to out.
+template <int N, int NI>
+__device__ __forceinline__ void roots_on_intervals(const double (&c)[N + 1], const double (&pts)[NI + 1], Four& out)
 {
-  double inv = 1.0 / c_in[4];
-  double c[5] = {c_in[0] * inv, c_in[1] * inv, c_in[2] * inv, c_in[3] * inv, 1.0};
+  double fprev = horner<N>(c, pts[0]);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const double lo = pts[i], hi = pts[i + 1];
+    const double fnext = horner<N>(c, hi);
+    if (hi > lo) {
+      if (fprev == 0.0) out.put(lo);
+      else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0) out.put(bracketed_root<N>(c, lo, hi, fprev));
+    }
+    fprev = fnext;
+  }
+}
+
+// Real roots of a quartic (c4 != 0), ascending.
+__device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four& roots)
+{
+  const double inv = fast_rcp(c_in[4]);
+  const double c[5] = {c_in[0] * inv, c_in[1] * inv, c_in[2] * inv, c_in[3] * inv, 1.0};
   double bound = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) bound = fmax(bound, fabs(c[i]));
   bound += 1.0;
-  // derivatives
-  double d1[4] = {c[1], 2.0 * c[2], 3.0 * c[3], 4.0};
-  double d2[3] = {2.0 * c[2], 6.0 * c[3], 12.0};
-  // roots of the second derivative (closed form, stable)
-  double s[2];
-  int ns = 0;
-  {
-    double disc = d2[1] * d2[1] - 4.0 * d2[2] * d2[0];
-    if (disc > 0.0) {
-      double q = -0.5 * (d2[1] + copysign(sqrt(disc), d2[1]));
-      double a = q / d2[2], b = (q != 0.0) ? d2[0] / q : a;
-      s[0] = fmin(a, b); s[1] = fmax(a, b);
-      ns = 2;
-    }
+  const double d1[4] = {c[1], 2.0 * c[2], 3.0 * c[3], 4.0};
+  const double d2[3] = {2.0 * c[2], 6.0 * c[3], 12.0};
+  // roots of the second derivative (closed form, stable); when absent both
+  // collapse onto -bound and the corresponding intervals are empty
+  double s0 = -bound, s1 = -bound;
+  const double disc = d2[1] * d2[1] - 4.0 * d2[2] * d2[0];
+  if (disc > 0.0) {
+    const double q = -0.5 * (d2[1] + copysign(sqrt(disc), d2[1]));
+    const double a = q * (1.0 / 12.0), b = (q != 0.0) ? d2[0] * fast_rcp(q) : a;
+    s0 = fmin(fmax(fmin(a, b), -bound), bound);
+    s1 = fmin(fmax(fmax(a, b), -bound), bound);
   }
-  // the first derivative is monotone between consecutive points of
-  // {-bound, s.., bound}: at most one critical point of the quartic each
-  double crit[3];
-  int nc = 0;
-  {
-    double pts[4];
-    int np = 0;
-    pts[np++] = -bound;
-    for (int i = 0; i < ns; ++i) if (s[i] > -bound && s[i] < bound) pts[np++] = s[i];
-    pts[np++] = bound;
-    double fprev = horner<3>(d1, pts[0]);
-    for (int i = 0; i + 1 < np; ++i) {
-      double fnext = horner<3>(d1, pts[i + 1]);
-      if (fprev == 0.0) crit[nc++] = pts[i];
-      else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0)
-        crit[nc++] = bracketed_root<3>(d1, pts[i], pts[i + 1], fprev);
-      fprev = fnext;
-    }
-  }
+  // the first derivative is monotone between consecutive points
+  Four crit;
+  crit.n = 0;
+  const double p3[4] = {-bound, s0, s1, bound};
+  roots_on_intervals<3, 3>(d1, p3, crit);
   // the quartic is monotone between consecutive critical points
-  int nr = 0;
-  double pts[5];
-  int np = 0;
-  pts[np++] = -bound;
-  for (int i = 0; i < nc; ++i) pts[np++] = crit[i];
-  pts[np++] = bound;
-  double fprev = horner<4>(c, pts[0]);
-  for (int i = 0; i + 1 < np; ++i) {
-    double fnext = horner<4>(c, pts[i + 1]);
-    if (fprev == 0.0) { if (nr < 4) root[nr++] = pts[i]; }
-    else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0) {
-      if (nr < 4) root[nr++] = bracketed_root<4>(c, pts[i], pts[i + 1], fprev);
-    }
-    fprev = fnext;
-  }
-  return nr;
+  const double p4[5] = {-bound, crit.n > 0 ? crit.v0 : bound, crit.n > 1 ? crit.v1 : bound,
+                        crit.n > 2 ? crit.v2 : bound, bound};
+  roots.n = 0;
+  roots_on_intervals<4, 4>(c, p4, roots);
 }
 
 // Neutrino energy and p_z as affine functions of (p_x, p_y) from
@@ -135,99 +140,131 @@ __device__ __forceinline__ bool nu_affine(const v4& b, const v4& l, double q2w, 
   return true;
 }
 
-// 4x4 Gaussian elimination with partial pivoting, all indexing static.
-// Returns det(A); if solve, overwrites r with A^-1 r.
-__device__ __forceinline__ double det_solve4(double (&A)[4][4], double (&r)[4], bool solve)
-{
-  double det = 1.0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    // pivot: bring the largest |A[k][c]|, k >= c, to row c
-#pragma unroll
-    for (int k = c + 1; k < 4; ++k) {
-      if (fabs(A[k][c]) > fabs(A[c][c])) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) { double t = A[c][j]; A[c][j] = A[k][j]; A[k][j] = t; }
-        double t = r[c]; r[c] = r[k]; r[k] = t;
-        det = -det;
-      }
-    }
-    double piv = A[c][c];
-    det *= piv;
-    if (piv == 0.0) return 0.0;
-    double ip = 1.0 / piv;
-#pragma unroll
-    for (int k = c + 1; k < 4; ++k) {
-      double f = A[k][c] * ip;
-#pragma unroll
-      for (int j = c; j < 4; ++j) A[k][j] -= f * A[c][j];
-      r[k] -= f * r[c];
-    }
-  }
-  if (solve) {
-#pragma unroll
-    for (int c = 3; c >= 0; --c) {
-      double s = r[c];
-#pragma unroll
-      for (int j = c + 1; j < 4; ++j) s -= A[c][j] * r[j];
-      r[c] = s / A[c][c];
-    }
-  }
-  return det;
-}
-
 // Virtualities (q2_W+, q2_t, q2_W-, q2_tbar) at v = (nu_x, nu_y, nu_z,
-// nubar_z) with nubar_xy = met - nu_xy, and their Jacobian w.r.t. v.
-__device__ __forceinline__ void dilep_eval(const v4& lp, const v4& wt, const v4& lm, const v4& wtb,
-                                           double wt2, double wtb2, double mx, double my,
-                                           const double (&v)[4], double (&F)[4], double (&J)[4][4])
+// nubar_z), with nubar_xy = met - nu_xy.
+struct DilepGeom {
+  v4 lp, wt, lm, wtb;      // l+, b + l+, l-, bbar + l- (scaled units)
+  double wt2, wtb2, mx, my;
+};
+
+__device__ __forceinline__ void dilep_F(const DilepGeom& g, const double (&v)[4], double (&F)[4], v4& nu, v4& nb)
 {
-  v4 nu{0.0, v[0], v[1], v[2]};
-  v4 nb{0.0, mx - v[0], my - v[1], v[3]};
+  nu = v4{0.0, v[0], v[1], v[2]};
+  nb = v4{0.0, g.mx - v[0], g.my - v[1], v[3]};
   nu.e = norm3(nu);
   nb.e = norm3(nb);
-  F[0] = 2.0 * mdot(lp, nu);
-  F[1] = wt2 + 2.0 * mdot(wt, nu);
-  F[2] = 2.0 * mdot(lm, nb);
-  F[3] = wtb2 + 2.0 * mdot(wtb, nb);
-  double inu = 1.0 / nu.e, inb = 1.0 / nb.e;
-  double n3[3] = {nu.x * inu, nu.y * inu, nu.z * inu};
-  double b3[3] = {nb.x * inb, nb.y * inb, nb.z * inb};
-  double l3[3] = {lp.x, lp.y, lp.z}, t3[3] = {wt.x, wt.y, wt.z};
-  double m3[3] = {lm.x, lm.y, lm.z}, u3[3] = {wtb.x, wtb.y, wtb.z};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    J[0][i] = 2.0 * (lp.e * n3[i] - l3[i]);
-    J[1][i] = 2.0 * (wt.e * n3[i] - t3[i]);
-  }
-  J[0][3] = 0.0; J[1][3] = 0.0;
-  double gl[3], gt[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) { gl[i] = 2.0 * (lm.e * b3[i] - m3[i]); gt[i] = 2.0 * (wtb.e * b3[i] - u3[i]); }
-  J[2][0] = -gl[0]; J[2][1] = -gl[1]; J[2][2] = 0.0; J[2][3] = gl[2];
-  J[3][0] = -gt[0]; J[3][1] = -gt[1]; J[3][2] = 0.0; J[3][3] = gt[2];
+  F[0] = 2.0 * mdot(g.lp, nu);
+  F[1] = g.wt2 + 2.0 * mdot(g.wt, nu);
+  F[2] = 2.0 * mdot(g.lm, nb);
+  F[3] = g.wtb2 + 2.0 * mdot(g.wtb, nb);
 }
 
-// Enumerates every accepted (nu, nubar) solution, calling
-// sink(nu, nubar, |det J|) in lab units.  Inputs in GeV / GeV^2.
-template <class Sink>
-__device__ __forceinline__ int solve_dilepton(const v4& b_in, const v4& bb_in, const v4& lp_in, const v4& lm_in,
-                                              double metx, double mety, double q2wp, double q2t,
-                                              double q2wm, double q2tb, Sink&& sink)
+// The Jacobian of F w.r.t. v has two zeros per row pair:
+//   rows W+, t   depend on (nu_x, nu_y, nu_z)     : a = dF0, b = dF1
+//   rows W-, tbar depend on (nu_x, nu_y, nubar_z) : c = dF2, d = dF3
+// (nubar_x,y = met - nu_x,y).  Eliminating nu_z and nubar_z leaves the 2x2
+// system [[E0, E1], [G0, G1]] in (nu_x, nu_y) with
+//   E = a_z b_xy - b_z a_xy,  G = c_z d_xy - d_z c_xy,
+// and det J = -(E0 G1 - E1 G0): no pivoting, no division.
+struct DilepJac { double a[3], b[3], c[3], d[3]; };
+
+__device__ __forceinline__ void dilep_J(const DilepGeom& g, const v4& nu, const v4& nb, DilepJac& J)
 {
+  const double inu = fast_rcp(nu.e), inb = fast_rcp(nb.e);
+  const double n3[3] = {nu.x * inu, nu.y * inu, nu.z * inu};
+  const double b3[3] = {nb.x * inb, nb.y * inb, nb.z * inb};
+  const double l3[3] = {g.lp.x, g.lp.y, g.lp.z}, t3[3] = {g.wt.x, g.wt.y, g.wt.z};
+  const double m3[3] = {g.lm.x, g.lm.y, g.lm.z}, u3[3] = {g.wtb.x, g.wtb.y, g.wtb.z};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    J.a[i] = 2.0 * (g.lp.e * n3[i] - l3[i]);
+    J.b[i] = 2.0 * (g.wt.e * n3[i] - t3[i]);
+    // d/dnu_{x,y} = -d/dnubar_{x,y}; the third entry is d/dnubar_z
+    const double sgn = i < 2 ? -1.0 : 1.0;
+    J.c[i] = sgn * 2.0 * (g.lm.e * b3[i] - m3[i]);
+    J.d[i] = sgn * 2.0 * (g.wtb.e * b3[i] - u3[i]);
+  }
+}
+
+__device__ __forceinline__ double dilep_det(const DilepJac& J)
+{
+  const double E0 = J.a[2] * J.b[0] - J.b[2] * J.a[0], E1 = J.a[2] * J.b[1] - J.b[2] * J.a[1];
+  const double G0 = J.c[2] * J.d[0] - J.d[2] * J.c[0], G1 = J.c[2] * J.d[1] - J.d[2] * J.c[1];
+  return -(E0 * G1 - E1 * G0);
+}
+
+// Newton step: solve J dv = r by the block elimination above.
+__device__ __forceinline__ bool dilep_step(const DilepJac& J, const double (&r)[4], double (&dv)[4])
+{
+  const double E0 = J.a[2] * J.b[0] - J.b[2] * J.a[0], E1 = J.a[2] * J.b[1] - J.b[2] * J.a[1];
+  const double G0 = J.c[2] * J.d[0] - J.d[2] * J.c[0], G1 = J.c[2] * J.d[1] - J.d[2] * J.c[1];
+  const double h0 = J.a[2] * r[1] - J.b[2] * r[0], h1 = J.c[2] * r[3] - J.d[2] * r[2];
+  const double D = E0 * G1 - E1 * G0;
+  if (D == 0.0) return false;
+  const double iD = fast_rcp(D);
+  dv[0] = (h0 * G1 - E1 * h1) * iD;
+  dv[1] = (E0 * h1 - h0 * G0) * iD;
+  // back-substitute through the better conditioned row of each pair
+  const bool ua = fabs(J.a[2]) >= fabs(J.b[2]);
+  const double pz = ua ? J.a[2] : J.b[2];
+  const double rz = (ua ? r[0] : r[1]) - (ua ? J.a[0] : J.b[0]) * dv[0] - (ua ? J.a[1] : J.b[1]) * dv[1];
+  const bool uc = fabs(J.c[2]) >= fabs(J.d[2]);
+  const double pb = uc ? J.c[2] : J.d[2];
+  const double rb = (uc ? r[2] : r[3]) - (uc ? J.c[0] : J.d[0]) * dv[0] - (uc ? J.c[1] : J.d[1]) * dv[1];
+  if (pz == 0.0 || pb == 0.0) return false;
+  dv[2] = rz * fast_rcp(pz);
+  dv[3] = rb * fast_rcp(pb);
+  return true;
+}
+
+// Accepted (nu, nubar) solutions of one point, held in four static slots
+// so that they stay in registers.
+struct NuSol { double nx, ny, nz, bx, by, bz, adet; };
+// Field-wise selects: an if-chain over whole records gets merged by the
+// compiler into a dynamically indexed (scratch) array.
+__device__ __forceinline__ NuSol sel(bool c, const NuSol& a, const NuSol& b)
+{
+  return NuSol{c ? a.nx : b.nx, c ? a.ny : b.ny, c ? a.nz : b.nz, c ? a.bx : b.bx,
+               c ? a.by : b.by, c ? a.bz : b.bz, c ? a.adet : b.adet};
+}
+struct NuSet {
+  NuSol s0, s1, s2, s3;
+  int n;
+  __device__ __forceinline__ void put(const NuSol& v)
+  {
+    s0 = sel(n == 0, v, s0);
+    s1 = sel(n == 1, v, s1);
+    s2 = sel(n == 2, v, s2);
+    s3 = sel(n >= 3, v, s3);
+    ++n;
+  }
+  __device__ __forceinline__ NuSol get(int k) const
+  {
+    return sel(k == 0, s0, sel(k == 1, s1, sel(k == 2, s2, s3)));
+  }
+};
+
+// Every accepted (nu, nubar) solution, in lab units (GeV) with |det J|
+// (GeV^4).  Inputs in GeV / GeV^2.
+__device__ __forceinline__ void solve_dilepton(const v4& b_in, const v4& bb_in, const v4& lp_in, const v4& lm_in,
+                                               double metx, double mety, double q2wp, double q2t, double q2wm,
+                                               double q2tb, NuSet& out)
+{
+  out.n = 0;
   // scale to O(1) numbers
   const double lam = 0.25 * (b_in.e + bb_in.e + lp_in.e + lm_in.e);
-  const double il = 1.0 / lam, il2 = il * il;
+  const double il = fast_rcp(lam), il2 = il * il;
   v4 b{b_in.e * il, b_in.x * il, b_in.y * il, b_in.z * il};
   v4 bb{bb_in.e * il, bb_in.x * il, bb_in.y * il, bb_in.z * il};
   v4 lp{lp_in.e * il, lp_in.x * il, lp_in.y * il, lp_in.z * il};
   v4 lm{lm_in.e * il, lm_in.x * il, lm_in.y * il, lm_in.z * il};
   const double mx = metx * il, my = mety * il;
   const double tq[4] = {q2wp * il2, q2t * il2, q2wm * il2, q2tb * il2};
+  const double itq[4] = {fast_rcp(tq[0]), fast_rcp(tq[1]), fast_rcp(tq[2]), fast_rcp(tq[3])};
 
   Affine A1, A2;
-  if (!nu_affine(b, lp, tq[0], tq[1], A1)) return 0;
-  if (!nu_affine(bb, lm, tq[2], tq[3], A2)) return 0;
+  if (!nu_affine(b, lp, tq[0], tq[1], A1)) return;
+  if (!nu_affine(bb, lm, tq[2], tq[3], A2)) return;
   // conic E^2 - p^2 = 0 of each side: {xx, xy, yy, x, y, 1}
   double c1[6] = {A1.e1 * A1.e1 - 1.0 - A1.z1 * A1.z1, 2.0 * (A1.e1 * A1.e2 - A1.z1 * A1.z2),
                   A1.e2 * A1.e2 - 1.0 - A1.z2 * A1.z2, 2.0 * (A1.e0 * A1.e1 - A1.z0 * A1.z1),
@@ -255,49 +292,53 @@ __device__ __forceinline__ int solve_dilepton(const v4& b_in, const v4& bb_in, c
                      P1 * P1 + 2.0 * P0 * P2 - Q0 * R2 - Q1 * R1,
                      2.0 * P1 * P2 - Q0 * R3 - Q1 * R2,
                      P2 * P2 - Q1 * R3};
-  if (quart[4] == 0.0) return 0;
-  double roots[4];
-  const int nr = quartic_real_roots(quart, roots);
+  if (quart[4] == 0.0) return;
+  Four roots;
+  quartic_real_roots(quart, roots);
+  const int nr = roots.n;
 
-  const v4 wt = add(b, lp), wtb = add(bb, lm);
-  const double wt2 = mdot(wt, wt), wtb2 = mdot(wtb, wtb);
-  int ns = 0;
+  DilepGeom g;
+  g.lp = lp; g.lm = lm; g.wt = add(b, lp); g.wtb = add(bb, lm);
+  g.wt2 = mdot(g.wt, g.wt); g.wtb2 = mdot(g.wtb, g.wtb); g.mx = mx; g.my = my;
   const double l4 = lam * lam * lam * lam;
   for (int k = 0; k < nr; ++k) {
-    const double px = roots[k];
+    const double px = roots.get(k);
     const double q = Q0 + Q1 * px;
     if (!(fabs(q) > 1e-12 * (fabs(Q0) + fabs(Q1 * px)))) continue;
-    const double py = -(P0 + (P1 + P2 * px) * px) / q;
+    const double py = -(P0 + (P1 + P2 * px) * px) * fast_rcp(q);
     const double E1 = A1.e0 + A1.e1 * px + A1.e2 * py;
     const double bx = mx - px, by = my - py;
     const double E2 = A2.e0 + A2.e1 * bx + A2.e2 * by;
     if (!(E1 > 0.0 && E2 > 0.0)) continue;
     double v[4] = {px, py, A1.z0 + A1.z1 * px + A1.z2 * py, A2.z0 + A2.z1 * bx + A2.z2 * by};
-    double F[4], J[4][4];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      dilep_eval(lp, wt, lm, wtb, wt2, wtb2, mx, my, v, F, J);
-      double r[4] = {F[0] - tq[0], F[1] - tq[1], F[2] - tq[2], F[3] - tq[3]};
-      if (det_solve4(J, r, true) == 0.0) break;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] -= r[i];
-    }
-    dilep_eval(lp, wt, lm, wtb, wt2, wtb2, mx, my, v, F, J);
+    double F[4];
+    v4 nu, nb;
+    dilep_F(g, v, F, nu, nb);
     double worst = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs(F[i] - tq[i]) / fabs(tq[i]));
+    for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - tq[i]) * itq[i]));
+    // the resultant loses digits near degenerate configurations: polish by
+    // Newton on the full system only where the residual shows it
+    for (int it = 0; it < 2 && worst > 1e-13; ++it) {
+      DilepJac J;
+      dilep_J(g, nu, nb, J);
+      double r[4] = {F[0] - tq[0], F[1] - tq[1], F[2] - tq[2], F[3] - tq[3]}, dv[4];
+      if (!dilep_step(J, r, dv)) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] -= dv[i];
+      dilep_F(g, v, F, nu, nb);
+      worst = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - tq[i]) * itq[i]));
+    }
     if (!(worst < 1e-6)) continue;
-    double dummy[4] = {0, 0, 0, 0};
-    double det = det_solve4(J, dummy, false);
+    DilepJac J;
+    dilep_J(g, nu, nb, J);
+    const double det = dilep_det(J);
     if (det == 0.0) continue;
-    v4 nu{0.0, v[0] * lam, v[1] * lam, v[2] * lam};
-    v4 nb{0.0, (mx - v[0]) * lam, (my - v[1]) * lam, v[3] * lam};
-    nu.e = norm3(nu);
-    nb.e = norm3(nb);
-    sink(nu, nb, fabs(det) * l4);
-    ++ns;
+    out.put(NuSol{v[0] * lam, v[1] * lam, v[2] * lam, (mx - v[0]) * lam, (my - v[1]) * lam, v[3] * lam,
+                  fabs(det) * l4});
   }
-  return ns;
 }
 
 }  // namespace memk

@@ -1,7 +1,8 @@
 """GPU (libmem, HIP) vs the FP64 oracle on identical inputs.
 
-Bars: bit-exact for the point stream and the VEGAS map inputs; FP64
-integrands within 1e-10 relative; the FP32 tt integrand within 1e-5
+Bars: bit-exact for the point stream and the VEGAS map inputs; the FP64
+Drell-Yan integrand within 1e-11 relative, the FP64-mode tt integrand
+within 1e-9 (see the note at its test); the FP32 tt integrand within 1e-5
 relative on every point the oracle does not flag as ill-conditioned; VEGAS
 refinement within 1e-12; iteration sums at the integrand tolerance; final
 estimates by a pull test.
@@ -126,7 +127,11 @@ def ill_conditioned(po, ev, perm, x, f0, rel=1e-7):
     return False
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-10)])
+# FP64 mode: the GPU accepts a quartic-derived neutrino solution without the
+# 4x4 Newton polish when its constraint residual is already <= 1e-13
+# relative (the oracle always polishes twice); the propagated difference is
+# the residual times the condition of the system, hence 1e-9.
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-9)])
 def test_tt_integrand(mem, precision, tol):
     p = tt_process(mem, precision)
     po = oracle.tt_params()
