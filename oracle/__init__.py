@@ -20,13 +20,15 @@ _LIB = None
 KIND_DY = 1
 KIND_TT = 2
 KIND_GENZ = 3
+KIND_TT_SL = 4
 NBINS = 64
 
 
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sqrt_s", "m_t", "w_t", "m_w", "w_w", "alpha", "alpha_s", "g_fermi",
-        "sigma_k", "tf_sigma", "r_lo", "r_hi", "m_lo", "m_hi")]
+        "sigma_k", "tf_sigma", "r_lo", "r_hi", "m_lo", "m_hi",
+        "lj_core", "lj_tail", "lj_ftail", "lj_r_lo", "lj_r_hi")]
 
 
 class Result(ctypes.Structure):
@@ -40,7 +42,7 @@ def dy_params(**kw):
     p = dict(sqrt_s=13000.0, m_t=172.5, w_t=1.4, m_w=80.4, w_w=2.1,
              alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
              sigma_k=20.0, tf_sigma=0.05, r_lo=0.75, r_hi=1.25,
-             m_lo=60.0, m_hi=120.0)
+             m_lo=60.0, m_hi=120.0, lj_core=0.10, lj_tail=0.25, lj_ftail=0.2, lj_r_lo=0.1, lj_r_hi=2.25)
     p.update(kw)
     return Params(**p)
 
@@ -51,9 +53,15 @@ def tt_params(**kw):
     p = dict(sqrt_s=13000.0, m_t=172.5, w_t=1.4, m_w=80.4, w_w=2.1,
              alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
              sigma_k=20.0, tf_sigma=0.15, r_lo=0.25, r_hi=1.75,
-             m_lo=0.0, m_hi=0.0)
+             m_lo=0.0, m_hi=0.0, lj_core=0.10, lj_tail=0.25, lj_ftail=0.2, lj_r_lo=0.1, lj_r_hi=2.25)
     p.update(kw)
     return Params(**p)
+
+
+def sl_params(**kw):
+    """ttbar semileptonic: b-jets Gaussian 15 % (r in [0.25, 1.75]), light
+    jets double Gaussian (10 %, 25 %, tail fraction 0.2; r in [0.1, 2.25])"""
+    return tt_params(**kw)
 
 
 def lib():
@@ -99,6 +107,11 @@ def _declare(L):
         "or_gauss_tf": (D, [D, D, D]),
         "or_genz_integrand": (D, [P]),
         "or_genz_exact": (D, []),
+        "or_tt_semilep_integrand": (D, [P, P, I, I, P, P]),
+        "or_semilep_perm": (None, [I, P, P, P, P]),
+        "or_semilep_map": (D, [P, P, I, P, P]),
+        "or_semilep_nu_z": (I, [P, D, D, D, P]),
+        "or_dgauss_tf": (D, [D, D, D, D, D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -163,6 +176,34 @@ def tt_integrand(p, ev, perm, x):
     ns = ctypes.c_int(0)
     v = lib().or_tt_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
     return v, ns.value
+
+
+def sl_integrand(p, ev, perm, x, charge=0):
+    ev = _f64(ev)
+    x = _f64(x)
+    ns = ctypes.c_int(0)
+    v = lib().or_tt_semilep_integrand(ctypes.byref(p), _ptr(ev), charge, perm, _ptr(x), ctypes.byref(ns))
+    return v, ns.value
+
+
+def sl_perm(perm):
+    vals = [ctypes.c_int() for _ in range(4)]
+    lib().or_semilep_perm(perm, *[ctypes.byref(v) for v in vals])
+    return tuple(v.value for v in vals)
+
+
+def sl_map(p, ev, perm, x):
+    ev, x = _f64(ev), _f64(x)
+    E4 = np.zeros(4)
+    jac = lib().or_semilep_map(ctypes.byref(p), _ptr(ev), perm, _ptr(x), _ptr(E4))
+    return jac, E4
+
+
+def sl_nu_z(l, nx, ny, q2):
+    l = _f64(l)
+    out = np.zeros(2)
+    n = lib().or_semilep_nu_z(_ptr(l), nx, ny, q2, _ptr(out))
+    return out[:n]
 
 
 def solve_dilepton(b, bb, lp, lm, met, q2):

@@ -447,8 +447,8 @@ static void boost_transverse(const double* P, const double* in, double* out)
   out[3] = in[3];
 }
 
-int or_dims(int kind) { return kind == OR_KIND_DY ? 2 : (kind == OR_KIND_GENZ ? 4 : 8); }
-int or_nperm(int kind) { return kind == OR_KIND_TT ? 2 : 1; }
+int or_dims(int kind) { return kind == OR_KIND_DY ? 2 : kind == OR_KIND_GENZ ? 4 : kind == OR_KIND_TT_SL ? 7 : 8; }
+int or_nperm(int kind) { return kind == OR_KIND_TT ? 2 : kind == OR_KIND_TT_SL ? 12 : 1; }
 
 double or_genz_integrand(const double* x)
 {
@@ -540,4 +540,171 @@ double or_tt_integrand(const or_params* p, const double* ev, int perm,
   double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
   double lep = 1.0 / (2.0 * lp[0] * 2.0 * lm[0]);
   return sum * two_pi_pow * lep * jetf * jbw;
+}
+
+/* ------------------------------------------------- ttbar semileptonic -- */
+double or_dgauss_tf(double meas, double truth, double core, double tail, double ftail)
+{
+  return (1.0 - ftail) * or_gauss_tf(meas, truth, core) + ftail * or_gauss_tf(meas, truth, tail);
+}
+
+void or_semilep_perm(int perm, int* i_bl, int* i_bh, int* i_ja, int* i_jb)
+{
+  int bl = perm / 3, r = perm % 3;
+  int bh = r < bl ? r : r + 1;          /* the r-th jet other than bl */
+  int rest[2], n = 0;
+  for (int j = 0; j < 4; ++j) if (j != bl && j != bh) rest[n++] = j;
+  *i_bl = bl; *i_bh = bh; *i_ja = rest[0]; *i_jb = rest[1];
+}
+
+/* The jet-energy part of the semileptonic map: x0 -> E_a (r map of light
+ * jet a), x1 -> q2 of the hadronic W -> E_b = q2/(2 E_a (1 - cos)),
+ * x2 -> q2 of the hadronic top -> E_bh linear in q2, x3 -> E_bl (r map).
+ * Writes (E_a, E_b, E_bh, E_bl); returns the Jacobian
+ * |d(E_a, E_b, E_bh, E_bl)/d(x0..x3)| or 0 outside the TF windows. */
+double or_semilep_map(const or_params* p, const double* ev, int perm, const double* x, double* E4)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  int ibl, ibh, ja, jb;
+  or_semilep_perm(perm, &ibl, &ibh, &ja, &jb);
+  double dir[4][3], em[4];
+  for (int k = 0; k < 4; ++k) {
+    const double* m = ev + 4 * k;
+    double pm = norm3(m);
+    em[k] = m[0];
+    for (int i = 0; i < 3; ++i) dir[k][i] = m[i + 1] / pm;
+  }
+  double jac = 1.0;
+  double ra = p->lj_r_lo + x[0] * (p->lj_r_hi - p->lj_r_lo);
+  double Ea = em[ja] / ra;
+  jac *= (p->lj_r_hi - p->lj_r_lo) * em[ja] / (ra * ra);
+  double q2wh;
+  jac *= or_bw_map(x[1], p->m_w, p->w_w, 0.0, S, &q2wh);
+  double ca = dir[ja][0] * dir[jb][0] + dir[ja][1] * dir[jb][1] + dir[ja][2] * dir[jb][2];
+  if (!(1.0 - ca > 0.0)) return 0.0;
+  double Eb = q2wh / (2.0 * Ea * (1.0 - ca));
+  jac *= 1.0 / (2.0 * Ea * (1.0 - ca));
+  double q2th;
+  jac *= or_bw_map(x[2], p->m_t, p->w_t, 0.0, S, &q2th);
+  double W[4] = {Ea + Eb, Ea * dir[ja][0] + Eb * dir[jb][0], Ea * dir[ja][1] + Eb * dir[jb][1],
+                 Ea * dir[ja][2] + Eb * dir[jb][2]};
+  double den = 2.0 * (W[0] - (dir[ibh][0] * W[1] + dir[ibh][1] * W[2] + dir[ibh][2] * W[3]));
+  if (!(den > 0.0)) return 0.0;
+  double Ebh = (q2th - q2wh) / den;
+  if (!(Ebh > 0.0)) return 0.0;
+  jac *= 1.0 / den;
+  double rb = p->r_lo + x[3] * (p->r_hi - p->r_lo);
+  double Ebl = em[ibl] / rb;
+  jac *= (p->r_hi - p->r_lo) * em[ibl] / (rb * rb);
+  double rr_b = em[jb] / Eb, rr_h = em[ibh] / Ebh;
+  if (rr_b < p->lj_r_lo || rr_b > p->lj_r_hi || rr_h < p->r_lo || rr_h > p->r_hi) return 0.0;
+  E4[0] = Ea; E4[1] = Eb; E4[2] = Ebh; E4[3] = Ebl;
+  return jac;
+}
+
+/* nu_z from 2 l.nu = q2 at fixed nu_T (massless l, nu): squaring gives
+ * l_T^2 nu_z^2 - 2 a l_z nu_z + E_l^2 nu_T^2 - a^2 = 0, a = q2/2 + l_T.nu_T;
+ * both roots satisfy the unsquared equation iff a > 0.  Returns the count. */
+int or_semilep_nu_z(const double* l, double nx, double ny, double q2, double* nz)
+{
+  double lt2 = l[1] * l[1] + l[2] * l[2];
+  double a = 0.5 * q2 + l[1] * nx + l[2] * ny;
+  double disc = a * a - lt2 * (nx * nx + ny * ny);
+  if (!(a > 0.0) || disc < 0.0 || !(lt2 > 0.0)) return 0;
+  double sq = l[0] * sqrt(disc);
+  nz[0] = (a * l[3] + sq) / lt2;
+  nz[1] = (a * l[3] - sq) / lt2;
+  return 2;
+}
+
+/* Variables: x0..x3 jet energies (or_semilep_map); x4, x5 recoil k_T;
+ * x6 q2 of the leptonic W (-> nu_z).  Sec. 3 / Eq. integrand with one
+ * hadronic W. */
+double or_tt_semilep_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
+                               const double* x, int* nsol_out)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  if (lep_charge == 0) lep_charge = ev[20] > 0 ? 1 : -1;
+  int ibl, ibh, ja, jb;
+  or_semilep_perm(perm, &ibl, &ibh, &ja, &jb);
+  const double* l = ev + 16;
+  if (nsol_out) *nsol_out = 0;
+  double E4[4];
+  double jac = or_semilep_map(p, ev, perm, x, E4);
+  if (jac == 0.0) return 0.0;
+  double qa[4], qb[4], bh[4], bl[4];
+  const int idx[4] = {ja, jb, ibh, ibl};
+  double* dst[4] = {qa, qb, bh, bl};
+  double tf = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    const double* m = ev + 4 * idx[k];
+    double pm = norm3(m), E = E4[k];
+    dst[k][0] = E;
+    for (int i = 0; i < 3; ++i) dst[k][i + 1] = E * m[i + 1] / pm;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    double T = k < 2 ? or_dgauss_tf(m[0], E, p->lj_core, p->lj_tail, p->lj_ftail)
+                     : or_gauss_tf(m[0], E, p->tf_sigma);
+    /* E^2 sin dE T / (2E) */
+    tf *= E * E * sin_th * T / (2.0 * E);
+  }
+  /* recoil and neutrino transverse momentum */
+  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
+  double phi = 2.0 * M_PI * x[5];
+  double nx = rho * cos(phi) - (qa[1] + qb[1] + bh[1] + bl[1] + l[1]);
+  double ny = rho * sin(phi) - (qa[2] + qb[2] + bh[2] + bl[2] + l[2]);
+  /* leptonic W: 2 l.nu = q2 -> quadratic in nu_z */
+  double q2wl;
+  jac *= or_bw_map(x[6], p->m_w, p->w_w, 0.0, S, &q2wl);
+  double nzs[2];
+  int nroot = or_semilep_nu_z(l, nx, ny, q2wl, nzs);
+  double sum = 0.0;
+  int ns = 0;
+  for (int s = 0; s < nroot; ++s) {
+    double nz = nzs[s];
+    double nu[4] = {sqrt(nx * nx + ny * ny + nz * nz), nx, ny, nz};
+    double dq = fabs(2.0 * (l[0] * nz / nu[0] - l[3]));
+    if (!(dq > 0.0)) continue;
+    ++ns;
+    double P[4];
+    for (int i = 0; i < 4; ++i) P[i] = qa[i] + qb[i] + bh[i] + bl[i] + l[i] + nu[i];
+    double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+    double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
+    double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+    double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+    double hq[2][4], hbh[4], hbl[4], hl[4], hn[4];
+    boost_transverse(P, qa, hq[0]);
+    boost_transverse(P, qb, hq[1]);
+    boost_transverse(P, bh, hbh);
+    boost_transverse(P, bl, hbl);
+    boost_transverse(P, l, hl);
+    boost_transverse(P, nu, hn);
+    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
+    double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
+    double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
+    double me = 0.0;
+    for (int o = 0; o < 2; ++o) {
+      /* light-jet ordering o: (quark, antiquark) of the hadronic W */
+      const double* qk = hq[o];
+      const double* qbk = hq[1 - o];
+      double mom[24];
+      if (lep_charge > 0) {
+        /* t -> b l+ nu, tbar -> bbar d ubar: W- current ubar(d) .. v(ubar) */
+        memcpy(mom, hbl, 32); memcpy(mom + 4, hl, 32); memcpy(mom + 8, hn, 32);
+        memcpy(mom + 12, hbh, 32); memcpy(mom + 16, qk, 32); memcpy(mom + 20, qbk, 32);
+      } else {
+        /* t -> b u dbar, tbar -> bbar l- nubar: W+ current ubar(u) .. v(dbar) */
+        memcpy(mom, hbh, 32); memcpy(mom + 4, qbk, 32); memcpy(mom + 8, qk, 32);
+        memcpy(mom + 12, hbl, 32); memcpy(mom + 16, hl, 32); memcpy(mom + 20, hn, 32);
+      }
+      me += g1 * g2 * or_tt_me2_gg(p, k1, k2, mom) + q1 * qb2 * or_tt_me2_qq(p, k1, k2, mom)
+          + qb1 * q2 * or_tt_me2_qq(p, k2, k1, mom);
+    }
+    me *= 3.0 * 2.0;   /* colour of the hadronic W, two quark generations */
+    double shat = x1 * x2 * S;
+    sum += (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat) / dq / (2.0 * nu[0]);
+  }
+  if (nsol_out) *nsol_out = ns;
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
+  return sum * two_pi_pow * tf * jac / (2.0 * l[0]);
 }

@@ -58,6 +58,8 @@ typedef struct {
   double tf_sigma;     /* relative width of the Gaussian energy TF */
   double r_lo, r_hi;   /* integration window of r = E_meas / E_true */
   double m_lo, m_hi;   /* Drell-Yan truth window on m_mumu */
+  /* light-jet double-Gaussian TF and its r window (semileptonic) */
+  double lj_core, lj_tail, lj_ftail, lj_r_lo, lj_r_hi;
 } or_params;
 
 /* toy parton densities x*f(x) of the configuration, and the gluon choice */
@@ -87,6 +89,20 @@ double or_dy_sigma_tau(const or_params* p, int nodes);
  * solutions when nsol != 0. */
 double or_tt_integrand(const or_params* p, const double* ev, int perm,
                        const double* x, int* nsol);
+
+/* ttbar semileptonic (one W -> q qbar').  ev = jets j0..j3, lepton as
+ * 5 x {E,px,py,pz}, then a sixth row {charge, 0, 0, 0} with the lepton
+ * charge +1 (l+: the top decays leptonically) or -1 (read when lep_charge
+ * is 0).  perm in [0,12): the ordered pair (b from the leptonic top, b from the
+ * hadronic top) of distinct jets, enumerated b_l-major; the remaining two
+ * jets are the W -> q qbar' pair, both orderings summed inside the
+ * integrand.  x in [0,1]^7. */
+double or_tt_semilep_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
+                               const double* x, int* nsol);
+void or_semilep_perm(int perm, int* i_bl, int* i_bh, int* i_ja, int* i_jb);
+double or_semilep_map(const or_params* p, const double* ev, int perm, const double* x, double* E4);
+int or_semilep_nu_z(const double* l, double nx, double ny, double q2, double* nz);
+double or_dgauss_tf(double meas, double truth, double core, double tail, double ftail);
 
 /* Building blocks exposed for tests. */
 /* all real (nu, nubar) solutions of Eq. dilepsolv; returns the count (<= 4),
@@ -128,7 +144,7 @@ double or_genz_integrand(const double* x);
 double or_genz_exact(void);
 
 /* -------------------------------------------------------------- driver -- */
-enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3 };
+enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4 };
 typedef struct {
   double I, sigma;          /* combined estimate over iterations >= 2 */
   double chi2dof;

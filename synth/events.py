@@ -12,6 +12,7 @@ weighted by any |M|^2.
 Layouts: `obs` is float64 [n_events, n_obj, 4] with rows (E, px, py, pz).
   Drell-Yan:       mu-, mu+
   ttbar dilepton:  jet_a, jet_b, l+, l-    (b/bbar order random)
+  ttbar semileptonic: j0..j3 (random order), lepton, (charge, 0, 0, 0)
 """
 import numpy as np
 
@@ -152,6 +153,76 @@ def ttbar_dilepton(n_events, seed, rel_sigma=0.15, sigma_k=20.0):
     obs = np.stack([j0, j1, lp, lm], axis=1)
     truth = {"b": b, "bb": bb, "lp": lp, "lm": lm, "nu": nu, "nub": nub, "k": k,
              "swap": swap, "mt1": mt1, "mt2": mt2, "mw1": mw1, "mw2": mw2}
+    return {"obs": obs, "truth": truth}
+
+
+def _smear_dgauss(rng, E, core, tail, ftail):
+    """E (1 + s z) with s = tail for a fraction ftail of the draws, else
+    core, redrawn while non-positive"""
+    out = np.empty_like(E)
+    todo = np.ones(E.shape, dtype=bool)
+    while np.any(todo):
+        n = int(todo.sum())
+        s = np.where(rng.random(n) < ftail, tail, core)
+        v = E[todo] * (1.0 + s * rng.standard_normal(n))
+        idx = np.flatnonzero(todo)
+        ok = v > 0.0
+        out[idx[ok]] = v[ok]
+        todo[idx[ok]] = False
+    return out
+
+
+def ttbar_semileptonic(n_events, seed, rel_sigma_b=0.15, lj=(0.10, 0.25, 0.2), sigma_k=20.0):
+    """pp -> t tbar with one W -> l nu and one W -> q qbar'.  Kinematics as
+    in ttbar_dilepton; the lepton charge is random (+1: the top decays
+    leptonically).  b-jet energies are smeared by rel_sigma_b, light-jet
+    energies by a double Gaussian (core, tail, tail fraction), the lepton is
+    exact, and the four jets are stored in random order.  Layout: jets
+    j0..j3, lepton, then a row (charge, 0, 0, 0)."""
+    rng = _rng(seed)
+    n = n_events
+    mt1 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mt2 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mw1 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mw2 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mtt = mt1 + mt2 + rng.gamma(2.0, 80.0, n)
+    ymax = np.log(SQRT_S / mtt)
+    y = np.clip(rng.standard_normal(n), -1.0, 1.0) * np.minimum(2.0, 0.9 * ymax)
+    t, tb = _two_body(mtt, mt1, mt2, _iso(rng, n))
+    b, wp = _two_body(mt1, np.zeros(n), mw1, _iso(rng, n))
+    bb, wm = _two_body(mt2, np.zeros(n), mw2, _iso(rng, n))
+    f1, f1b = _two_body(mw1, np.zeros(n), np.zeros(n), _iso(rng, n))   # W+ decay products
+    f2, f2b = _two_body(mw2, np.zeros(n), np.zeros(n), _iso(rng, n))   # W- decay products
+    f1, f1b = _boost(f1, wp), _boost(f1b, wp)
+    f2, f2b = _boost(f2, wm), _boost(f2b, wm)
+    b, f1, f1b = (_boost(v, t) for v in (b, f1, f1b))
+    bb, f2, f2b = (_boost(v, tb) for v in (bb, f2, f2b))
+    k = sigma_k * rng.standard_normal((n, 2))
+    mT = np.sqrt(mtt ** 2 + np.sum(k * k, axis=1))
+    P = np.stack([mT * np.cosh(y), k[:, 0], k[:, 1], mT * np.sinh(y)], axis=1)
+    b, f1, f1b, bb, f2, f2b = (_boost(v, P) for v in (b, f1, f1b, bb, f2, f2b))
+    charge = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    plus = charge[:, None] > 0
+    # l+ : top leptonic (W+ -> l+ nu), W- -> q qbar'; l- : the reverse
+    lep = np.where(plus, f1b, f2)
+    nu = np.where(plus, f1, f2b)
+    q1 = np.where(plus, f2, f1)
+    q2 = np.where(plus, f2b, f1b)
+    b_lep = np.where(plus, b, bb)
+    b_had = np.where(plus, bb, b)
+    jets = [_massless(_smear(rng, b_lep[:, 0], rel_sigma_b), b_lep),
+            _massless(_smear(rng, b_had[:, 0], rel_sigma_b), b_had),
+            _massless(_smear_dgauss(rng, q1[:, 0], *lj), q1),
+            _massless(_smear_dgauss(rng, q2[:, 0], *lj), q2)]
+    jets = np.stack(jets, axis=1)                     # order: b_lep, b_had, q, qbar
+    order = np.argsort(rng.random((n, 4)), axis=1)    # random jet order
+    obs_jets = np.take_along_axis(jets, order[:, :, None], axis=1)
+    crow = np.zeros((n, 4))
+    crow[:, 0] = charge
+    obs = np.concatenate([obs_jets, lep[:, None, :], crow[:, None, :]], axis=1)
+    pos = np.argsort(order, axis=1)                   # pos[i, parton] = jet slot
+    truth = {"b_lep": b_lep, "b_had": b_had, "q": q1, "qbar": q2, "lep": lep, "nu": nu, "k": k,
+             "charge": charge, "slot": pos}
     return {"obs": obs, "truth": truth}
 
 

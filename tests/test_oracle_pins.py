@@ -414,3 +414,121 @@ def test_tt_integrand_positive_at_truth():
         assert ns >= 1 and v > 0
         vals = np.array([oracle.tt_integrand(p, ev, rng.integers(2), rng.random(8))[0] for _ in range(100)])
         assert np.all(np.isfinite(vals)) and np.all(vals >= 0)
+
+
+# ------------------------------------------------------ semileptonic ----
+def test_semilep_permutations_cover_assignments():
+    seen = set()
+    for perm in range(12):
+        bl, bh, ja, jb = oracle.sl_perm(perm)
+        assert len({bl, bh, ja, jb}) == 4 and ja < jb
+        seen.add((bl, bh))
+    assert len(seen) == 12
+
+
+def test_semilep_map_jacobian_finite_difference():
+    """|d(E_a, E_b, E_bh, E_bl)/d(x0..x3)| of the jet-energy map by central
+    differences"""
+    p = oracle.sl_params()
+    d = events.ttbar_semileptonic(6, 51)
+    rng = np.random.default_rng(4)
+    checked = 0
+    for e in range(6):
+        for _ in range(40):
+            perm = int(rng.integers(12))
+            x = 0.05 + 0.9 * rng.random(7)
+            jac, E = oracle.sl_map(p, d["obs"][e], perm, x)
+            if jac == 0.0:
+                continue
+            J = np.zeros((4, 4))
+            ok = True
+            for j in range(4):
+                h = 1e-6
+                xp, xm = x.copy(), x.copy()
+                xp[j] += h
+                xm[j] -= h
+                jp, Ep = oracle.sl_map(p, d["obs"][e], perm, xp)
+                jm, Em = oracle.sl_map(p, d["obs"][e], perm, xm)
+                if jp == 0.0 or jm == 0.0:
+                    ok = False
+                    break
+                J[:, j] = (Ep - Em) / (2 * h)
+            if not ok:
+                continue
+            assert abs(np.linalg.det(J)) == pytest.approx(jac, rel=1e-5)
+            checked += 1
+    assert checked > 20
+
+
+def test_semilep_nu_z_roots():
+    """the generator's nu_z is a root of the leptonic W constraint, both
+    roots satisfy 2 l.nu = q2, and they agree with numpy's roots of the
+    squared quadratic"""
+    d = events.ttbar_semileptonic(30, 52)
+    t = d["truth"]
+    for i in range(30):
+        l, nu = t["lep"][i], t["nu"][i]
+        q2 = 2 * mdot(l, nu)
+        nz = oracle.sl_nu_z(l, nu[1], nu[2], q2)
+        assert len(nz) == 2
+        assert min(abs(nz - nu[3])) < 1e-9 * nu[0]
+        for z in nz:
+            n4 = np.array([math.sqrt(nu[1] ** 2 + nu[2] ** 2 + z * z), nu[1], nu[2], z])
+            assert 2 * mdot(l, n4) == pytest.approx(q2, rel=1e-10)
+        a = 0.5 * q2 + l[1] * nu[1] + l[2] * nu[2]
+        lt2 = l[1] ** 2 + l[2] ** 2
+        ref = np.roots([lt2, -2 * a * l[3], l[0] ** 2 * (nu[1] ** 2 + nu[2] ** 2) - a * a])
+        assert np.allclose(np.sort(nz), np.sort(ref.real), rtol=1e-8)
+
+
+def test_double_gaussian_tf_normalisation():
+    from scipy import integrate
+    L = oracle.lib()
+    for truth in (40.0, 250.0):
+        val, _ = integrate.quad(lambda e: L.or_dgauss_tf(e, truth, 0.10, 0.25, 0.2), truth * (1 - 4), truth * (1 + 4),
+                                epsabs=0, epsrel=1e-12, limit=200)
+        assert val == pytest.approx(1.0, abs=1e-9)
+
+
+def sl_truth_x(p, obs, tr, i):
+    """invert the semileptonic map at the generator's truth"""
+    S = p.sqrt_s ** 2
+    slot = tr["slot"][i]                       # parton -> jet slot: b_lep, b_had, q, qbar
+    bl, bh = int(slot[0]), int(slot[1])
+    perm = [k for k in range(12) if oracle.sl_perm(k)[:2] == (bl, bh)][0]
+    _, _, ja, jb = oracle.sl_perm(perm)
+    part = {int(slot[2]): tr["q"][i], int(slot[3]): tr["qbar"][i]}
+    qa, qb = part[ja], part[jb]
+    x = np.zeros(7)
+    x[0] = (obs[ja][0] / qa[0] - p.lj_r_lo) / (p.lj_r_hi - p.lj_r_lo)
+
+    def inv_bw(q, m, w):
+        t0, t1 = math.atan((0 - m * m) / (m * w)), math.atan((S - m * m) / (m * w))
+        return (math.atan((q - m * m) / (m * w)) - t0) / (t1 - t0)
+
+    W = qa + qb
+    x[1] = inv_bw(mdot(W, W), p.m_w, p.w_w)
+    T = W + tr["b_had"][i]
+    x[2] = inv_bw(mdot(T, T), p.m_t, p.w_t)
+    x[3] = (obs[bl][0] / tr["b_lep"][i][0] - p.r_lo) / (p.r_hi - p.r_lo)
+    k = tr["k"][i]
+    x[4] = 1 - math.exp(-(k @ k) / (2 * p.sigma_k ** 2))
+    x[5] = (math.atan2(k[1], k[0]) / (2 * math.pi)) % 1.0
+    Wl = tr["lep"][i] + tr["nu"][i]
+    x[6] = inv_bw(mdot(Wl, Wl), p.m_w, p.w_w)
+    return x, perm
+
+
+def test_semilep_integrand_positive_at_truth():
+    p = oracle.sl_params()
+    d = events.ttbar_semileptonic(8, 53)
+    for i in range(8):
+        x, perm = sl_truth_x(p, d["obs"][i], d["truth"], i)
+        jac, E = oracle.sl_map(p, d["obs"][i], perm, x)
+        tr = d["truth"]
+        if jac == 0.0:       # a truth energy outside a 5-sigma window: skip
+            continue
+        assert E[3] == pytest.approx(tr["b_lep"][i][0], rel=1e-9)
+        assert E[2] == pytest.approx(tr["b_had"][i][0], rel=1e-9)
+        v, ns = oracle.sl_integrand(p, d["obs"][i], perm, x)
+        assert ns >= 1 and v > 0
