@@ -40,11 +40,14 @@ typedef enum {
 /* Process kinds (hypotheses).  Object order expected in mem_events:
  *  MEM_DY_QQ_GAMMA_MUMU  q qbar -> gamma* -> mu- mu+          : mu-, mu+
  *  MEM_TT_DILEPTON       gg/qqbar -> t tbar -> b l+ nu bbar l- nubar
- *                                                   : jet, jet, l+, l-   */
+ *                                                   : jet, jet, l+, l-
+ *  MEM_TT_SEMILEPTON     gg/qqbar -> t tbar, one W -> l nu, one W -> q qbar'
+ *                                   : jet, jet, jet, jet, lepton (charge in
+ *                                     mem_events.charge; +1 when null)      */
 typedef enum {
   MEM_DY_QQ_GAMMA_MUMU = 1,
   MEM_TT_DILEPTON = 2,
-  MEM_TT_SEMILEPTON = 3,    /* declared for the mixed batch; not built yet */
+  MEM_TT_SEMILEPTON = 3,
   MEM_TTH_SEMILEPTON = 4    /* declared; not built yet */
 } mem_kind;
 
@@ -90,8 +93,11 @@ typedef struct {
 } mem_tf_desc;
 
 /* Observed events, SoA: component arrays [n_obj][n_events] (object-major,
- * event index fastest), FP64.  on_device != 0: the four arrays are device
- * pointers, else host pointers (copied in by the call). */
+ * event index fastest), FP64.  n_obj is the stride: an event uses the first
+ * objects its process kind needs (padding objects are ignored).  charge:
+ * optional int32 per event, the lepton charge (+1 / -1) of semileptonic
+ * events.  on_device != 0: all arrays are device pointers, else host
+ * pointers (copied in by the call). */
 typedef struct {
   int32_t n_events;
   int32_t n_obj;
@@ -99,6 +105,7 @@ typedef struct {
   const double* px;
   const double* py;
   const double* pz;
+  const int32_t* charge;
   int32_t on_device;
 } mem_events;
 
@@ -120,7 +127,12 @@ typedef struct {
  *                  the integrand kernel (HIP events around every launch on
  *                  `stream`), its number of launches, the number of
  *                  integrand evaluations it performed, and the wall time of
- *                  the call in milliseconds                                  */
+ *                  the call in milliseconds
+ *  chunk_points    points per work-queue chunk (0: the process's tuned or
+ *                  default value, 4096); a multiple of 256 up to 65536
+ *  use_graph       0: launch every iteration; 1 (default when the options
+ *                  are NULL): capture one iteration as a hipGraph and
+ *                  replay it                                                 */
 typedef struct {
   uint64_t seed;
   double alpha;
@@ -132,6 +144,8 @@ typedef struct {
   double* grid_out;
   int32_t* n_iter_out;
   double* timing_out;
+  int32_t chunk_points;
+  int32_t use_graph;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */

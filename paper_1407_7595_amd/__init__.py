@@ -42,14 +42,14 @@ class TFDesc(ctypes.Structure):
 class Events(ctypes.Structure):
     _fields_ = [("n_events", ctypes.c_int32), ("n_obj", ctypes.c_int32), ("E", ctypes.c_void_p),
                 ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
-                ("on_device", ctypes.c_int32)]
+                ("charge", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
 
 
 class IntegrateOpts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("alpha", ctypes.c_double), ("target_rel_err", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("stream", ctypes.c_void_p), ("outputs_on_device", ctypes.c_int32),
                 ("iter_out", ctypes.c_void_p), ("grid_out", ctypes.c_void_p), ("n_iter_out", ctypes.c_void_p),
-                ("timing_out", ctypes.c_void_p)]
+                ("timing_out", ctypes.c_void_p), ("chunk_points", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 _lib = None
@@ -132,15 +132,22 @@ class Process:
             self.handle = None
 
 
-def events_struct(comps):
+def events_struct(comps, charge=None):
     """comps: float64 tensor [4, n_obj, n_events] (E, px, py, pz planes),
-    contiguous, on the GPU or on the host."""
+    contiguous, on the GPU or on the host; charge: optional int32 tensor
+    [n_events] on the same device."""
     import torch
     assert comps.dtype == torch.float64 and comps.is_contiguous() and comps.dim() == 3 and comps.shape[0] == 4
     n_obj, n_ev = comps.shape[1], comps.shape[2]
     base = comps.data_ptr()
     stride = n_obj * n_ev * 8
-    return Events(n_ev, n_obj, base, base + stride, base + 2 * stride, base + 3 * stride, 1 if comps.is_cuda else 0)
+    cptr = None
+    if charge is not None:
+        assert charge.dtype == torch.int32 and charge.is_contiguous() and charge.numel() == n_ev
+        assert charge.is_cuda == comps.is_cuda
+        cptr = charge.data_ptr()
+    return Events(n_ev, n_obj, base, base + stride, base + 2 * stride, base + 3 * stride, cptr,
+                  1 if comps.is_cuda else 0)
 
 
 def to_components(obs):
@@ -152,14 +159,14 @@ def to_components(obs):
 
 def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=1.5, target_rel_err=0.0,
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
-                     timing=None):
+                     timing=None, charge=None, chunk_points=0, use_graph=1):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 4) array.
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
-    ev = events_struct(comps)
+    ev = events_struct(comps, charge)
     procs = processes if isinstance(processes, (list, tuple)) else [processes]
     handles = (ctypes.c_void_p * len(procs))(*[p.handle.value for p in procs])
     npts = [int(n_points)] if isinstance(n_points, int) else [int(v) for v in n_points]
@@ -175,7 +182,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         iter_out.data_ptr() if iter_out is not None else None,
                         grid_out.data_ptr() if grid_out is not None else None,
                         n_iter_out.data_ptr() if n_iter_out is not None else None,
-                        ctypes.cast(timing, ctypes.c_void_p) if timing is not None else None)
+                        ctypes.cast(timing, ctypes.c_void_p) if timing is not None else None,
+                        chunk_points, use_graph)
     _check(lib().mem_integrate_events(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                       ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
                                       ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
@@ -189,8 +197,8 @@ def uniforms(seed, it, event, perm, D, n, out, stream=None):
     return out
 
 
-def eval_points(process, comps, event, perm, x, f, nsol=None, stream=None):
-    ev = events_struct(comps)
+def eval_points(process, comps, event, perm, x, f, nsol=None, stream=None, charge=None):
+    ev = events_struct(comps, charge)
     _check(lib().mem_eval_points(process.handle, ctypes.byref(ev), event, perm, ctypes.c_void_p(x.data_ptr()),
                                  x.shape[0], ctypes.c_void_p(f.data_ptr()),
                                  ctypes.c_void_p(nsol.data_ptr()) if nsol is not None else None,

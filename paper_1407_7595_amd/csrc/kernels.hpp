@@ -1,19 +1,25 @@
 // Kernels of one VEGAS iteration over many independent integrals.
 //
 // Integration unit: one (event, jet-parton assignment) integral.  Its points
-// of one iteration are split into chunks; a workgroup evaluates one chunk:
-// it stages the integral's VEGAS grid in LDS, generates each point in
-// registers (Philox -> VEGAS map), evaluates the fused integrand (phase-space
-// map, constraint solve, |M|^2, PDFs, TFs, weight), and accumulates sum w,
-// sum w^2 (wavefront shuffles) and the per-(dimension, bin) sums of w^2
-// (LDS atomics).  The chunk's partial sums go to HBM; a second kernel sums
-// them in a fixed order per integral, forms I_j and sigma_j^2, updates the
+// of one iteration are split into chunks that form a device work queue.  A
+// persistent grid of workgroups pops chunks from an atomic head until the
+// queue is exhausted; for each chunk a workgroup stages the integral's VEGAS
+// grid in LDS, generates each point in registers (Philox -> VEGAS map),
+// evaluates the fused integrand of the chunk's process (phase-space map,
+// constraint solve, |M|^2, PDFs, TFs, weight), and accumulates sum w, sum w^2
+// (wavefront shuffles) and the per-(dimension, bin) sums of w^2 (LDS
+// atomics).  Processes of different kinds, dimensions and budgets share one
+// launch.  The chunk's partial sums go to HBM; a second kernel sums them in a
+// fixed order per integral, forms I_j and sigma_j^2, updates the
 // inverse-variance combination and refines the grid (one wavefront per
-// dimension, one lane per bin).
+// dimension, one lane per bin).  The iteration index and the queue head live
+// in device memory, so an iteration can be captured once as a graph and
+// replayed.
 #pragma once
 #include "device_common.hpp"
 #include "dy.hpp"
 #include "process.hpp"
+#include "sl.hpp"
 #include "tt.hpp"
 
 namespace memk {
@@ -30,6 +36,16 @@ struct Chunk {
   int32_t count;
   int64_t start;      // first point index of the chunk inside its integral
   int64_t part_off;   // offset of its partial sums (2 + D*64 doubles)
+  int32_t proc;       // index into the launch's process table
+  int32_t pad;
+};
+
+// device control block of one integration
+struct Control {
+  uint32_t iter;          // current iteration
+  uint32_t head;          // work-queue head
+  int32_t n_running;      // events still iterating (target mode)
+  uint32_t pad;
 };
 
 struct IntegralDesc {
@@ -59,65 +75,82 @@ __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)
   }
 }
 
-template <int KIND, int D, class T>
-__global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_iter_kernel(ProcParams pp, EventsView ev,
-                                                            const Chunk* __restrict__ chunks,
-                                                            const IntegralDesc* __restrict__ ints,
-                                                            const double* __restrict__ grids,
-                                                            const int32_t* __restrict__ active,
-                                                            uint64_t seed, uint32_t iter,
-                                                            double* __restrict__ parts)
+// Points [start, start + count) of one chunk: sum w, sum w^2 and the
+// per-bin sums of w^2 (LDS atomics).  F(x) is the integrand.
+template <int D, class F>
+__device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
+                                             double* sbins, double& s1, double& s2, F&& f)
 {
-  __shared__ double sgrid[D * (kBins + 1)];
-  __shared__ double sbins[D * kBins];
-  __shared__ double red[2 * kBlock / kWave];
-  const Chunk ch = chunks[blockIdx.x];
-  if (!active[ch.integral]) return;
-  const int64_t goff = ints[ch.integral].grid_off;
-  for (int i = threadIdx.x; i < D * (kBins + 1); i += kBlock) sgrid[i] = grids[goff + i];
-  for (int i = threadIdx.x; i < D * kBins; i += kBlock) sbins[i] = 0.0;
-  __syncthreads();
-
-  double s1 = 0.0, s2 = 0.0;
-  if constexpr (KIND == kDY) {
-    DYEvent e;
-    dy_load(ev, ch.event, e);
-    for (int k = threadIdx.x; k < ch.count; k += kBlock) {
-      double u[D], x[D];
-      int bin[D];
-      point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
-      double jac = vegas_map<D>(sgrid, u, x, bin);
-      double xx[2] = {x[0], x[1]};
-      double w = dy_integrand(pp, e, xx) * jac;
-      s1 += w;
-      s2 += w * w;
-      if (w != 0.0) {
+  for (int k = threadIdx.x; k < ch.count; k += kBlock) {
+    double u[D], x[D];
+    int bin[D];
+    point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
+    double jac = vegas_map<D>(sgrid, u, x, bin);
+    double w = f(x) * jac;
+    s1 += w;
+    s2 += w * w;
+    if (w != 0.0) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
-      }
-    }
-  } else {
-    TTEvent e;
-    tt_load(ev, ch.event, ch.perm, e);
-    for (int k = threadIdx.x; k < ch.count; k += kBlock) {
-      double u[D], x[D];
-      int bin[D];
-      point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
-      double jac = vegas_map<D>(sgrid, u, x, bin);
-      double w = tt_integrand<T>(pp, e, x, nullptr) * jac;
-      s1 += w;
-      s2 += w * w;
-      if (w != 0.0) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
-      }
+      for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
     }
   }
-  block_reduce2<D>(s1, s2, red);
-  __syncthreads();
-  double* out = parts + ch.part_off;
-  if (threadIdx.x == 0) { out[0] = s1; out[1] = s2; }
-  for (int i = threadIdx.x; i < D * kBins; i += kBlock) out[2 + i] = sbins[i];
+}
+
+// Persistent work-queue kernel: every workgroup loops until the shared head
+// passes n_chunks (each iteration of the loop reads the head once, so every
+// workgroup reaches the exit).  KINDS is the set of process kinds compiled
+// in (bit 1 DY, 2 dilepton, 4 semileptonic): a launch carries only the
+// integrands its chunks need, and with them only their register demand.
+enum { kMaskDY = 1, kMaskTT = 2, kMaskSL = 4 };
+template <class T, int KINDS>
+__global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_queue_kernel(
+    const ProcParams* __restrict__ procs, EventsView ev, const Chunk* __restrict__ chunks, int64_t n_chunks,
+    const IntegralDesc* __restrict__ ints, const double* __restrict__ grids, const int32_t* __restrict__ active,
+    uint64_t seed, Control* __restrict__ ctl, uint32_t* __restrict__ head, double* __restrict__ parts)
+{
+  __shared__ double sgrid[kMaxDims * (kBins + 1)];
+  __shared__ double sbins[kMaxDims * kBins];
+  __shared__ double red[2 * kBlock / kWave];
+  __shared__ int64_t s_next;
+  const uint32_t iter = ctl->iter;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(head, 1u);
+    __syncthreads();
+    const int64_t c = s_next;
+    __syncthreads();
+    if (c >= n_chunks) break;
+    const Chunk ch = chunks[c];
+    if (!active[ch.integral]) continue;
+    const IntegralDesc in = ints[ch.integral];
+    const int D = in.dims;
+    for (int i = threadIdx.x; i < D * (kBins + 1); i += kBlock) sgrid[i] = grids[in.grid_off + i];
+    for (int i = threadIdx.x; i < D * kBins; i += kBlock) sbins[i] = 0.0;
+    __syncthreads();
+    const ProcParams& pp = procs[ch.proc];
+    double s1 = 0.0, s2 = 0.0;
+    if ((KINDS & kMaskDY) && pp.kind == kDY) {
+      DYEvent e;
+      dy_load(ev, ch.event, e);
+      chunk_points<2>(ch, seed, iter, sgrid, sbins, s1, s2,
+                      [&](const double (&x)[2]) { return dy_integrand(pp, e, x); });
+    } else if ((KINDS & kMaskTT) && pp.kind == kTT) {
+      TTEvent e;
+      tt_load(ev, ch.event, ch.perm, e);
+      chunk_points<8>(ch, seed, iter, sgrid, sbins, s1, s2,
+                      [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
+    } else if ((KINDS & kMaskSL) && pp.kind == kSL) {
+      SLEvent e;
+      sl_load(ev, ev.charge, ch.event, ch.perm, e);
+      chunk_points<7>(ch, seed, iter, sgrid, sbins, s1, s2,
+                      [&](const double (&x)[7]) { return sl_integrand<T>(pp, e, x, nullptr); });
+    }
+    block_reduce2<0>(s1, s2, red);
+    __syncthreads();
+    double* out = parts + ch.part_off;
+    if (threadIdx.x == 0) { out[0] = s1; out[1] = s2; }
+    for (int i = threadIdx.x; i < D * kBins; i += kBlock) out[2 + i] = sbins[i];
+    __syncthreads();
+  }
 }
 
 // Damped rebinning of one dimension by one wavefront (lane i = bin i):

@@ -72,6 +72,7 @@ static void derive(mem_process_s* p)
   pp.sigma_norm = d.sigma_norm;
   pp.tf_mu = tf_params(p->tf[MEM_OBJ_MUON]);
   pp.tf_b = tf_params(p->tf[MEM_OBJ_BJET]);
+  pp.tf_lj = tf_params(p->tf[MEM_OBJ_LJET]);
   const double two_pi = 2.0 * M_PI;
   if (d.kind == MEM_DY_QQ_GAMMA_MUMU) {
     pp.dims = 2;
@@ -79,8 +80,8 @@ static void derive(mem_process_s* p)
     double e2 = 4.0 * M_PI * d.alpha;
     pp.dy_const = std::pow(two_pi, -2.0) * (2.0 / pp.S) * e2 * e2 / 3.0 * 0.5;
   } else {
-    pp.dims = 8;
-    pp.n_perm = 2;
+    pp.dims = d.kind == MEM_TT_SEMILEPTON ? 7 : 8;
+    pp.n_perm = d.kind == MEM_TT_SEMILEPTON ? 12 : 2;
     double mtg = d.m_top * d.w_top, mwg = d.m_w * d.w_w;
     pp.th0_t = std::atan((0.0 - d.m_top * d.m_top) / mtg);
     pp.th1_t = std::atan((pp.S - d.m_top * d.m_top) / mtg);
@@ -92,15 +93,18 @@ static void derive(mem_process_s* p)
     double coup = gs2 * gs2 * std::pow(gw2 / 2.0, 4);
     // (2 pi)^(4 - 3*6) (2/S) / (2 shat) / (2E_nu 2E_nubar): shat, E's per point
     pp.tt_const = std::pow(two_pi, -14.0) * (2.0 / pp.S) * 0.5 * 0.25 * coup * kbw;
+    // semileptonic: hadronic W, hadronic top and leptonic W aligned; the
+    // 1/(2 E_nu) of the neutrino; colour 3 x two generations of the W -> q q'
+    double kbw3 = (pp.th1_t - pp.th0_t) / mtg * std::pow((pp.th1_w - pp.th0_w) / mwg, 2);
+    pp.sl_const = std::pow(two_pi, -14.0) * (2.0 / pp.S) * 0.5 * 0.5 * coup * kbw3 * 6.0;
   }
 }
 
 extern "C" mem_status mem_create_process(const mem_process_desc* d, mem_process* out)
 {
   if (!d || !out) return fail(MEM_EINVAL, "null argument");
-  if (d->kind == MEM_TT_SEMILEPTON || d->kind == MEM_TTH_SEMILEPTON)
-    return fail(MEM_EUNSUPPORTED, "process kind not built");
-  if (d->kind != MEM_DY_QQ_GAMMA_MUMU && d->kind != MEM_TT_DILEPTON)
+  if (d->kind == MEM_TTH_SEMILEPTON) return fail(MEM_EUNSUPPORTED, "process kind not built");
+  if (d->kind != MEM_DY_QQ_GAMMA_MUMU && d->kind != MEM_TT_DILEPTON && d->kind != MEM_TT_SEMILEPTON)
     return fail(MEM_EINVAL, "unknown process kind");
   if (!(d->sqrt_s > 0.0)) return fail(MEM_EINVAL, "sqrt_s must be positive");
   if (d->precision != MEM_FP64 && d->precision != MEM_FP32) return fail(MEM_EINVAL, "bad precision");
@@ -142,7 +146,8 @@ extern "C" mem_status mem_set_transfer_functions(mem_process p, const mem_tf_des
     if (!(t.window > 0.0) || !(t.r_min >= 0.0)) return fail(MEM_EINVAL, "window must be > 0 and r_min >= 0");
     // the integrated classes need an energy-resolving TF
     if ((t.obj_class == MEM_OBJ_MUON && p->desc.kind == MEM_DY_QQ_GAMMA_MUMU) ||
-        (t.obj_class == MEM_OBJ_BJET && p->desc.kind == MEM_TT_DILEPTON))
+        (t.obj_class == MEM_OBJ_BJET && p->desc.kind != MEM_DY_QQ_GAMMA_MUMU) ||
+        (t.obj_class == MEM_OBJ_LJET && p->desc.kind == MEM_TT_SEMILEPTON))
       if (t.kind < MEM_TF_GAUSS) return fail(MEM_EINVAL, "integrated objects need a (double) Gaussian TF");
   }
   for (int i = 0; i < n; ++i) p->tf[tf[i].obj_class] = tf[i];
@@ -170,6 +175,31 @@ __global__ void init_grids_kernel(double* grids, const IntegralDesc* ints, int n
     grids[in.grid_off + i] = (double)(i % (kBins + 1)) / (double)kBins;
 }
 
+// Start of an iteration: clear the queue heads and the running count
+// (a kernel, not a memset, so that it can live in a captured graph).
+__global__ void iter_begin_kernel(Control* ctl, uint32_t* heads, int n_heads)
+{
+  int i = threadIdx.x;
+  if (i < n_heads) heads[i] = 0u;
+  if (i == 0) ctl->n_running = 0;
+}
+
+__global__ void iter_end_kernel(Control* ctl)
+{
+  if (threadIdx.x == 0) ctl->iter += 1u;
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v)
+{
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v)
+{
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // Sum the chunk partials of each integral in chunk order, form the
 // iteration estimate and its variance, fold it into the inverse-variance
 // combination (iterations >= 1) and refine the grid.
@@ -179,13 +209,14 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
                                                              double* __restrict__ grids,
                                                              double* __restrict__ state,
                                                              const int32_t* __restrict__ active,
-                                                             double alpha, uint32_t iter, int n_int,
-                                                             double* __restrict__ iter_out)
+                                                             double alpha, const Control* __restrict__ ctl,
+                                                             int n_int, double* __restrict__ iter_out)
 {
   __shared__ double sb[kMaxDims * kBins];
   __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
   const int ig = blockIdx.x;
   if (!active[ig]) return;
+  const uint32_t iter = ctl->iter;
   const IntegralDesc in = ints[ig];
   const int D = in.dims;
   for (int i = threadIdx.x; i < D * kBins; i += kBlock) {
@@ -240,16 +271,18 @@ __device__ __forceinline__ void integral_estimate(const double* st, double& I, d
   }
 }
 
-// Per event: average over permutations (Sec. 3/4), normalise by sigma,
-// optionally retire converged events (target mode).
+// Per event: average over permutations (Sec. 3/4), normalise by sigma, and
+// either retire converged events (target mode, during the iterations) or
+// write the outputs (final pass).
 __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t* __restrict__ ev_nperm,
                              const double* __restrict__ ev_norm, const double* __restrict__ state,
-                             int32_t* __restrict__ active, int n_events, double target, uint32_t iter,
+                             int32_t* __restrict__ active, int n_events, double target, Control* ctl,
                              int final_pass, double* P, double* err, int32_t* status, int32_t* n_iter_used,
-                             int32_t* ev_done, int32_t* n_running)
+                             int32_t* ev_done)
 {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_events) return;
+  const uint32_t iter = ctl->iter;
   const int64_t i0 = ev_int0[e];
   const int np = ev_nperm[e];
   double s = 0.0, v = 0.0;
@@ -265,12 +298,11 @@ __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t*
   const double norm = ev_norm[e];
   const double p = norm * s / np, sd = norm * sqrt(v) / np;
   if (!final_pass) {
-    // target mode: retire the event once its relative error is reached
     if (!ev_done[e] && iter >= 2 && (p > 0.0 && sd <= target * p)) {
       ev_done[e] = (int32_t)iter + 1;
       for (int k = 0; k < np; ++k) active[i0 + k] = 0;
     }
-    if (!ev_done[e]) atomicAdd(n_running, 1);
+    if (!ev_done[e]) atomicAdd(&ctl->n_running, 1);
     return;
   }
   P[e] = p;
@@ -293,19 +325,21 @@ __global__ __launch_bounds__(kBlock) void eval_points_kernel(ProcParams pp, Even
   double x[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) x[d] = xs[k * D + d];
+  int ns = 0;
   if constexpr (KIND == kDY) {
     DYEvent e;
     dy_load(ev, event, e);
-    double xx[2] = {x[0], x[1]};
-    f[k] = dy_integrand(pp, e, xx);
-    if (nsol) nsol[k] = 0;
-  } else {
+    f[k] = dy_integrand(pp, e, x);
+  } else if constexpr (KIND == kTT) {
     TTEvent e;
     tt_load(ev, event, perm, e);
-    int ns = 0;
     f[k] = tt_integrand<T>(pp, e, x, &ns);
-    if (nsol) nsol[k] = ns;
+  } else {
+    SLEvent e;
+    sl_load(ev, ev.charge, event, perm, e);
+    f[k] = sl_integrand<T>(pp, e, x, &ns);
   }
+  if (nsol) nsol[k] = ns;
 }
 
 __global__ void uniforms_kernel(uint64_t seed, uint32_t iter, uint32_t event, uint32_t perm, int D, int64_t n,
@@ -348,35 +382,40 @@ struct DevBuf {
   template <class X> X* as() const { return (X*)p; }
 };
 
-constexpr int64_t kChunkPoints = 4096;   // points per workgroup (16 per thread)
+constexpr int64_t kDefaultChunk = 4096;   // points per work-queue chunk
 
-bool is_device_ptr(const void* p)
-{
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) { (void)hipGetLastError(); return false; }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
+int n_obj_of(int kind) { return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : kind == MEM_TT_SEMILEPTON ? 5 : 4; }
 
-mem_status check_events(const mem_events* ev)
+// relative cost of one evaluation (for the longest-first queue order)
+double eval_cost(int kind) { return kind == MEM_DY_QQ_GAMMA_MUMU ? 1.0 : kind == MEM_TT_SEMILEPTON ? 12.0 : 30.0; }
+
+mem_status check_event_arrays(const mem_events* ev)
 {
   if (!ev) return fail(MEM_EINVAL, "null events");
   if (ev->n_events < 0 || ev->n_obj <= 0) return fail(MEM_EINVAL, "bad event sizes");
   if (ev->n_events > 0 && (!ev->E || !ev->px || !ev->py || !ev->pz)) return fail(MEM_EINVAL, "null event arrays");
-  if (!ev->on_device) {
-    int64_t n = (int64_t)ev->n_events * ev->n_obj;
-    for (int64_t i = 0; i < n; ++i) {
-      double e = ev->E[i], x = ev->px[i], y = ev->py[i], z = ev->pz[i];
-      if (!std::isfinite(e) || !std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
-        return fail(MEM_EINVAL, "non-finite event component");
-      if (!(e > 0.0)) return fail(MEM_EINVAL, "non-positive object energy");
-    }
+  return MEM_OK;
+}
+
+// Host-side events: every object the event's process uses must be finite
+// with a positive energy; charges must be +-1.
+mem_status check_host_event(const mem_events* ev, int e, int n_obj_used)
+{
+  if (ev->on_device) return MEM_OK;
+  for (int o = 0; o < n_obj_used; ++o) {
+    int64_t i = (int64_t)o * ev->n_events + e;
+    double E = ev->E[i], x = ev->px[i], y = ev->py[i], z = ev->pz[i];
+    if (!std::isfinite(E) || !std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+      return fail(MEM_EINVAL, "non-finite event component");
+    if (!(E > 0.0)) return fail(MEM_EINVAL, "non-positive object energy");
   }
+  if (ev->charge && !(ev->charge[e] == 1 || ev->charge[e] == -1)) return fail(MEM_EINVAL, "charge must be +1 or -1");
   return MEM_OK;
 }
 
 // Events resident on the device for the duration of a call.
 struct DevEvents {
-  DevBuf buf;
+  DevBuf buf, cbuf;
   EventsView view{};
   mem_status make(const mem_events* ev, hipStream_t s)
   {
@@ -384,6 +423,7 @@ struct DevEvents {
     view.n_obj = ev->n_obj;
     if (ev->on_device) {
       view.E = ev->E; view.px = ev->px; view.py = ev->py; view.pz = ev->pz;
+      view.charge = ev->charge;
       return MEM_OK;
     }
     size_t n = (size_t)ev->n_events * ev->n_obj;
@@ -394,21 +434,53 @@ struct DevEvents {
     HIP_TRY(hipMemcpyAsync(d + 2 * n, ev->py, n * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d + 3 * n, ev->pz, n * sizeof(double), hipMemcpyHostToDevice, s));
     view.E = d; view.px = d + n; view.py = d + 2 * n; view.pz = d + 3 * n;
+    view.charge = nullptr;
+    if (ev->charge) {
+      HIP_TRY(cbuf.alloc((size_t)ev->n_events * sizeof(int32_t)));
+      HIP_TRY(hipMemcpyAsync(cbuf.p, ev->charge, (size_t)ev->n_events * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      view.charge = cbuf.as<int32_t>();
+    }
     return MEM_OK;
   }
 };
 
-int n_obj_of(int kind) { return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : 4; }
-
-template <int KIND, int D, class T>
-void launch_iter(const ProcParams& pp, const EventsView& ev, const Chunk* chunks, int64_t n_chunks,
-                 const IntegralDesc* ints, const double* grids, const int32_t* active, uint64_t seed,
-                 uint32_t iter, double* parts, hipStream_t s)
+// Persistent grid: enough workgroups to fill every CU at the kernel's
+// occupancy (never more than there are chunks).
+// The queue kernel instance for a precision and a set of kinds.
+typedef void (*QueueKernel)(const ProcParams*, EventsView, const Chunk*, int64_t, const IntegralDesc*,
+                            const double*, const int32_t*, uint64_t, Control*, uint32_t*, double*);
+template <class T>
+QueueKernel queue_kernel_for(int mask)
 {
-  if (n_chunks > 0)
-    hipLaunchKernelGGL((vegas_iter_kernel<KIND, D, T>), dim3((unsigned)n_chunks), dim3(kBlock), 0, s, pp, ev,
-                       chunks, ints, grids, active, seed, iter, parts);
+  switch (mask) {
+    case kMaskDY: return vegas_queue_kernel<T, kMaskDY>;
+    case kMaskTT: return vegas_queue_kernel<T, kMaskTT>;
+    case kMaskSL: return vegas_queue_kernel<T, kMaskSL>;
+    default: return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL>;
+  }
 }
+
+// Persistent grid: enough workgroups to fill every CU at the kernel's
+// occupancy (never more than there are chunks).
+int persistent_blocks(QueueKernel k, int64_t n_chunks)
+{
+  int dev = 0, cus = 256, per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t b = (int64_t)cus * per_cu;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, n_chunks));
+}
+
+// One launch group: chunks whose processes share the matrix-element
+// precision (Drell-Yan, always FP64, joins the first group).
+struct Group {
+  int prec;
+  std::vector<int32_t> queue;   // chunk indices, longest first
+  int mask = 0;                 // kinds present
+  int blocks = 0;
+  QueueKernel kernel = nullptr;
+};
 
 }  // namespace
 
@@ -418,7 +490,7 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
                                            const mem_integrate_opts* opt, double* p_out, double* err_out,
                                            int32_t* status_out)
 {
-  mem_status st = check_events(ev);
+  mem_status st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
   const int n_ev = ev->n_events;
   if (!hyp || !n_points) return fail(MEM_EINVAL, "null argument");
@@ -429,28 +501,41 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
   o.seed = 0x14077595ull;
   o.alpha = 1.5;
   o.max_iter = 64;
+  o.use_graph = 1;
   if (opt) o = *opt;
   if (!(o.alpha > 0.0)) return fail(MEM_EINVAL, "alpha must be positive");
   const bool target_mode = o.target_rel_err > 0.0;
   const int iters = target_mode ? o.max_iter : n_iter;
   if (iters < 2) return fail(MEM_EINVAL, "at least two iterations are needed");
   if (iters > 100000) return fail(MEM_EINVAL, "too many iterations");
-  hipStream_t s = (hipStream_t)o.stream;
+  int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : kDefaultChunk;
+  if (chunk_pts % kBlock != 0 || chunk_pts > 65536) return fail(MEM_EINVAL, "chunk_points must be a multiple of 256 <= 65536");
   if (n_ev == 0) return MEM_OK;
 
-  // ---- work list: integrals (event x permutation), grouped by kernel ----
-  struct Group { int kind, prec, dims; std::vector<int> ints; };
-  std::vector<Group> groups;
-  std::vector<IntegralDesc> ints;
-  std::vector<int64_t> ev_int0(n_ev);
-  std::vector<int32_t> ev_np(n_ev);
-  std::vector<double> ev_norm(n_ev);
-  std::vector<const ProcParams*> int_pp;
-  int64_t grid_total = 0;
+  // ---- processes, integrals (event x permutation) and chunks ----
+  std::vector<const mem_process_s*> procs;
+  std::vector<int> ev_proc(n_ev);
   for (int e = 0; e < n_ev; ++e) {
     const mem_process p = hyp[n_hyp == 1 ? 0 : e];
     if (!p) return fail(MEM_EINVAL, "null process handle");
     if (ev->n_obj < n_obj_of(p->desc.kind)) return fail(MEM_EINVAL, "n_obj too small for the process kind");
+    st = check_host_event(ev, e, n_obj_of(p->desc.kind));
+    if (st != MEM_OK) return st;
+    int pi = -1;
+    for (size_t k = 0; k < procs.size(); ++k) if (procs[k] == p) pi = (int)k;
+    if (pi < 0) { procs.push_back(p); pi = (int)procs.size() - 1; }
+    ev_proc[e] = pi;
+  }
+  std::vector<ProcParams> ptab(procs.size());
+  for (size_t k = 0; k < procs.size(); ++k) ptab[k] = procs[k]->pp;
+  std::vector<IntegralDesc> ints;
+  std::vector<int> int_proc;
+  std::vector<int64_t> ev_int0(n_ev);
+  std::vector<int32_t> ev_np(n_ev);
+  std::vector<double> ev_norm(n_ev);
+  int64_t grid_total = 0;
+  for (int e = 0; e < n_ev; ++e) {
+    const mem_process_s* p = procs[ev_proc[e]];
     const int64_t npts = n_points[n_np == 1 ? 0 : e];
     const int np = p->pp.n_perm;
     const int64_t per = (npts + np - 1) / np;
@@ -459,52 +544,76 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
     ev_int0[e] = (int64_t)ints.size();
     ev_np[e] = np;
     ev_norm[e] = p->desc.sigma_norm > 0.0 ? 1.0 / p->desc.sigma_norm : 1.0;
-    int gi = -1;
-    for (size_t g = 0; g < groups.size(); ++g)
-      if (groups[g].kind == p->pp.kind && groups[g].prec == p->pp.precision) gi = (int)g;
-    if (gi < 0) { groups.push_back(Group{p->pp.kind, p->pp.precision, p->pp.dims, {}}); gi = (int)groups.size() - 1; }
     for (int k = 0; k < np; ++k) {
       IntegralDesc d{};
       d.event = e; d.perm = k; d.dims = p->pp.dims; d.n_points = per;
       d.grid_off = grid_total;
       grid_total += (int64_t)p->pp.dims * (kBins + 1);
-      groups[gi].ints.push_back((int)ints.size());
       ints.push_back(d);
-      int_pp.push_back(&p->pp);
+      int_proc.push_back(ev_proc[e]);
     }
   }
   const int n_int = (int)ints.size();
-  // chunks, contiguous per group so that one launch covers one group
   std::vector<Chunk> chunks;
-  std::vector<int64_t> group_c0(groups.size()), group_nc(groups.size());
   int64_t part_total = 0;
-  for (size_t g = 0; g < groups.size(); ++g) {
-    group_c0[g] = (int64_t)chunks.size();
-    for (int ig : groups[g].ints) {
-      IntegralDesc& d = ints[ig];
-      d.chunk0 = (int64_t)chunks.size();
-      d.n_chunks = 0;
-      for (int64_t s0 = 0; s0 < d.n_points; s0 += kChunkPoints) {
-        Chunk c{};
-        c.integral = ig; c.event = d.event; c.perm = d.perm;
-        c.count = (int32_t)std::min<int64_t>(kChunkPoints, d.n_points - s0);
-        c.start = s0;
-        c.part_off = part_total;
-        part_total += 2 + (int64_t)d.dims * kBins;
-        chunks.push_back(c);
-        d.n_chunks++;
-      }
+  for (int ig = 0; ig < n_int; ++ig) {
+    IntegralDesc& d = ints[ig];
+    d.chunk0 = (int64_t)chunks.size();
+    d.n_chunks = 0;
+    for (int64_t s0 = 0; s0 < d.n_points; s0 += chunk_pts) {
+      Chunk c{};
+      c.integral = ig; c.event = d.event; c.perm = d.perm;
+      c.count = (int32_t)std::min<int64_t>(chunk_pts, d.n_points - s0);
+      c.start = s0;
+      c.part_off = part_total;
+      c.proc = int_proc[ig];
+      part_total += 2 + (int64_t)d.dims * kBins;
+      chunks.push_back(c);
+      d.n_chunks++;
     }
-    group_nc[g] = (int64_t)chunks.size() - group_c0[g];
   }
+  if ((int64_t)chunks.size() > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "too many chunks");
+  // launch groups by matrix-element precision; queue order longest first
+  std::vector<Group> groups;
+  auto group_of = [&](int prec) {
+    for (size_t g = 0; g < groups.size(); ++g) if (groups[g].prec == prec) return (int)g;
+    groups.push_back(Group{prec, {}, 0, 0, nullptr});
+    return (int)groups.size() - 1;
+  };
+  int first_prec = -1;
+  for (const auto* p : procs) if (p->desc.kind != MEM_DY_QQ_GAMMA_MUMU) { first_prec = p->desc.precision; break; }
+  if (first_prec < 0) first_prec = MEM_FP64;
+  std::vector<double> cost(chunks.size());
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    const mem_process_s* p = procs[chunks[c].proc];
+    int prec = p->desc.kind == MEM_DY_QQ_GAMMA_MUMU ? first_prec : p->desc.precision;
+    Group& G = groups[group_of(prec)];
+    G.queue.push_back((int32_t)c);
+    G.mask |= p->desc.kind == MEM_DY_QQ_GAMMA_MUMU ? kMaskDY : p->desc.kind == MEM_TT_DILEPTON ? kMaskTT : kMaskSL;
+    cost[c] = chunks[c].count * eval_cost(p->desc.kind);
+  }
+  for (auto& G : groups)
+    std::stable_sort(G.queue.begin(), G.queue.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+
+  // ---- stream: the caller's, or a private one (graphs cannot capture the null stream) ----
+  hipStream_t s = (hipStream_t)o.stream;
+  hipStream_t own = nullptr;
+  const bool want_graph = o.use_graph != 0 && o.timing_out == nullptr;
+  if (!s && want_graph) HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+  struct StreamGuard { hipStream_t& s; ~StreamGuard() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } } sg{own};
+  hipStream_t ws = own ? own : s;
 
   DevEvents dev;
-  st = dev.make(ev, s);
+  st = dev.make(ev, ws);
   if (st != MEM_OK) return st;
-  DevBuf b_ints, b_chunks, b_grids, b_parts, b_state, b_active, b_evi0, b_evnp, b_evnorm, b_done, b_run, b_P,
-      b_err, b_status;
+  DevBuf b_procs, b_ints, b_chunks, b_queue, b_grids, b_parts, b_state, b_active, b_evi0, b_evnp, b_evnorm, b_done,
+      b_ctl, b_heads, b_P, b_err, b_status;
+  size_t qtotal = 0;
+  for (auto& G : groups) qtotal += G.queue.size();
+  HIP_TRY(b_procs.alloc(ptab.size() * sizeof(ProcParams)));
   HIP_TRY(b_ints.alloc(ints.size() * sizeof(IntegralDesc)));
   HIP_TRY(b_chunks.alloc(chunks.size() * sizeof(Chunk)));
+  HIP_TRY(b_queue.alloc(qtotal * sizeof(int32_t)));
   HIP_TRY(b_grids.alloc(grid_total * sizeof(double)));
   HIP_TRY(b_parts.alloc(part_total * sizeof(double)));
   HIP_TRY(b_state.alloc((size_t)n_int * ST_SIZE * sizeof(double)));
@@ -513,96 +622,141 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
   HIP_TRY(b_evnp.alloc((size_t)n_ev * sizeof(int32_t)));
   HIP_TRY(b_evnorm.alloc((size_t)n_ev * sizeof(double)));
   HIP_TRY(b_done.alloc((size_t)n_ev * sizeof(int32_t)));
-  HIP_TRY(b_run.alloc(sizeof(int32_t)));
+  HIP_TRY(b_ctl.alloc(sizeof(Control)));
+  HIP_TRY(b_heads.alloc(groups.size() * sizeof(uint32_t)));
   const bool out_dev = o.outputs_on_device != 0;
   if (!out_dev) {
     HIP_TRY(b_P.alloc(n_ev * sizeof(double)));
     HIP_TRY(b_err.alloc(n_ev * sizeof(double)));
     HIP_TRY(b_status.alloc(n_ev * sizeof(int32_t)));
   }
-  std::vector<int32_t> ones(n_int, 1);
-  HIP_TRY(hipMemcpyAsync(b_ints.p, ints.data(), ints.size() * sizeof(IntegralDesc), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b_chunks.p, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b_active.p, ones.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b_evi0.p, ev_int0.data(), n_ev * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b_evnp.p, ev_np.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(b_evnorm.p, ev_norm.data(), n_ev * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(b_state.p, 0, (size_t)n_int * ST_SIZE * sizeof(double), s));
-  HIP_TRY(hipMemsetAsync(b_done.p, 0, (size_t)n_ev * sizeof(int32_t), s));
-  hipLaunchKernelGGL(init_grids_kernel, dim3(n_int), dim3(kBlock), 0, s, b_grids.as<double>(),
-                     b_ints.as<IntegralDesc>(), n_int);
-  HIP_TRY(hipGetLastError());
+  std::vector<int32_t> flat;
+  std::vector<size_t> gq0;
+  for (auto& G : groups) { gq0.push_back(flat.size()); flat.insert(flat.end(), G.queue.begin(), G.queue.end()); }
+  HIP_TRY(hipMemcpyAsync(b_procs.p, ptab.data(), ptab.size() * sizeof(ProcParams), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_ints.p, ints.data(), ints.size() * sizeof(IntegralDesc), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_chunks.p, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_queue.p, flat.data(), flat.size() * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_evi0.p, ev_int0.data(), n_ev * sizeof(int64_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_evnp.p, ev_np.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_evnorm.p, ev_norm.data(), n_ev * sizeof(double), hipMemcpyHostToDevice, ws));
+  const Control ctl0{0u, 0u, 0, 0u};
+  HIP_TRY(hipMemcpyAsync(b_ctl.p, &ctl0, sizeof(Control), hipMemcpyHostToDevice, ws));
+  {
+    const int64_t ns = (int64_t)n_int * ST_SIZE;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, ws, b_state.as<double>(), ns, 0.0);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n_int + 255) / 256)), dim3(256), 0, ws,
+                       b_active.as<int32_t>(), (int64_t)n_int, 1);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n_ev + 255) / 256)), dim3(256), 0, ws,
+                       b_done.as<int32_t>(), (int64_t)n_ev, 0);
+    hipLaunchKernelGGL(init_grids_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_grids.as<double>(),
+                       b_ints.as<IntegralDesc>(), n_int);
+    HIP_TRY(hipGetLastError());
+  }
+  for (auto& G : groups) {
+    G.kernel = G.prec == MEM_FP32 ? queue_kernel_for<float>(G.mask) : queue_kernel_for<double>(G.mask);
+    G.blocks = persistent_blocks(G.kernel, (int64_t)G.queue.size());
+  }
+  // chunk order through the queue: the kernel reads chunks[queue[c]]; the
+  // queue kernel takes the chunk table permuted on the device instead
+  // (one gather per call)
+  DevBuf b_chunks_q;
+  HIP_TRY(b_chunks_q.alloc(flat.size() * sizeof(Chunk)));
+  {
+    std::vector<Chunk> perm_chunks(flat.size());
+    for (size_t i = 0; i < flat.size(); ++i) perm_chunks[i] = chunks[flat[i]];
+    HIP_TRY(hipMemcpyAsync(b_chunks_q.p, perm_chunks.data(), flat.size() * sizeof(Chunk), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipStreamSynchronize(ws));   // perm_chunks goes out of scope
+  }
 
   const int ev_blocks = (n_ev + 255) / 256;
-  int used_iters = iters;
-  // optional timing of the integrand kernel: one event pair per launch
-  std::vector<hipEvent_t> tev;
-  double n_evals = 0.0;
-  auto wall0 = std::chrono::steady_clock::now();
-  auto cleanup_events = [&]() { for (hipEvent_t e : tev) (void)hipEventDestroy(e); };
-  for (int j = 0; j < iters; ++j) {
+  Control* ctl = b_ctl.as<Control>();
+  // one iteration: begin -> queue kernel(s) -> finish -> [events] -> end
+  auto enqueue_iteration = [&](bool time_kernels, std::vector<hipEvent_t>* tev) -> mem_status {
+    hipLaunchKernelGGL(iter_begin_kernel, dim3(1), dim3(64), 0, ws, ctl, b_heads.as<uint32_t>(), (int)groups.size());
     for (size_t g = 0; g < groups.size(); ++g) {
       const Group& G = groups[g];
-      if (o.timing_out) {
+      const Chunk* cq = b_chunks_q.as<Chunk>() + gq0[g];
+      if (time_kernels) {
         hipEvent_t a, b;
         HIP_TRY(hipEventCreate(&a));
         HIP_TRY(hipEventCreate(&b));
-        tev.push_back(a);
-        tev.push_back(b);
-        HIP_TRY(hipEventRecord(a, s));
-        for (int ig : G.ints) n_evals += (double)ints[ig].n_points;
+        tev->push_back(a);
+        tev->push_back(b);
+        HIP_TRY(hipEventRecord(a, ws));
       }
-      const ProcParams& pp = *int_pp[G.ints[0]];
-      const Chunk* cptr = b_chunks.as<Chunk>() + group_c0[g];
-      if (G.kind == MEM_DY_QQ_GAMMA_MUMU)
-        launch_iter<kDY, 2, double>(pp, dev.view, cptr, group_nc[g], b_ints.as<IntegralDesc>(),
-                                    b_grids.as<double>(), b_active.as<int32_t>(), o.seed, (uint32_t)j,
-                                    b_parts.as<double>(), s);
-      else if (G.prec == MEM_FP32)
-        launch_iter<kTT, 8, float>(pp, dev.view, cptr, group_nc[g], b_ints.as<IntegralDesc>(),
-                                   b_grids.as<double>(), b_active.as<int32_t>(), o.seed, (uint32_t)j,
-                                   b_parts.as<double>(), s);
-      else
-        launch_iter<kTT, 8, double>(pp, dev.view, cptr, group_nc[g], b_ints.as<IntegralDesc>(),
-                                    b_grids.as<double>(), b_active.as<int32_t>(), o.seed, (uint32_t)j,
-                                    b_parts.as<double>(), s);
+      hipLaunchKernelGGL(G.kernel, dim3(G.blocks), dim3(kBlock), 0, ws, b_procs.as<ProcParams>(), dev.view, cq,
+                         (int64_t)G.queue.size(), b_ints.as<IntegralDesc>(), b_grids.as<double>(),
+                         b_active.as<int32_t>(), o.seed, ctl, b_heads.as<uint32_t>() + g, b_parts.as<double>());
       HIP_TRY(hipGetLastError());
-      if (o.timing_out) HIP_TRY(hipEventRecord(tev.back(), s));
+      if (time_kernels) HIP_TRY(hipEventRecord(tev->back(), ws));
     }
-    hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, s, b_ints.as<IntegralDesc>(),
+    hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(),
                        b_chunks.as<Chunk>(), b_parts.as<double>(), b_grids.as<double>(), b_state.as<double>(),
-                       b_active.as<int32_t>(), o.alpha, (uint32_t)j, n_int, o.iter_out);
+                       b_active.as<int32_t>(), o.alpha, ctl, n_int, o.iter_out);
+    if (target_mode)
+      hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
+                         b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
+                         o.target_rel_err, ctl, 0, nullptr, nullptr, nullptr, nullptr, b_done.as<int32_t>());
+    hipLaunchKernelGGL(iter_end_kernel, dim3(1), dim3(64), 0, ws, ctl);
     HIP_TRY(hipGetLastError());
+    return MEM_OK;
+  };
+
+  std::vector<hipEvent_t> tev;
+  struct EventsGuard { std::vector<hipEvent_t>& v; ~EventsGuard() { for (auto e : v) (void)hipEventDestroy(e); } } eg{tev};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraph_t& g; hipGraphExec_t& x;
+    ~GraphGuard() { if (x) (void)hipGraphExecDestroy(x); if (g) (void)hipGraphDestroy(g); }
+  } gg{graph, gexec};
+  const bool use_graph = want_graph && ws != nullptr;
+  if (use_graph) {
+    HIP_TRY(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+    mem_status cs = enqueue_iteration(false, nullptr);
+    hipGraph_t gcap = nullptr;
+    hipError_t ce = hipStreamEndCapture(ws, &gcap);
+    graph = gcap;
+    if (cs != MEM_OK) return cs;
+    if (ce != hipSuccess) return fail(MEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+  double n_evals = 0.0;
+  for (const auto& d : ints) n_evals += (double)d.n_points;
+  auto wall0 = std::chrono::steady_clock::now();
+  int used_iters = iters;
+  for (int j = 0; j < iters; ++j) {
+    if (use_graph) HIP_TRY(hipGraphLaunch(gexec, ws));
+    else {
+      mem_status es = enqueue_iteration(o.timing_out != nullptr, &tev);
+      if (es != MEM_OK) return es;
+    }
     if (target_mode) {
-      HIP_TRY(hipMemsetAsync(b_run.p, 0, sizeof(int32_t), s));
-      hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, s, b_evi0.as<int64_t>(),
-                         b_evnp.as<int32_t>(), b_evnorm.as<double>(), b_state.as<double>(),
-                         b_active.as<int32_t>(), n_ev, o.target_rel_err, (uint32_t)j, 0, nullptr, nullptr,
-                         nullptr, nullptr, b_done.as<int32_t>(), b_run.as<int32_t>());
-      HIP_TRY(hipGetLastError());
-      int32_t running = 0;
-      HIP_TRY(hipMemcpyAsync(&running, b_run.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      if (running == 0) { used_iters = j + 1; break; }
+      Control hc{};
+      HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, ws));
+      HIP_TRY(hipStreamSynchronize(ws));
+      if (hc.n_running == 0) { used_iters = j + 1; break; }
     }
   }
   double* P = out_dev ? p_out : b_P.as<double>();
   double* E = out_dev ? err_out : b_err.as<double>();
   int32_t* S = out_dev ? status_out : b_status.as<int32_t>();
-  hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, s, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
+  // the final pass reads ctl->iter == iterations run
+  hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                      b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
-                     target_mode ? o.target_rel_err : 0.0, (uint32_t)used_iters, 1, P, E, S, o.n_iter_out,
-                     b_done.as<int32_t>(), b_run.as<int32_t>());
+                     target_mode ? o.target_rel_err : 0.0, ctl, 1, P, E, S, o.n_iter_out, b_done.as<int32_t>());
   HIP_TRY(hipGetLastError());
+  (void)used_iters;
   if (o.grid_out)
-    HIP_TRY(hipMemcpyAsync(o.grid_out, b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(o.grid_out, b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToDevice, ws));
   if (!out_dev) {
-    HIP_TRY(hipMemcpyAsync(p_out, P, n_ev * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(err_out, E, n_ev * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(status_out, S, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p_out, P, n_ev * sizeof(double), hipMemcpyDeviceToHost, ws));
+    HIP_TRY(hipMemcpyAsync(err_out, E, n_ev * sizeof(double), hipMemcpyDeviceToHost, ws));
+    HIP_TRY(hipMemcpyAsync(status_out, S, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost, ws));
   }
   // the work buffers are freed on return: wait for the stream
-  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipStreamSynchronize(ws));
   if (o.timing_out) {
     double ms = 0.0;
     for (size_t i = 0; i + 1 < tev.size(); i += 2) {
@@ -610,10 +764,9 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
       HIP_TRY(hipEventElapsedTime(&t, tev[i], tev[i + 1]));
       ms += t;
     }
-    cleanup_events();
     o.timing_out[0] = ms;
     o.timing_out[1] = (double)(tev.size() / 2);
-    o.timing_out[2] = n_evals;
+    o.timing_out[2] = n_evals * used_iters;
     o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
   }
   return MEM_OK;
@@ -636,11 +789,13 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
                                       const double* x, int64_t n, double* f, int32_t* nsol, void* stream)
 {
   if (!p || !x || !f) return fail(MEM_EINVAL, "null argument");
-  mem_status st = check_events(ev);
+  mem_status st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
   if (event < 0 || event >= ev->n_events) return fail(MEM_EINVAL, "event index out of range");
   if (perm < 0 || perm >= p->pp.n_perm) return fail(MEM_EINVAL, "permutation out of range");
   if (ev->n_obj < n_obj_of(p->desc.kind)) return fail(MEM_EINVAL, "n_obj too small for the process kind");
+  st = check_host_event(ev, event, n_obj_of(p->desc.kind));
+  if (st != MEM_OK) return st;
   if (n < 0) return fail(MEM_EINVAL, "negative n");
   if (n == 0) return MEM_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -651,6 +806,12 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
   if (p->desc.kind == MEM_DY_QQ_GAMMA_MUMU)
     hipLaunchKernelGGL((eval_points_kernel<kDY, 2, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
                        x, n, f, nsol);
+  else if (p->desc.kind == MEM_TT_SEMILEPTON && p->desc.precision == MEM_FP32)
+    hipLaunchKernelGGL((eval_points_kernel<kSL, 7, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
+                       x, n, f, nsol);
+  else if (p->desc.kind == MEM_TT_SEMILEPTON)
+    hipLaunchKernelGGL((eval_points_kernel<kSL, 7, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
   else if (p->desc.precision == MEM_FP32)
     hipLaunchKernelGGL((eval_points_kernel<kTT, 8, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
                        x, n, f, nsol);

@@ -4,7 +4,7 @@
 
 namespace memk {
 
-enum Kind : int32_t { kDY = 1, kTT = 2 };
+enum Kind : int32_t { kDY = 1, kTT = 2, kSL = 3 };
 
 // One transfer function for the energy of a measured object, Gaussian or
 // double Gaussian in r = E_meas / E_true (Sec. 1, after Eq. 3).
@@ -27,6 +27,7 @@ struct ProcParams {
   double sigma_norm;
   TFParams tf_mu;                  // Drell-Yan muons
   TFParams tf_b;                   // tt b-jets
+  TFParams tf_lj;                  // light jets (semileptonic)
   // Breit-Wigner tan maps q2 = M^2 + M Gamma tan(theta), theta in [th0, th1]
   double th0_t, th1_t, th0_w, th1_w;
   // constant factors of the tt weight: couplings, (2 pi) powers, the
@@ -35,6 +36,9 @@ struct ProcParams {
   double tt_const;
   // Drell-Yan: (2 pi)^-2 (2/S) (4 pi alpha)^2 / 3 / 2
   double dy_const;
+  // semileptonic: as tt_const with three aligned propagators and the
+  // hadronic W's colour and generation factor
+  double sl_const;
 };
 
 struct EventsView {
@@ -42,6 +46,7 @@ struct EventsView {
   const double* px;
   const double* py;
   const double* pz;
+  const int32_t* charge;   // lepton charge per event (semileptonic), may be null
   int32_t n_events;
   int32_t n_obj;
   __device__ __forceinline__ void load(int obj, int ev, double& e, double& x, double& y, double& z) const

@@ -307,3 +307,119 @@ def test_target_mode(mem):
     assert conv.sum() >= 12
     assert np.all(err[conv] <= 0.01 * P[conv] * (1 + 1e-12))
     assert np.all(nu[conv] >= 3)
+
+
+# ---------------------------------------------------------- semileptonic ----
+def sl_split(obs):
+    """oracle layout (5 objects + a charge row) -> GPU components + charges"""
+    comps = torch.as_tensor(np.ascontiguousarray(obs[:, :5, :]), dtype=torch.float64).permute(2, 1, 0).contiguous()
+    charge = torch.as_tensor(obs[:, 5, 0].astype(np.int32))
+    return comps, charge
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-9)])
+def test_sl_integrand(mem, precision, tol):
+    from test_oracle_pins import sl_truth_x
+    p = mem.Process(mem.MEM_TT_SEMILEPTON, precision=precision)
+    po = oracle.sl_params()
+    d = events.ttbar_semileptonic(4, 61)
+    comps, charge = sl_split(d["obs"])
+    comps, charge = comps.cuda(), charge.cuda()
+    rng = np.random.default_rng(3)
+    n_cmp = 0
+    worst = 0.0
+    for e in range(4):
+        xt, tperm = sl_truth_x(po, d["obs"][e], d["truth"], e)
+        near = np.clip(xt + 0.003 * rng.standard_normal((150, 7)), 1e-6, 1 - 1e-6)
+        for perm in sorted({tperm, int(rng.integers(12)), int(rng.integers(12))}):
+            x = near if perm == tperm else rng.random((300, 7))
+            say(f"sl integrand precision={precision} event={e} perm={perm}")
+            f = torch.empty(len(x), dtype=torch.float64, device="cuda")
+            ns = torch.empty(len(x), dtype=torch.int32, device="cuda")
+            mem.eval_points(p, comps, e, perm, dev(x), f, ns, charge=charge)
+            torch.cuda.synchronize()
+            got, gns = f.cpu().numpy(), ns.cpu().numpy()
+            for k, xi in enumerate(x):
+                want, wns = oracle.sl_integrand(po, d["obs"][e], perm, xi)
+                if want == 0.0 and got[k] == 0.0:
+                    continue
+                r = abs(got[k] - want) / max(abs(want), 1e-300)
+                assert r <= tol and gns[k] == wns, (e, perm, k, got[k], want, gns[k], wns)
+                n_cmp += 1
+                worst = max(worst, r)
+    say(f"sl compared {n_cmp} nonzero points, worst rel {worst:.3g}")
+    assert n_cmp > 150
+
+
+def test_sl_iteration0_sums(mem):
+    p = mem.Process(mem.MEM_TT_SEMILEPTON, precision=mem.MEM_FP32)
+    po = oracle.sl_params()
+    d = events.ttbar_semileptonic(2, 62)
+    comps, charge = sl_split(d["obs"])
+    n_pts, seed = 12 * 700, 21        # 700 points per assignment: one ragged chunk each
+    it_out = torch.zeros(2 * 24 * 2, dtype=torch.float64, device="cuda")
+    say("sl integrate 2 events x 8400 points x 2 iterations")
+    mem.integrate_events(comps.cuda(), p, n_pts, 2, seed=seed, iter_out=it_out, charge=charge.cuda())
+    torch.cuda.synchronize()
+    rec = it_out.cpu().numpy().reshape(2, 24, 2)
+    g0 = oracle.uniform_grid(7)
+    for e in range(2):
+        for perm in (0, 5, 11):
+            s1, s2, _ = oracle.vegas_iteration(oracle.KIND_TT_SL, po, d["obs"][e], perm, seed, e, 0, 700, g0)
+            I0 = s1 / 700
+            assert rec[0, 12 * e + perm, 0] == pytest.approx(I0, rel=2e-5, abs=1e-300)
+
+
+def test_mixed_batch_queue_and_graph(mem):
+    """one call with Drell-Yan, dilepton and semileptonic events (uneven
+    budgets): each event's estimate equals the oracle's on the same point
+    stream within a small fraction of its MC error; graph replay and direct
+    launches agree"""
+    dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    tt = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    sl = mem.Process(mem.MEM_TT_SEMILEPTON, precision=mem.MEM_FP32)
+    dd = events.drell_yan(3, 71)["obs"]
+    dt = events.ttbar_dilepton(2, 72)["obs"]
+    ds = events.ttbar_semileptonic(2, 73)["obs"]
+    kinds = ["sl", "dy", "tt", "dy", "sl", "tt", "dy"]
+    src = {"dy": iter(dd), "tt": iter(dt), "sl": iter(ds)}
+    obs = np.zeros((len(kinds), 5, 4))
+    charge = np.ones(len(kinds), dtype=np.int32)
+    full = []
+    for i, k in enumerate(kinds):
+        o = next(src[k])
+        full.append(o)
+        n = {"dy": 2, "tt": 4, "sl": 5}[k]
+        obs[i, :n] = o[:n]
+        if k == "sl":
+            charge[i] = int(o[5, 0])
+    budgets = [4800, 2000, 3000, 1500, 6000, 2600, 900]
+    procs = [{"dy": dy, "tt": tt, "sl": sl}[k] for k in kinds]
+    comps = mem.to_components(obs).cuda()
+    ch = torch.as_tensor(charge).cuda()
+    say("mixed batch: graph")
+    P1, E1, S1 = mem.integrate_events(comps, procs, budgets, 4, seed=5, charge=ch, use_graph=1)
+    say("mixed batch: direct launches")
+    P2, E2, S2 = mem.integrate_events(comps, procs, budgets, 4, seed=5, charge=ch, use_graph=0)
+    torch.cuda.synchronize()
+    P1, E1, S1, P2 = P1.cpu().numpy(), E1.cpu().numpy(), S1.cpu().numpy(), P2.cpu().numpy()
+    assert np.all(S1 == 0)
+    assert np.allclose(P1, P2, rtol=1e-9, atol=0)
+    pars = {"dy": (oracle.KIND_DY, oracle.dy_params()), "tt": (oracle.KIND_TT, oracle.tt_params()),
+            "sl": (oracle.KIND_TT_SL, oracle.sl_params())}
+    for i, k in enumerate(kinds):
+        kind, po = pars[k]
+        npm = {"dy": 1, "tt": 2, "sl": 12}[k]
+        per = -(-budgets[i] // npm)
+        Is, vs = [], []
+        for perm in range(npm):
+            r, _, _, _ = oracle.integrate_one(kind, po, full[i], perm, 5, i, per, 4)
+            Is.append(r.I)
+            vs.append(r.sigma ** 2)
+        Po, Eo = np.mean(Is), np.sqrt(np.sum(vs)) / npm
+        say(f"event {i} ({k}): gpu {P1[i]:.6e} +- {E1[i]:.2e}  oracle {Po:.6e} +- {Eo:.2e}")
+        # Drell-Yan is FP64 on both sides (grids equal to rounding); the FP32
+        # integrands move the refined grids by ~1e-6, which shifts later
+        # iterations' points slightly: a fraction of the MC error
+        bar = 1e-3 if k == "dy" else 0.5
+        assert abs(P1[i] - Po) <= bar * Eo + 1e-9 * abs(Po)
