@@ -112,6 +112,11 @@ def _declare(L):
         "or_semilep_map": (D, [P, P, I, P, P]),
         "or_semilep_nu_z": (I, [P, D, D, D, P]),
         "or_dgauss_tf": (D, [D, D, D, D, D]),
+        "or_flow_nparams": (I, []),
+        "or_flow_forward": (D, [P, P, P, P]),
+        "or_flow_inverse": (D, [P, P, P, P]),
+        "or_flow_context": (None, [P, I, P]),
+        "or_flow_nll_grad": (D, [P, I, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -284,3 +289,51 @@ def call4(name, *args):
             keep.append(arr)
             conv.append(_ptr(arr))
     return getattr(lib(), name)(*conv)
+
+
+# ------------------------------------------------------------ flow ----
+FLOW_LAYERS, FLOW_H, FLOW_IN, FLOW_OUT = 6, 128, 28, 92
+FLOW_PER_LAYER = FLOW_H * FLOW_IN + FLOW_H + FLOW_H * FLOW_H + FLOW_H + FLOW_OUT * FLOW_H + FLOW_OUT
+
+
+def flow_init(seed, last_scale=0.0):
+    """parameters with the shapes of the flow: W1, W2 ~ N(0, 1/fan_in),
+    biases 0, the last layer scaled by last_scale (0: identity flow)"""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(FLOW_LAYERS):
+        out.append(rng.standard_normal(FLOW_H * FLOW_IN) / np.sqrt(FLOW_IN))
+        out.append(np.zeros(FLOW_H))
+        out.append(rng.standard_normal(FLOW_H * FLOW_H) / np.sqrt(FLOW_H))
+        out.append(np.zeros(FLOW_H))
+        out.append(last_scale * rng.standard_normal(FLOW_OUT * FLOW_H) / np.sqrt(FLOW_H))
+        out.append(last_scale * rng.standard_normal(FLOW_OUT))
+    return np.concatenate(out)
+
+
+def flow_forward(params, ctx, x):
+    params, ctx, x = _f64(params), _f64(ctx), _f64(x)
+    z = np.zeros(8)
+    lq = lib().or_flow_forward(_ptr(params), _ptr(ctx), _ptr(x), _ptr(z))
+    return z, lq
+
+
+def flow_inverse(params, ctx, z):
+    params, ctx, z = _f64(params), _f64(ctx), _f64(z)
+    x = np.zeros(8)
+    lq = lib().or_flow_inverse(_ptr(params), _ptr(ctx), _ptr(z), _ptr(x))
+    return x, lq
+
+
+def flow_context(ev, perm):
+    ev = _f64(ev)
+    c = np.zeros(24)
+    lib().or_flow_context(_ptr(ev), perm, _ptr(c))
+    return c
+
+
+def flow_nll_grad(params, x, ctx, wt):
+    params, x, ctx, wt = _f64(params), _f64(x), _f64(ctx), _f64(wt)
+    g = np.zeros(len(params))
+    loss = lib().or_flow_nll_grad(_ptr(params), len(wt), _ptr(x), _ptr(ctx), _ptr(wt), _ptr(g))
+    return loss, g

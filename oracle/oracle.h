@@ -143,6 +143,17 @@ double or_gauss_tf(double meas, double truth, double rel_sigma);
 double or_genz_integrand(const double* x);
 double or_genz_exact(void);
 
+/* ---------------------------------------------------- learned proposal -- */
+/* Conditional rational-quadratic spline flow on [0,1]^8 (definition in
+ * flow.c).  forward: x -> z, returns log q(x|c); inverse: z -> x, returns
+ * log q(x|c) at the returned x. */
+int or_flow_nparams(void);
+double or_flow_forward(const double* params, const double* ctx, const double* x, double* z);
+double or_flow_inverse(const double* params, const double* ctx, const double* z, double* x);
+void or_flow_context(const double* ev, int perm, double* ctx);
+double or_flow_nll_grad(const double* params, int n, const double* x, const double* ctx, const double* wt,
+                        double* grad);
+
 /* -------------------------------------------------------------- driver -- */
 enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4 };
 typedef struct {

@@ -532,3 +532,69 @@ def test_semilep_integrand_positive_at_truth():
         assert E[2] == pytest.approx(tr["b_had"][i][0], rel=1e-9)
         v, ns = oracle.sl_integrand(p, d["obs"][i], perm, x)
         assert ns >= 1 and v > 0
+
+
+# ------------------------------------------------------------ flow -----
+def test_flow_identity_at_init():
+    """zero last layer: the flow is the identity up to the fixed reversal
+    of the coordinate order, with log q = 0"""
+    p = oracle.flow_init(3, 0.0)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        c, x = rng.standard_normal(24), rng.random(8)
+        z, lq = oracle.flow_forward(p, c, x)
+        assert np.allclose(z, x[::-1], atol=1e-14) and abs(lq) < 1e-13
+
+
+def test_flow_inverse_and_logdet():
+    """inverse(forward(x)) = x; log q equals log|det dz/dx| by central
+    differences"""
+    p = oracle.flow_init(4, 0.3)
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        c, x = rng.standard_normal(24), 0.02 + 0.96 * rng.random(8)
+        z, lq = oracle.flow_forward(p, c, x)
+        x2, lq2 = oracle.flow_inverse(p, c, z)
+        assert np.allclose(x2, x, atol=1e-12) and lq2 == pytest.approx(lq, abs=1e-10)
+        J = np.zeros((8, 8))
+        for j in range(8):
+            h = 1e-6
+            e = np.zeros(8)
+            e[j] = h
+            J[:, j] = (oracle.flow_forward(p, c, x + e)[0] - oracle.flow_forward(p, c, x - e)[0]) / (2 * h)
+        assert np.log(abs(np.linalg.det(J))) == pytest.approx(lq, abs=1e-6)
+
+
+def test_flow_density_normalised():
+    """int q(x) dx = 1 over the cube: mean of q at uniform x"""
+    p = oracle.flow_init(5, 0.25)
+    rng = np.random.default_rng(2)
+    c = rng.standard_normal(24)
+    q = np.array([np.exp(oracle.flow_forward(p, c, rng.random(8))[1]) for _ in range(40000)])
+    assert abs(q.mean() - 1.0) < 4 * q.std() / np.sqrt(len(q))
+
+
+def test_flow_nll_gradient_finite_difference():
+    p = oracle.flow_init(6, 0.2)
+    rng = np.random.default_rng(3)
+    n = 5
+    x = 0.05 + 0.9 * rng.random((n, 8))
+    ctx = rng.standard_normal((n, 24))
+    wt = rng.random(n)
+    loss, g = oracle.flow_nll_grad(p, x, ctx, wt)
+    per = oracle.FLOW_PER_LAYER
+    # parameters from every block of every layer: W1, b1, W2, b2, W3, b3
+    offs = [0, 128 * 28, 128 * 28 + 128, 128 * 28 + 128 + 128 * 128, 128 * 28 + 256 + 128 * 128,
+            128 * 28 + 256 + 128 * 128 + 92 * 128]
+    sizes = [128 * 28, 128, 128 * 128, 128, 92 * 128, 92]
+    idx = []
+    for l in range(6):
+        for o, s in zip(offs, sizes):
+            idx += list(l * per + o + rng.integers(0, s, 2))
+    for i in idx:
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (oracle.flow_nll_grad(pp, x, ctx, wt)[0] - oracle.flow_nll_grad(pm, x, ctx, wt)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-7), (i, g[i], fd)
