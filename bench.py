@@ -114,7 +114,7 @@ def main():
 
     # fixed budget: integrand evaluation rate and kernel timing
     log(f"fixed-budget pass: {n_ev} events x {PTS} points x {FIXED_ITERS} iterations")
-    timing = (ctypes.c_double * 4)()
+    timing = (ctypes.c_double * 6)()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mem.integrate_events(comps, proc, PTS, FIXED_ITERS, outputs=(P, E, S), timing=timing)

@@ -109,6 +109,11 @@ typedef struct {
   int32_t on_device;
 } mem_events;
 
+/* A learned importance-sampling proposal: a conditional rational-quadratic
+ * spline flow on [0,1]^8 for the ttbar dilepton integrand (definition at
+ * mem_flow_create).  Owned by the library until mem_flow_destroy. */
+typedef struct mem_flow_s* mem_flow;
+
 /* Options of mem_integrate_events; pass NULL for the defaults listed.
  *  seed            Philox key (default: the process seed 0x14077595)
  *  alpha           VEGAS damping exponent (1.5)
@@ -123,16 +128,32 @@ typedef struct {
  *  grid_out        optional device pointer, [n_integrals][D][65]: the VEGAS
  *                  grids after the last refinement
  *  n_iter_out      optional device pointer [n_events]: iterations used
- *  timing_out      optional HOST pointer, 4 doubles: milliseconds spent in
+ *  timing_out      optional HOST pointer, 6 doubles: milliseconds spent in
  *                  the integrand kernel (HIP events around every launch on
  *                  `stream`), its number of launches, the number of
- *                  integrand evaluations it performed, and the wall time of
- *                  the call in milliseconds
+ *                  integrand evaluations it performed, the wall time of
+ *                  the call in milliseconds, milliseconds spent in the
+ *                  flow's sampling kernel and its number of launches (0
+ *                  without a flow)
  *  chunk_points    points per work-queue chunk (0: the process's tuned or
  *                  default value, 4096); a multiple of 256 up to 65536
  *  use_graph       0: launch every iteration; 1 (default when the options
  *                  are NULL): capture one iteration as a hipGraph and
- *                  replay it                                                 */
+ *                  replay it
+ *  flow            NULL: VEGAS (Sec. 2).  A flow: importance sampling from
+ *                  it instead (ttbar dilepton events only).  Batch j of an
+ *                  integral draws n_points/n_perm base points z from the
+ *                  point stream (counter blocks perm*16 + 8 + d/2,
+ *                  iteration j), maps them to x = T^-1(z; c) and weighs
+ *                  them by w = f(x)/q(x|c); all batches of an integral are
+ *                  pooled into one mean and one variance.  After the first
+ *                  batch every permutation must have ESS/N =
+ *                  (sum w)^2/(N sum w^2) >= ess_threshold, else the whole
+ *                  event is integrated by VEGAS with the same arguments
+ *                  (status MEM_EV_FLOW_FALLBACK when that converges).  In
+ *                  target mode the flow's stopping test runs from the
+ *                  second batch on.
+ *  ess_threshold   flow fallback threshold on ESS/N (0: 0.3)                */
 typedef struct {
   uint64_t seed;
   double alpha;
@@ -146,6 +167,8 @@ typedef struct {
   double* timing_out;
   int32_t chunk_points;
   int32_t use_graph;
+  mem_flow flow;
+  double ess_threshold;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */
@@ -153,7 +176,9 @@ enum {
   MEM_EV_OK = 0,
   MEM_EV_ZERO_INTEGRAND = 1,   /* every sampled weight was zero: P = err = 0 */
   MEM_EV_NOT_CONVERGED = 2,    /* target mode: max_iter reached */
-  MEM_EV_NONFINITE = 3         /* a non-finite weight was produced */
+  MEM_EV_NONFINITE = 3,        /* a non-finite weight was produced */
+  MEM_EV_FLOW_FALLBACK = 4     /* flow proposal below the ESS threshold; the
+                                  event was integrated by VEGAS instead */
 };
 
 /* Create a hypothesis (Sec. 1: process i).  Errors: MEM_EINVAL for a null
@@ -211,6 +236,88 @@ mem_status mem_eval_points(mem_process p, const mem_events* ev, int32_t event, i
  * [n_int][D][65]; alpha > 0. */
 mem_status mem_vegas_refine(const double* bins, double* grids, int32_t n_int, int32_t D,
                             double alpha, void* stream);
+
+/* Points of adapted VEGAS grids and their weights, the training samples of
+ * the flow.  For integral i = (event[i], perm[i]) with grid
+ * grids[i][D][65] (as written by mem_integrate_events' grid_out) and
+ * k < n_per: u from the point stream (seed, iter), x = VEGAS map of u, and
+ * w = f(x) J(x) (Sec. 2: the weight of x is its share of the integral).
+ * x_out: device float [n_int][n_per][D]; w_out: device float
+ * [n_int][n_per]; normalise != 0 divides each integral's weights by their
+ * sum.  event, perm: device int32 [n_int].  MEM_EINVAL on null pointers or
+ * n_per < 1. */
+mem_status mem_vegas_capture(mem_process p, const mem_events* ev, const int32_t* event, const int32_t* perm,
+                             int32_t n_int, const double* grids, int64_t n_per, uint64_t seed, uint32_t iter,
+                             int32_t normalise, float* x_out, float* w_out, void* stream);
+
+/* ---- learned proposal (conditional rational-quadratic spline flow) ----
+ * Density of x in [0,1]^8 given an event context c (24 floats):
+ * q(x|c) = |det dT/dx| with T = 6 coupling layers (Durkan et al. 2019
+ * splines, 8 bins, minimum bin width/height/derivative 1e-3, boundary
+ * derivative 1).  Coordinates are reversed before layer 3; layer l
+ * transforms positions {1,3,5,7} (l even) or {0,2,4,6} (l odd) given the
+ * other four and c, through an MLP 28 -> 128 -> 128 -> 92 with SiLU whose
+ * output at 23 j holds 8 width, 8 height and 7 derivative logits of the
+ * j-th transformed position (derivative = 1e-3 + softplus(logit + c0),
+ * c0 = ln(e^0.999 - 1), so zero logits give the identity).  Parameters:
+ * FP32 master copy, per layer row-major W1[128][28], b1[128],
+ * W2[128][128], b2[128], W3[92][128], b3[92] (192 552 floats); the two
+ * 128-wide layers run as BF16 matrix products with FP32 accumulation.
+ * Context of (event, perm), ttbar dilepton objects jet, jet, l+, l- with
+ * the jets swapped when perm = 1: for each of the four objects and for
+ * their sum (log(E/100), px/100, py/100, pz/100), then (log((|m|+1)/100),
+ * m_x/100, m_y/100, 0) of m = -(sum p_T). */
+#define MEM_FLOW_NPARAMS 192552
+#define MEM_FLOW_CONTEXT 24
+
+/* Arithmetic of the two 128-wide layers of every coupling MLP (forward
+ * passes; products always accumulate in FP32):
+ *  MEM_FLOW_BF16    activations rounded to BF16 (one matrix-core product)
+ *  MEM_FLOW_BF16X2  activations split into two BF16 terms, hi = bf16(h) and
+ *                   lo = bf16(h - hi) (about 16 significant bits; two
+ *                   products per layer)
+ * Weights are always the BF16 copies of the FP32 master parameters. */
+enum { MEM_FLOW_BF16 = 0, MEM_FLOW_BF16X2 = 1 };
+
+/* New flow with every parameter zero (the identity map, q = 1).
+ * MEM_EINVAL for an unknown mode. */
+mem_status mem_flow_create(int32_t mode, mem_flow* out);
+void mem_flow_destroy(mem_flow f);
+/* Copy all MEM_FLOW_NPARAMS parameters in (set; resets the Adam state) or
+ * out (get).  on_device: params is a device pointer, else host.  n must be
+ * MEM_FLOW_NPARAMS.  Synchronous. */
+mem_status mem_flow_set_params(mem_flow f, const float* params, int64_t n, int32_t on_device);
+mem_status mem_flow_get_params(mem_flow f, float* params, int64_t n, int32_t on_device);
+
+/* Contexts of n (event, perm) pairs of ttbar dilepton events.  event, perm:
+ * device int32 [n]; ctx: device float [n][24]. */
+mem_status mem_flow_context(const mem_events* ev, const int32_t* event, const int32_t* perm, int32_t n,
+                            float* ctx, void* stream);
+
+/* Sample n_per points of each of n_int contexts: z_k from the point stream
+ * (seed, iter, event[i], counter blocks perm[i]*16 + 8 + d/2; float of the
+ * 53-bit uniform, at most 1 - 2^-24), x = T^-1(z; c_i) and log q(x|c_i).
+ * ctx: device [n_int][24]; event, perm: device int32 [n_int]; x_out:
+ * device float [n_int][n_per][8]; logq_out: device float [n_int][n_per]. */
+mem_status mem_flow_sample(mem_flow f, const float* ctx, const int32_t* event, const int32_t* perm, int32_t n_int,
+                           int64_t n_per, uint64_t seed, uint32_t iter, float* x_out, float* logq_out,
+                           void* stream);
+
+/* log q(x_i | ctx[sint_i]) of n points (x: device float [n][8]; sint:
+ * device int32 [n], rows of ctx; logq_out: device float [n]). */
+mem_status mem_flow_log_prob(mem_flow f, const float* ctx, const int32_t* sint, const float* x, int64_t n,
+                             float* logq_out, void* stream);
+
+/* One training step on the weighted negative log-likelihood
+ * L = -sum_i wt_i log q(x_i | ctx[sint_i]): gradient by the flow's own
+ * backward kernels (FP32 accumulation of BF16 products), then, if lr > 0,
+ * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master
+ * parameters.  loss_out: optional HOST double (L; synchronises);
+ * grad_out: optional device float [MEM_FLOW_NPARAMS] (dL/dparams).
+ * Arrays as in mem_flow_log_prob; wt: device float [n].  Calls on one flow
+ * are serialised by the caller. */
+mem_status mem_flow_train_step(mem_flow f, const float* ctx, const int32_t* sint, const float* x, const float* wt,
+                               int64_t n, double lr, double* loss_out, float* grad_out, void* stream);
 
 const char* mem_status_string(mem_status s);
 /* Copies the message of the last failed call on this thread (may be empty). */

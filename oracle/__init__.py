@@ -81,6 +81,7 @@ def _declare(L):
     sig = {
         "or_philox4x32_10": (None, [P, P, P]),
         "or_uniforms": (None, [U64, U32, U32, U32, U32, I, P]),
+        "or_uniforms_block": (None, [U64, U32, U32, U32, U32, U32, I, P]),
         "or_vegas_map": (D, [P, I, P, P, P]),
         "or_vegas_uniform_grid": (None, [P, I]),
         "or_vegas_refine_dim": (None, [P, D, P]),
@@ -140,9 +141,9 @@ def philox(ctr, key):
     return out
 
 
-def uniforms(seed, k, it, event, perm, D):
+def uniforms(seed, k, it, event, perm, D, block0=0):
     u = np.zeros(D)
-    lib().or_uniforms(seed, k, it, event, perm, D, _ptr(u))
+    lib().or_uniforms_block(seed, k, it, event, perm, block0, D, _ptr(u))
     return u
 
 

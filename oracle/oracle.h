@@ -37,6 +37,8 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
  * is shifted right by 11 and scaled by 2^-53. */
 void or_uniforms(uint64_t seed, uint32_t k, uint32_t iter, uint32_t event,
                  uint32_t perm, int D, double* u);
+void or_uniforms_block(uint64_t seed, uint32_t k, uint32_t iter, uint32_t event,
+                       uint32_t perm, uint32_t block0, int D, double* u);
 
 /* ---------------------------------------------------------------- VEGAS -- */
 #define OR_NBINS 64

@@ -46,9 +46,17 @@ static double u53(uint32_t hi, uint32_t lo)
 void or_uniforms(uint64_t seed, uint32_t k, uint32_t iter, uint32_t event,
                  uint32_t perm, int D, double* u)
 {
+  or_uniforms_block(seed, k, iter, event, perm, 0u, D, u);
+}
+
+/* The same stream with the counter's last word perm*16 + block0 + b: the
+ * learned proposal draws its base points from blocks 8.. of a permutation. */
+void or_uniforms_block(uint64_t seed, uint32_t k, uint32_t iter, uint32_t event,
+                       uint32_t perm, uint32_t block0, int D, double* u)
+{
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   for (int b = 0; 2 * b < D; ++b) {
-    uint32_t ctr[4] = {k, iter, event, perm * 16u + (uint32_t)b};
+    uint32_t ctr[4] = {k, iter, event, perm * 16u + block0 + (uint32_t)b};
     uint32_t w[4];
     or_philox4x32_10(ctr, key, w);
     u[2 * b] = u53(w[0], w[1]);

@@ -16,12 +16,17 @@ MEM_DY_QQ_GAMMA_MUMU, MEM_TT_DILEPTON, MEM_TT_SEMILEPTON, MEM_TTH_SEMILEPTON = 1
 MEM_FP64, MEM_FP32 = 0, 1
 MEM_TF_DELTA, MEM_TF_UNIFORM, MEM_TF_GAUSS, MEM_TF_DGAUSS = range(4)
 MEM_OBJ_MUON, MEM_OBJ_LEPTON, MEM_OBJ_BJET, MEM_OBJ_LJET, MEM_OBJ_NEUTRINO = range(5)
-MEM_EV_OK, MEM_EV_ZERO_INTEGRAND, MEM_EV_NOT_CONVERGED, MEM_EV_NONFINITE = range(4)
+MEM_EV_OK, MEM_EV_ZERO_INTEGRAND, MEM_EV_NOT_CONVERGED, MEM_EV_NONFINITE, MEM_EV_FLOW_FALLBACK = range(5)
+FLOW_NPARAMS = 192552
+MEM_FLOW_BF16, MEM_FLOW_BF16X2 = 0, 1
+FLOW_CONTEXT = 24
 
 # every symbol include/mem.h declares
 EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_process",
            "mem_process_shape", "mem_integrate_events", "mem_uniforms", "mem_eval_points",
-           "mem_vegas_refine", "mem_status_string", "mem_last_error")
+           "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
+           "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
+           "mem_flow_log_prob", "mem_flow_train_step", "mem_status_string", "mem_last_error")
 
 
 class ProcessDesc(ctypes.Structure):
@@ -49,7 +54,8 @@ class IntegrateOpts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("alpha", ctypes.c_double), ("target_rel_err", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("stream", ctypes.c_void_p), ("outputs_on_device", ctypes.c_int32),
                 ("iter_out", ctypes.c_void_p), ("grid_out", ctypes.c_void_p), ("n_iter_out", ctypes.c_void_p),
-                ("timing_out", ctypes.c_void_p), ("chunk_points", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("timing_out", ctypes.c_void_p), ("chunk_points", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("flow", ctypes.c_void_p), ("ess_threshold", ctypes.c_double)]
 
 
 _lib = None
@@ -74,6 +80,15 @@ def lib():
             "mem_uniforms": (I32, [U64, U32, U32, U32, I32, I64, P, P]),
             "mem_eval_points": (I32, [P, P, I32, I32, P, I64, P, P, P]),
             "mem_vegas_refine": (I32, [P, P, I32, I32, D, P]),
+            "mem_vegas_capture": (I32, [P, P, P, P, I32, P, I64, U64, U32, I32, P, P, P]),
+            "mem_flow_create": (I32, [I32, P]),
+            "mem_flow_destroy": (None, [P]),
+            "mem_flow_set_params": (I32, [P, P, I64, I32]),
+            "mem_flow_get_params": (I32, [P, P, I64, I32]),
+            "mem_flow_context": (I32, [P, P, P, I32, P, P]),
+            "mem_flow_sample": (I32, [P, P, P, P, I32, I64, U64, U32, P, P, P]),
+            "mem_flow_log_prob": (I32, [P, P, P, P, I64, P, P]),
+            "mem_flow_train_step": (I32, [P, P, P, P, P, I64, D, P, P, P]),
             "mem_status_string": (ctypes.c_char_p, [I32]),
             "mem_last_error": (I32, [ctypes.c_char_p, ctypes.c_size_t]),
         }
@@ -159,10 +174,11 @@ def to_components(obs):
 
 def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=1.5, target_rel_err=0.0,
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
-                     timing=None, charge=None, chunk_points=0, use_graph=1):
+                     timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
-    int or a list per event; timing: optional ctypes (c_double * 4) array.
+    int or a list per event; timing: optional ctypes (c_double * 6) array;
+    flow: optional Flow (importance sampling from it, VEGAS fallback).
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
@@ -183,7 +199,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         grid_out.data_ptr() if grid_out is not None else None,
                         n_iter_out.data_ptr() if n_iter_out is not None else None,
                         ctypes.cast(timing, ctypes.c_void_p) if timing is not None else None,
-                        chunk_points, use_graph)
+                        chunk_points, use_graph, flow.handle.value if flow is not None else None, ess_threshold)
     _check(lib().mem_integrate_events(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                       ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
                                       ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
@@ -211,3 +227,77 @@ def vegas_refine(bins, grids, alpha=1.5, stream=None):
     _check(lib().mem_vegas_refine(ctypes.c_void_p(bins.data_ptr()), ctypes.c_void_p(grids.data_ptr()), n_int, D,
                                   alpha, _stream_ptr(stream)), "mem_vegas_refine")
     return grids
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def vegas_capture(process, comps, event, perm, grids, n_per, seed, it, x_out, w_out, normalise=1, stream=None,
+                  charge=None):
+    """mem_vegas_capture: points of adapted VEGAS grids and their weights.
+    event, perm: int32 device tensors [n_int]; grids: float64 device
+    [n_int, D, 65]; x_out: float32 [n_int, n_per, D]; w_out: float32
+    [n_int, n_per]."""
+    ev = events_struct(comps, charge)
+    _check(lib().mem_vegas_capture(process.handle, ctypes.byref(ev), _p(event), _p(perm), event.numel(), _p(grids),
+                                   n_per, seed, it, normalise, _p(x_out), _p(w_out), _stream_ptr(stream)),
+           "mem_vegas_capture")
+    return x_out, w_out
+
+
+class Flow:
+    """The learned proposal (mem_flow_*); released with the object."""
+
+    def __init__(self, mode=MEM_FLOW_BF16):
+        h = ctypes.c_void_p()
+        _check(lib().mem_flow_create(mode, ctypes.byref(h)), "mem_flow_create")
+        self.handle = h
+        self.mode = mode
+
+    def set_params(self, params):
+        """params: float32 tensor [192552] (host or device)"""
+        import torch
+        assert params.dtype == torch.float32 and params.is_contiguous() and params.numel() == FLOW_NPARAMS
+        _check(lib().mem_flow_set_params(self.handle, _p(params), FLOW_NPARAMS, 1 if params.is_cuda else 0),
+               "mem_flow_set_params")
+
+    def get_params(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(FLOW_NPARAMS, dtype=torch.float32)
+        _check(lib().mem_flow_get_params(self.handle, _p(out), FLOW_NPARAMS, 1 if out.is_cuda else 0),
+               "mem_flow_get_params")
+        return out
+
+    def sample(self, ctx, event, perm, n_per, seed, it, x_out, logq_out, stream=None):
+        _check(lib().mem_flow_sample(self.handle, _p(ctx), _p(event), _p(perm), event.numel(), n_per, seed, it,
+                                     _p(x_out), _p(logq_out), _stream_ptr(stream)), "mem_flow_sample")
+        return x_out, logq_out
+
+    def log_prob(self, ctx, sint, x, logq_out, stream=None):
+        _check(lib().mem_flow_log_prob(self.handle, _p(ctx), _p(sint), _p(x), sint.numel(), _p(logq_out),
+                                       _stream_ptr(stream)), "mem_flow_log_prob")
+        return logq_out
+
+    def train_step(self, ctx, sint, x, wt, lr=0.0, grad_out=None, want_loss=True, stream=None):
+        """one step on L = -sum wt log q; returns L (or None)"""
+        loss = ctypes.c_double(0.0)
+        _check(lib().mem_flow_train_step(self.handle, _p(ctx), _p(sint), _p(x), _p(wt), sint.numel(), lr,
+                                         ctypes.byref(loss) if want_loss else None,
+                                         _p(grad_out) if grad_out is not None else None, _stream_ptr(stream)),
+               "mem_flow_train_step")
+        return loss.value if want_loss else None
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.mem_flow_destroy(self.handle)
+            self.handle = None
+
+
+def flow_context(comps, event, perm, ctx_out, stream=None):
+    """mem_flow_context: ctx_out float32 device [n, 24]"""
+    ev = events_struct(comps)
+    _check(lib().mem_flow_context(ctypes.byref(ev), _p(event), _p(perm), event.numel(), _p(ctx_out),
+                                  _stream_ptr(stream)), "mem_flow_context")
+    return ctx_out

@@ -43,13 +43,16 @@ __device__ __forceinline__ double u53(uint32_t hi, uint32_t lo)
 }
 
 // Uniforms of point k: dims (2b, 2b+1) from counter {k, iter, event, perm*16+b}.
+// block0 offsets the counter block (the learned proposal draws its base
+// points from blocks 8..11 of the same stream).
 template <int D>
 __device__ __forceinline__ void point_uniforms(uint64_t seed, uint32_t k, uint32_t iter,
-                                               uint32_t event, uint32_t perm, double (&u)[D])
+                                               uint32_t event, uint32_t perm, double (&u)[D],
+                                               uint32_t block0 = 0u)
 {
 #pragma unroll
   for (int b = 0; 2 * b < D; ++b) {
-    u32x4 w = philox10(u32x4{k, iter, event, perm * 16u + (uint32_t)b},
+    u32x4 w = philox10(u32x4{k, iter, event, perm * 16u + block0 + (uint32_t)b},
                        (uint32_t)seed, (uint32_t)(seed >> 32));
     u[2 * b] = u53(w.x, w.y);
     if (2 * b + 1 < D) u[2 * b + 1] = u53(w.z, w.w);

@@ -76,7 +76,8 @@ __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)
 }
 
 // Points [start, start + count) of one chunk: sum w, sum w^2 and the
-// per-bin sums of w^2 (LDS atomics).  F(x) is the integrand.
+// per-bin sums of w^2 (LDS atomics into the calling wavefront's own bins).
+// F(x) is the integrand.
 template <int D, class F>
 __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
                                              double* sbins, double& s1, double& s2, F&& f)
@@ -109,7 +110,9 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_queue_kernel(
     uint64_t seed, Control* __restrict__ ctl, uint32_t* __restrict__ head, double* __restrict__ parts)
 {
   __shared__ double sgrid[kMaxDims * (kBins + 1)];
-  __shared__ double sbins[kMaxDims * kBins];
+  // per-wavefront bin sums, combined in wavefront order: the result does not
+  // depend on how the wavefronts interleave
+  __shared__ double sbins[kBlock / kWave][kMaxDims * kBins];
   __shared__ double red[2 * kBlock / kWave];
   __shared__ int64_t s_next;
   const uint32_t iter = ctl->iter;
@@ -124,31 +127,39 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_queue_kernel(
     const IntegralDesc in = ints[ch.integral];
     const int D = in.dims;
     for (int i = threadIdx.x; i < D * (kBins + 1); i += kBlock) sgrid[i] = grids[in.grid_off + i];
-    for (int i = threadIdx.x; i < D * kBins; i += kBlock) sbins[i] = 0.0;
+    for (int i = threadIdx.x; i < D * kBins; i += kBlock)
+#pragma unroll
+      for (int w = 0; w < kBlock / kWave; ++w) sbins[w][i] = 0.0;
     __syncthreads();
     const ProcParams& pp = procs[ch.proc];
+    double* wbins = sbins[threadIdx.x / kWave];
     double s1 = 0.0, s2 = 0.0;
     if ((KINDS & kMaskDY) && pp.kind == kDY) {
       DYEvent e;
       dy_load(ev, ch.event, e);
-      chunk_points<2>(ch, seed, iter, sgrid, sbins, s1, s2,
+      chunk_points<2>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[2]) { return dy_integrand(pp, e, x); });
     } else if ((KINDS & kMaskTT) && pp.kind == kTT) {
       TTEvent e;
       tt_load(ev, ch.event, ch.perm, e);
-      chunk_points<8>(ch, seed, iter, sgrid, sbins, s1, s2,
+      chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskSL) && pp.kind == kSL) {
       SLEvent e;
       sl_load(ev, ev.charge, ch.event, ch.perm, e);
-      chunk_points<7>(ch, seed, iter, sgrid, sbins, s1, s2,
+      chunk_points<7>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[7]) { return sl_integrand<T>(pp, e, x, nullptr); });
     }
     block_reduce2<0>(s1, s2, red);
     __syncthreads();
     double* out = parts + ch.part_off;
     if (threadIdx.x == 0) { out[0] = s1; out[1] = s2; }
-    for (int i = threadIdx.x; i < D * kBins; i += kBlock) out[2 + i] = sbins[i];
+    for (int i = threadIdx.x; i < D * kBins; i += kBlock) {
+      double b = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlock / kWave; ++w) b += sbins[w][i];
+      out[2 + i] = b;
+    }
     __syncthreads();
   }
 }

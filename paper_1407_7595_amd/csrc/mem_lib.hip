@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/mem.h"
+#include "flow_kernels.hpp"
 #include "kernels.hpp"
 
 using namespace memk;
@@ -484,6 +485,14 @@ struct Group {
 
 }  // namespace
 
+static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                 const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
+                                 double* p_out, double* err_out, int32_t* status_out);
+
+static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                  const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
+                                  double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask);
+
 // ---------------------------------------------------------- integrate ----
 extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                            const int64_t* n_points, int32_t n_np, int32_t n_iter,
@@ -511,6 +520,20 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
   int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : kDefaultChunk;
   if (chunk_pts % kBlock != 0 || chunk_pts > 65536) return fail(MEM_EINVAL, "chunk_points must be a multiple of 256 <= 65536");
   if (n_ev == 0) return MEM_OK;
+  if (o.flow) return integrate_flow(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out);
+  return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr);
+}
+
+// VEGAS over every event, or over the events with ev_mask[e] != 0 (host
+// array; the others are skipped and their outputs are undefined).
+static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                  const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
+                                  double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask)
+{
+  mem_status st = MEM_OK;
+  const int n_ev = ev->n_events;
+  const bool target_mode = o.target_rel_err > 0.0;
+  int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : kDefaultChunk;
 
   // ---- processes, integrals (event x permutation) and chunks ----
   std::vector<const mem_process_s*> procs;
@@ -653,6 +676,15 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
                        b_ints.as<IntegralDesc>(), n_int);
     HIP_TRY(hipGetLastError());
   }
+  if (ev_mask) {
+    // skipped events: integrals inactive and the event retired from the start
+    std::vector<int32_t> act(n_int), dn(n_ev);
+    for (int ig = 0; ig < n_int; ++ig) act[ig] = ev_mask[ints[ig].event] ? 1 : 0;
+    for (int e = 0; e < n_ev; ++e) dn[e] = ev_mask[e] ? 0 : 1;
+    HIP_TRY(hipMemcpyAsync(b_active.p, act.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemcpyAsync(b_done.p, dn.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipStreamSynchronize(ws));
+  }
   for (auto& G : groups) {
     G.kernel = G.prec == MEM_FP32 ? queue_kernel_for<float>(G.mask) : queue_kernel_for<double>(G.mask);
     G.blocks = persistent_blocks(G.kernel, (int64_t)G.queue.size());
@@ -768,6 +800,8 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
     o.timing_out[1] = (double)(tev.size() / 2);
     o.timing_out[2] = n_evals * used_iters;
     o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+    o.timing_out[4] = 0.0;
+    o.timing_out[5] = 0.0;
   }
   return MEM_OK;
 }
@@ -831,6 +865,624 @@ extern "C" mem_status mem_vegas_refine(const double* bins, double* grids, int32_
   if (n_int == 0) return MEM_OK;
   hipLaunchKernelGGL(refine_only_kernel, dim3(n_int), dim3(kBlock), 0, (hipStream_t)stream, bins, grids, D, alpha);
   HIP_TRY(hipGetLastError());
+  return MEM_OK;
+}
+
+// ------------------------------------------------------- training data ----
+extern "C" mem_status mem_vegas_capture(mem_process p, const mem_events* ev, const int32_t* event,
+                                        const int32_t* perm, int32_t n_int, const double* grids, int64_t n_per,
+                                        uint64_t seed, uint32_t iter, int32_t normalise, float* x_out,
+                                        float* w_out, void* stream)
+{
+  if (!p || !event || !perm || !grids || !x_out || !w_out) return fail(MEM_EINVAL, "null argument");
+  mem_status st = check_event_arrays(ev);
+  if (st != MEM_OK) return st;
+  if (n_int < 0 || n_per < 1 || n_per > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "bad sizes");
+  if (ev->n_obj < n_obj_of(p->desc.kind)) return fail(MEM_EINVAL, "n_obj too small for the process kind");
+  if (n_int == 0) return MEM_OK;
+  // the kernels index events through event[]: check them on the host
+  std::vector<int32_t> he(n_int), hp(n_int);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(he.data(), event, n_int * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hp.data(), perm, n_int * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < n_int; ++i) {
+    if (he[i] < 0 || he[i] >= ev->n_events) return fail(MEM_EINVAL, "event index out of range");
+    if (hp[i] < 0 || hp[i] >= p->pp.n_perm) return fail(MEM_EINVAL, "permutation out of range");
+    st = check_host_event(ev, he[i], n_obj_of(p->desc.kind));
+    if (st != MEM_OK) return st;
+  }
+  DevEvents dev;
+  st = dev.make(ev, s);
+  if (st != MEM_OK) return st;
+  const int64_t tot = (int64_t)n_int * n_per;
+  dim3 grid((unsigned)((tot + kBlock - 1) / kBlock));
+  const bool f32 = p->desc.precision == MEM_FP32;
+  switch (p->desc.kind) {
+    case MEM_DY_QQ_GAMMA_MUMU:
+      hipLaunchKernelGGL((capture_kernel<kDY, 2, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
+                         n_int, grids, n_per, seed, iter, x_out, w_out);
+      break;
+    case MEM_TT_SEMILEPTON:
+      if (f32)
+        hipLaunchKernelGGL((capture_kernel<kSL, 7, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
+                           n_int, grids, n_per, seed, iter, x_out, w_out);
+      else
+        hipLaunchKernelGGL((capture_kernel<kSL, 7, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                           perm, n_int, grids, n_per, seed, iter, x_out, w_out);
+      break;
+    default:
+      if (f32)
+        hipLaunchKernelGGL((capture_kernel<kTT, 8, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
+                           n_int, grids, n_per, seed, iter, x_out, w_out);
+      else
+        hipLaunchKernelGGL((capture_kernel<kTT, 8, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                           perm, n_int, grids, n_per, seed, iter, x_out, w_out);
+  }
+  HIP_TRY(hipGetLastError());
+  if (normalise) {
+    hipLaunchKernelGGL(normalise_kernel, dim3(n_int), dim3(kBlock), 0, s, w_out, n_per);
+    HIP_TRY(hipGetLastError());
+  }
+  if (!ev->on_device) HIP_TRY(hipStreamSynchronize(s));
+  return MEM_OK;
+}
+
+// ------------------------------------------------------------------ flow ----
+struct mem_flow_s {
+  float* P = nullptr;       // FP32 master parameters
+  float* grad = nullptr;
+  float* m = nullptr;       // Adam moments
+  float* v = nullptr;
+  uint16_t* Wb = nullptr;   // BF16 operand copies of the 128-wide layers
+  float* tape = nullptr;    // training tape, tape_cap samples
+  float* lq = nullptr;      // log q of the training samples
+  int64_t tape_cap = 0;
+  double* loss_parts = nullptr;
+  int64_t step = 0;
+  int32_t mode = MEM_FLOW_BF16;
+  ~mem_flow_s()
+  {
+    for (void* q : {(void*)P, (void*)grad, (void*)m, (void*)v, (void*)Wb, (void*)tape, (void*)lq, (void*)loss_parts})
+      if (q) (void)hipFree(q);
+  }
+};
+
+namespace {
+constexpr int kLossBlocks = 256;
+
+__global__ void fill_f32_kernel(float* p, int64_t n, float v)
+{
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void fill_f32(float* p, int64_t n, float v, hipStream_t s)
+{
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+}
+
+mem_status flow_convert(mem_flow f, hipStream_t s)
+{
+  const int64_t n = (int64_t)FLAYERS * FB_PER;
+  hipLaunchKernelGGL(flow_convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f->P, f->Wb);
+  HIP_TRY(hipGetLastError());
+  return MEM_OK;
+}
+
+mem_status flow_tape(mem_flow f, int64_t n)
+{
+  const int64_t need = (n + FP - 1) / FP * FP;
+  if (need <= f->tape_cap) return MEM_OK;
+  if (f->tape) { (void)hipFree(f->tape); f->tape = nullptr; }
+  if (f->lq) { (void)hipFree(f->lq); f->lq = nullptr; }
+  f->tape_cap = 0;
+  HIP_TRY(hipMalloc(&f->tape, (size_t)need * FLAYERS * FTAPE * sizeof(float)));
+  HIP_TRY(hipMalloc(&f->lq, (size_t)need * sizeof(float)));
+  f->tape_cap = need;
+  return MEM_OK;
+}
+
+// the first layer's context part of n contexts
+mem_status flow_cvec(mem_flow f, const float* ctx, int n, float* cvec, hipStream_t s)
+{
+  const int64_t t = (int64_t)n * FLAYERS * FH;
+  hipLaunchKernelGGL(flow_cvec_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, f->P, ctx, n, cvec);
+  HIP_TRY(hipGetLastError());
+  return MEM_OK;
+}
+
+// sint must index rows [0, n_ctx) of the context table
+mem_status check_sint(const int32_t* sint, int64_t n, hipStream_t s, int32_t* max_out)
+{
+  std::vector<int32_t> h(n);
+  HIP_TRY(hipMemcpyAsync(h.data(), sint, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int32_t mx = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (h[i] < 0) return fail(MEM_EINVAL, "negative context index");
+    mx = std::max(mx, h[i]);
+  }
+  *max_out = mx;
+  return MEM_OK;
+}
+}  // namespace
+
+extern "C" mem_status mem_flow_create(int32_t mode, mem_flow* out)
+{
+  if (!out) return fail(MEM_EINVAL, "null argument");
+  *out = nullptr;
+  if (mode != MEM_FLOW_BF16 && mode != MEM_FLOW_BF16X2) return fail(MEM_EINVAL, "unknown flow mode");
+  mem_flow f = new (std::nothrow) mem_flow_s;
+  if (!f) return fail(MEM_ENOMEM, "host allocation");
+  f->mode = mode;
+  auto bad = [&](mem_status st) { delete f; return st; };
+  for (float** q : {&f->P, &f->grad, &f->m, &f->v}) {
+    if (hipMalloc(q, (size_t)FNP * sizeof(float)) != hipSuccess) return bad(fail(MEM_ENOMEM, "flow parameters"));
+    if (hipMemset(*q, 0, (size_t)FNP * sizeof(float)) != hipSuccess) return bad(fail(MEM_EDEVICE, "hipMemset"));
+  }
+  if (hipMalloc(&f->Wb, (size_t)FLAYERS * FB_PER * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc(&f->loss_parts, kLossBlocks * sizeof(double)) != hipSuccess)
+    return bad(fail(MEM_ENOMEM, "flow buffers"));
+  mem_status st = flow_convert(f, nullptr);
+  if (st != MEM_OK) return bad(st);
+  if (hipDeviceSynchronize() != hipSuccess) return bad(fail(MEM_EDEVICE, "hipDeviceSynchronize"));
+  *out = f;
+  return MEM_OK;
+}
+
+extern "C" void mem_flow_destroy(mem_flow f)
+{
+  if (!f) return;
+  (void)hipDeviceSynchronize();
+  delete f;
+}
+
+extern "C" mem_status mem_flow_set_params(mem_flow f, const float* params, int64_t n, int32_t on_device)
+{
+  if (!f || !params) return fail(MEM_EINVAL, "null argument");
+  if (n != FNP) return fail(MEM_EINVAL, "parameter count must be 192552");
+  HIP_TRY(hipMemcpy(f->P, params, (size_t)FNP * sizeof(float),
+                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(f->m, 0, (size_t)FNP * sizeof(float)));
+  HIP_TRY(hipMemset(f->v, 0, (size_t)FNP * sizeof(float)));
+  f->step = 0;
+  mem_status st = flow_convert(f, nullptr);
+  if (st != MEM_OK) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_get_params(mem_flow f, float* params, int64_t n, int32_t on_device)
+{
+  if (!f || !params) return fail(MEM_EINVAL, "null argument");
+  if (n != FNP) return fail(MEM_EINVAL, "parameter count must be 192552");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(params, f->P, (size_t)FNP * sizeof(float),
+                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_context(const mem_events* ev, const int32_t* event, const int32_t* perm, int32_t n,
+                                       float* ctx, void* stream)
+{
+  if (!event || !perm || !ctx) return fail(MEM_EINVAL, "null argument");
+  mem_status st = check_event_arrays(ev);
+  if (st != MEM_OK) return st;
+  if (n < 0) return fail(MEM_EINVAL, "negative n");
+  if (ev->n_obj < 4) return fail(MEM_EINVAL, "n_obj too small for ttbar dilepton");
+  if (n == 0) return MEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> he(n), hp(n);
+  HIP_TRY(hipMemcpyAsync(he.data(), event, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hp.data(), perm, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    if (he[i] < 0 || he[i] >= ev->n_events) return fail(MEM_EINVAL, "event index out of range");
+    if (hp[i] < 0 || hp[i] > 1) return fail(MEM_EINVAL, "permutation out of range");
+    st = check_host_event(ev, he[i], 4);
+    if (st != MEM_OK) return st;
+  }
+  DevEvents dev;
+  st = dev.make(ev, s);
+  if (st != MEM_OK) return st;
+  hipLaunchKernelGGL(flow_ctx_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dev.view, event, perm, n, ctx);
+  HIP_TRY(hipGetLastError());
+  if (!ev->on_device) HIP_TRY(hipStreamSynchronize(s));
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_sample(mem_flow f, const float* ctx, const int32_t* event, const int32_t* perm,
+                                      int32_t n_int, int64_t n_per, uint64_t seed, uint32_t iter, float* x_out,
+                                      float* logq_out, void* stream)
+{
+  if (!f || !ctx || !event || !perm || !x_out || !logq_out) return fail(MEM_EINVAL, "null argument");
+  if (n_int < 0 || n_per < 1 || n_per > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "bad sizes");
+  if (n_int == 0) return MEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> he(n_int), hp(n_int);
+  HIP_TRY(hipMemcpyAsync(he.data(), event, n_int * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hp.data(), perm, n_int * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<FlowChunk> ch;
+  for (int i = 0; i < n_int; ++i)
+    for (int64_t s0 = 0; s0 < n_per; s0 += FP)
+      ch.push_back(FlowChunk{i, he[i], hp[i], (int32_t)std::min<int64_t>(FP, n_per - s0), s0, (int64_t)i * n_per + s0});
+  if ((int64_t)ch.size() > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "too many points");
+  DevBuf b_cvec, b_ch;
+  HIP_TRY(b_cvec.alloc((size_t)n_int * FLAYERS * FH * sizeof(float)));
+  HIP_TRY(b_ch.alloc(ch.size() * sizeof(FlowChunk)));
+  HIP_TRY(hipMemcpyAsync(b_ch.p, ch.data(), ch.size() * sizeof(FlowChunk), hipMemcpyHostToDevice, s));
+  mem_status st = flow_cvec(f, ctx, n_int, b_cvec.as<float>(), s);
+  if (st != MEM_OK) return st;
+  hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_sample_kernel<true> : flow_sample_kernel<false>,
+                     dim3((unsigned)ch.size()), dim3(FT), 0, s, f->P, f->Wb, b_cvec.as<float>(),
+                     b_ch.as<FlowChunk>(), seed, iter, (const uint32_t*)nullptr, (const int32_t*)nullptr, x_out,
+                     logq_out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));   // the chunk table is freed on return
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_log_prob(mem_flow f, const float* ctx, const int32_t* sint, const float* x, int64_t n,
+                                        float* logq_out, void* stream)
+{
+  if (!f || !ctx || !sint || !x || !logq_out) return fail(MEM_EINVAL, "null argument");
+  if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "bad size");
+  if (n == 0) return MEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t n_ctx = 0;
+  mem_status st = check_sint(sint, n, s, &n_ctx);
+  if (st != MEM_OK) return st;
+  n_ctx += 1;
+  st = flow_tape(f, n);
+  if (st != MEM_OK) return st;
+  DevBuf b_cvec;
+  HIP_TRY(b_cvec.alloc((size_t)n_ctx * FLAYERS * FH * sizeof(float)));
+  st = flow_cvec(f, ctx, n_ctx, b_cvec.as<float>(), s);
+  if (st != MEM_OK) return st;
+  hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_train_fwd_kernel<true> : flow_train_fwd_kernel<false>,
+                     dim3((unsigned)((n + FP - 1) / FP)), dim3(FT), 0, s, f->P, f->Wb,
+                     b_cvec.as<float>(), sint, x, (int)n, f->tape, logq_out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_train_step(mem_flow f, const float* ctx, const int32_t* sint, const float* x,
+                                          const float* wt, int64_t n, double lr, double* loss_out, float* grad_out,
+                                          void* stream)
+{
+  if (!f || !ctx || !sint || !x || !wt) return fail(MEM_EINVAL, "null argument");
+  if (n < 1 || n > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "bad size");
+  if (!(lr >= 0.0)) return fail(MEM_EINVAL, "lr must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t n_ctx = 0;
+  mem_status st = check_sint(sint, n, s, &n_ctx);
+  if (st != MEM_OK) return st;
+  n_ctx += 1;
+  st = flow_tape(f, n);
+  if (st != MEM_OK) return st;
+  DevBuf b_cvec;
+  HIP_TRY(b_cvec.alloc((size_t)n_ctx * FLAYERS * FH * sizeof(float)));
+  st = flow_cvec(f, ctx, n_ctx, b_cvec.as<float>(), s);
+  if (st != MEM_OK) return st;
+  fill_f32(f->grad, FNP, 0.0f, s);
+  const unsigned nb = (unsigned)((n + FP - 1) / FP);
+  hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_train_fwd_kernel<true> : flow_train_fwd_kernel<false>,
+                     dim3(nb), dim3(FT), 0, s, f->P, f->Wb, b_cvec.as<float>(), sint, x, (int)n, f->tape, f->lq);
+  hipLaunchKernelGGL(flow_train_bwd_kernel, dim3(nb), dim3(FT), 0, s, f->P, f->Wb, ctx, sint, wt, (int)n, f->tape,
+                     f->grad);
+  HIP_TRY(hipGetLastError());
+  if (grad_out) HIP_TRY(hipMemcpyAsync(grad_out, f->grad, (size_t)FNP * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (loss_out) {
+    hipLaunchKernelGGL(flow_loss_kernel, dim3(kLossBlocks), dim3(kBlock), 0, s, wt, f->lq, n, f->loss_parts);
+    HIP_TRY(hipGetLastError());
+    double h[kLossBlocks];
+    HIP_TRY(hipMemcpyAsync(h, f->loss_parts, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double L = 0.0;
+    for (int i = 0; i < kLossBlocks; ++i) L += h[i];
+    *loss_out = L;
+  }
+  if (lr > 0.0) {
+    f->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)f->step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)f->step)));
+    hipLaunchKernelGGL(flow_adam_kernel, dim3((FNP + 255) / 256), dim3(256), 0, s, f->P, f->grad, f->m, f->v, FNP,
+                       (float)lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+    HIP_TRY(hipGetLastError());
+    st = flow_convert(f, s);
+    if (st != MEM_OK) return st;
+  }
+  HIP_TRY(hipStreamSynchronize(s));   // the context projection is freed on return
+  return MEM_OK;
+}
+
+// Flow-proposal integration (see mem_integrate_opts.flow).
+static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                 const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
+                                 double* p_out, double* err_out, int32_t* status_out)
+{
+  const int n_ev = ev->n_events;
+  mem_flow fl = o.flow;
+  const double thr = o.ess_threshold > 0.0 ? o.ess_threshold : 0.3;
+  const bool target_mode = o.target_rel_err > 0.0;
+  std::vector<const mem_process_s*> procs;
+  std::vector<int> ev_proc(n_ev);
+  int prec = -1;
+  for (int e = 0; e < n_ev; ++e) {
+    const mem_process p = hyp[n_hyp == 1 ? 0 : e];
+    if (!p) return fail(MEM_EINVAL, "null process handle");
+    if (p->desc.kind != MEM_TT_DILEPTON) return fail(MEM_EUNSUPPORTED, "the flow proposal covers ttbar dilepton only");
+    if (prec < 0) prec = p->desc.precision;
+    if (p->desc.precision != prec) return fail(MEM_EINVAL, "one precision per flow call");
+    if (ev->n_obj < 4) return fail(MEM_EINVAL, "n_obj too small for the process kind");
+    mem_status st = check_host_event(ev, e, 4);
+    if (st != MEM_OK) return st;
+    int pi = -1;
+    for (size_t k = 0; k < procs.size(); ++k) if (procs[k] == p) pi = (int)k;
+    if (pi < 0) { procs.push_back(p); pi = (int)procs.size() - 1; }
+    ev_proc[e] = pi;
+  }
+  std::vector<ProcParams> ptab(procs.size());
+  for (size_t k = 0; k < procs.size(); ++k) ptab[k] = procs[k]->pp;
+  // integrals, sampling chunks (FP points), weight chunks (FW points)
+  std::vector<FlowIntegral> ints;
+  std::vector<int32_t> int_proc, int_ev, int_perm;
+  std::vector<int64_t> ev_int0(n_ev);
+  std::vector<int32_t> ev_np(n_ev);
+  std::vector<double> ev_norm(n_ev);
+  std::vector<FlowChunk> sch, wch;
+  int64_t tot = 0;
+  for (int e = 0; e < n_ev; ++e) {
+    const mem_process_s* p = procs[ev_proc[e]];
+    const int np = p->pp.n_perm;
+    const int64_t per = (n_points[n_np == 1 ? 0 : e] + np - 1) / np;
+    if (per < 2) return fail(MEM_EINVAL, "n_points too small");
+    if (per > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "n_points exceeds 2^32 per permutation");
+    ev_int0[e] = (int64_t)ints.size();
+    ev_np[e] = np;
+    ev_norm[e] = p->desc.sigma_norm > 0.0 ? 1.0 / p->desc.sigma_norm : 1.0;
+    for (int k = 0; k < np; ++k) {
+      const int ig = (int)ints.size();
+      FlowIntegral d{(int32_t)wch.size(), 0, per};
+      for (int64_t s0 = 0; s0 < per; s0 += FP)
+        sch.push_back(FlowChunk{ig, e, k, (int32_t)std::min<int64_t>(FP, per - s0), s0, tot + s0});
+      for (int64_t s0 = 0; s0 < per; s0 += FW) {
+        wch.push_back(FlowChunk{ig, e, k, (int32_t)std::min<int64_t>(FW, per - s0), s0, tot + s0});
+        d.n_wchunks++;
+      }
+      tot += per;
+      ints.push_back(d);
+      int_proc.push_back(ev_proc[e]);
+      int_ev.push_back(e);
+      int_perm.push_back(k);
+    }
+  }
+  if (tot > ((int64_t)1 << 28)) return fail(MEM_EINVAL, "a flow batch is limited to 2^28 points");
+  const int n_int = (int)ints.size();
+
+  hipStream_t s = (hipStream_t)o.stream;
+  hipStream_t own = nullptr;
+  const bool want_graph = o.use_graph != 0 && o.timing_out == nullptr;
+  if (!s && want_graph) HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+  struct StreamGuard { hipStream_t& s; ~StreamGuard() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } } sg{own};
+  hipStream_t ws = own ? own : s;
+  DevEvents dev;
+  mem_status st = dev.make(ev, ws);
+  if (st != MEM_OK) return st;
+  DevBuf b_procs, b_iproc, b_iev, b_iperm, b_ctx, b_cvec, b_ints, b_sch, b_wch, b_parts, b_state, b_active, b_evi0,
+      b_evnp, b_evnorm, b_done, b_ctl, b_x, b_lq, b_P, b_err, b_status;
+  HIP_TRY(b_procs.alloc(ptab.size() * sizeof(ProcParams)));
+  HIP_TRY(b_iproc.alloc(n_int * sizeof(int32_t)));
+  HIP_TRY(b_iev.alloc(n_int * sizeof(int32_t)));
+  HIP_TRY(b_iperm.alloc(n_int * sizeof(int32_t)));
+  HIP_TRY(b_ctx.alloc((size_t)n_int * FCTX * sizeof(float)));
+  HIP_TRY(b_cvec.alloc((size_t)n_int * FLAYERS * FH * sizeof(float)));
+  HIP_TRY(b_ints.alloc(ints.size() * sizeof(FlowIntegral)));
+  HIP_TRY(b_sch.alloc(sch.size() * sizeof(FlowChunk)));
+  HIP_TRY(b_wch.alloc(wch.size() * sizeof(FlowChunk)));
+  HIP_TRY(b_parts.alloc(wch.size() * 2 * sizeof(double)));
+  HIP_TRY(b_state.alloc((size_t)n_int * FS_SIZE * sizeof(double)));
+  HIP_TRY(b_active.alloc(n_int * sizeof(int32_t)));
+  HIP_TRY(b_evi0.alloc(n_ev * sizeof(int64_t)));
+  HIP_TRY(b_evnp.alloc(n_ev * sizeof(int32_t)));
+  HIP_TRY(b_evnorm.alloc(n_ev * sizeof(double)));
+  HIP_TRY(b_done.alloc(n_ev * sizeof(int32_t)));
+  HIP_TRY(b_ctl.alloc(sizeof(Control)));
+  HIP_TRY(b_x.alloc((size_t)tot * 8 * sizeof(float)));
+  HIP_TRY(b_lq.alloc((size_t)tot * sizeof(float)));
+  const bool out_dev = o.outputs_on_device != 0;
+  if (!out_dev) {
+    HIP_TRY(b_P.alloc(n_ev * sizeof(double)));
+    HIP_TRY(b_err.alloc(n_ev * sizeof(double)));
+    HIP_TRY(b_status.alloc(n_ev * sizeof(int32_t)));
+  }
+  HIP_TRY(hipMemcpyAsync(b_procs.p, ptab.data(), ptab.size() * sizeof(ProcParams), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_iproc.p, int_proc.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_iev.p, int_ev.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_iperm.p, int_perm.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_ints.p, ints.data(), ints.size() * sizeof(FlowIntegral), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_sch.p, sch.data(), sch.size() * sizeof(FlowChunk), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_wch.p, wch.data(), wch.size() * sizeof(FlowChunk), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_evi0.p, ev_int0.data(), n_ev * sizeof(int64_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_evnp.p, ev_np.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+  HIP_TRY(hipMemcpyAsync(b_evnorm.p, ev_norm.data(), n_ev * sizeof(double), hipMemcpyHostToDevice, ws));
+  const Control ctl0{0u, 0u, 0, 0u};
+  HIP_TRY(hipMemcpyAsync(b_ctl.p, &ctl0, sizeof(Control), hipMemcpyHostToDevice, ws));
+  {
+    const int64_t ns = (int64_t)n_int * FS_SIZE;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, ws, b_state.as<double>(), ns, 0.0);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n_int + 255) / 256), dim3(256), 0, ws, b_active.as<int32_t>(),
+                       (int64_t)n_int, 1);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n_ev + 255) / 256), dim3(256), 0, ws, b_done.as<int32_t>(),
+                       (int64_t)n_ev, 0);
+    hipLaunchKernelGGL(flow_ctx_kernel, dim3((n_int + 255) / 256), dim3(256), 0, ws, dev.view,
+                       b_iev.as<int32_t>(), b_iperm.as<int32_t>(), n_int, b_ctx.as<float>());
+    HIP_TRY(hipGetLastError());
+  }
+  st = flow_cvec(fl, b_ctx.as<float>(), n_int, b_cvec.as<float>(), ws);
+  if (st != MEM_OK) return st;
+
+  Control* ctl = b_ctl.as<Control>();
+  const int ev_blocks = (n_ev + 255) / 256;
+  auto wkernel = prec == MEM_FP32 ? flow_weight_kernel<float> : flow_weight_kernel<double>;
+  std::vector<hipEvent_t> tev_s, tev_w;
+  auto timed = [&](std::vector<hipEvent_t>* tv, bool on, auto&& launch) -> mem_status {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (on) {
+      HIP_TRY(hipEventCreate(&a));
+      HIP_TRY(hipEventCreate(&b));
+      tv->push_back(a);
+      tv->push_back(b);
+      HIP_TRY(hipEventRecord(a, ws));
+    }
+    launch();
+    HIP_TRY(hipGetLastError());
+    if (on) HIP_TRY(hipEventRecord(b, ws));
+    return MEM_OK;
+  };
+  auto enqueue_iteration = [&](bool time_kernels) -> mem_status {
+    hipLaunchKernelGGL(flow_iter_begin_kernel, dim3(1), dim3(64), 0, ws, &ctl->n_running);
+    mem_status es = timed(&tev_s, time_kernels, [&] {
+      hipLaunchKernelGGL(fl->mode == MEM_FLOW_BF16X2 ? flow_sample_kernel<true> : flow_sample_kernel<false>,
+                         dim3((unsigned)sch.size()), dim3(FT), 0, ws, fl->P, fl->Wb,
+                         b_cvec.as<float>(), b_sch.as<FlowChunk>(), o.seed, 0u, &ctl->iter, b_active.as<int32_t>(),
+                         b_x.as<float>(), b_lq.as<float>());
+    });
+    if (es != MEM_OK) return es;
+    es = timed(&tev_w, time_kernels, [&] {
+      hipLaunchKernelGGL(wkernel, dim3((unsigned)wch.size()), dim3(kBlock), 0, ws, b_procs.as<ProcParams>(),
+                         b_iproc.as<int32_t>(), dev.view, b_wch.as<FlowChunk>(), b_active.as<int32_t>(),
+                         b_x.as<float>(), b_lq.as<float>(), (double*)nullptr, b_parts.as<double>());
+    });
+    if (es != MEM_OK) return es;
+    hipLaunchKernelGGL(flow_finish_kernel, dim3((n_int + 255) / 256), dim3(256), 0, ws, b_ints.as<FlowIntegral>(),
+                       b_parts.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), &ctl->iter, n_int, thr,
+                       o.iter_out);
+    hipLaunchKernelGGL(flow_event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(),
+                       b_evnp.as<int32_t>(), b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
+                       target_mode ? o.target_rel_err : 0.0, &ctl->iter, &ctl->n_running, 0, nullptr, nullptr,
+                       nullptr, nullptr, b_done.as<int32_t>());
+    hipLaunchKernelGGL(flow_iter_end_kernel, dim3(1), dim3(64), 0, ws, &ctl->iter);
+    HIP_TRY(hipGetLastError());
+    return MEM_OK;
+  };
+
+  struct EventsGuard {
+    std::vector<hipEvent_t>& a; std::vector<hipEvent_t>& b;
+    ~EventsGuard() { for (auto e : a) (void)hipEventDestroy(e); for (auto e : b) (void)hipEventDestroy(e); }
+  } eg{tev_s, tev_w};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraph_t& g; hipGraphExec_t& x;
+    ~GraphGuard() { if (x) (void)hipGraphExecDestroy(x); if (g) (void)hipGraphDestroy(g); }
+  } gg{graph, gexec};
+  const bool use_graph = want_graph && ws != nullptr;
+  if (use_graph) {
+    HIP_TRY(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+    mem_status cs = enqueue_iteration(false);
+    hipGraph_t gcap = nullptr;
+    hipError_t ce = hipStreamEndCapture(ws, &gcap);
+    graph = gcap;
+    if (cs != MEM_OK) return cs;
+    if (ce != hipSuccess) return fail(MEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+  auto wall0 = std::chrono::steady_clock::now();
+  for (int j = 0; j < iters; ++j) {
+    if (use_graph) HIP_TRY(hipGraphLaunch(gexec, ws));
+    else {
+      mem_status es = enqueue_iteration(o.timing_out != nullptr);
+      if (es != MEM_OK) return es;
+    }
+    if (target_mode || j == 0) {
+      Control hc{};
+      HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, ws));
+      HIP_TRY(hipStreamSynchronize(ws));
+      if (hc.n_running == 0) break;
+    }
+  }
+  double* P = out_dev ? p_out : b_P.as<double>();
+  double* E = out_dev ? err_out : b_err.as<double>();
+  int32_t* S = out_dev ? status_out : b_status.as<int32_t>();
+  hipLaunchKernelGGL(flow_event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
+                     b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
+                     target_mode ? o.target_rel_err : 0.0, &ctl->iter, &ctl->n_running, 1, P, E, S, o.n_iter_out,
+                     b_done.as<int32_t>());
+  HIP_TRY(hipGetLastError());
+  double n_evals = 0.0;
+  {
+    std::vector<double> hs((size_t)n_int * FS_SIZE);
+    HIP_TRY(hipMemcpyAsync(hs.data(), b_state.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, ws));
+    HIP_TRY(hipStreamSynchronize(ws));
+    for (int i = 0; i < n_int; ++i) n_evals += hs[(size_t)i * FS_SIZE + FS_N];
+  }
+  // events below the ESS threshold: VEGAS on a compact copy
+  std::vector<int32_t> done(n_ev);
+  HIP_TRY(hipMemcpyAsync(done.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost, ws));
+  HIP_TRY(hipStreamSynchronize(ws));
+  std::vector<int32_t> fb;
+  for (int e = 0; e < n_ev; ++e) if (done[e] < 0) fb.push_back(e);
+  double fb_timing[6] = {0, 0, 0, 0, 0, 0};
+  if (!fb.empty()) {
+    // VEGAS on the same event set with every other event masked, so that a
+    // fallback event sees the point stream of a plain VEGAS call
+    const int nf = (int)fb.size();
+    std::vector<int32_t> mask(n_ev, 0);
+    for (int e : fb) mask[e] = 1;
+    DevBuf b_idx, b_fP, b_fE, b_fS, b_fN;
+    HIP_TRY(b_idx.alloc(nf * sizeof(int32_t)));
+    HIP_TRY(b_fP.alloc(n_ev * sizeof(double)));
+    HIP_TRY(b_fE.alloc(n_ev * sizeof(double)));
+    HIP_TRY(b_fS.alloc(n_ev * sizeof(int32_t)));
+    HIP_TRY(b_fN.alloc(n_ev * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(b_idx.p, fb.data(), nf * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+    mem_integrate_opts o2 = o;
+    o2.flow = nullptr;
+    o2.stream = ws;
+    o2.outputs_on_device = 1;
+    o2.iter_out = nullptr;
+    o2.grid_out = nullptr;
+    o2.n_iter_out = b_fN.as<int32_t>();
+    o2.timing_out = o.timing_out ? fb_timing : nullptr;
+    st = integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o2, b_fP.as<double>(), b_fE.as<double>(),
+                         b_fS.as<int32_t>(), mask.data());
+    if (st != MEM_OK) return st;
+    hipLaunchKernelGGL(scatter_fallback_kernel, dim3((nf + 255) / 256), dim3(256), 0, ws, b_idx.as<int32_t>(), nf,
+                       b_fP.as<double>(), b_fE.as<double>(), b_fS.as<int32_t>(), b_fN.as<int32_t>(), P, E, S,
+                       o.n_iter_out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(ws));
+  }
+  if (!out_dev) {
+    HIP_TRY(hipMemcpyAsync(p_out, P, n_ev * sizeof(double), hipMemcpyDeviceToHost, ws));
+    HIP_TRY(hipMemcpyAsync(err_out, E, n_ev * sizeof(double), hipMemcpyDeviceToHost, ws));
+    HIP_TRY(hipMemcpyAsync(status_out, S, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost, ws));
+  }
+  HIP_TRY(hipStreamSynchronize(ws));
+  if (o.timing_out) {
+    double ms_w = 0.0, ms_s = 0.0;
+    for (size_t i = 0; i + 1 < tev_w.size(); i += 2) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, tev_w[i], tev_w[i + 1]));
+      ms_w += t;
+    }
+    for (size_t i = 0; i + 1 < tev_s.size(); i += 2) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, tev_s[i], tev_s[i + 1]));
+      ms_s += t;
+    }
+    o.timing_out[0] = ms_w + fb_timing[0];
+    o.timing_out[1] = (double)(tev_w.size() / 2) + fb_timing[1];
+    o.timing_out[2] = n_evals + fb_timing[2];
+    o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+    o.timing_out[4] = ms_s;
+    o.timing_out[5] = (double)(tev_s.size() / 2);
+  }
   return MEM_OK;
 }
 

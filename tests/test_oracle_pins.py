@@ -75,6 +75,19 @@ def test_uniforms_word_layout():
             assert u[2 * b + 1] == lo * 2.0**-53
 
 
+def test_uniforms_block_offset():
+    """the counter-block offset addresses the same stream: blocks 16.. of
+    permutation p are blocks 0.. of permutation p + 1, and blocks 8.. are
+    disjoint from both"""
+    seed = 0x1407759577
+    for k, it, ev, perm in ((0, 0, 0, 0), (123, 4, 9, 3), (2**31, 7, 2**20, 5)):
+        a = oracle.uniforms(seed, k, it, ev, perm, 8, block0=16)
+        b = oracle.uniforms(seed, k, it, ev, perm + 1, 8)
+        assert np.array_equal(a, b)
+        z = oracle.uniforms(seed, k, it, ev, perm, 8, block0=8)
+        assert not np.any(np.isin(z, oracle.uniforms(seed, k, it, ev, perm, 8)))
+
+
 # --------------------------------------------------------------- VEGAS ----
 def test_uniform_grid_map_is_identity():
     g = oracle.uniform_grid(3)
@@ -535,6 +548,27 @@ def test_semilep_integrand_positive_at_truth():
 
 
 # ------------------------------------------------------------ flow -----
+def test_flow_context_permutation_and_balance():
+    """perm = 1 swaps the two jet slots and leaves the rest; the sum slot
+    holds the four objects' sum; MET balances the visible transverse
+    momentum"""
+    from synth import events
+    d = events.ttbar_dilepton(6, 41)
+    for e in range(6):
+        ev = d["obs"][e]
+        c0, c1 = oracle.flow_context(ev, 0), oracle.flow_context(ev, 1)
+        assert np.array_equal(c0[0:4], c1[4:8]) and np.array_equal(c0[4:8], c1[0:4])
+        assert np.array_equal(c0[8:], c1[8:])
+        S = ev[:4].sum(axis=0)
+        assert c0[16] == pytest.approx(np.log(S[0] / 100.0), rel=1e-14)
+        assert np.allclose(c0[17:20] * 100.0, S[1:], rtol=1e-13)
+        assert np.allclose(c0[21:23] * 100.0, -S[1:3], rtol=1e-13)
+        met = np.hypot(S[1], S[2])
+        assert c0[20] == pytest.approx(np.log((met + 1.0) / 100.0), rel=1e-13)
+        for k in range(4):
+            assert np.exp(c0[4 * k]) * 100.0 == pytest.approx(ev[k, 0], rel=1e-13)
+
+
 def test_flow_identity_at_init():
     """zero last layer: the flow is the identity up to the fixed reversal
     of the coordinate order, with log q = 0"""
