@@ -74,6 +74,109 @@ def cpu_baseline(obs, n_iters_gpu, budget_s):
             "evals_per_s": evals / dt, "seconds": dt}
 
 
+# Learned proposal (the flow leg): trained on VEGAS samples of fresh events,
+# then used on the benchmark events to the same accuracy.
+FLOW_TRAIN_EVENTS = 50000
+FLOW_TRAIN_PTS = 8192          # VEGAS points per training event per iteration
+FLOW_TRAIN_ITERS = 4
+FLOW_CAPTURE = 168             # samples per training integral: 100 000 x 168 ~ 2^24
+FLOW_BATCH = 65536             # training minibatch
+FLOW_EPOCHS = 8
+FLOW_LR = (2e-3, 1e-4)         # cosine decay between these
+FLOW_PTS = 16384               # flow points per event per batch
+SEED_TRAIN = 0x14077595 + 4
+PEAK_BF16 = 2.5e15             # MI355X dense BF16 matrix peak, FLOP/s
+
+
+def flow_leg(mem, proc, comps, n_ev, args):
+    """train the flow on VEGAS samples of fresh events, then integrate the
+    benchmark events to 1 % with it (VEGAS fallback below ESS/N = 0.3)"""
+    import math
+    import numpy as np
+    import torch
+    from synth import events
+    n_tr = args.flow_train_events
+    d = events.ttbar_dilepton(n_tr, SEED_TRAIN)
+    ctr = mem.to_components(d["obs"]).cuda()
+    n_int = 2 * n_tr
+    t0 = time.perf_counter()
+    grids = torch.empty((n_int, 8, 65), dtype=torch.float64, device="cuda")
+    mem.integrate_events(ctr, proc, FLOW_TRAIN_PTS, FLOW_TRAIN_ITERS, seed=SEED_TRAIN, grid_out=grids)
+    ev_idx = torch.arange(n_tr, dtype=torch.int32, device="cuda").repeat_interleave(2)
+    pm_idx = torch.tensor([0, 1], dtype=torch.int32, device="cuda").repeat(n_tr)
+    x = torch.empty((n_int, FLOW_CAPTURE, 8), dtype=torch.float32, device="cuda")
+    w = torch.empty((n_int, FLOW_CAPTURE), dtype=torch.float32, device="cuda")
+    mem.vegas_capture(proc, ctr, ev_idx, pm_idx, grids, FLOW_CAPTURE, SEED_TRAIN, 99, x, w, normalise=1)
+    ctx = torch.empty((n_int, 24), dtype=torch.float32, device="cuda")
+    mem.flow_context(ctr, ev_idx, pm_idx, ctx)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    del grids
+    xs, ws = x.reshape(-1, 8), w.reshape(-1)
+    sint = torch.arange(n_int, dtype=torch.int32, device="cuda").repeat_interleave(FLOW_CAPTURE)
+    n_s = xs.shape[0]
+    n_b = n_s // FLOW_BATCH
+    f = mem.Flow(mem.MEM_FLOW_BF16)
+    rng = np.random.default_rng(7)
+    total = FLOW_EPOCHS * n_b
+    log(f"flow: {n_s} training samples from {n_tr} events ({data_s:.1f} s); {FLOW_EPOCHS} epochs x {n_b} steps")
+    t0 = time.perf_counter()
+    k = 0
+    losses = []
+    for ep in range(FLOW_EPOCHS):
+        for b in rng.permutation(n_b):
+            lr = FLOW_LR[1] + 0.5 * (FLOW_LR[0] - FLOW_LR[1]) * (1 + math.cos(math.pi * k / total))
+            sl = slice(int(b) * FLOW_BATCH, (int(b) + 1) * FLOW_BATCH)
+            want = (k % n_b == 0) or k == total - 1
+            L = f.train_step(ctx, sint[sl], xs[sl], ws[sl], lr=lr, want_loss=want)
+            if want:
+                losses.append(L / (FLOW_BATCH / FLOW_CAPTURE))
+                log(f"  epoch {ep} step {k}: loss per integral {losses[-1]:.4f}")
+            k += 1
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del x, w, xs, ws, sint, ctx, ctr
+    torch.cuda.empty_cache()
+    # the benchmark events to 1 % with the flow
+    P = torch.empty(n_ev, dtype=torch.float64, device="cuda")
+    E = torch.empty_like(P)
+    S = torch.empty(n_ev, dtype=torch.int32, device="cuda")
+    n_used = torch.zeros(n_ev, dtype=torch.int32, device="cuda")
+    timing = (ctypes.c_double * 8)()
+
+    def run(tm=None):
+        mem.integrate_events(comps, proc, FLOW_PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER,
+                             outputs=(P, E, S), n_iter_out=n_used, flow=f, ess_threshold=0.3, timing=tm)
+
+    run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    value = n_ev * len(times) / sum(times)
+    st = S.cpu().numpy()
+    run(timing)                           # per-kernel times (direct launches)
+    torch.cuda.synchronize()
+    samp_ms, samp_n = timing[4], timing[5]
+    flow_pts = timing[6]
+    mfma = flow_pts * 6 * 2 * 128 * (128 + 96) / (samp_ms * 1e-3) if samp_ms > 0 else None
+    out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times),
+           "points_per_event_per_batch": FLOW_PTS, "fallback_fraction": float(np.mean(st == 4)),
+           "converged_fraction": float(np.mean((st == 0) | (st == 4))),
+           "median_batches": float(np.median(n_used.cpu().numpy())),
+           "train": {"events": n_tr, "samples": n_s, "epochs": FLOW_EPOCHS, "seconds": train_s,
+                     "data_seconds": data_s, "loss_first": losses[0], "loss_last": losses[-1]},
+           "sample_kernel": {"ms": samp_ms, "launches": samp_n, "points": flow_pts,
+                             "mfma_tflops": mfma / 1e12 if mfma else None,
+                             "mfma_frac": mfma / PEAK_BF16 if mfma else None},
+           "integrand_kernel_ms": timing[0], "fallback_evaluations": timing[7]}
+    log(f"flow: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +185,8 @@ def main():
     ap.add_argument("--events", type=int, default=N_EVENTS)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--flow-train-events", type=int, default=FLOW_TRAIN_EVENTS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -114,7 +219,7 @@ def main():
 
     # fixed budget: integrand evaluation rate and kernel timing
     log(f"fixed-budget pass: {n_ev} events x {PTS} points x {FIXED_ITERS} iterations")
-    timing = (ctypes.c_double * 6)()
+    timing = (ctypes.c_double * 8)()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mem.integrate_events(comps, proc, PTS, FIXED_ITERS, outputs=(P, E, S), timing=timing)
@@ -154,6 +259,11 @@ def main():
         achieved = per_launch / (kern_ms / launches * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": None}
+    flow = None
+    if not args.no_flow:
+        flow = flow_leg(mem, proc, comps, n_ev, args)
+        if value:
+            flow["vs_vegas"] = flow["events_per_s"] / value
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
@@ -171,7 +281,7 @@ def main():
         "fixed_budget": {"iterations": FIXED_ITERS, "seconds": fixed_s, "kernel_ms": kern_ms,
                          "median_rel_err": float(np.median(fixed_rel))},
         "converged_fraction": conv, "median_iterations": float(np.median(nu)) if args.steps else None,
-        "flow_vs_vegas": None,
+        "flow_vs_vegas": flow,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

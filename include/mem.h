@@ -128,13 +128,14 @@ typedef struct mem_flow_s* mem_flow;
  *  grid_out        optional device pointer, [n_integrals][D][65]: the VEGAS
  *                  grids after the last refinement
  *  n_iter_out      optional device pointer [n_events]: iterations used
- *  timing_out      optional HOST pointer, 6 doubles: milliseconds spent in
+ *  timing_out      optional HOST pointer, 8 doubles: milliseconds spent in
  *                  the integrand kernel (HIP events around every launch on
  *                  `stream`), its number of launches, the number of
  *                  integrand evaluations it performed, the wall time of
- *                  the call in milliseconds, milliseconds spent in the
- *                  flow's sampling kernel and its number of launches (0
- *                  without a flow)
+ *                  the call in milliseconds, then for a flow: milliseconds
+ *                  spent in its sampling kernel, its launches, the points
+ *                  it sampled, and the integrand evaluations of the VEGAS
+ *                  fallback (all 0 without a flow)
  *  chunk_points    points per work-queue chunk (0: the process's tuned or
  *                  default value, 4096); a multiple of 256 up to 65536
  *  use_graph       0: launch every iteration; 1 (default when the options

@@ -177,7 +177,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
-    int or a list per event; timing: optional ctypes (c_double * 6) array;
+    int or a list per event; timing: optional ctypes (c_double * 8) array;
     flow: optional Flow (importance sampling from it, VEGAS fallback).
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""

@@ -166,69 +166,6 @@ __device__ __forceinline__ void layer_mlp_mfma(const float* __restrict__ L, cons
   __syncthreads();
 }
 
-// ---------------------------------------------------------- sampling --
-// x = T^-1(z) with z from the point stream (counter block perm*16 + 8 + b),
-// log q(x|c).  Outputs x as float[8] and log q per point.  The iteration
-// index comes from iter_p when given (graph replays), else from iter.
-template <bool X2>
-__global__ __launch_bounds__(FT) void flow_sample_kernel(const float* __restrict__ P, const uint16_t* __restrict__ Wb,
-                                                         const float* __restrict__ cvec,
-                                                         const FlowChunk* __restrict__ chunks, uint64_t seed,
-                                                         uint32_t iter, const uint32_t* __restrict__ iter_p,
-                                                         const int32_t* __restrict__ active,
-                                                         float* __restrict__ xout, float* __restrict__ lqout)
-{
-  __shared__ FlowSmem<X2> S;
-  const FlowChunk ch = chunks[blockIdx.x];
-  if (active && !active[ch.integral]) return;
-  if (iter_p) iter = *iter_p;
-  const int t = threadIdx.x;
-  if (t < FP) {
-    double u[8];
-    point_uniforms<8>(seed, (uint32_t)(ch.start + t), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u, 8u);
-#pragma unroll
-    for (int d = 0; d < 8; ++d) S.v[t][d] = fminf((float)u[d], 0.99999994f);
-    S.logq[t] = 0.0f;
-  }
-  for (int l = FLAYERS - 1; l >= 0; --l) {
-    int A[4], B[4];
-    flow_masks(l, A, B);
-    const float* L = P + (int64_t)l * FPER;
-    if (t < FH) S.cv[t] = cvec[((int64_t)ch.integral * FLAYERS + l) * FH + t];
-    __syncthreads();
-    layer_h1(L, B, S, nullptr, nullptr, 0);
-    __syncthreads();
-    layer_mlp_mfma(L, Wb + (int64_t)l * FB_PER, S, nullptr, 0);
-    // spline inverse: two threads per point, two positions each
-    {
-      const int p = t >> 1, j0 = 2 * (t & 1);
-      float lsum = 0.0f;
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        Spline sp;
-        spline_make(&S.th[p * FOUTP + 23 * (j0 + jj)], sp);
-        float ld;
-        const int a = A[j0 + jj];
-        S.v[p][a] = spline_inv(sp, S.v[p][a], ld);
-        lsum += ld;
-      }
-      lsum += __shfl_xor(lsum, 1, kWave);
-      if ((t & 1) == 0) S.logq[p] += lsum;
-    }
-    __syncthreads();
-    if (l == 3 && t < FP) {
-#pragma unroll
-      for (int d = 0; d < 4; ++d) { float x = S.v[t][d]; S.v[t][d] = S.v[t][7 - d]; S.v[t][7 - d] = x; }
-    }
-    __syncthreads();
-  }
-  if (t < ch.count) {
-#pragma unroll
-    for (int d = 0; d < 8; ++d) xout[(ch.out + t) * 8 + d] = S.v[t][d];
-    lqout[ch.out + t] = S.logq[t];
-  }
-}
-
 // w = f(x) / q(x|c) for flow points of the ttbar dilepton process; per
 // chunk (up to FW points of one integral) sum w and sum w^2.  A point at
 // x_d = 1 (the spline's upper edge in FP32) is moved just inside the cube.
@@ -455,12 +392,12 @@ __global__ void scatter_fallback_kernel(const int32_t* __restrict__ idx, int n, 
 constexpr int FTAPE = 8 + FH + FH + FOUTP;
 
 // Forward T(x) for training samples (any integrals), writing the tape and
-// log q.
+// log q.  cvec holds the context projections of contexts ctx0, ctx0 + 1, ..
 template <bool X2>
 __global__ __launch_bounds__(FT) void flow_train_fwd_kernel(const float* __restrict__ P,
                                                             const uint16_t* __restrict__ Wb,
                                                             const float* __restrict__ cvec,
-                                                            const int32_t* __restrict__ sint,
+                                                            const int32_t* __restrict__ sint, int32_t ctx0,
                                                             const float* __restrict__ xs, int n,
                                                             float* __restrict__ tape, float* __restrict__ lq)
 {
@@ -472,7 +409,7 @@ __global__ __launch_bounds__(FT) void flow_train_fwd_kernel(const float* __restr
 #pragma unroll
     for (int d = 0; d < 8; ++d) S.v[t][d] = i < n ? xs[i * 8 + d] : 0.5f;
     S.logq[t] = 0.0f;
-    S.sint[t] = i < n ? sint[i] : sint[0];
+    S.sint[t] = (i < n ? sint[i] : sint[0]) - ctx0;
   }
   __syncthreads();
   for (int l = 0; l < FLAYERS; ++l) {

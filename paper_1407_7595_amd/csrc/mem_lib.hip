@@ -17,6 +17,7 @@
 
 #include "../../include/mem.h"
 #include "flow_kernels.hpp"
+#include "flow_sample.hpp"
 #include "kernels.hpp"
 
 using namespace memk;
@@ -800,8 +801,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     o.timing_out[1] = (double)(tev.size() / 2);
     o.timing_out[2] = n_evals * used_iters;
     o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
-    o.timing_out[4] = 0.0;
-    o.timing_out[5] = 0.0;
+    for (int i = 4; i < 8; ++i) o.timing_out[i] = 0.0;
   }
   return MEM_OK;
 }
@@ -935,6 +935,7 @@ struct mem_flow_s {
   float* m = nullptr;       // Adam moments
   float* v = nullptr;
   uint16_t* Wb = nullptr;   // BF16 operand copies of the 128-wide layers
+  uint16_t* Wf = nullptr;   // the same in matrix-core fragment order (sampling)
   float* tape = nullptr;    // training tape, tape_cap samples
   float* lq = nullptr;      // log q of the training samples
   int64_t tape_cap = 0;
@@ -943,7 +944,8 @@ struct mem_flow_s {
   int32_t mode = MEM_FLOW_BF16;
   ~mem_flow_s()
   {
-    for (void* q : {(void*)P, (void*)grad, (void*)m, (void*)v, (void*)Wb, (void*)tape, (void*)lq, (void*)loss_parts})
+    for (void* q : {(void*)P, (void*)grad, (void*)m, (void*)v, (void*)Wb, (void*)Wf, (void*)tape, (void*)lq,
+                    (void*)loss_parts})
       if (q) (void)hipFree(q);
   }
 };
@@ -966,6 +968,8 @@ mem_status flow_convert(mem_flow f, hipStream_t s)
 {
   const int64_t n = (int64_t)FLAYERS * FB_PER;
   hipLaunchKernelGGL(flow_convert_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f->P, f->Wb);
+  const int64_t nf = (int64_t)FLAYERS * FS_PER;
+  hipLaunchKernelGGL(flow_swizzle_kernel, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, f->P, f->Wf);
   HIP_TRY(hipGetLastError());
   return MEM_OK;
 }
@@ -992,18 +996,21 @@ mem_status flow_cvec(mem_flow f, const float* ctx, int n, float* cvec, hipStream
   return MEM_OK;
 }
 
-// sint must index rows [0, n_ctx) of the context table
-mem_status check_sint(const int32_t* sint, int64_t n, hipStream_t s, int32_t* max_out)
+// range [min, max] of the context rows a sample set uses (read back and
+// checked on the host: the kernels index the context table with them)
+mem_status sint_range(const int32_t* sint, int64_t n, hipStream_t s, int32_t* lo, int32_t* hi)
 {
   std::vector<int32_t> h(n);
   HIP_TRY(hipMemcpyAsync(h.data(), sint, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  int32_t mx = 0;
+  int32_t mn = h[0], mx = h[0];
   for (int64_t i = 0; i < n; ++i) {
     if (h[i] < 0) return fail(MEM_EINVAL, "negative context index");
+    mn = std::min(mn, h[i]);
     mx = std::max(mx, h[i]);
   }
-  *max_out = mx;
+  *lo = mn;
+  *hi = mx;
   return MEM_OK;
 }
 }  // namespace
@@ -1022,6 +1029,7 @@ extern "C" mem_status mem_flow_create(int32_t mode, mem_flow* out)
     if (hipMemset(*q, 0, (size_t)FNP * sizeof(float)) != hipSuccess) return bad(fail(MEM_EDEVICE, "hipMemset"));
   }
   if (hipMalloc(&f->Wb, (size_t)FLAYERS * FB_PER * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc(&f->Wf, (size_t)FLAYERS * FS_PER * sizeof(uint16_t)) != hipSuccess ||
       hipMalloc(&f->loss_parts, kLossBlocks * sizeof(double)) != hipSuccess)
     return bad(fail(MEM_ENOMEM, "flow buffers"));
   mem_status st = flow_convert(f, nullptr);
@@ -1115,8 +1123,8 @@ extern "C" mem_status mem_flow_sample(mem_flow f, const float* ctx, const int32_
   HIP_TRY(hipMemcpyAsync(b_ch.p, ch.data(), ch.size() * sizeof(FlowChunk), hipMemcpyHostToDevice, s));
   mem_status st = flow_cvec(f, ctx, n_int, b_cvec.as<float>(), s);
   if (st != MEM_OK) return st;
-  hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_sample_kernel<true> : flow_sample_kernel<false>,
-                     dim3((unsigned)ch.size()), dim3(FT), 0, s, f->P, f->Wb, b_cvec.as<float>(),
+  hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_sample2_kernel<true> : flow_sample2_kernel<false>,
+                     dim3((unsigned)ch.size()), dim3(FT), 0, s, f->P, f->Wf, b_cvec.as<float>(),
                      b_ch.as<FlowChunk>(), seed, iter, (const uint32_t*)nullptr, (const int32_t*)nullptr, x_out,
                      logq_out);
   HIP_TRY(hipGetLastError());
@@ -1131,19 +1139,19 @@ extern "C" mem_status mem_flow_log_prob(mem_flow f, const float* ctx, const int3
   if (n < 0 || n > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "bad size");
   if (n == 0) return MEM_OK;
   hipStream_t s = (hipStream_t)stream;
-  int32_t n_ctx = 0;
-  mem_status st = check_sint(sint, n, s, &n_ctx);
+  int32_t c_lo = 0, c_hi = 0;
+  mem_status st = sint_range(sint, n, s, &c_lo, &c_hi);
   if (st != MEM_OK) return st;
-  n_ctx += 1;
+  const int n_ctx = c_hi - c_lo + 1;
   st = flow_tape(f, n);
   if (st != MEM_OK) return st;
   DevBuf b_cvec;
   HIP_TRY(b_cvec.alloc((size_t)n_ctx * FLAYERS * FH * sizeof(float)));
-  st = flow_cvec(f, ctx, n_ctx, b_cvec.as<float>(), s);
+  st = flow_cvec(f, ctx + (int64_t)c_lo * FCTX, n_ctx, b_cvec.as<float>(), s);
   if (st != MEM_OK) return st;
   hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_train_fwd_kernel<true> : flow_train_fwd_kernel<false>,
                      dim3((unsigned)((n + FP - 1) / FP)), dim3(FT), 0, s, f->P, f->Wb,
-                     b_cvec.as<float>(), sint, x, (int)n, f->tape, logq_out);
+                     b_cvec.as<float>(), sint, c_lo, x, (int)n, f->tape, logq_out);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   return MEM_OK;
@@ -1157,20 +1165,21 @@ extern "C" mem_status mem_flow_train_step(mem_flow f, const float* ctx, const in
   if (n < 1 || n > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "bad size");
   if (!(lr >= 0.0)) return fail(MEM_EINVAL, "lr must be >= 0");
   hipStream_t s = (hipStream_t)stream;
-  int32_t n_ctx = 0;
-  mem_status st = check_sint(sint, n, s, &n_ctx);
+  int32_t c_lo = 0, c_hi = 0;
+  mem_status st = sint_range(sint, n, s, &c_lo, &c_hi);
   if (st != MEM_OK) return st;
-  n_ctx += 1;
+  const int n_ctx = c_hi - c_lo + 1;
   st = flow_tape(f, n);
   if (st != MEM_OK) return st;
   DevBuf b_cvec;
   HIP_TRY(b_cvec.alloc((size_t)n_ctx * FLAYERS * FH * sizeof(float)));
-  st = flow_cvec(f, ctx, n_ctx, b_cvec.as<float>(), s);
+  st = flow_cvec(f, ctx + (int64_t)c_lo * FCTX, n_ctx, b_cvec.as<float>(), s);
   if (st != MEM_OK) return st;
   fill_f32(f->grad, FNP, 0.0f, s);
   const unsigned nb = (unsigned)((n + FP - 1) / FP);
   hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_train_fwd_kernel<true> : flow_train_fwd_kernel<false>,
-                     dim3(nb), dim3(FT), 0, s, f->P, f->Wb, b_cvec.as<float>(), sint, x, (int)n, f->tape, f->lq);
+                     dim3(nb), dim3(FT), 0, s, f->P, f->Wb, b_cvec.as<float>(), sint, c_lo, x, (int)n, f->tape,
+                     f->lq);
   hipLaunchKernelGGL(flow_train_bwd_kernel, dim3(nb), dim3(FT), 0, s, f->P, f->Wb, ctx, sint, wt, (int)n, f->tape,
                      f->grad);
   HIP_TRY(hipGetLastError());
@@ -1347,8 +1356,8 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
   auto enqueue_iteration = [&](bool time_kernels) -> mem_status {
     hipLaunchKernelGGL(flow_iter_begin_kernel, dim3(1), dim3(64), 0, ws, &ctl->n_running);
     mem_status es = timed(&tev_s, time_kernels, [&] {
-      hipLaunchKernelGGL(fl->mode == MEM_FLOW_BF16X2 ? flow_sample_kernel<true> : flow_sample_kernel<false>,
-                         dim3((unsigned)sch.size()), dim3(FT), 0, ws, fl->P, fl->Wb,
+      hipLaunchKernelGGL(fl->mode == MEM_FLOW_BF16X2 ? flow_sample2_kernel<true> : flow_sample2_kernel<false>,
+                         dim3((unsigned)sch.size()), dim3(FT), 0, ws, fl->P, fl->Wf,
                          b_cvec.as<float>(), b_sch.as<FlowChunk>(), o.seed, 0u, &ctl->iter, b_active.as<int32_t>(),
                          b_x.as<float>(), b_lq.as<float>());
     });
@@ -1427,7 +1436,7 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
   HIP_TRY(hipStreamSynchronize(ws));
   std::vector<int32_t> fb;
   for (int e = 0; e < n_ev; ++e) if (done[e] < 0) fb.push_back(e);
-  double fb_timing[6] = {0, 0, 0, 0, 0, 0};
+  double fb_timing[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (!fb.empty()) {
     // VEGAS on the same event set with every other event masked, so that a
     // fallback event sees the point stream of a plain VEGAS call
@@ -1482,6 +1491,8 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
     o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     o.timing_out[4] = ms_s;
     o.timing_out[5] = (double)(tev_s.size() / 2);
+    o.timing_out[6] = n_evals;
+    o.timing_out[7] = fb_timing[2];
   }
   return MEM_OK;
 }

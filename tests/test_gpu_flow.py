@@ -187,7 +187,8 @@ def test_flow_sample_matches_oracle(mem, mode, scale, bias, mdx, xdx, mdl, xdl):
     dself = np.abs(lq2.cpu().numpy() - lq.reshape(-1))
     say(f"{mode}: forward log q at the samples vs their sampling log q: median {np.median(dself):.2e} "
         f"max {dself.max():.2e}")
-    assert within(dself, mdl, xdl)
+    # two GPU passes (inverse, then forward), each within the oracle bar
+    assert within(dself, 2 * mdl, 2 * xdl)
 
 
 @pytest.mark.parametrize("mode,scale,bias,mdx,xdx,mdl,xdl", SAMPLE_CASES)
