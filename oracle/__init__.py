@@ -21,6 +21,7 @@ KIND_DY = 1
 KIND_TT = 2
 KIND_GENZ = 3
 KIND_TT_SL = 4
+KIND_TTH = 5
 NBINS = 64
 
 
@@ -28,7 +29,7 @@ class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sqrt_s", "m_t", "w_t", "m_w", "w_w", "alpha", "alpha_s", "g_fermi",
         "sigma_k", "tf_sigma", "r_lo", "r_hi", "m_lo", "m_hi",
-        "lj_core", "lj_tail", "lj_ftail", "lj_r_lo", "lj_r_hi")]
+        "lj_core", "lj_tail", "lj_ftail", "lj_r_lo", "lj_r_hi", "m_h", "w_h", "m_b")]
 
 
 class Result(ctypes.Structure):
@@ -42,7 +43,8 @@ def dy_params(**kw):
     p = dict(sqrt_s=13000.0, m_t=172.5, w_t=1.4, m_w=80.4, w_w=2.1,
              alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
              sigma_k=20.0, tf_sigma=0.05, r_lo=0.75, r_hi=1.25,
-             m_lo=60.0, m_hi=120.0, lj_core=0.10, lj_tail=0.25, lj_ftail=0.2, lj_r_lo=0.1, lj_r_hi=2.25)
+             m_lo=60.0, m_hi=120.0, lj_core=0.10, lj_tail=0.25, lj_ftail=0.2, lj_r_lo=0.1, lj_r_hi=2.25,
+             m_h=125.0, w_h=0.00407, m_b=4.18)
     p.update(kw)
     return Params(**p)
 
@@ -53,7 +55,8 @@ def tt_params(**kw):
     p = dict(sqrt_s=13000.0, m_t=172.5, w_t=1.4, m_w=80.4, w_w=2.1,
              alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
              sigma_k=20.0, tf_sigma=0.15, r_lo=0.25, r_hi=1.75,
-             m_lo=0.0, m_hi=0.0, lj_core=0.10, lj_tail=0.25, lj_ftail=0.2, lj_r_lo=0.1, lj_r_hi=2.25)
+             m_lo=0.0, m_hi=0.0, lj_core=0.10, lj_tail=0.25, lj_ftail=0.2, lj_r_lo=0.1, lj_r_hi=2.25,
+             m_h=125.0, w_h=0.00407, m_b=4.18)
     p.update(kw)
     return Params(**p)
 
@@ -114,6 +117,13 @@ def _declare(L):
         "or_semilep_nu_z": (I, [P, D, D, D, P]),
         "or_dgauss_tf": (D, [D, D, D, D, D]),
         "or_flow_nparams": (I, []),
+        "or_gg_tth_prod": (D, [D, P, P, P, P, P]),
+        "or_gg_tth_ward": (D, [D, P, P, P, P, P]),
+        "or_tth_soft_check": (D, [D, P, D]),
+        "or_tth_me2_gg": (D, [P, P, P, P, P, P]),
+        "or_tth_perm": (None, [I, P, P, P, P, P]),
+        "or_tth_map": (D, [P, P, I, P, P]),
+        "or_tth_integrand": (D, [P, P, I, I, P, P]),
         "or_flow_forward": (D, [P, P, P, P]),
         "or_flow_inverse": (D, [P, P, P, P]),
         "or_flow_context": (None, [P, I, P]),
@@ -338,3 +348,39 @@ def flow_nll_grad(params, x, ctx, wt):
     g = np.zeros(len(params))
     loss = lib().or_flow_nll_grad(_ptr(params), len(wt), _ptr(x), _ptr(ctx), _ptr(wt), _ptr(g))
     return loss, g
+
+
+# ------------------------------------------------------------ ttbar H ----
+def gg_tth_prod(mt, k1, k2, pt, ptb, ph):
+    a = [_f64(v) for v in (k1, k2, pt, ptb, ph)]
+    return lib().or_gg_tth_prod(mt, *[_ptr(v) for v in a])
+
+
+def gg_tth_ward(mt, k1, k2, pt, ptb, ph):
+    a = [_f64(v) for v in (k1, k2, pt, ptb, ph)]
+    return lib().or_gg_tth_ward(mt, *[_ptr(v) for v in a])
+
+
+def tth_soft_check(mt, mom, delta):
+    m = _f64(mom).reshape(-1)
+    return lib().or_tth_soft_check(mt, _ptr(m), delta)
+
+
+def tth_perm(perm):
+    v = [ctypes.c_int(0) for _ in range(5)]
+    lib().or_tth_perm(perm, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)     # i_h1, i_h2, i_bl, i_bh, o
+
+
+def tth_map(p, ev, perm, x):
+    ev, x = _f64(ev), _f64(x)
+    E6 = np.zeros(6)
+    jac = lib().or_tth_map(ctypes.byref(p), _ptr(ev), perm, _ptr(x), _ptr(E6))
+    return jac, E6
+
+
+def tth_integrand(p, ev, perm, x, charge=0):
+    ev, x = _f64(ev), _f64(x)
+    ns = ctypes.c_int(0)
+    v = lib().or_tth_integrand(ctypes.byref(p), _ptr(ev), charge, perm, _ptr(x), ctypes.byref(ns))
+    return v, ns.value

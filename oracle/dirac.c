@@ -422,3 +422,224 @@ double or_tt_me2_qq(const or_params* p, const double* kq, const double* kqb, con
     }
   return sum * decay_couplings(p, mom, pt, ptb) / 36.0;
 }
+
+/* ---------------------------------------------------------- ttbar H --- */
+/* g(k1) g(k2) -> t tbar H: the Higgs (unit Yukawa vertex, the coupling
+ * m_t/v is applied by the caller) is inserted at every position of the top
+ * line of each gg -> t tbar diagram.  Between the top row R and the
+ * antitop column C, for the colour ordering T^a T^b (gluon 1 next to the
+ * top):
+ *   H S(pt+pH) e1 S(pt+pH-k1) e2  +  e1 S(pt-k1) H S(pt-k1+pH) e2
+ *   + e1 S(pt-k1) e2 S(-ptb-pH) H
+ * and the s-channel current V (as in gg -> t tbar) with the Higgs on either
+ * side of it, entering the two orderings with opposite signs;
+ * S(q) = (qslash + m)/(q^2 - m^2). */
+static mat4 prop_m(const double* q, double mt)
+{
+  return mscale(madd(slash_r(q), ID4, mt), 1.0 / (mdot(q, q) - mt * mt));
+}
+
+static void build_ggh(double mt, const double* k1, const double* k2, const double* pt, const double* ptb,
+                      const double* ph, const double* e1, const double* e2, mat4* m12, mat4* m21)
+{
+  double qa[4], qb1[4], qb2[4], qc[4], ra1[4], rb1[4], rb2[4], K[4];
+  for (int i = 0; i < 4; ++i) {
+    qa[i] = pt[i] + ph[i];                  /* after H next to the top */
+    qc[i] = -ptb[i] - ph[i];                /* before H next to the antitop */
+    qb1[i] = pt[i] - k1[i];                 /* ordering 12 */
+    qb2[i] = pt[i] + ph[i] - k1[i];
+    rb1[i] = pt[i] - k2[i];                 /* ordering 21 */
+    rb2[i] = pt[i] + ph[i] - k2[i];
+    ra1[i] = pt[i] - k1[i] + ph[i];
+    K[i] = k1[i] + k2[i];
+  }
+  double rb2b[4];
+  for (int i = 0; i < 4; ++i) rb2b[i] = pt[i] - k2[i] + ph[i];
+  mat4 s1 = slash_r(e1), s2 = slash_r(e2);
+  mat4 Sa = prop_m(qa, mt), Sc = prop_m(qc, mt);
+  /* ordering 12 */
+  mat4 t12 = mmul(mmul(mmul(Sa, s1), prop_m(qb2, mt)), s2);
+  t12 = madd(t12, mmul(mmul(mmul(s1, prop_m(qb1, mt)), prop_m(ra1, mt)), s2), 1.0);
+  t12 = madd(t12, mmul(mmul(mmul(s1, prop_m(qb1, mt)), s2), Sc), 1.0);
+  /* ordering 21 */
+  mat4 t21 = mmul(mmul(mmul(Sa, s2), prop_m(rb2, mt)), s1);
+  t21 = madd(t21, mmul(mmul(mmul(s2, prop_m(rb1, mt)), prop_m(rb2b, mt)), s1), 1.0);
+  t21 = madd(t21, mmul(mmul(mmul(s2, prop_m(rb1, mt)), s1), Sc), 1.0);
+  /* s-channel */
+  double s = mdot(K, K);
+  double V[4];
+  double e1e2 = mdot(e1, e2), k2e1 = mdot(k2, e1), k1e2 = mdot(k1, e2);
+  for (int i = 0; i < 4; ++i) V[i] = e1e2 * (k1[i] - k2[i]) + 2.0 * k2e1 * e2[i] - 2.0 * k1e2 * e1[i];
+  mat4 sV = mscale(slash_r(V), 1.0 / s);
+  mat4 sch = madd(mmul(Sa, sV), mmul(sV, Sc), 1.0);
+  *m12 = madd(t12, sch, 1.0);
+  *m21 = madd(t21, sch, -1.0);
+}
+
+/* spin- and colour-summed |M|^2 of g g -> t tbar H for on-shell tops, with
+ * unit Yukawa coupling, averaged over the 256 initial colours and
+ * polarisations */
+double or_gg_tth_prod(double mt, const double* k1, const double* k2, const double* pt, const double* ptb,
+                      const double* ph)
+{
+  init_gamma();
+  double sum = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      double e1[4], e2[4];
+      lin_pol(a, e1);
+      lin_pol(b, e2);
+      mat4 m12, m21;
+      build_ggh(mt, k1, k2, pt, ptb, ph, e1, e2, &m12, &m21);
+      for (int st = 0; st < 2; ++st)
+        for (int sb = 0; sb < 2; ++sb) {
+          spin4 R = dbar(spinor_u(pt, mt, st));
+          spin4 C = spinor_v(ptb, mt, sb);
+          sum += colour_gg(rowcol(R, mvec(m12, C)), rowcol(R, mvec(m21, C)));
+        }
+    }
+  return sum / 256.0;
+}
+
+/* Ward identity: with e1 -> k1 every colour-ordered amplitude vanishes.
+ * Returns the largest |A| relative to the largest amplitude with physical
+ * polarisations. */
+double or_gg_tth_ward(double mt, const double* k1, const double* k2, const double* pt, const double* ptb,
+                      const double* ph)
+{
+  init_gamma();
+  double worst = 0.0, scale = 0.0;
+  for (int b = 0; b < 2; ++b) {
+    double e2[4], ex[4];
+    lin_pol(b, e2);
+    lin_pol(0, ex);
+    mat4 g12, g21, p12, p21;
+    build_ggh(mt, k1, k2, pt, ptb, ph, k1, e2, &g12, &g21);
+    build_ggh(mt, k1, k2, pt, ptb, ph, ex, e2, &p12, &p21);
+    for (int st = 0; st < 2; ++st)
+      for (int sb = 0; sb < 2; ++sb) {
+        spin4 R = dbar(spinor_u(pt, mt, st));
+        spin4 C = spinor_v(ptb, mt, sb);
+        worst = fmax(worst, fmax(cabs(rowcol(R, mvec(g12, C))), cabs(rowcol(R, mvec(g21, C)))));
+        scale = fmax(scale, fmax(cabs(rowcol(R, mvec(p12, C))), cabs(rowcol(R, mvec(p21, C)))));
+      }
+  }
+  return scale > 0.0 ? worst / scale : worst;
+}
+
+/* Decayed top line with zero-width propagators, for the soft-Higgs check:
+ * ubar(b) J+slash P_L S(pt) [production] S(-ptb) J-slash P_L v(bbar). */
+static void ord_amps_tt(double mt, const double* k1, const double* k2, const double* mom, int i_sp, int a, int b,
+                        cx* a12, cx* a21)
+{
+  const double *bq = mom, *lp = mom + 4, *nu = mom + 8;
+  const double *bb = mom + 12, *lm = mom + 16, *nub = mom + 20;
+  double pt[4], ptb[4], mptb[4];
+  for (int i = 0; i < 4; ++i) { pt[i] = bq[i] + lp[i] + nu[i]; ptb[i] = bb[i] + lm[i] + nub[i]; mptb[i] = -ptb[i]; }
+  mat4 PL = proj_left();
+  int sb = (i_sp >> 2) & 1, sn = (i_sp >> 1) & 1, sl = i_sp & 1;
+  cx J[4], Jm[4];
+  current_L(dbar(spinor_u(nu, 0.0, sn)), spinor_v(lp, 0.0, sl), J);
+  current_L(dbar(spinor_u(lm, 0.0, sl)), spinor_v(nub, 0.0, sn), Jm);
+  spin4 R = rowmat(rowmat(dbar(spinor_u(bq, 0.0, sb)), mmul(slash(J), PL)), prop_m(pt, mt));
+  spin4 C = mvec(prop_m(mptb, mt), mvec(mmul(slash(Jm), PL), spinor_v(bb, 0.0, sb)));
+  gg_vertices gv;
+  build_gg(mt, k1, k2, pt, NULL, NULL, 0, &gv);
+  *a12 = rowcol(R, mvec(gv.g12[a][b], C));
+  *a21 = rowcol(R, mvec(gv.g21[a][b], C));
+}
+
+static void ord_amps_tth(double mt, const double* k1, const double* k2, const double* mom, const double* ph,
+                         int i_sp, int a, int b, cx* a12, cx* a21)
+{
+  const double *bq = mom, *lp = mom + 4, *nu = mom + 8;
+  const double *bb = mom + 12, *lm = mom + 16, *nub = mom + 20;
+  double pt[4], ptb[4], mptb[4];
+  for (int i = 0; i < 4; ++i) { pt[i] = bq[i] + lp[i] + nu[i]; ptb[i] = bb[i] + lm[i] + nub[i]; mptb[i] = -ptb[i]; }
+  mat4 PL = proj_left();
+  int sb = (i_sp >> 2) & 1, sn = (i_sp >> 1) & 1, sl = i_sp & 1;
+  cx J[4], Jm[4];
+  current_L(dbar(spinor_u(nu, 0.0, sn)), spinor_v(lp, 0.0, sl), J);
+  current_L(dbar(spinor_u(lm, 0.0, sl)), spinor_v(nub, 0.0, sn), Jm);
+  spin4 R = rowmat(rowmat(dbar(spinor_u(bq, 0.0, sb)), mmul(slash(J), PL)), prop_m(pt, mt));
+  spin4 C = mvec(prop_m(mptb, mt), mvec(mmul(slash(Jm), PL), spinor_v(bb, 0.0, sb)));
+  double e1[4], e2[4];
+  lin_pol(a, e1);
+  lin_pol(b, e2);
+  mat4 m12, m21;
+  build_ggh(mt, k1, k2, pt, ptb, ph, e1, e2, &m12, &m21);
+  *a12 = rowcol(R, mvec(m12, C));
+  *a21 = rowcol(R, mvec(m21, C));
+}
+
+/* Soft-Higgs theorem: a zero-momentum scalar with unit coupling inserted
+ * into a fermion line turns each propagator S into S S = dS/dm, so the
+ * t tbar H amplitude at pH -> 0 equals d/dm of the t tbar amplitude (top
+ * mass in every propagator, the two decay propagators included, momenta
+ * fixed).  mom: the six decay momenta (massless); the gluons are placed
+ * along +-z to balance the t tbar system plus pH = delta (1, 0, 0, 1).
+ * Returns the largest relative deviation over spins, polarisations and the
+ * two colour orderings. */
+double or_tth_soft_check(double mt, const double* mom, double delta)
+{
+  init_gamma();
+  double P[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 6; ++k)
+    for (int i = 0; i < 4; ++i) P[i] += mom[4 * k + i];
+  double ph[4] = {delta, 0.0, 0.0, delta};
+  /* gluons with zero p_T balancing P (+ ph); P must have P_T = 0 */
+  double E = P[0], Z = P[3];
+  double k1t[4] = {0.5 * (E + Z), 0, 0, 0.5 * (E + Z)}, k2t[4] = {0.5 * (E - Z), 0, 0, -0.5 * (E - Z)};
+  double Eh = E + ph[0], Zh = Z + ph[3];
+  double k1h[4] = {0.5 * (Eh + Zh), 0, 0, 0.5 * (Eh + Zh)}, k2h[4] = {0.5 * (Eh - Zh), 0, 0, -0.5 * (Eh - Zh)};
+  double worst = 0.0;
+  const double h = 1e-4 * mt;
+  for (int isp = 0; isp < 8; ++isp)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        cx p12, p21, m12, m21, h12, h21;
+        ord_amps_tt(mt + h, k1t, k2t, mom, isp, a, b, &p12, &p21);
+        ord_amps_tt(mt - h, k1t, k2t, mom, isp, a, b, &m12, &m21);
+        ord_amps_tth(mt, k1h, k2h, mom, ph, isp, a, b, &h12, &h21);
+        cx d12 = (p12 - m12) / (2.0 * h), d21 = (p21 - m21) / (2.0 * h);
+        double sc = fmax(cabs(d12), cabs(d21));
+        if (sc == 0.0) continue;
+        worst = fmax(worst, fmax(cabs(h12 - d12), cabs(h21 - d21)) / sc);
+      }
+  return worst;
+}
+
+/* g g -> t tbar H with decayed tops (massless decay products, V-A W
+ * couplings), H -> b bbar: the spin- and colour-summed |M|^2 averaged over
+ * initial states, times the top and W Breit-Wigner factors and couplings
+ * (as or_tt_me2_gg), the Yukawa coupling (m_t/v)^2, the H -> b bbar decay
+ * (m_b/v)^2 3 Tr(pb pbbar) = 6 (m_b/v)^2 (pb+pbbar)^2, and the Higgs
+ * Breit-Wigner factor.  mom: 6 decay momenta as or_tt_me2_gg; hb, hbb: the
+ * Higgs decay b quarks. */
+double or_tth_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom, const double* hb,
+                     const double* hbb)
+{
+  init_gamma();
+  spin4 R[8], C[8];
+  double pt[4], ptb[4], ph[4];
+  decay_wavefunctions(p->m_t, mom, R, C, pt, ptb);
+  for (int i = 0; i < 4; ++i) ph[i] = hb[i] + hbb[i];
+  double sum = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      double e1[4], e2[4];
+      lin_pol(a, e1);
+      lin_pol(b, e2);
+      mat4 m12, m21;
+      build_ggh(p->m_t, k1, k2, pt, ptb, ph, e1, e2, &m12, &m21);
+      for (int j = 0; j < 8; ++j) {
+        spin4 c12 = mvec(m12, C[j]);
+        spin4 c21 = mvec(m21, C[j]);
+        for (int i = 0; i < 8; ++i) sum += colour_gg(rowcol(R[i], c12), rowcol(R[i], c21));
+      }
+    }
+  double v2 = 1.0 / (sqrt(2.0) * p->g_fermi);
+  double yt2 = p->m_t * p->m_t / v2, yb2 = p->m_b * p->m_b / v2;
+  double q2h = mdot(ph, ph);
+  return sum * decay_couplings(p, mom, pt, ptb) / 256.0 * yt2 * 6.0 * yb2 * q2h * bw2(q2h, p->m_h, p->w_h);
+}

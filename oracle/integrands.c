@@ -447,8 +447,14 @@ static void boost_transverse(const double* P, const double* in, double* out)
   out[3] = in[3];
 }
 
-int or_dims(int kind) { return kind == OR_KIND_DY ? 2 : kind == OR_KIND_GENZ ? 4 : kind == OR_KIND_TT_SL ? 7 : 8; }
-int or_nperm(int kind) { return kind == OR_KIND_TT ? 2 : kind == OR_KIND_TT_SL ? 12 : 1; }
+int or_dims(int kind)
+{
+  return kind == OR_KIND_DY ? 2 : kind == OR_KIND_GENZ ? 4 : kind == OR_KIND_TT_SL ? 7 : kind == OR_KIND_TTH ? 9 : 8;
+}
+int or_nperm(int kind)
+{
+  return kind == OR_KIND_TT ? 2 : kind == OR_KIND_TT_SL ? 12 : kind == OR_KIND_TTH ? 24 : 1;
+}
 
 double or_genz_integrand(const double* x)
 {
@@ -706,5 +712,161 @@ double or_tt_semilep_integrand(const or_params* p, const double* ev, int lep_cha
   }
   if (nsol_out) *nsol_out = ns;
   double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
+  return sum * two_pi_pow * tf * jac / (2.0 * l[0]);
+}
+
+/* -------------------------------------------------------------- ttbar H -- */
+/* Event rows: four b-tagged jets b0..b3, two light jets l0, l1, the lepton,
+ * then (charge, 0, 0, 0).  Assignment perm in [0, 24): o = perm % 2 picks
+ * the quark of the hadronic W (l0 for o = 0, l1 for o = 1); perm / 2 in
+ * [0, 12) picks the b pair of the Higgs (6 pairs, ascending) and which of
+ * the two remaining b-jets comes from the leptonic top (the lower one for
+ * an even value). */
+void or_tth_perm(int perm, int* i_h1, int* i_h2, int* i_bl, int* i_bh, int* o)
+{
+  static const int pairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  *o = perm & 1;
+  int bp = perm >> 1, hp = bp >> 1;
+  *i_h1 = pairs[hp][0];
+  *i_h2 = pairs[hp][1];
+  int rest[2], n = 0;
+  for (int j = 0; j < 4; ++j) if (j != *i_h1 && j != *i_h2) rest[n++] = j;
+  *i_bl = (bp & 1) ? rest[1] : rest[0];
+  *i_bh = (bp & 1) ? rest[0] : rest[1];
+}
+
+/* Jet energies of the ttH map (all jets double-Gaussian, one r window):
+ * x0 -> E(l0) (r map), x1 -> hadronic W q2 -> E(l1), x2 -> hadronic top q2
+ * -> E(b_h), x3 -> E(b_l) (r map), x7 -> E(h1) (r map), x8 -> Higgs q2 ->
+ * E(h2) = q2 / (2 E(h1) (1 - cos)).  E6 = (l0, l1, b_h, b_l, h1, h2);
+ * returns the Jacobian or 0 outside the windows. */
+double or_tth_map(const or_params* p, const double* ev, int perm, const double* x, double* E6)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  int ih1, ih2, ibl, ibh, o;
+  or_tth_perm(perm, &ih1, &ih2, &ibl, &ibh, &o);
+  const int rows[6] = {4, 5, ibh, ibl, ih1, ih2};
+  double dir[6][3], em[6];
+  for (int k = 0; k < 6; ++k) {
+    const double* m = ev + 4 * rows[k];
+    double pm = norm3(m);
+    em[k] = m[0];
+    for (int i = 0; i < 3; ++i) dir[k][i] = m[i + 1] / pm;
+  }
+  const double rlo = p->lj_r_lo, rhi = p->lj_r_hi;
+  double jac = 1.0;
+  double ra = rlo + x[0] * (rhi - rlo);
+  double Ea = em[0] / ra;
+  jac *= (rhi - rlo) * em[0] / (ra * ra);
+  double q2wh;
+  jac *= or_bw_map(x[1], p->m_w, p->w_w, 0.0, S, &q2wh);
+  double ca = dir[0][0] * dir[1][0] + dir[0][1] * dir[1][1] + dir[0][2] * dir[1][2];
+  if (!(1.0 - ca > 0.0)) return 0.0;
+  double Eb = q2wh / (2.0 * Ea * (1.0 - ca));
+  jac *= 1.0 / (2.0 * Ea * (1.0 - ca));
+  double q2th;
+  jac *= or_bw_map(x[2], p->m_t, p->w_t, 0.0, S, &q2th);
+  double W[4] = {Ea + Eb, Ea * dir[0][0] + Eb * dir[1][0], Ea * dir[0][1] + Eb * dir[1][1],
+                 Ea * dir[0][2] + Eb * dir[1][2]};
+  double den = 2.0 * (W[0] - (dir[2][0] * W[1] + dir[2][1] * W[2] + dir[2][2] * W[3]));
+  if (!(den > 0.0)) return 0.0;
+  double Ebh = (q2th - q2wh) / den;
+  if (!(Ebh > 0.0)) return 0.0;
+  jac *= 1.0 / den;
+  double rl = rlo + x[3] * (rhi - rlo);
+  double Ebl = em[3] / rl;
+  jac *= (rhi - rlo) * em[3] / (rl * rl);
+  double r1 = rlo + x[7] * (rhi - rlo);
+  double E1 = em[4] / r1;
+  jac *= (rhi - rlo) * em[4] / (r1 * r1);
+  double q2h;
+  jac *= or_bw_map(x[8], p->m_h, p->w_h, 0.0, S, &q2h);
+  double c12 = dir[4][0] * dir[5][0] + dir[4][1] * dir[5][1] + dir[4][2] * dir[5][2];
+  if (!(1.0 - c12 > 0.0)) return 0.0;
+  double E2 = q2h / (2.0 * E1 * (1.0 - c12));
+  jac *= 1.0 / (2.0 * E1 * (1.0 - c12));
+  const double rs[3] = {em[1] / Eb, em[2] / Ebh, em[5] / E2};
+  for (int k = 0; k < 3; ++k)
+    if (rs[k] < rlo || rs[k] > rhi) return 0.0;
+  E6[0] = Ea; E6[1] = Eb; E6[2] = Ebh; E6[3] = Ebl; E6[4] = E1; E6[5] = E2;
+  return jac;
+}
+
+/* Variables: x0..x3, x7, x8 jet energies (or_tth_map); x4, x5 recoil k_T;
+ * x6 leptonic W q2 (-> nu_z).  gg -> t tbar H, H -> b bbar, one W -> l nu,
+ * one W -> q qbar'. */
+double or_tth_integrand(const or_params* p, const double* ev, int lep_charge, int perm, const double* x,
+                        int* nsol_out)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  if (lep_charge == 0) lep_charge = ev[28] > 0 ? 1 : -1;
+  int ih1, ih2, ibl, ibh, o;
+  or_tth_perm(perm, &ih1, &ih2, &ibl, &ibh, &o);
+  const double* l = ev + 24;
+  if (nsol_out) *nsol_out = 0;
+  double E6[6];
+  double jac = or_tth_map(p, ev, perm, x, E6);
+  if (jac == 0.0) return 0.0;
+  const int rows[6] = {4, 5, ibh, ibl, ih1, ih2};
+  double j4[6][4];
+  double tf = 1.0;
+  for (int k = 0; k < 6; ++k) {
+    const double* m = ev + 4 * rows[k];
+    double pm = norm3(m), E = E6[k];
+    j4[k][0] = E;
+    for (int i = 0; i < 3; ++i) j4[k][i + 1] = E * m[i + 1] / pm;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    double T = or_dgauss_tf(m[0], E, p->lj_core, p->lj_tail, p->lj_ftail);
+    tf *= E * E * sin_th * T / (2.0 * E);
+  }
+  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
+  double phi = 2.0 * M_PI * x[5];
+  double vx = 0.0, vy = 0.0;
+  for (int k = 0; k < 6; ++k) { vx += j4[k][1]; vy += j4[k][2]; }
+  double nx = rho * cos(phi) - (vx + l[1]);
+  double ny = rho * sin(phi) - (vy + l[2]);
+  double q2wl;
+  jac *= or_bw_map(x[6], p->m_w, p->w_w, 0.0, S, &q2wl);
+  double nzs[2];
+  int nroot = or_semilep_nu_z(l, nx, ny, q2wl, nzs);
+  double sum = 0.0;
+  int ns = 0;
+  for (int s = 0; s < nroot; ++s) {
+    double nz = nzs[s];
+    double nu[4] = {sqrt(nx * nx + ny * ny + nz * nz), nx, ny, nz};
+    double dq = fabs(2.0 * (l[0] * nz / nu[0] - l[3]));
+    if (!(dq > 0.0)) continue;
+    ++ns;
+    double P[4];
+    for (int i = 0; i < 4; ++i) {
+      P[i] = l[i] + nu[i];
+      for (int k = 0; k < 6; ++k) P[i] += j4[k][i];
+    }
+    double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+    double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
+    double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+    double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+    double h[6][4], hl[4], hn[4];
+    for (int k = 0; k < 6; ++k) boost_transverse(P, j4[k], h[k]);
+    boost_transverse(P, l, hl);
+    boost_transverse(P, nu, hn);
+    const double* qk = h[o];
+    const double* qbk = h[1 - o];
+    double mom[24];
+    if (lep_charge > 0) {
+      memcpy(mom, h[3], 32); memcpy(mom + 4, hl, 32); memcpy(mom + 8, hn, 32);
+      memcpy(mom + 12, h[2], 32); memcpy(mom + 16, qk, 32); memcpy(mom + 20, qbk, 32);
+    } else {
+      memcpy(mom, h[2], 32); memcpy(mom + 4, qbk, 32); memcpy(mom + 8, qk, 32);
+      memcpy(mom + 12, h[3], 32); memcpy(mom + 16, hl, 32); memcpy(mom + 20, hn, 32);
+    }
+    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
+    double me = g1 * g2 * or_tth_me2_gg(p, k1, k2, mom, h[4], h[5]) * 3.0 * 2.0;
+    double shat = x1 * x2 * S;
+    sum += (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat) / dq / (2.0 * nu[0]);
+  }
+  if (nsol_out) *nsol_out = ns;
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 8.0);
   return sum * two_pi_pow * tf * jac / (2.0 * l[0]);
 }

@@ -62,6 +62,8 @@ typedef struct {
   double m_lo, m_hi;   /* Drell-Yan truth window on m_mumu */
   /* light-jet double-Gaussian TF and its r window (semileptonic) */
   double lj_core, lj_tail, lj_ftail, lj_r_lo, lj_r_hi;
+  /* Higgs mass and width, b mass in the H -> b bbar coupling (ttH) */
+  double m_h, w_h, m_b;
 } or_params;
 
 /* toy parton densities x*f(x) of the configuration, and the gluon choice */
@@ -157,7 +159,7 @@ double or_flow_nll_grad(const double* params, int n, const double* x, const doub
                         double* grad);
 
 /* -------------------------------------------------------------- driver -- */
-enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4 };
+enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_KIND_TTH = 5 };
 typedef struct {
   double I, sigma;          /* combined estimate over iterations >= 2 */
   double chi2dof;
@@ -192,4 +194,25 @@ int or_nperm(int kind);
 #ifdef __cplusplus
 }
 #endif
+/* ----------------------------------------------------------- ttbar H -- */
+/* g g -> t tbar H (Higgs at every position of the top line of the three
+ * gg -> t tbar diagrams; unit Yukawa): spin/colour-summed |M|^2 of on-shell
+ * tops averaged over initial states; the Ward-identity residual (e1 -> k1,
+ * relative); the soft-Higgs check against d/dm of the t tbar amplitude
+ * (relative deviation); the decayed |M|^2 with couplings and Breit-Wigner
+ * factors (see dirac.c). */
+double or_gg_tth_prod(double mt, const double* k1, const double* k2, const double* pt, const double* ptb,
+                      const double* ph);
+double or_gg_tth_ward(double mt, const double* k1, const double* k2, const double* pt, const double* ptb,
+                      const double* ph);
+double or_tth_soft_check(double mt, const double* mom, double delta);
+double or_tth_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom, const double* hb,
+                     const double* hbb);
+
+/* c3 event rows b0..b3, l0, l1, lepton, (charge,0,0,0); 24 assignments */
+void or_tth_perm(int perm, int* i_h1, int* i_h2, int* i_bl, int* i_bh, int* o);
+double or_tth_map(const or_params* p, const double* ev, int perm, const double* x, double* E6);
+double or_tth_integrand(const or_params* p, const double* ev, int lep_charge, int perm, const double* x,
+                        int* nsol_out);
+
 #endif

@@ -13,12 +13,15 @@ Layouts: `obs` is float64 [n_events, n_obj, 4] with rows (E, px, py, pz).
   Drell-Yan:       mu-, mu+
   ttbar dilepton:  jet_a, jet_b, l+, l-    (b/bbar order random)
   ttbar semileptonic: j0..j3 (random order), lepton, (charge, 0, 0, 0)
+  ttbar H:         b0..b3 (b-tagged, random order), l0, l1 (random order),
+                   lepton, (charge, 0, 0, 0)
 """
 import numpy as np
 
 SQRT_S = 13000.0
 M_T, W_T = 172.5, 1.4
 M_W, W_W = 80.4, 2.1
+M_H = 125.0
 
 
 def _rng(seed):
@@ -223,6 +226,64 @@ def ttbar_semileptonic(n_events, seed, rel_sigma_b=0.15, lj=(0.10, 0.25, 0.2), s
     pos = np.argsort(order, axis=1)                   # pos[i, parton] = jet slot
     truth = {"b_lep": b_lep, "b_had": b_had, "q": q1, "qbar": q2, "lep": lep, "nu": nu, "k": k,
              "charge": charge, "slot": pos}
+    return {"obs": obs, "truth": truth}
+
+
+def ttbar_higgs(n_events, seed, lj=(0.10, 0.25, 0.2), sigma_k=20.0):
+    """gg -> t tbar H with H -> b bbar (narrow, 125 GeV), one W -> l nu and
+    one W -> q qbar'.  The t tbar H mass rises from threshold with a
+    Gamma(2, 100 GeV) excess, the t tbar subsystem mass is uniform between
+    its threshold and the kinematic limit, all decays are isotropic, the
+    system gets a Gaussian recoil k_T and a Gaussian rapidity; all six jet
+    energies are smeared by the double Gaussian `lj`, the lepton is exact.
+    The four b-jets and the two light jets are stored in random order."""
+    rng = _rng(seed)
+    n = n_events
+    mt1 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mt2 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mw1 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mw2 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mh = np.full(n, M_H)
+    mtth = mt1 + mt2 + mh + rng.gamma(2.0, 100.0, n)
+    mtt = mt1 + mt2 + rng.random(n) * (mtth - mh - mt1 - mt2)
+    ymax = np.log(SQRT_S / mtth)
+    y = np.clip(rng.standard_normal(n), -1.0, 1.0) * np.minimum(2.0, 0.9 * ymax)
+    tt, h = _two_body(mtth, mtt, mh, _iso(rng, n))
+    t, tb = _two_body(mtt, mt1, mt2, _iso(rng, n))
+    t, tb = _boost(t, tt), _boost(tb, tt)
+    hb, hbb = _two_body(mh, np.zeros(n), np.zeros(n), _iso(rng, n))
+    hb, hbb = _boost(hb, h), _boost(hbb, h)
+    b, wp = _two_body(mt1, np.zeros(n), mw1, _iso(rng, n))
+    bb, wm = _two_body(mt2, np.zeros(n), mw2, _iso(rng, n))
+    f1, f1b = _two_body(mw1, np.zeros(n), np.zeros(n), _iso(rng, n))
+    f2, f2b = _two_body(mw2, np.zeros(n), np.zeros(n), _iso(rng, n))
+    f1, f1b = _boost(f1, wp), _boost(f1b, wp)
+    f2, f2b = _boost(f2, wm), _boost(f2b, wm)
+    b, f1, f1b = (_boost(v, t) for v in (b, f1, f1b))
+    bb, f2, f2b = (_boost(v, tb) for v in (bb, f2, f2b))
+    k = sigma_k * rng.standard_normal((n, 2))
+    mT = np.sqrt(mtth ** 2 + np.sum(k * k, axis=1))
+    P = np.stack([mT * np.cosh(y), k[:, 0], k[:, 1], mT * np.sinh(y)], axis=1)
+    b, f1, f1b, bb, f2, f2b, hb, hbb = (_boost(v, P) for v in (b, f1, f1b, bb, f2, f2b, hb, hbb))
+    charge = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    plus = charge[:, None] > 0
+    lep = np.where(plus, f1b, f2)
+    nu = np.where(plus, f1, f2b)
+    q1 = np.where(plus, f2, f1)
+    q2 = np.where(plus, f2b, f1b)
+    b_lep = np.where(plus, b, bb)
+    b_had = np.where(plus, bb, b)
+    bjets = np.stack([_massless(_smear_dgauss(rng, v[:, 0], *lj), v) for v in (b_lep, b_had, hb, hbb)], axis=1)
+    ljets = np.stack([_massless(_smear_dgauss(rng, v[:, 0], *lj), v) for v in (q1, q2)], axis=1)
+    border = np.argsort(rng.random((n, 4)), axis=1)
+    lorder = np.argsort(rng.random((n, 2)), axis=1)
+    crow = np.zeros((n, 4))
+    crow[:, 0] = charge
+    obs = np.concatenate([np.take_along_axis(bjets, border[:, :, None], axis=1),
+                          np.take_along_axis(ljets, lorder[:, :, None], axis=1),
+                          lep[:, None, :], crow[:, None, :]], axis=1)
+    truth = {"b_lep": b_lep, "b_had": b_had, "hb": hb, "hbb": hbb, "q": q1, "qbar": q2, "lep": lep, "nu": nu,
+             "k": k, "charge": charge, "bslot": np.argsort(border, axis=1), "lslot": np.argsort(lorder, axis=1)}
     return {"obs": obs, "truth": truth}
 
 

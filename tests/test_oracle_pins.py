@@ -547,6 +547,113 @@ def test_semilep_integrand_positive_at_truth():
         assert ns >= 1 and v > 0
 
 
+# ------------------------------------------------------------ ttbar H ----
+def tth_kinematics(n, seed, mt=172.5):
+    """on-shell t, tbar, H in the partonic CM with gluons along z"""
+    rng = events._rng(seed)
+    roots = 700.0 + 300.0 * rng.random(n)
+    mtt = 2 * mt + rng.random(n) * (roots - 125.0 - 2 * mt)
+    tt, h = events._two_body(roots, mtt, np.full(n, 125.0), events._iso(rng, n))
+    t, tb = events._two_body(mtt, np.full(n, mt), np.full(n, mt), events._iso(rng, n))
+    return roots, events._boost(t, tt), events._boost(tb, tt), h
+
+
+def test_gg_tth_gauge_lorentz_bose():
+    """e1 -> k1 annihilates both colour orderings (all 8 diagrams); |M|^2 is
+    invariant under a boost along and a rotation about the beam, and
+    symmetric under exchange of the two gluons"""
+    mt = 172.5
+    roots, t, tb, h = tth_kinematics(8, 5)
+    B = np.array([[np.cosh(0.7), 0, 0, np.sinh(0.7)], [0, 1, 0, 0], [0, 0, 1, 0], [np.sinh(0.7), 0, 0, np.cosh(0.7)]])
+    c, s = np.cos(1.1), np.sin(1.1)
+    L = B @ np.array([[1, 0, 0, 0], [0, c, -s, 0], [0, s, c, 0], [0, 0, 0, 1]])
+    for i in range(8):
+        k1 = np.array([roots[i] / 2, 0, 0, roots[i] / 2])
+        k2 = np.array([roots[i] / 2, 0, 0, -roots[i] / 2])
+        m0 = oracle.gg_tth_prod(mt, k1, k2, t[i], tb[i], h[i])
+        assert m0 > 0
+        assert oracle.gg_tth_ward(mt, k1, k2, t[i], tb[i], h[i]) < 1e-10
+        assert oracle.gg_tth_prod(mt, k2, k1, t[i], tb[i], h[i]) == pytest.approx(m0, rel=1e-13)
+        assert oracle.gg_tth_prod(mt, L @ k1, L @ k2, L @ t[i], L @ tb[i], L @ h[i]) == pytest.approx(m0, rel=1e-11)
+
+
+def test_tth_soft_higgs_theorem():
+    """A(gg -> t tbar H) at p_H -> 0 equals d/dm A(gg -> t tbar) for the
+    decayed tops (the scalar vertex is the identity and every top propagator
+    takes one insertion): the deviation falls linearly with p_H"""
+    rng = events._rng(9)
+    for _ in range(3):
+        M = 420.0 + 200.0 * rng.random(1)
+        t1, t2 = events._two_body(M, np.array([162.0]), np.array([184.0]), events._iso(rng, 1))
+        b, wp = events._two_body(np.array([162.0]), np.zeros(1), np.array([79.0]), events._iso(rng, 1))
+        bb, wm = events._two_body(np.array([184.0]), np.zeros(1), np.array([81.0]), events._iso(rng, 1))
+        lp, nu = events._two_body(np.array([79.0]), np.zeros(1), np.zeros(1), events._iso(rng, 1))
+        lm, nub = events._two_body(np.array([81.0]), np.zeros(1), np.zeros(1), events._iso(rng, 1))
+        lp, nu = events._boost(lp, wp), events._boost(nu, wp)
+        lm, nub = events._boost(lm, wm), events._boost(nub, wm)
+        b, lp, nu = (events._boost(v, t1) for v in (b, lp, nu))
+        bb, lm, nub = (events._boost(v, t2) for v in (bb, lm, nub))
+        Pz = np.array([[np.sqrt(M[0] ** 2 + 150.0 ** 2), 0, 0, 150.0]])
+        mom = np.concatenate([events._boost(v, Pz) for v in (b, lp, nu, bb, lm, nub)])
+        d3, d4, d5 = (oracle.tth_soft_check(172.5, mom, dl) for dl in (1e-3, 1e-4, 1e-5))
+        assert 5.0 < d3 / d4 < 20.0 and 5.0 < d4 / d5 < 20.0 and d5 < 1e-4, (d3, d4, d5)
+
+
+def tth_truth_x(p, obs, tr, i):
+    """invert the ttH map at the generator's truth"""
+    S = p.sqrt_s ** 2
+    bs, ls = tr["bslot"][i], tr["lslot"][i]          # parton -> slot
+    bl, bh, h1, h2 = (int(v) for v in bs)
+    hpair = tuple(sorted((h1, h2)))
+    perm = [k for k in range(24) if oracle.tth_perm(k)[:4] == hpair + (bl, bh)
+            and oracle.tth_perm(k)[4] == (0 if int(ls[0]) == 0 else 1)][0]
+    ih1 = hpair[0]
+    part_b = {bl: tr["b_lep"][i], bh: tr["b_had"][i], h1: tr["hb"][i], h2: tr["hbb"][i]}
+    part_l = {int(ls[0]): tr["q"][i], int(ls[1]): tr["qbar"][i]}
+    x = np.zeros(9)
+    r = lambda meas, true: (meas / true - p.lj_r_lo) / (p.lj_r_hi - p.lj_r_lo)
+
+    def inv_bw(q, m, w):
+        t0, t1 = math.atan((0 - m * m) / (m * w)), math.atan((S - m * m) / (m * w))
+        return (math.atan((q - m * m) / (m * w)) - t0) / (t1 - t0)
+
+    x[0] = r(obs[4][0], part_l[0][0])
+    W = part_l[0] + part_l[1]
+    x[1] = inv_bw(mdot(W, W), p.m_w, p.w_w)
+    T = W + tr["b_had"][i]
+    x[2] = inv_bw(mdot(T, T), p.m_t, p.w_t)
+    x[3] = r(obs[bl][0], tr["b_lep"][i][0])
+    k = tr["k"][i]
+    x[4] = 1 - math.exp(-(k @ k) / (2 * p.sigma_k ** 2))
+    x[5] = (math.atan2(k[1], k[0]) / (2 * math.pi)) % 1.0
+    Wl = tr["lep"][i] + tr["nu"][i]
+    x[6] = inv_bw(mdot(Wl, Wl), p.m_w, p.w_w)
+    x[7] = r(obs[ih1][0], part_b[ih1][0])
+    H = tr["hb"][i] + tr["hbb"][i]
+    x[8] = inv_bw(mdot(H, H), p.m_h, p.w_h)
+    return x, perm
+
+
+def test_tth_integrand_positive_at_truth():
+    p = oracle.tt_params()
+    d = events.ttbar_higgs(10, 71)
+    n_ok = 0
+    for i in range(10):
+        x, perm = tth_truth_x(p, d["obs"][i], d["truth"], i)
+        if np.any(x <= 0) or np.any(x >= 1):
+            continue
+        jac, E = oracle.tth_map(p, d["obs"][i], perm, x)
+        if jac == 0.0:       # a truth energy outside the r window: skip
+            continue
+        tr = d["truth"]
+        assert E[2] == pytest.approx(tr["b_had"][i][0], rel=1e-8)
+        assert E[3] == pytest.approx(tr["b_lep"][i][0], rel=1e-8)
+        v, ns = oracle.tth_integrand(p, d["obs"][i], perm, x)
+        assert ns >= 1 and v > 0
+        n_ok += 1
+    assert n_ok >= 5
+
+
 # ------------------------------------------------------------ flow -----
 def test_flow_context_permutation_and_balance():
     """perm = 1 swaps the two jet slots and leaves the rest; the sum slot
