@@ -43,12 +43,15 @@ typedef enum {
  *                                                   : jet, jet, l+, l-
  *  MEM_TT_SEMILEPTON     gg/qqbar -> t tbar, one W -> l nu, one W -> q qbar'
  *                                   : jet, jet, jet, jet, lepton (charge in
- *                                     mem_events.charge; +1 when null)      */
+ *                                     mem_events.charge; +1 when null)
+ *  MEM_TTH_SEMILEPTON    gg -> t tbar H, H -> b bbar, one W -> l nu, one
+ *                        W -> q qbar': b-jet x 4, light jet x 2, lepton
+ *                                   (charge as above)                        */
 typedef enum {
   MEM_DY_QQ_GAMMA_MUMU = 1,
   MEM_TT_DILEPTON = 2,
   MEM_TT_SEMILEPTON = 3,
-  MEM_TTH_SEMILEPTON = 4    /* declared; not built yet */
+  MEM_TTH_SEMILEPTON = 4
 } mem_kind;
 
 typedef enum { MEM_FP64 = 0, MEM_FP32 = 1 } mem_precision;
@@ -59,7 +62,9 @@ typedef enum { MEM_FP64 = 0, MEM_FP32 = 1 } mem_precision;
  * of the hard system (tt kinds).  m_lo, m_hi: Drell-Yan window on the true
  * pair mass.  sigma_norm: the 1/sigma_i of Eq. mem_def; 0 = unnormalised.
  * precision: arithmetic of the matrix element / PDF / TF stage
- * (MEM_FP64 for Drell-Yan, MEM_FP32 or MEM_FP64 for tt). */
+ * (MEM_FP64 for Drell-Yan, MEM_FP32 or MEM_FP64 for tt).  m_h, w_h: the
+ * Higgs; m_b: the b mass in the H -> b bbar coupling (0: 4.18 GeV; the b
+ * quarks are massless in the kinematics). */
 typedef struct {
   int32_t kind;
   int32_t precision;
@@ -69,6 +74,7 @@ typedef struct {
   double sigma_k;
   double m_lo, m_hi;
   double sigma_norm;
+  double m_b;
 } mem_process_desc;
 
 typedef struct mem_process_s* mem_process;
@@ -136,8 +142,9 @@ typedef struct mem_flow_s* mem_flow;
  *                  spent in its sampling kernel, its launches, the points
  *                  it sampled, and the integrand evaluations of the VEGAS
  *                  fallback (all 0 without a flow)
- *  chunk_points    points per work-queue chunk (0: the process's tuned or
- *                  default value, 4096); a multiple of 256 up to 65536
+ *  chunk_points    points per work-queue chunk for every process of the
+ *                  call (0: each process's tuned value, see mem_autotune,
+ *                  else 4096); a multiple of 256 up to 65536
  *  use_graph       0: launch every iteration; 1 (default when the options
  *                  are NULL): capture one iteration as a hipGraph and
  *                  replay it
@@ -184,10 +191,11 @@ enum {
 
 /* Create a hypothesis (Sec. 1: process i).  Errors: MEM_EINVAL for a null
  * pointer, unknown kind, non-positive sqrt_s/masses/widths or
- * m_hi <= m_lo for Drell-Yan; MEM_EUNSUPPORTED for kinds not built;
+ * m_hi <= m_lo for Drell-Yan; MEM_EUNSUPPORTED for Drell-Yan in FP32;
  * MEM_ENOMEM.  The handle is owned by the library until
- * mem_destroy_process.  Default TFs: muon Gaussian 5 %, b-jet Gaussian 15 %,
- * window 5, r_min 0.1. */
+ * mem_destroy_process.  Default TFs: muon Gaussian 5 %, b-jet Gaussian 15 %
+ * (double Gaussian 10 %/25 %, tail 0.2 for t tbar H), light jet double
+ * Gaussian 10 %/25 %, tail 0.2; window 5, r_min 0.1. */
 mem_status mem_create_process(const mem_process_desc* d, mem_process* out);
 
 /* Replace the TF of the listed object classes (copied in).  MEM_EINVAL on
@@ -216,6 +224,34 @@ mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, in
                                 const int64_t* n_points, int32_t n_np, int32_t n_iter,
                                 const mem_integrate_opts* opt,
                                 double* p_out, double* err_out, int32_t* status_out);
+
+/* ---- autotuner ----
+ * Points per work-queue chunk (the tile one workgroup integrates) trade
+ * queue overhead and per-chunk partial sums against load balance and tail
+ * effects; the best value depends on the GPU, the process and its
+ * precision.  mem_autotune times a 2-iteration integration of the given
+ * events (n_points per event per iteration) with each candidate (NULL:
+ * 1024, 2048, 4096, 8192, 16384; each a multiple of 256 <= 65536), keeps
+ * the fastest integrand rate in the process (used by every later
+ * mem_integrate_events call whose options do not set chunk_points) and
+ * reports it in best_out / rate_out (evaluations per second of the
+ * integrand kernel; both optional).  table_path (optional): a text table
+ * of lines "arch kind precision chunk_points evals_per_s", created or
+ * updated in place for this device and process.  Errors: MEM_EINVAL (null
+ * process, no events, bad candidates, unwritable table), the errors of
+ * mem_integrate_events. */
+mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, const int32_t* candidates,
+                        int32_t n_cand, const char* table_path, int32_t* best_out, double* rate_out);
+
+/* Look up the tuned chunk size of a process in a table written by
+ * mem_autotune, for architecture `arch` (e.g. "gfx950"; NULL: the current
+ * device's).  found (optional) is set to 1 when the entry exists; a
+ * missing entry is not an error.  MEM_EINVAL for an unreadable table or a
+ * malformed entry. */
+mem_status mem_tuning_load(mem_process p, const char* table_path, const char* arch, int32_t* found);
+
+/* The chunk size integrations of this process use by default. */
+mem_status mem_process_chunk_points(mem_process p, int32_t* chunk_points);
 
 /* ---- building blocks of the path, exposed for checks and custom drivers ---- */
 

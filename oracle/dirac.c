@@ -640,6 +640,8 @@ double or_tth_me2_gg(const or_params* p, const double* k1, const double* k2, con
     }
   double v2 = 1.0 / (sqrt(2.0) * p->g_fermi);
   double yt2 = p->m_t * p->m_t / v2, yb2 = p->m_b * p->m_b / v2;
-  double q2h = mdot(ph, ph);
+  /* massless b quarks: (pb + pbbar)^2 = 2 pb.pbbar, which avoids the
+   * cancellation in E^2 - p^2 of the pair (the Higgs width is 4 MeV) */
+  double q2h = 2.0 * mdot(hb, hbb);
   return sum * decay_couplings(p, mom, pt, ptb) / 256.0 * yt2 * 6.0 * yb2 * q2h * bw2(q2h, p->m_h, p->w_h);
 }

@@ -26,7 +26,8 @@ EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_proc
            "mem_process_shape", "mem_integrate_events", "mem_uniforms", "mem_eval_points",
            "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
-           "mem_flow_log_prob", "mem_flow_train_step", "mem_status_string", "mem_last_error")
+           "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
+           "mem_process_chunk_points", "mem_status_string", "mem_last_error")
 
 
 class ProcessDesc(ctypes.Structure):
@@ -35,7 +36,7 @@ class ProcessDesc(ctypes.Structure):
                 ("w_w", ctypes.c_double), ("m_h", ctypes.c_double), ("w_h", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("alpha_s", ctypes.c_double), ("g_fermi", ctypes.c_double),
                 ("sigma_k", ctypes.c_double), ("m_lo", ctypes.c_double), ("m_hi", ctypes.c_double),
-                ("sigma_norm", ctypes.c_double)]
+                ("sigma_norm", ctypes.c_double), ("m_b", ctypes.c_double)]
 
 
 class TFDesc(ctypes.Structure):
@@ -89,6 +90,9 @@ def lib():
             "mem_flow_sample": (I32, [P, P, P, P, I32, I64, U64, U32, P, P, P]),
             "mem_flow_log_prob": (I32, [P, P, P, P, I64, P, P]),
             "mem_flow_train_step": (I32, [P, P, P, P, P, I64, D, P, P, P]),
+            "mem_autotune": (I32, [P, P, I64, P, I32, ctypes.c_char_p, P, P]),
+            "mem_tuning_load": (I32, [P, ctypes.c_char_p, ctypes.c_char_p, P]),
+            "mem_process_chunk_points": (I32, [P, P]),
             "mem_status_string": (ctypes.c_char_p, [I32]),
             "mem_last_error": (I32, [ctypes.c_char_p, ctypes.c_size_t]),
         }
@@ -124,9 +128,9 @@ class Process:
 
     def __init__(self, kind, precision=MEM_FP32, sqrt_s=13000.0, m_top=172.5, w_top=1.4, m_w=80.4, w_w=2.1,
                  m_h=125.0, w_h=0.00407, alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
-                 sigma_k=20.0, m_lo=60.0, m_hi=120.0, sigma_norm=0.0):
+                 sigma_k=20.0, m_lo=60.0, m_hi=120.0, sigma_norm=0.0, m_b=4.18):
         d = ProcessDesc(kind, precision, sqrt_s, m_top, w_top, m_w, w_w, m_h, w_h, alpha, alpha_s, g_fermi,
-                        sigma_k, m_lo, m_hi, sigma_norm)
+                        sigma_k, m_lo, m_hi, sigma_norm, m_b)
         h = ctypes.c_void_p()
         _check(lib().mem_create_process(ctypes.byref(d), ctypes.byref(h)), "mem_create_process")
         self.handle = h
@@ -135,6 +139,27 @@ class Process:
     def set_transfer_functions(self, tfs):
         arr = (TFDesc * len(tfs))(*tfs)
         _check(lib().mem_set_transfer_functions(self.handle, arr, len(tfs)), "mem_set_transfer_functions")
+
+    def autotune(self, comps, n_points, candidates=None, table_path=None, charge=None):
+        """mem_autotune on the given events; returns (chunk_points, evals/s)"""
+        ev = events_struct(comps, charge)
+        cand = (ctypes.c_int32 * len(candidates))(*candidates) if candidates else None
+        best, rate = ctypes.c_int32(), ctypes.c_double()
+        _check(lib().mem_autotune(self.handle, ctypes.byref(ev), n_points, cand, len(candidates) if candidates else 0,
+                                  table_path.encode() if table_path else None, ctypes.byref(best),
+                                  ctypes.byref(rate)), "mem_autotune")
+        return best.value, rate.value
+
+    def load_tuning(self, table_path, arch=None):
+        found = ctypes.c_int32()
+        _check(lib().mem_tuning_load(self.handle, table_path.encode(), arch.encode() if arch else None,
+                                     ctypes.byref(found)), "mem_tuning_load")
+        return bool(found.value)
+
+    def chunk_points(self):
+        c = ctypes.c_int32()
+        _check(lib().mem_process_chunk_points(self.handle, ctypes.byref(c)), "mem_process_chunk_points")
+        return c.value
 
     def shape(self):
         d, n = ctypes.c_int32(), ctypes.c_int32()

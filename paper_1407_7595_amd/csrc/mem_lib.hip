@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,7 @@ struct mem_process_s {
   mem_process_desc desc;
   mem_tf_desc tf[5];
   ProcParams pp;
+  int32_t chunk_points = 0;   // tuned points per work-queue chunk (0: library default)
 };
 
 static TFParams tf_params(const mem_tf_desc& t)
@@ -82,8 +84,8 @@ static void derive(mem_process_s* p)
     double e2 = 4.0 * M_PI * d.alpha;
     pp.dy_const = std::pow(two_pi, -2.0) * (2.0 / pp.S) * e2 * e2 / 3.0 * 0.5;
   } else {
-    pp.dims = d.kind == MEM_TT_SEMILEPTON ? 7 : 8;
-    pp.n_perm = d.kind == MEM_TT_SEMILEPTON ? 12 : 2;
+    pp.dims = d.kind == MEM_TT_SEMILEPTON ? 7 : d.kind == MEM_TTH_SEMILEPTON ? 9 : 8;
+    pp.n_perm = d.kind == MEM_TT_SEMILEPTON ? 12 : d.kind == MEM_TTH_SEMILEPTON ? 24 : 2;
     double mtg = d.m_top * d.w_top, mwg = d.m_w * d.w_w;
     pp.th0_t = std::atan((0.0 - d.m_top * d.m_top) / mtg);
     pp.th1_t = std::atan((pp.S - d.m_top * d.m_top) / mtg);
@@ -99,15 +101,30 @@ static void derive(mem_process_s* p)
     // 1/(2 E_nu) of the neutrino; colour 3 x two generations of the W -> q q'
     double kbw3 = (pp.th1_t - pp.th0_t) / mtg * std::pow((pp.th1_w - pp.th0_w) / mwg, 2);
     pp.sl_const = std::pow(two_pi, -14.0) * (2.0 / pp.S) * 0.5 * 0.5 * coup * kbw3 * 6.0;
+    if (d.kind == MEM_TTH_SEMILEPTON) {
+      // Higgs map aligned with its Breit-Wigner; Yukawa (m_t/v)^2 and the
+      // H -> b bbar factor 6 (m_b/v)^2 q2_H (q2_H applied per point);
+      // two more final-state particles: (2 pi)^-6
+      const double mhg = d.m_h * d.w_h;
+      pp.m_h = d.m_h; pp.w_h = d.w_h;
+      pp.th0_h = std::atan((0.0 - d.m_h * d.m_h) / mhg);
+      pp.th1_h = std::atan((pp.S - d.m_h * d.m_h) / mhg);
+      const double v2 = 1.0 / (std::sqrt(2.0) * d.g_fermi);
+      const double mb = d.m_b > 0.0 ? d.m_b : 4.18;
+      pp.tth_const = pp.sl_const * std::pow(two_pi, -6.0) * (pp.th1_h - pp.th0_h) / mhg
+                   * (d.m_top * d.m_top / v2) * 6.0 * (mb * mb / v2);
+    }
   }
 }
 
 extern "C" mem_status mem_create_process(const mem_process_desc* d, mem_process* out)
 {
   if (!d || !out) return fail(MEM_EINVAL, "null argument");
-  if (d->kind == MEM_TTH_SEMILEPTON) return fail(MEM_EUNSUPPORTED, "process kind not built");
-  if (d->kind != MEM_DY_QQ_GAMMA_MUMU && d->kind != MEM_TT_DILEPTON && d->kind != MEM_TT_SEMILEPTON)
+  if (d->kind != MEM_DY_QQ_GAMMA_MUMU && d->kind != MEM_TT_DILEPTON && d->kind != MEM_TT_SEMILEPTON &&
+      d->kind != MEM_TTH_SEMILEPTON)
     return fail(MEM_EINVAL, "unknown process kind");
+  if (d->kind == MEM_TTH_SEMILEPTON && !(d->m_h > 0.0 && d->w_h > 0.0 && d->m_b >= 0.0))
+    return fail(MEM_EINVAL, "Higgs mass and width must be positive");
   if (!(d->sqrt_s > 0.0)) return fail(MEM_EINVAL, "sqrt_s must be positive");
   if (d->precision != MEM_FP64 && d->precision != MEM_FP32) return fail(MEM_EINVAL, "bad precision");
   if (d->kind == MEM_DY_QQ_GAMMA_MUMU) {
@@ -130,6 +147,8 @@ extern "C" mem_status mem_create_process(const mem_process_desc* d, mem_process*
   p->tf[MEM_OBJ_BJET] = mem_tf_desc{MEM_OBJ_BJET, MEM_TF_GAUSS, 0.15, 0.15, 0.0, 5.0, 0.1};
   p->tf[MEM_OBJ_LJET] = mem_tf_desc{MEM_OBJ_LJET, MEM_TF_DGAUSS, 0.10, 0.25, 0.2, 5.0, 0.1};
   p->tf[MEM_OBJ_NEUTRINO] = mem_tf_desc{MEM_OBJ_NEUTRINO, MEM_TF_UNIFORM, 0.0, 0.0, 0.0, 5.0, 0.1};
+  if (d->kind == MEM_TTH_SEMILEPTON)   // every jet double-Gaussian
+    p->tf[MEM_OBJ_BJET] = mem_tf_desc{MEM_OBJ_BJET, MEM_TF_DGAUSS, 0.10, 0.25, 0.2, 5.0, 0.1};
   derive(p);
   *out = p;
   return MEM_OK;
@@ -336,10 +355,14 @@ __global__ __launch_bounds__(kBlock) void eval_points_kernel(ProcParams pp, Even
     TTEvent e;
     tt_load(ev, event, perm, e);
     f[k] = tt_integrand<T>(pp, e, x, &ns);
-  } else {
+  } else if constexpr (KIND == kSL) {
     SLEvent e;
     sl_load(ev, ev.charge, event, perm, e);
     f[k] = sl_integrand<T>(pp, e, x, &ns);
+  } else {
+    TTHEvent e;
+    tth_load(ev, ev.charge, event, perm, e);
+    f[k] = tth_integrand<T>(pp, e, x, &ns);
   }
   if (nsol) nsol[k] = ns;
 }
@@ -386,10 +409,22 @@ struct DevBuf {
 
 constexpr int64_t kDefaultChunk = 4096;   // points per work-queue chunk
 
-int n_obj_of(int kind) { return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : kind == MEM_TT_SEMILEPTON ? 5 : 4; }
+int n_obj_of(int kind)
+{
+  return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : kind == MEM_TT_SEMILEPTON ? 5 : kind == MEM_TTH_SEMILEPTON ? 7 : 4;
+}
 
 // relative cost of one evaluation (for the longest-first queue order)
-double eval_cost(int kind) { return kind == MEM_DY_QQ_GAMMA_MUMU ? 1.0 : kind == MEM_TT_SEMILEPTON ? 12.0 : 30.0; }
+double eval_cost(int kind)
+{
+  return kind == MEM_DY_QQ_GAMMA_MUMU ? 1.0 : kind == MEM_TT_SEMILEPTON ? 12.0 : kind == MEM_TTH_SEMILEPTON ? 30.0 : 30.0;
+}
+
+int kind_mask(int kind)
+{
+  return kind == MEM_DY_QQ_GAMMA_MUMU ? kMaskDY : kind == MEM_TT_DILEPTON ? kMaskTT
+       : kind == MEM_TT_SEMILEPTON ? kMaskSL : kMaskTTH;
+}
 
 mem_status check_event_arrays(const mem_events* ev)
 {
@@ -458,7 +493,10 @@ QueueKernel queue_kernel_for(int mask)
     case kMaskDY: return vegas_queue_kernel<T, kMaskDY>;
     case kMaskTT: return vegas_queue_kernel<T, kMaskTT>;
     case kMaskSL: return vegas_queue_kernel<T, kMaskSL>;
-    default: return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL>;
+    case kMaskTTH: return vegas_queue_kernel<T, kMaskTTH>;
+    default:
+      if (!(mask & kMaskTTH)) return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL>;
+      return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL | kMaskTTH>;
   }
 }
 
@@ -534,7 +572,6 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   mem_status st = MEM_OK;
   const int n_ev = ev->n_events;
   const bool target_mode = o.target_rel_err > 0.0;
-  int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : kDefaultChunk;
 
   // ---- processes, integrals (event x permutation) and chunks ----
   std::vector<const mem_process_s*> procs;
@@ -582,6 +619,9 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   int64_t part_total = 0;
   for (int ig = 0; ig < n_int; ++ig) {
     IntegralDesc& d = ints[ig];
+    // the call's chunk size, else the process's tuned one, else the default
+    const int tuned = procs[int_proc[ig]]->chunk_points;
+    const int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : tuned > 0 ? tuned : kDefaultChunk;
     d.chunk0 = (int64_t)chunks.size();
     d.n_chunks = 0;
     for (int64_t s0 = 0; s0 < d.n_points; s0 += chunk_pts) {
@@ -613,7 +653,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     int prec = p->desc.kind == MEM_DY_QQ_GAMMA_MUMU ? first_prec : p->desc.precision;
     Group& G = groups[group_of(prec)];
     G.queue.push_back((int32_t)c);
-    G.mask |= p->desc.kind == MEM_DY_QQ_GAMMA_MUMU ? kMaskDY : p->desc.kind == MEM_TT_DILEPTON ? kMaskTT : kMaskSL;
+    G.mask |= kind_mask(p->desc.kind);
     cost[c] = chunks[c].count * eval_cost(p->desc.kind);
   }
   for (auto& G : groups)
@@ -840,6 +880,12 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
   if (p->desc.kind == MEM_DY_QQ_GAMMA_MUMU)
     hipLaunchKernelGGL((eval_points_kernel<kDY, 2, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
                        x, n, f, nsol);
+  else if (p->desc.kind == MEM_TTH_SEMILEPTON && p->desc.precision == MEM_FP32)
+    hipLaunchKernelGGL((eval_points_kernel<kTTH, 9, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
+  else if (p->desc.kind == MEM_TTH_SEMILEPTON)
+    hipLaunchKernelGGL((eval_points_kernel<kTTH, 9, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
   else if (p->desc.kind == MEM_TT_SEMILEPTON && p->desc.precision == MEM_FP32)
     hipLaunchKernelGGL((eval_points_kernel<kSL, 7, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
                        x, n, f, nsol);
@@ -865,6 +911,121 @@ extern "C" mem_status mem_vegas_refine(const double* bins, double* grids, int32_
   if (n_int == 0) return MEM_OK;
   hipLaunchKernelGGL(refine_only_kernel, dim3(n_int), dim3(kBlock), 0, (hipStream_t)stream, bins, grids, D, alpha);
   HIP_TRY(hipGetLastError());
+  return MEM_OK;
+}
+
+// -------------------------------------------------------------- autotuner ----
+namespace {
+std::string device_arch()
+{
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tuning_key(const std::string& arch, const mem_process_s* p)
+{
+  return arch + " " + std::to_string(p->desc.kind) + " " + std::to_string(p->desc.precision);
+}
+
+bool valid_chunk(int64_t c) { return c > 0 && c % kBlock == 0 && c <= 65536; }
+}  // namespace
+
+extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, const int32_t* candidates,
+                                   int32_t n_cand, const char* table_path, int32_t* best_out, double* rate_out)
+{
+  if (!p) return fail(MEM_EINVAL, "null process");
+  mem_status st = check_event_arrays(ev);
+  if (st != MEM_OK) return st;
+  if (ev->n_events < 1) return fail(MEM_EINVAL, "the tuner needs at least one event");
+  static const int32_t kDefaults[] = {1024, 2048, 4096, 8192, 16384};
+  if (!candidates) { candidates = kDefaults; n_cand = 5; }
+  if (n_cand < 1) return fail(MEM_EINVAL, "no candidates");
+  for (int i = 0; i < n_cand; ++i)
+    if (!valid_chunk(candidates[i])) return fail(MEM_EINVAL, "candidates must be multiples of 256 <= 65536");
+  const int n_ev = ev->n_events;
+  std::vector<double> P(n_ev), E(n_ev);
+  std::vector<int32_t> S(n_ev);
+  double best_rate = -1.0;
+  int32_t best = candidates[0];
+  for (int i = 0; i < n_cand; ++i) {
+    double rate = 0.0;
+    for (int rep = 0; rep < 2; ++rep) {   // the better of two runs
+      double tm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      mem_integrate_opts o{};
+      o.seed = 0x5EEDu + (uint64_t)rep;
+      o.alpha = 1.5;
+      o.max_iter = 2;
+      o.chunk_points = candidates[i];
+      o.use_graph = 0;
+      o.timing_out = tm;
+      st = mem_integrate_events(ev, &p, 1, &n_points, 1, 2, &o, P.data(), E.data(), S.data());
+      if (st != MEM_OK) return st;
+      if (tm[0] > 0.0) rate = std::max(rate, tm[2] / (tm[0] * 1e-3));
+    }
+    if (rate > best_rate) { best_rate = rate; best = candidates[i]; }
+  }
+  p->chunk_points = best;
+  if (best_out) *best_out = best;
+  if (rate_out) *rate_out = best_rate;
+  if (table_path) {
+    const std::string arch = device_arch();
+    if (arch.empty()) return fail(MEM_EDEVICE, "cannot read the device architecture");
+    const std::string key = tuning_key(arch, p);
+    std::vector<std::string> lines;
+    if (FILE* fh = std::fopen(table_path, "r")) {
+      char buf[512];
+      while (std::fgets(buf, sizeof buf, fh)) {
+        std::string ln(buf);
+        while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+        if (ln.empty() || ln.compare(0, key.size() + 1, key + " ") == 0) continue;
+        lines.push_back(ln);
+      }
+      std::fclose(fh);
+    }
+    char row[256];
+    std::snprintf(row, sizeof row, "%s %d %.6g", key.c_str(), best, best_rate);
+    lines.push_back(row);
+    FILE* fo = std::fopen(table_path, "w");
+    if (!fo) return fail(MEM_EINVAL, std::string("cannot write ") + table_path);
+    std::fputs("# arch kind precision chunk_points evals_per_s\n", fo);
+    for (const auto& ln : lines)
+      if (ln[0] != '#') { std::fputs(ln.c_str(), fo); std::fputc('\n', fo); }
+    std::fclose(fo);
+  }
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_tuning_load(mem_process p, const char* table_path, const char* arch, int32_t* found)
+{
+  if (!p || !table_path) return fail(MEM_EINVAL, "null argument");
+  if (found) *found = 0;
+  const std::string a = arch ? std::string(arch) : device_arch();
+  if (a.empty()) return fail(MEM_EDEVICE, "cannot read the device architecture");
+  FILE* fh = std::fopen(table_path, "r");
+  if (!fh) return fail(MEM_EINVAL, std::string("cannot read ") + table_path);
+  const std::string key = tuning_key(a, p);
+  char buf[512];
+  mem_status st = MEM_OK;
+  while (std::fgets(buf, sizeof buf, fh)) {
+    std::string ln(buf);
+    if (ln.compare(0, key.size() + 1, key + " ") != 0) continue;
+    long c = std::strtol(ln.c_str() + key.size() + 1, nullptr, 10);
+    if (!valid_chunk(c)) { st = fail(MEM_EINVAL, "malformed tuning entry"); break; }
+    p->chunk_points = (int32_t)c;
+    if (found) *found = 1;
+  }
+  std::fclose(fh);
+  return st;
+}
+
+extern "C" mem_status mem_process_chunk_points(mem_process p, int32_t* chunk_points)
+{
+  if (!p || !chunk_points) return fail(MEM_EINVAL, "null argument");
+  *chunk_points = p->chunk_points > 0 ? p->chunk_points : (int32_t)kDefaultChunk;
   return MEM_OK;
 }
 

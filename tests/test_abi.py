@@ -54,8 +54,13 @@ def test_create_process_validation(mem):
     with pytest.raises(mem.MemError) as e:
         mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64, m_lo=120.0, m_hi=60.0)
     assert e.value.status == mem.MEM_EINVAL
+    tth = mem.Process(mem.MEM_TTH_SEMILEPTON)
+    assert tth.shape() == (9, 24)
     with pytest.raises(mem.MemError) as e:
-        mem.Process(mem.MEM_TTH_SEMILEPTON)
+        mem.Process(mem.MEM_TTH_SEMILEPTON, w_h=0.0)
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:
+        mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP32)
     assert e.value.status == mem.MEM_EUNSUPPORTED
     L = mem.lib()
     assert L.mem_create_process(None, None) == mem.MEM_EINVAL
@@ -99,3 +104,27 @@ def test_integrate_rejects_bad_host_events_before_any_launch(mem):
     with pytest.raises(mem.MemError) as e:          # two hypotheses for three events
         mem.integrate_events(good, [p, p], 1000, 3)
     assert e.value.status == mem.MEM_EINVAL
+
+
+def test_tuning_table_lookup(mem, tmp_path):
+    """mem_tuning_load reads the tuner's table (no GPU needed with an
+    explicit architecture)"""
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    assert p.chunk_points() == 4096
+    t = tmp_path / "tune.txt"
+    t.write_text("# arch kind precision chunk_points evals_per_s\n"
+                 "gfx942 2 1 2048 1e9\n"
+                 "gfx950 2 0 1024 5e8\n"
+                 "gfx950 2 1 8192 1.5e9\n")
+    assert p.load_tuning(str(t), arch="gfx950")
+    assert p.chunk_points() == 8192
+    q = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    assert not q.load_tuning(str(t), arch="gfx950")
+    assert q.chunk_points() == 4096
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 2 1 1000 1e9\n")
+    with pytest.raises(mem.MemError) as e:
+        p.load_tuning(str(bad), arch="gfx950")
+    assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError):
+        p.load_tuning(str(tmp_path / "missing.txt"), arch="gfx950")
