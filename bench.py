@@ -81,7 +81,7 @@ FLOW_TRAIN_PTS = 8192          # VEGAS points per training event per iteration
 FLOW_TRAIN_ITERS = 4
 FLOW_CAPTURE = 168             # samples per training integral: 100 000 x 168 ~ 2^24
 FLOW_BATCH = 65536             # training minibatch
-FLOW_EPOCHS = 8
+FLOW_EPOCHS = 24
 FLOW_LR = (2e-3, 1e-4)         # cosine decay between these
 FLOW_PTS = 16384               # flow points per event per batch
 SEED_TRAIN = 0x14077595 + 4
@@ -144,9 +144,9 @@ def flow_leg(mem, proc, comps, n_ev, args):
     n_used = torch.zeros(n_ev, dtype=torch.int32, device="cuda")
     timing = (ctypes.c_double * 8)()
 
-    def run(tm=None):
+    def run(tm=None, thr=0.3):
         mem.integrate_events(comps, proc, FLOW_PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER,
-                             outputs=(P, E, S), n_iter_out=n_used, flow=f, ess_threshold=0.3, timing=tm)
+                             outputs=(P, E, S), n_iter_out=n_used, flow=f, ess_threshold=thr, timing=tm)
 
     run()
     torch.cuda.synchronize()
@@ -158,15 +158,24 @@ def flow_leg(mem, proc, comps, n_ev, args):
         times.append(time.perf_counter() - t0)
     value = n_ev * len(times) / sum(times)
     st = S.cpu().numpy()
+    nu_fb = n_used.cpu().numpy()
     run(timing)                           # per-kernel times (direct launches)
     torch.cuda.synchronize()
     samp_ms, samp_n = timing[4], timing[5]
     flow_pts = timing[6]
     mfma = flow_pts * 6 * 2 * 128 * (128 + 96) / (samp_ms * 1e-3) if samp_ms > 0 else None
-    out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times),
+    # the proposal alone (no fallback), for reference
+    t0 = time.perf_counter()
+    run(thr=1e-12)
+    torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t0
+    st_alone = S.cpu().numpy()
+    alone = {"events_per_s": n_ev / alone_s, "converged_fraction": float(np.mean(st_alone == 0)),
+             "median_batches": float(np.median(n_used.cpu().numpy()))}
+    out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times), "flow_alone": alone,
            "points_per_event_per_batch": FLOW_PTS, "fallback_fraction": float(np.mean(st == 4)),
            "converged_fraction": float(np.mean((st == 0) | (st == 4))),
-           "median_batches": float(np.median(n_used.cpu().numpy())),
+           "median_batches": float(np.median(nu_fb)),
            "train": {"events": n_tr, "samples": n_s, "epochs": FLOW_EPOCHS, "seconds": train_s,
                      "data_seconds": data_s, "loss_first": losses[0], "loss_last": losses[-1]},
            "sample_kernel": {"ms": samp_ms, "launches": samp_n, "points": flow_pts,

@@ -21,6 +21,7 @@
 #include "process.hpp"
 #include "sl.hpp"
 #include "tt.hpp"
+#include "tth.hpp"
 
 namespace memk {
 
@@ -100,9 +101,9 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
 // Persistent work-queue kernel: every workgroup loops until the shared head
 // passes n_chunks (each iteration of the loop reads the head once, so every
 // workgroup reaches the exit).  KINDS is the set of process kinds compiled
-// in (bit 1 DY, 2 dilepton, 4 semileptonic): a launch carries only the
+// in (bit 1 DY, 2 dilepton, 4 semileptonic, 8 t tbar H): a launch carries only the
 // integrands its chunks need, and with them only their register demand.
-enum { kMaskDY = 1, kMaskTT = 2, kMaskSL = 4 };
+enum { kMaskDY = 1, kMaskTT = 2, kMaskSL = 4, kMaskTTH = 8 };
 template <class T, int KINDS>
 __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_queue_kernel(
     const ProcParams* __restrict__ procs, EventsView ev, const Chunk* __restrict__ chunks, int64_t n_chunks,
@@ -140,8 +141,15 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_queue_kernel(
       chunk_points<2>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[2]) { return dy_integrand(pp, e, x); });
     } else if ((KINDS & kMaskTT) && pp.kind == kTT) {
+#ifdef MEM_EVENT_LDS
+      __shared__ TTEvent se;
+      if (threadIdx.x == 0) tt_load(ev, ch.event, ch.perm, se);
+      __syncthreads();
+      const TTEvent& e = se;
+#else
       TTEvent e;
       tt_load(ev, ch.event, ch.perm, e);
+#endif
       chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskSL) && pp.kind == kSL) {
@@ -149,6 +157,11 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void vegas_queue_kernel(
       sl_load(ev, ev.charge, ch.event, ch.perm, e);
       chunk_points<7>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[7]) { return sl_integrand<T>(pp, e, x, nullptr); });
+    } else if ((KINDS & kMaskTTH) && pp.kind == kTTH) {
+      TTHEvent e;
+      tth_load(ev, ev.charge, ch.event, ch.perm, e);
+      chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2,
+                      [&](const double (&x)[9]) { return tth_integrand<T>(pp, e, x, nullptr); });
     }
     block_reduce2<0>(s1, s2, red);
     __syncthreads();

@@ -4,7 +4,7 @@
 
 namespace memk {
 
-enum Kind : int32_t { kDY = 1, kTT = 2, kSL = 3 };
+enum Kind : int32_t { kDY = 1, kTT = 2, kSL = 3, kTTH = 4 };
 
 // One transfer function for the energy of a measured object, Gaussian or
 // double Gaussian in r = E_meas / E_true (Sec. 1, after Eq. 3).
@@ -30,6 +30,7 @@ struct ProcParams {
   TFParams tf_lj;                  // light jets (semileptonic)
   // Breit-Wigner tan maps q2 = M^2 + M Gamma tan(theta), theta in [th0, th1]
   double th0_t, th1_t, th0_w, th1_w;
+  double m_h, w_h, th0_h, th1_h;   // Higgs (t tbar H)
   // constant factors of the tt weight: couplings, (2 pi) powers, the
   // product of the four (th1 - th0)/(M Gamma) that remain after the
   // propagators cancel against the map Jacobians
@@ -39,6 +40,9 @@ struct ProcParams {
   // semileptonic: as tt_const with three aligned propagators and the
   // hadronic W's colour and generation factor
   double sl_const;
+  // t tbar H: as sl_const with the Higgs map, the Yukawa coupling and the
+  // H -> b bbar decay (times q2_H per point)
+  double tth_const;
 };
 
 struct EventsView {

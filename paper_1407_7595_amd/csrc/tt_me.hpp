@@ -203,4 +203,102 @@ __device__ __forceinline__ T qq_sum(const drow<T>& R, const drow<T>& C, const v4
   return T(2) * (abs2(aL) + abs2(aR)) * is * is;
 }
 
+// ------------------------------------------------------------ t tbar H --
+// Generic Dirac-row operations for chains with a Higgs insertion.
+// p.sigma-bar = [[p0+p3, p1 - i p2], [p1 + i p2, p0-p3]]
+template <class T>
+__device__ __forceinline__ sp<T> row_psigbar(sp<T> r, const mom<T>& p)
+{
+  cx<T> m00{p.e + p.z, T(0)}, m01{p.x, -p.y}, m10{p.x, p.y}, m11{p.e - p.z, T(0)};
+  return sp<T>{r.a * m00 + r.b * m10, r.a * m01 + r.b * m11};
+}
+// R (q-slash + m)
+template <class T>
+__device__ __forceinline__ drow<T> row_prop(const drow<T>& R, const mom<T>& q, T m)
+{
+  sp<T> l = row_psigbar(R.R, q), r = row_psig(R.L, q);
+  return drow<T>{{m * R.L.a + l.a, m * R.L.b + l.b}, {r.a + m * R.R.a, r.b + m * R.R.b}};
+}
+template <class T>
+__device__ __forceinline__ drow<T> row_scale(const drow<T>& R, T f)
+{
+  return drow<T>{{f * R.L.a, f * R.L.b}, {f * R.R.a, f * R.R.b}};
+}
+// R eps-slash for a gluon along +-z with helicity label h (0: +, 1: -):
+// (R_R (e.sigma-bar), R_L (e.sigma)), one nonzero entry each
+template <class T>
+__device__ __forceinline__ drow<T> row_eps(const drow<T>& R, int h)
+{
+  const T s2 = T(1.41421356237309504880);
+  const cx<T> z{T(0), T(0)};
+  if (h == 0) return drow<T>{{z, s2 * R.R.a}, {z, -s2 * R.L.a}};
+  return drow<T>{{s2 * R.R.b, z}, {-s2 * R.L.b, z}};
+}
+// R (k1 - k2)-slash, k1 = (a,0,0,a), k2 = (bm,0,0,-bm)
+template <class T>
+__device__ __forceinline__ drow<T> row_kslash(const drow<T>& R, T a, T bm)
+{
+  return drow<T>{{(T(2) * a) * R.R.a, (T(-2) * bm) * R.R.b}, {(T(-2) * bm) * R.L.a, (T(2) * a) * R.L.b}};
+}
+template <class T> __device__ __forceinline__ cx<T> row_col(const drow<T>& R, const drow<T>& C)
+{
+  return dot2(R.L, C.L) + dot2(R.R, C.R);
+}
+template <class T> __device__ __forceinline__ T mom2(const mom<T>& q) { return q.e * q.e - q.x * q.x - q.y * q.y - q.z * q.z; }
+template <class T> __device__ __forceinline__ mom<T> madd(const mom<T>& a, const mom<T>& b, T f)
+{
+  return mom<T>{a.e + f * b.e, a.x + f * b.x, a.y + f * b.y, a.z + f * b.z};
+}
+
+// Sum over gluon helicities and colours of |A|^2 for g(k1) g(k2) -> t tbar H
+// with unit Yukawa vertex: the Higgs at every position of the top line of
+// the three gg -> t tbar diagrams (8 diagrams), colour orderings as gg_sum.
+// pt, ptb: top and antitop momenta; ph: Higgs momentum (FP64: the internal
+// momenta and their propagator denominators are formed in FP64, where
+// (p_t + p_H)^2 - m_t^2 would lose digits to cancellation in FP32).
+template <class T>
+__device__ __forceinline__ T gg_tth_sum(const drow<T>& R, const drow<T>& C, const v4& pt, const v4& ptb,
+                                        const v4& ph, double a, double bm, T mt)
+{
+  const double m2 = (double)mt * (double)mt;
+  const v4 qa = add(pt, ph);                                      // H next to the top
+  const v4 qc{-ptb.e - ph.e, -ptb.x - ph.x, -ptb.y - ph.y, -ptb.z - ph.z};   // H next to the antitop
+  const v4 q1{pt.e - a, pt.x, pt.y, pt.z - a}, q2{pt.e - bm, pt.x, pt.y, pt.z + bm};   // pt - k_i
+  const v4 q1h = add(q1, ph), q2h = add(q2, ph);                  // pt - k_i + ph
+  auto to = [](const v4& v) { return mom<T>{T(v.e), T(v.x), T(v.y), T(v.z)}; };
+  const T iDa = T(1.0 / (mdot(qa, qa) - m2)), iDc = T(1.0 / (mdot(qc, qc) - m2));
+  const T iD1 = T(1.0 / (mdot(q1, q1) - m2)), iD2 = T(1.0 / (mdot(q2, q2) - m2));
+  const T iD1h = T(1.0 / (mdot(q1h, q1h) - m2)), iD2h = T(1.0 / (mdot(q2h, q2h) - m2));
+  const T s = T(4.0 * a * bm);
+  const T ta = T(a), tbm = T(bm);
+  const mom<T> qaT = to(qa), qcT = to(qc), q1T = to(q1), q2T = to(q2), q1hT = to(q1h), q2hT = to(q2h);
+  const drow<T> Sa = row_scale(row_prop(R, qaT, mt), iDa);     // R S(pt + ph)
+  // s-channel current with the Higgs on either side of it
+  const cx<T> sch = (T(1) / s) * (row_col(row_kslash(Sa, ta, tbm), C)
+                                 + iDc * row_col(row_prop(row_kslash(R, ta, tbm), qcT, mt), C));
+  T sum = T(0);
+#pragma unroll
+  for (int h1 = 0; h1 < 2; ++h1)
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      // ordering 12: gluon 1 next to the top
+      const drow<T> e1 = row_eps(R, h1);
+      const drow<T> e1q = row_prop(e1, q1T, mt);                // R e1 (pt - k1 + m)
+      cx<T> a12 = (iD1h) * row_col(row_eps(row_prop(row_eps(Sa, h1), q1hT, mt), h2), C);
+      a12 = a12 + (iD1 * iD1h) * row_col(row_eps(row_prop(e1q, q1hT, mt), h2), C);
+      a12 = a12 + (iD1 * iDc) * row_col(row_prop(row_eps(e1q, h2), qcT, mt), C);
+      // ordering 21: gluon 2 next to the top
+      const drow<T> e2 = row_eps(R, h2);
+      const drow<T> e2q = row_prop(e2, q2T, mt);
+      cx<T> a21 = (iD2h) * row_col(row_eps(row_prop(row_eps(Sa, h2), q2hT, mt), h1), C);
+      a21 = a21 + (iD2 * iD2h) * row_col(row_eps(row_prop(e2q, q2hT, mt), h1), C);
+      a21 = a21 + (iD2 * iDc) * row_col(row_prop(row_eps(e2q, h1), qcT, mt), C);
+      // eps1.eps2 = -1 for opposite labels, 0 for equal ones
+      if (h1 != h2) { a12 = a12 - sch; a21 = a21 + sch; }
+      const cx<T> x = a12 * conj(a21);
+      sum += T(16.0 / 3.0) * (abs2(a12) + abs2(a21)) - T(4.0 / 3.0) * x.re;
+    }
+  return sum;
+}
+
 }  // namespace memk
