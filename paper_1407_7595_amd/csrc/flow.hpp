@@ -49,10 +49,15 @@ __device__ __forceinline__ uint16_t f2bf(float v)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float silu(float a) { return a / (1.0f + __expf(-a)); }
+// Reciprocal by the hardware approximation (1 ulp): the activations are
+// rounded to BF16 (or split into two BF16 terms, ~2^-17), far coarser than
+// the correctly rounded division this replaces (about ten instructions).
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float silu(float a) { return a * frcp(1.0f + __expf(-a)); }
 __device__ __forceinline__ float dsilu(float a)
 {
-  const float s = 1.0f / (1.0f + __expf(-a));
+  const float s = frcp(1.0f + __expf(-a));
   return s * (1.0f + a * (1.0f - s));
 }
 __device__ __forceinline__ float softplus(float v) { return v > 20.0f ? v : log1pf(__expf(v)); }
@@ -96,7 +101,7 @@ __device__ __forceinline__ void spline_make(const float* th, Spline& s)
   float ew[FK], eh[FK], sw = 0.0f, sh = 0.0f;
 #pragma unroll
   for (int k = 0; k < FK; ++k) { ew[k] = __expf(th[k] - mw); sw += ew[k]; eh[k] = __expf(th[FK + k] - mh); sh += eh[k]; }
-  const float iw = cw / sw, ih = cw / sh;
+  const float iw = cw * frcp(sw), ih = cw * frcp(sh);
   s.xk[0] = 0.0f; s.yk[0] = 0.0f;
 #pragma unroll
   for (int k = 0; k < FK; ++k) { s.xk[k + 1] = s.xk[k] + m + ew[k] * iw; s.yk[k + 1] = s.yk[k] + m + eh[k] * ih; }
@@ -123,29 +128,30 @@ __device__ __forceinline__ Bin spline_bin(const Spline& s, float v, bool by_y)
 __device__ __forceinline__ float spline_fwd(const Spline& s, float x, float& ld)
 {
   const Bin b = spline_bin(s, x, false);
-  const float sk = b.h / b.w, t = (x - b.x0) / b.w, omt = 1.0f - t;
+  const float iw = frcp(b.w);
+  const float sk = b.h * iw, t = (x - b.x0) * iw, omt = 1.0f - t;
   const float g = b.d1 + b.d0 - 2.0f * sk;
   const float den = sk + g * t * omt;
   const float nd = b.d1 * t * t + 2.0f * sk * t * omt + b.d0 * omt * omt;
-  ld = __logf(sk * sk * nd) - 2.0f * __logf(den);
-  return b.y0 + b.h * (sk * t * t + b.d0 * t * omt) / den;
+  ld = __logf(sk * sk * nd * frcp(den * den));
+  return b.y0 + b.h * (sk * t * t + b.d0 * t * omt) * frcp(den);
 }
 
 // inverse: x(y) from the quadratic in t; log dy/dx at the returned x
 __device__ __forceinline__ float spline_inv(const Spline& s, float y, float& ld)
 {
   const Bin b = spline_bin(s, y, true);
-  const float sk = b.h / b.w, dy = y - b.y0;
+  const float sk = b.h * frcp(b.w), dy = y - b.y0;
   const float g = b.d1 + b.d0 - 2.0f * sk;
   const float qa = b.h * (sk - b.d0) + dy * g;
   const float qb = b.h * b.d0 - dy * g;
   const float qc = -sk * dy;
   const float disc = fmaxf(qb * qb - 4.0f * qa * qc, 0.0f);
-  const float t = fminf(fmaxf((2.0f * qc) / (-qb - sqrtf(disc)), 0.0f), 1.0f);
+  const float t = fminf(fmaxf((2.0f * qc) * frcp(-qb - sqrtf(disc)), 0.0f), 1.0f);
   const float omt = 1.0f - t;
   const float den = sk + g * t * omt;
   const float nd = b.d1 * t * t + 2.0f * sk * t * omt + b.d0 * omt * omt;
-  ld = __logf(sk * sk * nd) - 2.0f * __logf(den);
+  ld = __logf(sk * sk * nd * frcp(den * den));
   return fminf(fmaxf(b.x0 + t * b.w, 0.0f), 1.0f);
 }
 

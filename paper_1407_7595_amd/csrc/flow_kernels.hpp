@@ -466,16 +466,17 @@ __device__ __forceinline__ void spline_backward(const float* th, float x, float 
 #pragma unroll
   for (int k = 0; k < FK; ++k) { pw[k] = __expf(th[k] - mw); sw += pw[k]; ph[k] = __expf(th[FK + k] - mh); sh += ph[k]; }
   // knots exactly as the forward pass forms them (same bin for x)
-  const float iw = cw / sw, ih = cw / sh;
+  const float kiw = cw * frcp(sw), kih = cw * frcp(sh);
   float xk[FK + 1], yk[FK + 1], d[FK + 1];
   xk[0] = 0.0f;
   yk[0] = 0.0f;
 #pragma unroll
-  for (int k = 0; k < FK; ++k) { xk[k + 1] = xk[k] + m + pw[k] * iw; yk[k + 1] = yk[k] + m + ph[k] * ih; }
+  for (int k = 0; k < FK; ++k) { xk[k + 1] = xk[k] + m + pw[k] * kiw; yk[k + 1] = yk[k] + m + ph[k] * kih; }
   xk[FK] = 1.0f;
   yk[FK] = 1.0f;
+  const float isw = frcp(sw), ish = frcp(sh);
 #pragma unroll
-  for (int k = 0; k < FK; ++k) { pw[k] /= sw; ph[k] /= sh; }
+  for (int k = 0; k < FK; ++k) { pw[k] *= isw; ph[k] *= ish; }
   d[0] = 1.0f; d[FK] = 1.0f;
 #pragma unroll
   for (int k = 1; k < FK; ++k) d[k] = m + softplus(th[2 * FK + k - 1] + c0);
@@ -486,27 +487,29 @@ __device__ __forceinline__ void spline_backward(const float* th, float x, float 
 #pragma unroll
   for (int k = 0; k < FK; ++k)
     if (k == kb) { w = xk[k + 1] - xk[k]; h = yk[k + 1] - yk[k]; x0 = xk[k]; d0 = d[k]; d1 = d[k + 1]; }
-  const float t = (x - x0) / w, omt = 1.0f - t, sk = h / w;
+  const float iw = frcp(w);
+  const float t = (x - x0) * iw, omt = 1.0f - t, sk = h * iw;
   const float g = d1 + d0 - 2.0f * sk;
   const float den = sk + g * t * omt, nu = sk * t * t + d0 * t * omt;
   const float nd = d1 * t * t + 2.0f * sk * t * omt + d0 * omt * omt;
-  const float id2 = 1.0f / (den * den);
+  const float iden = frcp(den), ind = frcp(nd);
+  const float id2 = iden * iden;
   const float dy_dt = h * ((2.0f * sk * t + d0 * (1.0f - 2.0f * t)) * den - nu * g * (1.0f - 2.0f * t)) * id2;
   const float dy_dsk = h * (t * t * den - nu * (1.0f - 2.0f * t * omt)) * id2;
-  const float dy_dh = nu / den;
+  const float dy_dh = nu * iden;
   const float dy_dd0 = h * (t * omt * den - nu * t * omt) * id2;
   const float dy_dd1 = -h * nu * t * omt * id2;
-  const float dl_dt = (2.0f * d1 * t + 2.0f * sk * (1.0f - 2.0f * t) - 2.0f * d0 * omt) / nd
-                    - 2.0f * g * (1.0f - 2.0f * t) / den;
-  const float dl_dsk = 2.0f / sk + 2.0f * t * omt / nd - 2.0f * (1.0f - 2.0f * t * omt) / den;
-  const float dl_dd0 = omt * omt / nd - 2.0f * t * omt / den;
-  const float dl_dd1 = t * t / nd - 2.0f * t * omt / den;
+  const float dl_dt = (2.0f * d1 * t + 2.0f * sk * (1.0f - 2.0f * t) - 2.0f * d0 * omt) * ind
+                    - 2.0f * g * (1.0f - 2.0f * t) * iden;
+  const float dl_dsk = 2.0f * frcp(sk) + 2.0f * t * omt * ind - 2.0f * (1.0f - 2.0f * t * omt) * iden;
+  const float dl_dd0 = omt * omt * ind - 2.0f * t * omt * iden;
+  const float dl_dd1 = t * t * ind - 2.0f * t * omt * iden;
   // combine the two outputs with their incoming gradients
   const float c_t = gy * dy_dt + gl * dl_dt, c_sk = gy * dy_dsk + gl * dl_dsk;
-  gx = c_t / w;
-  const float g_w = c_t * (-t / w) + c_sk * (-h / (w * w));
-  const float g_x0 = -c_t / w;
-  const float g_h = gy * dy_dh + c_sk / w;
+  gx = c_t * iw;
+  const float g_w = c_t * (-t * iw) + c_sk * (-h * iw * iw);
+  const float g_x0 = -c_t * iw;
+  const float g_h = gy * dy_dh + c_sk * iw;
   float gw[FK], gh[FK];
 #pragma unroll
   for (int k = 0; k < FK; ++k) {
@@ -520,7 +523,7 @@ __device__ __forceinline__ void spline_backward(const float* th, float x, float 
   for (int k = 0; k < FK; ++k) { gth[k] = cw * pw[k] * (gw[k] - aw); gth[FK + k] = cw * ph[k] * (gh[k] - ah); }
 #pragma unroll
   for (int k = 1; k < FK; ++k) {
-    const float sg = 1.0f / (1.0f + __expf(-(th[2 * FK + k - 1] + c0)));
+    const float sg = frcp(1.0f + __expf(-(th[2 * FK + k - 1] + c0)));
     const float gd = (k == kb ? gy * dy_dd0 + gl * dl_dd0 : 0.0f) + (k == kb + 1 ? gy * dy_dd1 + gl * dl_dd1 : 0.0f);
     gth[2 * FK + k - 1] = gd * sg;
   }
