@@ -37,7 +37,7 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 # peak is half the FP32 one).  Counted by paper_1407_7595_amd/opcount.py on
 # 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 2368.7 FP64 +
 # 1065.3 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
-FLOP_PER_EVAL = 2.0 * 2368.7 + 1065.3
+FLOP_PER_EVAL = 2.0 * 1283.3 + 1051.9
 
 
 def log(*a):

@@ -121,6 +121,30 @@ __device__ __forceinline__ double fast_rcp(double d)
 #endif
 }
 
+// FP64 1/sqrt(d), d > 0: hardware estimate refined by two Newton steps
+// r <- r + r (1 - d r^2) / 2.
+__device__ __forceinline__ double fast_rsqrt(double d)
+{
+#ifdef MEM_HOST_COUNT
+  return 1.0 / sqrt(d);
+#else
+  double r = __builtin_amdgcn_rsq(d);
+  double e = __fma_rn(-d * r, r, 1.0);
+  r = __fma_rn(0.5 * r, e, r);
+  e = __fma_rn(-d * r, r, 1.0);
+  return __fma_rn(0.5 * r, e, r);
+#endif
+}
+
+// Reciprocal in the matrix-element type: the hardware v_rcp_f32 (1 ulp) in
+// FP32, fast_rcp in FP64.
+#ifdef MEM_HOST_COUNT
+template <class T> inline T rcp_t(T x) { return T(1) / x; }
+#else
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return fast_rcp(x); }
+#endif
+
 // ------------------------------------------------------ four-vector math --
 struct v4 { double e, x, y, z; };
 __device__ __forceinline__ double mdot(const v4& a, const v4& b)

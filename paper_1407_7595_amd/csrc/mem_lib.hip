@@ -57,6 +57,8 @@ static TFParams tf_params(const mem_tf_desc& t)
   double smax = std::max(p.s_core, p.s_tail);
   p.r_lo = std::max(t.r_min, 1.0 - t.window * smax);
   p.r_hi = 1.0 + t.window * smax;
+  p.i_core = 1.0 / p.s_core;
+  p.i_tail = 1.0 / p.s_tail;
   return p;
 }
 
@@ -69,6 +71,7 @@ static void derive(mem_process_s* p)
   pp.precision = d.precision;
   pp.sqrt_s = d.sqrt_s;
   pp.S = d.sqrt_s * d.sqrt_s;
+  pp.inv_sqrt_s = 1.0 / d.sqrt_s;
   pp.m_t = d.m_top; pp.w_t = d.w_top; pp.m_w = d.m_w; pp.w_w = d.w_w;
   pp.alpha = d.alpha; pp.alpha_s = d.alpha_s; pp.g_fermi = d.g_fermi;
   pp.sigma_k = d.sigma_k;
@@ -795,8 +798,6 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     if (ce != hipSuccess) return fail(MEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
     HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   }
-  double n_evals = 0.0;
-  for (const auto& d : ints) n_evals += (double)d.n_points;
   auto wall0 = std::chrono::steady_clock::now();
   int used_iters = iters;
   for (int j = 0; j < iters; ++j) {
@@ -820,7 +821,6 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                      b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
                      target_mode ? o.target_rel_err : 0.0, ctl, 1, P, E, S, o.n_iter_out, b_done.as<int32_t>());
   HIP_TRY(hipGetLastError());
-  (void)used_iters;
   if (o.grid_out)
     HIP_TRY(hipMemcpyAsync(o.grid_out, b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToDevice, ws));
   if (!out_dev) {
@@ -837,9 +837,18 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       HIP_TRY(hipEventElapsedTime(&t, tev[i], tev[i + 1]));
       ms += t;
     }
+    // evaluations: each integral's points times the iterations its event
+    // ran (converged events stop; events outside the mask run none)
+    std::vector<int32_t> dn(n_ev);
+    HIP_TRY(hipMemcpy(dn.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost));
+    double n_evals = 0.0;
+    for (const auto& d : ints) {
+      if (ev_mask && !ev_mask[d.event]) continue;
+      n_evals += (double)d.n_points * (double)(dn[d.event] ? dn[d.event] : used_iters);
+    }
     o.timing_out[0] = ms;
     o.timing_out[1] = (double)(tev.size() / 2);
-    o.timing_out[2] = n_evals * used_iters;
+    o.timing_out[2] = n_evals;
     o.timing_out[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     for (int i = 4; i < 8; ++i) o.timing_out[i] = 0.0;
   }

@@ -69,6 +69,8 @@ inline CD::CD(const CF& f) : v(f.v) {}
   inline TY log(TY a) { g_t.trans[K]++; return TY(std::log(a.v)); }                              \
   inline TY tan(TY a) { g_t.trans[K]++; return TY(std::tan(a.v)); }                              \
   inline TY atan(TY a) { g_t.trans[K]++; return TY(std::atan(a.v)); }                            \
+  inline TY acos(TY a) { g_t.trans[K]++; return TY(std::acos(a.v)); }                            \
+  inline TY cbrt(TY a) { g_t.trans[K]++; return TY(std::cbrt(a.v)); }                            \
   inline TY sin(TY a) { g_t.trans[K]++; return TY(std::sin(a.v)); }                              \
   inline TY cos(TY a) { g_t.trans[K]++; return TY(std::cos(a.v)); }                              \
   inline TY pow(TY a, TY b) { g_t.trans[K]++; return TY(std::pow(a.v, b.v)); }                   \
@@ -169,8 +171,9 @@ int main(int argc, char** argv)
   ProcParams pp{};
   const double sqs = 13000.0, mt = 172.5, wt = 1.4, mw = 80.4, ww = 2.1, as = 0.118, gf = 1.1663787e-5;
   pp.kind = kTT; pp.precision = 1; pp.dims = 8; pp.n_perm = 2;
-  pp.sqrt_s = sqs; pp.S = sqs * sqs; pp.m_t = mt; pp.w_t = wt; pp.m_w = mw; pp.w_w = ww; pp.sigma_k = 20.0;
+  pp.sqrt_s = sqs; pp.S = sqs * sqs; pp.inv_sqrt_s = 1.0 / sqs; pp.m_t = mt; pp.w_t = wt; pp.m_w = mw; pp.w_w = ww; pp.sigma_k = 20.0;
   pp.tf_b.s_core = 0.15; pp.tf_b.s_tail = 0.15; pp.tf_b.f_tail = 0.0; pp.tf_b.r_lo = 0.25; pp.tf_b.r_hi = 1.75;
+  pp.tf_b.i_core = 1.0 / 0.15; pp.tf_b.i_tail = 1.0 / 0.15;
   const double S = sqs * sqs;
   pp.th0_t = std::atan(-mt * mt / (mt * wt)); pp.th1_t = std::atan((S - mt * mt) / (mt * wt));
   pp.th0_w = std::atan(-mw * mw / (mw * ww)); pp.th1_w = std::atan((S - mw * mw) / (mw * ww));

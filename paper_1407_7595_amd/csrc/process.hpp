@@ -11,6 +11,7 @@ enum Kind : int32_t { kDY = 1, kTT = 2, kSL = 3, kTTH = 4 };
 struct TFParams {
   double s_core, s_tail, f_tail;  // relative widths and tail fraction
   double r_lo, r_hi;              // integration window in r
+  double i_core, i_tail;          // 1 / s_core, 1 / s_tail
 };
 
 // Everything the integrand needs about a hypothesis, precomputed on the host.
@@ -19,7 +20,7 @@ struct ProcParams {
   int32_t precision;               // 0: FP64 matrix element stage, 1: FP32
   int32_t dims;
   int32_t n_perm;
-  double sqrt_s, S;
+  double sqrt_s, S, inv_sqrt_s;
   double m_t, w_t, m_w, w_w;
   double alpha, alpha_s, g_fermi;
   double sigma_k;

@@ -81,8 +81,8 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   const TFParams& tl = pp.tf_lj;
   // light jet a from its r
   const double ema = ev.em[0];
-  const double ra = tl.r_lo + x[0] * (tl.r_hi - tl.r_lo);
-  const v4 qa = sl_jet<0>(ev, ema / ra);
+  const double ra = tl.r_lo + x[0] * (tl.r_hi - tl.r_lo), ira = fast_rcp(ra);
+  const v4 qa = sl_jet<0>(ev, ema * ira);
   // hadronic W: q2 = 2 E_a E_b (1 - cos(a, b))
   const double mwg = pp.m_w * pp.w_w, mtg = pp.m_t * pp.w_t;
   const double q2wh = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[1] * (pp.th1_w - pp.th0_w));
@@ -104,16 +104,16 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   const v4 bh = sl_jet<2>(ev, Ebh);
   // leptonic b from its r
   const double eml = ev.em[3];
-  const double rl = tb.r_lo + x[3] * (tb.r_hi - tb.r_lo);
-  const v4 bl = sl_jet<3>(ev, eml / rl);
+  const double rl = tb.r_lo + x[3] * (tb.r_hi - tb.r_lo), irl = fast_rcp(rl);
+  const v4 bl = sl_jet<3>(ev, eml * irl);
   // solved energies must lie inside their TF windows
-  const double rb = ev.em[1] / Eb, rh = ev.em[2] / Ebh;
+  const double rb = ev.em[1] * fast_rcp(Eb), rh = ev.em[2] * fast_rcp(Ebh);
   if (rb < tl.r_lo || rb > tl.r_hi || rh < tb.r_lo || rh > tb.r_hi) return 0.0;
   // jet factors E^2 sin dE T / (2E): sin/2 tf_r(r) times dE per unit variable
-  T jetf = T(0.5 * ev.sin_th[0] * (tl.r_hi - tl.r_lo) * ema / (ra * ra)) * tf_r<T>(T(ra), tl);
+  T jetf = T(0.5 * ev.sin_th[0] * (tl.r_hi - tl.r_lo) * ema * ira * ira) * tf_r<T>(T(ra), tl);
   jetf *= T(0.5 * ev.sin_th[1] * dEb) * tf_r<T>(T(rb), tl);
   jetf *= T(0.5 * ev.sin_th[2] * dEh) * tf_r<T>(T(rh), tb);
-  jetf *= T(0.5 * ev.sin_th[3] * (tb.r_hi - tb.r_lo) * eml / (rl * rl)) * tf_r<T>(T(rl), tb);
+  jetf *= T(0.5 * ev.sin_th[3] * (tb.r_hi - tb.r_lo) * eml * irl * irl) * tf_r<T>(T(rl), tb);
   // neutrino transverse momentum from the recoil
   const double rho = pp.sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
   const double phi = 2.0 * M_PI * x[5];
@@ -128,7 +128,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   if (!(a > 0.0) || disc < 0.0 || !(lt2 > 0.0)) return 0.0;
   const double sq = l.e * sqrt(disc), ilt2 = fast_rcp(lt2);
   const T mt = T(pp.m_t);
-  const double isqs = 1.0 / pp.sqrt_s;
+  const double isqs = pp.inv_sqrt_s;
   const v4 vis = add(add(add(qa, qb), add(bh, bl)), l);
   double acc = 0.0;
   int ns = 0;
@@ -136,7 +136,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
     const double nz = (a * l.z + (s ? -sq : sq)) * ilt2;
     v4 nu{0.0, nx, ny, nz};
     nu.e = norm3(nu);
-    const double dq = fabs(2.0 * (l.e * nz / nu.e - l.z));
+    const double dq = fabs(2.0 * (l.e * nz * fast_rcp(nu.e) - l.z));
     if (!(dq > 0.0)) continue;
     ++ns;
     const v4 P = add(vis, nu);
@@ -180,10 +180,10 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
       me += g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
     }
     const double shat = x1 * x2 * pp.S;
-    acc += (P.e / Eh) * (double)me * bwtl / (shat * x1 * x2 * dq * nu.e);
+    acc += P.e * (double)me * bwtl * fast_rcp(Eh * shat * x1 * x2 * dq * nu.e);
   }
   if (nsol_out) *nsol_out = ns;
-  return acc * pp.sl_const * (double)jetf / (2.0 * l.e);
+  return acc * pp.sl_const * (double)jetf * fast_rcp(2.0 * l.e);
 }
 
 }  // namespace memk

@@ -51,12 +51,12 @@ template <class T>
 __device__ __forceinline__ T tf_r(T r, const TFParams& tf)
 {
   const T inv_sqrt_2pi = T(0.39894228040143267794);
-  T d = r - T(1);
-  T sc = T(tf.s_core);
-  T g = exp(T(-0.5) * d * d / (sc * sc)) / sc;
+  const T d = r - T(1);
+  const T ic = T(tf.i_core), dc = d * ic;
+  T g = exp(T(-0.5) * dc * dc) * ic;
   if (tf.f_tail > 0.0) {
-    T st = T(tf.s_tail), f = T(tf.f_tail);
-    g = (T(1) - f) * g + f * exp(T(-0.5) * d * d / (st * st)) / st;
+    const T it = T(tf.i_tail), f = T(tf.f_tail), dt = d * it;
+    g = (T(1) - f) * g + f * exp(T(-0.5) * dt * dt) * it;
   }
   return inv_sqrt_2pi * g;
 }
@@ -66,10 +66,11 @@ struct TBoost {
   double bx, by, g, g2;
   __device__ __forceinline__ TBoost(const v4& P)
   {
-    bx = P.x / P.e; by = P.y / P.e;
-    double b2 = bx * bx + by * by;
-    g = 1.0 / sqrt(1.0 - b2);
-    g2 = b2 > 0.0 ? (g - 1.0) / b2 : 0.0;
+    const double ie = fast_rcp(P.e);
+    bx = P.x * ie; by = P.y * ie;
+    const double b2 = bx * bx + by * by;
+    g = fast_rsqrt(1.0 - b2);
+    g2 = g * g * fast_rcp(g + 1.0);     // (g - 1) / b2 without the cancellation
   }
   template <class T>
   __device__ __forceinline__ mom<T> apply(const v4& v) const
@@ -94,11 +95,11 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
   T jetf = T(1);
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    double r = tf.r_lo + x[k] * (tf.r_hi - tf.r_lo);
-    double E = ev.em[k] / r;
+    const double r = tf.r_lo + x[k] * (tf.r_hi - tf.r_lo), ir = fast_rcp(r);
+    const double E = ev.em[k] * ir;
     bq[k] = v4{E, E * ev.n[k][0], E * ev.n[k][1], E * ev.n[k][2]};
     // E^2 sin dE T / (2E): the true energy cancels against the TF
-    jetf *= T(ev.sin_th[k] * (tf.r_hi - tf.r_lo) * ev.em[k] / (r * r) * 0.5) * tf_r<T>(T(r), tf);
+    jetf *= T(ev.sin_th[k] * (tf.r_hi - tf.r_lo) * E * ir * 0.5) * tf_r<T>(T(r), tf);
   }
   const double mtg = pp.m_t * pp.w_t, mwg = pp.m_w * pp.w_w;
   const double q2t = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
@@ -117,7 +118,7 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
 
   // matrix element stage: only the solutions are live here
   const T mt = T(pp.m_t);
-  const double isqs = 1.0 / pp.sqrt_s;
+  const double isqs = pp.inv_sqrt_s;
   double acc = 0.0;
   for (int k = 0; k < ns; ++k) {
     const NuSol sk = sols.get(k);
@@ -147,7 +148,7 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
     T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
     T me = g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
     double shat = x1 * x2 * pp.S;
-    acc += (P.e / Eh) * (double)me / (shat * x1 * x2 * sk.adet * nu.e * nb.e);
+    acc += P.e * (double)me * fast_rcp(Eh * shat * x1 * x2 * sk.adet * nu.e * nb.e);
   }
   if (nsol_out) *nsol_out = ns;
   return acc * pp.tt_const * ev.lep_fac * (double)jetf;

@@ -47,11 +47,11 @@ __device__ __forceinline__ sp<T> lam(const v4& p)
 {
   if (p.z >= 0.0) {
     double ep = p.e + p.z;
-    double n = 1.0 / sqrt(ep);
+    const double n = fast_rsqrt(ep);
     return sp<T>{{T(-p.x * n), T(p.y * n)}, {T(ep * n), T(0)}};
   }
   double em = p.e - p.z;
-  double n = 1.0 / sqrt(em);
+  const double n = fast_rsqrt(em);
   return sp<T>{{T(em * n), T(0)}, {T(-p.x * n), T(-p.y * n)}};
 }
 // lambda-tilde(p): (p.sigma) lt = 0 (right-handed), |lt|^2 = 2E
@@ -60,11 +60,11 @@ __device__ __forceinline__ sp<T> lamt(const v4& p)
 {
   if (p.z >= 0.0) {
     double ep = p.e + p.z;
-    double n = 1.0 / sqrt(ep);
+    const double n = fast_rsqrt(ep);
     return sp<T>{{T(ep * n), T(0)}, {T(p.x * n), T(p.y * n)}};
   }
   double em = p.e - p.z;
-  double n = 1.0 / sqrt(em);
+  const double n = fast_rsqrt(em);
   return sp<T>{{T(p.x * n), T(-p.y * n)}, {T(em * n), T(0)}};
 }
 // eps^T v with eps = [[0,1],[-1,0]]: (-v_b, v_a)
@@ -159,13 +159,13 @@ __device__ __forceinline__ T gg_sum(const drow<T>& R, const drow<T>& C, const mo
   T mt2 = mt * mt;
   T Dt = (q1.e * q1.e - q1.x * q1.x - q1.y * q1.y - q1.z * q1.z) - mt2;
   T Du = (q2.e * q2.e - q2.x * q2.x - q2.y * q2.y - q2.z * q2.z) - mt2;
-  T iDt = T(1) / Dt, iDu = T(1) / Du;
+  const T iDt = rcp_t(Dt), iDu = rcp_t(Du);
   T s = T(4) * a * bm;
   // R (k1-k2)-slash C = R_L (K.sigma) C_R + R_R (K.sigma-bar) C_L,
   // K.sigma = diag(-2bm, 2a), K.sigma-bar = diag(2a, -2bm)
   cx<T> rkc = (T(-2) * bm) * (R.L.a * C.R.a) + (T(2) * a) * (R.L.b * C.R.b)
             + (T(2) * a) * (R.R.a * C.L.a) + (T(-2) * bm) * (R.R.b * C.L.b);
-  cx<T> sch = (T(1) / s) * rkc;
+  cx<T> sch = rcp_t(s) * rkc;
   T sum = T(0);
 #pragma unroll
   for (int h1 = 0; h1 < 2; ++h1)
@@ -194,7 +194,7 @@ __device__ __forceinline__ T qq_sum(const drow<T>& R, const drow<T>& C, const v4
   // R J-slash C = R_L (J.sigma) C_R + R_R (J.sigma-bar) C_L
   sp<T> lq = lam<T>(kq), lqb = lam<T>(kqb), tq = lamt<T>(kq), tqb = lamt<T>(kqb);
   double s = 2.0 * mdot(kq, kqb);
-  T is = T(1.0 / s);
+  T is = T(fast_rcp(s));
   // left
   sp<T> e1 = epsT(cj(lqb)), e2 = epsT(lq);      // J.sigma-bar = 2 e1 e2^T
   cx<T> aL = T(2) * (dot2(R.L, lq) * dot2(cj(lqb), C.R)) + T(2) * (dot2(R.R, e1) * dot2(e2, C.L));
@@ -266,15 +266,15 @@ __device__ __forceinline__ T gg_tth_sum(const drow<T>& R, const drow<T>& C, cons
   const v4 q1{pt.e - a, pt.x, pt.y, pt.z - a}, q2{pt.e - bm, pt.x, pt.y, pt.z + bm};   // pt - k_i
   const v4 q1h = add(q1, ph), q2h = add(q2, ph);                  // pt - k_i + ph
   auto to = [](const v4& v) { return mom<T>{T(v.e), T(v.x), T(v.y), T(v.z)}; };
-  const T iDa = T(1.0 / (mdot(qa, qa) - m2)), iDc = T(1.0 / (mdot(qc, qc) - m2));
-  const T iD1 = T(1.0 / (mdot(q1, q1) - m2)), iD2 = T(1.0 / (mdot(q2, q2) - m2));
-  const T iD1h = T(1.0 / (mdot(q1h, q1h) - m2)), iD2h = T(1.0 / (mdot(q2h, q2h) - m2));
+  const T iDa = T(fast_rcp(mdot(qa, qa) - m2)), iDc = T(fast_rcp(mdot(qc, qc) - m2));
+  const T iD1 = T(fast_rcp(mdot(q1, q1) - m2)), iD2 = T(fast_rcp(mdot(q2, q2) - m2));
+  const T iD1h = T(fast_rcp(mdot(q1h, q1h) - m2)), iD2h = T(fast_rcp(mdot(q2h, q2h) - m2));
   const T s = T(4.0 * a * bm);
   const T ta = T(a), tbm = T(bm);
   const mom<T> qaT = to(qa), qcT = to(qc), q1T = to(q1), q2T = to(q2), q1hT = to(q1h), q2hT = to(q2h);
   const drow<T> Sa = row_scale(row_prop(R, qaT, mt), iDa);     // R S(pt + ph)
   // s-channel current with the Higgs on either side of it
-  const cx<T> sch = (T(1) / s) * (row_col(row_kslash(Sa, ta, tbm), C)
+  const cx<T> sch = rcp_t(s) * (row_col(row_kslash(Sa, ta, tbm), C)
                                  + iDc * row_col(row_prop(row_kslash(R, ta, tbm), qcT, mt), C));
   T sum = T(0);
 #pragma unroll

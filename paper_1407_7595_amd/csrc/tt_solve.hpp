@@ -11,6 +11,15 @@
 // the second derivative) and refined by bracketed Newton; each candidate is
 // polished by two Newton steps on the full 4x4 system.  Everything runs in
 // FP64: the coefficients cancel strongly (Sec. 4).
+//
+// The root finder runs in lockstep across a wavefront, so its cost is the
+// slowest lane's iteration count.  Two things keep that short: every
+// bracketed search starts from a model estimate (the closed-form cubic for
+// the critical points, the local quadratic at a critical point for the
+// quartic roots), and it stops as soon as the residual is within the
+// rounding error of its own evaluation instead of waiting for the step to
+// vanish, which near a root with condition number above a few never
+// happens and left the search bisecting to the last bit.
 #pragma once
 #include "device_common.hpp"
 
@@ -34,16 +43,25 @@ __device__ __forceinline__ void horner_d(const double (&c)[N + 1], double t, dou
   for (int i = N - 1; i >= 0; --i) { df = __fma_rn(df, t, f); f = __fma_rn(f, t, c[i]); }
 }
 
-// Root of a polynomial that is monotone on [lo, hi] with a sign change:
-// Newton steps, falling back to bisection whenever a step leaves the bracket.
+// Root of a polynomial that is monotone on [lo, hi] with a sign change,
+// starting at x0 (the midpoint when x0 is not inside): Newton steps, with
+// bisection whenever a step leaves the bracket.  Stops when |p(x)| is at
+// most 1e-15 sum |c_i| |x|^i (x is then the exact root of a polynomial
+// whose coefficients differ from c by ~1e-15 relative; the degree-4 Horner
+// rounding bound is 8 u = 8.9e-16) or when the step vanishes.
 template <int N>
-__device__ __forceinline__ double bracketed_root(const double (&c)[N + 1], double lo, double hi, double flo)
+__device__ __forceinline__ double bracketed_root(const double (&c)[N + 1], double lo, double hi, double flo,
+                                                 double x0)
 {
-  double x = 0.5 * (lo + hi);
+  double x = (x0 > lo && x0 < hi) ? x0 : 0.5 * (lo + hi);
   for (int it = 0; it < 80; ++it) {
     double f, df;
     horner_d<N>(c, x, f, df);
-    if (f == 0.0) return x;
+    const double ax = fabs(x);
+    double fa = fabs(c[N]);
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) fa = __fma_rn(fa, ax, fabs(c[i]));
+    if (fabs(f) <= 1e-15 * fa) return x;
     if ((f < 0.0) == (flo < 0.0)) lo = x; else hi = x;
     double xn = x - f * fast_rcp(df);
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
@@ -70,9 +88,11 @@ struct Four {
 };
 
 // Roots of a polynomial in each of `NI` consecutive intervals of pts
-// (monotone on each), appended ascending to out.
-template <int N, int NI>
-__device__ __forceinline__ void roots_on_intervals(const double (&c)[N + 1], const double (&pts)[NI + 1], Four& out)
+// (monotone on each), appended ascending to out; guess(i, lo, hi, flo, fhi)
+// gives the starting point in interval i.
+template <int N, int NI, class Guess>
+__device__ __forceinline__ void roots_on_intervals(const double (&c)[N + 1], const double (&pts)[NI + 1], Four& out,
+                                                   Guess guess)
 {
   double fprev = horner<N>(c, pts[0]);
 #pragma unroll
@@ -81,9 +101,33 @@ __device__ __forceinline__ void roots_on_intervals(const double (&c)[N + 1], con
     const double fnext = horner<N>(c, hi);
     if (hi > lo) {
       if (fprev == 0.0) out.put(lo);
-      else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0) out.put(bracketed_root<N>(c, lo, hi, fprev));
+      else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0)
+        out.put(bracketed_root<N>(c, lo, hi, fprev, guess(i, lo, hi, fprev, fnext)));
     }
     fprev = fnext;
+  }
+}
+
+// Real roots of the monic cubic t^3 + A t^2 + B t + C in closed form
+// (trigonometric form for three real roots, Cardano's with the
+// non-cancelling cube root otherwise; the single root is repeated).  Used
+// only as starting points: accuracy is lost near a double root.
+__device__ __forceinline__ void cubic_estimates(double A, double B, double C, double (&r)[3])
+{
+  const double a3 = A * (1.0 / 3.0);
+  const double p = B - A * a3, q = C + a3 * (2.0 * a3 * a3 - B);
+  const double D = 0.25 * q * q + p * p * p * (1.0 / 27.0);
+  if (D <= 0.0 && p < 0.0) {
+    const double m = sqrt(-p * (1.0 / 3.0));
+    const double cphi = fmin(1.0, fmax(-1.0, -0.5 * q * fast_rcp(m * m * m)));
+    double st, ct;
+    sincos(acos(cphi) * (1.0 / 3.0), &st, &ct);
+    r[0] = 2.0 * m * ct - a3;
+    r[1] = m * (-ct + 1.7320508075688772 * st) - a3;
+    r[2] = m * (-ct - 1.7320508075688772 * st) - a3;
+  } else {
+    const double u = cbrt(-0.5 * q - copysign(sqrt(fmax(D, 0.0)), q));
+    r[0] = r[1] = r[2] = (u != 0.0 ? u - p * fast_rcp(3.0 * u) : 0.0) - a3;
   }
 }
 
@@ -108,16 +152,29 @@ __device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four
     s0 = fmin(fmax(fmin(a, b), -bound), bound);
     s1 = fmin(fmax(fmax(a, b), -bound), bound);
   }
-  // the first derivative is monotone between consecutive points
+  // the first derivative is monotone between consecutive points; its roots
+  // start from the closed form (the estimate that falls inside)
+  double est[3];
+  cubic_estimates(0.75 * c[3], 0.5 * c[2], 0.25 * c[1], est);
   Four crit;
   crit.n = 0;
   const double p3[4] = {-bound, s0, s1, bound};
-  roots_on_intervals<3, 3>(d1, p3, crit);
-  // the quartic is monotone between consecutive critical points
+  roots_on_intervals<3, 3>(d1, p3, crit, [&](int, double lo, double hi, double, double) {
+    return (est[0] > lo && est[0] < hi) ? est[0] : (est[1] > lo && est[1] < hi) ? est[1] : est[2];
+  });
+  // the quartic is monotone between consecutive critical points; a root
+  // starts from the quadratic model p(e) + p''(e) d^2 / 2 at the critical
+  // end e with the smaller |p| (interior intervals have two)
   const double p4[5] = {-bound, crit.n > 0 ? crit.v0 : bound, crit.n > 1 ? crit.v1 : bound,
                         crit.n > 2 ? crit.v2 : bound, bound};
   roots.n = 0;
-  roots_on_intervals<4, 4>(c, p4, roots);
+  roots_on_intervals<4, 4>(c, p4, roots, [&](int i, double lo, double hi, double flo, double fhi) {
+    const bool lo_crit = i > 0, hi_crit = hi < bound;
+    const bool use_lo = lo_crit && (!hi_crit || fabs(flo) <= fabs(fhi));
+    const double e = use_lo ? lo : hi, fe = use_lo ? flo : fhi;
+    const double d = sqrt(fabs(2.0 * fe * fast_rcp(horner<2>(d2, e))));
+    return use_lo ? lo + d : hi - d;
+  });
 }
 
 // Neutrino energy and p_z as affine functions of (p_x, p_y) from
@@ -130,7 +187,7 @@ __device__ __forceinline__ bool nu_affine(const v4& b, const v4& l, double q2w, 
   double h2 = 0.5 * (q2t - q2w) - mdot(b, l);
   double det = l.z * b.e - l.e * b.z;
   if (det == 0.0) return false;
-  double id = 1.0 / det;
+  const double id = fast_rcp(det);
   a.e0 = (l.z * h2 - b.z * h1) * id;
   a.e1 = (l.z * b.x - b.z * l.x) * id;
   a.e2 = (l.z * b.y - b.z * l.y) * id;

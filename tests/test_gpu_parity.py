@@ -96,6 +96,7 @@ def test_dy_integrand_fp64(mem):
         mem.eval_points(p, comps, e, 0, dev(x), f)
         torch.cuda.synchronize()
         got = f.cpu().numpy()
+        assert np.all(np.isfinite(got))
         want = np.array([oracle.dy_integrand(po, d["obs"][e], xi) for xi in x])
         assert np.sum(want > 0) > 50
         assert np.allclose(got, want, rtol=1e-11, atol=0), np.max(np.abs(got - want) / np.maximum(want, 1e-300))
@@ -149,6 +150,7 @@ def test_tt_integrand(mem, precision, tol):
             mem.eval_points(p, comps, e, perm, dev(x), f, ns)
             torch.cuda.synchronize()
             got = f.cpu().numpy()
+            assert np.all(np.isfinite(got)), (e, perm)
             gns = ns.cpu().numpy()
             for k, xi in enumerate(x):
                 want, wns = oracle.tt_integrand(po, d["obs"][e], perm, xi)
@@ -339,6 +341,7 @@ def test_sl_integrand(mem, precision, tol):
             mem.eval_points(p, comps, e, perm, dev(x), f, ns, charge=charge)
             torch.cuda.synchronize()
             got, gns = f.cpu().numpy(), ns.cpu().numpy()
+            assert np.all(np.isfinite(got)), (e, perm)
             for k, xi in enumerate(x):
                 want, wns = oracle.sl_integrand(po, d["obs"][e], perm, xi)
                 if want == 0.0 and got[k] == 0.0:

@@ -76,6 +76,7 @@ def test_tth_integrand(mem, precision, tol):
             mem.eval_points(p, comps, e, perm, dev(x), f, ns, charge=charge)
             torch.cuda.synchronize()
             got, gns = f.cpu().numpy(), ns.cpu().numpy()
+            assert np.all(np.isfinite(got)), (e, perm)
             for k, xi in enumerate(x):
                 want, wns = oracle.tth_integrand(po, d["obs"][e], perm, xi)
                 if want == 0.0 and got[k] == 0.0:
