@@ -103,6 +103,16 @@ __device__ __forceinline__ double wave_scan(double v)
   return v;
 }
 
+// Orders the LDS accesses of the lanes of one wavefront around this point
+// (a wavefront-scope fence pair around a code-motion barrier; no block
+// barrier, so wavefronts of a block may run different trip counts).
+__device__ __forceinline__ void wave_sync()
+{
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 #endif  // MEM_HOST_COUNT
 
 // FP64 reciprocal: hardware estimate refined by two Newton steps (full

@@ -103,6 +103,82 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
   }
 }
 
+// Dilepton chunk with the neutrino solutions of each wavefront compacted
+// before the matrix element stage.  Every lane solves its point (0 to 4
+// solutions); the wavefront packs all its solutions into an LDS queue
+// (exclusive prefix sum of the counts from three ballots); every lane then
+// evaluates queue entries lane, lane + 64, ... and each point sums its own
+// entries in order.  The matrix element runs ceil(total / 64) times per
+// wavefront instead of max(solutions) times, and every value equals
+// tt_integrand's bit for bit (same functions, same summation order).  ON =
+// false compiles to nothing (no LDS) for launches without dilepton chunks.
+constexpr int kTTQFields = 9;    // nx ny nz bx by bz |det J| E0 E1
+template <class T, bool ON>
+__device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
+                                                double* sbins, double& s1, double& s2, const ProcParams& pp,
+                                                const TTEvent& ev)
+{
+  if constexpr (ON) {
+    __shared__ double squeue[kBlock / kWave][kTTQFields][4 * kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    double (*q)[4 * kWave] = squeue[threadIdx.x / kWave];
+    const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;     // lanes below this one
+    // wave-uniform trip count: lanes past the chunk's end idle
+    for (int kb = threadIdx.x - lane; kb < ch.count; kb += kBlock) {
+      const int k = kb + lane;
+      const bool live = k < ch.count;
+      TTFront<T> f;
+      f.E0 = f.E1 = 0.0;
+      f.jetf = T(0);
+      f.sols.n = 0;
+      double jac = 0.0;
+      int bin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (live) {
+        double u[8], x[8];
+        point_uniforms<8>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
+        jac = vegas_map<8>(sgrid, u, x, bin);
+        tt_front<T>(pp, ev, x, f);
+      }
+      const int ns = f.sols.n;
+      int off = 0, total = 0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const uint64_t m = __ballot((ns >> b) & 1);
+        off += __popcll(m & lt) << b;
+        total += __popcll(m) << b;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < ns) {
+          const NuSol s = f.sols.get(j);
+          const int i = off + j;
+          q[0][i] = s.nx; q[1][i] = s.ny; q[2][i] = s.nz;
+          q[3][i] = s.bx; q[4][i] = s.by; q[5][i] = s.bz;
+          q[6][i] = s.adet; q[7][i] = f.E0; q[8][i] = f.E1;
+        }
+      }
+      wave_sync();
+      for (int i = lane; i < total; i += kWave) {
+        const NuSol s{q[0][i], q[1][i], q[2][i], q[3][i], q[4][i], q[5][i], q[6][i]};
+        q[0][i] = tt_solution<T>(pp, ev, q[7][i], q[8][i], s);
+      }
+      wave_sync();
+      double acc = 0.0;
+      for (int j = 0; j < ns; ++j) acc += q[0][off + j];
+      wave_sync();     // the next round overwrites the queue
+      if (live) {
+        const double w = tt_point<T>(pp, ev, acc, f.jetf) * jac;
+        s1 += w;
+        s2 += w * w;
+        if (w != 0.0) {
+#pragma unroll
+          for (int d = 0; d < 8; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
+        }
+      }
+    }
+  }
+}
+
 // Persistent work-queue kernel: every workgroup loops until the shared head
 // passes n_chunks (each iteration of the loop reads the head once, so every
 // workgroup reaches the exit).  KINDS is the set of process kinds compiled
@@ -155,8 +231,13 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
     } else if ((KINDS & kMaskTT) && pp.kind == kTT) {
       TTEvent e;
       tt_load(ev, ch.event, ch.perm, e);
-      chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
-                      [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
+      // launches that also carry t tbar H chunks run at two waves per SIMD,
+      // where the 72 KB queue would not fit twice: per-lane solution loop
+      if constexpr ((KINDS & kMaskTTH) == 0)
+        chunk_points_tt<T, (KINDS & kMaskTT) != 0>(ch, seed, iter, sgrid, wbins, s1, s2, pp, e);
+      else
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+                        [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskSL) && pp.kind == kSL) {
       SLEvent e;
       sl_load(ev, ev.charge, ch.event, ch.perm, e);

@@ -86,9 +86,19 @@ struct TBoost {
   }
 };
 
+// The integrand in two stages.  tt_front: per point, the jet energies,
+// TFs, virtualities, recoil and the neutrino solve; tt_solution: per
+// neutrino solution, the boost, |M|^2, PDFs and the weight.  The solutions
+// of a point are summed in order, then times the point factors.
 template <class T>
-__device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEvent& ev, const double (&x)[8],
-                                               int* nsol_out)
+struct TTFront {
+  double E0, E1;     // parton energies of the two jets
+  T jetf;            // jet factors (TF, phase-space density)
+  NuSet sols;
+};
+
+template <class T>
+__device__ __forceinline__ void tt_front(const ProcParams& pp, const TTEvent& ev, const double (&x)[8], TTFront<T>& f)
 {
   const TFParams& tf = pp.tf_b;
   v4 bq[2];
@@ -101,6 +111,9 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
     // E^2 sin dE T / (2E): the true energy cancels against the TF
     jetf *= T(ev.sin_th[k] * (tf.r_hi - tf.r_lo) * E * ir * 0.5) * tf_r<T>(T(r), tf);
   }
+  f.E0 = bq[0].e;
+  f.E1 = bq[1].e;
+  f.jetf = jetf;
   const double mtg = pp.m_t * pp.w_t, mwg = pp.m_w * pp.w_w;
   const double q2t = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
   const double q2tb = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[3] * (pp.th1_t - pp.th0_t));
@@ -111,47 +124,65 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
   const double sphi = sin(phi), cphi = cos(phi);
   const double metx = rho * cphi - (bq[0].x + bq[1].x + ev.lp.x + ev.lm.x);
   const double mety = rho * sphi - (bq[0].y + bq[1].y + ev.lp.y + ev.lm.y);
+  solve_dilepton(bq[0], bq[1], ev.lp, ev.lm, metx, mety, q2wp, q2t, q2wm, q2tb, f.sols);
+}
 
-  NuSet sols;
-  solve_dilepton(bq[0], bq[1], ev.lp, ev.lm, metx, mety, q2wp, q2t, q2wm, q2tb, sols);
-  const int ns = sols.n;
-
-  // matrix element stage: only the solutions are live here
+// Weight of one neutrino solution sk of a point whose jets have parton
+// energies E0, E1 (0 when x1 or x2 falls outside (0, 1]).
+template <class T>
+__device__ __forceinline__ double tt_solution(const ProcParams& pp, const TTEvent& ev, double E0, double E1,
+                                              const NuSol& sk)
+{
+  const v4 b0{E0, E0 * ev.n[0][0], E0 * ev.n[0][1], E0 * ev.n[0][2]};
+  const v4 b1{E1, E1 * ev.n[1][0], E1 * ev.n[1][1], E1 * ev.n[1][2]};
+  v4 nu{0.0, sk.nx, sk.ny, sk.nz}, nb{0.0, sk.bx, sk.by, sk.bz};
+  nu.e = norm3(nu);
+  nb.e = norm3(nb);
+  const v4 P = add(add(add(b0, b1), add(ev.lp, ev.lm)), add(nu, nb));
+  const double Eh = sqrt(P.e * P.e - P.x * P.x - P.y * P.y);
+  const double x1 = (Eh + P.z) * pp.inv_sqrt_s, x2 = (Eh - P.z) * pp.inv_sqrt_s;
+  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
   const T mt = T(pp.m_t);
-  const double isqs = pp.inv_sqrt_s;
-  double acc = 0.0;
-  for (int k = 0; k < ns; ++k) {
-    const NuSol sk = sols.get(k);
-    v4 nu{0.0, sk.nx, sk.ny, sk.nz}, nb{0.0, sk.bx, sk.by, sk.bz};
-    nu.e = norm3(nu);
-    nb.e = norm3(nb);
-    v4 P = add(add(add(bq[0], bq[1]), add(ev.lp, ev.lm)), add(nu, nb));
-    double Eh = sqrt(P.e * P.e - P.x * P.x - P.y * P.y);
-    double x1 = (Eh + P.z) * isqs, x2 = (Eh - P.z) * isqs;
-    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
-    TBoost B(P);
-    v4 hb = B.apply64(bq[0]), hl = B.apply64(ev.lp), hn = B.apply64(nu);
-    v4 hbb = B.apply64(bq[1]), hlm = B.apply64(ev.lm), hnb = B.apply64(nb);
-    v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
-    mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
-    drow<T> R, C;
-    decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
-    double a = 0.5 * x1 * pp.sqrt_s, bm = 0.5 * x2 * pp.sqrt_s;
-    T mgg = gg_sum<T>(R, C, pt, T(a), T(bm), mt);
-    v4 k1{a, 0.0, 0.0, a}, k2{bm, 0.0, 0.0, -bm};
-    T mq1 = qq_sum<T>(R, C, k1, k2);
-    T mq2 = qq_sum<T>(R, C, k2, k1);
-    // toy densities x f(x) (configuration) and x g(x) = 3 (1-x)^5
-    double o1 = 1.0 - x1, o2 = 1.0 - x2;
-    T g1 = T(3.0 * o1 * o1 * o1 * o1 * o1), g2 = T(3.0 * o2 * o2 * o2 * o2 * o2);
-    T q1 = T(xfu(x1, o1) + xfd(x1, o1)), q2 = T(xfu(x2, o2) + xfd(x2, o2));
-    T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
-    T me = g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
-    double shat = x1 * x2 * pp.S;
-    acc += P.e * (double)me * fast_rcp(Eh * shat * x1 * x2 * sk.adet * nu.e * nb.e);
-  }
-  if (nsol_out) *nsol_out = ns;
+  TBoost B(P);
+  const v4 hb = B.apply64(b0), hl = B.apply64(ev.lp), hn = B.apply64(nu);
+  const v4 hbb = B.apply64(b1), hlm = B.apply64(ev.lm), hnb = B.apply64(nb);
+  const v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
+  const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
+  drow<T> R, C;
+  decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
+  const double a = 0.5 * x1 * pp.sqrt_s, bm = 0.5 * x2 * pp.sqrt_s;
+  const T mgg = gg_sum<T>(R, C, pt, T(a), T(bm), mt);
+  const v4 k1{a, 0.0, 0.0, a}, k2{bm, 0.0, 0.0, -bm};
+  const T mq1 = qq_sum<T>(R, C, k1, k2);
+  const T mq2 = qq_sum<T>(R, C, k2, k1);
+  // toy densities x f(x) (configuration) and x g(x) = 3 (1-x)^5
+  const double o1 = 1.0 - x1, o2 = 1.0 - x2;
+  const T g1 = T(3.0 * o1 * o1 * o1 * o1 * o1), g2 = T(3.0 * o2 * o2 * o2 * o2 * o2);
+  const T q1 = T(xfu(x1, o1) + xfd(x1, o1)), q2 = T(xfu(x2, o2) + xfd(x2, o2));
+  const T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
+  const T me = g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
+  const double shat = x1 * x2 * pp.S;
+  return P.e * (double)me * fast_rcp(Eh * shat * x1 * x2 * sk.adet * nu.e * nb.e);
+}
+
+// The point's value from the sum of its solution weights.
+template <class T>
+__device__ __forceinline__ double tt_point(const ProcParams& pp, const TTEvent& ev, double acc, T jetf)
+{
   return acc * pp.tt_const * ev.lep_fac * (double)jetf;
+}
+
+template <class T>
+__device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEvent& ev, const double (&x)[8],
+                                               int* nsol_out)
+{
+  TTFront<T> f;
+  tt_front<T>(pp, ev, x, f);
+  const int ns = f.sols.n;
+  double acc = 0.0;
+  for (int k = 0; k < ns; ++k) acc += tt_solution<T>(pp, ev, f.E0, f.E1, f.sols.get(k));
+  if (nsol_out) *nsol_out = ns;
+  return tt_point<T>(pp, ev, acc, f.jetf);
 }
 
 }  // namespace memk
