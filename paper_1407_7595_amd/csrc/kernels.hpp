@@ -103,71 +103,102 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
   }
 }
 
-// Dilepton chunk with the neutrino solutions of each wavefront compacted
-// before the matrix element stage.  Every lane solves its point (0 to 4
-// solutions); the wavefront packs all its solutions into an LDS queue
-// (exclusive prefix sum of the counts from three ballots); every lane then
-// evaluates queue entries lane, lane + 64, ... and each point sums its own
-// entries in order.  The matrix element runs ceil(total / 64) times per
-// wavefront instead of max(solutions) times, and every value equals
-// tt_integrand's bit for bit (same functions, same summation order).  ON =
-// false compiles to nothing (no LDS) for launches without dilepton chunks.
-constexpr int kTTQFields = 9;    // nx ny nz bx by bz |det J| E0 E1
+// Dilepton chunk with the real roots of each wavefront compacted before
+// the per-root work.  Every lane maps its point and forms the resultant
+// quartic and its real roots (0 to 4); the lane's solve state goes to an
+// LDS record and its roots to an LDS queue (exclusive prefix sum of the
+// counts from three ballots).  Every lane then takes queue entries lane,
+// lane + 64, ...: it rebuilds the owner's geometry from the record, polishes
+// and tests the root (dilep_accept) and evaluates the matrix element stage
+// (tt_solution); each point sums its own entries in root order.  The
+// per-root work runs ceil(total / 64) times per wavefront instead of
+// max(roots) times, and every value equals tt_integrand's bit for bit (same
+// functions, same order; a rejected root adds +0).  ON = false compiles to
+// nothing (no LDS) for launches without dilepton chunks.
+constexpr int kTTRec = 30;       // DilepPoint (28 doubles) + the two jet energies
 template <class T, bool ON>
 __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
                                                 double* sbins, double& s1, double& s2, const ProcParams& pp,
                                                 const TTEvent& ev)
 {
   if constexpr (ON) {
-    __shared__ double squeue[kBlock / kWave][kTTQFields][4 * kWave];
-    const int lane = threadIdx.x & (kWave - 1);
-    double (*q)[4 * kWave] = squeue[threadIdx.x / kWave];
+    __shared__ double srec[kBlock / kWave][kTTRec][kWave];
+    __shared__ double spx[kBlock / kWave][4 * kWave];
+    __shared__ double sres[kBlock / kWave][4 * kWave];
+    __shared__ int sown[kBlock / kWave][4 * kWave];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    double (*rec)[kWave] = srec[wv];
+    double* qpx = spx[wv];
+    double* qres = sres[wv];
+    int* qown = sown[wv];
     const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;     // lanes below this one
     // wave-uniform trip count: lanes past the chunk's end idle
     for (int kb = threadIdx.x - lane; kb < ch.count; kb += kBlock) {
       const int k = kb + lane;
       const bool live = k < ch.count;
-      TTFront<T> f;
-      f.E0 = f.E1 = 0.0;
-      f.jetf = T(0);
-      f.sols.n = 0;
+      TTMaps<T> m;
+      m.jetf = T(0);
+      m.bq[0].e = m.bq[1].e = 0.0;
+      DilepPoint s;
+      Four roots;
+      roots.n = 0;
       double jac = 0.0;
       int bin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (live) {
         double u[8], x[8];
         point_uniforms<8>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
         jac = vegas_map<8>(sgrid, u, x, bin);
-        tt_front<T>(pp, ev, x, f);
+        tt_maps<T>(pp, ev, x, m);
+        double quart[5];
+        if (dilep_prepare(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, s, quart))
+          quartic_real_roots(quart, roots);
       }
-      const int ns = f.sols.n;
+      const int nr = roots.n;
       int off = 0, total = 0;
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const uint64_t m = __ballot((ns >> b) & 1);
-        off += __popcll(m & lt) << b;
-        total += __popcll(m) << b;
+        const uint64_t msk = __ballot((nr >> b) & 1);
+        off += __popcll(msk & lt) << b;
+        total += __popcll(msk) << b;
       }
+      if (nr > 0) {
+        const double r[kTTRec] = {s.A1.e0, s.A1.e1, s.A1.e2, s.A1.z0, s.A1.z1, s.A1.z2,
+                                  s.A2.e0, s.A2.e1, s.A2.e2, s.A2.z0, s.A2.z1, s.A2.z2,
+                                  s.P0, s.P1, s.P2, s.Q0, s.Q1,
+                                  s.tq[0], s.tq[1], s.tq[2], s.tq[3], s.itq[0], s.itq[1], s.itq[2], s.itq[3],
+                                  s.lam, s.mx, s.my, m.bq[0].e, m.bq[1].e};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j < ns) {
-          const NuSol s = f.sols.get(j);
-          const int i = off + j;
-          q[0][i] = s.nx; q[1][i] = s.ny; q[2][i] = s.nz;
-          q[3][i] = s.bx; q[4][i] = s.by; q[5][i] = s.bz;
-          q[6][i] = s.adet; q[7][i] = f.E0; q[8][i] = f.E1;
+        for (int f = 0; f < kTTRec; ++f) rec[f][lane] = r[f];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j < nr) {
+            qpx[off + j] = roots.get(j);
+            qown[off + j] = lane;
+          }
         }
       }
       wave_sync();
       for (int i = lane; i < total; i += kWave) {
-        const NuSol s{q[0][i], q[1][i], q[2][i], q[3][i], q[4][i], q[5][i], q[6][i]};
-        q[0][i] = tt_solution<T>(pp, ev, q[7][i], q[8][i], s);
+        const int o = qown[i];
+        DilepPoint t;
+        t.A1 = Affine{rec[0][o], rec[1][o], rec[2][o], rec[3][o], rec[4][o], rec[5][o]};
+        t.A2 = Affine{rec[6][o], rec[7][o], rec[8][o], rec[9][o], rec[10][o], rec[11][o]};
+        t.P0 = rec[12][o]; t.P1 = rec[13][o]; t.P2 = rec[14][o]; t.Q0 = rec[15][o]; t.Q1 = rec[16][o];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { t.tq[c] = rec[17 + c][o]; t.itq[c] = rec[21 + c][o]; }
+        t.lam = rec[25][o]; t.mx = rec[26][o]; t.my = rec[27][o];
+        const double E0 = rec[28][o], E1 = rec[29][o];
+        DilepGeom g;
+        dilep_geom(tt_jet(ev, 0, E0), tt_jet(ev, 1, E1), ev.lp, ev.lm, t, g);
+        NuSol sol;
+        qres[i] = dilep_accept(t, g, qpx[i], sol) ? tt_solution<T>(pp, ev, E0, E1, sol) : 0.0;
       }
       wave_sync();
       double acc = 0.0;
-      for (int j = 0; j < ns; ++j) acc += q[0][off + j];
+      for (int j = 0; j < nr; ++j) acc += qres[off + j];
       wave_sync();     // the next round overwrites the queue
       if (live) {
-        const double w = tt_point<T>(pp, ev, acc, f.jetf) * jac;
+        const double w = tt_point<T>(pp, ev, acc, m.jetf) * jac;
         s1 += w;
         s2 += w * w;
         if (w != 0.0) {
@@ -232,7 +263,7 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
       TTEvent e;
       tt_load(ev, ch.event, ch.perm, e);
       // launches that also carry t tbar H chunks run at two waves per SIMD,
-      // where the 72 KB queue would not fit twice: per-lane solution loop
+      // where the 80 KB of queues would not fit twice: per-lane root loop
       if constexpr ((KINDS & kMaskTTH) == 0)
         chunk_points_tt<T, (KINDS & kMaskTT) != 0>(ch, seed, iter, sgrid, wbins, s1, s2, pp, e);
       else

@@ -86,45 +86,48 @@ struct TBoost {
   }
 };
 
-// The integrand in two stages.  tt_front: per point, the jet energies,
-// TFs, virtualities, recoil and the neutrino solve; tt_solution: per
-// neutrino solution, the boost, |M|^2, PDFs and the weight.  The solutions
-// of a point are summed in order, then times the point factors.
+// The integrand in stages.  tt_maps: per point, the jet energies, TFs,
+// virtualities and recoil; the neutrino solve (solve_dilepton, or its
+// stages dilep_prepare / quartic_real_roots / dilep_accept); tt_solution:
+// per neutrino solution, the boost, |M|^2, PDFs and the weight.  The
+// solutions of a point are summed in order, then times the point factors.
 template <class T>
-struct TTFront {
-  double E0, E1;     // parton energies of the two jets
+struct TTMaps {
+  v4 bq[2];          // the two jets (parton energies)
   T jetf;            // jet factors (TF, phase-space density)
-  NuSet sols;
+  double q2t, q2tb, q2wp, q2wm, metx, mety;
 };
 
 template <class T>
-__device__ __forceinline__ void tt_front(const ProcParams& pp, const TTEvent& ev, const double (&x)[8], TTFront<T>& f)
+__device__ __forceinline__ void tt_maps(const ProcParams& pp, const TTEvent& ev, const double (&x)[8], TTMaps<T>& m)
 {
   const TFParams& tf = pp.tf_b;
-  v4 bq[2];
   T jetf = T(1);
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const double r = tf.r_lo + x[k] * (tf.r_hi - tf.r_lo), ir = fast_rcp(r);
     const double E = ev.em[k] * ir;
-    bq[k] = v4{E, E * ev.n[k][0], E * ev.n[k][1], E * ev.n[k][2]};
+    m.bq[k] = v4{E, E * ev.n[k][0], E * ev.n[k][1], E * ev.n[k][2]};
     // E^2 sin dE T / (2E): the true energy cancels against the TF
     jetf *= T(ev.sin_th[k] * (tf.r_hi - tf.r_lo) * E * ir * 0.5) * tf_r<T>(T(r), tf);
   }
-  f.E0 = bq[0].e;
-  f.E1 = bq[1].e;
-  f.jetf = jetf;
+  m.jetf = jetf;
   const double mtg = pp.m_t * pp.w_t, mwg = pp.m_w * pp.w_w;
-  const double q2t = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
-  const double q2tb = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[3] * (pp.th1_t - pp.th0_t));
-  const double q2wp = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[4] * (pp.th1_w - pp.th0_w));
-  const double q2wm = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[5] * (pp.th1_w - pp.th0_w));
+  m.q2t = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
+  m.q2tb = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[3] * (pp.th1_t - pp.th0_t));
+  m.q2wp = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[4] * (pp.th1_w - pp.th0_w));
+  m.q2wm = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[5] * (pp.th1_w - pp.th0_w));
   const double rho = pp.sigma_k * sqrt(-2.0 * log(1.0 - x[6]));
   const double phi = 2.0 * M_PI * x[7];
   const double sphi = sin(phi), cphi = cos(phi);
-  const double metx = rho * cphi - (bq[0].x + bq[1].x + ev.lp.x + ev.lm.x);
-  const double mety = rho * sphi - (bq[0].y + bq[1].y + ev.lp.y + ev.lm.y);
-  solve_dilepton(bq[0], bq[1], ev.lp, ev.lm, metx, mety, q2wp, q2t, q2wm, q2tb, f.sols);
+  m.metx = rho * cphi - (m.bq[0].x + m.bq[1].x + ev.lp.x + ev.lm.x);
+  m.mety = rho * sphi - (m.bq[0].y + m.bq[1].y + ev.lp.y + ev.lm.y);
+}
+
+// jet of event slot k with parton energy E
+__device__ __forceinline__ v4 tt_jet(const TTEvent& ev, int k, double E)
+{
+  return v4{E, E * ev.n[k][0], E * ev.n[k][1], E * ev.n[k][2]};
 }
 
 // Weight of one neutrino solution sk of a point whose jets have parton
@@ -133,8 +136,7 @@ template <class T>
 __device__ __forceinline__ double tt_solution(const ProcParams& pp, const TTEvent& ev, double E0, double E1,
                                               const NuSol& sk)
 {
-  const v4 b0{E0, E0 * ev.n[0][0], E0 * ev.n[0][1], E0 * ev.n[0][2]};
-  const v4 b1{E1, E1 * ev.n[1][0], E1 * ev.n[1][1], E1 * ev.n[1][2]};
+  const v4 b0 = tt_jet(ev, 0, E0), b1 = tt_jet(ev, 1, E1);
   v4 nu{0.0, sk.nx, sk.ny, sk.nz}, nb{0.0, sk.bx, sk.by, sk.bz};
   nu.e = norm3(nu);
   nb.e = norm3(nb);
@@ -176,13 +178,15 @@ template <class T>
 __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEvent& ev, const double (&x)[8],
                                                int* nsol_out)
 {
-  TTFront<T> f;
-  tt_front<T>(pp, ev, x, f);
-  const int ns = f.sols.n;
+  TTMaps<T> m;
+  tt_maps<T>(pp, ev, x, m);
+  NuSet sols;
+  solve_dilepton(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, sols);
+  const int ns = sols.n;
   double acc = 0.0;
-  for (int k = 0; k < ns; ++k) acc += tt_solution<T>(pp, ev, f.E0, f.E1, f.sols.get(k));
+  for (int k = 0; k < ns; ++k) acc += tt_solution<T>(pp, ev, m.bq[0].e, m.bq[1].e, sols.get(k));
   if (nsol_out) *nsol_out = ns;
-  return tt_point<T>(pp, ev, acc, f.jetf);
+  return tt_point<T>(pp, ev, acc, m.jetf);
 }
 
 }  // namespace memk

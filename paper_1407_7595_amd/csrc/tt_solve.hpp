@@ -301,6 +301,132 @@ struct NuSet {
   }
 };
 
+// Per-point state of the solve once the resultant is formed (scaled units:
+// momenta / lam, virtualities / lam^2).
+struct DilepPoint {
+  Affine A1, A2;                  // E, p_z of nu (A1) and nubar (A2), affine in p_x, p_y
+  double P0, P1, P2, Q0, Q1;      // p_y = -(P0 + P1 px + P2 px^2) / (Q0 + Q1 px)
+  double tq[4], itq[4];           // target virtualities and their reciprocals
+  double lam, mx, my;             // scale; missing transverse momentum
+};
+
+// Scaling, the affine neutrino kinematics, the two conics and their
+// resultant (quartic in p_x, quart[0..4]).  false: no solution possible.
+__device__ __forceinline__ bool dilep_prepare(const v4& b_in, const v4& bb_in, const v4& lp_in, const v4& lm_in,
+                                              double metx, double mety, double q2wp, double q2t, double q2wm,
+                                              double q2tb, DilepPoint& s, double (&quart)[5])
+{
+  // scale to O(1) numbers
+  const double lam = 0.25 * (b_in.e + bb_in.e + lp_in.e + lm_in.e);
+  const double il = fast_rcp(lam), il2 = il * il;
+  const v4 b{b_in.e * il, b_in.x * il, b_in.y * il, b_in.z * il};
+  const v4 bb{bb_in.e * il, bb_in.x * il, bb_in.y * il, bb_in.z * il};
+  const v4 lp{lp_in.e * il, lp_in.x * il, lp_in.y * il, lp_in.z * il};
+  const v4 lm{lm_in.e * il, lm_in.x * il, lm_in.y * il, lm_in.z * il};
+  const double mx = metx * il, my = mety * il;
+  s.lam = lam; s.mx = mx; s.my = my;
+  s.tq[0] = q2wp * il2; s.tq[1] = q2t * il2; s.tq[2] = q2wm * il2; s.tq[3] = q2tb * il2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s.itq[i] = fast_rcp(s.tq[i]);
+
+  Affine& A1 = s.A1;
+  Affine& A2 = s.A2;
+  if (!nu_affine(b, lp, s.tq[0], s.tq[1], A1)) return false;
+  if (!nu_affine(bb, lm, s.tq[2], s.tq[3], A2)) return false;
+  // conic E^2 - p^2 = 0 of each side: {xx, xy, yy, x, y, 1}
+  const double c1[6] = {A1.e1 * A1.e1 - 1.0 - A1.z1 * A1.z1, 2.0 * (A1.e1 * A1.e2 - A1.z1 * A1.z2),
+                        A1.e2 * A1.e2 - 1.0 - A1.z2 * A1.z2, 2.0 * (A1.e0 * A1.e1 - A1.z0 * A1.z1),
+                        2.0 * (A1.e0 * A1.e2 - A1.z0 * A1.z2), A1.e0 * A1.e0 - A1.z0 * A1.z0};
+  const double cb[6] = {A2.e1 * A2.e1 - 1.0 - A2.z1 * A2.z1, 2.0 * (A2.e1 * A2.e2 - A2.z1 * A2.z2),
+                        A2.e2 * A2.e2 - 1.0 - A2.z2 * A2.z2, 2.0 * (A2.e0 * A2.e1 - A2.z0 * A2.z1),
+                        2.0 * (A2.e0 * A2.e2 - A2.z0 * A2.z2), A2.e0 * A2.e0 - A2.z0 * A2.z0};
+  // substitute nubar_xy = met - nu_xy
+  const double c2[6] = {cb[0], cb[1], cb[2],
+                        -2.0 * mx * cb[0] - my * cb[1] - cb[3],
+                        -2.0 * my * cb[2] - mx * cb[1] - cb[4],
+                        (cb[0] * mx + cb[1] * my + cb[3]) * mx + (cb[2] * my + cb[4]) * my + cb[5]};
+  // as polynomials in py: a py^2 + (b0 + b1 px) py + (g0 + g1 px + g2 px^2)
+  const double a1 = c1[2], a2 = c2[2];
+  const double P0 = a1 * c2[5] - a2 * c1[5], P1 = a1 * c2[3] - a2 * c1[3], P2 = a1 * c2[0] - a2 * c1[0];
+  const double Q0 = a1 * c2[4] - a2 * c1[4], Q1 = a1 * c2[1] - a2 * c1[1];
+  s.P0 = P0; s.P1 = P1; s.P2 = P2; s.Q0 = Q0; s.Q1 = Q1;
+  // R = B1 C2 - B2 C1 (cubic)
+  const double R0 = c1[4] * c2[5] - c2[4] * c1[5];
+  const double R1 = c1[4] * c2[3] + c1[1] * c2[5] - c2[4] * c1[3] - c2[1] * c1[5];
+  const double R2 = c1[4] * c2[0] + c1[1] * c2[3] - c2[4] * c1[0] - c2[1] * c1[3];
+  const double R3 = c1[1] * c2[0] - c2[1] * c1[0];
+  // resultant P^2 - Q R
+  quart[0] = P0 * P0 - Q0 * R0;
+  quart[1] = 2.0 * P0 * P1 - Q0 * R1 - Q1 * R0;
+  quart[2] = P1 * P1 + 2.0 * P0 * P2 - Q0 * R2 - Q1 * R1;
+  quart[3] = 2.0 * P1 * P2 - Q0 * R3 - Q1 * R2;
+  quart[4] = P2 * P2 - Q1 * R3;
+  return quart[4] != 0.0;
+}
+
+// Scaled geometry of the two top sides from the unscaled inputs.
+__device__ __forceinline__ void dilep_geom(const v4& b_in, const v4& bb_in, const v4& lp_in, const v4& lm_in,
+                                           const DilepPoint& s, DilepGeom& g)
+{
+  const double il = fast_rcp(s.lam);
+  const v4 b{b_in.e * il, b_in.x * il, b_in.y * il, b_in.z * il};
+  const v4 bb{bb_in.e * il, bb_in.x * il, bb_in.y * il, bb_in.z * il};
+  g.lp = v4{lp_in.e * il, lp_in.x * il, lp_in.y * il, lp_in.z * il};
+  g.lm = v4{lm_in.e * il, lm_in.x * il, lm_in.y * il, lm_in.z * il};
+  g.wt = add(b, g.lp);
+  g.wtb = add(bb, g.lm);
+  g.wt2 = mdot(g.wt, g.wt);
+  g.wtb2 = mdot(g.wtb, g.wtb);
+  g.mx = s.mx;
+  g.my = s.my;
+}
+
+// One real root px of the resultant: p_y from the conics, positive
+// energies, conditional Newton polish on the full system, residual test;
+// on acceptance the solution in lab units (GeV) with |det J| (GeV^4).
+__device__ __forceinline__ bool dilep_accept(const DilepPoint& s, const DilepGeom& g, double px, NuSol& out)
+{
+  const Affine& A1 = s.A1;
+  const Affine& A2 = s.A2;
+  const double q = s.Q0 + s.Q1 * px;
+  if (!(fabs(q) > 1e-12 * (fabs(s.Q0) + fabs(s.Q1 * px)))) return false;
+  const double py = -(s.P0 + (s.P1 + s.P2 * px) * px) * fast_rcp(q);
+  const double E1 = A1.e0 + A1.e1 * px + A1.e2 * py;
+  const double bx = s.mx - px, by = s.my - py;
+  const double E2 = A2.e0 + A2.e1 * bx + A2.e2 * by;
+  if (!(E1 > 0.0 && E2 > 0.0)) return false;
+  double v[4] = {px, py, A1.z0 + A1.z1 * px + A1.z2 * py, A2.z0 + A2.z1 * bx + A2.z2 * by};
+  double F[4];
+  v4 nu, nb;
+  dilep_F(g, v, F, nu, nb);
+  double worst = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - s.tq[i]) * s.itq[i]));
+  // the resultant loses digits near degenerate configurations: polish by
+  // Newton on the full system only where the residual shows it
+  for (int it = 0; it < 2 && worst > 1e-13; ++it) {
+    DilepJac J;
+    dilep_J(g, nu, nb, J);
+    double r[4] = {F[0] - s.tq[0], F[1] - s.tq[1], F[2] - s.tq[2], F[3] - s.tq[3]}, dv[4];
+    if (!dilep_step(J, r, dv)) break;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] -= dv[i];
+    dilep_F(g, v, F, nu, nb);
+    worst = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - s.tq[i]) * s.itq[i]));
+  }
+  if (!(worst < 1e-6)) return false;
+  DilepJac J;
+  dilep_J(g, nu, nb, J);
+  const double det = dilep_det(J);
+  if (det == 0.0) return false;
+  const double lam = s.lam, l4 = lam * lam * lam * lam;
+  out = NuSol{v[0] * lam, v[1] * lam, v[2] * lam, (s.mx - v[0]) * lam, (s.my - v[1]) * lam, v[3] * lam,
+              fabs(det) * l4};
+  return true;
+}
+
 // Every accepted (nu, nubar) solution, in lab units (GeV) with |det J|
 // (GeV^4).  Inputs in GeV / GeV^2.
 __device__ __forceinline__ void solve_dilepton(const v4& b_in, const v4& bb_in, const v4& lp_in, const v4& lm_in,
@@ -308,93 +434,16 @@ __device__ __forceinline__ void solve_dilepton(const v4& b_in, const v4& bb_in, 
                                                double q2tb, NuSet& out)
 {
   out.n = 0;
-  // scale to O(1) numbers
-  const double lam = 0.25 * (b_in.e + bb_in.e + lp_in.e + lm_in.e);
-  const double il = fast_rcp(lam), il2 = il * il;
-  v4 b{b_in.e * il, b_in.x * il, b_in.y * il, b_in.z * il};
-  v4 bb{bb_in.e * il, bb_in.x * il, bb_in.y * il, bb_in.z * il};
-  v4 lp{lp_in.e * il, lp_in.x * il, lp_in.y * il, lp_in.z * il};
-  v4 lm{lm_in.e * il, lm_in.x * il, lm_in.y * il, lm_in.z * il};
-  const double mx = metx * il, my = mety * il;
-  const double tq[4] = {q2wp * il2, q2t * il2, q2wm * il2, q2tb * il2};
-  const double itq[4] = {fast_rcp(tq[0]), fast_rcp(tq[1]), fast_rcp(tq[2]), fast_rcp(tq[3])};
-
-  Affine A1, A2;
-  if (!nu_affine(b, lp, tq[0], tq[1], A1)) return;
-  if (!nu_affine(bb, lm, tq[2], tq[3], A2)) return;
-  // conic E^2 - p^2 = 0 of each side: {xx, xy, yy, x, y, 1}
-  double c1[6] = {A1.e1 * A1.e1 - 1.0 - A1.z1 * A1.z1, 2.0 * (A1.e1 * A1.e2 - A1.z1 * A1.z2),
-                  A1.e2 * A1.e2 - 1.0 - A1.z2 * A1.z2, 2.0 * (A1.e0 * A1.e1 - A1.z0 * A1.z1),
-                  2.0 * (A1.e0 * A1.e2 - A1.z0 * A1.z2), A1.e0 * A1.e0 - A1.z0 * A1.z0};
-  double cb[6] = {A2.e1 * A2.e1 - 1.0 - A2.z1 * A2.z1, 2.0 * (A2.e1 * A2.e2 - A2.z1 * A2.z2),
-                  A2.e2 * A2.e2 - 1.0 - A2.z2 * A2.z2, 2.0 * (A2.e0 * A2.e1 - A2.z0 * A2.z1),
-                  2.0 * (A2.e0 * A2.e2 - A2.z0 * A2.z2), A2.e0 * A2.e0 - A2.z0 * A2.z0};
-  // substitute nubar_xy = met - nu_xy
-  double c2[6] = {cb[0], cb[1], cb[2],
-                  -2.0 * mx * cb[0] - my * cb[1] - cb[3],
-                  -2.0 * my * cb[2] - mx * cb[1] - cb[4],
-                  (cb[0] * mx + cb[1] * my + cb[3]) * mx + (cb[2] * my + cb[4]) * my + cb[5]};
-  // as polynomials in py: a py^2 + (b0 + b1 px) py + (g0 + g1 px + g2 px^2)
-  const double a1 = c1[2], a2 = c2[2];
-  const double P0 = a1 * c2[5] - a2 * c1[5], P1 = a1 * c2[3] - a2 * c1[3], P2 = a1 * c2[0] - a2 * c1[0];
-  const double Q0 = a1 * c2[4] - a2 * c1[4], Q1 = a1 * c2[1] - a2 * c1[1];
-  // R = B1 C2 - B2 C1 (cubic)
-  const double R0 = c1[4] * c2[5] - c2[4] * c1[5];
-  const double R1 = c1[4] * c2[3] + c1[1] * c2[5] - c2[4] * c1[3] - c2[1] * c1[5];
-  const double R2 = c1[4] * c2[0] + c1[1] * c2[3] - c2[4] * c1[0] - c2[1] * c1[3];
-  const double R3 = c1[1] * c2[0] - c2[1] * c1[0];
-  // resultant P^2 - Q R
-  double quart[5] = {P0 * P0 - Q0 * R0,
-                     2.0 * P0 * P1 - Q0 * R1 - Q1 * R0,
-                     P1 * P1 + 2.0 * P0 * P2 - Q0 * R2 - Q1 * R1,
-                     2.0 * P1 * P2 - Q0 * R3 - Q1 * R2,
-                     P2 * P2 - Q1 * R3};
-  if (quart[4] == 0.0) return;
+  DilepPoint s;
+  double quart[5];
+  if (!dilep_prepare(b_in, bb_in, lp_in, lm_in, metx, mety, q2wp, q2t, q2wm, q2tb, s, quart)) return;
   Four roots;
   quartic_real_roots(quart, roots);
-  const int nr = roots.n;
-
   DilepGeom g;
-  g.lp = lp; g.lm = lm; g.wt = add(b, lp); g.wtb = add(bb, lm);
-  g.wt2 = mdot(g.wt, g.wt); g.wtb2 = mdot(g.wtb, g.wtb); g.mx = mx; g.my = my;
-  const double l4 = lam * lam * lam * lam;
-  for (int k = 0; k < nr; ++k) {
-    const double px = roots.get(k);
-    const double q = Q0 + Q1 * px;
-    if (!(fabs(q) > 1e-12 * (fabs(Q0) + fabs(Q1 * px)))) continue;
-    const double py = -(P0 + (P1 + P2 * px) * px) * fast_rcp(q);
-    const double E1 = A1.e0 + A1.e1 * px + A1.e2 * py;
-    const double bx = mx - px, by = my - py;
-    const double E2 = A2.e0 + A2.e1 * bx + A2.e2 * by;
-    if (!(E1 > 0.0 && E2 > 0.0)) continue;
-    double v[4] = {px, py, A1.z0 + A1.z1 * px + A1.z2 * py, A2.z0 + A2.z1 * bx + A2.z2 * by};
-    double F[4];
-    v4 nu, nb;
-    dilep_F(g, v, F, nu, nb);
-    double worst = 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - tq[i]) * itq[i]));
-    // the resultant loses digits near degenerate configurations: polish by
-    // Newton on the full system only where the residual shows it
-    for (int it = 0; it < 2 && worst > 1e-13; ++it) {
-      DilepJac J;
-      dilep_J(g, nu, nb, J);
-      double r[4] = {F[0] - tq[0], F[1] - tq[1], F[2] - tq[2], F[3] - tq[3]}, dv[4];
-      if (!dilep_step(J, r, dv)) break;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] -= dv[i];
-      dilep_F(g, v, F, nu, nb);
-      worst = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - tq[i]) * itq[i]));
-    }
-    if (!(worst < 1e-6)) continue;
-    DilepJac J;
-    dilep_J(g, nu, nb, J);
-    const double det = dilep_det(J);
-    if (det == 0.0) continue;
-    out.put(NuSol{v[0] * lam, v[1] * lam, v[2] * lam, (mx - v[0]) * lam, (my - v[1]) * lam, v[3] * lam,
-                  fabs(det) * l4});
+  dilep_geom(b_in, bb_in, lp_in, lm_in, s, g);
+  for (int k = 0; k < roots.n; ++k) {
+    NuSol sol;
+    if (dilep_accept(s, g, roots.get(k), sol)) out.put(sol);
   }
 }
 
