@@ -104,6 +104,12 @@ MIX(CF, int)
 inline CD operator*(CD a, CF b) { return a * CD(b); }
 inline CD operator*(CF a, CD b) { return CD(a) * b; }
 inline void sincos(CD a, CD* s, CD* c) { g_t.trans[F64] += 2; *s = CD(std::sin(a.v)); *c = CD(std::cos(a.v)); }
+inline void sincospi(CD a, CD* s, CD* c)
+{
+  g_t.trans[F64] += 2;
+  *s = CD(std::sin(M_PI * a.v));
+  *c = CD(std::cos(M_PI * a.v));
+}
 inline CD __fma_rn(CD a, CD b, CD c) { g_t.fma[F64]++; return CD(std::fma(a.v, b.v, c.v)); }
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 

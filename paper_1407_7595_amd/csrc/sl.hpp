@@ -85,7 +85,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   const v4 qa = sl_jet<0>(ev, ema * ira);
   // hadronic W: q2 = 2 E_a E_b (1 - cos(a, b))
   const double mwg = pp.m_w * pp.w_w, mtg = pp.m_t * pp.w_t;
-  const double q2wh = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[1] * (pp.th1_w - pp.th0_w));
+  const double q2wh = pp.m_w * pp.m_w + mwg * tan_halfpi(pp.th0_w + x[1] * (pp.th1_w - pp.th0_w));
   const v4 ua = sl_jet<0>(ev, 1.0), ub = sl_jet<1>(ev, 1.0);
   const double omc = 1.0 - (ua.x * ub.x + ua.y * ub.y + ua.z * ub.z);
   if (!(omc > 0.0)) return 0.0;
@@ -93,7 +93,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   const double Eb = q2wh * dEb;
   const v4 qb = sl_jet<1>(ev, Eb);
   // hadronic top: q2 = q2_W + 2 E_bh (E_W - n_bh . p_W)
-  const double q2th = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
+  const double q2th = pp.m_t * pp.m_t + mtg * tan_halfpi(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
   const v4 W = add(qa, qb);
   const v4 uh = sl_jet<2>(ev, 1.0);
   const double den = 2.0 * (W.e - (uh.x * W.x + uh.y * W.y + uh.z * W.z));
@@ -116,11 +116,12 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   jetf *= T(0.5 * ev.sin_th[3] * (tb.r_hi - tb.r_lo) * eml * irl * irl) * tf_r<T>(T(rl), tb);
   // neutrino transverse momentum from the recoil
   const double rho = pp.sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
-  const double phi = 2.0 * M_PI * x[5];
-  const double nx = rho * cos(phi) - (qa.x + qb.x + bh.x + bl.x + ev.l.x);
-  const double ny = rho * sin(phi) - (qa.y + qb.y + bh.y + bl.y + ev.l.y);
+  double sphi, cphi;
+  sincospi(2.0 * x[5], &sphi, &cphi);     // angle 2 pi x5
+  const double nx = rho * cphi - (qa.x + qb.x + bh.x + bl.x + ev.l.x);
+  const double ny = rho * sphi - (qa.y + qb.y + bh.y + bl.y + ev.l.y);
   // leptonic W: 2 l.nu = q2 at fixed nu_T -> l_T^2 nu_z^2 - 2 a l_z nu_z + E_l^2 nu_T^2 - a^2 = 0
-  const double q2wl = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[6] * (pp.th1_w - pp.th0_w));
+  const double q2wl = pp.m_w * pp.m_w + mwg * tan_halfpi(pp.th0_w + x[6] * (pp.th1_w - pp.th0_w));
   const v4& l = ev.l;
   const double lt2 = l.x * l.x + l.y * l.y;
   const double a = 0.5 * q2wl + l.x * nx + l.y * ny;

@@ -113,13 +113,13 @@ __device__ __forceinline__ void tt_maps(const ProcParams& pp, const TTEvent& ev,
   }
   m.jetf = jetf;
   const double mtg = pp.m_t * pp.w_t, mwg = pp.m_w * pp.w_w;
-  m.q2t = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
-  m.q2tb = pp.m_t * pp.m_t + mtg * tan(pp.th0_t + x[3] * (pp.th1_t - pp.th0_t));
-  m.q2wp = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[4] * (pp.th1_w - pp.th0_w));
-  m.q2wm = pp.m_w * pp.m_w + mwg * tan(pp.th0_w + x[5] * (pp.th1_w - pp.th0_w));
+  m.q2t = pp.m_t * pp.m_t + mtg * tan_halfpi(pp.th0_t + x[2] * (pp.th1_t - pp.th0_t));
+  m.q2tb = pp.m_t * pp.m_t + mtg * tan_halfpi(pp.th0_t + x[3] * (pp.th1_t - pp.th0_t));
+  m.q2wp = pp.m_w * pp.m_w + mwg * tan_halfpi(pp.th0_w + x[4] * (pp.th1_w - pp.th0_w));
+  m.q2wm = pp.m_w * pp.m_w + mwg * tan_halfpi(pp.th0_w + x[5] * (pp.th1_w - pp.th0_w));
   const double rho = pp.sigma_k * sqrt(-2.0 * log(1.0 - x[6]));
-  const double phi = 2.0 * M_PI * x[7];
-  const double sphi = sin(phi), cphi = cos(phi);
+  double sphi, cphi;
+  sincospi(2.0 * x[7], &sphi, &cphi);     // angle 2 pi x7
   m.metx = rho * cphi - (m.bq[0].x + m.bq[1].x + ev.lp.x + ev.lm.x);
   m.mety = rho * sphi - (m.bq[0].y + m.bq[1].y + ev.lp.y + ev.lm.y);
 }
