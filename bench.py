@@ -35,9 +35,18 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 # Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
 # FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
 # peak is half the FP32 one).  Counted by paper_1407_7595_amd/opcount.py on
-# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 2368.7 FP64 +
-# 1065.3 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
+# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1307.4 FP64 +
+# 1051.9 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
 FLOP_PER_EVAL = 2.0 * 1307.4 + 1051.9
+
+# HBM bytes per fixed-budget launch of the integrand kernel (4096 events x
+# 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
+# script's fixed-budget pass, each scaled by what the counter reads for plain
+# kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
+# FETCH 97 030 KiB x 2.000 + WRITE 266 093 KiB x 1.000.  Valid for this
+# workload and the kernel build the counters were taken on; None otherwise.
+TRAFFIC_BYTES_PER_LAUNCH = (97030 * 2.000 + 266093 * 1.000) * 1024
+TRAFFIC_WORKLOAD = (4096, 65536)
 
 
 def log(*a):
@@ -269,8 +278,9 @@ def main():
     if FLOP_PER_EVAL is not None and launches > 0:
         per_launch = FLOP_PER_EVAL * n_evals / launches
         achieved = per_launch / (kern_ms / launches * 1e-3)
+        traffic = TRAFFIC_BYTES_PER_LAUNCH if (n_ev, PTS) == TRAFFIC_WORKLOAD else None
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32, "traffic": None}
+                "frac": achieved / PEAK_FP32, "traffic": traffic}
     flow = None
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)
