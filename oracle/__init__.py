@@ -94,6 +94,10 @@ def _declare(L):
         "or_dy_sigma_2d": (D, [P, I]),
         "or_dy_sigma_tau": (D, [P, I]),
         "or_tt_integrand": (D, [P, P, I, P, P]),
+        "or_tt_parton_weight": (D, [P, P]),
+        "or_decay_w_factor": (D, [P, D]),
+        "or_ps_volume": (D, [I, D, U64, I64, P]),
+        "or_top_width": (D, [P, U64, I64, P]),
         "or_solve_dilepton": (I, [P, P, P, P, D, D, D, D, D, D, P, P, P]),
         "or_dilepton_residual": (None, [P, P, P, P, P, P, P]),
         "or_tt_me2_gg": (D, [P, P, P, P]),
@@ -192,6 +196,23 @@ def tt_integrand(p, ev, perm, x):
     ns = ctypes.c_int(0)
     v = lib().or_tt_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
     return v, ns.value
+
+
+def ps_volume(n, sqrt_s, seed, n_points):
+    err = ctypes.c_double()
+    v = lib().or_ps_volume(n, sqrt_s, seed, n_points, ctypes.byref(err))
+    return v, err.value
+
+
+def top_width(p, seed, n_points):
+    err = ctypes.c_double()
+    v = lib().or_top_width(ctypes.byref(p), seed, n_points, ctypes.byref(err))
+    return v, err.value
+
+
+def tt_parton_weight(p, ev):
+    """ev: [6, 4] b, bbar, l+, l-, nu, nubar"""
+    return lib().or_tt_parton_weight(ctypes.byref(p), _ptr(_f64(ev)))
 
 
 def sl_integrand(p, ev, perm, x, charge=0):

@@ -363,6 +363,15 @@ static double bw2(double q2, double m, double w)
   return 1.0 / (d * d + m * m * w * w);
 }
 
+/* One W chain of a top decay: the two W vertices (g_W / sqrt 2)^2 each,
+ * squared, with g_W^2 = 8 G_F M_W^2 / sqrt 2, times the W Breit-Wigner
+ * factor at virtuality w2. */
+double or_decay_w_factor(const or_params* p, double w2)
+{
+  double gw2 = 8.0 * p->g_fermi * p->m_w * p->m_w / sqrt(2.0);
+  return (gw2 / 2.0) * (gw2 / 2.0) * bw2(w2, p->m_w, p->w_w);
+}
+
 static double decay_couplings(const or_params* p, const double* mom, const double* pt, const double* ptb)
 {
   const double *b = mom, *lp = mom + 4, *nu = mom + 8;
@@ -370,11 +379,9 @@ static double decay_couplings(const or_params* p, const double* mom, const doubl
   (void)b; (void)bb;
   double wp[4], wm[4];
   for (int i = 0; i < 4; ++i) { wp[i] = lp[i] + nu[i]; wm[i] = lm[i] + nub[i]; }
-  double gw2 = 8.0 * p->g_fermi * p->m_w * p->m_w / sqrt(2.0);
   double gs2 = 4.0 * M_PI * p->alpha_s;
-  double c = gs2 * gs2 * pow(gw2 / 2.0, 4);
-  return c * bw2(mdot(pt, pt), p->m_t, p->w_t) * bw2(mdot(ptb, ptb), p->m_t, p->w_t)
-           * bw2(mdot(wp, wp), p->m_w, p->w_w) * bw2(mdot(wm, wm), p->m_w, p->w_w);
+  return gs2 * gs2 * or_decay_w_factor(p, mdot(wp, wp)) * or_decay_w_factor(p, mdot(wm, wm))
+         * bw2(mdot(pt, pt), p->m_t, p->w_t) * bw2(mdot(ptb, ptb), p->m_t, p->w_t);
 }
 
 double or_tt_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom)

@@ -549,6 +549,43 @@ double or_tt_integrand(const or_params* p, const double* ev, int perm,
 }
 
 /* ------------------------------------------------- ttbar semileptonic -- */
+/* The weight of one assignment: jets b (from t) and bb, the leptons and
+ * neutrinos as given (Eq. integrand with every transfer function a delta
+ * function: only the flux, the x1, x2 delta functions and |M|^2 x PDFs
+ * remain). */
+static double parton_assignment(const or_params* p, const double* b, const double* bb, const double* lp,
+                                const double* lm, const double* nu, const double* nub)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  double lab[6][4];
+  memcpy(lab[0], b, sizeof(lab[0]));   memcpy(lab[1], lp, sizeof(lab[1]));
+  memcpy(lab[2], nu, sizeof(lab[2]));  memcpy(lab[3], bb, sizeof(lab[3]));
+  memcpy(lab[4], lm, sizeof(lab[4]));  memcpy(lab[5], nub, sizeof(lab[5]));
+  double P[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 6; ++k) for (int i = 0; i < 4; ++i) P[i] += lab[k][i];
+  double hard[24];
+  for (int k = 0; k < 6; ++k) boost_transverse(P, lab[k], hard + 4 * k);
+  double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+  double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
+  double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+  double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+  double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
+  double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
+  double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
+  double me = g1 * g2 * or_tt_me2_gg(p, k1, k2, hard)
+            + q1 * qb2 * or_tt_me2_qq(p, k1, k2, hard)
+            + qb1 * q2 * or_tt_me2_qq(p, k2, k1, hard);
+  double shat = x1 * x2 * S;
+  return (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat);
+}
+
+double or_tt_parton_weight(const or_params* p, const double* ev)
+{
+  const double *b = ev, *bb = ev + 4, *lp = ev + 8, *lm = ev + 12, *nu = ev + 16, *nub = ev + 20;
+  return 0.5 * (parton_assignment(p, b, bb, lp, lm, nu, nub) + parton_assignment(p, bb, b, lp, lm, nu, nub));
+}
+
 double or_dgauss_tf(double meas, double truth, double core, double tail, double ftail)
 {
   return (1.0 - ftail) * or_gauss_tf(meas, truth, core) + ftail * or_gauss_tf(meas, truth, tail);

@@ -94,6 +94,31 @@ double or_dy_sigma_tau(const or_params* p, int nodes);
 double or_tt_integrand(const or_params* p, const double* ev, int perm,
                        const double* x, int* nsol);
 
+/* One W chain of the top decays in the ttbar matrix element: the two W
+ * vertices squared, (g_W^2 / 2)^2 with g_W^2 = 8 G_F M_W^2 / sqrt 2, times
+ * the W Breit-Wigner factor 1 / ((w2 - M_W^2)^2 + M_W^2 Gamma_W^2). */
+double or_decay_w_factor(const or_params* p, double w2);
+
+/* Volume of massless n-body phase space (2 <= n <= 6) at sqrt(s), by Monte
+ * Carlo over sequential two-body splittings (n_points Philox points);
+ * writes the MC error to err. */
+double or_ps_volume(int n, double sqrt_s, uint64_t seed, int64_t n_points, double* err);
+
+/* Width Gamma(t -> b l+ nu) of an on-shell top from its three-body decay
+ * phase space with the matrix element's W chain (or_decay_w_factor x
+ * or_top_decay_spinsum); writes the MC error to err. */
+double or_top_width(const or_params* p, uint64_t seed, int64_t n_points, double* err);
+
+/* Parton-level weight of a ttbar dilepton event whose six final-state
+ * partons are all known (transfer functions are delta functions, Sec. 4's
+ * parton-level timing).  ev = b, bbar, l+, l-, nu, nubar as 6 x
+ * {E,px,py,pz}.  For each assignment of the two b partons (as given, then
+ * swapped): boost to zero transverse momentum, x1, x2 = (E' +- P_z)/sqrt(S),
+ * w = (2/S) (E/E') [f_g f_g |M_gg|^2 + f_q f_qbar |M_qq|^2 (both beam
+ * orderings)] / (2 shat); 0 when x1 or x2 leaves (0, 1].  Returns the
+ * average over the two assignments. */
+double or_tt_parton_weight(const or_params* p, const double* ev);
+
 /* ttbar semileptonic (one W -> q qbar').  ev = jets j0..j3, lepton as
  * 5 x {E,px,py,pz}, then a sixth row {charge, 0, 0, 0} with the lepton
  * charge +1 (l+: the top decays leptonically) or -1 (read when lep_charge

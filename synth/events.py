@@ -159,6 +159,18 @@ def ttbar_dilepton(n_events, seed, rel_sigma=0.15, sigma_k=20.0):
     return {"obs": obs, "truth": truth}
 
 
+def ttbar_dilepton_partons(n_events, seed, sigma_k=20.0):
+    """parton-level ttbar dilepton events (every transfer function a delta
+    function): the generator of ttbar_dilepton without smearing; rows b-quark
+    0, b-quark 1 (the b and the bbar in random order), l+, l-, nu, nubar"""
+    d = ttbar_dilepton(n_events, seed, rel_sigma=0.0, sigma_k=sigma_k)
+    t = d["truth"]
+    swap = t["swap"][:, None]
+    q0 = np.where(swap, t["bb"], t["b"])
+    q1 = np.where(swap, t["b"], t["bb"])
+    return {"obs": np.stack([q0, q1, t["lp"], t["lm"], t["nu"], t["nub"]], axis=1), "truth": t}
+
+
 def _smear_dgauss(rng, E, core, tail, ftail):
     """E (1 + s z) with s = tail for a fraction ftail of the draws, else
     core, redrawn while non-positive"""

@@ -739,3 +739,103 @@ def test_flow_nll_gradient_finite_difference():
         pm[i] -= h
         fd = (oracle.flow_nll_grad(pp, x, ctx, wt)[0] - oracle.flow_nll_grad(pm, x, ctx, wt)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-7), (i, g[i], fd)
+
+
+# ------------------------------------------------------ parton-level weight --
+def _boost_z_axis_rotation(mom, phi):
+    c, s = np.cos(phi), np.sin(phi)
+    out = mom.copy()
+    out[:, 1] = c * mom[:, 1] - s * mom[:, 2]
+    out[:, 2] = s * mom[:, 1] + c * mom[:, 2]
+    return out
+
+
+def _transverse_boost(mom, bx, by):
+    b2 = bx * bx + by * by
+    g = 1.0 / np.sqrt(1.0 - b2)
+    out = mom.copy()
+    bp = bx * mom[:, 1] + by * mom[:, 2]
+    out[:, 0] = g * (mom[:, 0] + bp)
+    k = (g - 1.0) * bp / b2 + g * mom[:, 0]
+    out[:, 1] = mom[:, 1] + k * bx
+    out[:, 2] = mom[:, 2] + k * by
+    return out
+
+
+def test_parton_weight_symmetries():
+    """the parton-level weight depends on the final state only through its
+    zero-transverse-momentum frame and the beam axis: unchanged by a common
+    transverse boost or a rotation about the beam, and by the reflection
+    z -> -z, which exchanges the beams (x1 <-> x2, gg and q qbar channels
+    mapped onto themselves); averaged over the b assignments it does not
+    depend on the order of the b partons; positive for generated events"""
+    p = oracle.tt_params()
+    d = events.ttbar_dilepton_partons(40, 5)
+    rng = np.random.default_rng(3)
+    for ev in d["obs"]:
+        w = oracle.tt_parton_weight(p, ev)
+        assert w > 0.0
+        rot = _boost_z_axis_rotation(ev, rng.uniform(0, 2 * np.pi))
+        assert oracle.tt_parton_weight(p, rot) == pytest.approx(w, rel=1e-11)
+        bx, by = rng.uniform(-0.3, 0.3, 2)
+        bst = _transverse_boost(ev, bx, by)
+        assert oracle.tt_parton_weight(p, bst) == pytest.approx(w, rel=1e-9)
+        refl = ev.copy()
+        refl[:, 3] = -refl[:, 3]
+        assert oracle.tt_parton_weight(p, refl) == pytest.approx(w, rel=1e-11)
+        sw = ev[[1, 0, 2, 3, 4, 5]]
+        assert oracle.tt_parton_weight(p, sw) == pytest.approx(w, rel=1e-14)
+
+
+def test_parton_weight_limits():
+    """an event whose mass in its zero-transverse-momentum frame exceeds
+    sqrt(S) needs x1 x2 > 1 and weighs 0; scaling every momentum of an event
+    by s (below that limit) scales the weight as the flux, the densities and
+    the dimensionless |M|^2 dictate, so it is finite and positive"""
+    p = oracle.tt_params()
+    ev = events.ttbar_dilepton_partons(3, 8)["obs"][0]
+    P = ev.sum(axis=0)
+    m = np.sqrt(P[0] ** 2 - P[1] ** 2 - P[2] ** 2 - P[3] ** 2)
+    big = ev * (1.01 * p.sqrt_s / m)
+    assert oracle.tt_parton_weight(p, big) == 0.0
+    mid = ev * (0.5 * p.sqrt_s / m)
+    w = oracle.tt_parton_weight(p, mid)
+    assert np.isfinite(w) and w >= 0.0
+
+
+# ------------------------------------------------------------ phase space --
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_massless_phase_space_volumes(n):
+    """massless n-body phase space: Phi_2 = 1/(8 pi), Phi_3 = s/(256 pi^3),
+    Phi_4 = s^2/(24576 pi^5), i.e. (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) /
+    ((n-1)! (n-2)!)"""
+    rs = 500.0
+    s = rs * rs
+    exact = (2 * math.pi) ** (4 - 3 * n) * (math.pi / 2) ** (n - 1) * s ** (n - 2) / (
+        math.factorial(n - 1) * math.factorial(n - 2))
+    v, err = oracle.ps_volume(n, rs, 0x5eed, 200000)
+    if n == 2:
+        assert v == pytest.approx(1 / (8 * math.pi), rel=1e-14) and err < 1e-15 * v
+    else:
+        assert abs(v - exact) < 4 * err and err < 0.01 * exact, (v, exact, err)
+    if n == 3:
+        assert exact == pytest.approx(s / (256 * math.pi ** 3), rel=1e-14)
+
+
+def test_top_width_from_decay_phase_space():
+    """Gamma(t -> b l+ nu) integrated over the three-body decay phase space with
+    the matrix element's W chain equals, in the narrow-width limit,
+    Gamma(t -> bW) Gamma(W -> l nu) / Gamma_W with the closed forms
+    Gamma(t -> bW) = G_F m_t^3 / (8 sqrt2 pi) (1 - r)^2 (1 + 2r), r = M_W^2/m_t^2,
+    and Gamma(W -> l nu) = G_F M_W^3 / (6 sqrt2 pi): this fixes the
+    normalisation of the decay vertices and of the W Breit-Wigner factor"""
+    gw = 0.01
+    p = oracle.tt_params(w_w=gw)
+    gf, mt, mw = p.g_fermi, p.m_t, p.m_w
+    r = mw * mw / (mt * mt)
+    g_tbw = gf * mt ** 3 / (8 * math.sqrt(2) * math.pi) * (1 - r) ** 2 * (1 + 2 * r)
+    g_wlnu = gf * mw ** 3 / (6 * math.sqrt(2) * math.pi)
+    want = g_tbw * g_wlnu / gw
+    v, err = oracle.top_width(p, 0x70b, 400000)
+    assert abs(v - want) < 4 * err + 2e-3 * want, (v, want, err)
+    assert err < 3e-3 * want
