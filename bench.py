@@ -35,9 +35,9 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 # Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
 # FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
 # peak is half the FP32 one).  Counted by paper_1407_7595_amd/opcount.py on
-# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1307.4 FP64 +
+# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1338.7 FP64 +
 # 1051.9 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
-FLOP_PER_EVAL = 2.0 * 1307.4 + 1051.9
+FLOP_PER_EVAL = 2.0 * 1338.7 + 1051.9
 
 # HBM bytes per fixed-budget launch of the integrand kernel (4096 events x
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
@@ -45,7 +45,7 @@ FLOP_PER_EVAL = 2.0 * 1307.4 + 1051.9
 # kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
 # FETCH 97 030 KiB x 2.000 + WRITE 266 093 KiB x 1.000.  Valid for this
 # workload and the kernel build the counters were taken on; None otherwise.
-TRAFFIC_BYTES_PER_LAUNCH = (97030 * 2.000 + 266093 * 1.000) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (98045 * 2.000 + 266102 * 1.000) * 1024
 TRAFFIC_WORKLOAD = (4096, 65536)
 
 
@@ -195,6 +195,33 @@ def flow_leg(mem, proc, comps, n_ev, args):
     return out
 
 
+PARTON_EVENTS = 100000
+
+
+def parton_leg(mem, proc):
+    """parton-level weights (transfer functions are delta functions: the
+    matrix element x PDFs at given momenta, no integration) for 10^5 events,
+    the workload of the paper's parton-level timing"""
+    import numpy as np
+    import torch
+    from synth import events
+    obs = events.ttbar_dilepton_partons(PARTON_EVENTS, SEED_EVENTS + 10)["obs"]
+    comps = torch.as_tensor(np.ascontiguousarray(obs.transpose(2, 1, 0))).cuda()
+    w = torch.empty(PARTON_EVENTS, dtype=torch.float64, device="cuda")
+    mem.parton_weights(proc, comps, out=w)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mem.parton_weights(proc, comps, out=w)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out = {"events": PARTON_EVENTS, "assignments": 2, "ms": dt * 1e3, "events_per_s": PARTON_EVENTS / dt,
+           "nonzero_fraction": float((w > 0).double().mean())}
+    log(f"parton level: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +308,7 @@ def main():
         traffic = TRAFFIC_BYTES_PER_LAUNCH if (n_ev, PTS) == TRAFFIC_WORKLOAD else None
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": traffic}
+    parton = parton_leg(mem, proc)
     flow = None
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)
@@ -304,6 +332,7 @@ def main():
                          "median_rel_err": float(np.median(fixed_rel))},
         "converged_fraction": conv, "median_iterations": float(np.median(nu)) if args.steps else None,
         "flow_vs_vegas": flow,
+        "parton_level": parton,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

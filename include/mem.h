@@ -268,6 +268,25 @@ mem_status mem_uniforms(uint64_t seed, uint32_t iter, uint32_t event, uint32_t p
 mem_status mem_eval_points(mem_process p, const mem_events* ev, int32_t event, int32_t perm,
                            const double* x, int64_t n, double* f, int32_t* nsol, void* stream);
 
+/* Parton-level weights (Sec. 4's parton-level timing: transfer functions
+ * are delta functions, so nothing is integrated and the method reduces to
+ * the matrix element at the given momenta).  ttbar dilepton processes
+ * only.  Event e holds six objects in this order: b, bbar, l+, l-, nu,
+ * nubar (massless, GeV).  Per assignment of the two b partons (as given,
+ * then swapped), the final state is boosted to zero transverse momentum,
+ * x1, x2 = (E' +- P_z) / sqrt(S), and
+ *   w = (2 / S) (E / E') sum_channels f(x1) f(x2) |M|^2 / (2 shat)
+ * (gg and the two q qbar orderings; |M|^2 with its couplings, the top and
+ * W Breit-Wigner propagators at the partons' virtualities, spin and colour
+ * averages); w_out[e] is the average over the two assignments, 0
+ * where x1 or x2 leaves (0, 1].  FP32 or FP64 per the process precision.
+ * w_out: n_events doubles, device memory when ev->on_device, else host
+ * (may be null when n_events is 0).
+ * MEM_EUNSUPPORTED for other kinds; MEM_EINVAL for null pointers, fewer
+ * than 6 objects, or (host events) non-finite or non-positive-energy
+ * objects. */
+mem_status mem_parton_weights(mem_process p, const mem_events* ev, double* w_out, void* stream);
+
 /* VEGAS damped rebinning (Lepage 1978) of n_int x D grids in place from
  * per-bin sums of w^2.  bins: device [n_int][D][64]; grids: device
  * [n_int][D][65]; alpha > 0. */
@@ -281,8 +300,10 @@ mem_status mem_vegas_refine(const double* bins, double* grids, int32_t n_int, in
  * w = f(x) J(x) (Sec. 2: the weight of x is its share of the integral).
  * x_out: device float [n_int][n_per][D]; w_out: device float
  * [n_int][n_per]; normalise != 0 divides each integral's weights by their
- * sum.  event, perm: device int32 [n_int].  MEM_EINVAL on null pointers or
- * n_per < 1. */
+ * sum.  event, perm: device int32 [n_int].  Every process kind (D = 2, 8,
+ * 7, 9 for Drell-Yan, dilepton, semileptonic, t tbar H); w is rounded to
+ * FP32 (t tbar H weights, ~1e-40 with the physical constants, come out
+ * subnormal or zero).  MEM_EINVAL on null pointers or n_per < 1. */
 mem_status mem_vegas_capture(mem_process p, const mem_events* ev, const int32_t* event, const int32_t* perm,
                              int32_t n_int, const double* grids, int64_t n_per, uint64_t seed, uint32_t iter,
                              int32_t normalise, float* x_out, float* w_out, void* stream);

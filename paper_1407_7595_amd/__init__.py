@@ -27,7 +27,7 @@ EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_proc
            "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
-           "mem_process_chunk_points", "mem_status_string", "mem_last_error")
+           "mem_process_chunk_points", "mem_parton_weights", "mem_status_string", "mem_last_error")
 
 
 class ProcessDesc(ctypes.Structure):
@@ -80,6 +80,7 @@ def lib():
             "mem_integrate_events": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
             "mem_uniforms": (I32, [U64, U32, U32, U32, I32, I64, P, P]),
             "mem_eval_points": (I32, [P, P, I32, I32, P, I64, P, P, P]),
+            "mem_parton_weights": (I32, [P, P, P, P]),
             "mem_vegas_refine": (I32, [P, P, I32, I32, D, P]),
             "mem_vegas_capture": (I32, [P, P, P, P, I32, P, I64, U64, U32, I32, P, P, P]),
             "mem_flow_create": (I32, [I32, P]),
@@ -245,6 +246,18 @@ def eval_points(process, comps, event, perm, x, f, nsol=None, stream=None, charg
                                  ctypes.c_void_p(nsol.data_ptr()) if nsol is not None else None,
                                  _stream_ptr(stream)), "mem_eval_points")
     return f
+
+
+def parton_weights(process, comps, out=None, stream=None):
+    """mem_parton_weights: comps [4, 6, n_events] float64 (b, bbar, l+, l-,
+    nu, nubar) on the device or the host; returns the weights [n_events]
+    float64 on the same device (or writes into `out`)."""
+    import torch
+    ev = events_struct(comps, None)
+    w = torch.empty(ev.n_events, dtype=torch.float64, device=comps.device) if out is None else out
+    _check(lib().mem_parton_weights(process.handle, ctypes.byref(ev), ctypes.c_void_p(w.data_ptr()),
+                                    _stream_ptr(stream)), "mem_parton_weights")
+    return w
 
 
 def vegas_refine(bins, grids, alpha=1.5, stream=None):

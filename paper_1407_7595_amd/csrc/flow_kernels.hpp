@@ -310,7 +310,7 @@ __global__ void flow_iter_end_kernel(uint32_t* iter_p) { if (threadIdx.x == 0) *
 // density of x is 1/J, so w/sum(w) weights each point by its share of the
 // integrand (the flow's training target).  Thread per point.
 template <int KIND, int D, class T>
-__global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void capture_kernel(
+__global__ __launch_bounds__(kBlock, KIND == kTTH ? 2 : MEM_TT_WAVES) void capture_kernel(
     ProcParams pp, EventsView ev, const int32_t* __restrict__ event, const int32_t* __restrict__ perm,
     int n_int, const double* __restrict__ grids, int64_t n_per, uint64_t seed, uint32_t iter,
     float* __restrict__ xo, float* __restrict__ wo)
@@ -333,6 +333,10 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void capture_kernel(
     SLEvent se;
     sl_load(ev, ev.charge, e, pm, se);
     f = sl_integrand<T>(pp, se, x, nullptr);
+  } else if constexpr (KIND == kTTH) {
+    TTHEvent he;
+    tth_load(ev, ev.charge, e, pm, he);
+    f = tth_integrand<T>(pp, he, x, nullptr);
   } else {
     DYEvent de;
     dy_load(ev, e, de);

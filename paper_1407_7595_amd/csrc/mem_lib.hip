@@ -98,6 +98,7 @@ static void derive(mem_process_s* p)
     double gs2 = 4.0 * M_PI * d.alpha_s;
     double gw2 = 8.0 * d.g_fermi * d.m_w * d.m_w / std::sqrt(2.0);
     double coup = gs2 * gs2 * std::pow(gw2 / 2.0, 4);
+    pp.me_const = coup;
     // (2 pi)^(4 - 3*6) (2/S) / (2 shat) / (2E_nu 2E_nubar): shat, E's per point
     pp.tt_const = std::pow(two_pi, -14.0) * (2.0 / pp.S) * 0.5 * 0.25 * coup * kbw;
     // semileptonic: hadronic W, hadronic top and leptonic W aligned; the
@@ -912,6 +913,58 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
   return MEM_OK;
 }
 
+// Parton-level weights: one thread per event, the two b assignments in
+// order (objects b, bbar, l+, l-, nu, nubar; assignment 1 swaps the b's).
+template <class T>
+__global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void parton_kernel(ProcParams pp, EventsView ev,
+                                                                      double* __restrict__ w)
+{
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= ev.n_events) return;
+  v4 o[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ev.load(k, e, o[k].e, o[k].x, o[k].y, o[k].z);
+  const double w0 = tt_parton<T>(pp, o[0], o[2], o[4], o[1], o[3], o[5]);
+  const double w1 = tt_parton<T>(pp, o[1], o[2], o[4], o[0], o[3], o[5]);
+  w[e] = 0.5 * (w0 + w1);
+}
+
+extern "C" mem_status mem_parton_weights(mem_process p, const mem_events* ev, double* w_out, void* stream)
+{
+  if (!p) return fail(MEM_EINVAL, "null argument");
+  mem_status st = check_event_arrays(ev);
+  if (st != MEM_OK) return st;
+  if (!w_out && ev->n_events > 0) return fail(MEM_EINVAL, "null argument");
+  if (p->desc.kind != MEM_TT_DILEPTON) return fail(MEM_EUNSUPPORTED, "parton-level weights: ttbar dilepton only");
+  if (ev->n_obj < 6) return fail(MEM_EINVAL, "parton-level events need 6 objects");
+  for (int e = 0; e < ev->n_events; ++e) {
+    st = check_host_event(ev, e, 6);
+    if (st != MEM_OK) return st;
+  }
+  if (ev->n_events == 0) return MEM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  DevEvents dev;
+  st = dev.make(ev, s);
+  if (st != MEM_OK) return st;
+  DevBuf wbuf;
+  double* w = w_out;
+  if (!ev->on_device) {
+    HIP_TRY(wbuf.alloc((size_t)ev->n_events * sizeof(double)));
+    w = wbuf.as<double>();
+  }
+  dim3 grid((unsigned)((ev->n_events + kBlock - 1) / kBlock));
+  if (p->desc.precision == MEM_FP32)
+    hipLaunchKernelGGL(parton_kernel<float>, grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
+  else
+    hipLaunchKernelGGL(parton_kernel<double>, grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
+  HIP_TRY(hipGetLastError());
+  if (!ev->on_device) {
+    HIP_TRY(hipMemcpyAsync(w_out, w, (size_t)ev->n_events * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return MEM_OK;
+}
+
 extern "C" mem_status mem_vegas_refine(const double* bins, double* grids, int32_t n_int, int32_t D, double alpha,
                                        void* stream)
 {
@@ -1081,13 +1134,24 @@ extern "C" mem_status mem_vegas_capture(mem_process p, const mem_events* ev, con
         hipLaunchKernelGGL((capture_kernel<kSL, 7, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
                            perm, n_int, grids, n_per, seed, iter, x_out, w_out);
       break;
-    default:
+    case MEM_TTH_SEMILEPTON:
+      if (f32)
+        hipLaunchKernelGGL((capture_kernel<kTTH, 9, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                           perm, n_int, grids, n_per, seed, iter, x_out, w_out);
+      else
+        hipLaunchKernelGGL((capture_kernel<kTTH, 9, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                           perm, n_int, grids, n_per, seed, iter, x_out, w_out);
+      break;
+    case MEM_TT_DILEPTON:
       if (f32)
         hipLaunchKernelGGL((capture_kernel<kTT, 8, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
                            n_int, grids, n_per, seed, iter, x_out, w_out);
       else
         hipLaunchKernelGGL((capture_kernel<kTT, 8, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
                            perm, n_int, grids, n_per, seed, iter, x_out, w_out);
+      break;
+    default:
+      return fail(MEM_EINVAL, "unknown process kind");
   }
   HIP_TRY(hipGetLastError());
   if (normalise) {

@@ -27,8 +27,8 @@ enum { F64 = 0, F32 = 1 };
 struct CF;
 struct CD {
   double v;
-  CD() : v(0) {}
-  CD(double x) : v(x) {}
+  constexpr CD() : v(0) {}
+  constexpr CD(double x) : v(x) {}
   CD(float x) : v(x) {}
   CD(int x) : v(x) {}
   CD(unsigned x) : v(x) {}

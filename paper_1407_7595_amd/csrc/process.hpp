@@ -44,6 +44,8 @@ struct ProcParams {
   // t tbar H: as sl_const with the Higgs map, the Yukawa coupling and the
   // H -> b bbar decay (times q2_H per point)
   double tth_const;
+  // couplings of the t tbar |M|^2: g_s^4 (g_W^2 / 2)^4
+  double me_const;
 };
 
 struct EventsView {

@@ -128,7 +128,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
   const double disc = a * a - lt2 * (nx * nx + ny * ny);
   if (!(a > 0.0) || disc < 0.0 || !(lt2 > 0.0)) return 0.0;
   const double sq = l.e * sqrt(disc), ilt2 = fast_rcp(lt2);
-  const T mt = T(pp.m_t);
+  const T mt = T(pp.m_t * kMeScale);      // matrix-element units
   const double isqs = pp.inv_sqrt_s;
   const v4 vis = add(add(add(qa, qb), add(bh, bl)), l);
   double acc = 0.0;
@@ -149,9 +149,9 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
     const double dtl = mdot(tl4, tl4) - pp.m_t * pp.m_t;
     const double bwtl = fast_rcp(dtl * dtl + mtg * mtg);
     TBoost B(P);
-    const v4 hqa = B.apply64(qa), hqb = B.apply64(qb), hbh = B.apply64(bh);
-    const v4 hbl = B.apply64(bl), hl = B.apply64(l), hn = B.apply64(nu);
-    const double ak = 0.5 * x1 * pp.sqrt_s, bk = 0.5 * x2 * pp.sqrt_s;
+    const v4 hqa = B.apply_me(qa), hqb = B.apply_me(qb), hbh = B.apply_me(bh);
+    const v4 hbl = B.apply_me(bl), hl = B.apply_me(l), hn = B.apply_me(nu);
+    const double ak = 0.5 * x1 * pp.sqrt_s * kMeScale, bk = 0.5 * x2 * pp.sqrt_s * kMeScale;
     const v4 k1{ak, 0.0, 0.0, ak}, k2{bk, 0.0, 0.0, -bk};
     const double o1 = 1.0 - x1, o2 = 1.0 - x2;
     const T g1 = T(3.0 * o1 * o1 * o1 * o1 * o1), g2 = T(3.0 * o2 * o2 * o2 * o2 * o2);
@@ -181,7 +181,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
       me += g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
     }
     const double shat = x1 * x2 * pp.S;
-    acc += P.e * (double)me * bwtl * fast_rcp(Eh * shat * x1 * x2 * dq * nu.e);
+    acc += P.e * ((double)me * kMeDeg8) * bwtl * fast_rcp(Eh * shat * x1 * x2 * dq * nu.e);
   }
   if (nsol_out) *nsol_out = ns;
   return acc * pp.sl_const * (double)jetf * fast_rcp(2.0 * l.e);

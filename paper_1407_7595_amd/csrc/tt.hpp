@@ -84,6 +84,12 @@ struct TBoost {
     double bp = bx * v.x + by * v.y;
     return v4{g * (v.e - bp), v.x + (g2 * bp - g * v.e) * bx, v.y + (g2 * bp - g * v.e) * by, v.z};
   }
+  // boosted and in matrix-element units (kMeScale, exact)
+  __device__ __forceinline__ v4 apply_me(const v4& v) const
+  {
+    const v4 h = apply64(v);
+    return v4{h.e * kMeScale, h.x * kMeScale, h.y * kMeScale, h.z * kMeScale};
+  }
 };
 
 // The integrand in stages.  tt_maps: per point, the jet energies, TFs,
@@ -130,29 +136,33 @@ __device__ __forceinline__ v4 tt_jet(const TTEvent& ev, int k, double E)
   return v4{E, E * ev.n[k][0], E * ev.n[k][1], E * ev.n[k][2]};
 }
 
-// Weight of one neutrino solution sk of a point whose jets have parton
-// energies E0, E1 (0 when x1 or x2 falls outside (0, 1]).
+// |M|^2 x PDFs of a final state given in the lab (b, l+, nu from the top;
+// bbar, l-, nubar from the antitop): boost to zero transverse momentum,
+// x1, x2 = (E' +- P_z) / sqrt(S), the gg and q qbar channels with the toy
+// densities.  Returns false (me = 0) when x1 or x2 falls outside (0, 1];
+// P.e and E' (Eh) are returned for the energy delta function.
 template <class T>
-__device__ __forceinline__ double tt_solution(const ProcParams& pp, const TTEvent& ev, double E0, double E1,
-                                              const NuSol& sk)
+__device__ __forceinline__ bool tt_me_pdf(const ProcParams& pp, const v4& b0, const v4& lp, const v4& nu,
+                                          const v4& b1, const v4& lm, const v4& nb, double& me_out, double& Pe,
+                                          double& Eh, double& x1, double& x2)
 {
-  const v4 b0 = tt_jet(ev, 0, E0), b1 = tt_jet(ev, 1, E1);
-  v4 nu{0.0, sk.nx, sk.ny, sk.nz}, nb{0.0, sk.bx, sk.by, sk.bz};
-  nu.e = norm3(nu);
-  nb.e = norm3(nb);
-  const v4 P = add(add(add(b0, b1), add(ev.lp, ev.lm)), add(nu, nb));
-  const double Eh = sqrt(P.e * P.e - P.x * P.x - P.y * P.y);
-  const double x1 = (Eh + P.z) * pp.inv_sqrt_s, x2 = (Eh - P.z) * pp.inv_sqrt_s;
-  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
-  const T mt = T(pp.m_t);
+  me_out = 0.0;
+  const v4 P = add(add(add(b0, b1), add(lp, lm)), add(nu, nb));
+  Pe = P.e;
+  Eh = sqrt(P.e * P.e - P.x * P.x - P.y * P.y);
+  x1 = (Eh + P.z) * pp.inv_sqrt_s;
+  x2 = (Eh - P.z) * pp.inv_sqrt_s;
+  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return false;
+  // |M|^2 in the hard frame, in matrix-element units
+  const T mt = T(pp.m_t * kMeScale);
   TBoost B(P);
-  const v4 hb = B.apply64(b0), hl = B.apply64(ev.lp), hn = B.apply64(nu);
-  const v4 hbb = B.apply64(b1), hlm = B.apply64(ev.lm), hnb = B.apply64(nb);
+  const v4 hb = B.apply_me(b0), hl = B.apply_me(lp), hn = B.apply_me(nu);
+  const v4 hbb = B.apply_me(b1), hlm = B.apply_me(lm), hnb = B.apply_me(nb);
   const v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
   const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
   drow<T> R, C;
   decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
-  const double a = 0.5 * x1 * pp.sqrt_s, bm = 0.5 * x2 * pp.sqrt_s;
+  const double a = 0.5 * x1 * pp.sqrt_s * kMeScale, bm = 0.5 * x2 * pp.sqrt_s * kMeScale;
   const T mgg = gg_sum<T>(R, C, pt, T(a), T(bm), mt);
   const v4 k1{a, 0.0, 0.0, a}, k2{bm, 0.0, 0.0, -bm};
   const T mq1 = qq_sum<T>(R, C, k1, k2);
@@ -163,8 +173,53 @@ __device__ __forceinline__ double tt_solution(const ProcParams& pp, const TTEven
   const T q1 = T(xfu(x1, o1) + xfd(x1, o1)), q2 = T(xfu(x2, o2) + xfd(x2, o2));
   const T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
   const T me = g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
+  me_out = (double)me * kMeDeg8;
+  return true;
+}
+
+// Weight of one neutrino solution sk of a point whose jets have parton
+// energies E0, E1 (0 when x1 or x2 falls outside (0, 1]).
+template <class T>
+__device__ __forceinline__ double tt_solution(const ProcParams& pp, const TTEvent& ev, double E0, double E1,
+                                              const NuSol& sk)
+{
+  const v4 b0 = tt_jet(ev, 0, E0), b1 = tt_jet(ev, 1, E1);
+  v4 nu{0.0, sk.nx, sk.ny, sk.nz}, nb{0.0, sk.bx, sk.by, sk.bz};
+  nu.e = norm3(nu);
+  nb.e = norm3(nb);
+  double me, Pe, Eh, x1, x2;
+  if (!tt_me_pdf<T>(pp, b0, ev.lp, nu, b1, ev.lm, nb, me, Pe, Eh, x1, x2)) return 0.0;
   const double shat = x1 * x2 * pp.S;
-  return P.e * (double)me * fast_rcp(Eh * shat * x1 * x2 * sk.adet * nu.e * nb.e);
+  return Pe * me * fast_rcp(Eh * shat * x1 * x2 * sk.adet * nu.e * nb.e);
+}
+
+// Breit-Wigner factor 1 / ((q2 - m^2)^2 + m^2 Gamma^2)
+__device__ __forceinline__ double bw_factor(double q2, double m, double w)
+{
+  const double d = q2 - m * m;
+  return fast_rcp(d * d + m * m * w * w);
+}
+
+// Parton-level weight of one assignment (transfer functions are delta
+// functions; Sec. 4's parton-level timing): the energy and longitudinal
+// momentum delta functions (2/S) (E / E'), the flux 1/(2 shat) and the
+// complete |M|^2 times the densities f(x1) f(x2).  tt_me_pdf works with
+// x f(x) and leaves out the couplings and the four top and W Breit-Wigner
+// factors (in the integrand the maps' Jacobians cancel those):
+// me_const / (x1 x2) and the factors at the partons' virtualities restore
+// them.
+template <class T>
+__device__ __forceinline__ double tt_parton(const ProcParams& pp, const v4& b0, const v4& lp, const v4& nu,
+                                           const v4& b1, const v4& lm, const v4& nb)
+{
+  double me, Pe, Eh, x1, x2;
+  if (!tt_me_pdf<T>(pp, b0, lp, nu, b1, lm, nb, me, Pe, Eh, x1, x2)) return 0.0;
+  const v4 wp = add(lp, nu), wm = add(lm, nb), t = add(b0, wp), tb = add(b1, wm);
+  const double bw = bw_factor(mdot(t, t), pp.m_t, pp.w_t) * bw_factor(mdot(tb, tb), pp.m_t, pp.w_t)
+                  * bw_factor(mdot(wp, wp), pp.m_w, pp.w_w) * bw_factor(mdot(wm, wm), pp.m_w, pp.w_w);
+  const double shat = x1 * x2 * pp.S;
+  return (2.0 * pp.inv_sqrt_s * pp.inv_sqrt_s) * (Pe * fast_rcp(Eh)) * pp.me_const * bw * me
+         * fast_rcp(2.0 * shat * x1 * x2);
 }
 
 // The point's value from the sum of its solution weights.

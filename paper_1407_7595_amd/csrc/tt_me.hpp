@@ -25,6 +25,15 @@
 
 namespace memk {
 
+// Unit of the momenta and masses that enter |M|^2: 256 GeV.  Without its
+// Breit-Wigner denominators the six-fermion |M|^2 is homogeneous of degree
+// 8 in momenta and masses.  In GeV its values exceed the FP32 range when a
+// neutrino carries several TeV (a far off-shell leptonic W), while in units
+// of 256 GeV they sit near 1.  The unit is a power of two, so the rescaling
+// is exact and FP64 results do not change.
+constexpr double kMeScale = 1.0 / 256.0;       // GeV -> matrix-element units
+constexpr double kMeDeg8 = 0x1p64;             // 256^8: |M|^2 back to GeV units
+
 template <class T> struct cx { T re, im; };
 template <class T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }

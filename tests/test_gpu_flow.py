@@ -332,6 +332,70 @@ def test_vegas_capture_matches_oracle(mem):
     assert np.allclose(s, 1.0, rtol=1e-5)
 
 
+@pytest.mark.parametrize("kind", ["dy", "sl", "tth"])
+def test_vegas_capture_every_process(mem, kind):
+    """capture of the other process kinds on adapted grids: x bit-equal to
+    the oracle's VEGAS map, w = f J within the FP32 integrand bar (points
+    whose oracle value moves by more than a tenth of the bar under 1-ulp
+    changes of x are counted and excluded).  t tbar H weights lie near the
+    bottom of the FP32 range (~1e-40): they are compared after rounding the
+    oracle's weight to FP32, with an absolute slack of two subnormal steps."""
+    n_obj, D, npm = {"dy": (2, 2, 1), "sl": (5, 7, 12), "tth": (7, 9, 24)}[kind]
+    if kind == "dy":
+        p = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+        po, okind, obs, bar = oracle.dy_params(), oracle.KIND_DY, events.drell_yan(2, 81)["obs"], 1e-6
+        f_or = lambda ev, perm, x: oracle.dy_integrand(po, ev, x)
+    else:
+        p = mem.Process(mem.MEM_TT_SEMILEPTON if kind == "sl" else mem.MEM_TTH_SEMILEPTON, precision=mem.MEM_FP32)
+        po, bar = oracle.tt_params(), 2e-5
+        okind = oracle.KIND_TT_SL if kind == "sl" else oracle.KIND_TTH
+        obs = (events.ttbar_semileptonic(2, 82) if kind == "sl" else events.ttbar_higgs(2, 83))["obs"]
+        fn = oracle.sl_integrand if kind == "sl" else oracle.tth_integrand
+        f_or = lambda ev, perm, x: fn(po, ev, perm, x)[0]
+    comps = torch.as_tensor(np.ascontiguousarray(obs[:, :n_obj, :].transpose(2, 1, 0))).cuda()
+    charge = torch.as_tensor(obs[:, n_obj, 0].astype(np.int32) if kind != "dy" else np.ones(2, np.int32)).cuda()
+    grids = torch.empty((2 * npm, D, 65), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, p, 2048 * npm, 3, seed=41, grid_out=grids, charge=charge)
+    # integrals (event 0, perm 0) and (event 1, last perm)
+    sel = [0, 2 * npm - 1]
+    ev_idx, perm_idx = np.array([0, 1]), np.array([0, npm - 1])
+    g = grids[sel].contiguous()
+    n_per, seed, it = 600, 43, 3
+    x = torch.empty((2, n_per, D), dtype=torch.float32, device="cuda")
+    w = torch.empty((2, n_per), dtype=torch.float32, device="cuda")
+    say(f"capture {kind}: 2 integrals x {n_per}")
+    mem.vegas_capture(p, comps, dev(ev_idx, torch.int32), dev(perm_idx, torch.int32), g, n_per, seed, it, x, w,
+                      normalise=0, charge=charge)
+    torch.cuda.synchronize()
+    xg, wg, gh = x.cpu().numpy(), w.cpu().numpy(), g.cpu().numpy()
+    n_cmp = n_flag = 0
+    for i in range(2):
+        ev = obs[ev_idx[i]]
+        for k in range(n_per):
+            u = oracle.uniforms(seed, k, it, ev_idx[i], perm_idx[i], D)
+            xo, jac, _ = oracle.vegas_map(gh[i], u)
+            assert np.array_equal(xg[i, k], xo.astype(np.float32)), (i, k)
+            wo = oracle.weight_at(okind, po, ev, perm_idx[i], gh[i], u)
+            assert np.isfinite(wg[i, k]), (i, k)
+            if wo == 0.0 and wg[i, k] == 0.0:
+                continue
+            if abs(float(wg[i, k]) - float(np.float32(wo))) <= bar * abs(wo) + 2 * 2.0 ** -149:
+                n_cmp += 1
+                continue
+            if abs(wg[i, k] - wo) > bar * abs(wo):
+                f0 = wo / jac
+                moved = False
+                for xp in (np.nextafter(xo, 1.0), np.nextafter(xo, 0.0), xo * (1 + 2e-16)):
+                    f1 = f_or(ev, perm_idx[i], np.clip(xp, 0.0, 1.0 - 2 ** -53))
+                    moved |= abs(f1 - f0) > 0.1 * bar * max(abs(f0), 1e-300)
+                assert moved, (kind, i, k, wg[i, k], wo)
+                n_flag += 1
+                continue
+            n_cmp += 1
+    say(f"{kind}: compared {n_cmp} nonzero weights, {n_flag} flagged ill-conditioned")
+    assert n_cmp > 20 and n_flag <= 0.02 * n_cmp + 2
+
+
 # --------------------------------------------------------------- estimator --
 def test_flow_fallback_is_vegas(mem):
     """an ESS threshold no proposal can meet sends every event to VEGAS:

@@ -354,6 +354,58 @@ def test_sl_integrand(mem, precision, tol):
     assert n_cmp > 150
 
 
+# Far off-shell W bosons (their tan-map variable within 1e-4 of 1) put
+# several TeV on a neutrino; the FP32 |M|^2, homogeneous of degree 8 in the
+# momenta, then leaves the FP32 range unless it is formed in units of
+# 256 GeV.  Every value must be finite.  In this corner the single diagrams
+# of gg -> t tbar grow with the off-shell tops' energy while their sum does
+# not, and FP32 rounding of the diagrams shows in the sum: the dilepton
+# points reach a median of 1.6e-6 and a 99th percentile of 1.7e-5 (a host
+# model of the FP32 arithmetic shows the same), so the accuracy bars here are
+# percentiles ten times looser than on ordinary points.
+@pytest.mark.parametrize("kind", ["tt", "sl"])
+def test_fp32_far_off_shell(mem, kind):
+    rng = np.random.default_rng(31)
+    if kind == "tt":
+        p, po = tt_process(mem, 1), oracle.tt_params()
+        d = events.ttbar_dilepton(64, 21)
+        comps, charge, D, perms = mem.to_components(d["obs"]).cuda(), None, 8, (0, 1)
+    else:
+        p, po = mem.Process(mem.MEM_TT_SEMILEPTON, precision=1), oracle.sl_params()
+        d = events.ttbar_semileptonic(4, 61)
+        comps, charge = sl_split(d["obs"])
+        comps, charge, D, perms = comps.cuda(), charge.cuda(), 7, (0, 5, 11)
+    rel = []
+    for e in range(len(d["obs"])):
+        for perm in perms:
+            x = rng.random((4000 if kind == "tt" else 500, D))
+            if kind == "tt":
+                # top and W+ virtualities both far above their poles (the
+                # band where solutions exist and the GeV-unit FP32 |M|^2
+                # overflowed)
+                x[:, 2] = 1.0 - 10.0 ** (-4.8 - 0.7 * x[:, 2])
+                x[:, 4] = 1.0 - 10.0 ** (-4.2 - 0.7 * x[:, 4])
+            else:
+                x[:, 6] = 1.0 - 10.0 ** (-4.0 - 1.5 * x[:, 6])
+            say(f"far off-shell {kind} event={e} perm={perm}")
+            f = torch.empty(len(x), dtype=torch.float64, device="cuda")
+            mem.eval_points(p, comps, e, perm, dev(x), f, charge=charge)
+            torch.cuda.synchronize()
+            got = f.cpu().numpy()
+            assert np.all(np.isfinite(got)), (kind, e, perm, got[~np.isfinite(got)][:4])
+            integ = oracle.tt_integrand if kind == "tt" else oracle.sl_integrand
+            for k, xi in enumerate(x):
+                want = integ(po, d["obs"][e], perm, xi)[0]
+                if want == 0.0 and got[k] == 0.0:
+                    continue
+                rel.append(abs(got[k] - want) / max(abs(want), 1e-300))
+    rel = np.array(rel)
+    say(f"{kind}: {len(rel)} nonzero points, median {np.median(rel):.3g}, p99 {np.quantile(rel, 0.99):.3g}, "
+        f"max {rel.max():.3g}")
+    assert len(rel) > (200 if kind == "tt" else 400)
+    assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.99) <= 1e-4 and rel.max() <= 3e-4
+
+
 def test_sl_iteration0_sums(mem):
     p = mem.Process(mem.MEM_TT_SEMILEPTON, precision=mem.MEM_FP32)
     po = oracle.sl_params()

@@ -1,0 +1,87 @@
+"""Parton-level weights on the GPU (mem_parton_weights) against the FP64
+oracle: FP64 within 1e-10 relative on every event; FP32 within 1e-5 at the
+99.9th percentile and within 3e-5 on every event (device and host event
+arrays), the empty batch, and the error paths.  The FP32 tail: events whose
+gg amplitudes cancel strongly between the t-channel and s-channel diagrams
+lose log10 of that cancellation in digits to the FP32 rounding of the
+individual diagrams (1 event in 3000 at 1.4e-5 with the oracle's weight
+stable under 1-ulp input changes).  The FP64 bar:
+the GPU forms the top and W virtualities E^2 - p^2 from lab momenta, the
+oracle in the zero-transverse-momentum frame; near a Breit-Wigner pole
+(q^2 - m^2 ~ 10 GeV^2 against E^2 ~ 1e5 GeV^2) their rounding is amplified
+to ~1e-11 relative (a host build of the device formula agrees with the
+oracle to 9.5e-12 over 300 events)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import events
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mem():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1407_7595_amd as m
+    m.lib()
+    return m
+
+
+def comps_of(obs, device="cuda"):
+    return torch.as_tensor(np.ascontiguousarray(obs.transpose(2, 1, 0)), dtype=torch.float64, device=device)
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-10)])
+def test_parton_weights_match_oracle(mem, precision, tol):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=precision)
+    po = oracle.tt_params()
+    d = events.ttbar_dilepton_partons(3000, 11)
+    say(f"parton weights precision={precision}: 3000 events")
+    w = mem.parton_weights(p, comps_of(d["obs"]))
+    torch.cuda.synchronize()
+    got = w.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    want = np.array([oracle.tt_parton_weight(po, ev) for ev in d["obs"]])
+    assert np.all(want > 0.0)
+    rel = np.abs(got - want) / want
+    q999 = np.quantile(rel, 0.999)
+    say(f"  worst rel {rel.max():.3g}, 99.9 % {q999:.3g}, median {np.median(rel):.3g}")
+    if precision == 0:
+        assert rel.max() <= tol
+    else:
+        assert q999 <= tol and rel.max() <= 3 * tol
+
+
+def test_parton_weights_host_arrays_and_edges(mem):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = events.ttbar_dilepton_partons(257, 12)          # ragged: one full block and one lane
+    say("parton weights: host arrays, 257 events")
+    wd = mem.parton_weights(p, comps_of(d["obs"]))
+    wh = mem.parton_weights(p, comps_of(d["obs"], "cpu"))
+    torch.cuda.synchronize()
+    assert np.array_equal(wd.cpu().numpy(), wh.numpy())
+    # empty batch
+    e = mem.parton_weights(p, torch.zeros((4, 6, 0), dtype=torch.float64, device="cuda"))
+    assert e.numel() == 0
+    # fewer than 6 objects, other process kinds
+    with pytest.raises(mem.MemError):
+        mem.parton_weights(p, comps_of(d["obs"][:, :4]))
+    sl = mem.Process(mem.MEM_TT_SEMILEPTON, precision=mem.MEM_FP32)
+    with pytest.raises(mem.MemError):
+        mem.parton_weights(sl, comps_of(d["obs"]))
+    # a non-finite host event is rejected before any launch
+    bad = d["obs"].copy()
+    bad[3, 4, 1] = np.nan
+    with pytest.raises(mem.MemError):
+        mem.parton_weights(p, comps_of(bad, "cpu"))
