@@ -29,7 +29,50 @@ class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sqrt_s", "m_t", "w_t", "m_w", "w_w", "alpha", "alpha_s", "g_fermi",
         "sigma_k", "tf_sigma", "r_lo", "r_hi", "m_lo", "m_hi",
-        "lj_core", "lj_tail", "lj_ftail", "lj_r_lo", "lj_r_hi", "m_h", "w_h", "m_b")]
+        "lj_core", "lj_tail", "lj_ftail", "lj_r_lo", "lj_r_hi", "m_h", "w_h", "m_b")] + [
+        ("pdf", ctypes.c_void_p)]
+
+
+class _PdfGridC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("nq", ctypes.c_int), ("lx_min", ctypes.c_double),
+                ("lx_max", ctypes.c_double), ("lq_min", ctypes.c_double), ("lq_max", ctypes.c_double),
+                ("xf", ctypes.c_void_p)]
+
+
+class PdfGrid:
+    """x f(x, Q) of the flavours -5..5 on a uniform (ln x, ln Q) grid,
+    values float32 [nq][nx][11]; bounds (lx_min, lx_max, lq_min, lq_max)."""
+
+    def __init__(self, xf, bounds):
+        self.xf = np.ascontiguousarray(xf, dtype=np.float32)
+        nq, nx, nf = self.xf.shape
+        assert nf == 11 and nx >= 2 and nq >= 2
+        self.bounds = tuple(float(b) for b in bounds)
+        self.c = _PdfGridC(nx, nq, *self.bounds, self.xf.ctypes.data)
+
+    def ptr(self):
+        return ctypes.cast(ctypes.pointer(self.c), ctypes.c_void_p)
+
+
+def with_pdf(params, grid):
+    """a copy of params whose integrands take their densities from grid
+    (None: the toy densities)"""
+    q = Params()
+    ctypes.pointer(q)[0] = params
+    q.pdf = grid.ptr().value if grid is not None else None
+    q._grid = grid          # keep the table alive
+    return q
+
+
+def pdf_interp(grid, fl, x, Q):
+    return lib().or_pdf_interp(ctypes.byref(grid.c), int(fl), float(x), float(Q))
+
+
+def pdf_tabulate_toy(nx, nq, bounds):
+    xf = np.zeros((nq, nx, 11), dtype=np.float32)
+    g = PdfGrid(xf, bounds)
+    lib().or_pdf_tabulate_toy(ctypes.byref(g.c), xf.ctypes.data)
+    return g
 
 
 class Result(ctypes.Structure):
@@ -95,6 +138,8 @@ def _declare(L):
         "or_dy_sigma_tau": (D, [P, I]),
         "or_tt_integrand": (D, [P, P, I, P, P]),
         "or_tt_parton_weight": (D, [P, P]),
+        "or_pdf_interp": (D, [P, ctypes.c_int, D, D]),
+        "or_pdf_tabulate_toy": (None, [P, P]),
         "or_decay_w_factor": (D, [P, D]),
         "or_ps_volume": (D, [I, D, U64, I64, P]),
         "or_top_width": (D, [P, U64, I64, P]),

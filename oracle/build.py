@@ -7,7 +7,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox_vegas.c", "dirac.c", "integrands.c", "driver.c", "flow.c", "phasespace.c"]
+SOURCES = ["philox_vegas.c", "dirac.c", "integrands.c", "driver.c", "flow.c", "phasespace.c", "pdfgrid.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

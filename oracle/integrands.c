@@ -24,6 +24,55 @@ double or_xf_d(double x) { return sqrt(x) * pow(1.0 - x, 4); }
 double or_xf_qbar(double x) { return 0.2 * pow(1.0 - x, 7); }
 double or_xf_g(double x) { return 3.0 * pow(1.0 - x, 5); }
 
+/* densities f = x f / x of the 11 flavours at (x, Q) from the grid */
+static void grid_f(const or_params* p, double x, double Q, double* f)
+{
+  for (int k = 0; k < 11; ++k) f[k] = or_pdf_interp(p->pdf, k - 5, x, Q) / x;
+}
+
+/* Parton luminosities of the top processes at (x1, x2) (Eq. mem_def: the
+ * densities of both beams): gg = f_g f_g, qq12 = sum_q f_q(x1) f_qbar(x2),
+ * qq21 = sum_q f_qbar(x1) f_q(x2), the sums over d, u, s, c, b.  Toy
+ * densities: u + d against the common sea antiquark. */
+typedef struct { double gg, qq12, qq21; } tt_lumi;
+static tt_lumi tt_lumis(const or_params* p, double x1, double x2)
+{
+  tt_lumi L;
+  if (!p->pdf) {
+    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
+    double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
+    double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
+    L.gg = g1 * g2;
+    L.qq12 = q1 * qb2;
+    L.qq21 = qb1 * q2;
+    return L;
+  }
+  double f1[11], f2[11];
+  grid_f(p, x1, p->m_t, f1);
+  grid_f(p, x2, p->m_t, f2);
+  L.gg = f1[5] * f2[5];
+  L.qq12 = L.qq21 = 0.0;
+  for (int q = 1; q <= 5; ++q) {
+    L.qq12 += f1[5 + q] * f2[5 - q];
+    L.qq21 += f1[5 - q] * f2[5 + q];
+  }
+  return L;
+}
+
+/* Drell-Yan luminosity sum_q e_q^2 (f_q(x1) f_qbar(x2) + f_qbar(x1) f_q(x2))
+ * at the scale Q (grid densities only; charges -1/3, 2/3, -1/3, 2/3, -1/3
+ * for d, u, s, c, b) */
+static double dy_grid_lumi(const or_params* p, double x1, double x2, double Q)
+{
+  static const double e2[6] = {0.0, 1.0 / 9.0, 4.0 / 9.0, 1.0 / 9.0, 4.0 / 9.0, 1.0 / 9.0};
+  double f1[11], f2[11];
+  grid_f(p, x1, Q, f1);
+  grid_f(p, x2, Q, f2);
+  double lum = 0.0;
+  for (int q = 1; q <= 5; ++q) lum += e2[q] * (f1[5 + q] * f2[5 - q] + f1[5 - q] * f2[5 + q]);
+  return lum;
+}
+
 double or_gauss_tf(double meas, double truth, double rel_sigma)
 {
   double s = rel_sigma * truth;
@@ -73,9 +122,14 @@ double or_dy_integrand(const or_params* p, const double* ev, const double* x)
   double c = cos_cs(mu[0], mu[1]);
   double e2 = 4.0 * M_PI * p->alpha;
   double me_unit = e2 * e2 * (1.0 + c * c) / 3.0;   /* for Q_q^2 = 1 */
-  double fu1 = or_xf_u(x1) / x1, fd1 = or_xf_d(x1) / x1, fq1 = or_xf_qbar(x1) / x1;
-  double fu2 = or_xf_u(x2) / x2, fd2 = or_xf_d(x2) / x2, fq2 = or_xf_qbar(x2) / x2;
-  double lum = 4.0 / 9.0 * (fu1 * fq2 + fq1 * fu2) + 1.0 / 9.0 * (fd1 * fq2 + fq1 * fd2);
+  double lum;
+  if (p->pdf) {
+    lum = dy_grid_lumi(p, x1, x2, M);
+  } else {
+    double fu1 = or_xf_u(x1) / x1, fd1 = or_xf_d(x1) / x1, fq1 = or_xf_qbar(x1) / x1;
+    double fu2 = or_xf_u(x2) / x2, fd2 = or_xf_d(x2) / x2, fq2 = or_xf_qbar(x2) / x2;
+    lum = 4.0 / 9.0 * (fu1 * fq2 + fq1 * fu2) + 1.0 / 9.0 * (fd1 * fq2 + fq1 * fd2);
+  }
   double shat = x1 * x2 * S;
   double flux = 1.0 / (2.0 * shat);
   double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 2.0);
@@ -532,12 +586,10 @@ double or_tt_integrand(const or_params* p, const double* ev, int perm,
     if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
     double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
     double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
-    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
-    double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
-    double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
-    double me = g1 * g2 * or_tt_me2_gg(p, k1, k2, hard)
-              + q1 * qb2 * or_tt_me2_qq(p, k1, k2, hard)
-              + qb1 * q2 * or_tt_me2_qq(p, k2, k1, hard);
+    const tt_lumi L = tt_lumis(p, x1, x2);
+    double me = L.gg * or_tt_me2_gg(p, k1, k2, hard)
+              + L.qq12 * or_tt_me2_qq(p, k1, k2, hard)
+              + L.qq21 * or_tt_me2_qq(p, k2, k1, hard);
     double shat = x1 * x2 * S;
     double f = (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat)
              / fabs(detj[s]) / (2.0 * v[0] * 2.0 * vb[0]);
@@ -570,12 +622,10 @@ static double parton_assignment(const or_params* p, const double* b, const doubl
   if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
   double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
   double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
-  double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
-  double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
-  double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
-  double me = g1 * g2 * or_tt_me2_gg(p, k1, k2, hard)
-            + q1 * qb2 * or_tt_me2_qq(p, k1, k2, hard)
-            + qb1 * q2 * or_tt_me2_qq(p, k2, k1, hard);
+  const tt_lumi L = tt_lumis(p, x1, x2);
+  double me = L.gg * or_tt_me2_gg(p, k1, k2, hard)
+            + L.qq12 * or_tt_me2_qq(p, k1, k2, hard)
+            + L.qq21 * or_tt_me2_qq(p, k2, k1, hard);
   double shat = x1 * x2 * S;
   return (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat);
 }
@@ -722,9 +772,7 @@ double or_tt_semilep_integrand(const or_params* p, const double* ev, int lep_cha
     boost_transverse(P, bl, hbl);
     boost_transverse(P, l, hl);
     boost_transverse(P, nu, hn);
-    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
-    double q1 = (or_xf_u(x1) + or_xf_d(x1)) / x1, qb1 = or_xf_qbar(x1) / x1;
-    double q2 = (or_xf_u(x2) + or_xf_d(x2)) / x2, qb2 = or_xf_qbar(x2) / x2;
+    const tt_lumi L = tt_lumis(p, x1, x2);
     double me = 0.0;
     for (int o = 0; o < 2; ++o) {
       /* light-jet ordering o: (quark, antiquark) of the hadronic W */
@@ -740,8 +788,8 @@ double or_tt_semilep_integrand(const or_params* p, const double* ev, int lep_cha
         memcpy(mom, hbh, 32); memcpy(mom + 4, qbk, 32); memcpy(mom + 8, qk, 32);
         memcpy(mom + 12, hbl, 32); memcpy(mom + 16, hl, 32); memcpy(mom + 20, hn, 32);
       }
-      me += g1 * g2 * or_tt_me2_gg(p, k1, k2, mom) + q1 * qb2 * or_tt_me2_qq(p, k1, k2, mom)
-          + qb1 * q2 * or_tt_me2_qq(p, k2, k1, mom);
+      me += L.gg * or_tt_me2_gg(p, k1, k2, mom) + L.qq12 * or_tt_me2_qq(p, k1, k2, mom)
+          + L.qq21 * or_tt_me2_qq(p, k2, k1, mom);
     }
     me *= 3.0 * 2.0;   /* colour of the hadronic W, two quark generations */
     double shat = x1 * x2 * S;
@@ -898,7 +946,14 @@ double or_tth_integrand(const or_params* p, const double* ev, int lep_charge, in
       memcpy(mom, h[2], 32); memcpy(mom + 4, qbk, 32); memcpy(mom + 8, qk, 32);
       memcpy(mom + 12, h[3], 32); memcpy(mom + 16, hl, 32); memcpy(mom + 20, hn, 32);
     }
-    double g1 = or_xf_g(x1) / x1, g2 = or_xf_g(x2) / x2;
+    double g1, g2;
+    if (p->pdf) {
+      g1 = or_pdf_interp(p->pdf, 0, x1, p->m_t) / x1;
+      g2 = or_pdf_interp(p->pdf, 0, x2, p->m_t) / x2;
+    } else {
+      g1 = or_xf_g(x1) / x1;
+      g2 = or_xf_g(x2) / x2;
+    }
     double me = g1 * g2 * or_tth_me2_gg(p, k1, k2, mom, h[4], h[5]) * 3.0 * 2.0;
     double shat = x1 * x2 * S;
     sum += (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat) / dq / (2.0 * nu[0]);

@@ -64,7 +64,34 @@ typedef struct {
   double lj_core, lj_tail, lj_ftail, lj_r_lo, lj_r_hi;
   /* Higgs mass and width, b mass in the H -> b bbar coupling (ttH) */
   double m_h, w_h, m_b;
+  /* parton densities from a grid (or_pdf_grid below); NULL: the toy
+   * densities */
+  const struct or_pdf_grid_s* pdf;
 } or_params;
+
+/* ------------------------------------------------------------ PDF grids -- */
+/* Parton densities from a table (Sec. 4: the densities of d, u, s, c, b,
+ * their antiquarks and the gluon are stored on grids in (x, Q) and
+ * evaluated by bilinear interpolation).  Readings: the grid is uniform in
+ * (ln x, ln Q) with its first and last nodes on the bounds,
+ *   ln x_i = lx_min + i (lx_max - lx_min) / (nx - 1),  i = 0 .. nx - 1,
+ * ln Q likewise, and holds x f(x, Q) of the 11 flavours fl = -5 .. 5
+ * (PDG codes: 1 d, 2 u, 3 s, 4 c, 5 b, negative for the antiquarks, 0 for
+ * the gluon) at index fl + 5, laid out [nq][nx][11]. */
+typedef struct or_pdf_grid_s {
+  int nx, nq;
+  double lx_min, lx_max, lq_min, lq_max;
+  const float* xf;
+} or_pdf_grid;
+/* x f(x, Q) of flavour fl: bilinear interpolation in (ln x, ln Q) over the
+ * grid cell that holds the point; outside the grid the edge cell's
+ * bilinear function continues (linear extrapolation).  0 for |fl| > 5. */
+double or_pdf_interp(const or_pdf_grid* g, int fl, double x, double Q);
+/* The toy densities tabulated at the nodes of g (u, d, ubar = dbar, g;
+ * s, c, b and their antiquarks zero) into xf_out [nq][nx][11]. */
+void or_pdf_tabulate_toy(const or_pdf_grid* g, float* xf_out);
+/* Factorisation scales (the paper does not state them): the pair mass for
+ * Drell-Yan, m_t for the top processes. */
 
 /* toy parton densities x*f(x) of the configuration, and the gluon choice */
 double or_xf_u(double x);

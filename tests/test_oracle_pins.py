@@ -839,3 +839,185 @@ def test_top_width_from_decay_phase_space():
     v, err = oracle.top_width(p, 0x70b, 400000)
     assert abs(v - want) < 4 * err + 2e-3 * want, (v, want, err)
     assert err < 3e-3 * want
+
+
+# ----------------------------------------------------------- PDF grids ----
+PDF_BOUNDS = (math.log(1e-5), 0.0, math.log(10.0), math.log(13000.0))
+
+
+def _grid_from(tables, nx=320, nq=16, bounds=PDF_BOUNDS, qfac=None):
+    """grid whose flavour fl holds tables[fl] (a function of x), times
+    qfac(ln Q) when given"""
+    lx = np.linspace(bounds[0], bounds[1], nx)
+    lq = np.linspace(bounds[2], bounds[3], nq)
+    xf = np.zeros((nq, nx, 11))
+    x = np.exp(lx)
+    for fl, f in tables.items():
+        col = np.array([f(v) if v < 1.0 else 0.0 for v in x])
+        for j in range(nq):
+            xf[j, :, fl + 5] = col * (qfac(lq[j]) if qfac else 1.0)
+    return oracle.PdfGrid(xf.astype(np.float32), bounds)
+
+
+def _toy_tables():
+    L = oracle.lib()
+    return {2: L.or_xf_u, 1: L.or_xf_d, -2: L.or_xf_qbar, -1: L.or_xf_qbar, 0: L.or_xf_g}
+
+
+def test_pdf_grid_bilinear_exact():
+    """the interpolant reproduces c0 + c1 ln x + c2 ln Q + c3 ln x ln Q (a
+    different one per flavour) inside the grid and, by linear
+    extrapolation of the edge cells, outside it; node values exact"""
+    b = (-8.0, 0.0, 1.0, 5.0)                 # unit node spacing, exact in FP32
+    nx, nq = 9, 5
+    coef = {fl: (fl + 7.0, 0.5 * fl - 1.0, 2.0 - 0.25 * fl, 0.125 * (fl + 2)) for fl in range(-5, 6)}
+    lx, lq = np.linspace(b[0], b[1], nx), np.linspace(b[2], b[3], nq)
+    xf = np.zeros((nq, nx, 11))
+    for fl, (c0, c1, c2, c3) in coef.items():
+        xf[:, :, fl + 5] = c0 + c1 * lx[None, :] + c2 * lq[:, None] + c3 * lx[None, :] * lq[:, None]
+    g = oracle.PdfGrid(xf.astype(np.float32), b)
+    assert np.array_equal(g.xf, xf)
+    rng = np.random.default_rng(5)
+    for a, q in zip(rng.uniform(-10.0, 1.0, 300), rng.uniform(0.0, 6.5, 300)):
+        for fl in (-5, -2, 0, 1, 5):
+            c0, c1, c2, c3 = coef[fl]
+            want = c0 + c1 * a + c2 * q + c3 * a * q
+            got = oracle.pdf_interp(g, fl, math.exp(a), math.exp(q))
+            assert abs(got - want) <= 1e-12 * max(1.0, abs(want)), (fl, a, q, got, want)
+    for i in (0, 3, 8):
+        for j in (0, 2, 4):
+            assert oracle.pdf_interp(g, 2, math.exp(lx[i]), math.exp(lq[j])) == pytest.approx(xf[j, i, 7], rel=1e-14)
+    assert oracle.pdf_interp(g, 6, 0.1, 100.0) == 0.0 and oracle.pdf_interp(g, -6, 0.1, 100.0) == 0.0
+
+
+def test_pdf_grid_toy_accuracy():
+    """Sec. 4 states interpolated densities within 1 % of the directly
+    queried ones: the toy densities tabulated on 320 x 16 nodes, x in
+    [1e-5, 1], Q in [10, 13000] GeV, meet that on x in [1e-4, 0.5] (the
+    range the top processes sample); s, c, b are zero"""
+    g = oracle.pdf_tabulate_toy(320, 16, PDF_BOUNDS)
+    ref = _grid_from(_toy_tables())
+    assert np.array_equal(g.xf, ref.xf)
+    rng = np.random.default_rng(6)
+    for fl, f in _toy_tables().items():
+        for x in np.exp(rng.uniform(math.log(1e-4), math.log(0.5), 400)):
+            Q = math.exp(rng.uniform(PDF_BOUNDS[2], PDF_BOUNDS[3]))
+            assert abs(oracle.pdf_interp(g, fl, x, Q) / f(x) - 1.0) < 0.01, (fl, x)
+    for fl in (3, 4, 5, -3, -4, -5):
+        assert oracle.pdf_interp(g, fl, 0.01, 100.0) == 0.0
+
+
+def _dy_points(p, ev, n, rng):
+    """points of the Drell-Yan map inside the mass window, with their pair mass"""
+    out = []
+    while len(out) < n:
+        x = rng.random(2)
+        mu = []
+        for k in range(2):
+            r = p.r_lo + x[k] * (p.r_hi - p.r_lo)
+            pm = np.linalg.norm(ev[k][1:])
+            pk = pm / r
+            mu.append(np.concatenate([[pk], pk * ev[k][1:] / pm]))
+        P = mu[0] + mu[1]
+        m2 = mdot(P, P)
+        if p.m_lo ** 2 <= m2 <= p.m_hi ** 2:
+            out.append((x, math.sqrt(m2)))
+    return out
+
+
+def test_pdf_grid_drell_yan_flavours_and_scale():
+    """Drell-Yan with grid densities: the luminosity weights each flavour by
+    its charge squared (c as u, d and s a quarter of u), pairs a quark with
+    its own antiquark, and takes the pair mass as the scale (a grid scaled
+    by a linear function of ln Q scales the integrand by its square at M)"""
+    p = oracle.dy_params()
+    L = oracle.lib()
+    ev = events.drell_yan(1, 71)["obs"][0]
+    pts = _dy_points(p, ev, 40, np.random.default_rng(7))
+    U, Q = L.or_xf_u, L.or_xf_qbar
+    gu = _grid_from({2: U, -2: Q})
+    gc = _grid_from({4: U, -4: Q})
+    gs = _grid_from({3: U, -3: Q})
+    gx = _grid_from({2: U, -1: Q})                      # u against dbar: no pair
+    qf = lambda lq: 0.5 + 0.3 * lq
+    gq = _grid_from({2: U, -2: Q}, qfac=qf)
+    for x, M in pts:
+        vu = oracle.dy_integrand(oracle.with_pdf(p, gu), ev, x)
+        assert vu > 0
+        assert oracle.dy_integrand(oracle.with_pdf(p, gc), ev, x) == pytest.approx(vu, rel=1e-12)
+        assert oracle.dy_integrand(oracle.with_pdf(p, gs), ev, x) == pytest.approx(0.25 * vu, rel=1e-12)
+        assert oracle.dy_integrand(oracle.with_pdf(p, gx), ev, x) == 0.0
+        vq = oracle.dy_integrand(oracle.with_pdf(p, gq), ev, x)
+        assert vq == pytest.approx(vu * qf(math.log(M)) ** 2, rel=2e-6)
+    # the full toy tables reproduce the toy integrand within the 1 % of the tables
+    gt = oracle.pdf_tabulate_toy(320, 16, PDF_BOUNDS)
+    for x, _ in pts:
+        assert oracle.dy_integrand(oracle.with_pdf(p, gt), ev, x) == pytest.approx(
+            oracle.dy_integrand(p, ev, x), rel=0.01)
+
+
+def test_pdf_grid_top_flavours_and_scale():
+    """ttbar dilepton with grid densities: q qbar -> t tbar is flavour-blind
+    (u and b tables give the same value), a quark pairs only with its own
+    antiquark (u against dbar leaves the gg channel alone), the scale is
+    m_t (a ln Q-linear factor enters squared at m_t), and the toy tables
+    reproduce the toy integrand within 1 %"""
+    p = oracle.tt_params()
+    L = oracle.lib()
+    d = events.ttbar_dilepton(3, 41)
+    U, Q, G = L.or_xf_u, L.or_xf_qbar, L.or_xf_g
+    gu = _grid_from({2: U, -2: Q, 0: G})
+    gb = _grid_from({5: U, -5: Q, 0: G})
+    gx = _grid_from({2: U, -1: Q, 0: G})
+    gg = _grid_from({0: G})
+    qf = lambda lq: 0.5 + 0.3 * lq
+    gq = _grid_from({2: U, -2: Q, 0: G}, qfac=qf)
+    gt = oracle.pdf_tabulate_toy(320, 16, PDF_BOUNDS)
+    rng = np.random.default_rng(8)
+    n = 0
+    for i in range(3):
+        ev = d["obs"][i]
+        xt, perm = tt_truth_x(p, ev, d["truth"], i)
+        for x in np.clip(xt + 0.002 * rng.standard_normal((30, 8)), 1e-6, 1 - 1e-6):
+            vu = oracle.tt_integrand(oracle.with_pdf(p, gu), ev, perm, x)[0]
+            if vu == 0.0:
+                continue
+            n += 1
+            assert oracle.tt_integrand(oracle.with_pdf(p, gb), ev, perm, x)[0] == pytest.approx(vu, rel=1e-12)
+            vx = oracle.tt_integrand(oracle.with_pdf(p, gx), ev, perm, x)[0]
+            assert vx == pytest.approx(oracle.tt_integrand(oracle.with_pdf(p, gg), ev, perm, x)[0], rel=1e-12)
+            assert vx < vu
+            vq = oracle.tt_integrand(oracle.with_pdf(p, gq), ev, perm, x)[0]
+            assert vq == pytest.approx(vu * qf(math.log(p.m_t)) ** 2, rel=2e-6)
+            assert oracle.tt_integrand(oracle.with_pdf(p, gt), ev, perm, x)[0] == pytest.approx(
+                oracle.tt_integrand(p, ev, perm, x)[0], rel=0.01)
+    assert n > 30
+
+
+def test_pdf_grid_tth_gluon_and_scale():
+    """gg -> ttbar H with grid densities: only the gluon table enters, at the
+    scale m_t; the toy gluon table reproduces the toy integrand within 1 %"""
+    p = oracle.tt_params()
+    L = oracle.lib()
+    d = events.ttbar_higgs(10, 71)
+    G = L.or_xf_g
+    gg = _grid_from({0: G})
+    gq = _grid_from({0: G, 2: L.or_xf_u, -2: L.or_xf_qbar})
+    qf = lambda lq: 0.5 + 0.3 * lq
+    gs = _grid_from({0: G}, qfac=qf)
+    gt = oracle.pdf_tabulate_toy(320, 16, PDF_BOUNDS)
+    n = 0
+    for i in range(10):
+        x, perm = tth_truth_x(p, d["obs"][i], d["truth"], i)
+        if np.any(x <= 0) or np.any(x >= 1):
+            continue
+        v = oracle.tth_integrand(oracle.with_pdf(p, gg), d["obs"][i], perm, x)[0]
+        if v == 0.0:
+            continue
+        n += 1
+        assert oracle.tth_integrand(oracle.with_pdf(p, gq), d["obs"][i], perm, x)[0] == v
+        assert oracle.tth_integrand(oracle.with_pdf(p, gs), d["obs"][i], perm, x)[0] == pytest.approx(
+            v * qf(math.log(p.m_t)) ** 2, rel=2e-6)
+        assert oracle.tth_integrand(oracle.with_pdf(p, gt), d["obs"][i], perm, x)[0] == pytest.approx(
+            oracle.tth_integrand(p, d["obs"][i], perm, x)[0], rel=0.01)
+    assert n >= 5
