@@ -222,6 +222,28 @@ def parton_leg(mem, proc):
     return out
 
 
+def pdf_grid_leg(mem, comps, n_ev, kern_ms_toy):
+    """the fixed-budget pass again with the densities interpolated from
+    (ln x, ln Q) grids (the library's toy densities tabulated on 320 x 16
+    nodes, x in [1e-5, 1], Q in [10, 13000] GeV): the cost of the paper's
+    grid-PDF design against the closed-form toy densities"""
+    import math
+    import torch
+    bounds = (math.log(1e-5), 0.0, math.log(10.0), math.log(13000.0))
+    proc = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    proc.set_pdf_grid(mem.toy_pdf_table(320, 16, bounds), bounds)
+    timing = (ctypes.c_double * 8)()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mem.integrate_events(comps, proc, PTS, FIXED_ITERS, timing=timing)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"grid": "320 x 16 nodes, 11 flavours", "kernel_ms": timing[0], "evals_per_s": timing[2] / wall,
+           "kernel_time_vs_toy": timing[0] / kern_ms_toy}
+    log(f"pdf grid: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +253,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--no-grid", action="store_true", help="skip the grid-PDF pass")
     ap.add_argument("--flow-train-events", type=int, default=FLOW_TRAIN_EVENTS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB fill and a 256 MiB elementwise copy (reference for HBM byte counters)")
@@ -309,6 +332,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": traffic}
     parton = parton_leg(mem, proc)
+    grid = None if args.no_grid else pdf_grid_leg(mem, comps, n_ev, kern_ms)
     flow = None
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)
@@ -333,6 +357,7 @@ def main():
         "converged_fraction": conv, "median_iterations": float(np.median(nu)) if args.steps else None,
         "flow_vs_vegas": flow,
         "parton_level": parton,
+        "pdf_grid": grid,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -204,6 +204,32 @@ mem_status mem_set_transfer_functions(mem_process p, const mem_tf_desc* tf, int3
 
 void mem_destroy_process(mem_process p);
 
+/* Parton densities from a table (Sec. 4: the densities of d, u, s, c, b,
+ * their antiquarks and the gluon are stored on (x, Q) grids and
+ * interpolated bilinearly inside the integrand).
+ *  xf      host array [nq][nx][11] float: x f(x, Q) of flavour fl = -5..5
+ *          (PDG codes: 1 d, 2 u, 3 s, 4 c, 5 b, negative for antiquarks,
+ *          0 the gluon) at index fl + 5, at node (ix, iq) with
+ *            ln x = bounds[0] + ix (bounds[1] - bounds[0]) / (nx - 1),
+ *            ln Q = bounds[2] + iq (bounds[3] - bounds[2]) / (nq - 1);
+ *          copied to the current device (the process then integrates on
+ *          that device only).  NULL restores the built-in toy densities.
+ *  nx, nq  >= 2 each; nx * nq <= 2^22
+ *  bounds  ln x and ln Q ranges (natural logarithms), increasing
+ * Outside the grid the edge cells extrapolate linearly.  Factorisation
+ * scale (not stated in the paper): the muon pair mass for Drell-Yan, m_t
+ * for the top processes.  Errors: MEM_EINVAL for a null process or bounds,
+ * nx or nq < 2, a grid above the size limit, bounds not increasing or not
+ * finite, a non-finite table entry; MEM_EUNSUPPORTED for t tbar H (its
+ * integrand keeps the toy gluon density); MEM_ENOMEM. */
+mem_status mem_set_pdf_grid(mem_process p, const float* xf, int32_t nx, int32_t nq, const double* bounds);
+
+/* The library's toy densities tabulated at the nodes of such a grid into
+ * the caller's host array xf [nq][nx][11] (u and d valence-like, a common
+ * sea for ubar and dbar, the gluon; s, c, b and their antiquarks zero;
+ * zero at x >= 1).  MEM_EINVAL as for mem_set_pdf_grid. */
+mem_status mem_toy_pdf_table(float* xf, int32_t nx, int32_t nq, const double* bounds);
+
 /* Integration dimension and number of jet-parton assignments of a process. */
 mem_status mem_process_shape(mem_process p, int32_t* dims, int32_t* n_perm);
 

@@ -27,7 +27,8 @@ EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_proc
            "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
-           "mem_process_chunk_points", "mem_parton_weights", "mem_status_string", "mem_last_error")
+           "mem_process_chunk_points", "mem_parton_weights", "mem_set_pdf_grid", "mem_toy_pdf_table",
+           "mem_status_string", "mem_last_error")
 
 
 class ProcessDesc(ctypes.Structure):
@@ -75,6 +76,8 @@ def lib():
         sigs = {
             "mem_create_process": (I32, [P, P]),
             "mem_set_transfer_functions": (I32, [P, P, I32]),
+            "mem_set_pdf_grid": (I32, [P, P, I32, I32, P]),
+            "mem_toy_pdf_table": (I32, [P, I32, I32, P]),
             "mem_destroy_process": (None, [P]),
             "mem_process_shape": (I32, [P, P, P]),
             "mem_integrate_events": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
@@ -140,6 +143,20 @@ class Process:
     def set_transfer_functions(self, tfs):
         arr = (TFDesc * len(tfs))(*tfs)
         _check(lib().mem_set_transfer_functions(self.handle, arr, len(tfs)), "mem_set_transfer_functions")
+
+    def set_pdf_grid(self, xf, bounds):
+        """mem_set_pdf_grid: xf float32 [nq][nx][11] on the host (x f of the
+        flavours -5..5), bounds (ln x_min, ln x_max, ln Q_min, ln Q_max);
+        xf None restores the toy densities"""
+        if xf is None:
+            _check(lib().mem_set_pdf_grid(self.handle, None, 0, 0, None), "mem_set_pdf_grid")
+            return
+        import numpy as np
+        a = np.ascontiguousarray(xf, dtype=np.float32)
+        if a.ndim != 3 or a.shape[2] != 11:
+            raise ValueError("xf must be [nq][nx][11]")
+        b = (ctypes.c_double * 4)(*bounds)
+        _check(lib().mem_set_pdf_grid(self.handle, a.ctypes.data, a.shape[1], a.shape[0], b), "mem_set_pdf_grid")
 
     def autotune(self, comps, n_points, candidates=None, table_path=None, charge=None):
         """mem_autotune on the given events; returns (chunk_points, evals/s)"""
@@ -246,6 +263,16 @@ def eval_points(process, comps, event, perm, x, f, nsol=None, stream=None, charg
                                  ctypes.c_void_p(nsol.data_ptr()) if nsol is not None else None,
                                  _stream_ptr(stream)), "mem_eval_points")
     return f
+
+
+def toy_pdf_table(nx, nq, bounds):
+    """mem_toy_pdf_table: the library's toy densities at the nodes of an
+    (ln x, ln Q) grid, float32 [nq][nx][11]"""
+    import numpy as np
+    a = np.zeros((nq, nx, 11), dtype=np.float32)
+    b = (ctypes.c_double * 4)(*bounds)
+    _check(lib().mem_toy_pdf_table(a.ctypes.data, nx, nq, b), "mem_toy_pdf_table")
+    return a
 
 
 def parton_weights(process, comps, out=None, stream=None):

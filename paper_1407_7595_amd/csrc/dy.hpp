@@ -8,6 +8,7 @@
 // the Collins-Soper angle.
 #pragma once
 #include "device_common.hpp"
+#include "pdf.hpp"
 #include "process.hpp"
 
 namespace memk {
@@ -42,9 +43,12 @@ __device__ __forceinline__ double tf_r64(double r, const TFParams& tf)
   return inv_sqrt_2pi * g;
 }
 
-__device__ __forceinline__ double xfu(double x, double omx) { double o = omx * omx * omx; return 2.0 * sqrt(x) * o; }
-__device__ __forceinline__ double xfd(double x, double omx) { double o = omx * omx; return sqrt(x) * o * o; }
-__device__ __forceinline__ double xfq(double omx) { double o2 = omx * omx, o4 = o2 * o2; return 0.2 * o4 * o2 * omx; }
+// toy densities x f(x) of the configuration (omx = 1 - x): u and d
+// valence-like, the common sea antiquark, the gluon x g(x) = 3 (1-x)^5
+__host__ __device__ inline double xfu(double x, double omx) { double o = omx * omx * omx; return 2.0 * sqrt(x) * o; }
+__host__ __device__ inline double xfd(double x, double omx) { double o = omx * omx; return sqrt(x) * o * o; }
+__host__ __device__ inline double xfq(double omx) { double o2 = omx * omx, o4 = o2 * o2; return 0.2 * o4 * o2 * omx; }
+__host__ __device__ inline double xfg(double omx) { return 3.0 * omx * omx * omx * omx * omx; }
 
 __device__ __forceinline__ double dy_integrand(const ProcParams& pp, const DYEvent& ev, const double (&x)[2])
 {
@@ -67,11 +71,19 @@ __device__ __forceinline__ double dy_integrand(const ProcParams& pp, const DYEve
   if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
   double pt2 = P.x * P.x + P.y * P.y;
   double c = 2.0 * (mu[0].z * mu[1].e - mu[0].e * mu[1].z) / (sqrt(m2) * sqrt(m2 + pt2));
-  double o1 = 1.0 - x1, o2 = 1.0 - x2;
-  double u1 = xfu(x1, o1), d1 = xfd(x1, o1), q1 = xfq(o1);
-  double u2 = xfu(x2, o2), d2 = xfd(x2, o2), q2 = xfq(o2);
   // parton densities f = xf / x; the 1/(x1 x2) joins 1/shat below
-  double lum = (4.0 / 9.0) * (u1 * q2 + q1 * u2) + (1.0 / 9.0) * (d1 * q2 + q1 * d2);
+  double lum;
+#ifndef MEM_HOST_COUNT
+  if (pp.pdf_xf) {
+    lum = pdf_grid_dy_lumi(pp, x1, x2, m2);
+  } else
+#endif
+  {
+    double o1 = 1.0 - x1, o2 = 1.0 - x2;
+    double u1 = xfu(x1, o1), d1 = xfd(x1, o1), q1 = xfq(o1);
+    double u2 = xfu(x2, o2), d2 = xfd(x2, o2), q2 = xfq(o2);
+    lum = (4.0 / 9.0) * (u1 * q2 + q1 * u2) + (1.0 / 9.0) * (d1 * q2 + q1 * d2);
+  }
   double shat = x1 * x2 * pp.S;
   return w * lum * (1.0 + c * c) / (shat * x1 * x2);
 }

@@ -46,7 +46,31 @@ struct mem_process_s {
   mem_tf_desc tf[5];
   ProcParams pp;
   int32_t chunk_points = 0;   // tuned points per work-queue chunk (0: library default)
+  // parton-density grid on the device (null: toy densities) and its shape
+  float* pdf_dev = nullptr;
+  int32_t pdf_nx = 0, pdf_nq = 0;
+  double pdf_bounds[4] = {0.0, 0.0, 0.0, 0.0};
+  ~mem_process_s() { if (pdf_dev) (void)hipFree(pdf_dev); }
 };
+
+// grid fields of the process parameters from the process's grid
+static void apply_pdf(mem_process_s* p)
+{
+  ProcParams& pp = p->pp;
+  pp.pdf_xf = p->pdf_dev;
+  if (!p->pdf_dev) return;
+  pp.pdf_nx = p->pdf_nx;
+  pp.pdf_nq = p->pdf_nq;
+  pp.pdf_lx0 = p->pdf_bounds[0];
+  pp.pdf_ihx = (p->pdf_nx - 1) / (p->pdf_bounds[1] - p->pdf_bounds[0]);
+  pp.pdf_lq0 = p->pdf_bounds[2];
+  pp.pdf_ihq = (p->pdf_nq - 1) / (p->pdf_bounds[3] - p->pdf_bounds[2]);
+  const double s = (std::log(p->desc.m_top) - pp.pdf_lq0) * pp.pdf_ihq;
+  double c = std::floor(s);
+  c = c < 0.0 ? 0.0 : c > (double)(p->pdf_nq - 2) ? (double)(p->pdf_nq - 2) : c;
+  pp.pdf_iq_mt = (int32_t)c;
+  pp.pdf_uq_mt = s - c;
+}
 
 static TFParams tf_params(const mem_tf_desc& t)
 {
@@ -119,6 +143,7 @@ static void derive(mem_process_s* p)
                    * (d.m_top * d.m_top / v2) * 6.0 * (mb * mb / v2);
     }
   }
+  apply_pdf(p);
 }
 
 extern "C" mem_status mem_create_process(const mem_process_desc* d, mem_process* out)
@@ -181,6 +206,73 @@ extern "C" mem_status mem_set_transfer_functions(mem_process p, const mem_tf_des
 }
 
 extern "C" void mem_destroy_process(mem_process p) { delete p; }
+
+static mem_status check_pdf_shape(int32_t nx, int32_t nq, const double* b)
+{
+  if (!b) return fail(MEM_EINVAL, "null bounds");
+  if (nx < 2 || nq < 2) return fail(MEM_EINVAL, "the grid needs at least 2 x 2 nodes");
+  if ((int64_t)nx * nq > (int64_t)1 << 22) return fail(MEM_EINVAL, "grid above 2^22 nodes");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(b[k])) return fail(MEM_EINVAL, "bounds must be finite");
+  if (!(b[1] > b[0] && b[3] > b[2])) return fail(MEM_EINVAL, "bounds must increase");
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_set_pdf_grid(mem_process p, const float* xf, int32_t nx, int32_t nq, const double* bounds)
+{
+  if (!p) return fail(MEM_EINVAL, "null process");
+  if (!xf) {
+    if (p->pdf_dev) (void)hipFree(p->pdf_dev);
+    p->pdf_dev = nullptr;
+    apply_pdf(p);
+    return MEM_OK;
+  }
+  if (p->desc.kind == MEM_TTH_SEMILEPTON) return fail(MEM_EUNSUPPORTED, "t tbar H keeps the toy gluon density");
+  mem_status st = check_pdf_shape(nx, nq, bounds);
+  if (st != MEM_OK) return st;
+  const size_t nodes = (size_t)nx * nq;
+  // device node layout: quark / antiquark pairs in 16-byte groups
+  std::vector<float> pad(nodes * kPdfNode, 0.0f);
+  for (size_t n = 0; n < nodes; ++n)
+    for (int fl = -5; fl <= 5; ++fl) {
+      const float v = xf[n * 11 + fl + 5];
+      if (!std::isfinite(v)) return fail(MEM_EINVAL, "non-finite table entry");
+      pad[n * kPdfNode + pdf_slot(fl)] = v;
+    }
+  float* d = nullptr;
+  if (hipMalloc(&d, pad.size() * sizeof(float)) != hipSuccess) return fail(MEM_ENOMEM, "device allocation of the grid");
+  if (hipMemcpy(d, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return fail(MEM_EDEVICE, "copy of the grid");
+  }
+  if (p->pdf_dev) (void)hipFree(p->pdf_dev);
+  p->pdf_dev = d;
+  p->pdf_nx = nx;
+  p->pdf_nq = nq;
+  for (int k = 0; k < 4; ++k) p->pdf_bounds[k] = bounds[k];
+  apply_pdf(p);
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_toy_pdf_table(float* xf, int32_t nx, int32_t nq, const double* bounds)
+{
+  if (!xf) return fail(MEM_EINVAL, "null table");
+  mem_status st = check_pdf_shape(nx, nq, bounds);
+  if (st != MEM_OK) return st;
+  const double hx = (bounds[1] - bounds[0]) / (nx - 1);
+  for (int j = 0; j < nq; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double x = std::exp(bounds[0] + i * hx), o = 1.0 - x;
+      float* v = xf + ((size_t)j * nx + i) * 11;
+      for (int k = 0; k < 11; ++k) v[k] = 0.0f;
+      if (!(x < 1.0)) continue;
+      v[5 + 2] = (float)xfu(x, o);
+      v[5 + 1] = (float)xfd(x, o);
+      v[5 - 2] = v[5 - 1] = (float)xfq(o);
+      v[5] = (float)xfg(o);
+    }
+  return MEM_OK;
+}
 
 extern "C" mem_status mem_process_shape(mem_process p, int32_t* dims, int32_t* n_perm)
 {

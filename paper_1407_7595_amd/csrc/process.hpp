@@ -46,6 +46,15 @@ struct ProcParams {
   double tth_const;
   // couplings of the t tbar |M|^2: g_s^4 (g_W^2 / 2)^4
   double me_const;
+  // parton densities from a grid (null: the toy densities): x f of the
+  // 11 flavours in nodes of 12 floats (layout in pdf.hpp), [nq][nx][12],
+  // uniform in ln x and ln Q; position = (ln v - v0) * inverse step
+  const float* pdf_xf;
+  int32_t pdf_nx, pdf_nq;
+  double pdf_lx0, pdf_ihx, pdf_lq0, pdf_ihq;
+  // the top processes' fixed scale m_t: its Q cell and weight
+  int32_t pdf_iq_mt;
+  double pdf_uq_mt;
 };
 
 struct EventsView {

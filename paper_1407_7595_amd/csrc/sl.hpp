@@ -153,10 +153,8 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
     const v4 hbl = B.apply_me(bl), hl = B.apply_me(l), hn = B.apply_me(nu);
     const double ak = 0.5 * x1 * pp.sqrt_s * kMeScale, bk = 0.5 * x2 * pp.sqrt_s * kMeScale;
     const v4 k1{ak, 0.0, 0.0, ak}, k2{bk, 0.0, 0.0, -bk};
-    const double o1 = 1.0 - x1, o2 = 1.0 - x2;
-    const T g1 = T(3.0 * o1 * o1 * o1 * o1 * o1), g2 = T(3.0 * o2 * o2 * o2 * o2 * o2);
-    const T q1 = T(xfu(x1, o1) + xfd(x1, o1)), q2 = T(xfu(x2, o2) + xfd(x2, o2));
-    const T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
+    T gg, qq12, qq21;
+    tt_lumis<T>(pp, x1, x2, gg, qq12, qq21);
     T me = T(0);
     for (int o = 0; o < 2; ++o) {
       // ordering o: (quark, antiquark) of the hadronic W
@@ -178,7 +176,7 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
       const T mgg = gg_sum<T>(R, C, pt, T(ak), T(bk), mt);
       const T mq1 = qq_sum<T>(R, C, k1, k2);
       const T mq2 = qq_sum<T>(R, C, k2, k1);
-      me += g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
+      me += gg * mgg * T(1.0 / 256.0) + (qq12 * mq1 + qq21 * mq2) * T(1.0 / 36.0);
     }
     const double shat = x1 * x2 * pp.S;
     acc += P.e * ((double)me * kMeDeg8) * bwtl * fast_rcp(Eh * shat * x1 * x2 * dq * nu.e);

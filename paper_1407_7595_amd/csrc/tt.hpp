@@ -136,6 +136,27 @@ __device__ __forceinline__ v4 tt_jet(const TTEvent& ev, int k, double E)
   return v4{E, E * ev.n[k][0], E * ev.n[k][1], E * ev.n[k][2]};
 }
 
+// Luminosities in x f form at (x1, x2): gg = xg xg, qq12 = sum_q xq(x1)
+// xqbar(x2), qq21 = sum_q xqbar(x1) xq(x2).  Toy densities: u + d against
+// the common sea; with a grid, the sums over d, u, s, c, b at m_t.
+template <class T>
+__device__ __forceinline__ void tt_lumis(const ProcParams& pp, double x1, double x2, T& gg, T& qq12, T& qq21)
+{
+#ifndef MEM_HOST_COUNT      // the host operation count covers the toy densities
+  if (pp.pdf_xf) {
+    pdf_grid_tt_lumis<T>(pp, x1, x2, gg, qq12, qq21);
+    return;
+  }
+#endif
+  const double o1 = 1.0 - x1, o2 = 1.0 - x2;
+  const T g1 = T(3.0 * o1 * o1 * o1 * o1 * o1), g2 = T(3.0 * o2 * o2 * o2 * o2 * o2);
+  const T q1 = T(xfu(x1, o1) + xfd(x1, o1)), q2 = T(xfu(x2, o2) + xfd(x2, o2));
+  const T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
+  gg = g1 * g2;
+  qq12 = q1 * qb2;
+  qq21 = qb1 * q2;
+}
+
 // |M|^2 x PDFs of a final state given in the lab (b, l+, nu from the top;
 // bbar, l-, nubar from the antitop): boost to zero transverse momentum,
 // x1, x2 = (E' +- P_z) / sqrt(S), the gg and q qbar channels with the toy
@@ -153,6 +174,10 @@ __device__ __forceinline__ bool tt_me_pdf(const ProcParams& pp, const v4& b0, co
   x1 = (Eh + P.z) * pp.inv_sqrt_s;
   x2 = (Eh - P.z) * pp.inv_sqrt_s;
   if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return false;
+  // densities x f: toy (configuration) or from the grid; formed before the
+  // matrix element so that only the three luminosities stay live across it
+  T gg, qq12, qq21;
+  tt_lumis<T>(pp, x1, x2, gg, qq12, qq21);
   // |M|^2 in the hard frame, in matrix-element units
   const T mt = T(pp.m_t * kMeScale);
   TBoost B(P);
@@ -167,12 +192,7 @@ __device__ __forceinline__ bool tt_me_pdf(const ProcParams& pp, const v4& b0, co
   const v4 k1{a, 0.0, 0.0, a}, k2{bm, 0.0, 0.0, -bm};
   const T mq1 = qq_sum<T>(R, C, k1, k2);
   const T mq2 = qq_sum<T>(R, C, k2, k1);
-  // toy densities x f(x) (configuration) and x g(x) = 3 (1-x)^5
-  const double o1 = 1.0 - x1, o2 = 1.0 - x2;
-  const T g1 = T(3.0 * o1 * o1 * o1 * o1 * o1), g2 = T(3.0 * o2 * o2 * o2 * o2 * o2);
-  const T q1 = T(xfu(x1, o1) + xfd(x1, o1)), q2 = T(xfu(x2, o2) + xfd(x2, o2));
-  const T qb1 = T(xfq(o1)), qb2 = T(xfq(o2));
-  const T me = g1 * g2 * mgg * T(1.0 / 256.0) + (q1 * qb2 * mq1 + qb1 * q2 * mq2) * T(1.0 / 36.0);
+  const T me = gg * mgg * T(1.0 / 256.0) + (qq12 * mq1 + qq21 * mq2) * T(1.0 / 36.0);
   me_out = (double)me * kMeDeg8;
   return true;
 }

@@ -128,3 +128,42 @@ def test_tuning_table_lookup(mem, tmp_path):
     assert e.value.status == mem.MEM_EINVAL
     with pytest.raises(mem.MemError):
         p.load_tuning(str(tmp_path / "missing.txt"), arch="gfx950")
+
+
+def test_toy_pdf_table_matches_oracle(mem):
+    """the library's toy densities at grid nodes against the oracle's own
+    tabulation (two implementations of the same densities), to FP32
+    rounding"""
+    import math
+    import numpy as np
+    import oracle
+    b = (math.log(1e-5), 0.0, math.log(10.0), math.log(13000.0))
+    got = mem.toy_pdf_table(320, 4, b)
+    want = oracle.pdf_tabulate_toy(320, 4, b).xf
+    assert got.shape == want.shape == (4, 320, 11)
+    np.testing.assert_allclose(got, want, rtol=2.0 ** -23, atol=0.0)
+    assert np.all(got[..., [0, 1, 2, 8, 9, 10]] == 0.0)
+    assert np.all(got[:, -1, :] == 0.0)          # x = 1
+
+
+def test_pdf_grid_validation(mem):
+    import math
+    import numpy as np
+    p = mem.Process(mem.MEM_TT_DILEPTON)
+    good_b = (math.log(1e-5), 0.0, math.log(10.0), math.log(13000.0))
+    xf = np.ones((4, 8, 11), dtype=np.float32)
+    nan = xf.copy()
+    nan[1, 2, 3] = np.nan
+    for a, b in ((xf, (0.0, -1.0, 1.0, 2.0)), (xf, (0.0, 1.0, 2.0, 2.0)), (xf[:, :1], good_b), (xf[:1], good_b),
+                 (nan, good_b), (xf, (0.0, float("inf"), 1.0, 2.0))):
+        with pytest.raises(mem.MemError) as e:
+            p.set_pdf_grid(a, b)
+        assert e.value.status == mem.MEM_EINVAL
+    p.set_pdf_grid(None, None)                   # back to the toy densities: no device work
+    tth = mem.Process(mem.MEM_TTH_SEMILEPTON)
+    with pytest.raises(mem.MemError) as e:
+        tth.set_pdf_grid(xf, good_b)
+    assert e.value.status == mem.MEM_EUNSUPPORTED
+    L = mem.lib()
+    assert L.mem_set_pdf_grid(None, None, 0, 0, None) == mem.MEM_EINVAL
+    assert L.mem_toy_pdf_table(None, 8, 4, None) == mem.MEM_EINVAL
