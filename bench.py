@@ -155,7 +155,8 @@ def flow_leg(mem, proc, comps, n_ev, args):
 
     def run(tm=None, thr=0.3):
         mem.integrate_events(comps, proc, FLOW_PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER,
-                             outputs=(P, E, S), n_iter_out=n_used, flow=f, ess_threshold=thr, timing=tm)
+                             outputs=(P, E, S), n_iter_out=n_used, flow=f, ess_threshold=thr, timing=tm,
+                             allocation=mem.MEM_ALLOC_NEYMAN)
 
     run()
     torch.cuda.synchronize()
@@ -302,9 +303,9 @@ def main():
         f"{n_evals:.3g} evaluations -> {evals_per_s:.3g} evals/s")
     fixed_rel = (E / P).cpu().numpy()
 
-    def step():
+    def step(alloc=mem.MEM_ALLOC_NEYMAN):
         mem.integrate_events(comps, proc, PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
-                             n_iter_out=n_used)
+                             n_iter_out=n_used, allocation=alloc)
 
     for w in range(args.warmup):
         log(f"warmup step {w}")
@@ -323,6 +324,19 @@ def main():
     nu = n_used.cpu().numpy()
     conv = float(np.mean(st == 0))
     value = n_ev * args.steps / total if total > 0 else None
+    # the same step with every event's points split equally over its two
+    # assignments (plain VEGAS budget split), for comparison
+    equal = None
+    if args.steps:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(mem.MEM_ALLOC_EQUAL)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        equal = {"events_per_s": n_ev / te, "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
+                 "median_iterations": float(np.median(n_used.cpu().numpy())),
+                 "mean_iterations": float(np.mean(n_used.cpu().numpy()))}
+        log(f"equal split: {equal}")
 
     roof = None
     if FLOP_PER_EVAL is not None and launches > 0:
@@ -350,11 +364,13 @@ def main():
         "config": {"workload": f"ttbar dilepton MEM, {n_ev} events, 8D VEGAS, {PTS} points/event/iteration "
                                f"to 1% per-event error (max {MAX_ITER} iterations)",
                    "events": n_ev, "points_per_iteration": PTS, "target_rel_err": TARGET,
-                   "proposal": "vegas"},
+                   "proposal": "vegas", "allocation": "neyman across the two assignments"},
         "integrand_evals_per_s": evals_per_s,
         "fixed_budget": {"iterations": FIXED_ITERS, "seconds": fixed_s, "kernel_ms": kern_ms,
                          "median_rel_err": float(np.median(fixed_rel))},
         "converged_fraction": conv, "median_iterations": float(np.median(nu)) if args.steps else None,
+        "mean_iterations": float(np.mean(nu)) if args.steps else None,
+        "vegas_equal_split": equal,
         "flow_vs_vegas": flow,
         "parton_level": parton,
         "pdf_grid": grid,

@@ -161,7 +161,22 @@ typedef struct mem_flow_s* mem_flow;
  *                  (status MEM_EV_FLOW_FALLBACK when that converges).  In
  *                  target mode the flow's stopping test runs from the
  *                  second batch on.
- *  ess_threshold   flow fallback threshold on ESS/N (0: 0.3)                */
+ *  ess_threshold   flow fallback threshold on ESS/N (0: 0.3)
+ *  allocation      how an event's points are shared among its permutations
+ *                  (VEGAS; ignored with a flow).  MEM_ALLOC_EQUAL (0, the
+ *                  default): every iteration gives each permutation
+ *                  ceil(n_points / n_perm) points.  MEM_ALLOC_NEYMAN (1): the
+ *                  first iteration splits equally; from then on permutation k
+ *                  gets a floor of 1/8 of the equal share plus a part of the
+ *                  rest proportional to the standard deviation of its weights
+ *                  in the previous iteration (Neyman allocation, which
+ *                  minimises the variance of the permutation average for a
+ *                  fixed total), at most min(n_perm, 4) equal shares; the
+ *                  event's total per iteration stays n_perm equal shares up
+ *                  to that cap.  Same point stream (point k of an integral is
+ *                  the same u in either mode); estimates differ from equal
+ *                  splitting by MC fluctuation only.                        */
+enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
 typedef struct {
   uint64_t seed;
   double alpha;
@@ -177,6 +192,7 @@ typedef struct {
   int32_t use_graph;
   mem_flow flow;
   double ess_threshold;
+  int32_t allocation;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */

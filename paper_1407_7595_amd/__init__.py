@@ -18,6 +18,7 @@ MEM_TF_DELTA, MEM_TF_UNIFORM, MEM_TF_GAUSS, MEM_TF_DGAUSS = range(4)
 MEM_OBJ_MUON, MEM_OBJ_LEPTON, MEM_OBJ_BJET, MEM_OBJ_LJET, MEM_OBJ_NEUTRINO = range(5)
 MEM_EV_OK, MEM_EV_ZERO_INTEGRAND, MEM_EV_NOT_CONVERGED, MEM_EV_NONFINITE, MEM_EV_FLOW_FALLBACK = range(5)
 FLOW_NPARAMS = 192552
+MEM_ALLOC_EQUAL, MEM_ALLOC_NEYMAN = 0, 1
 MEM_FLOW_BF16, MEM_FLOW_BF16X2 = 0, 1
 FLOW_CONTEXT = 24
 
@@ -57,7 +58,7 @@ class IntegrateOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("stream", ctypes.c_void_p), ("outputs_on_device", ctypes.c_int32),
                 ("iter_out", ctypes.c_void_p), ("grid_out", ctypes.c_void_p), ("n_iter_out", ctypes.c_void_p),
                 ("timing_out", ctypes.c_void_p), ("chunk_points", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("flow", ctypes.c_void_p), ("ess_threshold", ctypes.c_double)]
+                ("flow", ctypes.c_void_p), ("ess_threshold", ctypes.c_double), ("allocation", ctypes.c_int32)]
 
 
 _lib = None
@@ -217,11 +218,13 @@ def to_components(obs):
 
 def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=1.5, target_rel_err=0.0,
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
-                     timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0):
+                     timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
+                     allocation=0):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
-    flow: optional Flow (importance sampling from it, VEGAS fallback).
+    flow: optional Flow (importance sampling from it, VEGAS fallback);
+    allocation: MEM_ALLOC_EQUAL or MEM_ALLOC_NEYMAN across permutations.
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
@@ -242,7 +245,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         grid_out.data_ptr() if grid_out is not None else None,
                         n_iter_out.data_ptr() if n_iter_out is not None else None,
                         ctypes.cast(timing, ctypes.c_void_p) if timing is not None else None,
-                        chunk_points, use_graph, flow.handle.value if flow is not None else None, ess_threshold)
+                        chunk_points, use_graph, flow.handle.value if flow is not None else None, ess_threshold,
+                        allocation)
     _check(lib().mem_integrate_events(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                       ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
                                       ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),

@@ -227,7 +227,8 @@ template <class T, int KINDS>
 __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kernel(
     const ProcParams* __restrict__ procs, EventsView ev, const Chunk* __restrict__ chunks, int64_t n_chunks,
     const IntegralDesc* __restrict__ ints, const double* __restrict__ grids, const int32_t* __restrict__ active,
-    uint64_t seed, Control* __restrict__ ctl, uint32_t* __restrict__ head, double* __restrict__ parts)
+    uint64_t seed, Control* __restrict__ ctl, uint32_t* __restrict__ head, double* __restrict__ parts,
+    const int64_t* __restrict__ alloc)
 {
   __shared__ double sgrid[kMaxDims * (kBins + 1)];
   // per-wavefront bin sums, combined in wavefront order: the result does not
@@ -242,8 +243,15 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
     const int64_t c = s_next;
     __syncthreads();
     if (c >= n_chunks) break;
-    const Chunk ch = chunks[c];
+    Chunk ch = chunks[c];
     if (!active[ch.integral]) continue;
+    if (alloc) {
+      // this iteration's points of the integral (Neyman allocation): the
+      // chunks past them are skipped, the one across the end is cut
+      const int64_t na = alloc[ch.integral];
+      if (ch.start >= na) continue;
+      if (ch.start + ch.count > na) ch.count = (int32_t)(na - ch.start);
+    }
     const IntegralDesc in = ints[ch.integral];
     const int D = in.dims;
     for (int i = threadIdx.x; i < D * (kBins + 1); i += kBlock) sgrid[i] = grids[in.grid_off + i];

@@ -327,7 +327,9 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
                                                              double* __restrict__ state,
                                                              const int32_t* __restrict__ active,
                                                              double alpha, const Control* __restrict__ ctl,
-                                                             int n_int, double* __restrict__ iter_out)
+                                                             int n_int, double* __restrict__ iter_out,
+                                                             const int64_t* __restrict__ alloc,
+                                                             double* __restrict__ n_evals)
 {
   __shared__ double sb[kMaxDims * kBins];
   __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
@@ -336,19 +338,26 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
   const uint32_t iter = ctl->iter;
   const IntegralDesc in = ints[ig];
   const int D = in.dims;
+  // this iteration's points: the equal share, or the allocation (its chunks
+  // are the first ones of the integral)
+  const int64_t npts = alloc ? alloc[ig] : in.n_points;
+  int nch = in.n_chunks;
+  if (alloc)
+    while (nch > 0 && chunks[in.chunk0 + nch - 1].start >= npts) --nch;
   for (int i = threadIdx.x; i < D * kBins; i += kBlock) {
     double acc = 0.0;
-    for (int c = 0; c < in.n_chunks; ++c) acc += parts[chunks[in.chunk0 + c].part_off + 2 + i];
+    for (int c = 0; c < nch; ++c) acc += parts[chunks[in.chunk0 + c].part_off + 2 + i];
     sb[i] = acc;
   }
   if (threadIdx.x == 0) {
     double s1 = 0.0, s2 = 0.0;
-    for (int c = 0; c < in.n_chunks; ++c) {
+    for (int c = 0; c < nch; ++c) {
       const double* p = parts + chunks[in.chunk0 + c].part_off;
       s1 += p[0];
       s2 += p[1];
     }
-    const double N = (double)in.n_points;
+    const double N = (double)npts;
+    atomicAdd(n_evals, N);
     const double I = s1 / N;
     double var = (s2 / N - I * I) / (N - 1.0);
     if (var < 0.0) var = 0.0;
@@ -430,6 +439,68 @@ __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t*
   else if (target > 0.0 && !ev_done[e]) stt = MEM_EV_NOT_CONVERGED;
   status[e] = stt;
   if (n_iter_used) n_iter_used[e] = ev_done[e] ? ev_done[e] : (int32_t)iter;
+}
+
+// Neyman allocation of each running event's points among its permutations
+// for the next iteration.  sigma_k, the standard deviation of permutation
+// k's weights, comes from the last iteration's variance of its mean times
+// its points.  The permutation average's variance sum sigma_k^2 / n_k is
+// smallest for n_k proportional to sigma_k under a fixed total; here every
+// permutation keeps a floor (1/8 of the equal share, so that its grid keeps
+// adapting and its variance stays estimated) and the rest of the event's
+// budget (n_perm equal shares) goes by sigma_k, water-filled under each
+// integral's chunk coverage: a permutation above its cap gets the cap and
+// the others share what is left.
+constexpr int kMaxPerm = 24;
+__global__ void neyman_kernel(const int64_t* __restrict__ ev_int0, const int32_t* __restrict__ ev_nperm,
+                              const IntegralDesc* __restrict__ ints, const double* __restrict__ state,
+                              const int32_t* __restrict__ active, const int64_t* __restrict__ cap,
+                              int64_t* __restrict__ alloc, int n_events)
+{
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_events) return;
+  const int64_t i0 = ev_int0[e];
+  const int np = ev_nperm[e];
+  if (np < 2 || np > kMaxPerm || !active[i0]) return;   // retired events keep their allocation
+  const int64_t per = ints[i0].n_points;
+  const int64_t floor_pts = per / 8 > 2 ? per / 8 : 2;
+  double sig[kMaxPerm];
+  bool capped[kMaxPerm];
+  double ssum = 0.0;
+  for (int k = 0; k < np; ++k) {
+    const double v = state[(i0 + k) * ST_SIZE + ST_LAST_V];
+    sig[k] = sqrt(v * (double)alloc[i0 + k]);
+    capped[k] = false;
+    ssum += sig[k];
+  }
+  if (!(ssum > 0.0) || !isfinite(ssum)) return;          // nothing to go by: keep the split
+  double rest = (double)(per * np);                       // points for the uncapped permutations
+  int n_free = np;
+  for (int round = 0; round < np; ++round) {
+    double s_free = 0.0;
+    for (int k = 0; k < np; ++k) if (!capped[k]) s_free += sig[k];
+    const double share = rest - (double)(n_free * floor_pts);
+    bool changed = false;
+    for (int k = 0; k < np; ++k) {
+      if (capped[k]) continue;
+      const double want = (double)floor_pts + (s_free > 0.0 ? share * (sig[k] / s_free) : share / n_free);
+      if (want > (double)cap[i0 + k]) {
+        capped[k] = true;
+        rest -= (double)cap[i0 + k];
+        --n_free;
+        changed = true;
+      }
+    }
+    if (!changed || n_free == 0) {
+      for (int k = 0; k < np; ++k) {
+        int64_t n;
+        if (capped[k]) n = cap[i0 + k];
+        else n = floor_pts + (int64_t)(s_free > 0.0 ? share * (sig[k] / s_free) : share / n_free);
+        alloc[i0 + k] = n < 2 ? 2 : n > cap[i0 + k] ? cap[i0 + k] : n;
+      }
+      return;
+    }
+  }
 }
 
 template <int KIND, int D, class T>
@@ -581,7 +652,8 @@ struct DevEvents {
 // occupancy (never more than there are chunks).
 // The queue kernel instance for a precision and a set of kinds.
 typedef void (*QueueKernel)(const ProcParams*, EventsView, const Chunk*, int64_t, const IntegralDesc*,
-                            const double*, const int32_t*, uint64_t, Control*, uint32_t*, double*);
+                            const double*, const int32_t*, uint64_t, Control*, uint32_t*, double*,
+                            const int64_t*);
 template <class T>
 QueueKernel queue_kernel_for(int mask)
 {
@@ -698,6 +770,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     const int64_t per = (npts + np - 1) / np;
     if (per < 2) return fail(MEM_EINVAL, "n_points too small");
     if (per > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "n_points exceeds 2^32 per permutation");
+    if (o.allocation == MEM_ALLOC_NEYMAN && per * std::min(np, 4) > (int64_t)0xFFFFFFFF)
+      return fail(MEM_EINVAL, "n_points exceeds 2^32 per permutation under Neyman allocation");
     ev_int0[e] = (int64_t)ints.size();
     ev_np[e] = np;
     ev_norm[e] = p->desc.sigma_norm > 0.0 ? 1.0 / p->desc.sigma_norm : 1.0;
@@ -711,6 +785,14 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     }
   }
   const int n_int = (int)ints.size();
+  // Neyman allocation: an integral may take up to min(n_perm, 4) equal
+  // shares in an iteration, so its chunks cover that many points
+  const bool neyman = o.allocation == MEM_ALLOC_NEYMAN;
+  std::vector<int64_t> cover(n_int);
+  for (int ig = 0; ig < n_int; ++ig) {
+    const int np = ev_np[ints[ig].event];
+    cover[ig] = neyman ? ints[ig].n_points * std::min(np, 4) : ints[ig].n_points;
+  }
   std::vector<Chunk> chunks;
   int64_t part_total = 0;
   for (int ig = 0; ig < n_int; ++ig) {
@@ -720,10 +802,10 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     const int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : tuned > 0 ? tuned : kDefaultChunk;
     d.chunk0 = (int64_t)chunks.size();
     d.n_chunks = 0;
-    for (int64_t s0 = 0; s0 < d.n_points; s0 += chunk_pts) {
+    for (int64_t s0 = 0; s0 < cover[ig]; s0 += chunk_pts) {
       Chunk c{};
       c.integral = ig; c.event = d.event; c.perm = d.perm;
-      c.count = (int32_t)std::min<int64_t>(chunk_pts, d.n_points - s0);
+      c.count = (int32_t)std::min<int64_t>(chunk_pts, cover[ig] - s0);
       c.start = s0;
       c.part_off = part_total;
       c.proc = int_proc[ig];
@@ -767,7 +849,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   st = dev.make(ev, ws);
   if (st != MEM_OK) return st;
   DevBuf b_procs, b_ints, b_chunks, b_queue, b_grids, b_parts, b_state, b_active, b_evi0, b_evnp, b_evnorm, b_done,
-      b_ctl, b_heads, b_P, b_err, b_status;
+      b_ctl, b_heads, b_P, b_err, b_status, b_alloc, b_cover, b_nev;
   size_t qtotal = 0;
   for (auto& G : groups) qtotal += G.queue.size();
   HIP_TRY(b_procs.alloc(ptab.size() * sizeof(ProcParams)));
@@ -784,6 +866,11 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   HIP_TRY(b_done.alloc((size_t)n_ev * sizeof(int32_t)));
   HIP_TRY(b_ctl.alloc(sizeof(Control)));
   HIP_TRY(b_heads.alloc(groups.size() * sizeof(uint32_t)));
+  HIP_TRY(b_nev.alloc(sizeof(double)));
+  if (neyman) {
+    HIP_TRY(b_alloc.alloc((size_t)n_int * sizeof(int64_t)));
+    HIP_TRY(b_cover.alloc((size_t)n_int * sizeof(int64_t)));
+  }
   const bool out_dev = o.outputs_on_device != 0;
   if (!out_dev) {
     HIP_TRY(b_P.alloc(n_ev * sizeof(double)));
@@ -800,6 +887,14 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   HIP_TRY(hipMemcpyAsync(b_evi0.p, ev_int0.data(), n_ev * sizeof(int64_t), hipMemcpyHostToDevice, ws));
   HIP_TRY(hipMemcpyAsync(b_evnp.p, ev_np.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, ws));
   HIP_TRY(hipMemcpyAsync(b_evnorm.p, ev_norm.data(), n_ev * sizeof(double), hipMemcpyHostToDevice, ws));
+  std::vector<int64_t> alloc0;
+  if (neyman) {
+    // the first iteration splits equally
+    alloc0.resize(n_int);
+    for (int ig = 0; ig < n_int; ++ig) alloc0[ig] = ints[ig].n_points;
+    HIP_TRY(hipMemcpyAsync(b_alloc.p, alloc0.data(), n_int * sizeof(int64_t), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemcpyAsync(b_cover.p, cover.data(), n_int * sizeof(int64_t), hipMemcpyHostToDevice, ws));
+  }
   const Control ctl0{0u, 0u, 0, 0u};
   HIP_TRY(hipMemcpyAsync(b_ctl.p, &ctl0, sizeof(Control), hipMemcpyHostToDevice, ws));
   {
@@ -809,6 +904,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                        b_active.as<int32_t>(), (int64_t)n_int, 1);
     hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n_ev + 255) / 256)), dim3(256), 0, ws,
                        b_done.as<int32_t>(), (int64_t)n_ev, 0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, ws, b_nev.as<double>(), (int64_t)1, 0.0);
     hipLaunchKernelGGL(init_grids_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_grids.as<double>(),
                        b_ints.as<IntegralDesc>(), n_int);
     HIP_TRY(hipGetLastError());
@@ -856,17 +952,23 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       }
       hipLaunchKernelGGL(G.kernel, dim3(G.blocks), dim3(kBlock), 0, ws, b_procs.as<ProcParams>(), dev.view, cq,
                          (int64_t)G.queue.size(), b_ints.as<IntegralDesc>(), b_grids.as<double>(),
-                         b_active.as<int32_t>(), o.seed, ctl, b_heads.as<uint32_t>() + g, b_parts.as<double>());
+                         b_active.as<int32_t>(), o.seed, ctl, b_heads.as<uint32_t>() + g, b_parts.as<double>(),
+                         neyman ? b_alloc.as<int64_t>() : nullptr);
       HIP_TRY(hipGetLastError());
       if (time_kernels) HIP_TRY(hipEventRecord(tev->back(), ws));
     }
     hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(),
                        b_chunks.as<Chunk>(), b_parts.as<double>(), b_grids.as<double>(), b_state.as<double>(),
-                       b_active.as<int32_t>(), o.alpha, ctl, n_int, o.iter_out);
+                       b_active.as<int32_t>(), o.alpha, ctl, n_int, o.iter_out,
+                       neyman ? b_alloc.as<int64_t>() : nullptr, b_nev.as<double>());
     if (target_mode)
       hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                          b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
                          o.target_rel_err, ctl, 0, nullptr, nullptr, nullptr, nullptr, b_done.as<int32_t>());
+    if (neyman)
+      hipLaunchKernelGGL(neyman_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
+                         b_ints.as<IntegralDesc>(), b_state.as<double>(), b_active.as<int32_t>(),
+                         b_cover.as<int64_t>(), b_alloc.as<int64_t>(), n_ev);
     hipLaunchKernelGGL(iter_end_kernel, dim3(1), dim3(64), 0, ws, ctl);
     HIP_TRY(hipGetLastError());
     return MEM_OK;
@@ -892,7 +994,6 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   }
   auto wall0 = std::chrono::steady_clock::now();
-  int used_iters = iters;
   for (int j = 0; j < iters; ++j) {
     if (use_graph) HIP_TRY(hipGraphLaunch(gexec, ws));
     else {
@@ -903,7 +1004,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       Control hc{};
       HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, ws));
       HIP_TRY(hipStreamSynchronize(ws));
-      if (hc.n_running == 0) { used_iters = j + 1; break; }
+      if (hc.n_running == 0) break;
     }
   }
   double* P = out_dev ? p_out : b_P.as<double>();
@@ -930,15 +1031,11 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       HIP_TRY(hipEventElapsedTime(&t, tev[i], tev[i + 1]));
       ms += t;
     }
-    // evaluations: each integral's points times the iterations its event
-    // ran (converged events stop; events outside the mask run none)
-    std::vector<int32_t> dn(n_ev);
-    HIP_TRY(hipMemcpy(dn.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost));
+    // evaluations, counted on the device: every active integral's points
+    // of every iteration (converged events stop; events outside the mask
+    // run none)
     double n_evals = 0.0;
-    for (const auto& d : ints) {
-      if (ev_mask && !ev_mask[d.event]) continue;
-      n_evals += (double)d.n_points * (double)(dn[d.event] ? dn[d.event] : used_iters);
-    }
+    HIP_TRY(hipMemcpy(&n_evals, b_nev.p, sizeof(double), hipMemcpyDeviceToHost));
     o.timing_out[0] = ms;
     o.timing_out[1] = (double)(tev.size() / 2);
     o.timing_out[2] = n_evals;

@@ -1,0 +1,160 @@
+"""Neyman allocation of an event's points among its permutations
+(MEM_ALLOC_NEYMAN): estimate-level checks.
+
+The allocation changes which points of the stream an integral evaluates
+after the first iteration, so values are not comparable point by point;
+what must hold: the first iteration is the equal split bit for bit, the
+estimates agree with equal splitting and with the oracle within the
+combined MC error, the error at a fixed budget shrinks where one
+permutation dominates the variance, the budget is respected, and graph
+replay and per-iteration launches give the same numbers.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import events
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mem():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1407_7595_amd as m
+    m.lib()
+    return m
+
+
+def run(mem, comps, procs, n_pts, n_it, alloc, **kw):
+    P, E, S = mem.integrate_events(comps, procs, n_pts, n_it, seed=77, allocation=alloc, **kw)
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), E.cpu().numpy(), S.cpu().numpy()
+
+
+def test_first_iteration_is_the_equal_split(mem):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = events.ttbar_dilepton(16, 101)
+    comps = mem.to_components(d["obs"]).cuda()
+    outs = []
+    for alloc in (mem.MEM_ALLOC_EQUAL, mem.MEM_ALLOC_NEYMAN):
+        say(f"iteration sums, allocation {alloc}")
+        it = torch.zeros(4 * 32 * 2, dtype=torch.float64, device="cuda")
+        run(mem, comps, p, 8192, 4, alloc, iter_out=it)
+        outs.append(it.cpu().numpy().reshape(4, 32, 2))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert not np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_estimates_agree_and_errors_shrink(mem):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = events.ttbar_dilepton(96, 102)
+    comps = mem.to_components(d["obs"]).cuda()
+    say("96 dilepton events, equal split")
+    Pe, Ee, Se = run(mem, comps, p, 16384, 6, mem.MEM_ALLOC_EQUAL)
+    say("96 dilepton events, Neyman allocation")
+    Pn, En, Sn = run(mem, comps, p, 16384, 6, mem.MEM_ALLOC_NEYMAN)
+    assert np.all(Se == 0) and np.all(Sn == 0)
+    ok = (Pe > 0) & (Pn > 0)
+    assert ok.sum() >= 90
+    pull = (Pn - Pe)[ok] / np.sqrt(En[ok] ** 2 + Ee[ok] ** 2)
+    ratio = En[ok] / Pn[ok] / (Ee[ok] / Pe[ok])
+    say(f"  pulls: median |pull| {np.median(np.abs(pull)):.3g}, max {np.abs(pull).max():.3g}; "
+        f"relative error Neyman / equal: median {np.median(ratio):.3g}")
+    # independent points after the first iteration: pulls are N(0, ~1)
+    assert np.median(np.abs(pull)) < 1.0 and np.abs(pull).max() < 4.5
+    assert np.median(ratio) < 0.95
+
+
+def test_against_oracle_pull(mem):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    po = oracle.tt_params()
+    d = events.ttbar_dilepton(10, 0x14077596)
+    comps = mem.to_components(d["obs"]).cuda()
+    say("10 events against the oracle (equal split in the oracle)")
+    P, E, S = run(mem, comps, p, 8000, 6, mem.MEM_ALLOC_NEYMAN)
+    Po, Eo, So = oracle.integrate_events(oracle.KIND_TT, po, d["obs"], 77, 8000, 6)
+    assert np.all(S == 0) and np.all(P > 0)
+    pull = (P - Po) / np.sqrt(E ** 2 + Eo ** 2)
+    say("  pulls", np.round(pull, 3))
+    assert np.all(np.abs(pull) < 4.0)
+
+
+def test_budget_graph_and_mixed_batch(mem):
+    """points evaluated never exceed the equal split's; graph replay equals
+    per-iteration launches; a mixed batch with 12-permutation events"""
+    from test_gpu_parity import sl_split
+    tt = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    sl = mem.Process(mem.MEM_TT_SEMILEPTON, precision=mem.MEM_FP32)
+    dt = events.ttbar_dilepton(12, 103)["obs"]
+    ds = events.ttbar_semileptonic(6, 104)["obs"]
+    obs = np.zeros((18, 5, 4))
+    obs[:12, :4] = dt
+    obs[12:, :5] = ds[:, :5]
+    charge = np.ones(18, dtype=np.int32)
+    charge[12:] = ds[:, 5, 0].astype(np.int32)
+    comps = torch.as_tensor(np.ascontiguousarray(obs.transpose(2, 1, 0))).cuda()
+    ch = torch.as_tensor(charge).cuda()
+    procs = [tt] * 12 + [sl] * 6
+    n_pts = [8192] * 12 + [12 * 1024] * 6
+    res = {}
+    for alloc in (mem.MEM_ALLOC_EQUAL, mem.MEM_ALLOC_NEYMAN):
+        for graph in (0, 1):
+            say(f"mixed batch allocation {alloc} graph {graph}")
+            timing = (ctypes.c_double * 8)() if graph == 0 else None
+            P, E, S = run(mem, comps, procs, n_pts, 5, alloc, charge=ch, timing=timing)
+            res[(alloc, graph)] = (P, E, S, timing[2] if timing is not None else None)
+    for alloc in (0, 1):
+        assert np.array_equal(res[(alloc, 0)][0], res[(alloc, 1)][0])
+        assert np.all(res[(alloc, 1)][2] == 0)
+    n_eq, n_ney = res[(0, 0)][3], res[(1, 0)][3]
+    say(f"  evaluations: equal {n_eq:.0f}, Neyman {n_ney:.0f}")
+    assert n_eq == 5 * (12 * 8192 + 6 * 12 * 1024)
+    assert 0.97 * n_eq <= n_ney <= n_eq
+    Pe, Ee = res[(0, 1)][0], res[(0, 1)][1]
+    Pn, En = res[(1, 1)][0], res[(1, 1)][1]
+    pull = (Pn - Pe)[:12] / np.sqrt(En[:12] ** 2 + Ee[:12] ** 2)
+    say("  dilepton pulls", np.round(pull, 3))
+    assert np.all(np.abs(pull) < 4.5)
+    # semileptonic at 1024 points per permutation and iteration: the weights
+    # are heavy-tailed and the equal split falls far below the integral (its
+    # error estimate too small); against a 64x equal-split reference the
+    # Neyman estimates are the closer ones
+    say("  semileptonic reference: equal split, 64x points, 8 iterations")
+    Pr, Er, Sr = run(mem, comps[:, :, 12:].contiguous(), sl, 64 * 12 * 1024, 8, mem.MEM_ALLOC_EQUAL,
+                     charge=ch[12:].contiguous())
+    assert np.all(Sr == 0) and np.all(Er < 0.05 * Pr)
+    de = np.abs(Pe[12:] - Pr) / Pr
+    dn = np.abs(Pn[12:] - Pr) / Pr
+    say(f"  semileptonic |P - ref| / ref: equal {np.round(de, 3)}, Neyman {np.round(dn, 3)}")
+    assert np.median(dn) <= np.median(de)
+
+
+def test_target_mode_fewer_iterations(mem):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = events.ttbar_dilepton(128, 105)
+    comps = mem.to_components(d["obs"]).cuda()
+    iters = {}
+    for alloc in (mem.MEM_ALLOC_EQUAL, mem.MEM_ALLOC_NEYMAN):
+        say(f"target 2 %, allocation {alloc}")
+        n_it = torch.zeros(128, dtype=torch.int32, device="cuda")
+        P, E, S = mem.integrate_events(comps, p, 16384, 0, seed=78, target_rel_err=0.02, max_iter=40,
+                                       allocation=alloc, n_iter_out=n_it)
+        torch.cuda.synchronize()
+        S, P, E = S.cpu().numpy(), P.cpu().numpy(), E.cpu().numpy()
+        assert np.all(S == 0)
+        assert np.all(E <= 0.02 * P * (1 + 1e-12))
+        iters[alloc] = n_it.cpu().numpy()
+    say(f"  mean iterations: equal {iters[0].mean():.3g}, Neyman {iters[1].mean():.3g}")
+    assert iters[1].mean() < iters[0].mean()
