@@ -927,11 +927,13 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   // (one gather per call)
   DevBuf b_chunks_q;
   HIP_TRY(b_chunks_q.alloc(flat.size() * sizeof(Chunk)));
+  std::vector<size_t> gqn(groups.size());     // queue length per group
   {
     std::vector<Chunk> perm_chunks(flat.size());
     for (size_t i = 0; i < flat.size(); ++i) perm_chunks[i] = chunks[flat[i]];
     HIP_TRY(hipMemcpyAsync(b_chunks_q.p, perm_chunks.data(), flat.size() * sizeof(Chunk), hipMemcpyHostToDevice, ws));
     HIP_TRY(hipStreamSynchronize(ws));   // perm_chunks goes out of scope
+    for (size_t g = 0; g < groups.size(); ++g) gqn[g] = groups[g].queue.size();
   }
 
   const int ev_blocks = (n_ev + 255) / 256;
@@ -951,7 +953,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
         HIP_TRY(hipEventRecord(a, ws));
       }
       hipLaunchKernelGGL(G.kernel, dim3(G.blocks), dim3(kBlock), 0, ws, b_procs.as<ProcParams>(), dev.view, cq,
-                         (int64_t)G.queue.size(), b_ints.as<IntegralDesc>(), b_grids.as<double>(),
+                         (int64_t)gqn[g], b_ints.as<IntegralDesc>(), b_grids.as<double>(),
                          b_active.as<int32_t>(), o.seed, ctl, b_heads.as<uint32_t>() + g, b_parts.as<double>(),
                          neyman ? b_alloc.as<int64_t>() : nullptr);
       HIP_TRY(hipGetLastError());
@@ -983,7 +985,9 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     ~GraphGuard() { if (x) (void)hipGraphExecDestroy(x); if (g) (void)hipGraphDestroy(g); }
   } gg{graph, gexec};
   const bool use_graph = want_graph && ws != nullptr;
-  if (use_graph) {
+  auto capture = [&]() -> mem_status {
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
     HIP_TRY(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
     mem_status cs = enqueue_iteration(false, nullptr);
     hipGraph_t gcap = nullptr;
@@ -992,7 +996,48 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     if (cs != MEM_OK) return cs;
     if (ce != hipSuccess) return fail(MEM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
     HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    return MEM_OK;
+  };
+  if (use_graph) {
+    mem_status cs = capture();
+    if (cs != MEM_OK) return cs;
   }
+  // Target mode: once the running events have halved since the queue was
+  // last built, the queue is rebuilt from the running events' chunks only
+  // (same order), so that late iterations do not pop the retired events'
+  // chunks one by one.  Partial sums live in per-chunk slots and are summed
+  // per integral in chunk order, so the results do not change.
+  std::vector<int32_t> qhost(flat.begin(), flat.end());
+  int64_t running_at_build = n_ev;
+  auto compact = [&]() -> mem_status {
+    std::vector<int32_t> dn(n_ev);
+    HIP_TRY(hipMemcpy(dn.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> nq;
+    std::vector<size_t> ng(groups.size());
+    size_t pos = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+      const size_t start = nq.size();
+      for (size_t i = 0; i < gqn[g]; ++i) {
+        const int32_t c = qhost[pos + i];
+        if (!dn[chunks[c].event]) nq.push_back(c);
+      }
+      pos += gqn[g];
+      ng[g] = nq.size() - start;
+    }
+    std::vector<Chunk> pc(nq.size());
+    for (size_t i = 0; i < nq.size(); ++i) pc[i] = chunks[nq[i]];
+    if (!pc.empty())
+      HIP_TRY(hipMemcpy(b_chunks_q.p, pc.data(), pc.size() * sizeof(Chunk), hipMemcpyHostToDevice));
+    size_t off = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+      gq0[g] = off;
+      gqn[g] = ng[g];
+      off += ng[g];
+      groups[g].blocks = persistent_blocks(groups[g].kernel, (int64_t)ng[g]);
+    }
+    qhost.swap(nq);
+    return use_graph ? capture() : MEM_OK;
+  };
   auto wall0 = std::chrono::steady_clock::now();
   for (int j = 0; j < iters; ++j) {
     if (use_graph) HIP_TRY(hipGraphLaunch(gexec, ws));
@@ -1005,6 +1050,11 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, ws));
       HIP_TRY(hipStreamSynchronize(ws));
       if (hc.n_running == 0) break;
+      if (2 * (int64_t)hc.n_running <= running_at_build && n_ev >= 64) {
+        running_at_build = hc.n_running;
+        mem_status cs = compact();
+        if (cs != MEM_OK) return cs;
+      }
     }
   }
   double* P = out_dev ? p_out : b_P.as<double>();

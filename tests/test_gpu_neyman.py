@@ -38,7 +38,7 @@ def mem():
 
 
 def run(mem, comps, procs, n_pts, n_it, alloc, **kw):
-    P, E, S = mem.integrate_events(comps, procs, n_pts, n_it, seed=77, allocation=alloc, **kw)
+    P, E, S = mem.integrate_events(comps, procs, n_pts, n_it, seed=kw.pop("seed", 77), allocation=alloc, **kw)
     torch.cuda.synchronize()
     return P.cpu().numpy(), E.cpu().numpy(), S.cpu().numpy()
 
@@ -158,3 +158,31 @@ def test_target_mode_fewer_iterations(mem):
         iters[alloc] = n_it.cpu().numpy()
     say(f"  mean iterations: equal {iters[0].mean():.3g}, Neyman {iters[1].mean():.3g}")
     assert iters[1].mean() < iters[0].mean()
+
+
+@pytest.mark.parametrize("alloc", [0, 1])
+def test_target_mode_matches_fixed_runs(mem, alloc):
+    """an event retired after n iterations in target mode (where the queue is
+    rebuilt from the running events as they retire) has exactly the
+    estimate of a fixed run of n iterations"""
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = events.ttbar_dilepton(160, 106)
+    comps = mem.to_components(d["obs"]).cuda()
+    n_it = torch.zeros(160, dtype=torch.int32, device="cuda")
+    say(f"target 3 %, allocation {alloc}, 160 events")
+    P, E, S = mem.integrate_events(comps, p, 8192, 0, seed=79, target_rel_err=0.03, max_iter=30,
+                                   allocation=alloc, n_iter_out=n_it)
+    torch.cuda.synchronize()
+    P, E, S, n = P.cpu().numpy(), E.cpu().numpy(), S.cpu().numpy(), n_it.cpu().numpy()
+    ok = S == 0
+    assert ok.sum() >= 150
+    counts = np.unique(n[ok], return_counts=True)
+    say(f"  iterations used: {dict(zip(counts[0].tolist(), counts[1].tolist()))}")
+    checked = 0
+    for it in counts[0][:4]:
+        say(f"  fixed run of {it} iterations")
+        Pf, Ef, Sf = run(mem, comps, p, 8192, int(it), alloc, seed=79)
+        sel = ok & (n == it)
+        assert np.array_equal(P[sel], Pf[sel]) and np.array_equal(E[sel], Ef[sel])
+        checked += int(sel.sum())
+    assert checked >= 100
