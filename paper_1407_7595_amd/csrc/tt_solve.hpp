@@ -43,13 +43,28 @@ __device__ __forceinline__ void horner_d(const double (&c)[N + 1], double t, dou
   for (int i = N - 1; i >= 0; --i) { df = __fma_rn(df, t, f); f = __fma_rn(f, t, c[i]); }
 }
 
+// Reciprocal for a Newton step: the hardware estimate refined once (an
+// error of the step's size times ~1e-15 changes no iterate that matters:
+// the step is recomputed from the new residual every iteration).
+__device__ __forceinline__ double step_rcp(double d)
+{
+#ifdef MEM_HOST_COUNT
+  return 1.0 / d;
+#else
+  const double r = __builtin_amdgcn_rcp(d);
+  return __fma_rn(r, __fma_rn(-d, r, 1.0), r);
+#endif
+}
+
 // Root of a polynomial that is monotone on [lo, hi] with a sign change,
 // starting at x0 (the midpoint when x0 is not inside): Newton steps, with
 // bisection whenever a step leaves the bracket.  Stops when |p(x)| is at
 // most 1e-15 sum |c_i| |x|^i (x is then the exact root of a polynomial
 // whose coefficients differ from c by ~1e-15 relative; the degree-4 Horner
-// rounding bound is 8 u = 8.9e-16) or when the step vanishes.
-template <int N>
+// rounding bound is 8 u = 8.9e-16) or when the step vanishes.  TEST0 =
+// false skips that test at the starting point (the quartic's model
+// estimates are never within rounding of a root).
+template <int N, bool TEST0 = true>
 __device__ __forceinline__ double bracketed_root(const double (&c)[N + 1], double lo, double hi, double flo,
                                                  double x0)
 {
@@ -57,13 +72,15 @@ __device__ __forceinline__ double bracketed_root(const double (&c)[N + 1], doubl
   for (int it = 0; it < 80; ++it) {
     double f, df;
     horner_d<N>(c, x, f, df);
-    const double ax = fabs(x);
-    double fa = fabs(c[N]);
+    if (TEST0 || it > 0) {
+      const double ax = fabs(x);
+      double fa = fabs(c[N]);
 #pragma unroll
-    for (int i = N - 1; i >= 0; --i) fa = __fma_rn(fa, ax, fabs(c[i]));
-    if (fabs(f) <= 1e-15 * fa) return x;
+      for (int i = N - 1; i >= 0; --i) fa = __fma_rn(fa, ax, fabs(c[i]));
+      if (fabs(f) <= 1e-15 * fa) return x;
+    }
     if ((f < 0.0) == (flo < 0.0)) lo = x; else hi = x;
-    double xn = x - f * fast_rcp(df);
+    double xn = x - f * step_rcp(df);
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
     if (fabs(xn - x) <= 4e-16 * fabs(x) + 1e-300 || !(hi > lo)) return xn;
     x = xn;
@@ -90,7 +107,7 @@ struct Four {
 // Roots of a polynomial in each of `NI` consecutive intervals of pts
 // (monotone on each), appended ascending to out; guess(i, lo, hi, flo, fhi)
 // gives the starting point in interval i.
-template <int N, int NI, class Guess>
+template <int N, int NI, bool TEST0, class Guess>
 __device__ __forceinline__ void roots_on_intervals(const double (&c)[N + 1], const double (&pts)[NI + 1], Four& out,
                                                    Guess guess)
 {
@@ -102,7 +119,7 @@ __device__ __forceinline__ void roots_on_intervals(const double (&c)[N + 1], con
     if (hi > lo) {
       if (fprev == 0.0) out.put(lo);
       else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0)
-        out.put(bracketed_root<N>(c, lo, hi, fprev, guess(i, lo, hi, fprev, fnext)));
+        out.put(bracketed_root<N, TEST0>(c, lo, hi, fprev, guess(i, lo, hi, fprev, fnext)));
     }
     fprev = fnext;
   }
@@ -159,7 +176,7 @@ __device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four
   Four crit;
   crit.n = 0;
   const double p3[4] = {-bound, s0, s1, bound};
-  roots_on_intervals<3, 3>(d1, p3, crit, [&](int, double lo, double hi, double, double) {
+  roots_on_intervals<3, 3, true>(d1, p3, crit, [&](int, double lo, double hi, double, double) {
     return (est[0] > lo && est[0] < hi) ? est[0] : (est[1] > lo && est[1] < hi) ? est[1] : est[2];
   });
   // the quartic is monotone between consecutive critical points; a root
@@ -168,7 +185,7 @@ __device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four
   const double p4[5] = {-bound, crit.n > 0 ? crit.v0 : bound, crit.n > 1 ? crit.v1 : bound,
                         crit.n > 2 ? crit.v2 : bound, bound};
   roots.n = 0;
-  roots_on_intervals<4, 4>(c, p4, roots, [&](int i, double lo, double hi, double flo, double fhi) {
+  roots_on_intervals<4, 4, false>(c, p4, roots, [&](int i, double lo, double hi, double flo, double fhi) {
     const bool lo_crit = i > 0, hi_crit = hi < bound;
     const bool use_lo = lo_crit && (!hi_crit || fabs(flo) <= fabs(fhi));
     const double e = use_lo ? lo : hi, fe = use_lo ? flo : fhi;
