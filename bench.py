@@ -35,9 +35,9 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 # Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
 # FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
 # peak is half the FP32 one).  Counted by paper_1407_7595_amd/opcount.py on
-# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1328.7 FP64 +
-# 1051.9 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
-FLOP_PER_EVAL = 2.0 * 1328.7 + 1051.9
+# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1254.9 FP64 +
+# 742.0 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
+FLOP_PER_EVAL = 2.0 * 1254.9 + 742.0
 
 # HBM bytes per fixed-budget launch of the integrand kernel (4096 events x
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this

@@ -152,7 +152,6 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
     const v4 hqa = B.apply_me(qa), hqb = B.apply_me(qb), hbh = B.apply_me(bh);
     const v4 hbl = B.apply_me(bl), hl = B.apply_me(l), hn = B.apply_me(nu);
     const double ak = 0.5 * x1 * pp.sqrt_s * kMeScale, bk = 0.5 * x2 * pp.sqrt_s * kMeScale;
-    const v4 k1{ak, 0.0, 0.0, ak}, k2{bk, 0.0, 0.0, -bk};
     T gg, qq12, qq21;
     tt_lumis<T>(pp, x1, x2, gg, qq12, qq21);
     T me = T(0);
@@ -174,9 +173,8 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
       drow<T> R, C;
       decay_rows<T>(tb_, tf1b, tf1, ab_, af2, af2b, pt, ptb, mt, R, C);
       const T mgg = gg_sum<T>(R, C, pt, T(ak), T(bk), mt);
-      const T mq1 = qq_sum<T>(R, C, k1, k2);
-      const T mq2 = qq_sum<T>(R, C, k2, k1);
-      me += gg * mgg * T(1.0 / 256.0) + (qq12 * mq1 + qq21 * mq2) * T(1.0 / 36.0);
+      const T mqq = qq_beams<T>(R, C, T(ak), T(bk));
+      me += gg * mgg * T(1.0 / 256.0) + (qq12 + qq21) * mqq * T(1.0 / 36.0);
     }
     const double shat = x1 * x2 * pp.S;
     acc += P.e * ((double)me * kMeDeg8) * bwtl * fast_rcp(Eh * shat * x1 * x2 * dq * nu.e);

@@ -189,10 +189,9 @@ __device__ __forceinline__ bool tt_me_pdf(const ProcParams& pp, const v4& b0, co
   decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
   const double a = 0.5 * x1 * pp.sqrt_s * kMeScale, bm = 0.5 * x2 * pp.sqrt_s * kMeScale;
   const T mgg = gg_sum<T>(R, C, pt, T(a), T(bm), mt);
-  const v4 k1{a, 0.0, 0.0, a}, k2{bm, 0.0, 0.0, -bm};
-  const T mq1 = qq_sum<T>(R, C, k1, k2);
-  const T mq2 = qq_sum<T>(R, C, k2, k1);
-  const T me = gg * mgg * T(1.0 / 256.0) + (qq12 * mq1 + qq21 * mq2) * T(1.0 / 36.0);
+  // q qbar: the same |M|^2 for the quark from either beam
+  const T mqq = qq_beams<T>(R, C, T(a), T(bm));
+  const T me = gg * mgg * T(1.0 / 256.0) + (qq12 + qq21) * mqq * T(1.0 / 36.0);
   me_out = (double)me * kMeDeg8;
   return true;
 }

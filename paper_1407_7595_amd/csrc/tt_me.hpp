@@ -191,25 +191,26 @@ __device__ __forceinline__ T gg_sum(const drow<T>& R, const drow<T>& C, const mo
   return sum;
 }
 
-// q(kq) qbar(kqb) -> t tbar through one s-channel gluon, summed over the
-// two non-vanishing quark helicities and colours (factor 2).
+// q qbar -> t tbar through one s-channel gluon, summed over the two
+// non-vanishing quark helicities and colours (factor 2), for beams along
+// +-z: k1 = (a,0,0,a), k2 = (bm,0,0,-bm).  The quark currents are
+//   left:  J.sigma-bar = 2 (eps^T lqb*)(lq^T eps),  J.sigma = 2 lq lqb^dagger
+//   right: J.sigma = 2 (eps^T ltqb*)(ltq^T eps),    J.sigma-bar = 2 ltq ltqb^dagger
+// and R J-slash C = R_L (J.sigma) C_R + R_R (J.sigma-bar) C_L.  With the
+// beam spinors written out (lambda(k1) = (0, al), lambda~(k1) = (al, 0),
+// lambda(k2) = (be, 0), lambda~(k2) = (0, be), al = sqrt(2a), be = sqrt(2bm))
+// the two helicity amplitudes of a quark along +z are
+//   A_L = 2 al be X,  X = R_L.b C_R.a - R_R.b C_L.a,
+//   A_R = 2 al be Y,  Y = R_R.a C_L.b - R_L.a C_R.b,
+// and for the quark along -z they are -A_R and -A_L: both orderings give
+//   2 (|A_L|^2 + |A_R|^2) / s^2 = 8 (|X|^2 + |Y|^2) / s,  s = 4 a bm,
+// with no square roots.
 template <class T>
-__device__ __forceinline__ T qq_sum(const drow<T>& R, const drow<T>& C, const v4& kq, const v4& kqb)
+__device__ __forceinline__ T qq_beams(const drow<T>& R, const drow<T>& C, T a, T bm)
 {
-  // left-handed current: J.sigma-bar = 2 (eps^T lqb*)(lq^T eps),
-  //                      J.sigma     = 2 lq lqb^dagger
-  // right-handed:        J.sigma     = 2 (eps^T ltqb*)(ltq^T eps),
-  //                      J.sigma-bar = 2 ltq ltqb^dagger
-  // R J-slash C = R_L (J.sigma) C_R + R_R (J.sigma-bar) C_L
-  sp<T> lq = lam<T>(kq), lqb = lam<T>(kqb), tq = lamt<T>(kq), tqb = lamt<T>(kqb);
-  double s = 2.0 * mdot(kq, kqb);
-  T is = T(fast_rcp(s));
-  // left
-  sp<T> e1 = epsT(cj(lqb)), e2 = epsT(lq);      // J.sigma-bar = 2 e1 e2^T
-  cx<T> aL = T(2) * (dot2(R.L, lq) * dot2(cj(lqb), C.R)) + T(2) * (dot2(R.R, e1) * dot2(e2, C.L));
-  sp<T> f1 = epsT(cj(tqb)), f2 = epsT(tq);      // J.sigma = 2 f1 f2^T
-  cx<T> aR = T(2) * (dot2(R.L, f1) * dot2(f2, C.R)) + T(2) * (dot2(R.R, tq) * dot2(cj(tqb), C.L));
-  return T(2) * (abs2(aL) + abs2(aR)) * is * is;
+  const cx<T> X = R.L.b * C.R.a - R.R.b * C.L.a;
+  const cx<T> Y = R.R.a * C.L.b - R.L.a * C.R.b;
+  return T(8) * (abs2(X) + abs2(Y)) * rcp_t(T(4) * a * bm);
 }
 
 // ------------------------------------------------------------ t tbar H --
