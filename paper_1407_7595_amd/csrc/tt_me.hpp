@@ -50,31 +50,19 @@ template <class T> struct sp { cx<T> a, b; };   // two-component spinor
 
 // lambda(p): (p.sigma-bar) lambda = 0, lambda lambda^dagger = p.sigma
 // (the left-handed massless solution, normalised to |lambda|^2 = 2E).
-// E +- p_z is formed in FP64 on the side without cancellation.
+// E + |p_z| is formed in FP64 (no cancellation); for p_z >= 0
+//   lambda = (-p_x n, p_y n; (E + p_z) n, 0),
+// otherwise ((E - p_z) n, 0; -p_x n, -p_y n), n = 1/sqrt(E + |p_z|): one
+// reciprocal square root and selects, so that the lanes of a wavefront
+// with either sign share one path.
 template <class T>
 __device__ __forceinline__ sp<T> lam(const v4& p)
 {
-  if (p.z >= 0.0) {
-    double ep = p.e + p.z;
-    const double n = fast_rsqrt(ep);
-    return sp<T>{{T(-p.x * n), T(p.y * n)}, {T(ep * n), T(0)}};
-  }
-  double em = p.e - p.z;
-  const double n = fast_rsqrt(em);
-  return sp<T>{{T(em * n), T(0)}, {T(-p.x * n), T(-p.y * n)}};
-}
-// lambda-tilde(p): (p.sigma) lt = 0 (right-handed), |lt|^2 = 2E
-template <class T>
-__device__ __forceinline__ sp<T> lamt(const v4& p)
-{
-  if (p.z >= 0.0) {
-    double ep = p.e + p.z;
-    const double n = fast_rsqrt(ep);
-    return sp<T>{{T(ep * n), T(0)}, {T(p.x * n), T(p.y * n)}};
-  }
-  double em = p.e - p.z;
-  const double n = fast_rsqrt(em);
-  return sp<T>{{T(p.x * n), T(-p.y * n)}, {T(em * n), T(0)}};
+  const bool up = p.z >= 0.0;
+  const double ep = p.e + fabs(p.z);
+  const double n = fast_rsqrt(ep);
+  const T q = T(ep * n), xn = T(-p.x * n), yn = T(p.y * n);
+  return up ? sp<T>{{xn, yn}, {q, T(0)}} : sp<T>{{q, T(0)}, {xn, -yn}};
 }
 // eps^T v with eps = [[0,1],[-1,0]]: (-v_b, v_a)
 template <class T> __device__ __forceinline__ sp<T> epsT(sp<T> v) { return sp<T>{-v.b, v.a}; }
