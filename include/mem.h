@@ -228,8 +228,9 @@ void mem_destroy_process(mem_process p);
  *          0 the gluon) at index fl + 5, at node (ix, iq) with
  *            ln x = bounds[0] + ix (bounds[1] - bounds[0]) / (nx - 1),
  *            ln Q = bounds[2] + iq (bounds[3] - bounds[2]) / (nq - 1);
- *          copied to the current device (the process then integrates on
- *          that device only).  NULL restores the built-in toy densities.
+ *          copied to the current device; every later call with this
+ *          process returns MEM_EINVAL on another current device.  NULL
+ *          restores the built-in toy densities.
  *  nx, nq  >= 2 each; nx * nq <= 2^22
  *  bounds  ln x and ln Q ranges (natural logarithms), increasing
  * Outside the grid the edge cells extrapolate linearly.  Factorisation

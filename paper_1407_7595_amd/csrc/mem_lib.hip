@@ -48,6 +48,7 @@ struct mem_process_s {
   int32_t chunk_points = 0;   // tuned points per work-queue chunk (0: library default)
   // parton-density grid on the device (null: toy densities) and its shape
   float* pdf_dev = nullptr;
+  int pdf_device = -1;        // the device that holds pdf_dev
   int32_t pdf_nx = 0, pdf_nq = 0;
   double pdf_bounds[4] = {0.0, 0.0, 0.0, 0.0};
   ~mem_process_s() { if (pdf_dev) (void)hipFree(pdf_dev); }
@@ -207,6 +208,18 @@ extern "C" mem_status mem_set_transfer_functions(mem_process p, const mem_tf_des
 
 extern "C" void mem_destroy_process(mem_process p) { delete p; }
 
+// A process with a PDF grid runs on the device that holds the grid.
+static mem_status check_pdf_device(const mem_process_s* p)
+{
+  if (!p->pdf_dev) return MEM_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MEM_EDEVICE, "hipGetDevice");
+  if (dev != p->pdf_device)
+    return fail(MEM_EINVAL, "the process's PDF grid lives on device " + std::to_string(p->pdf_device) +
+                                ", the current device is " + std::to_string(dev));
+  return MEM_OK;
+}
+
 static mem_status check_pdf_shape(int32_t nx, int32_t nq, const double* b)
 {
   if (!b) return fail(MEM_EINVAL, "null bounds");
@@ -247,6 +260,7 @@ extern "C" mem_status mem_set_pdf_grid(mem_process p, const float* xf, int32_t n
   }
   if (p->pdf_dev) (void)hipFree(p->pdf_dev);
   p->pdf_dev = d;
+  if (hipGetDevice(&p->pdf_device) != hipSuccess) p->pdf_device = -1;
   p->pdf_nx = nx;
   p->pdf_nq = nq;
   for (int k = 0; k < 4; ++k) p->pdf_bounds[k] = bounds[k];
@@ -755,6 +769,10 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     if (pi < 0) { procs.push_back(p); pi = (int)procs.size() - 1; }
     ev_proc[e] = pi;
   }
+  for (const auto* pr : procs) {
+    mem_status ps = check_pdf_device(pr);
+    if (ps != MEM_OK) return ps;
+  }
   std::vector<ProcParams> ptab(procs.size());
   for (size_t k = 0; k < procs.size(); ++k) ptab[k] = procs[k]->pp;
   std::vector<IntegralDesc> ints;
@@ -1112,7 +1130,9 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
                                       const double* x, int64_t n, double* f, int32_t* nsol, void* stream)
 {
   if (!p || !x || !f) return fail(MEM_EINVAL, "null argument");
-  mem_status st = check_event_arrays(ev);
+  mem_status st = check_pdf_device(p);
+  if (st != MEM_OK) return st;
+  st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
   if (event < 0 || event >= ev->n_events) return fail(MEM_EINVAL, "event index out of range");
   if (perm < 0 || perm >= p->pp.n_perm) return fail(MEM_EINVAL, "permutation out of range");
@@ -1171,7 +1191,9 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void parton_kernel(ProcParams
 extern "C" mem_status mem_parton_weights(mem_process p, const mem_events* ev, double* w_out, void* stream)
 {
   if (!p) return fail(MEM_EINVAL, "null argument");
-  mem_status st = check_event_arrays(ev);
+  mem_status st = check_pdf_device(p);
+  if (st != MEM_OK) return st;
+  st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
   if (!w_out && ev->n_events > 0) return fail(MEM_EINVAL, "null argument");
   if (p->desc.kind != MEM_TT_DILEPTON) return fail(MEM_EUNSUPPORTED, "parton-level weights: ttbar dilepton only");
@@ -1337,7 +1359,9 @@ extern "C" mem_status mem_vegas_capture(mem_process p, const mem_events* ev, con
                                         float* w_out, void* stream)
 {
   if (!p || !event || !perm || !grids || !x_out || !w_out) return fail(MEM_EINVAL, "null argument");
-  mem_status st = check_event_arrays(ev);
+  mem_status st = check_pdf_device(p);
+  if (st != MEM_OK) return st;
+  st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
   if (n_int < 0 || n_per < 1 || n_per > (int64_t)0xFFFFFFFF) return fail(MEM_EINVAL, "bad sizes");
   if (ev->n_obj < n_obj_of(p->desc.kind)) return fail(MEM_EINVAL, "n_obj too small for the process kind");
@@ -1707,6 +1731,10 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
     for (size_t k = 0; k < procs.size(); ++k) if (procs[k] == p) pi = (int)k;
     if (pi < 0) { procs.push_back(p); pi = (int)procs.size() - 1; }
     ev_proc[e] = pi;
+  }
+  for (const auto* pr : procs) {
+    mem_status ps = check_pdf_device(pr);
+    if (ps != MEM_OK) return ps;
   }
   std::vector<ProcParams> ptab(procs.size());
   for (size_t k = 0; k < procs.size(); ++k) ptab[k] = procs[k]->pp;
