@@ -182,7 +182,17 @@ def flow_leg(mem, proc, comps, n_ev, args):
     st_alone = S.cpu().numpy()
     alone = {"events_per_s": n_ev / alone_s, "converged_fraction": float(np.mean(st_alone == 0)),
              "median_batches": float(np.median(n_used.cpu().numpy()))}
+    # VEGAS alone with the flow leg's points per iteration (the fallback's
+    # setting): the like-for-like reference for the proposal
+    t0 = time.perf_counter()
+    mem.integrate_events(comps, proc, FLOW_PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER,
+                         outputs=(P, E, S), n_iter_out=n_used, allocation=mem.MEM_ALLOC_NEYMAN)
+    torch.cuda.synchronize()
+    v_s = time.perf_counter() - t0
+    vegas_same = {"events_per_s": n_ev / v_s, "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
+                  "mean_iterations": float(np.mean(n_used.cpu().numpy()))}
     out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times), "flow_alone": alone,
+           "vegas_same_points": vegas_same,
            "points_per_event_per_batch": FLOW_PTS, "fallback_fraction": float(np.mean(st == 4)),
            "converged_fraction": float(np.mean((st == 0) | (st == 4))),
            "median_batches": float(np.median(nu_fb)),
