@@ -163,7 +163,8 @@ typedef struct mem_flow_s* mem_flow;
  *                  second batch on.
  *  ess_threshold   flow fallback threshold on ESS/N (0: 0.3)
  *  allocation      how an event's points are shared among its permutations
- *                  (VEGAS; ignored with a flow).  MEM_ALLOC_EQUAL (0, the
+ *                  (VEGAS, a flow's VEGAS fallback included; the flow's own
+ *                  batches ignore it).  MEM_ALLOC_EQUAL (0, the
  *                  default): every iteration gives each permutation
  *                  ceil(n_points / n_perm) points.  MEM_ALLOC_NEYMAN (1): the
  *                  first iteration splits equally; from then on permutation k
@@ -175,7 +176,8 @@ typedef struct mem_flow_s* mem_flow;
  *                  event's total per iteration stays n_perm equal shares up
  *                  to that cap.  Same point stream (point k of an integral is
  *                  the same u in either mode); estimates differ from equal
- *                  splitting by MC fluctuation only.                        */
+ *                  splitting by MC fluctuation only.  Other values:
+ *                  MEM_EINVAL.                                              */
 enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
 typedef struct {
   uint64_t seed;

@@ -734,6 +734,7 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
   o.use_graph = 1;
   if (opt) o = *opt;
   if (!(o.alpha > 0.0)) return fail(MEM_EINVAL, "alpha must be positive");
+  if (o.allocation != MEM_ALLOC_EQUAL && o.allocation != MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "unknown allocation");
   const bool target_mode = o.target_rel_err > 0.0;
   const int iters = target_mode ? o.max_iter : n_iter;
   if (iters < 2) return fail(MEM_EINVAL, "at least two iterations are needed");

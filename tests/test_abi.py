@@ -104,6 +104,9 @@ def test_integrate_rejects_bad_host_events_before_any_launch(mem):
     with pytest.raises(mem.MemError) as e:          # two hypotheses for three events
         mem.integrate_events(good, [p, p], 1000, 3)
     assert e.value.status == mem.MEM_EINVAL
+    with pytest.raises(mem.MemError) as e:          # unknown point allocation
+        mem.integrate_events(good, p, 1000, 3, allocation=7)
+    assert e.value.status == mem.MEM_EINVAL
 
 
 def test_tuning_table_lookup(mem, tmp_path):
