@@ -150,8 +150,19 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
         jac = vegas_map<8>(sgrid, u, x, bin);
         tt_maps<T>(pp, ev, x, m);
         double quart[5];
-        if (dilep_prepare(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, s, quart))
+        if (dilep_prepare(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, s, quart)) {
+          // the solve state goes to the lane's LDS record before the root
+          // search, so that it is not held in registers across it (the
+          // previous round's readers finished at its last wave_sync)
+          const double r[kTTRec] = {s.A1.e0, s.A1.e1, s.A1.e2, s.A1.z0, s.A1.z1, s.A1.z2,
+                                    s.A2.e0, s.A2.e1, s.A2.e2, s.A2.z0, s.A2.z1, s.A2.z2,
+                                    s.P0, s.P1, s.P2, s.Q0, s.Q1,
+                                    s.tq[0], s.tq[1], s.tq[2], s.tq[3], s.itq[0], s.itq[1], s.itq[2], s.itq[3],
+                                    s.lam, s.mx, s.my, m.bq[0].e, m.bq[1].e};
+#pragma unroll
+          for (int f = 0; f < kTTRec; ++f) rec[f][lane] = r[f];
           quartic_real_roots(quart, roots);
+        }
       }
       const int nr = roots.n;
       int off = 0, total = 0;
@@ -162,13 +173,6 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
         total += __popcll(msk) << b;
       }
       if (nr > 0) {
-        const double r[kTTRec] = {s.A1.e0, s.A1.e1, s.A1.e2, s.A1.z0, s.A1.z1, s.A1.z2,
-                                  s.A2.e0, s.A2.e1, s.A2.e2, s.A2.z0, s.A2.z1, s.A2.z2,
-                                  s.P0, s.P1, s.P2, s.Q0, s.Q1,
-                                  s.tq[0], s.tq[1], s.tq[2], s.tq[3], s.itq[0], s.itq[1], s.itq[2], s.itq[3],
-                                  s.lam, s.mx, s.my, m.bq[0].e, m.bq[1].e};
-#pragma unroll
-        for (int f = 0; f < kTTRec; ++f) rec[f][lane] = r[f];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (j < nr) {
