@@ -187,3 +187,44 @@ def test_target_mode_matches_fixed_runs(mem, alloc):
         assert np.array_equal(P[sel], Pf[sel]) and np.array_equal(E[sel], Ef[sel])
         checked += int(sel.sum())
     assert checked >= 100
+
+
+def test_target_mode_mixed_groups_match_fixed_runs(mem):
+    """a mixed batch with two launch groups (dilepton in FP32, semileptonic
+    in FP64, Drell-Yan joining the first) in target mode with Neyman
+    allocation: every event retired after n iterations equals the same
+    batch run for n fixed iterations"""
+    dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    tt = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    sl = mem.Process(mem.MEM_TT_SEMILEPTON, precision=mem.MEM_FP64)
+    n_dy, n_tt, n_sl = 40, 48, 24
+    obs = np.zeros((n_dy + n_tt + n_sl, 5, 4))
+    obs[:n_dy, :2] = events.drell_yan(n_dy, 107)["obs"]
+    obs[n_dy:n_dy + n_tt, :4] = events.ttbar_dilepton(n_tt, 108)["obs"]
+    ds = events.ttbar_semileptonic(n_sl, 109)["obs"]
+    obs[n_dy + n_tt:, :5] = ds[:, :5]
+    charge = np.ones(len(obs), dtype=np.int32)
+    charge[n_dy + n_tt:] = ds[:, 5, 0].astype(np.int32)
+    comps = torch.as_tensor(np.ascontiguousarray(obs.transpose(2, 1, 0))).cuda()
+    ch = torch.as_tensor(charge).cuda()
+    procs = [dy] * n_dy + [tt] * n_tt + [sl] * n_sl
+    n_pts = [4096] * n_dy + [8192] * n_tt + [12 * 1024] * n_sl
+    n_it = torch.zeros(len(obs), dtype=torch.int32, device="cuda")
+    say("mixed batch, target 3 %, Neyman, two launch groups")
+    P, E, S = mem.integrate_events(comps, procs, n_pts, 0, seed=80, target_rel_err=0.03, max_iter=12,
+                                   allocation=1, n_iter_out=n_it, charge=ch)
+    torch.cuda.synchronize()
+    P, E, S, n = P.cpu().numpy(), E.cpu().numpy(), S.cpu().numpy(), n_it.cpu().numpy()
+    assert np.all((S == 0) | (S == mem.MEM_EV_NOT_CONVERGED))
+    counts = np.unique(n, return_counts=True)
+    say(f"  iterations used: {dict(zip(counts[0].tolist(), counts[1].tolist()))}")
+    checked = 0
+    for it in counts[0]:
+        if it < 2:
+            continue
+        Pf, Ef, Sf = run(mem, comps, procs, n_pts, int(it), 1, seed=80, charge=ch)
+        sel = n == it
+        assert np.array_equal(P[sel], Pf[sel]) and np.array_equal(E[sel], Ef[sel]), it
+        checked += int(sel.sum())
+    say(f"  {checked} events equal to their fixed runs")
+    assert checked == len(obs)
