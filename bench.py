@@ -45,7 +45,7 @@ FLOP_PER_EVAL = 2.0 * 1254.9 + 742.0
 # kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
 # FETCH 97 030 KiB x 2.000 + WRITE 266 093 KiB x 1.000.  Valid for this
 # workload and the kernel build the counters were taken on; None otherwise.
-TRAFFIC_BYTES_PER_LAUNCH = (98116 * 2.000 + 266100 * 1.000) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (97400 * 2.000 + 266094 * 1.000) * 1024
 TRAFFIC_WORKLOAD = (4096, 65536)
 
 
