@@ -22,6 +22,8 @@ KIND_TT = 2
 KIND_GENZ = 3
 KIND_TT_SL = 4
 KIND_TTH = 5
+KIND_TTH_LL = 6
+KIND_TTBB_LL = 7
 NBINS = 64
 
 
@@ -173,6 +175,15 @@ def _declare(L):
         "or_tth_perm": (None, [I, P, P, P, P, P]),
         "or_tth_map": (D, [P, P, I, P, P]),
         "or_tth_integrand": (D, [P, P, I, I, P, P]),
+        "or_gg_ttbb_prod": (D, [D, P, P, P, P, P, P]),
+        "or_gg_ttbb_ward": (D, [D, P, P, P, P, P, P, I]),
+        "or_gg_ttbb_prod_explicit": (D, [D, P, P, P, P, P, P]),
+        "or_ttbb_me2_gg": (D, [P, P, P, P, P, P]),
+        "or_colour_matrix_ttbb": (D, [I, I]),
+        "or_colour_fabc": (D, [I, I, I]),
+        "or_f2_perm": (None, [I, I, P]),
+        "or_tthll_integrand": (D, [P, P, I, P, P]),
+        "or_ttbbll_integrand": (D, [P, P, I, P, P]),
         "or_flow_forward": (D, [P, P, P, P]),
         "or_flow_inverse": (D, [P, P, P, P]),
         "or_flow_context": (None, [P, I, P]),
@@ -430,6 +441,60 @@ def gg_tth_ward(mt, k1, k2, pt, ptb, ph):
 def tth_soft_check(mt, mom, delta):
     m = _f64(mom).reshape(-1)
     return lib().or_tth_soft_check(mt, _ptr(m), delta)
+
+
+# ------------------------------------------------------ ttbar b bbar ----
+def gg_ttbb_prod(mt, k1, k2, p3, p4, p5, p6):
+    a = [_f64(v) for v in (k1, k2, p3, p4, p5, p6)]
+    return lib().or_gg_ttbb_prod(mt, *[_ptr(v) for v in a])
+
+
+def gg_ttbb_prod_explicit(mt, k1, k2, p3, p4, p5, p6):
+    a = [_f64(v) for v in (k1, k2, p3, p4, p5, p6)]
+    return lib().or_gg_ttbb_prod_explicit(mt, *[_ptr(v) for v in a])
+
+
+def gg_ttbb_ward(mt, k1, k2, p3, p4, p5, p6, g):
+    a = [_f64(v) for v in (k1, k2, p3, p4, p5, p6)]
+    return lib().or_gg_ttbb_ward(mt, *[_ptr(v) for v in a], g)
+
+
+def ttbb_me2_gg(p, k1, k2, mom, p5, p6):
+    a = [_f64(v) for v in (k1, k2)]
+    m = _f64(mom).reshape(-1)
+    b = [_f64(v) for v in (p5, p6)]
+    return lib().or_ttbb_me2_gg(ctypes.byref(p), _ptr(a[0]), _ptr(a[1]), _ptr(m), _ptr(b[0]), _ptr(b[1]))
+
+
+def colour_matrix_ttbb():
+    L = lib()
+    return np.array([[L.or_colour_matrix_ttbb(d, e) for e in range(38)] for d in range(38)])
+
+
+def colour_fabc():
+    L = lib()
+    return np.array([[[L.or_colour_fabc(a, b, c) for c in range(8)] for b in range(8)] for a in range(8)])
+
+
+def f2_perm(kind, perm):
+    """event rows of (b, bbar, pair jet 1, pair jet 2) for an assignment"""
+    rows = np.zeros(4, dtype=np.int32)
+    lib().or_f2_perm(kind, perm, _ptr(rows))
+    return tuple(int(r) for r in rows)
+
+
+def tthll_integrand(p, ev, perm, x):
+    ev, x = _f64(ev), _f64(x)
+    ns = ctypes.c_int(0)
+    v = lib().or_tthll_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
+    return v, ns.value
+
+
+def ttbbll_integrand(p, ev, perm, x):
+    ev, x = _f64(ev), _f64(x)
+    ns = ctypes.c_int(0)
+    v = lib().or_ttbbll_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
+    return v, ns.value
 
 
 def tth_perm(perm):

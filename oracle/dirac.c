@@ -652,3 +652,562 @@ double or_tth_me2_gg(const or_params* p, const double* k1, const double* k2, con
   double q2h = 2.0 * mdot(hb, hbb);
   return sum * decay_couplings(p, mom, pt, ptb) / 256.0 * yt2 * 6.0 * yb2 * q2h * bw2(q2h, p->m_h, p->w_h);
 }
+
+/* ------------------------------------------------------ ttbar b bbar --- */
+/* g(k1, a) g(k2, b) -> t(p3, i) tbar(p4, j) b(p5, k) bbar(p6, l), the
+ * irreducible background of Sec. 4's t tbar H analysis.  Tree level QCD
+ * only: 36 Feynman diagrams, written out one by one with the Feynman rules
+ * in one fixed convention (couplings g_s stripped, put back as g_s^8 in
+ * |M|^2):
+ *   quark-gluon vertex  i gamma^mu T^a,   quark propagator i (pslash+m)/(p^2-m^2),
+ *   gluon propagator    -i g_mu_nu delta^ab / q^2,
+ *   triple-gluon vertex (all momenta incoming, legs (k1,a,mu) (k2,b,nu) (k3,c,rho))
+ *     f^abc [g^mu_nu (k1-k2)^rho + g^nu_rho (k2-k3)^mu + g^rho_mu (k3-k1)^nu],
+ *   four-gluon vertex   -i [f^abe f^cde (g^mu_rho g^nu_sigma - g^mu_sigma g^nu_rho)
+ *                          + f^ace f^bde (g^mu_nu g^rho_sigma - g^mu_sigma g^nu_rho)
+ *                          + f^ade f^bce (g^mu_nu g^rho_sigma - g^mu_rho g^nu_sigma)].
+ * Each diagram is a Lorentz factor A_d times a colour tensor c_d(a,b,i,j,k,l)
+ * built from explicit Gell-Mann matrices; the colour sum is
+ *   sum_colours |sum_d c_d A_d|^2 = sum_dd' A_d CM_dd' conj(A_d'),
+ * CM_dd' = sum over all 5184 colour assignments of c_d conj(c_d').
+ * The four-gluon diagram is kept as its three colour terms: 38 terms. */
+
+#define NTB 38
+static cx TG[8][3][3];
+static double FABC[8][8][8];
+static cx CMAT[NTB][NTB];
+static cx TENS[NTB][5184];
+static int ttbb_ready = 0;
+
+/* colour words: symbols 'a', 'b' (the two gluons), 'c', 'e', 'g', 'h'
+ * (internal, summed); tw and bw are the ordered generator products along the
+ * top and the bottom line (from the quark end), f the structure constants,
+ * up to two triples separated by '|' */
+typedef struct { const char *tw, *bw, *f; } ttbb_colour;
+static const ttbb_colour TTBB_COL[NTB] = {
+  /* A: the b pair from a gluon off the top line, both gluons on the top line */
+  {"abc", "c", ""}, {"acb", "c", ""}, {"bac", "c", ""}, {"bca", "c", ""}, {"cab", "c", ""}, {"cba", "c", ""},
+  /* B: the top pair from a gluon off the b line, both gluons on the b line */
+  {"c", "abc", ""}, {"c", "acb", ""}, {"c", "bac", ""}, {"c", "bca", ""}, {"c", "cab", ""}, {"c", "cba", ""},
+  /* C: gluon x on the top line, y on the b line, a gluon exchanged; (x, y) =
+   * (a, b) then (b, a); t order (x, exchange) / (exchange, x), b order
+   * (y, exchange) / (exchange, y) */
+  {"ac", "bc", ""}, {"ac", "cb", ""}, {"ca", "bc", ""}, {"ca", "cb", ""},
+  {"bc", "ac", ""}, {"bc", "ca", ""}, {"cb", "ac", ""}, {"cb", "ca", ""},
+  /* D: g g -> g* (e), on the top line with the b pair gluon (c) / on the b line */
+  {"ec", "c", "abe"}, {"ce", "c", "abe"}, {"c", "ec", "abe"}, {"c", "ce", "abe"},
+  /* E1: gluon x on the exchanged gluon, y on the top line / on the b line */
+  {"be", "c", "ace"}, {"eb", "c", "ace"}, {"c", "be", "ace"}, {"c", "eb", "ace"},
+  {"ae", "c", "bce"}, {"ea", "c", "bce"}, {"c", "ae", "bce"}, {"c", "ea", "bce"},
+  /* E2: both gluons on the exchanged gluon: x then y from the b line, the
+   * g g -> g* gluon joining it, the four-gluon vertex (three terms) */
+  {"g", "c", "ace|beg"}, {"g", "c", "bce|aeg"}, {"g", "c", "abe|ecg"},
+  {"g", "c", "abh|cgh"}, {"g", "c", "ach|bgh"}, {"g", "c", "agh|bch"},
+};
+
+static void init_colour(void)
+{
+  memset(TG, 0, sizeof(TG));
+  /* T^a = lambda^a / 2 */
+  TG[0][0][1] = TG[0][1][0] = 0.5;
+  TG[1][0][1] = -0.5 * I; TG[1][1][0] = 0.5 * I;
+  TG[2][0][0] = 0.5; TG[2][1][1] = -0.5;
+  TG[3][0][2] = TG[3][2][0] = 0.5;
+  TG[4][0][2] = -0.5 * I; TG[4][2][0] = 0.5 * I;
+  TG[5][1][2] = TG[5][2][1] = 0.5;
+  TG[6][1][2] = -0.5 * I; TG[6][2][1] = 0.5 * I;
+  TG[7][0][0] = TG[7][1][1] = 0.5 / sqrt(3.0); TG[7][2][2] = -1.0 / sqrt(3.0);
+  /* f^abc = -2i Tr([T^a, T^b] T^c) */
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int c = 0; c < 8; ++c) {
+        cx t = 0;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+              t += (TG[a][i][j] * TG[b][j][k] - TG[b][i][j] * TG[a][j][k]) * TG[c][k][i];
+        FABC[a][b][c] = creal(-2.0 * I * t);
+      }
+}
+
+/* product of the generators named by word w (symbol values in v) */
+static void word_mat(const char* w, const int* v, cx out[3][3])
+{
+  cx m[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (const char* s = w; *s; ++s) {
+    const int g = v[(int)*s];
+    cx r[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        cx t = 0;
+        for (int k = 0; k < 3; ++k) t += m[i][k] * TG[g][k][j];
+        r[i][j] = t;
+      }
+    memcpy(m, r, sizeof(m));
+  }
+  memcpy(out, m, sizeof(m));
+}
+
+/* colour tensor of term d: t[a][b][i][j][k][l] (5184 entries) */
+static void colour_tensor(int d, cx* t)
+{
+  const ttbb_colour* c = &TTBB_COL[d];
+  static const char internal[4] = {'c', 'e', 'g', 'h'};
+  int used[4] = {0, 0, 0, 0}, n_used = 0;
+  for (int q = 0; q < 4; ++q) {
+    used[q] = strchr(c->tw, internal[q]) != NULL || strchr(c->bw, internal[q]) != NULL
+              || strchr(c->f, internal[q]) != NULL;
+    n_used += used[q];
+  }
+  memset(t, 0, sizeof(cx) * 5184);
+  int v[128];
+  int n_int = 1;
+  for (int q = 0; q < n_used; ++q) n_int *= 8;
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int it = 0; it < n_int; ++it) {
+        v['a'] = a; v['b'] = b;
+        int r = it;
+        for (int q = 0; q < 4; ++q)
+          if (used[q]) { v[(int)internal[q]] = r % 8; r /= 8; }
+        double f = 1.0;
+        for (const char* s = c->f; *s; s += (s[3] == '|') ? 4 : 3) {
+          f *= FABC[v[(int)s[0]]][v[(int)s[1]]][v[(int)s[2]]];
+          if (s[3] == 0) break;
+        }
+        if (f == 0.0) continue;
+        cx mt[3][3], mb[3][3];
+        word_mat(c->tw, v, mt);
+        word_mat(c->bw, v, mb);
+        cx* o = t + (a * 8 + b) * 81;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+              for (int l = 0; l < 3; ++l) o[((i * 3 + j) * 3 + k) * 3 + l] += f * mt[i][j] * mb[k][l];
+      }
+}
+
+static void init_ttbb(void)
+{
+  if (ttbb_ready) return;
+  init_gamma();
+  init_colour();
+  for (int d = 0; d < NTB; ++d) colour_tensor(d, TENS[d]);
+  for (int d = 0; d < NTB; ++d)
+    for (int e = 0; e < NTB; ++e) {
+      cx s = 0;
+      for (int q = 0; q < 5184; ++q) s += TENS[d][q] * conj(TENS[e][q]);
+      CMAT[d][e] = s;
+    }
+  ttbb_ready = 1;
+}
+
+double or_colour_matrix_ttbb(int d, int e)
+{
+  init_ttbb();
+  return creal(CMAT[d][e]);
+}
+double or_colour_fabc(int a, int b, int c)
+{
+  init_ttbb();
+  return FABC[a][b][c];
+}
+
+static cx cdot4(const cx* a, const cx* b) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
+static cx cdotr(const cx* a, const double* p) { return a[0] * p[0] - a[1] * p[1] - a[2] * p[2] - a[3] * p[3]; }
+
+/* triple-gluon vertex contracted with two legs (J1, k1), (J2, k2), momenta
+ * incoming; the third leg (incoming momentum k3 = -k1-k2) is left open:
+ * W^rho = (J1.J2)(k1-k2)^rho + J2^rho J1.(k2-k3) + J1^rho J2.(k3-k1) */
+static void vertex3(const cx* J1, const double* k1, const cx* J2, const double* k2, cx* W)
+{
+  double k3[4], d12[4], d23[4], d31[4];
+  for (int i = 0; i < 4; ++i) {
+    k3[i] = -k1[i] - k2[i];
+    d12[i] = k1[i] - k2[i]; d23[i] = k2[i] - k3[i]; d31[i] = k3[i] - k1[i];
+  }
+  cx j12 = cdot4(J1, J2), a = cdotr(J1, d23), b = cdotr(J2, d31);
+  for (int i = 0; i < 4; ++i) W[i] = j12 * d12[i] + a * J2[i] + b * J1[i];
+}
+/* the current of an internal gluon of momentum Q whose far end gives W:
+ * (-i / Q^2) W */
+static void gluon_current(const cx* W, const double* Q, cx* J)
+{
+  cx f = -I / mdot(Q, Q);
+  for (int i = 0; i < 4; ++i) J[i] = f * W[i];
+}
+
+/* fermion line between its quark row and antiquark column, insertions in
+ * order from the quark end: (i J1-slash) S(p - q1) (i J2-slash) ...
+ * (i Jn-slash); p the outgoing quark momentum, q_k the momentum entering
+ * at insertion k, S(p) = i (pslash + m) / (p^2 - m^2) */
+static mat4 line_mat(double m, const double* pout, int n, cx J[][4], double q[][4])
+{
+  mat4 M = mscale(slash(J[0]), I);
+  double p[4];
+  memcpy(p, pout, sizeof(p));
+  for (int k = 1; k < n; ++k) {
+    for (int i = 0; i < 4; ++i) p[i] -= q[k - 1][i];
+    mat4 S = mscale(madd(slash_r(p), ID4, m), I / (mdot(p, p) - m * m));
+    M = mmul(mmul(M, S), mscale(slash(J[k]), I));
+  }
+  return M;
+}
+
+/* the top line's matrix when the top pair attaches through one gluon whose
+ * other end is fn(J) for the gluon's current J (linear in J):
+ * sum_nu fn(e_nu) (-i/Pt^2) i gamma^nu = (1/Pt^2) sum_nu fn(e_nu) gamma^nu */
+typedef cx (*ttbb_rest_fn)(const cx* Jt, const void* ctx);
+
+typedef struct {
+  const double *k1, *k2, *p5, *p6, *Pt, *Pb;
+  const cx *e1, *e2, *Gb;
+  spin4 U, V;
+  int x, y;        /* gluon indices 0/1 for the E1 terms */
+  int order;       /* insertion order on the b line */
+} bctx;
+
+static const double* kk(const bctx* c, int g) { return g ? c->k2 : c->k1; }
+static const cx* ee(const bctx* c, int g) { return g ? c->e2 : c->e1; }
+
+static cx bline(const bctx* c, int n, cx J[][4], double q[][4])
+{
+  return rowcol(c->U, mvec(line_mat(0.0, c->p5, n, J, q), c->V));
+}
+
+/* B: b line with the two gluons and the top pair's gluon in one of 6 orders */
+static const int PERM3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+static cx rest_B(const cx* Jt, const void* vc)
+{
+  const bctx* c = vc;
+  cx J[3][4];
+  double q[3][4];
+  for (int s = 0; s < 3; ++s) {
+    int w = PERM3[c->order][s];
+    for (int i = 0; i < 4; ++i) {
+      J[s][i] = w == 0 ? c->e1[i] : w == 1 ? c->e2[i] : Jt[i];
+      q[s][i] = w == 0 ? c->k1[i] : w == 1 ? c->k2[i] : -c->Pt[i];
+    }
+  }
+  return bline(c, 3, J, q);
+}
+/* D on the b line: g g -> g* and the top pair's gluon */
+static cx rest_Db(const cx* Jt, const void* vc)
+{
+  const bctx* c = vc;
+  cx W[4], G12[4], J[2][4];
+  double K[4], q[2][4];
+  for (int i = 0; i < 4; ++i) K[i] = c->k1[i] + c->k2[i];
+  vertex3(c->e1, c->k1, c->e2, c->k2, W);
+  gluon_current(W, K, G12);
+  for (int i = 0; i < 4; ++i) {
+    J[c->order][i] = G12[i];     q[c->order][i] = K[i];
+    J[1 - c->order][i] = Jt[i];  q[1 - c->order][i] = -c->Pt[i];
+  }
+  return bline(c, 2, J, q);
+}
+/* E1 on the b line: gluon x joins the top pair's gluon, gluon y on the b line */
+static cx rest_E1b(const cx* Jt, const void* vc)
+{
+  const bctx* c = vc;
+  const double* kx = kk(c, c->x);
+  double mPt[4], Q[4], q[2][4];
+  for (int i = 0; i < 4; ++i) { mPt[i] = -c->Pt[i]; Q[i] = kx[i] - c->Pt[i]; }
+  cx W[4], G[4], J[2][4];
+  vertex3(ee(c, c->x), kx, Jt, mPt, W);
+  gluon_current(W, Q, G);
+  const int sy = c->order == 0 ? 0 : 1;      /* order 0: (y, e), 1: (e, y) */
+  for (int i = 0; i < 4; ++i) {
+    J[sy][i] = ee(c, c->y)[i];  q[sy][i] = kk(c, c->y)[i];
+    J[1 - sy][i] = G[i];        q[1 - sy][i] = Q[i];
+  }
+  return bline(c, 2, J, q);
+}
+static mat4 top_from_rest(ttbb_rest_fn fn, const bctx* c)
+{
+  mat4 M;
+  memset(&M, 0, sizeof(M));
+  for (int nu = 0; nu < 4; ++nu) {
+    cx e[4] = {0, 0, 0, 0};
+    e[nu] = 1.0;
+    M = madd(M, G[nu], fn(e, c));
+  }
+  return mscale(M, 1.0 / mdot(c->Pt, c->Pt));
+}
+
+/* the 38 top-line matrices M_d (amplitude_d = R M_d C) for gluon
+ * polarisations e1, e2 (complex, upper index) and b spinors U (row), V */
+static void ttbb_mats(double mt, const double* k1, const double* k2, const double* p3, const double* p4,
+                      const double* p5, const double* p6, const cx* e1, const cx* e2, spin4 U, spin4 V,
+                      mat4* M)
+{
+  double Pb[4], Pt[4], mPb[4];
+  for (int i = 0; i < 4; ++i) { Pb[i] = p5[i] + p6[i]; Pt[i] = p3[i] + p4[i]; mPb[i] = -Pb[i]; }
+  /* the b pair's gluon current (1/Pb^2) ubar gamma V... from the rules:
+   * (-i/Pb^2) U (i gamma^mu) V */
+  cx Xb[4], Gb[4];
+  for (int mu = 0; mu < 4; ++mu) Xb[mu] = I * rowcol(U, mvec(G[mu], V));
+  gluon_current(Xb, Pb, Gb);
+  const cx* E[2] = {e1, e2};
+  const double* K[2] = {k1, k2};
+  int d = 0;
+  /* A */
+  for (int o = 0; o < 6; ++o) {
+    cx J[3][4];
+    double q[3][4];
+    for (int s = 0; s < 3; ++s) {
+      int w = PERM3[o][s];
+      for (int i = 0; i < 4; ++i) {
+        J[s][i] = w < 2 ? E[w][i] : Gb[i];
+        q[s][i] = w < 2 ? K[w][i] : mPb[i];
+      }
+    }
+    M[d++] = line_mat(mt, p3, 3, J, q);
+  }
+  bctx c = {k1, k2, p5, p6, Pt, Pb, e1, e2, Gb, U, V, 0, 1, 0};
+  /* B */
+  for (int o = 0; o < 6; ++o) { c.order = o; M[d++] = top_from_rest(rest_B, &c); }
+  /* C */
+  for (int xy = 0; xy < 2; ++xy) {
+    const int x = xy, y = 1 - xy;
+    for (int to = 0; to < 2; ++to)
+      for (int bo = 0; bo < 2; ++bo) {
+        /* exchanged gluon: the b line with gluon y and an open index */
+        double Q[4], qb[2][4];
+        for (int i = 0; i < 4; ++i) Q[i] = Pb[i] - K[y][i];
+        cx X[4];
+        for (int mu = 0; mu < 4; ++mu) {
+          cx Jb[2][4];
+          cx eo[4] = {0, 0, 0, 0};
+          eo[mu] = 1.0;
+          const int sy = bo;     /* bo 0: (y, exchange), 1: (exchange, y) */
+          for (int i = 0; i < 4; ++i) {
+            Jb[sy][i] = E[y][i];  qb[sy][i] = K[y][i];
+            Jb[1 - sy][i] = eo[i]; qb[1 - sy][i] = Q[i];
+          }
+          /* open upper index mu: slash(e_mu) = g_mumu gamma^mu */
+          X[mu] = (mu == 0 ? 1.0 : -1.0) * rowcol(U, mvec(line_mat(0.0, p5, 2, Jb, qb), V));
+        }
+        cx Gx[4];
+        gluon_current(X, Q, Gx);
+        cx J[2][4];
+        double q[2][4];
+        const int sx = to;       /* to 0: (x, exchange), 1: (exchange, x) */
+        for (int i = 0; i < 4; ++i) {
+          J[sx][i] = E[x][i];   q[sx][i] = K[x][i];
+          J[1 - sx][i] = Gx[i]; q[1 - sx][i] = -Q[i];
+        }
+        M[d++] = line_mat(mt, p3, 2, J, q);
+      }
+  }
+  /* D */
+  {
+    cx W[4], G12[4];
+    double Kt[4];
+    for (int i = 0; i < 4; ++i) Kt[i] = k1[i] + k2[i];
+    vertex3(e1, k1, e2, k2, W);
+    gluon_current(W, Kt, G12);
+    for (int o = 0; o < 2; ++o) {
+      cx J[2][4];
+      double q[2][4];
+      for (int i = 0; i < 4; ++i) {
+        J[o][i] = G12[i];    q[o][i] = Kt[i];
+        J[1 - o][i] = Gb[i]; q[1 - o][i] = mPb[i];
+      }
+      M[d++] = line_mat(mt, p3, 2, J, q);
+    }
+    for (int o = 0; o < 2; ++o) { c.order = o; M[d++] = top_from_rest(rest_Db, &c); }
+  }
+  /* E1: x = gluon 1 (a) then x = gluon 2 (b) */
+  for (int x = 0; x < 2; ++x) {
+    const int y = 1 - x;
+    double Q[4];
+    for (int i = 0; i < 4; ++i) Q[i] = K[x][i] - Pb[i];
+    cx W[4], Gxb[4];
+    vertex3(E[x], K[x], Gb, mPb, W);
+    gluon_current(W, Q, Gxb);
+    for (int o = 0; o < 2; ++o) {    /* o 0: (y, e), 1: (e, y) */
+      cx J[2][4];
+      double q[2][4];
+      for (int i = 0; i < 4; ++i) {
+        J[o][i] = E[y][i];    q[o][i] = K[y][i];
+        J[1 - o][i] = Gxb[i]; q[1 - o][i] = Q[i];
+      }
+      M[d++] = line_mat(mt, p3, 2, J, q);
+    }
+    c.x = x; c.y = y;
+    for (int o = 0; o < 2; ++o) { c.order = o; M[d++] = top_from_rest(rest_E1b, &c); }
+  }
+  /* E2: single insertion on the top line, carrying Pt */
+  {
+    cx Jt[6][4];
+    for (int xy = 0; xy < 2; ++xy) {
+      const int x = xy, y = 1 - xy;
+      double Q[4], mQ[4];
+      for (int i = 0; i < 4; ++i) { Q[i] = K[x][i] - Pb[i]; mQ[i] = Q[i]; }
+      cx W[4], Gxb[4], W2[4];
+      vertex3(E[x], K[x], Gb, mPb, W);
+      gluon_current(W, Q, Gxb);
+      vertex3(E[y], K[y], Gxb, mQ, W2);
+      gluon_current(W2, Pt, Jt[xy]);
+    }
+    {
+      cx W[4], G12[4], W2[4];
+      double Kt[4];
+      for (int i = 0; i < 4; ++i) Kt[i] = k1[i] + k2[i];
+      vertex3(e1, k1, e2, k2, W);
+      gluon_current(W, Kt, G12);
+      vertex3(G12, Kt, Gb, mPb, W2);
+      gluon_current(W2, Pt, Jt[2]);
+    }
+    {
+      /* four-gluon vertex, legs (e1, mu) (e2, nu) (Gb, rho), open sigma */
+      cx e1Gb = cdot4(e1, Gb), e2Gb = cdot4(e2, Gb), e1e2 = cdot4(e1, e2);
+      cx X[3][4];
+      for (int i = 0; i < 4; ++i) {
+        X[0][i] = -I * (e1Gb * e2[i] - e1[i] * e2Gb);
+        X[1][i] = -I * (e1e2 * Gb[i] - e1[i] * e2Gb);
+        X[2][i] = -I * (e1e2 * Gb[i] - e1Gb * e2[i]);
+      }
+      for (int t = 0; t < 3; ++t) gluon_current(X[t], Pt, Jt[3 + t]);
+    }
+    for (int t = 0; t < 6; ++t) M[d++] = mscale(slash(Jt[t]), I);
+  }
+}
+
+/* colour-summed |sum_d c_d R M_d C|^2 */
+static double ttbb_colour_sum(spin4 R, spin4 C, const mat4* M)
+{
+  cx A[NTB];
+  for (int d = 0; d < NTB; ++d) A[d] = rowcol(R, mvec(M[d], C));
+  double s = 0.0;
+  for (int d = 0; d < NTB; ++d) {
+    cx t = 0;
+    for (int e = 0; e < NTB; ++e) t += CMAT[d][e] * conj(A[e]);
+    s += creal(A[d] * t);
+  }
+  return s;
+}
+
+/* the same sum with the colour-dressed amplitude formed for each of the
+ * 5184 colour assignments (no cancellation between linearly dependent
+ * colour terms: the form used where the sum is expected to vanish) */
+static double ttbb_colour_sum_explicit(spin4 R, spin4 C, const mat4* M)
+{
+  cx A[NTB];
+  for (int d = 0; d < NTB; ++d) A[d] = rowcol(R, mvec(M[d], C));
+  double s = 0.0;
+  for (int q = 0; q < 5184; ++q) {
+    cx t = 0;
+    for (int d = 0; d < NTB; ++d) t += TENS[d][q] * A[d];
+    s += creal(t * conj(t));
+  }
+  return s;
+}
+
+static void pol_vec(int which, cx e[4])
+{
+  double r[4];
+  lin_pol(which, r);
+  for (int i = 0; i < 4; ++i) e[i] = r[i];
+}
+
+/* spin- and colour-summed |M|^2 of g g -> t tbar b bbar for on-shell tops of
+ * mass mt (massless b), without couplings, averaged over the 256 initial
+ * colours and polarisations */
+static double gg_ttbb_prod(double mt, const double* k1, const double* k2, const double* p3, const double* p4,
+                           const double* p5, const double* p6, int explicit_colour)
+{
+  init_ttbb();
+  double sum = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int s5 = 0; s5 < 2; ++s5)
+        for (int s6 = 0; s6 < 2; ++s6) {
+          cx e1[4], e2[4];
+          pol_vec(a, e1);
+          pol_vec(b, e2);
+          mat4 M[NTB];
+          ttbb_mats(mt, k1, k2, p3, p4, p5, p6, e1, e2, dbar(spinor_u(p5, 0.0, s5)), spinor_v(p6, 0.0, s6), M);
+          for (int st = 0; st < 2; ++st)
+            for (int sb = 0; sb < 2; ++sb)
+              sum += explicit_colour
+                         ? ttbb_colour_sum_explicit(dbar(spinor_u(p3, mt, st)), spinor_v(p4, mt, sb), M)
+                         : ttbb_colour_sum(dbar(spinor_u(p3, mt, st)), spinor_v(p4, mt, sb), M);
+        }
+  return sum / 256.0;
+}
+double or_gg_ttbb_prod(double mt, const double* k1, const double* k2, const double* p3, const double* p4,
+                       const double* p5, const double* p6)
+{
+  return gg_ttbb_prod(mt, k1, k2, p3, p4, p5, p6, 0);
+}
+/* the same with the colour sum taken over explicit colour assignments */
+double or_gg_ttbb_prod_explicit(double mt, const double* k1, const double* k2, const double* p3,
+                                const double* p4, const double* p5, const double* p6)
+{
+  return gg_ttbb_prod(mt, k1, k2, p3, p4, p5, p6, 1);
+}
+
+/* Ward identity: with the polarisation of gluon g (0 or 1) replaced by its
+ * momentum and the other gluon physical, the colour-summed |M|^2 vanishes.
+ * Returns that sum relative to the one with physical polarisations. */
+double or_gg_ttbb_ward(double mt, const double* k1, const double* k2, const double* p3, const double* p4,
+                       const double* p5, const double* p6, int g)
+{
+  init_ttbb();
+  double bad = 0.0, good = 0.0;
+  for (int b = 0; b < 2; ++b)
+    for (int s5 = 0; s5 < 2; ++s5)
+      for (int s6 = 0; s6 < 2; ++s6) {
+        cx ek[4], ep[4], eo[4];
+        const double* kg = g ? k2 : k1;
+        for (int i = 0; i < 4; ++i) ek[i] = kg[i];
+        pol_vec(0, ep);
+        pol_vec(b, eo);
+        mat4 Mk[NTB], Mp[NTB];
+        spin4 U = dbar(spinor_u(p5, 0.0, s5)), V = spinor_v(p6, 0.0, s6);
+        if (g == 0) {
+          ttbb_mats(mt, k1, k2, p3, p4, p5, p6, ek, eo, U, V, Mk);
+          ttbb_mats(mt, k1, k2, p3, p4, p5, p6, ep, eo, U, V, Mp);
+        } else {
+          ttbb_mats(mt, k1, k2, p3, p4, p5, p6, eo, ek, U, V, Mk);
+          ttbb_mats(mt, k1, k2, p3, p4, p5, p6, eo, ep, U, V, Mp);
+        }
+        for (int st = 0; st < 2; ++st)
+          for (int sb = 0; sb < 2; ++sb) {
+            spin4 R = dbar(spinor_u(p3, mt, st)), C = spinor_v(p4, mt, sb);
+            bad += ttbb_colour_sum_explicit(R, C, Mk);
+            good += ttbb_colour_sum_explicit(R, C, Mp);
+          }
+      }
+  return good > 0.0 ? fabs(bad) / good : fabs(bad);
+}
+
+/* g g -> t tbar b bbar with decayed tops (as or_tt_me2_gg): spin- and
+ * colour-summed |M|^2 averaged over initial states, times the top and W
+ * Breit-Wigner factors and all couplings (g_s^8 for the production).
+ * mom: the six top decay momenta; p5, p6: the b and bbar of the gluon. */
+double or_ttbb_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom, const double* p5,
+                      const double* p6)
+{
+  init_ttbb();
+  spin4 R[8], C[8];
+  double pt[4], ptb[4];
+  decay_wavefunctions(p->m_t, mom, R, C, pt, ptb);
+  double sum = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int s5 = 0; s5 < 2; ++s5)
+        for (int s6 = 0; s6 < 2; ++s6) {
+          cx e1[4], e2[4];
+          pol_vec(a, e1);
+          pol_vec(b, e2);
+          mat4 M[NTB];
+          ttbb_mats(p->m_t, k1, k2, pt, ptb, p5, p6, e1, e2, dbar(spinor_u(p5, 0.0, s5)), spinor_v(p6, 0.0, s6), M);
+          for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) sum += ttbb_colour_sum(R[i], C[j], M);
+        }
+  double gs2 = 4.0 * M_PI * p->alpha_s;
+  return sum * decay_couplings(p, mom, pt, ptb) * gs2 * gs2 / 256.0;
+}

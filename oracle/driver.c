@@ -19,6 +19,8 @@ static double integrand(int kind, const or_params* p, const double* ev, int perm
   if (kind == OR_KIND_GENZ) return or_genz_integrand(x);
   if (kind == OR_KIND_TT_SL) return or_tt_semilep_integrand(p, ev, 0, perm, x, NULL);
   if (kind == OR_KIND_TTH) return or_tth_integrand(p, ev, 0, perm, x, NULL);
+  if (kind == OR_KIND_TTH_LL) return or_tthll_integrand(p, ev, perm, x, NULL);
+  if (kind == OR_KIND_TTBB_LL) return or_ttbbll_integrand(p, ev, perm, x, NULL);
   return or_tt_integrand(p, ev, perm, x, NULL);
 }
 

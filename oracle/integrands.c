@@ -507,7 +507,8 @@ int or_dims(int kind)
 }
 int or_nperm(int kind)
 {
-  return kind == OR_KIND_TT ? 2 : kind == OR_KIND_TT_SL ? 12 : kind == OR_KIND_TTH ? 24 : 1;
+  return kind == OR_KIND_TT ? 2 : kind == OR_KIND_TT_SL ? 12 : kind == OR_KIND_TTH ? 24
+       : kind == OR_KIND_TTH_LL ? 12 : kind == OR_KIND_TTBB_LL ? 24 : 1;
 }
 
 double or_genz_integrand(const double* x)
@@ -961,4 +962,149 @@ double or_tth_integrand(const or_params* p, const double* ev, int lep_charge, in
   if (nsol_out) *nsol_out = ns;
   double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 8.0);
   return sum * two_pi_pow * tf * jac / (2.0 * l[0]);
+}
+
+/* ------------------------------------- t tbar H against t tbar b bbar -- */
+/* Sec. 4's analysis in the dilepton channel: four b-jets (event rows 0-3),
+ * l+ (row 4), l- (row 5).  Jet assignments (the outer sum of Eq.
+ * integrand):
+ *   OR_KIND_TTH_LL, 12: perm = 2 hp + s; the Higgs pair is the hp-th of the
+ *     six ascending jet pairs, the other two jets (ascending) go to b and
+ *     bbar of the tops in that order for s = 0 and swapped for s = 1;
+ *   OR_KIND_TTBB_LL, 24: the perm-th permutation in lexicographic order of
+ *     the four jets onto (b, bbar, b', bbar'), b' bbar' the gluon's pair.
+ * rows[0..3] = event rows of (b, bbar, pair jet 1, pair jet 2). */
+void or_f2_perm(int kind, int perm, int* rows)
+{
+  if (kind == OR_KIND_TTH_LL) {
+    static const int pairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    int hp = perm >> 1, s = perm & 1;
+    rows[2] = pairs[hp][0];
+    rows[3] = pairs[hp][1];
+    int rest[2], n = 0;
+    for (int j = 0; j < 4; ++j) if (j != rows[2] && j != rows[3]) rest[n++] = j;
+    rows[0] = rest[s];
+    rows[1] = rest[1 - s];
+    return;
+  }
+  /* lexicographic permutation number perm of (0, 1, 2, 3) */
+  int avail[4] = {0, 1, 2, 3}, na = 4, r = perm;
+  static const int fact[4] = {6, 2, 1, 1};
+  for (int k = 0; k < 4; ++k) {
+    int q = r / fact[k];
+    r %= fact[k];
+    rows[k] = avail[q];
+    for (int j = q; j < na - 1; ++j) avail[j] = avail[j + 1];
+    --na;
+  }
+}
+
+/* Variables x in [0,1]^8 (the paper's eight: four jet energies, four
+ * propagator virtualities of Eq. dilepsolv):
+ *   x0, x1  r = E_meas / E of the b and bbar jets
+ *   x2..x5  q2 of t, tbar, W+, W- (tan maps over [0, S])
+ *   x6      r of pair jet 1
+ *   x7      t tbar H: q2 of the Higgs (tan map; Eq. mhsolve) giving the
+ *           energy of pair jet 2; t tbar b bbar: r of pair jet 2.
+ * All four jets carry the Gaussian TF of the b-jets.  The neutrinos'
+ * transverse momenta add up to minus that of the visible objects (the
+ * transverse momentum balance of Sec. 3; no recoil).  Only the gg initial
+ * state. */
+static double f2_integrand(int kind, const or_params* p, const double* ev, int perm, const double* x,
+                           int* nsol_out)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  int rows[4];
+  or_f2_perm(kind, perm, rows);
+  const double* lp = ev + 16;
+  const double* lm = ev + 20;
+  if (nsol_out) *nsol_out = 0;
+  double dir[4][3], em[4], sin_th[4];
+  for (int k = 0; k < 4; ++k) {
+    const double* m = ev + 4 * rows[k];
+    double pm = norm3(m);
+    em[k] = m[0];
+    for (int i = 0; i < 3; ++i) dir[k][i] = m[i + 1] / pm;
+    sin_th[k] = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+  }
+  const double rlo = p->r_lo, rhi = p->r_hi;
+  double E[4], jac = 1.0;
+  const int xr[3] = {0, 1, 6};
+  for (int k = 0; k < 3; ++k) {
+    double r = rlo + x[xr[k]] * (rhi - rlo);
+    E[k] = em[k] / r;
+    jac *= (rhi - rlo) * em[k] / (r * r);
+  }
+  double q2h = 0.0;
+  if (kind == OR_KIND_TTH_LL) {
+    jac *= or_bw_map(x[7], p->m_h, p->w_h, 0.0, S, &q2h);
+    double c12 = dir[2][0] * dir[3][0] + dir[2][1] * dir[3][1] + dir[2][2] * dir[3][2];
+    if (!(1.0 - c12 > 0.0)) return 0.0;
+    E[3] = q2h / (2.0 * E[2] * (1.0 - c12));
+    jac *= 1.0 / (2.0 * E[2] * (1.0 - c12));
+    double r3 = em[3] / E[3];
+    if (r3 < rlo || r3 > rhi) return 0.0;
+  } else {
+    double r = rlo + x[7] * (rhi - rlo);
+    E[3] = em[3] / r;
+    jac *= (rhi - rlo) * em[3] / (r * r);
+  }
+  double j4[4][4];
+  double jetf = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    j4[k][0] = E[k];
+    for (int i = 0; i < 3; ++i) j4[k][i + 1] = E[k] * dir[k][i];
+    /* E^2 sin(theta) T(E_meas | E) / (2E) */
+    jetf *= E[k] * E[k] * sin_th[k] * or_gauss_tf(em[k], E[k], p->tf_sigma) / (2.0 * E[k]);
+  }
+  double q2t, q2tb, q2wp, q2wm;
+  jac *= or_bw_map(x[2], p->m_t, p->w_t, 0.0, S, &q2t) * or_bw_map(x[3], p->m_t, p->w_t, 0.0, S, &q2tb)
+       * or_bw_map(x[4], p->m_w, p->w_w, 0.0, S, &q2wp) * or_bw_map(x[5], p->m_w, p->w_w, 0.0, S, &q2wm);
+  double metx = -(lp[1] + lm[1]), mety = -(lp[2] + lm[2]);
+  for (int k = 0; k < 4; ++k) { metx -= j4[k][1]; mety -= j4[k][2]; }
+  double nu[16], nub[16], detj[4];
+  int ns = or_solve_dilepton(j4[0], j4[1], lp, lm, metx, mety, q2wp, q2t, q2wm, q2tb, nu, nub, detj);
+  if (nsol_out) *nsol_out = ns;
+  double sum = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const double* v = nu + 4 * s;
+    const double* vb = nub + 4 * s;
+    double lab[8][4];
+    memcpy(lab[0], j4[0], 32); memcpy(lab[1], lp, 32); memcpy(lab[2], v, 32);
+    memcpy(lab[3], j4[1], 32); memcpy(lab[4], lm, 32); memcpy(lab[5], vb, 32);
+    memcpy(lab[6], j4[2], 32); memcpy(lab[7], j4[3], 32);
+    double P[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) for (int i = 0; i < 4; ++i) P[i] += lab[k][i];
+    double hard[32];
+    for (int k = 0; k < 8; ++k) boost_transverse(P, lab[k], hard + 4 * k);
+    double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+    double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
+    double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+    double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+    double g1, g2;
+    if (p->pdf) {
+      g1 = or_pdf_interp(p->pdf, 0, x1, p->m_t) / x1;
+      g2 = or_pdf_interp(p->pdf, 0, x2, p->m_t) / x2;
+    } else {
+      g1 = or_xf_g(x1) / x1;
+      g2 = or_xf_g(x2) / x2;
+    }
+    double me = kind == OR_KIND_TTH_LL ? or_tth_me2_gg(p, k1, k2, hard, hard + 24, hard + 28)
+                                       : or_ttbb_me2_gg(p, k1, k2, hard, hard + 24, hard + 28);
+    double shat = x1 * x2 * S;
+    sum += (2.0 / S) * (P[0] / Eh) * g1 * g2 * me / (2.0 * shat) / fabs(detj[s]) / (2.0 * v[0] * 2.0 * vb[0]);
+  }
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 8.0);
+  double lep = 1.0 / (2.0 * lp[0] * 2.0 * lm[0]);
+  return sum * two_pi_pow * lep * jetf * jac;
+}
+
+double or_tthll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out)
+{
+  return f2_integrand(OR_KIND_TTH_LL, p, ev, perm, x, nsol_out);
+}
+double or_ttbbll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out)
+{
+  return f2_integrand(OR_KIND_TTBB_LL, p, ev, perm, x, nsol_out);
 }

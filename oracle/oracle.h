@@ -211,7 +211,15 @@ double or_flow_nll_grad(const double* params, int n, const double* x, const doub
                         double* grad);
 
 /* -------------------------------------------------------------- driver -- */
-enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_KIND_TTH = 5 };
+enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_KIND_TTH = 5,
+       OR_KIND_TTH_LL = 6, OR_KIND_TTBB_LL = 7 };
+/* t tbar H (H -> b bbar) and t tbar b bbar, both tops decaying to b l nu
+ * (Sec. 4's analysis): events b-jets 0-3, l+, l- as 6 x {E,px,py,pz};
+ * assignments and variables in integrands.c (or_f2_perm: the event rows of
+ * b, bbar and the pair jets for an assignment). */
+void or_f2_perm(int kind, int perm, int* rows);
+double or_tthll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out);
+double or_ttbbll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out);
 typedef struct {
   double I, sigma;          /* combined estimate over iterations >= 2 */
   double chi2dof;
@@ -258,6 +266,24 @@ double or_gg_tth_prod(double mt, const double* k1, const double* k2, const doubl
 double or_gg_tth_ward(double mt, const double* k1, const double* k2, const double* pt, const double* ptb,
                       const double* ph);
 double or_tth_soft_check(double mt, const double* mom, double delta);
+/* g g -> t tbar b bbar (the t tbar H analysis' background, Sec. 4): 36
+ * tree-level QCD diagrams with explicit SU(3) colour sums.  _prod: on-shell
+ * tops of mass mt, massless b, spin and colour summed and averaged, no
+ * couplings; _ward: the Ward identity for gluon g (0/1), |M|^2 with that
+ * gluon's polarisation replaced by its momentum relative to the physical
+ * one; _me2_gg: decayed tops (mom as or_tt_me2_gg), couplings, top and W
+ * Breit-Wigner factors included.  or_colour_matrix_ttbb: the colour matrix
+ * of the 38 colour terms; or_colour_fabc: f^abc from the generators. */
+double or_gg_ttbb_prod(double mt, const double* k1, const double* k2, const double* p3, const double* p4,
+                       const double* p5, const double* p6);
+double or_gg_ttbb_prod_explicit(double mt, const double* k1, const double* k2, const double* p3,
+                                const double* p4, const double* p5, const double* p6);
+double or_gg_ttbb_ward(double mt, const double* k1, const double* k2, const double* p3, const double* p4,
+                       const double* p5, const double* p6, int g);
+double or_ttbb_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom, const double* p5,
+                      const double* p6);
+double or_colour_matrix_ttbb(int d, int e);
+double or_colour_fabc(int a, int b, int c);
 double or_tth_me2_gg(const or_params* p, const double* k1, const double* k2, const double* mom, const double* hb,
                      const double* hbb);
 

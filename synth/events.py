@@ -15,6 +15,7 @@ Layouts: `obs` is float64 [n_events, n_obj, 4] with rows (E, px, py, pz).
   ttbar semileptonic: j0..j3 (random order), lepton, (charge, 0, 0, 0)
   ttbar H:         b0..b3 (b-tagged, random order), l0, l1 (random order),
                    lepton, (charge, 0, 0, 0)
+  ttbar H and ttbar b bbar, dilepton: b0..b3 (random order), l+, l-
 """
 import numpy as np
 
@@ -297,6 +298,83 @@ def ttbar_higgs(n_events, seed, lj=(0.10, 0.25, 0.2), sigma_k=20.0):
     truth = {"b_lep": b_lep, "b_had": b_had, "hb": hb, "hbb": hbb, "q": q1, "qbar": q2, "lep": lep, "nu": nu,
              "k": k, "charge": charge, "bslot": np.argsort(border, axis=1), "lslot": np.argsort(lorder, axis=1)}
     return {"obs": obs, "truth": truth}
+
+
+def _dilepton_tops(rng, n, t, tb, mt1, mt2):
+    """b l+ nu from the top and bbar l- nubar from the antitop, isotropic
+    decays with Breit-Wigner W masses, in the frame of t and tb"""
+    mw1 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    mw2 = _bw(rng, n, M_W, W_W, 65.0, 95.0)
+    b, wp = _two_body(mt1, np.zeros(n), mw1, _iso(rng, n))
+    bb, wm = _two_body(mt2, np.zeros(n), mw2, _iso(rng, n))
+    lp, nu = _two_body(mw1, np.zeros(n), np.zeros(n), _iso(rng, n))
+    lm, nub = _two_body(mw2, np.zeros(n), np.zeros(n), _iso(rng, n))
+    lp, nu = _boost(lp, wp), _boost(nu, wp)
+    lm, nub = _boost(lm, wm), _boost(nub, wm)
+    b, lp, nu = (_boost(v, t) for v in (b, lp, nu))
+    bb, lm, nub = (_boost(v, tb) for v in (bb, lm, nub))
+    return b, lp, nu, bb, lm, nub
+
+
+def _four_b_dilepton(rng, n, M, y, parts, rel_sigma):
+    """boost the hard system (mass M, rapidity y, no transverse recoil) to
+    the lab, smear the four b energies, store the b-jets in random order"""
+    P = np.stack([M * np.cosh(y), np.zeros(n), np.zeros(n), M * np.sinh(y)], axis=1)
+    b, lp, nu, bb, lm, nub, p1, p2 = (_boost(v, P) for v in parts)
+    quarks = (b, bb, p1, p2)
+    jets = np.stack([_massless(_smear(rng, v[:, 0], rel_sigma), v) for v in quarks], axis=1)
+    order = np.argsort(rng.random((n, 4)), axis=1)
+    obs = np.concatenate([np.take_along_axis(jets, order[:, :, None], axis=1), lp[:, None, :], lm[:, None, :]], axis=1)
+    truth = {"b": b, "bb": bb, "p1": p1, "p2": p2, "lp": lp, "lm": lm, "nu": nu, "nub": nub,
+             "slot": np.argsort(order, axis=1)}
+    return {"obs": obs, "truth": truth}
+
+
+def ttbar_higgs_dilepton(n_events, seed, rel_sigma=0.15):
+    """gg -> t tbar H, H -> b bbar (125 GeV, narrow), both tops to b l nu
+    (Sec. 4's signal).  Masses and decays as ttbar_higgs, no transverse
+    recoil (the hard system's transverse momentum is zero, as the
+    integrand's transverse momentum balance assumes); the four b-jet
+    energies are smeared by the Gaussian rel_sigma, the leptons are exact.
+    truth slot[:, q] is the jet row of quark q in (b, bbar, b of H, bbar of H)."""
+    rng = _rng(seed)
+    n = n_events
+    mt1 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mt2 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mh = np.full(n, M_H)
+    M = mt1 + mt2 + mh + rng.gamma(2.0, 100.0, n)
+    mtt = mt1 + mt2 + rng.random(n) * (M - mh - mt1 - mt2)
+    y = np.clip(rng.standard_normal(n), -1.0, 1.0) * np.minimum(2.0, 0.9 * np.log(SQRT_S / M))
+    tt, h = _two_body(M, mtt, mh, _iso(rng, n))
+    t, tb = _two_body(mtt, mt1, mt2, _iso(rng, n))
+    t, tb = _boost(t, tt), _boost(tb, tt)
+    hb, hbb = _two_body(mh, np.zeros(n), np.zeros(n), _iso(rng, n))
+    hb, hbb = _boost(hb, h), _boost(hbb, h)
+    parts = _dilepton_tops(rng, n, t, tb, mt1, mt2) + (hb, hbb)
+    return _four_b_dilepton(rng, n, M, y, parts, rel_sigma)
+
+
+def ttbar_bbbar_dilepton(n_events, seed, rel_sigma=0.15):
+    """gg -> t tbar b bbar with both tops to b l nu (Sec. 4's background):
+    the extra b bbar pair has a mass 20 GeV + Gamma(1.5, 60 GeV), the t tbar
+    b bbar mass rises from threshold with a Gamma(2, 120 GeV) excess and the
+    t tbar mass is uniform in between; decays isotropic, no recoil, jets as
+    ttbar_higgs_dilepton (slot order b, bbar, b', bbar')."""
+    rng = _rng(seed)
+    n = n_events
+    mt1 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mt2 = _bw(rng, n, M_T, W_T, 160.0, 185.0)
+    mbb = 20.0 + rng.gamma(1.5, 60.0, n)
+    M = mt1 + mt2 + mbb + rng.gamma(2.0, 120.0, n)
+    mtt = mt1 + mt2 + rng.random(n) * (M - mbb - mt1 - mt2)
+    y = np.clip(rng.standard_normal(n), -1.0, 1.0) * np.minimum(2.0, 0.9 * np.log(SQRT_S / M))
+    tt, g = _two_body(M, mtt, mbb, _iso(rng, n))
+    t, tb = _two_body(mtt, mt1, mt2, _iso(rng, n))
+    t, tb = _boost(t, tt), _boost(tb, tt)
+    p1, p2 = _two_body(mbb, np.zeros(n), np.zeros(n), _iso(rng, n))
+    p1, p2 = _boost(p1, g), _boost(p2, g)
+    parts = _dilepton_tops(rng, n, t, tb, mt1, mt2) + (p1, p2)
+    return _four_b_dilepton(rng, n, M, y, parts, rel_sigma)
 
 
 def budgets(n_events, seed, lo=16384, hi=262144):
