@@ -46,12 +46,26 @@ typedef enum {
  *                                     mem_events.charge; +1 when null)
  *  MEM_TTH_SEMILEPTON    gg -> t tbar H, H -> b bbar, one W -> l nu, one
  *                        W -> q qbar': b-jet x 4, light jet x 2, lepton
- *                                   (charge as above)                        */
+ *                                   (charge as above)
+ *  MEM_TTH_DILEPTON      gg -> t tbar H, H -> b bbar, both tops -> b l nu
+ *                        (Sec. 4's signal, Eqs. integrand, dilepsolv and
+ *                        mhsolve; 8 dimensions, 12 assignments)
+ *                                   : b-jet x 4, l+, l-
+ *  MEM_TTBB_DILEPTON     gg -> t tbar b bbar, both tops -> b l nu (Sec. 4's
+ *                        background; 36 tree-level QCD diagrams; 8
+ *                        dimensions, 24 assignments): b-jet x 4, l+, l-
+ *  The two dilepton four-b kinds use the b-jet transfer function for all
+ *  four jets, take the neutrinos' summed transverse momentum as minus that
+ *  of the visible objects (no recoil; sigma_k unused), and integrate in
+ *  batches that hold no other kind (MEM_EUNSUPPORTED otherwise); flow
+ *  proposals, training capture and parton-level weights do not cover them. */
 typedef enum {
   MEM_DY_QQ_GAMMA_MUMU = 1,
   MEM_TT_DILEPTON = 2,
   MEM_TT_SEMILEPTON = 3,
-  MEM_TTH_SEMILEPTON = 4
+  MEM_TTH_SEMILEPTON = 4,
+  MEM_TTH_DILEPTON = 5,
+  MEM_TTBB_DILEPTON = 6
 } mem_kind;
 
 typedef enum { MEM_FP64 = 0, MEM_FP32 = 1 } mem_precision;
@@ -248,6 +262,14 @@ mem_status mem_set_pdf_grid(mem_process p, const float* xf, int32_t nx, int32_t 
  * sea for ubar and dbar, the gluon; s, c, b and their antiquarks zero;
  * zero at x >= 1).  MEM_EINVAL as for mem_set_pdf_grid. */
 mem_status mem_toy_pdf_table(float* xf, int32_t nx, int32_t nq, const double* bounds);
+
+/* Event discriminant of Sec. 4, D = log10(p_sig / p_bkg), per event: for
+ * the t tbar H and t tbar b bbar densities of mem_integrate_events on the
+ * same events.  p_sig, p_bkg, d_out: device arrays of n doubles (caller
+ * owned; d_out may alias neither input).  p_sig > 0 with p_bkg == 0 gives
+ * +inf, the reverse -inf, both zero NaN.  Asynchronous on stream.
+ * MEM_EINVAL for n < 0 or null arrays with n > 0. */
+mem_status mem_discriminant(const double* p_sig, const double* p_bkg, int64_t n, double* d_out, void* stream);
 
 /* Integration dimension and number of jet-parton assignments of a process. */
 mem_status mem_process_shape(mem_process p, int32_t* dims, int32_t* n_perm);

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libmem.so")
 
 MEM_OK, MEM_EINVAL, MEM_ENOMEM, MEM_EDEVICE, MEM_EUNSUPPORTED = range(5)
 MEM_DY_QQ_GAMMA_MUMU, MEM_TT_DILEPTON, MEM_TT_SEMILEPTON, MEM_TTH_SEMILEPTON = 1, 2, 3, 4
+MEM_TTH_DILEPTON, MEM_TTBB_DILEPTON = 5, 6
 MEM_FP64, MEM_FP32 = 0, 1
 MEM_TF_DELTA, MEM_TF_UNIFORM, MEM_TF_GAUSS, MEM_TF_DGAUSS = range(4)
 MEM_OBJ_MUON, MEM_OBJ_LEPTON, MEM_OBJ_BJET, MEM_OBJ_LJET, MEM_OBJ_NEUTRINO = range(5)
@@ -29,7 +30,7 @@ EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_proc
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
            "mem_process_chunk_points", "mem_parton_weights", "mem_set_pdf_grid", "mem_toy_pdf_table",
-           "mem_status_string", "mem_last_error")
+           "mem_discriminant", "mem_status_string", "mem_last_error")
 
 
 class ProcessDesc(ctypes.Structure):
@@ -84,6 +85,7 @@ def lib():
             "mem_integrate_events": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
             "mem_uniforms": (I32, [U64, U32, U32, U32, I32, I64, P, P]),
             "mem_eval_points": (I32, [P, P, I32, I32, P, I64, P, P, P]),
+            "mem_discriminant": (I32, [P, P, I64, P, P]),
             "mem_parton_weights": (I32, [P, P, P, P]),
             "mem_vegas_refine": (I32, [P, P, I32, I32, D, P]),
             "mem_vegas_capture": (I32, [P, P, P, P, I32, P, I64, U64, U32, I32, P, P, P]),
@@ -267,6 +269,19 @@ def eval_points(process, comps, event, perm, x, f, nsol=None, stream=None, charg
                                  ctypes.c_void_p(nsol.data_ptr()) if nsol is not None else None,
                                  _stream_ptr(stream)), "mem_eval_points")
     return f
+
+
+def discriminant(p_sig, p_bkg, out=None, stream=None):
+    """mem_discriminant: D = log10(p_sig / p_bkg) per event; float64 device
+    tensors of one length; returns `out` (allocated when None)."""
+    import torch
+    if p_sig.shape != p_bkg.shape or p_sig.dtype != torch.float64 or p_bkg.dtype != torch.float64:
+        raise ValueError("p_sig and p_bkg: float64 tensors of one shape")
+    d = torch.empty_like(p_sig) if out is None else out
+    _check(lib().mem_discriminant(ctypes.c_void_p(p_sig.data_ptr()), ctypes.c_void_p(p_bkg.data_ptr()),
+                                  p_sig.numel(), ctypes.c_void_p(d.data_ptr()), _stream_ptr(stream)),
+           "mem_discriminant")
+    return d
 
 
 def toy_pdf_table(nx, nq, bounds):

@@ -22,6 +22,7 @@
 #include "sl.hpp"
 #include "tt.hpp"
 #include "tth.hpp"
+#include "f2.hpp"
 
 namespace memk {
 
@@ -217,16 +218,20 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
 // Persistent work-queue kernel: every workgroup loops until the shared head
 // passes n_chunks (each iteration of the loop reads the head once, so every
 // workgroup reaches the exit).  KINDS is the set of process kinds compiled
-// in (bit 1 DY, 2 dilepton, 4 semileptonic, 8 t tbar H): a launch carries only the
+// in (bit 1 DY, 2 dilepton, 4 semileptonic, 8 t tbar H, 16 t tbar H
+// dilepton, 32 t tbar b bbar dilepton): a launch carries only the
 // integrands its chunks need, and with them only their register demand.
-enum { kMaskDY = 1, kMaskTT = 2, kMaskSL = 4, kMaskTTH = 8 };
+enum { kMaskDY = 1, kMaskTT = 2, kMaskSL = 4, kMaskTTH = 8, kMaskTHL = 16, kMaskTBB = 32 };
 // Instances that carry the t tbar H integrand stay at two waves per SIMD:
 // compiled at one, the FP32 instance returned wrong iteration sums (zero or
 // infinite for every integral) although the same integrand evaluated point
 // by point was right, and host builds of the integrand run clean under
 // MemorySanitizer and UBSan.  The cause is not known; at two waves the
 // instance matches the oracle.
-template <int KINDS> constexpr int queue_waves() { return (KINDS & kMaskTTH) ? 2 : MEM_TT_WAVES; }
+template <int KINDS> constexpr int queue_waves()
+{
+  return (KINDS & (kMaskTTH | kMaskTHL | kMaskTBB)) ? 2 : MEM_TT_WAVES;
+}
 template <class T, int KINDS>
 __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kernel(
     const ProcParams* __restrict__ procs, EventsView ev, const Chunk* __restrict__ chunks, int64_t n_chunks,
@@ -291,6 +296,16 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
       tth_load(ev, ev.charge, ch.event, ch.perm, e);
       chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[9]) { return tth_integrand<T>(pp, e, x, nullptr); });
+    } else if ((KINDS & kMaskTHL) && pp.kind == kTHL) {
+      F2Event e;
+      f2_load(ev, true, ch.event, ch.perm, e);
+      chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+                      [&](const double (&x)[8]) { return f2_integrand<T, true>(pp, e, x, nullptr); });
+    } else if ((KINDS & kMaskTBB) && pp.kind == kTBB) {
+      F2Event e;
+      f2_load(ev, false, ch.event, ch.perm, e);
+      chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+                      [&](const double (&x)[8]) { return f2_integrand<T, false>(pp, e, x, nullptr); });
     }
     block_reduce2<0>(s1, s2, red);
     __syncthreads();

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
@@ -113,7 +114,8 @@ static void derive(mem_process_s* p)
     pp.dy_const = std::pow(two_pi, -2.0) * (2.0 / pp.S) * e2 * e2 / 3.0 * 0.5;
   } else {
     pp.dims = d.kind == MEM_TT_SEMILEPTON ? 7 : d.kind == MEM_TTH_SEMILEPTON ? 9 : 8;
-    pp.n_perm = d.kind == MEM_TT_SEMILEPTON ? 12 : d.kind == MEM_TTH_SEMILEPTON ? 24 : 2;
+    pp.n_perm = d.kind == MEM_TT_SEMILEPTON ? 12 : d.kind == MEM_TTH_SEMILEPTON ? 24
+              : d.kind == MEM_TTH_DILEPTON ? 12 : d.kind == MEM_TTBB_DILEPTON ? 24 : 2;
     double mtg = d.m_top * d.w_top, mwg = d.m_w * d.w_w;
     pp.th0_t = std::atan((0.0 - d.m_top * d.m_top) / mtg);
     pp.th1_t = std::atan((pp.S - d.m_top * d.m_top) / mtg);
@@ -143,6 +145,23 @@ static void derive(mem_process_s* p)
       pp.tth_const = pp.sl_const * std::pow(two_pi, -6.0) * (pp.th1_h - pp.th0_h) / mhg
                    * (d.m_top * d.m_top / v2) * 6.0 * (mb * mb / v2);
     }
+    if (d.kind == MEM_TTH_DILEPTON || d.kind == MEM_TTBB_DILEPTON) {
+      // eight final-state particles: (2 pi)^(4 - 24); all four top and W
+      // propagators aligned
+      const double base = std::pow(two_pi, -20.0) * (2.0 / pp.S) * 0.5 * 0.25 * std::pow(gw2 / 2.0, 4) * kbw / 256.0;
+      if (d.kind == MEM_TTBB_DILEPTON) {
+        pp.f2_const = base * gs2 * gs2 * gs2 * gs2;
+      } else {
+        const double mhg = d.m_h * d.w_h;
+        pp.m_h = d.m_h; pp.w_h = d.w_h;
+        pp.th0_h = std::atan((0.0 - d.m_h * d.m_h) / mhg);
+        pp.th1_h = std::atan((pp.S - d.m_h * d.m_h) / mhg);
+        const double v2 = 1.0 / (std::sqrt(2.0) * d.g_fermi);
+        const double mb = d.m_b > 0.0 ? d.m_b : 4.18;
+        pp.f2_const = base * gs2 * gs2 * (pp.th1_h - pp.th0_h) / mhg * (d.m_top * d.m_top / v2) * 6.0
+                    * (mb * mb / v2);
+      }
+    }
   }
   apply_pdf(p);
 }
@@ -151,9 +170,10 @@ extern "C" mem_status mem_create_process(const mem_process_desc* d, mem_process*
 {
   if (!d || !out) return fail(MEM_EINVAL, "null argument");
   if (d->kind != MEM_DY_QQ_GAMMA_MUMU && d->kind != MEM_TT_DILEPTON && d->kind != MEM_TT_SEMILEPTON &&
-      d->kind != MEM_TTH_SEMILEPTON)
+      d->kind != MEM_TTH_SEMILEPTON && d->kind != MEM_TTH_DILEPTON && d->kind != MEM_TTBB_DILEPTON)
     return fail(MEM_EINVAL, "unknown process kind");
-  if (d->kind == MEM_TTH_SEMILEPTON && !(d->m_h > 0.0 && d->w_h > 0.0 && d->m_b >= 0.0))
+  if ((d->kind == MEM_TTH_SEMILEPTON || d->kind == MEM_TTH_DILEPTON) &&
+      !(d->m_h > 0.0 && d->w_h > 0.0 && d->m_b >= 0.0))
     return fail(MEM_EINVAL, "Higgs mass and width must be positive");
   if (!(d->sqrt_s > 0.0)) return fail(MEM_EINVAL, "sqrt_s must be positive");
   if (d->precision != MEM_FP64 && d->precision != MEM_FP32) return fail(MEM_EINVAL, "bad precision");
@@ -208,9 +228,84 @@ extern "C" mem_status mem_set_transfer_functions(mem_process p, const mem_tf_des
 
 extern "C" void mem_destroy_process(mem_process p) { delete p; }
 
-// A process with a PDF grid runs on the device that holds the grid.
+// Colour matrix of the twelve colour tensors of g g -> t tbar b bbar
+// (ttbb_me.hpp), [P|Q]x = P_il Q_kj and [P|Q]= = P_ij Q_kl over (P, Q) =
+// (ab,1) (ba,1) (1,ab) (1,ba) (a,b) (b,a), from explicit generators
+// T^a = lambda^a / 2: G_mn = sum over a, b, i, j, k, l of t_m conj(t_n).
+static void ttbb_colour_matrix(double* G)
+{
+  typedef std::complex<double> C;
+  C T[8][3][3] = {};
+  const C I(0.0, 1.0);
+  T[0][0][1] = T[0][1][0] = 0.5;
+  T[1][0][1] = -0.5 * I; T[1][1][0] = 0.5 * I;
+  T[2][0][0] = 0.5; T[2][1][1] = -0.5;
+  T[3][0][2] = T[3][2][0] = 0.5;
+  T[4][0][2] = -0.5 * I; T[4][2][0] = 0.5 * I;
+  T[5][1][2] = T[5][2][1] = 0.5;
+  T[6][1][2] = -0.5 * I; T[6][2][1] = 0.5 * I;
+  T[7][0][0] = T[7][1][1] = 0.5 / std::sqrt(3.0); T[7][2][2] = -1.0 / std::sqrt(3.0);
+  for (int q = 0; q < 144; ++q) G[q] = 0.0;
+  std::vector<C> t(12 * 81);
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      // the five matrices 1, T^a, T^b, T^a T^b, T^b T^a
+      C M[5][3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          M[0][i][j] = i == j ? 1.0 : 0.0;
+          M[1][i][j] = T[a][i][j];
+          M[2][i][j] = T[b][i][j];
+          C ab = 0.0, ba = 0.0;
+          for (int k = 0; k < 3; ++k) { ab += T[a][i][k] * T[b][k][j]; ba += T[b][i][k] * T[a][k][j]; }
+          M[3][i][j] = ab;
+          M[4][i][j] = ba;
+        }
+      static const int PQ[6][2] = {{3, 0}, {4, 0}, {0, 3}, {0, 4}, {1, 2}, {2, 1}};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+              const int o = ((i * 3 + j) * 3 + k) * 3 + l;
+              for (int m = 0; m < 6; ++m) {
+                t[m * 81 + o] = M[PQ[m][0]][i][l] * M[PQ[m][1]][k][j];
+                t[(6 + m) * 81 + o] = M[PQ[m][0]][i][j] * M[PQ[m][1]][k][l];
+              }
+            }
+      for (int m = 0; m < 12; ++m)
+        for (int n = 0; n < 12; ++n) {
+          C s = 0.0;
+          for (int o = 0; o < 81; ++o) s += t[m * 81 + o] * std::conj(t[n * 81 + o]);
+          G[m * 12 + n] += s.real();
+        }
+    }
+}
+
+// The colour matrix in each device's constant memory, once per device.
+static mem_status ensure_ttbb_colour()
+{
+  static bool done[64] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(MEM_EDEVICE, "hipGetDevice");
+  if (done[dev]) return MEM_OK;
+  double G[144];
+  float Gf[144];
+  ttbb_colour_matrix(G);
+  for (int q = 0; q < 144; ++q) Gf[q] = (float)G[q];
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(kColTTBB), G, sizeof(G)));
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(kColTTBBf), Gf, sizeof(Gf)));
+  done[dev] = true;
+  return MEM_OK;
+}
+
+// Device state a process needs before a launch: its PDF grid lives on the
+// current device; the t tbar b bbar colour matrix is in place.
 static mem_status check_pdf_device(const mem_process_s* p)
 {
+  if (p->desc.kind == MEM_TTBB_DILEPTON) {
+    mem_status st = ensure_ttbb_colour();
+    if (st != MEM_OK) return st;
+  }
   if (!p->pdf_dev) return MEM_OK;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(MEM_EDEVICE, "hipGetDevice");
@@ -540,6 +635,10 @@ __global__ __launch_bounds__(kBlock) void eval_points_kernel(ProcParams pp, Even
     SLEvent e;
     sl_load(ev, ev.charge, event, perm, e);
     f[k] = sl_integrand<T>(pp, e, x, &ns);
+  } else if constexpr (KIND == kTHL || KIND == kTBB) {
+    F2Event e;
+    f2_load(ev, KIND == kTHL, event, perm, e);
+    f[k] = f2_integrand<T, KIND == kTHL>(pp, e, x, &ns);
   } else {
     TTHEvent e;
     tth_load(ev, ev.charge, event, perm, e);
@@ -592,19 +691,23 @@ constexpr int64_t kDefaultChunk = 4096;   // points per work-queue chunk
 
 int n_obj_of(int kind)
 {
-  return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : kind == MEM_TT_SEMILEPTON ? 5 : kind == MEM_TTH_SEMILEPTON ? 7 : 4;
+  return kind == MEM_DY_QQ_GAMMA_MUMU ? 2 : kind == MEM_TT_SEMILEPTON ? 5 : kind == MEM_TTH_SEMILEPTON ? 7
+       : (kind == MEM_TTH_DILEPTON || kind == MEM_TTBB_DILEPTON) ? 6 : 4;
 }
+bool is_f2(int kind) { return kind == MEM_TTH_DILEPTON || kind == MEM_TTBB_DILEPTON; }
 
 // relative cost of one evaluation (for the longest-first queue order)
 double eval_cost(int kind)
 {
-  return kind == MEM_DY_QQ_GAMMA_MUMU ? 1.0 : kind == MEM_TT_SEMILEPTON ? 12.0 : kind == MEM_TTH_SEMILEPTON ? 30.0 : 30.0;
+  return kind == MEM_DY_QQ_GAMMA_MUMU ? 1.0 : kind == MEM_TT_SEMILEPTON ? 12.0 : kind == MEM_TTH_SEMILEPTON ? 30.0
+       : kind == MEM_TTH_DILEPTON ? 40.0 : kind == MEM_TTBB_DILEPTON ? 200.0 : 30.0;
 }
 
 int kind_mask(int kind)
 {
   return kind == MEM_DY_QQ_GAMMA_MUMU ? kMaskDY : kind == MEM_TT_DILEPTON ? kMaskTT
-       : kind == MEM_TT_SEMILEPTON ? kMaskSL : kMaskTTH;
+       : kind == MEM_TT_SEMILEPTON ? kMaskSL : kind == MEM_TTH_DILEPTON ? kMaskTHL
+       : kind == MEM_TTBB_DILEPTON ? kMaskTBB : kMaskTTH;
 }
 
 mem_status check_event_arrays(const mem_events* ev)
@@ -676,6 +779,9 @@ QueueKernel queue_kernel_for(int mask)
     case kMaskTT: return vegas_queue_kernel<T, kMaskTT>;
     case kMaskSL: return vegas_queue_kernel<T, kMaskSL>;
     case kMaskTTH: return vegas_queue_kernel<T, kMaskTTH>;
+    case kMaskTHL: return vegas_queue_kernel<T, kMaskTHL>;
+    case kMaskTBB: return vegas_queue_kernel<T, kMaskTBB>;
+    case kMaskTHL | kMaskTBB: return vegas_queue_kernel<T, kMaskTHL | kMaskTBB>;
     default:
       if (!(mask & kMaskTTH)) return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL>;
       return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL | kMaskTTH>;
@@ -770,10 +876,14 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     if (pi < 0) { procs.push_back(p); pi = (int)procs.size() - 1; }
     ev_proc[e] = pi;
   }
+  int n_f2 = 0;
   for (const auto* pr : procs) {
     mem_status ps = check_pdf_device(pr);
     if (ps != MEM_OK) return ps;
+    n_f2 += is_f2(pr->desc.kind) ? 1 : 0;
   }
+  if (n_f2 > 0 && n_f2 < (int)procs.size())
+    return fail(MEM_EUNSUPPORTED, "t tbar H / t tbar b bbar dilepton integrate in a batch of their own");
   std::vector<ProcParams> ptab(procs.size());
   for (size_t k = 0; k < procs.size(); ++k) ptab[k] = procs[k]->pp;
   std::vector<IntegralDesc> ints;
@@ -1150,6 +1260,18 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
   if (p->desc.kind == MEM_DY_QQ_GAMMA_MUMU)
     hipLaunchKernelGGL((eval_points_kernel<kDY, 2, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event, perm,
                        x, n, f, nsol);
+  else if (p->desc.kind == MEM_TTH_DILEPTON && p->desc.precision == MEM_FP32)
+    hipLaunchKernelGGL((eval_points_kernel<kTHL, 8, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
+  else if (p->desc.kind == MEM_TTH_DILEPTON)
+    hipLaunchKernelGGL((eval_points_kernel<kTHL, 8, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
+  else if (p->desc.kind == MEM_TTBB_DILEPTON && p->desc.precision == MEM_FP32)
+    hipLaunchKernelGGL((eval_points_kernel<kTBB, 8, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
+  else if (p->desc.kind == MEM_TTBB_DILEPTON)
+    hipLaunchKernelGGL((eval_points_kernel<kTBB, 8, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
+                       perm, x, n, f, nsol);
   else if (p->desc.kind == MEM_TTH_SEMILEPTON && p->desc.precision == MEM_FP32)
     hipLaunchKernelGGL((eval_points_kernel<kTTH, 9, float>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
                        perm, x, n, f, nsol);
@@ -1170,6 +1292,35 @@ extern "C" mem_status mem_eval_points(mem_process p, const mem_events* ev, int32
                        perm, x, n, f, nsol);
   HIP_TRY(hipGetLastError());
   if (!ev->on_device) HIP_TRY(hipStreamSynchronize(s));   // the staged copy is freed on return
+  return MEM_OK;
+}
+
+// Event discriminant of Sec. 4: D = log10(p_signal / p_background).
+__global__ void discriminant_kernel(const double* __restrict__ ps, const double* __restrict__ pb, int64_t n,
+                                    double* __restrict__ d)
+{
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double s = ps[k], b = pb[k];
+  double v;
+  if (s > 0.0 && b > 0.0) v = log10(s) - log10(b);
+  else if (s > 0.0 && b == 0.0) v = HUGE_VAL;
+  else if (s == 0.0 && b > 0.0) v = -HUGE_VAL;
+  else v = __builtin_nan("");
+  d[k] = v;
+}
+
+extern "C" mem_status mem_discriminant(const double* p_sig, const double* p_bkg, int64_t n, double* d_out,
+                                       void* stream)
+{
+  if (n < 0) return fail(MEM_EINVAL, "negative n");
+  if (n == 0) return MEM_OK;
+  if (!p_sig || !p_bkg || !d_out) return fail(MEM_EINVAL, "null argument");
+  if (n > ((int64_t)1 << 40)) return fail(MEM_EINVAL, "n too large");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(discriminant_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p_sig,
+                     p_bkg, n, d_out);
+  HIP_TRY(hipGetLastError());
   return MEM_OK;
 }
 
@@ -1414,6 +1565,9 @@ extern "C" mem_status mem_vegas_capture(mem_process p, const mem_events* ev, con
         hipLaunchKernelGGL((capture_kernel<kTT, 8, double>), grid, dim3(kBlock), 0, s, p->pp, dev.view, event,
                            perm, n_int, grids, n_per, seed, iter, x_out, w_out);
       break;
+    case MEM_TTH_DILEPTON:
+    case MEM_TTBB_DILEPTON:
+      return fail(MEM_EUNSUPPORTED, "training capture covers the single-top-pair kinds");
     default:
       return fail(MEM_EINVAL, "unknown process kind");
   }

@@ -4,7 +4,7 @@
 
 namespace memk {
 
-enum Kind : int32_t { kDY = 1, kTT = 2, kSL = 3, kTTH = 4 };
+enum Kind : int32_t { kDY = 1, kTT = 2, kSL = 3, kTTH = 4, kTHL = 5, kTBB = 6 };
 
 // One transfer function for the energy of a measured object, Gaussian or
 // double Gaussian in r = E_meas / E_true (Sec. 1, after Eq. 3).
@@ -46,6 +46,11 @@ struct ProcParams {
   double tth_const;
   // couplings of the t tbar |M|^2: g_s^4 (g_W^2 / 2)^4
   double me_const;
+  // t tbar H and t tbar b bbar, dilepton: (2 pi)^-20 (2/S) / (2 shat)
+  // / (2E_nu 2E_nubar), the couplings, the initial-state average 1/256 and
+  // the (th1 - th0)/(M Gamma) of the aligned propagators (for t tbar H with
+  // the Yukawa and H -> b bbar factors; times q2_H per point)
+  double f2_const;
   // parton densities from a grid (null: the toy densities): x f of the
   // 11 flavours in nodes of 12 floats (layout in pdf.hpp), [nq][nx][12],
   // uniform in ln x and ln Q; position = (ln v - v0) * inverse step

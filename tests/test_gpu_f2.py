@@ -1,0 +1,186 @@
+"""Sec. 4's analysis on the GPU against the FP64 oracle: t tbar H (H -> b
+bbar) and t tbar b bbar, both in the dilepton channel with four b-jets
+(8 dimensions, Eqs. integrand, dilepsolv, mhsolve).
+
+Bars: the integrand on identical points, FP32 matrix element within 1e-5
+relative and FP64 within 1e-9, with the neutrino solution count equal
+(points whose oracle value moves by more than a tenth of the bar under
+1-ulp input changes are counted and excluded, at most 1 %); the first
+iteration's sums on the uniform grid within 2e-5 (FP32); t tbar H
+estimates by a pull test (|pull| < 3); the discriminant against log10 of
+the two densities to 1e-12.  The t tbar b bbar oracle takes about 10 ms per
+point, so its estimate-level check is the first-iteration sums."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import events
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+KINDS = {"tth": (oracle.KIND_TTH_LL, 12), "ttbb": (oracle.KIND_TTBB_LL, 24)}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mem():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1407_7595_amd as m
+    m.lib()
+    return m
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def gen(which, n, seed):
+    return (events.ttbar_higgs_dilepton if which == "tth" else events.ttbar_bbbar_dilepton)(n, seed)
+
+
+def integrand(which):
+    return oracle.tthll_integrand if which == "tth" else oracle.ttbbll_integrand
+
+
+def gpu_kind(mem, which):
+    return mem.MEM_TTH_DILEPTON if which == "tth" else mem.MEM_TTBB_DILEPTON
+
+
+def ill_conditioned(f, po, ev, perm, x, f0, rel):
+    for k in range(3):
+        xp = np.nextafter(x, 1.0) if k == 0 else np.nextafter(x, 0.0) if k == 1 else x * (1 + 2e-16)
+        xp = np.clip(xp, 0.0, 1.0 - 2 ** -53)
+        if abs(f(po, ev, perm, xp)[0] - f0) > rel * max(abs(f0), 1e-300):
+            return True
+    return False
+
+
+@pytest.mark.parametrize("which", ["tth", "ttbb"])
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-9)])
+def test_f2_integrand(mem, which, precision, tol):
+    from test_oracle_pins import f2_truth_x
+    kind, n_perm = KINDS[which]
+    f_or = integrand(which)
+    p = mem.Process(gpu_kind(mem, which), precision=precision)
+    po = oracle.tt_params()
+    d = gen(which, 3, 31)
+    comps = mem.to_components(d["obs"]).cuda()
+    rng = np.random.default_rng(6)
+    n_pts = 150 if which == "tth" else 60
+    n_cmp = n_flag = n_zero = 0
+    worst = 0.0
+    for e in range(3):
+        xt, tperm = f2_truth_x(po, kind, d, e)
+        near = np.clip(xt + 0.004 * rng.standard_normal((n_pts, 8)), 1e-6, 1 - 1e-6)
+        for perm in sorted({tperm, int(rng.integers(n_perm))}):
+            x = near if perm == tperm else rng.random((n_pts, 8))
+            say(f"{which} integrand precision={precision} event={e} perm={perm}")
+            f = torch.empty(len(x), dtype=torch.float64, device="cuda")
+            ns = torch.empty(len(x), dtype=torch.int32, device="cuda")
+            mem.eval_points(p, comps, e, perm, dev(x), f, ns)
+            torch.cuda.synchronize()
+            got, gns = f.cpu().numpy(), ns.cpu().numpy()
+            assert np.all(np.isfinite(got)), (e, perm)
+            for k, xi in enumerate(x):
+                want, wns = f_or(po, d["obs"][e], perm, xi)
+                if want == 0.0 and got[k] == 0.0:
+                    n_zero += 1
+                    continue
+                r = abs(got[k] - want) / max(abs(want), 1e-300)
+                if (r > tol or gns[k] != wns) and ill_conditioned(f_or, po, d["obs"][e], perm, xi, want, 0.1 * tol):
+                    n_flag += 1
+                    continue
+                assert r <= tol and gns[k] == wns, (e, perm, k, got[k], want, gns[k], wns)
+                n_cmp += 1
+                worst = max(worst, r)
+    say(f"{which} compared {n_cmp} nonzero points, worst rel {worst:.3g}, zero {n_zero}, flagged {n_flag}")
+    assert n_cmp > (120 if which == "tth" else 60) and n_flag <= 0.01 * n_cmp + 2
+
+
+@pytest.mark.parametrize("which", ["tth", "ttbb"])
+def test_f2_iteration0_sums(mem, which):
+    kind, n_perm = KINDS[which]
+    p = mem.Process(gpu_kind(mem, which), precision=mem.MEM_FP32)
+    po = oracle.tt_params()
+    d = gen(which, 2, 32)
+    comps = mem.to_components(d["obs"]).cuda()
+    n_per, seed = 600, 29                 # one ragged chunk per assignment
+    n_int = 2 * n_perm
+    it_out = torch.zeros(2 * n_int * 2, dtype=torch.float64, device="cuda")
+    say(f"{which} integrate 2 events x {n_perm} x {n_per} points x 2 iterations")
+    mem.integrate_events(comps, p, n_perm * n_per, 2, seed=seed, iter_out=it_out)
+    torch.cuda.synchronize()
+    rec = it_out.cpu().numpy().reshape(2, n_int, 2)
+    g0 = oracle.uniform_grid(8)
+    perms = (0, 5, 11) if which == "tth" else (3, 17)
+    n_nz = 0
+    for e in range(2):
+        for perm in perms:
+            s1, s2, _ = oracle.vegas_iteration(kind, po, d["obs"][e], perm, seed, e, 0, n_per, g0)
+            I0 = s1 / n_per
+            n_nz += I0 > 0
+            say(f"  event {e} perm {perm}: gpu {rec[0, n_perm * e + perm, 0]:.6e} oracle {I0:.6e}")
+            assert rec[0, n_perm * e + perm, 0] == pytest.approx(I0, rel=2e-5, abs=1e-300), (e, perm)
+    assert n_nz >= 2
+
+
+def test_tth_dilepton_estimates_pull(mem):
+    p = mem.Process(mem.MEM_TTH_DILEPTON, precision=mem.MEM_FP32)
+    po = oracle.tt_params()
+    n_ev, n_pts, n_it = 3, 12 * 1500, 4
+    d = gen("tth", n_ev, 33)
+    comps = mem.to_components(d["obs"]).cuda()
+    say(f"tth dilepton integrate {n_ev} events x {n_pts} x {n_it}")
+    P, err, st = mem.integrate_events(comps, p, n_pts, n_it, seed=81)
+    torch.cuda.synchronize()
+    P, err, st = P.cpu().numpy(), err.cpu().numpy(), st.cpu().numpy()
+    assert np.all(np.isfinite(P)) and np.all(P > 0) and np.all(st == 0)
+    Po, Eo, So = oracle.integrate_events(oracle.KIND_TTH_LL, po, d["obs"], 81, n_pts, n_it)
+    pl = (P - Po) / np.sqrt(err ** 2 + Eo ** 2)
+    say("tth dilepton P", P, "oracle", Po, "pulls", np.round(pl, 3))
+    assert np.all(np.abs(pl) < 3.0)
+
+
+def test_discriminant_and_batches(mem):
+    """D = log10(p_ttH / p_ttbb) for signal and background samples: the
+    device kernel equals log10 of the two densities; signal events sit
+    higher than background events (medians); the two kinds share a batch,
+    other kinds may not join it"""
+    sig = gen("tth", 8, 34)["obs"]
+    bkg = gen("ttbb", 8, 35)["obs"]
+    obs = np.concatenate([sig, bkg])
+    comps = mem.to_components(obs).cuda()
+    h_s = mem.Process(mem.MEM_TTH_DILEPTON, precision=mem.MEM_FP32)
+    h_b = mem.Process(mem.MEM_TTBB_DILEPTON, precision=mem.MEM_FP32)
+    say("discriminant: 16 events under both hypotheses")
+    Ps, Es, Ss = mem.integrate_events(comps, h_s, 12 * 2048, 5, seed=91)
+    Pb, Eb, Sb = mem.integrate_events(comps, h_b, 24 * 1024, 5, seed=92)
+    D = mem.discriminant(Ps, Pb)
+    torch.cuda.synchronize()
+    ps, pb, d = Ps.cpu().numpy(), Pb.cpu().numpy(), D.cpu().numpy()
+    assert np.all(ps > 0) and np.all(pb > 0)
+    assert np.allclose(d, np.log10(ps) - np.log10(pb), rtol=0, atol=1e-12)
+    say(f"  D signal {np.round(d[:8], 2)}\n  D background {np.round(d[8:], 2)}")
+    assert np.median(d[:8]) > np.median(d[8:])
+    # one batch holding both kinds: each event its own hypothesis
+    hyp = [h_s] * 8 + [h_b] * 8
+    Pm, _, _ = mem.integrate_events(comps, hyp, [12 * 512] * 8 + [24 * 256] * 8, 3, seed=93)
+    torch.cuda.synchronize()
+    assert np.all(Pm.cpu().numpy() > 0)
+    h_tt = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    with pytest.raises(RuntimeError, match="batch of their own"):
+        mem.integrate_events(comps, [h_s] * 15 + [h_tt], 4096, 2, seed=94)
+    z = torch.zeros(3, dtype=torch.float64, device="cuda")
+    o = torch.ones(3, dtype=torch.float64, device="cuda")
+    dz = mem.discriminant(o, z).cpu().numpy()
+    assert np.all(np.isposinf(dz))
+    assert np.all(np.isnan(mem.discriminant(z, z).cpu().numpy()))

@@ -1021,3 +1021,138 @@ def test_pdf_grid_tth_gluon_and_scale():
         assert oracle.tth_integrand(oracle.with_pdf(p, gt), d["obs"][i], perm, x)[0] == pytest.approx(
             oracle.tth_integrand(p, d["obs"][i], perm, x)[0], rel=0.01)
     assert n >= 5
+
+
+# ------------------------------------------ t tbar b bbar and Sec. 4 (f2) --
+def _ttbb_kin(rng, mt, mb=0.0, spread=150.0):
+    """g(k1) g(k2) -> p3 p4 p5 p6 in the partonic rest frame, masses (mt, mt,
+    mb, mb), gluons along +-z"""
+    ps = rng.normal(0.0, spread, (3, 3))
+    P = np.vstack([ps, -ps.sum(0)])
+    m = np.array([mt, mt, mb, mb])
+    E = np.sqrt((P ** 2).sum(1) + m ** 2)
+    mom = np.column_stack([E, P])
+    W = E.sum()
+    return np.array([W / 2, 0, 0, W / 2]), np.array([W / 2, 0, 0, -W / 2]), mom
+
+
+def test_ttbb_colour_closed_forms():
+    """SU(3) pins of the colour machinery: f^123 = 1, f^acd f^bcd = N
+    delta^ab, and diagonal colour-matrix entries of four diagram classes
+    worked out by hand with Tr(T^a T^b) = delta^ab / 2 and sum_a T^a T^a = C_F:
+    (T^aT^bT^c)_ij T^c_kl: C_F^3 N / 2 = 32/9; (T^aT^c)_ij (T^bT^c)_kl: 2 C_F^2
+    = 32/9; f^abe (T^eT^c)_ij T^c_kl: N^2 C_F^2 / 2 = 8; f^ace f^beg T^g_ij
+    T^c_kl: N^2 (N^2 - 1) / 4 = 18."""
+    F = oracle.colour_fabc()
+    assert F[0, 1, 2] == pytest.approx(1.0, abs=1e-14)
+    assert np.allclose(np.einsum("acd,bcd->ab", F, F), 3.0 * np.eye(8), atol=1e-13)
+    assert np.allclose(F, -np.transpose(F, (1, 0, 2)), atol=1e-14)
+    CM = oracle.colour_matrix_ttbb()
+    assert np.allclose(CM, CM.T, atol=1e-12)
+    assert np.min(np.linalg.eigvalsh(CM)) > -1e-10            # a Gram matrix
+    for d, v in ((0, 32 / 9), (6, 32 / 9), (12, 32 / 9), (20, 8.0), (32, 18.0)):
+        assert CM[d, d] == pytest.approx(v, rel=1e-12), d
+
+
+@pytest.mark.parametrize("mt", [172.5, 0.0])
+def test_ttbb_ward_identity(mt):
+    """with either gluon's polarisation replaced by its momentum (the other
+    physical) the colour-summed |M|^2 vanishes: every diagram, colour factor
+    and relative sign enters"""
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        k1, k2, m = _ttbb_kin(rng, mt)
+        for g in (0, 1):
+            assert oracle.gg_ttbb_ward(mt, k1, k2, *m, g) < 1e-20
+
+
+def test_ttbb_symmetries():
+    """Bose symmetry (k1 <-> k2); with massless tops the t tbar <-> b bbar
+    exchange; the colour quadratic form equals the explicit colour sum"""
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        k1, k2, m = _ttbb_kin(rng, 172.5)
+        v = oracle.gg_ttbb_prod(172.5, k1, k2, *m)
+        assert v > 0.0
+        assert oracle.gg_ttbb_prod(172.5, k2, k1, *m) == pytest.approx(v, rel=1e-12)
+        assert oracle.gg_ttbb_prod_explicit(172.5, k1, k2, *m) == pytest.approx(v, rel=1e-10)
+        k1, k2, m = _ttbb_kin(rng, 0.0)
+        v0 = oracle.gg_ttbb_prod(0.0, k1, k2, *m)
+        assert oracle.gg_ttbb_prod(0.0, k1, k2, m[2], m[3], m[0], m[1]) == pytest.approx(v0, rel=1e-12)
+
+
+def test_f2_assignments():
+    """every assignment is a distinct placement of the four jets: 12 for
+    t tbar H (the Higgs pair unordered), 24 for t tbar b bbar"""
+    L = oracle.lib()
+    assert L.or_nperm(oracle.KIND_TTH_LL) == 12 and L.or_nperm(oracle.KIND_TTBB_LL) == 24
+    assert L.or_dims(oracle.KIND_TTH_LL) == 8 and L.or_dims(oracle.KIND_TTBB_LL) == 8
+    seen = set()
+    for q in range(12):
+        r = oracle.f2_perm(oracle.KIND_TTH_LL, q)
+        assert sorted(r) == [0, 1, 2, 3] and r[2] < r[3]
+        seen.add((r[0], r[1], frozenset(r[2:])))
+    assert len(seen) == 12
+    perms = [oracle.f2_perm(oracle.KIND_TTBB_LL, q) for q in range(24)]
+    assert perms == sorted(perms) and len(set(perms)) == 24
+
+
+def _inv_bw(q2, m, w, S=13000.0 ** 2):
+    mw = m * w
+    t0, t1 = math.atan(-m * m / mw), math.atan((S - m * m) / mw)
+    return (math.atan((q2 - m * m) / mw) - t0) / (t1 - t0)
+
+
+def f2_truth_x(po, kind, d, e):
+    """the assignment and the point x of the generated partons of event e"""
+    t, obs, slot = d["truth"], d["obs"][e], d["truth"]["slot"][e]
+    m2 = lambda v: v[0] ** 2 - v[1] ** 2 - v[2] ** 2 - v[3] ** 2
+    for perm in range(oracle.lib().or_nperm(kind)):
+        rows = oracle.f2_perm(kind, perm)
+        if kind == oracle.KIND_TTH_LL:
+            ok = rows[:2] == tuple(slot[:2]) and sorted(rows[2:]) == sorted(slot[2:])
+        else:
+            ok = rows == tuple(slot)
+        if ok:
+            break
+    q = {slot[0]: t["b"][e], slot[1]: t["bb"][e], slot[2]: t["p1"][e], slot[3]: t["p2"][e]}
+    r = lambda row: (obs[row][0] / q[row][0] - po.r_lo) / (po.r_hi - po.r_lo)
+    x = np.zeros(8)
+    x[0], x[1], x[6] = r(rows[0]), r(rows[1]), r(rows[2])
+    x[2] = _inv_bw(m2(t["b"][e] + t["lp"][e] + t["nu"][e]), po.m_t, po.w_t)
+    x[3] = _inv_bw(m2(t["bb"][e] + t["lm"][e] + t["nub"][e]), po.m_t, po.w_t)
+    x[4] = _inv_bw(m2(t["lp"][e] + t["nu"][e]), po.m_w, po.w_w)
+    x[5] = _inv_bw(m2(t["lm"][e] + t["nub"][e]), po.m_w, po.w_w)
+    if kind == oracle.KIND_TTH_LL:
+        h1, h2 = q[rows[2]], q[rows[3]]
+        x[7] = _inv_bw(2.0 * (h1[0] * h2[0] - h1[1:] @ h2[1:]), po.m_h, po.w_h)
+    else:
+        x[7] = r(rows[3])
+    return x, perm
+
+
+@pytest.mark.parametrize("kind", [oracle.KIND_TTH_LL, oracle.KIND_TTBB_LL])
+def test_f2_integrand_truth_and_relabelling(kind):
+    """at the generated partons' point the integrand is positive and its
+    neutrino solve has a solution; relabelling the event's jets and
+    following them with the assignment leaves every value unchanged"""
+    po = oracle.tt_params()
+    gen = events.ttbar_higgs_dilepton if kind == oracle.KIND_TTH_LL else events.ttbar_bbbar_dilepton
+    f = oracle.tthll_integrand if kind == oracle.KIND_TTH_LL else oracle.ttbbll_integrand
+    d = gen(4, 21)
+    n = oracle.lib().or_nperm(kind)
+    for e in range(4):
+        x, perm = f2_truth_x(po, kind, d, e)
+        assert np.all((x > 0) & (x < 1))
+        v, ns = f(po, d["obs"][e], perm, x)
+        assert v > 0.0 and ns >= 1
+        # swap two jet rows (t tbar H: the b and bbar jets, which keeps the
+        # Higgs pair's order) and find the assignment with the same partons
+        rows = oracle.f2_perm(kind, perm)
+        i, j = (rows[0], rows[1]) if kind == oracle.KIND_TTH_LL else (0, 3)
+        ev2 = d["obs"][e].copy()
+        ev2[[i, j]] = ev2[[j, i]]
+        sw = {i: j, j: i}
+        want = tuple(sw.get(r, r) for r in rows)
+        p2 = [q for q in range(n) if oracle.f2_perm(kind, q) == want][0]
+        assert f(po, ev2, p2, x)[0] == v
