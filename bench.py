@@ -207,6 +207,11 @@ def flow_leg(mem, proc, comps, n_ev, args):
 
 
 PARTON_EVENTS = 100000
+# Sec. 4's analysis: half t tbar H, half t tbar b bbar dilepton events, each
+# integrated under both hypotheses at a fixed budget
+F2_EVENTS = 1024
+F2_PTS = 49152
+F2_ITERS = 6
 
 
 def parton_leg(mem, proc):
@@ -255,6 +260,46 @@ def pdf_grid_leg(mem, comps, n_ev, kern_ms_toy):
     return out
 
 
+def tth_vs_ttbb_leg(mem):
+    """Sec. 4's analysis: the event discriminant D = log10(p_ttH / p_ttbb)
+    for seeded t tbar H and t tbar b bbar dilepton events (four b-jets, 8D),
+    each event integrated under both hypotheses (FP32 matrix elements,
+    Neyman allocation across the assignments, a fixed budget)"""
+    import numpy as np
+    import torch
+    from synth import events
+    n_half = F2_EVENTS // 2
+    obs = np.concatenate([events.ttbar_higgs_dilepton(n_half, SEED_EVENTS + 20)["obs"],
+                          events.ttbar_bbbar_dilepton(n_half, SEED_EVENTS + 21)["obs"]])
+    comps = mem.to_components(obs).cuda()
+    out = {"events": F2_EVENTS, "signal_events": n_half, "iterations": F2_ITERS}
+    res = {}
+    for name, kind, pts in (("tth", mem.MEM_TTH_DILEPTON, F2_PTS), ("ttbb", mem.MEM_TTBB_DILEPTON, F2_PTS)):
+        proc = mem.Process(kind, precision=mem.MEM_FP32)
+        mem.integrate_events(comps[:, :, :64].contiguous(), proc, pts, 2, allocation=mem.MEM_ALLOC_NEYMAN)
+        timing = (ctypes.c_double * 8)()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P, E, S = mem.integrate_events(comps, proc, pts, F2_ITERS, timing=timing, allocation=mem.MEM_ALLOC_NEYMAN)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = P
+        p_, e_ = P.cpu().numpy(), E.cpu().numpy()
+        ok = p_ > 0
+        out[name] = {"points_per_iteration": pts, "seconds": wall, "events_per_s": F2_EVENTS / wall,
+                     "kernel_ms": timing[0], "evals_per_s": timing[2] / wall,
+                     "median_rel_err": float(np.median(e_[ok] / p_[ok])) if ok.any() else None,
+                     "status_ok": float((S == 0).double().mean())}
+    D = mem.discriminant(res["tth"], res["ttbb"]).cpu().numpy()
+    ds, db = D[:n_half], D[n_half:]
+    out["D_median_signal"] = float(np.median(ds))
+    out["D_median_background"] = float(np.median(db))
+    out["signal_above_background_median"] = float(np.mean(ds > np.median(db)))
+    out["events_per_s_both"] = F2_EVENTS / (out["tth"]["seconds"] + out["ttbb"]["seconds"])
+    log(f"tth vs ttbb: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +310,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
     ap.add_argument("--no-grid", action="store_true", help="skip the grid-PDF pass")
+    ap.add_argument("--no-f2", action="store_true", help="skip the t tbar H vs t tbar b bbar pass")
     ap.add_argument("--flow-train-events", type=int, default=FLOW_TRAIN_EVENTS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB fill and a 256 MiB elementwise copy (reference for HBM byte counters)")
@@ -357,6 +403,7 @@ def main():
                 "frac": achieved / PEAK_FP32, "traffic": traffic}
     parton = parton_leg(mem, proc)
     grid = None if args.no_grid else pdf_grid_leg(mem, comps, n_ev, kern_ms)
+    f2 = None if args.no_f2 else tth_vs_ttbb_leg(mem)
     flow = None
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)
@@ -384,6 +431,7 @@ def main():
         "flow_vs_vegas": flow,
         "parton_level": parton,
         "pdf_grid": grid,
+        "tth_vs_ttbb": f2,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -230,7 +230,7 @@ enum { kMaskDY = 1, kMaskTT = 2, kMaskSL = 4, kMaskTTH = 8, kMaskTHL = 16, kMask
 // instance matches the oracle.
 template <int KINDS> constexpr int queue_waves()
 {
-  return (KINDS & (kMaskTTH | kMaskTHL | kMaskTBB)) ? 2 : MEM_TT_WAVES;
+  return (KINDS & kMaskTTH) ? 2 : MEM_TT_WAVES;
 }
 template <class T, int KINDS>
 __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kernel(

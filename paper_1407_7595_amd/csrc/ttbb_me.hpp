@@ -193,12 +193,15 @@ __device__ __forceinline__ T gg_ttbb_sum(const drow<T>& R, const drow<T>& C, con
   const sp<T> z2{zc, zc};
   const T h = T(0.5), hn = T(0.5 / 3.0);
   T sum = T(0);
+  // helicity loops kept rolled: one copy of the 38 diagrams in registers
+#pragma unroll 1
   for (int hb = 0; hb < 2; ++hb) {
     // (U, V) = (ubar_1, v_1) = ((0, lambda5^*), (lambda6, 0)) or
     //          (ubar_2, v_2) = ((eps^T lambda5, 0), (0, eps^T lambda6^*))
     const drow<T> U = hb == 0 ? drow<T>{z2, cj(l5)} : drow<T>{epsT(l5), z2};
     const drow<T> V = hb == 0 ? drow<T>{l6, z2} : drow<T>{z2, epsT(cj(l6))};
     const cv<T> Gb = cvs(iPb, vec_rc(U, V));
+#pragma unroll 1
     for (int hh = 0; hh < 4; ++hh) {
       // gluon polarisations (0, 1, +-i, 0)/sqrt2
       const T sy1 = (hh & 1) ? -s2 : s2, sy2 = (hh & 2) ? -s2 : s2;
