@@ -300,6 +300,34 @@ def tth_vs_ttbb_leg(mem):
     return out
 
 
+def f2_parton_leg(mem):
+    """Sec. 4's parton-level timing (its Table 2): 10^5 t tbar H and 10^5
+    t tbar b bbar dilepton events at parton level, every placement of the
+    four b quarks summed, FP32 matrix elements"""
+    import numpy as np
+    import torch
+    from synth import events
+    out = {"events": PARTON_EVENTS}
+    for name, kind, genf, seed in (("tth", mem.MEM_TTH_DILEPTON, events.ttbar_higgs_dilepton, 30),
+                                   ("ttbb", mem.MEM_TTBB_DILEPTON, events.ttbar_bbbar_dilepton, 31)):
+        ev = events.four_b_partons(genf(PARTON_EVENTS, SEED_EVENTS + seed), SEED_EVENTS + seed + 1)
+        comps = torch.as_tensor(np.ascontiguousarray(ev.transpose(2, 1, 0))).cuda()
+        proc = mem.Process(kind, precision=mem.MEM_FP32)
+        w = torch.empty(PARTON_EVENTS, dtype=torch.float64, device="cuda")
+        mem.parton_weights(proc, comps, out=w)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mem.parton_weights(proc, comps, out=w)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"seconds": dt, "events_per_s": PARTON_EVENTS / dt,
+                     "assignments": 12 if name == "tth" else 24, "nonzero_fraction": float((w > 0).double().mean())}
+    log(f"tth vs ttbb parton level: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +432,8 @@ def main():
     parton = parton_leg(mem, proc)
     grid = None if args.no_grid else pdf_grid_leg(mem, comps, n_ev, kern_ms)
     f2 = None if args.no_f2 else tth_vs_ttbb_leg(mem)
+    if f2 is not None:
+        f2["parton_level"] = f2_parton_leg(mem)
     flow = None
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)

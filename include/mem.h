@@ -349,9 +349,14 @@ mem_status mem_eval_points(mem_process p, const mem_events* ev, int32_t event, i
  * where x1 or x2 leaves (0, 1].  FP32 or FP64 per the process precision.
  * w_out: n_events doubles, device memory when ev->on_device, else host
  * (may be null when n_events is 0).
+ * MEM_TTH_DILEPTON and MEM_TTBB_DILEPTON (Sec. 4's parton-level timing,
+ * its Table 2): objects b quarks 0-3 (any order), l+, l-, nu, nubar; the
+ * same formula with the gg channel, the complete t tbar H (with H -> b bbar
+ * and the Higgs Breit-Wigner) or t tbar b bbar |M|^2, averaged over the 12
+ * or 24 placements of the four b quarks.
  * MEM_EUNSUPPORTED for other kinds; MEM_EINVAL for null pointers, fewer
- * than 6 objects, or (host events) non-finite or non-positive-energy
- * objects. */
+ * than 6 objects (8 for the four-b kinds), or (host events) non-finite or
+ * non-positive-energy objects. */
 mem_status mem_parton_weights(mem_process p, const mem_events* ev, double* w_out, void* stream);
 
 /* VEGAS damped rebinning (Lepage 1978) of n_int x D grids in place from

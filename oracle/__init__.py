@@ -184,6 +184,7 @@ def _declare(L):
         "or_f2_perm": (None, [I, I, P]),
         "or_tthll_integrand": (D, [P, P, I, P, P]),
         "or_ttbbll_integrand": (D, [P, P, I, P, P]),
+        "or_f2_parton_weight": (D, [I, P, P]),
         "or_flow_forward": (D, [P, P, P, P]),
         "or_flow_inverse": (D, [P, P, P, P]),
         "or_flow_context": (None, [P, I, P]),
@@ -495,6 +496,10 @@ def ttbbll_integrand(p, ev, perm, x):
     ns = ctypes.c_int(0)
     v = lib().or_ttbbll_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
     return v, ns.value
+
+
+def f2_parton_weight(kind, p, ev):
+    return lib().or_f2_parton_weight(kind, ctypes.byref(p), _ptr(_f64(ev)))
 
 
 def tth_perm(perm):

@@ -1108,3 +1108,47 @@ double or_ttbbll_integrand(const or_params* p, const double* ev, int perm, const
 {
   return f2_integrand(OR_KIND_TTBB_LL, p, ev, perm, x, nsol_out);
 }
+
+/* Parton level for Sec. 4's processes (its Table 2 workload): the transfer
+ * functions are delta functions, so only the energy and longitudinal
+ * momentum delta functions, the flux, the densities and the complete
+ * |M|^2 remain; the weight is the mean over the jet assignments (the four b
+ * quarks placed as in or_f2_perm).  ev: 8 x {E,px,py,pz}: b quarks 0-3 (any
+ * order), l+, l-, nu, nubar. */
+double or_f2_parton_weight(int kind, const or_params* p, const double* ev)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  const double *lp = ev + 16, *lm = ev + 20, *nu = ev + 24, *nub = ev + 28;
+  const int n = or_nperm(kind);
+  double sum = 0.0;
+  for (int perm = 0; perm < n; ++perm) {
+    int rows[4];
+    or_f2_perm(kind, perm, rows);
+    double lab[8][4];
+    memcpy(lab[0], ev + 4 * rows[0], 32); memcpy(lab[1], lp, 32); memcpy(lab[2], nu, 32);
+    memcpy(lab[3], ev + 4 * rows[1], 32); memcpy(lab[4], lm, 32); memcpy(lab[5], nub, 32);
+    memcpy(lab[6], ev + 4 * rows[2], 32); memcpy(lab[7], ev + 4 * rows[3], 32);
+    double P[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) for (int i = 0; i < 4; ++i) P[i] += lab[k][i];
+    double hard[32];
+    for (int k = 0; k < 8; ++k) boost_transverse(P, lab[k], hard + 4 * k);
+    double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+    double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
+    double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+    double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+    double g1, g2;
+    if (p->pdf) {
+      g1 = or_pdf_interp(p->pdf, 0, x1, p->m_t) / x1;
+      g2 = or_pdf_interp(p->pdf, 0, x2, p->m_t) / x2;
+    } else {
+      g1 = or_xf_g(x1) / x1;
+      g2 = or_xf_g(x2) / x2;
+    }
+    double me = kind == OR_KIND_TTH_LL ? or_tth_me2_gg(p, k1, k2, hard, hard + 24, hard + 28)
+                                       : or_ttbb_me2_gg(p, k1, k2, hard, hard + 24, hard + 28);
+    double shat = x1 * x2 * S;
+    sum += (2.0 / S) * (P[0] / Eh) * g1 * g2 * me / (2.0 * shat);
+  }
+  return sum / n;
+}

@@ -220,6 +220,9 @@ enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_K
 void or_f2_perm(int kind, int perm, int* rows);
 double or_tthll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out);
 double or_ttbbll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out);
+/* parton level (transfer functions delta functions): ev = 8 x {E,px,py,pz},
+ * b quarks 0-3, l+, l-, nu, nubar; mean over the jet assignments */
+double or_f2_parton_weight(int kind, const or_params* p, const double* ev);
 typedef struct {
   double I, sigma;          /* combined estimate over iterations >= 2 */
   double chi2dof;

@@ -174,4 +174,60 @@ __device__ __forceinline__ double f2_integrand(const ProcParams& pp, const F2Eve
   return acc * pp.f2_const * q2h * ev.lep_fac * (double)jetf;
 }
 
+// Parton level (Sec. 4's Table 2 workload): the transfer functions are
+// delta functions, so the weight of an assignment is (2/S) (E / E') times
+// the complete |M|^2 and densities over 2 shat x1 x2 (x f form); the four
+// top and W Breit-Wigner factors (and the Higgs one with its q2_H) are
+// evaluated, f2_parton_const holds the couplings.  o: b quarks 0-3, l+, l-,
+// nu, nubar; the weight is the mean over the assignments.
+__device__ __forceinline__ v4 pick4(const v4& a, const v4& b, const v4& c, const v4& d, int r)
+{
+  return r == 0 ? a : r == 1 ? b : r == 2 ? c : d;
+}
+
+template <class T, bool TTH>
+__device__ __forceinline__ double f2_parton(const ProcParams& pp, const v4 (&o)[8])
+{
+  constexpr int n = TTH ? 12 : 24;
+  const T mt = T(pp.m_t * kMeScale);
+  double sum = 0.0;
+#pragma unroll 1
+  for (int perm = 0; perm < n; ++perm) {
+    int rows[4];
+    f2_rows(TTH, perm, rows);
+    const v4 b0 = pick4(o[0], o[1], o[2], o[3], rows[0]), b1 = pick4(o[0], o[1], o[2], o[3], rows[1]);
+    const v4 q1 = pick4(o[0], o[1], o[2], o[3], rows[2]), q2 = pick4(o[0], o[1], o[2], o[3], rows[3]);
+    const v4 P = add(add(add(b0, b1), add(q1, q2)), add(add(o[4], o[5]), add(o[6], o[7])));
+    const double Eh = sqrt(P.e * P.e - P.x * P.x - P.y * P.y);
+    const double x1 = (Eh + P.z) * pp.inv_sqrt_s, x2 = (Eh - P.z) * pp.inv_sqrt_s;
+    if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) continue;
+    T gg, qq12, qq21;
+    tt_lumis<T>(pp, x1, x2, gg, qq12, qq21);
+    TBoost B(P);
+    const v4 hb = B.apply_me(b0), hl = B.apply_me(o[4]), hn = B.apply_me(o[6]);
+    const v4 hbb = B.apply_me(b1), hlm = B.apply_me(o[5]), hnb = B.apply_me(o[7]);
+    const v4 h1 = B.apply_me(q1), h2 = B.apply_me(q2);
+    const v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
+    const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
+    drow<T> R, C;
+    decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
+    const double a = 0.5 * x1 * pp.sqrt_s * kMeScale, bm = 0.5 * x2 * pp.sqrt_s * kMeScale;
+    const v4 wp = add(o[4], o[6]), wm = add(o[5], o[7]), t = add(b0, wp), tb = add(b1, wm);
+    double bw = bw_factor(mdot(t, t), pp.m_t, pp.w_t) * bw_factor(mdot(tb, tb), pp.m_t, pp.w_t)
+              * bw_factor(mdot(wp, wp), pp.m_w, pp.w_w) * bw_factor(mdot(wm, wm), pp.m_w, pp.w_w);
+    double me;
+    if constexpr (TTH) {
+      // massless b quarks: (p1 + p2)^2 = 2 p1.p2
+      const double q2h = 2.0 * (q1.e * q2.e - q1.x * q2.x - q1.y * q2.y - q1.z * q2.z);
+      bw *= q2h * bw_factor(q2h, pp.m_h, pp.w_h);
+      me = (double)(gg * gg_tth_sum<T>(R, C, tp, tm, add(h1, h2), a, bm, mt)) * kMeDeg6;
+    } else {
+      me = (double)(gg * gg_ttbb_sum<T>(R, C, tp, tm, h1, h2, a, bm, mt)) * kMeDeg4;
+    }
+    const double shat = x1 * x2 * pp.S;
+    sum += P.e * me * bw * fast_rcp(Eh * 2.0 * shat * x1 * x2);
+  }
+  return sum * (2.0 * pp.inv_sqrt_s * pp.inv_sqrt_s) * pp.f2_parton_const / n;
+}
+
 }  // namespace memk

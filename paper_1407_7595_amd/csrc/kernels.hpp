@@ -296,16 +296,19 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
       tth_load(ev, ev.charge, ch.event, ch.perm, e);
       chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2,
                       [&](const double (&x)[9]) { return tth_integrand<T>(pp, e, x, nullptr); });
-    } else if ((KINDS & kMaskTHL) && pp.kind == kTHL) {
-      F2Event e;
-      f2_load(ev, true, ch.event, ch.perm, e);
-      chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
-                      [&](const double (&x)[8]) { return f2_integrand<T, true>(pp, e, x, nullptr); });
-    } else if ((KINDS & kMaskTBB) && pp.kind == kTBB) {
-      F2Event e;
-      f2_load(ev, false, ch.event, ch.perm, e);
-      chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
-                      [&](const double (&x)[8]) { return f2_integrand<T, false>(pp, e, x, nullptr); });
+    } else if ((KINDS & (kMaskTHL | kMaskTBB)) && (pp.kind == kTHL || pp.kind == kTBB)) {
+      // the chunk's event is the same for the whole workgroup: one copy in
+      // LDS instead of 58 registers per lane across the matrix element
+      __shared__ F2Event sf2;
+      const bool tth = pp.kind == kTHL;
+      if (threadIdx.x == 0) f2_load(ev, tth, ch.event, ch.perm, sf2);
+      __syncthreads();
+      if ((KINDS & kMaskTHL) && tth)
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+                        [&](const double (&x)[8]) { return f2_integrand<T, true>(pp, sf2, x, nullptr); });
+      else if (KINDS & kMaskTBB)
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+                        [&](const double (&x)[8]) { return f2_integrand<T, false>(pp, sf2, x, nullptr); });
     }
     block_reduce2<0>(s1, s2, red);
     __syncthreads();

@@ -149,8 +149,10 @@ static void derive(mem_process_s* p)
       // eight final-state particles: (2 pi)^(4 - 24); all four top and W
       // propagators aligned
       const double base = std::pow(two_pi, -20.0) * (2.0 / pp.S) * 0.5 * 0.25 * std::pow(gw2 / 2.0, 4) * kbw / 256.0;
+      const double pbase = std::pow(gw2 / 2.0, 4) / 256.0;
       if (d.kind == MEM_TTBB_DILEPTON) {
         pp.f2_const = base * gs2 * gs2 * gs2 * gs2;
+        pp.f2_parton_const = pbase * gs2 * gs2 * gs2 * gs2;
       } else {
         const double mhg = d.m_h * d.w_h;
         pp.m_h = d.m_h; pp.w_h = d.w_h;
@@ -160,6 +162,7 @@ static void derive(mem_process_s* p)
         const double mb = d.m_b > 0.0 ? d.m_b : 4.18;
         pp.f2_const = base * gs2 * gs2 * (pp.th1_h - pp.th0_h) / mhg * (d.m_top * d.m_top / v2) * 6.0
                     * (mb * mb / v2);
+        pp.f2_parton_const = pbase * gs2 * gs2 * (d.m_top * d.m_top / v2) * 6.0 * (mb * mb / v2);
       }
     }
   }
@@ -1340,6 +1343,20 @@ __global__ __launch_bounds__(kBlock, MEM_TT_WAVES) void parton_kernel(ProcParams
   w[e] = 0.5 * (w0 + w1);
 }
 
+// Parton-level weights of the four-b dilepton kinds: one thread per event,
+// the 12 or 24 assignments in order (objects: b quarks 0-3, l+, l-, nu,
+// nubar).
+template <class T, bool TTH>
+__global__ __launch_bounds__(kBlock, 1) void f2_parton_kernel(ProcParams pp, EventsView ev, double* __restrict__ w)
+{
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= ev.n_events) return;
+  v4 o[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ev.load(k, e, o[k].e, o[k].x, o[k].y, o[k].z);
+  w[e] = f2_parton<T, TTH>(pp, o);
+}
+
 extern "C" mem_status mem_parton_weights(mem_process p, const mem_events* ev, double* w_out, void* stream)
 {
   if (!p) return fail(MEM_EINVAL, "null argument");
@@ -1348,10 +1365,13 @@ extern "C" mem_status mem_parton_weights(mem_process p, const mem_events* ev, do
   st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
   if (!w_out && ev->n_events > 0) return fail(MEM_EINVAL, "null argument");
-  if (p->desc.kind != MEM_TT_DILEPTON) return fail(MEM_EUNSUPPORTED, "parton-level weights: ttbar dilepton only");
-  if (ev->n_obj < 6) return fail(MEM_EINVAL, "parton-level events need 6 objects");
+  const bool four_b = is_f2(p->desc.kind);
+  if (p->desc.kind != MEM_TT_DILEPTON && !four_b)
+    return fail(MEM_EUNSUPPORTED, "parton-level weights: ttbar dilepton and the four-b dilepton kinds");
+  const int n_obj = four_b ? 8 : 6;
+  if (ev->n_obj < n_obj) return fail(MEM_EINVAL, "parton-level events need 6 objects (8 for the four-b kinds)");
   for (int e = 0; e < ev->n_events; ++e) {
-    st = check_host_event(ev, e, 6);
+    st = check_host_event(ev, e, n_obj);
     if (st != MEM_OK) return st;
   }
   if (ev->n_events == 0) return MEM_OK;
@@ -1366,7 +1386,16 @@ extern "C" mem_status mem_parton_weights(mem_process p, const mem_events* ev, do
     w = wbuf.as<double>();
   }
   dim3 grid((unsigned)((ev->n_events + kBlock - 1) / kBlock));
-  if (p->desc.precision == MEM_FP32)
+  const bool f32 = p->desc.precision == MEM_FP32;
+  if (p->desc.kind == MEM_TTH_DILEPTON && f32)
+    hipLaunchKernelGGL((f2_parton_kernel<float, true>), grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
+  else if (p->desc.kind == MEM_TTH_DILEPTON)
+    hipLaunchKernelGGL((f2_parton_kernel<double, true>), grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
+  else if (p->desc.kind == MEM_TTBB_DILEPTON && f32)
+    hipLaunchKernelGGL((f2_parton_kernel<float, false>), grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
+  else if (p->desc.kind == MEM_TTBB_DILEPTON)
+    hipLaunchKernelGGL((f2_parton_kernel<double, false>), grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
+  else if (f32)
     hipLaunchKernelGGL(parton_kernel<float>, grid, dim3(kBlock), 0, s, p->pp, dev.view, w);
   else
     hipLaunchKernelGGL(parton_kernel<double>, grid, dim3(kBlock), 0, s, p->pp, dev.view, w);

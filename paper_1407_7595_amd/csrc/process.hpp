@@ -51,6 +51,9 @@ struct ProcParams {
   // the (th1 - th0)/(M Gamma) of the aligned propagators (for t tbar H with
   // the Yukawa and H -> b bbar factors; times q2_H per point)
   double f2_const;
+  // their parton-level weights: the couplings and 1/256 (Breit-Wigner
+  // factors per point)
+  double f2_parton_const;
   // parton densities from a grid (null: the toy densities): x f of the
   // 11 flavours in nodes of 12 floats (layout in pdf.hpp), [nq][nx][12],
   // uniform in ln x and ln Q; position = (ln v - v0) * inverse step

@@ -377,6 +377,17 @@ def ttbar_bbbar_dilepton(n_events, seed, rel_sigma=0.15):
     return _four_b_dilepton(rng, n, M, y, parts, rel_sigma)
 
 
+def four_b_partons(d, seed):
+    """parton-level events from a four-b dilepton sample's truth: the four
+    b quarks in random order, then l+, l-, nu, nubar (exact momenta)"""
+    t = d["truth"]
+    rng = _rng(seed)
+    quarks = np.stack([t["b"], t["bb"], t["p1"], t["p2"]], axis=1)
+    order = np.argsort(rng.random((quarks.shape[0], 4)), axis=1)
+    rest = np.stack([t["lp"], t["lm"], t["nu"], t["nub"]], axis=1)
+    return np.concatenate([np.take_along_axis(quarks, order[:, :, None], axis=1), rest], axis=1)
+
+
 def budgets(n_events, seed, lo=16384, hi=262144):
     """per-event point budgets drawn uniformly from [lo, hi)"""
     rng = _rng(seed)

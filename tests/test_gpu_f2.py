@@ -184,3 +184,25 @@ def test_discriminant_and_batches(mem):
     dz = mem.discriminant(o, z).cpu().numpy()
     assert np.all(np.isposinf(dz))
     assert np.all(np.isnan(mem.discriminant(z, z).cpu().numpy()))
+
+
+@pytest.mark.parametrize("which", ["tth", "ttbb"])
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-10)])
+def test_f2_parton_weights(mem, which, precision, tol):
+    """parton level (Sec. 4's Table 2 workload): the mean over the b-quark
+    placements of the complete |M|^2 x densities, against the oracle"""
+    kind, _ = KINDS[which]
+    n = 160 if which == "tth" else 24
+    ev = events.four_b_partons(gen(which, n, 36), 37)
+    p = mem.Process(gpu_kind(mem, which), precision=precision)
+    say(f"{which} parton weights precision={precision}, {n} events")
+    comps = torch.as_tensor(np.ascontiguousarray(ev.transpose(2, 1, 0)), dtype=torch.float64).cuda()
+    got = mem.parton_weights(p, comps).cpu().numpy()
+    want = np.array([oracle.f2_parton_weight(kind, oracle.tt_params(), e) for e in ev])
+    assert np.all(want > 0.0)
+    rel = np.abs(got - want) / want
+    say(f"  worst rel {rel.max():.3g}, median {np.median(rel):.3g}")
+    if precision == 0:
+        assert rel.max() <= tol
+    else:
+        assert np.quantile(rel, 0.99) <= tol and rel.max() <= 3 * tol

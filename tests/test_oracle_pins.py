@@ -1156,3 +1156,23 @@ def test_f2_integrand_truth_and_relabelling(kind):
         want = tuple(sw.get(r, r) for r in rows)
         p2 = [q for q in range(n) if oracle.f2_perm(kind, q) == want][0]
         assert f(po, ev2, p2, x)[0] == v
+
+
+@pytest.mark.parametrize("kind", [oracle.KIND_TTH_LL, oracle.KIND_TTBB_LL])
+def test_f2_parton_weight_invariances(kind):
+    """the parton-level weight (mean over every placement of the four b
+    quarks) does not depend on the order the b quarks are stored in, and is
+    invariant under a rotation about the beam"""
+    po = oracle.tt_params()
+    gen = events.ttbar_higgs_dilepton if kind == oracle.KIND_TTH_LL else events.ttbar_bbbar_dilepton
+    ev = events.four_b_partons(gen(2, 41), 42)
+    c, s = math.cos(0.7), math.sin(0.7)
+    for e in ev:
+        w = oracle.f2_parton_weight(kind, po, e)
+        assert w > 0.0
+        sh = e.copy()
+        sh[:4] = e[[2, 0, 3, 1]]
+        assert oracle.f2_parton_weight(kind, po, sh) == pytest.approx(w, rel=1e-12)
+        rot = e.copy()
+        rot[:, 1], rot[:, 2] = c * e[:, 1] - s * e[:, 2], s * e[:, 1] + c * e[:, 2]
+        assert oracle.f2_parton_weight(kind, po, rot) == pytest.approx(w, rel=1e-9)
