@@ -64,6 +64,21 @@ def test_create_process_validation(mem):
     assert e.value.status == mem.MEM_EUNSUPPORTED
     L = mem.lib()
     assert L.mem_create_process(None, None) == mem.MEM_EINVAL
+    # Sec. 4's four-b dilepton kinds: 8 dimensions, 12 and 24 assignments
+    assert mem.Process(mem.MEM_TTH_DILEPTON).shape() == (8, 12)
+    assert mem.Process(mem.MEM_TTBB_DILEPTON, precision=mem.MEM_FP64).shape() == (8, 24)
+    with pytest.raises(mem.MemError) as e:
+        mem.Process(mem.MEM_TTH_DILEPTON, m_h=0.0)
+    assert e.value.status == mem.MEM_EINVAL
+
+
+def test_discriminant_argument_checks(mem):
+    """mem_discriminant validates before touching the device: nothing to do
+    for n = 0, MEM_EINVAL for n < 0 and for null arrays"""
+    L = mem.lib()
+    assert L.mem_discriminant(None, None, 0, None, None) == mem.MEM_OK
+    assert L.mem_discriminant(None, None, -1, None, None) == mem.MEM_EINVAL
+    assert L.mem_discriminant(None, None, 4, None, None) == mem.MEM_EINVAL
 
 
 def test_transfer_function_validation(mem):
