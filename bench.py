@@ -308,11 +308,13 @@ def f2_parton_leg(mem):
     import torch
     from synth import events
     out = {"events": PARTON_EVENTS}
+    samples, procs = {}, {}
     for name, kind, genf, seed in (("tth", mem.MEM_TTH_DILEPTON, events.ttbar_higgs_dilepton, 30),
                                    ("ttbb", mem.MEM_TTBB_DILEPTON, events.ttbar_bbbar_dilepton, 31)):
         ev = events.four_b_partons(genf(PARTON_EVENTS, SEED_EVENTS + seed), SEED_EVENTS + seed + 1)
         comps = torch.as_tensor(np.ascontiguousarray(ev.transpose(2, 1, 0))).cuda()
         proc = mem.Process(kind, precision=mem.MEM_FP32)
+        samples[name], procs[name] = comps, proc
         w = torch.empty(PARTON_EVENTS, dtype=torch.float64, device="cuda")
         mem.parton_weights(proc, comps, out=w)
         torch.cuda.synchronize()
@@ -324,6 +326,16 @@ def f2_parton_leg(mem):
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"seconds": dt, "events_per_s": PARTON_EVENTS / dt,
                      "assignments": 12 if name == "tth" else 24, "nonzero_fraction": float((w > 0).double().mean())}
+    # D at parton level: both hypotheses on both samples
+    d = {}
+    for name, comps in samples.items():
+        ws = mem.parton_weights(procs["tth"], comps)
+        wb = mem.parton_weights(procs["ttbb"], comps)
+        ok = (ws > 0) & (wb > 0)
+        d[name] = mem.discriminant(ws[ok].contiguous(), wb[ok].contiguous()).cpu().numpy()
+    out["D_median_signal"] = float(np.median(d["tth"]))
+    out["D_median_background"] = float(np.median(d["ttbb"]))
+    out["signal_above_background_median"] = float(np.mean(d["tth"] > np.median(d["ttbb"])))
     log(f"tth vs ttbb parton level: {out}")
     return out
 
