@@ -34,7 +34,7 @@ typedef enum {
   MEM_EINVAL = 1,       /* invalid argument (null pointer, bad size, NaN input) */
   MEM_ENOMEM = 2,       /* device or host allocation failed */
   MEM_EDEVICE = 3,      /* a HIP runtime call failed */
-  MEM_EUNSUPPORTED = 4  /* valid request that this build does not implement */
+  MEM_EUNSUPPORTED = 4  /* valid request that the library does not implement */
 } mem_status;
 
 /* Process kinds (hypotheses).  Object order expected in mem_events:
