@@ -300,6 +300,35 @@ def tth_vs_ttbb_leg(mem):
     return out
 
 
+def f2_oracle_rates(seconds=6.0):
+    """the oracle (FP64 C, one core) on the Sec. 4 workloads, bounded by
+    `seconds` per measurement: parton-level weights per event and integrand
+    evaluations at uniform random points"""
+    import numpy as np
+    import oracle
+    from synth import events
+    po = oracle.tt_params()
+    out = {"cores": 1, "kind": "oracle"}
+    rng = np.random.default_rng(5)
+    for name, kind, genf, fint in (("tth", oracle.KIND_TTH_LL, events.ttbar_higgs_dilepton, oracle.tthll_integrand),
+                                   ("ttbb", oracle.KIND_TTBB_LL, events.ttbar_bbbar_dilepton, oracle.ttbbll_integrand)):
+        d = genf(64, SEED_EVENTS + 40)
+        ev = events.four_b_partons(d, SEED_EVENTS + 41)
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds / 2 and n < len(ev):
+            oracle.f2_parton_weight(kind, po, ev[n])
+            n += 1
+        par = n / (time.perf_counter() - t0)
+        n, t0 = 0, time.perf_counter()
+        n_perm = 12 if name == "tth" else 24
+        while time.perf_counter() - t0 < seconds / 2:
+            fint(po, d["obs"][n % 64], n % n_perm, rng.random(8))
+            n += 1
+        out[name] = {"parton_events_per_s": par, "integrand_evals_per_s": n / (time.perf_counter() - t0)}
+    log(f"tth vs ttbb oracle: {out}")
+    return out
+
+
 def f2_parton_leg(mem):
     """Sec. 4's parton-level timing (its Table 2): 10^5 t tbar H and 10^5
     t tbar b bbar dilepton events at parton level, every placement of the
@@ -446,6 +475,8 @@ def main():
     f2 = None if args.no_f2 else tth_vs_ttbb_leg(mem)
     if f2 is not None:
         f2["parton_level"] = f2_parton_leg(mem)
+        if not args.no_cpu:
+            f2["oracle"] = f2_oracle_rates()
     flow = None
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)
