@@ -1176,3 +1176,35 @@ def test_f2_parton_weight_invariances(kind):
         rot = e.copy()
         rot[:, 1], rot[:, 2] = c * e[:, 1] - s * e[:, 2], s * e[:, 1] + c * e[:, 2]
         assert oracle.f2_parton_weight(kind, po, rot) == pytest.approx(w, rel=1e-9)
+
+
+def test_four_b_generators():
+    """Sec. 4's synthetic samples: no recoil (the partons' transverse
+    momenta sum to zero), the t tbar H sample's Higgs pair at 125 GeV, the
+    t tbar b bbar pair above its 20 GeV floor, the measured jets along the
+    quarks and the truth slots a permutation"""
+    for gen, key in ((events.ttbar_higgs_dilepton, "tth"), (events.ttbar_bbbar_dilepton, "ttbb")):
+        d = gen(200, 51)
+        t = d["truth"]
+        parts = [t[k] for k in ("b", "bb", "p1", "p2", "lp", "lm", "nu", "nub")]
+        P = sum(parts)
+        assert np.max(np.abs(P[:, 1:3])) < 1e-8 * np.max(P[:, 0])
+        q = t["p1"] + t["p2"]
+        m = np.sqrt(np.maximum(q[:, 0] ** 2 - np.sum(q[:, 1:] ** 2, axis=1), 0.0))
+        if key == "tth":
+            assert np.allclose(m, 125.0, rtol=1e-9)
+        else:
+            assert np.all(m > 20.0 - 1e-9)
+        obs = d["obs"]
+        assert obs.shape == (200, 6, 4)
+        for e in range(5):
+            slot = t["slot"][e]
+            assert sorted(slot) == [0, 1, 2, 3]
+            for quark, row in zip((t["b"][e], t["bb"][e], t["p1"][e], t["p2"][e]), slot):
+                j = obs[e, row]
+                cosang = (j[1:] @ quark[1:]) / (np.linalg.norm(j[1:]) * np.linalg.norm(quark[1:]))
+                assert cosang == pytest.approx(1.0, abs=1e-12)
+        pe = events.four_b_partons(d, 52)
+        assert pe.shape == (200, 8, 4)
+        assert np.allclose(np.sort(pe[:, :4, 0], axis=1),
+                           np.sort(np.stack([t["b"][:, 0], t["bb"][:, 0], t["p1"][:, 0], t["p2"][:, 0]], 1), axis=1))
