@@ -296,8 +296,10 @@ def toy_pdf_table(nx, nq, bounds):
 
 def parton_weights(process, comps, out=None, stream=None):
     """mem_parton_weights: comps [4, 6, n_events] float64 (b, bbar, l+, l-,
-    nu, nubar) on the device or the host; returns the weights [n_events]
-    float64 on the same device (or writes into `out`)."""
+    nu, nubar) for ttbar dilepton, [4, 8, n_events] (four b quarks, l+, l-,
+    nu, nubar) for the four-b dilepton kinds, on the device or the host;
+    returns the weights [n_events] float64 on the same device (or writes
+    into `out`)."""
     import torch
     ev = events_struct(comps, None)
     w = torch.empty(ev.n_events, dtype=torch.float64, device=comps.device) if out is None else out
