@@ -22,7 +22,7 @@ For each configuration, on seeded synthetic events:
   budget (integrals are independent, so the rate carries over);
   events/s at the configured budget derived from it.
 
-    python paper_1407_7595_amd/config_table.py [--out FILE.json] [--quick]
+    python measure/config_table.py [--out FILE.json] [--quick]
 
 Prints a markdown table and one JSON line.
 """

@@ -3,7 +3,7 @@
 whose name contains one of the given substrings, the number of dispatches
 and, per counter, the sum over dispatches and the mean per dispatch.
 
-    python paper_1407_7595_amd/pmc_summary.py CSV [KERNEL_SUBSTRING ...]
+    python measure/pmc_summary.py CSV [KERNEL_SUBSTRING ...]
 
 With no substrings every kernel is listed.
 """

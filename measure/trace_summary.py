@@ -2,7 +2,7 @@
 `rocprofv3 --kernel-trace --stats -d DIR -o NAME -- ...`): per-kernel totals
 and, for one kernel, the durations of its first N dispatches.
 
-    python paper_1407_7595_amd/trace_summary.py DB [KERNEL_SUBSTRING N]
+    python measure/trace_summary.py DB [KERNEL_SUBSTRING N]
 """
 import sqlite3
 import sys

@@ -157,6 +157,8 @@ def _declare(L):
         "or_vegas_iteration": (None, [I, P, P, I, U64, U32, U32, I64, P, P, P, P]),
         "or_weight_at": (D, [I, P, P, I, P, P]),
         "or_integrate_events": (None, [I, P, P, I, I, U64, I64, I, D, D, P, P, P]),
+        "or_integrate_events_iters": (None, [I, P, P, I, I, U64, I64, I, P, D, D, P, P, P]),
+        "or_set_threads": (None, [I]), "or_max_threads": (I, []),
         "or_dims": (I, [I]), "or_nperm": (I, [I]),
         "or_bw_map": (D, [D, D, D, D, D, P]),
         "or_gauss_tf": (D, [D, D, D]),
@@ -350,14 +352,32 @@ def weight_at(kind, p, ev, perm, grid, u):
 
 
 def integrate_events(kind, p, events, seed, n_points, n_iter, alpha=1.5, sigma_norm=0.0):
+    """P, err, status per event; n_iter is one count for every event or an
+    array with one count per event"""
     ev = _f64(events)
     n_events, n_obj = ev.shape[0], ev.shape[1]
     P = np.zeros(n_events)
     err = np.zeros(n_events)
     st = np.zeros(n_events, dtype=np.int32)
-    lib().or_integrate_events(kind, ctypes.byref(p), _ptr(ev), n_events, n_obj, seed,
-                              n_points, n_iter, alpha, sigma_norm, _ptr(P), _ptr(err), _ptr(st))
+    if np.ndim(n_iter) == 0:
+        lib().or_integrate_events(kind, ctypes.byref(p), _ptr(ev), n_events, n_obj, seed,
+                                  n_points, int(n_iter), alpha, sigma_norm, _ptr(P), _ptr(err), _ptr(st))
+    else:
+        its = np.ascontiguousarray(n_iter, dtype=np.int32)
+        assert its.shape == (n_events,)
+        lib().or_integrate_events_iters(kind, ctypes.byref(p), _ptr(ev), n_events, n_obj, seed,
+                                        n_points, 0, its.ctypes.data_as(ctypes.c_void_p), alpha, sigma_norm,
+                                        _ptr(P), _ptr(err), _ptr(st))
     return P, err, st
+
+
+def set_threads(n):
+    """OpenMP threads of later oracle calls (n < 1: the runtime default)"""
+    lib().or_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().or_max_threads())
 
 
 def _vec(a):

@@ -12,6 +12,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static double integrand(int kind, const or_params* p, const double* ev, int perm, const double* x)
 {
@@ -105,10 +108,13 @@ void or_integrate_one(int kind, const or_params* p, const double* ev, int perm,
   free(grid); free(bins); free(Is); free(Vs);
 }
 
-void or_integrate_events(int kind, const or_params* p, const double* events,
-                         int n_events, int n_obj, uint64_t seed, int64_t n_points,
-                         int n_iter, double alpha, double sigma_norm,
-                         double* P, double* err, int32_t* status)
+/* Events integrated independently; event e runs n_iter_ev[e] iterations
+ * when that array is given, else n_iter.  OpenMP over (event, assignment)
+ * integrals. */
+void or_integrate_events_iters(int kind, const or_params* p, const double* events,
+                               int n_events, int n_obj, uint64_t seed, int64_t n_points,
+                               int n_iter, const int32_t* n_iter_ev, double alpha, double sigma_norm,
+                               double* P, double* err, int32_t* status)
 {
   int np = or_nperm(kind);
   int64_t per = (n_points + np - 1) / np;   /* points per permutation */
@@ -117,8 +123,9 @@ void or_integrate_events(int kind, const or_params* p, const double* events,
   #pragma omp parallel for schedule(dynamic, 1)
   for (int i = 0; i < n_int; ++i) {
     int e = i / np, perm = i % np;
+    int it = n_iter_ev ? n_iter_ev[e] : n_iter;
     or_integrate_one(kind, p, events + (size_t)e * n_obj * 4, perm, seed, (uint32_t)e,
-                     per, n_iter, alpha, NULL, NULL, NULL, &r[i]);
+                     per, it, alpha, NULL, NULL, NULL, &r[i]);
   }
   double norm = sigma_norm > 0.0 ? 1.0 / sigma_norm : 1.0;
   for (int e = 0; e < n_events; ++e) {
@@ -134,4 +141,33 @@ void or_integrate_events(int kind, const or_params* p, const double* events,
     status[e] = bad ? 3 : (s == 0.0 ? 1 : 0);
   }
   free(r);
+}
+
+void or_integrate_events(int kind, const or_params* p, const double* events,
+                         int n_events, int n_obj, uint64_t seed, int64_t n_points,
+                         int n_iter, double alpha, double sigma_norm,
+                         double* P, double* err, int32_t* status)
+{
+  or_integrate_events_iters(kind, p, events, n_events, n_obj, seed, n_points, n_iter, NULL, alpha,
+                            sigma_norm, P, err, status);
+}
+
+/* OpenMP thread count of later calls (n < 1: the runtime's default) and the
+ * count a parallel region would use now. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

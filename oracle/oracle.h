@@ -251,6 +251,12 @@ void or_integrate_events(int kind, const or_params* p, const double* events,
                          int n_events, int n_obj, uint64_t seed, int64_t n_points,
                          int n_iter, double alpha, double sigma_norm,
                          double* P, double* err, int32_t* status);
+void or_integrate_events_iters(int kind, const or_params* p, const double* events,
+                               int n_events, int n_obj, uint64_t seed, int64_t n_points,
+                               int n_iter, const int32_t* n_iter_ev, double alpha, double sigma_norm,
+                               double* P, double* err, int32_t* status);
+void or_set_threads(int n);
+int or_max_threads(void);
 int or_dims(int kind);
 int or_nperm(int kind);
 
