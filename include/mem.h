@@ -167,14 +167,16 @@ typedef struct mem_flow_s* mem_flow;
  *                  integral draws n_points/n_perm base points z from the
  *                  point stream (counter blocks perm*16 + 8 + d/2,
  *                  iteration j), maps them to x = T^-1(z; c) and weighs
- *                  them by w = f(x)/q(x|c); all batches of an integral are
- *                  pooled into one mean and one variance.  After the first
- *                  batch every permutation must have ESS/N =
- *                  (sum w)^2/(N sum w^2) >= ess_threshold, else the whole
- *                  event is integrated by VEGAS with the same arguments
- *                  (status MEM_EV_FLOW_FALLBACK when that converges).  In
- *                  target mode the flow's stopping test runs from the
- *                  second batch on.
+ *                  them by w = f(x)/q(x|c).  The first batch is a pilot:
+ *                  every permutation must have ESS/N =
+ *                  (sum w)^2/(N sum w^2) >= ess_threshold on it, else the
+ *                  whole event is integrated by VEGAS with the same
+ *                  arguments (status MEM_EV_FLOW_FALLBACK when that
+ *                  converges); its weights do not enter the estimate
+ *                  (selected on them, it would bias it).  Batches 2, 3, ...
+ *                  of an integral are pooled into one mean and one
+ *                  variance; in target mode the stopping test runs after
+ *                  each of them.
  *  ess_threshold   flow fallback threshold on ESS/N (0: 0.3)
  *  allocation      how an event's points are shared among its permutations
  *                  (VEGAS, a flow's VEGAS fallback included; the flow's own
@@ -191,8 +193,56 @@ typedef struct mem_flow_s* mem_flow;
  *                  to that cap.  Same point stream (point k of an integral is
  *                  the same u in either mode); estimates differ from equal
  *                  splitting by MC fluctuation only.  Other values:
- *                  MEM_EINVAL.                                              */
+ *                  MEM_EINVAL.
+ *  weights_out     optional device pointer [iterations][weights_stride]
+ *                  doubles: the weight w = f(x) J(x) of every point the
+ *                  integrand kernel evaluates for integral weights_integral
+ *                  (integral index = sum of the earlier events'
+ *                  permutation counts + permutation), at
+ *                  [iteration][point index k].  Entries an iteration does
+ *                  not evaluate are left as they were.  weights_stride must
+ *                  be at least the integral's points per iteration (its
+ *                  equal share, times min(n_perm, 4) under Neyman
+ *                  allocation).  VEGAS only (MEM_EUNSUPPORTED with a flow).
+ *  hooks, hook_event  test hooks (MEM_HOOK_*; 0 = none)
+ *  checkpoint      NULL, or a handle from mem_checkpoint_create (VEGAS only;
+ *                  MEM_EUNSUPPORTED with a flow).  An empty handle: the
+ *                  integration starts afresh.  A handle holding the state
+ *                  of an earlier call over the same events, processes,
+ *                  n_points, seed, alpha and allocation: the integration
+ *                  resumes from it (grids, cumulative sums, iteration
+ *                  count, retired events, allocations) and runs n_iter
+ *                  more iterations (fixed mode) or continues to the target
+ *                  or to max_iter iterations in total (target mode); the
+ *                  result equals that of one uninterrupted call bit for
+ *                  bit.  A handle whose state does not match: MEM_EINVAL.
+ *                  In every case the handle holds the final state when the
+ *                  call returns MEM_OK (unchanged otherwise).
+ *  alloc_fn, free_fn, alloc_user  optional allocator for the call's
+ *                  device work buffers (both or neither); NULL: hipMalloc
+ *                  and hipFree.                                           */
 enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
+
+/* Per-integral state of a VEGAS integration, owned by the library (see
+ * mem_checkpoint_create). */
+typedef struct mem_checkpoint_s* mem_checkpoint;
+
+/* Device memory for the work buffers of a call, supplied by the caller
+ * (for instance a caching allocator).  alloc_fn returns `bytes` of device
+ * memory on the current device usable on `stream` (NULL: failure, the call
+ * returns MEM_ENOMEM); free_fn gets back every block alloc_fn returned,
+ * with its size, once the call's work on `stream` has completed and before
+ * the call returns.  `user` is passed through. */
+typedef void* (*mem_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*mem_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
+/* Test hooks (mem_integrate_opts.hooks): conditions forced from the host so
+ * that failure handling can be exercised with valid inputs.
+ *  MEM_HOOK_NONFINITE  every integrand weight of event hook_event is
+ *                      replaced by a quiet NaN (VEGAS: the event ends with
+ *                      status MEM_EV_NONFINITE; its grids stay unrefined) */
+enum { MEM_HOOK_NONFINITE = 1 };
+
 typedef struct {
   uint64_t seed;
   double alpha;
@@ -209,6 +259,15 @@ typedef struct {
   mem_flow flow;
   double ess_threshold;
   int32_t allocation;
+  double* weights_out;
+  int64_t weights_stride;
+  int32_t weights_integral;
+  uint32_t hooks;
+  int32_t hook_event;
+  mem_checkpoint checkpoint;
+  mem_alloc_fn alloc_fn;
+  mem_free_fn free_fn;
+  void* alloc_user;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */
@@ -291,6 +350,19 @@ mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, in
                                 const int64_t* n_points, int32_t n_np, int32_t n_iter,
                                 const mem_integrate_opts* opt,
                                 double* p_out, double* err_out, int32_t* status_out);
+
+/* Checkpoints of VEGAS integrations (per-integral grids, cumulative sums,
+ * iteration counter, retired events and allocations, held in host memory).
+ * create: an empty handle.  save: write the state to a file (MEM_EINVAL for
+ * an empty handle or an unwritable path).  load: a new handle from a file
+ * written by save (MEM_EINVAL for an unreadable or malformed file).  A
+ * handle is used by one call at a time. */
+mem_status mem_checkpoint_create(mem_checkpoint* out);
+void mem_checkpoint_destroy(mem_checkpoint c);
+mem_status mem_checkpoint_save(mem_checkpoint c, const char* path);
+mem_status mem_checkpoint_load(const char* path, mem_checkpoint* out);
+/* Iterations the state holds (0 for an empty handle). */
+mem_status mem_checkpoint_iterations(mem_checkpoint c, int32_t* n_iter);
 
 /* ---- autotuner ----
  * Points per work-queue chunk (the tile one workgroup integrates) trade

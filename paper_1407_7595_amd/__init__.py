@@ -30,7 +30,8 @@ EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_proc
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
            "mem_process_chunk_points", "mem_parton_weights", "mem_set_pdf_grid", "mem_toy_pdf_table",
-           "mem_discriminant", "mem_status_string", "mem_last_error")
+           "mem_discriminant", "mem_checkpoint_create", "mem_checkpoint_destroy", "mem_checkpoint_save",
+           "mem_checkpoint_load", "mem_checkpoint_iterations", "mem_status_string", "mem_last_error")
 
 
 class ProcessDesc(ctypes.Structure):
@@ -59,7 +60,32 @@ class IntegrateOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("stream", ctypes.c_void_p), ("outputs_on_device", ctypes.c_int32),
                 ("iter_out", ctypes.c_void_p), ("grid_out", ctypes.c_void_p), ("n_iter_out", ctypes.c_void_p),
                 ("timing_out", ctypes.c_void_p), ("chunk_points", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("flow", ctypes.c_void_p), ("ess_threshold", ctypes.c_double), ("allocation", ctypes.c_int32)]
+                ("flow", ctypes.c_void_p), ("ess_threshold", ctypes.c_double), ("allocation", ctypes.c_int32),
+                ("weights_out", ctypes.c_void_p), ("weights_stride", ctypes.c_int64),
+                ("weights_integral", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
+                ("checkpoint", ctypes.c_void_p), ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
+                ("alloc_user", ctypes.c_void_p)]
+
+
+MEM_HOOK_NONFINITE = 1
+
+# allocator hook signatures (mem_alloc_fn, mem_free_fn)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, user):
+    import torch
+    return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+
+
+def _torch_free(ptr, nbytes, stream, user):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# the library's work buffers from PyTorch's caching allocator
+TORCH_ALLOCATOR = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
 
 
 _lib = None
@@ -100,6 +126,11 @@ def lib():
             "mem_autotune": (I32, [P, P, I64, P, I32, ctypes.c_char_p, P, P]),
             "mem_tuning_load": (I32, [P, ctypes.c_char_p, ctypes.c_char_p, P]),
             "mem_process_chunk_points": (I32, [P, P]),
+            "mem_checkpoint_create": (I32, [P]),
+            "mem_checkpoint_destroy": (None, [P]),
+            "mem_checkpoint_save": (I32, [P, ctypes.c_char_p]),
+            "mem_checkpoint_load": (I32, [ctypes.c_char_p, P]),
+            "mem_checkpoint_iterations": (I32, [P, P]),
             "mem_status_string": (ctypes.c_char_p, [I32]),
             "mem_last_error": (I32, [ctypes.c_char_p, ctypes.c_size_t]),
         }
@@ -221,12 +252,17 @@ def to_components(obs):
 def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=1.5, target_rel_err=0.0,
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
-                     allocation=0):
+                     allocation=0, weights_out=None, weights_integral=0, hooks=0, hook_event=0,
+                     checkpoint=None, allocator=None):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
     flow: optional Flow (importance sampling from it, VEGAS fallback);
-    allocation: MEM_ALLOC_EQUAL or MEM_ALLOC_NEYMAN across permutations.
+    allocation: MEM_ALLOC_EQUAL or MEM_ALLOC_NEYMAN across permutations;
+    weights_out: optional float64 device tensor [iterations, stride] for
+    the weights of integral weights_integral; hooks / hook_event: test
+    hooks (MEM_HOOK_*); checkpoint: optional Checkpoint; allocator:
+    None (hipMalloc), TORCH_ALLOCATOR, or a pair (ALLOC_FN, FREE_FN).
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
@@ -248,12 +284,42 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         n_iter_out.data_ptr() if n_iter_out is not None else None,
                         ctypes.cast(timing, ctypes.c_void_p) if timing is not None else None,
                         chunk_points, use_graph, flow.handle.value if flow is not None else None, ess_threshold,
-                        allocation)
+                        allocation,
+                        weights_out.data_ptr() if weights_out is not None else None,
+                        weights_out.shape[-1] if weights_out is not None else 0, weights_integral, hooks, hook_event,
+                        checkpoint.handle.value if checkpoint is not None else None,
+                        ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
+                        ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None)
     _check(lib().mem_integrate_events(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                       ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
                                       ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
            "mem_integrate_events")
     return P, err, status
+
+
+class Checkpoint:
+    """mem_checkpoint: the state of a VEGAS integration between calls"""
+
+    def __init__(self, path=None):
+        self.handle = ctypes.c_void_p()
+        if path is None:
+            _check(lib().mem_checkpoint_create(ctypes.byref(self.handle)), "mem_checkpoint_create")
+        else:
+            _check(lib().mem_checkpoint_load(os.fsencode(path), ctypes.byref(self.handle)), "mem_checkpoint_load")
+
+    def save(self, path):
+        _check(lib().mem_checkpoint_save(self.handle, os.fsencode(path)), "mem_checkpoint_save")
+
+    @property
+    def iterations(self):
+        n = ctypes.c_int32()
+        _check(lib().mem_checkpoint_iterations(self.handle, ctypes.byref(n)), "mem_checkpoint_iterations")
+        return n.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.mem_checkpoint_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
 
 
 def uniforms(seed, it, event, perm, D, n, out, stream=None):

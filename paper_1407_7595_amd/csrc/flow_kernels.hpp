@@ -206,8 +206,12 @@ struct FlowIntegral {
 };
 
 // Fold one batch into every active integral (chunk partials in a fixed
-// order).  After the first batch: ESS/N = (sum w)^2 / (N sum w^2); below
-// the threshold the integral is handed to VEGAS.
+// order).  The first batch is a pilot: its ESS/N = (sum w)^2 / (N sum w^2)
+// decides whether the integral stays with the proposal (below the threshold
+// it is handed to VEGAS), and its sums are left out of the estimate.  A
+// batch that passed the test is more likely to have missed the large
+// weights, so pooling it would bias the kept integrals low; the later
+// batches are independent of the decision.
 __global__ void flow_finish_kernel(const FlowIntegral* __restrict__ ints, const double* __restrict__ parts,
                                    double* __restrict__ state, int32_t* __restrict__ active,
                                    const uint32_t* __restrict__ iter_p, int n_int, double ess_thr,
@@ -221,14 +225,15 @@ __global__ void flow_finish_kernel(const FlowIntegral* __restrict__ ints, const 
   double* st = state + (int64_t)ig * FS_SIZE;
   const double N = (double)in.n_points;
   if (!isfinite(s1) || !isfinite(s2)) st[FS_NONFINITE] = 1.0;
-  st[FS_S1] += s1;
-  st[FS_S2] += s2;
-  st[FS_N] += N;
   const uint32_t iter = *iter_p;
   if (iter == 0) {
     const double ess = s2 > 0.0 ? s1 * s1 / (N * s2) : 0.0;
     st[FS_ESS] = ess;
     if (!(ess >= ess_thr)) { st[FS_FALLBACK] = 1.0; active[ig] = 0; }
+  } else {
+    st[FS_S1] += s1;
+    st[FS_S2] += s2;
+    st[FS_N] += N;
   }
   if (iter_out) {
     const double I = s1 / N;
@@ -238,8 +243,9 @@ __global__ void flow_finish_kernel(const FlowIntegral* __restrict__ ints, const 
   }
 }
 
-// Pooled estimate of one flow integral: every batch is drawn from the same
-// proposal, so all points enter one mean and one variance.
+// Pooled estimate of one flow integral: every batch after the pilot is
+// drawn from the same proposal, so their points enter one mean and one
+// variance.
 __device__ __forceinline__ void flow_estimate(const double* st, double& I, double& var)
 {
   const double N = st[FS_N];

@@ -65,6 +65,16 @@ struct IntegralDesc {
   int64_t chunk0;     // first chunk
 };
 
+// Checks: the weights of one integral recorded per iteration, and a forced
+// non-finite weight for one event (the host-forced failure of the status
+// path).  Zero-initialised = off.
+struct QueueHooks {
+  double* wout;        // [iteration][w_stride] weights of integral w_int (null: off)
+  int64_t w_stride;
+  int32_t w_int;
+  int32_t nan_event;   // event whose weights become NaN (-1: none)
+};
+
 // per-integral running state
 enum { ST_WSUM = 0, ST_WISUM, ST_ISUM, ST_NITER, ST_NONFINITE, ST_LAST_I, ST_LAST_V, ST_SIZE = 8 };
 
@@ -85,9 +95,12 @@ __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)
 // Points [start, start + count) of one chunk: sum w, sum w^2 and the
 // per-bin sums of w^2 (LDS atomics into the calling wavefront's own bins).
 // F(x) is the integrand.
+// wrec: null, or where point k's weight is recorded (wrec[k]); poison:
+// every weight becomes NaN (test hook).
 template <int D, class F>
 __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
-                                             double* sbins, double& s1, double& s2, F&& f)
+                                             double* sbins, double& s1, double& s2, double* wrec, bool poison,
+                                             F&& f)
 {
   for (int k = threadIdx.x; k < ch.count; k += kBlock) {
     double u[D], x[D];
@@ -95,6 +108,8 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
     point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
     double jac = vegas_map<D>(sgrid, u, x, bin);
     double w = f(x) * jac;
+    if (poison) w = __builtin_nan("");
+    if (wrec) wrec[k] = w;
     s1 += w;
     s2 += w * w;
     if (w != 0.0) {
@@ -119,8 +134,8 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
 constexpr int kTTRec = 30;       // DilepPoint (28 doubles) + the two jet energies
 template <class T, bool ON>
 __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
-                                                double* sbins, double& s1, double& s2, const ProcParams& pp,
-                                                const TTEvent& ev)
+                                                double* sbins, double& s1, double& s2, double* wrec, bool poison,
+                                                const ProcParams& pp, const TTEvent& ev)
 {
   if constexpr (ON) {
     __shared__ double srec[kBlock / kWave][kTTRec][kWave];
@@ -203,7 +218,9 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
       for (int j = 0; j < nr; ++j) acc += qres[off + j];
       wave_sync();     // the next round overwrites the queue
       if (live) {
-        const double w = tt_point<T>(pp, ev, acc, m.jetf) * jac;
+        double w = tt_point<T>(pp, ev, acc, m.jetf) * jac;
+        if (poison) w = __builtin_nan("");
+        if (wrec) wrec[k] = w;
         s1 += w;
         s2 += w * w;
         if (w != 0.0) {
@@ -237,7 +254,7 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
     const ProcParams* __restrict__ procs, EventsView ev, const Chunk* __restrict__ chunks, int64_t n_chunks,
     const IntegralDesc* __restrict__ ints, const double* __restrict__ grids, const int32_t* __restrict__ active,
     uint64_t seed, Control* __restrict__ ctl, uint32_t* __restrict__ head, double* __restrict__ parts,
-    const int64_t* __restrict__ alloc)
+    const int64_t* __restrict__ alloc, QueueHooks hk)
 {
   __shared__ double sgrid[kMaxDims * (kBins + 1)];
   // per-wavefront bin sums, combined in wavefront order: the result does not
@@ -271,10 +288,12 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
     const ProcParams& pp = procs[ch.proc];
     double* wbins = sbins[threadIdx.x / kWave];
     double s1 = 0.0, s2 = 0.0;
+    double* wrec = (hk.wout && ch.integral == hk.w_int) ? hk.wout + (int64_t)iter * hk.w_stride + ch.start : nullptr;
+    const bool poison = ch.event == hk.nan_event;
     if ((KINDS & kMaskDY) && pp.kind == kDY) {
       DYEvent e;
       dy_load(ev, ch.event, e);
-      chunk_points<2>(ch, seed, iter, sgrid, wbins, s1, s2,
+      chunk_points<2>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
                       [&](const double (&x)[2]) { return dy_integrand(pp, e, x); });
     } else if ((KINDS & kMaskTT) && pp.kind == kTT) {
       TTEvent e;
@@ -282,19 +301,19 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
       // launches that also carry t tbar H chunks run at two waves per SIMD,
       // where the 80 KB of queues would not fit twice: per-lane root loop
       if constexpr ((KINDS & kMaskTTH) == 0)
-        chunk_points_tt<T, (KINDS & kMaskTT) != 0>(ch, seed, iter, sgrid, wbins, s1, s2, pp, e);
+        chunk_points_tt<T, (KINDS & kMaskTT) != 0>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, pp, e);
       else
-        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
                         [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskSL) && pp.kind == kSL) {
       SLEvent e;
       sl_load(ev, ev.charge, ch.event, ch.perm, e);
-      chunk_points<7>(ch, seed, iter, sgrid, wbins, s1, s2,
+      chunk_points<7>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
                       [&](const double (&x)[7]) { return sl_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskTTH) && pp.kind == kTTH) {
       TTHEvent e;
       tth_load(ev, ev.charge, ch.event, ch.perm, e);
-      chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2,
+      chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
                       [&](const double (&x)[9]) { return tth_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & (kMaskTHL | kMaskTBB)) && (pp.kind == kTHL || pp.kind == kTBB)) {
       // the chunk's event is the same for the whole workgroup: one copy in
@@ -304,10 +323,10 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
       if (threadIdx.x == 0) f2_load(ev, tth, ch.event, ch.perm, sf2);
       __syncthreads();
       if ((KINDS & kMaskTHL) && tth)
-        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
                         [&](const double (&x)[8]) { return f2_integrand<T, true>(pp, sf2, x, nullptr); });
       else if (KINDS & kMaskTBB)
-        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2,
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
                         [&](const double (&x)[8]) { return f2_integrand<T, false>(pp, sf2, x, nullptr); });
     }
     block_reduce2<0>(s1, s2, red);

@@ -683,10 +683,73 @@ __global__ __launch_bounds__(kBlock) void refine_only_kernel(const double* __res
 // ------------------------------------------------------------ helpers ----
 namespace {
 
+// Device memory of one call's work buffers: hipMalloc / hipFree, the
+// caller's allocator hook, or a fixed arena handed in by the caller of the
+// no-allocation entry point.  Blocks go back (hook, hipFree) when the
+// workspace is destroyed, after the call has synchronised its stream.
+class Workspace {
+ public:
+  Workspace() = default;
+  Workspace(mem_alloc_fn a, mem_free_fn f, void* user, hipStream_t s) : afn_(a), ffn_(f), user_(user), s_(s) {}
+  Workspace(char* arena, size_t cap) : arena_(arena), cap_(cap) {}
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  ~Workspace()
+  {
+    // a call that returns early may still have work queued on the caller's
+    // stream: the hook's memory may be handed out again at once
+    if (afn_ && !blocks_.empty()) (void)hipStreamSynchronize(s_);
+    for (auto& b : blocks_) {
+      if (afn_) ffn_(b.first, b.second, (void*)s_, user_);
+      else (void)hipFree(b.first);
+    }
+  }
+  bool arena() const { return arena_ != nullptr; }
+  size_t used() const { return used_; }
+  hipError_t get(void** p, size_t bytes)
+  {
+    bytes = bytes ? (bytes + 255) / 256 * 256 : 256;
+    *p = nullptr;
+    if (arena_) {
+      if (used_ + bytes > cap_) return hipErrorOutOfMemory;
+      *p = arena_ + used_;
+      used_ += bytes;
+      return hipSuccess;
+    }
+    if (afn_) {
+      void* q = afn_(bytes, (void*)s_, user_);
+      if (!q) return hipErrorOutOfMemory;
+      *p = q;
+    } else {
+      hipError_t e = hipMalloc(p, bytes);
+      if (e != hipSuccess) return e;
+    }
+    blocks_.emplace_back(*p, bytes);
+    used_ += bytes;
+    return hipSuccess;
+  }
+
+ private:
+  mem_alloc_fn afn_ = nullptr;
+  mem_free_fn ffn_ = nullptr;
+  void* user_ = nullptr;
+  hipStream_t s_ = nullptr;
+  char* arena_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  std::vector<std::pair<void*, size_t>> blocks_;
+};
+
+// A device buffer: its own hipMalloc block, or a block of a workspace
+// (released with the workspace).
 struct DevBuf {
   void* p = nullptr;
-  ~DevBuf() { if (p) (void)hipFree(p); }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 8); }
+  Workspace* w = nullptr;
+  DevBuf() = default;
+  explicit DevBuf(Workspace* ws) : w(ws) {}
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { if (p && !w) (void)hipFree(p); }
+  hipError_t alloc(size_t bytes) { return w ? w->get(&p, bytes) : hipMalloc(&p, bytes ? bytes : 8); }
   template <class X> X* as() const { return (X*)p; }
 };
 
@@ -741,6 +804,8 @@ mem_status check_host_event(const mem_events* ev, int e, int n_obj_used)
 struct DevEvents {
   DevBuf buf, cbuf;
   EventsView view{};
+  DevEvents() = default;
+  explicit DevEvents(Workspace* w) : buf(w), cbuf(w) {}
   mem_status make(const mem_events* ev, hipStream_t s)
   {
     view.n_events = ev->n_events;
@@ -773,7 +838,7 @@ struct DevEvents {
 // The queue kernel instance for a precision and a set of kinds.
 typedef void (*QueueKernel)(const ProcParams*, EventsView, const Chunk*, int64_t, const IntegralDesc*,
                             const double*, const int32_t*, uint64_t, Control*, uint32_t*, double*,
-                            const int64_t*);
+                            const int64_t*, QueueHooks);
 template <class T>
 QueueKernel queue_kernel_for(int mask)
 {
@@ -815,13 +880,129 @@ struct Group {
 
 }  // namespace
 
+// ------------------------------------------------------ checkpoints ----
+// The state of a VEGAS integration between calls, in host memory: what
+// identifies the integration (so that a resume can be refused when the
+// call differs) and everything the device iterates on.
+struct mem_checkpoint_s {
+  bool has = false;
+  // identity
+  int32_t n_ev = 0, n_int = 0, allocation = 0;
+  uint64_t seed = 0;
+  double alpha = 0.0;
+  std::vector<uint64_t> ev_key;       // per event: hash of its process's description and TFs
+  std::vector<int64_t> int_key;       // per integral: event, perm, dims, points per iteration
+  // state
+  uint32_t iter = 0;
+  std::vector<double> grids, state;
+  std::vector<int32_t> active, done;
+  std::vector<int64_t> alloc;
+};
+
+namespace {
+
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull)
+{
+  const unsigned char* c = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+uint64_t process_key(const mem_process_s* p)
+{
+  uint64_t h = fnv1a(&p->desc, sizeof(p->desc));
+  h = fnv1a(p->tf, sizeof(p->tf), h);
+  h = fnv1a(&p->pdf_dev, sizeof(p->pdf_dev), h);
+  return h;
+}
+
+}  // namespace
+
+extern "C" mem_status mem_checkpoint_create(mem_checkpoint* out)
+{
+  if (!out) return fail(MEM_EINVAL, "null argument");
+  *out = new (std::nothrow) mem_checkpoint_s();
+  return *out ? MEM_OK : fail(MEM_ENOMEM, "checkpoint allocation failed");
+}
+
+extern "C" void mem_checkpoint_destroy(mem_checkpoint c) { delete c; }
+
+extern "C" mem_status mem_checkpoint_iterations(mem_checkpoint c, int32_t* n_iter)
+{
+  if (!c || !n_iter) return fail(MEM_EINVAL, "null argument");
+  *n_iter = c->has ? (int32_t)c->iter : 0;
+  return MEM_OK;
+}
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'M', 'E', 'M', 'C', 'K', 'P', 'T', '1'};
+
+template <class V>
+bool put_vec(std::FILE* f, const std::vector<V>& v)
+{
+  const uint64_t n = v.size();
+  return std::fwrite(&n, sizeof(n), 1, f) == 1 && (n == 0 || std::fwrite(v.data(), sizeof(V), n, f) == n);
+}
+template <class V>
+bool get_vec(std::FILE* f, std::vector<V>& v)
+{
+  uint64_t n = 0;
+  if (std::fread(&n, sizeof(n), 1, f) != 1 || n > ((uint64_t)1 << 36) / sizeof(V)) return false;
+  v.resize(n);
+  return n == 0 || std::fread(v.data(), sizeof(V), n, f) == n;
+}
+
+}  // namespace
+
+extern "C" mem_status mem_checkpoint_save(mem_checkpoint c, const char* path)
+{
+  if (!c || !path) return fail(MEM_EINVAL, "null argument");
+  if (!c->has) return fail(MEM_EINVAL, "empty checkpoint");
+  std::FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(MEM_EINVAL, std::string("cannot write ") + path);
+  bool ok = std::fwrite(kCkptMagic, 1, 8, f) == 8;
+  ok = ok && std::fwrite(&c->n_ev, sizeof(int32_t), 1, f) == 1 && std::fwrite(&c->n_int, sizeof(int32_t), 1, f) == 1;
+  ok = ok && std::fwrite(&c->allocation, sizeof(int32_t), 1, f) == 1 && std::fwrite(&c->iter, sizeof(uint32_t), 1, f) == 1;
+  ok = ok && std::fwrite(&c->seed, sizeof(uint64_t), 1, f) == 1 && std::fwrite(&c->alpha, sizeof(double), 1, f) == 1;
+  ok = ok && put_vec(f, c->ev_key) && put_vec(f, c->int_key) && put_vec(f, c->grids) && put_vec(f, c->state);
+  ok = ok && put_vec(f, c->active) && put_vec(f, c->done) && put_vec(f, c->alloc);
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? MEM_OK : fail(MEM_EINVAL, std::string("write failed: ") + path);
+}
+
+extern "C" mem_status mem_checkpoint_load(const char* path, mem_checkpoint* out)
+{
+  if (!path || !out) return fail(MEM_EINVAL, "null argument");
+  std::FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(MEM_EINVAL, std::string("cannot read ") + path);
+  mem_checkpoint_s c;
+  char magic[8];
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kCkptMagic, 8) == 0;
+  ok = ok && std::fread(&c.n_ev, sizeof(int32_t), 1, f) == 1 && std::fread(&c.n_int, sizeof(int32_t), 1, f) == 1;
+  ok = ok && std::fread(&c.allocation, sizeof(int32_t), 1, f) == 1 && std::fread(&c.iter, sizeof(uint32_t), 1, f) == 1;
+  ok = ok && std::fread(&c.seed, sizeof(uint64_t), 1, f) == 1 && std::fread(&c.alpha, sizeof(double), 1, f) == 1;
+  ok = ok && get_vec(f, c.ev_key) && get_vec(f, c.int_key) && get_vec(f, c.grids) && get_vec(f, c.state);
+  ok = ok && get_vec(f, c.active) && get_vec(f, c.done) && get_vec(f, c.alloc);
+  std::fclose(f);
+  ok = ok && c.n_ev >= 0 && c.n_int >= 0 && (int64_t)c.ev_key.size() == c.n_ev &&
+       (int64_t)c.int_key.size() == 4 * (int64_t)c.n_int && (int64_t)c.state.size() == (int64_t)c.n_int * ST_SIZE &&
+       (int64_t)c.active.size() == c.n_int && (int64_t)c.done.size() == c.n_ev &&
+       (c.alloc.empty() || (int64_t)c.alloc.size() == c.n_int);
+  if (!ok) return fail(MEM_EINVAL, std::string("malformed checkpoint file ") + path);
+  c.has = true;
+  *out = new (std::nothrow) mem_checkpoint_s(std::move(c));
+  return *out ? MEM_OK : fail(MEM_ENOMEM, "checkpoint allocation failed");
+}
+
 static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                  const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
-                                 double* p_out, double* err_out, int32_t* status_out);
+                                 double* p_out, double* err_out, int32_t* status_out, Workspace& work);
 
 static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                   const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
-                                  double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask);
+                                  double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask,
+                                  Workspace& work);
 
 // ---------------------------------------------------------- integrate ----
 extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
@@ -846,20 +1027,29 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
   if (o.allocation != MEM_ALLOC_EQUAL && o.allocation != MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "unknown allocation");
   const bool target_mode = o.target_rel_err > 0.0;
   const int iters = target_mode ? o.max_iter : n_iter;
-  if (iters < 2) return fail(MEM_EINVAL, "at least two iterations are needed");
+  const bool resume = o.checkpoint && o.checkpoint->has;
+  if (iters < (resume ? 1 : 2)) return fail(MEM_EINVAL, "at least two iterations are needed (one when resuming)");
   if (iters > 100000) return fail(MEM_EINVAL, "too many iterations");
   int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : kDefaultChunk;
   if (chunk_pts % kBlock != 0 || chunk_pts > 65536) return fail(MEM_EINVAL, "chunk_points must be a multiple of 256 <= 65536");
+  if ((o.alloc_fn == nullptr) != (o.free_fn == nullptr)) return fail(MEM_EINVAL, "alloc_fn and free_fn go together");
+  if (o.hooks & ~(uint32_t)MEM_HOOK_NONFINITE) return fail(MEM_EINVAL, "unknown hook");
+  if ((o.hooks & MEM_HOOK_NONFINITE) && (o.hook_event < 0 || o.hook_event >= n_ev))
+    return fail(MEM_EINVAL, "hook_event outside the events");
+  if (o.flow && (o.weights_out || o.checkpoint || o.hooks))
+    return fail(MEM_EUNSUPPORTED, "weights_out, checkpoints and hooks are VEGAS-only");
   if (n_ev == 0) return MEM_OK;
-  if (o.flow) return integrate_flow(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out);
-  return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr);
+  Workspace work(o.alloc_fn, o.free_fn, o.alloc_user, (hipStream_t)o.stream);
+  if (o.flow) return integrate_flow(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, work);
+  return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr, work);
 }
 
 // VEGAS over every event, or over the events with ev_mask[e] != 0 (host
 // array; the others are skipped and their outputs are undefined).
 static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                   const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
-                                  double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask)
+                                  double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask,
+                                  Workspace& work)
 {
   mem_status st = MEM_OK;
   const int n_ev = ev->n_events;
@@ -947,6 +1137,37 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     }
   }
   if ((int64_t)chunks.size() > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "too many chunks");
+  QueueHooks hooks{nullptr, 0, -1, -1};
+  if (o.weights_out) {
+    if (o.weights_integral < 0 || o.weights_integral >= n_int) return fail(MEM_EINVAL, "weights_integral outside the integrals");
+    if (o.weights_stride < cover[o.weights_integral]) return fail(MEM_EINVAL, "weights_stride below the integral's points");
+    hooks.wout = o.weights_out;
+    hooks.w_stride = o.weights_stride;
+    hooks.w_int = o.weights_integral;
+  }
+  if (o.hooks & MEM_HOOK_NONFINITE) hooks.nan_event = o.hook_event;
+  // checkpoint: what identifies this integration, and the state to resume from
+  mem_checkpoint_s* ck = o.checkpoint;
+  std::vector<uint64_t> ev_key(n_ev);
+  std::vector<int64_t> int_key(4 * (size_t)n_int);
+  if (ck) {
+    for (int e = 0; e < n_ev; ++e) ev_key[e] = process_key(procs[ev_proc[e]]);
+    for (int ig = 0; ig < n_int; ++ig) {
+      int_key[4 * ig] = ints[ig].event; int_key[4 * ig + 1] = ints[ig].perm;
+      int_key[4 * ig + 2] = ints[ig].dims; int_key[4 * ig + 3] = ints[ig].n_points;
+    }
+    if (ck->has) {
+      if (ev_mask) return fail(MEM_EUNSUPPORTED, "checkpoints of masked integrations");
+      if (ck->n_ev != n_ev || ck->n_int != n_int || ck->seed != o.seed || ck->alpha != o.alpha ||
+          ck->allocation != o.allocation || ck->ev_key != ev_key || ck->int_key != int_key ||
+          (int64_t)ck->grids.size() != grid_total)
+        return fail(MEM_EINVAL, "the checkpoint holds a different integration");
+    }
+  }
+  const bool resume = ck && ck->has;
+  const uint32_t iter0 = resume ? ck->iter : 0u;
+  // iterations this call runs: n_iter more, or up to max_iter in total
+  const int run_iters = target_mode ? std::max<int>(0, iters - (int)iter0) : iters;
   // launch groups by matrix-element precision; queue order longest first
   std::vector<Group> groups;
   auto group_of = [&](int prec) {
@@ -977,11 +1198,12 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   struct StreamGuard { hipStream_t& s; ~StreamGuard() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } } sg{own};
   hipStream_t ws = own ? own : s;
 
-  DevEvents dev;
+  DevEvents dev(&work);
   st = dev.make(ev, ws);
   if (st != MEM_OK) return st;
-  DevBuf b_procs, b_ints, b_chunks, b_queue, b_grids, b_parts, b_state, b_active, b_evi0, b_evnp, b_evnorm, b_done,
-      b_ctl, b_heads, b_P, b_err, b_status, b_alloc, b_cover, b_nev;
+  DevBuf b_procs(&work), b_ints(&work), b_chunks(&work), b_queue(&work), b_grids(&work), b_parts(&work),
+      b_state(&work), b_active(&work), b_evi0(&work), b_evnp(&work), b_evnorm(&work), b_done(&work), b_ctl(&work),
+      b_heads(&work), b_P(&work), b_err(&work), b_status(&work), b_alloc(&work), b_cover(&work), b_nev(&work);
   size_t qtotal = 0;
   for (auto& G : groups) qtotal += G.queue.size();
   HIP_TRY(b_procs.alloc(ptab.size() * sizeof(ProcParams)));
@@ -1041,6 +1263,18 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                        b_ints.as<IntegralDesc>(), n_int);
     HIP_TRY(hipGetLastError());
   }
+  if (resume) {
+    // the state of the earlier call; the host vectors live in the handle
+    const Control ctlr{iter0, 0u, 0, 0u};
+    HIP_TRY(hipMemcpyAsync(b_ctl.p, &ctlr, sizeof(Control), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemcpyAsync(b_grids.p, ck->grids.data(), grid_total * sizeof(double), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemcpyAsync(b_state.p, ck->state.data(), ck->state.size() * sizeof(double), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemcpyAsync(b_active.p, ck->active.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemcpyAsync(b_done.p, ck->done.data(), n_ev * sizeof(int32_t), hipMemcpyHostToDevice, ws));
+    if (neyman && (int64_t)ck->alloc.size() == n_int)
+      HIP_TRY(hipMemcpyAsync(b_alloc.p, ck->alloc.data(), n_int * sizeof(int64_t), hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipStreamSynchronize(ws));
+  }
   if (ev_mask) {
     // skipped events: integrals inactive and the event retired from the start
     std::vector<int32_t> act(n_int), dn(n_ev);
@@ -1057,7 +1291,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   // chunk order through the queue: the kernel reads chunks[queue[c]]; the
   // queue kernel takes the chunk table permuted on the device instead
   // (one gather per call)
-  DevBuf b_chunks_q;
+  DevBuf b_chunks_q(&work);
   HIP_TRY(b_chunks_q.alloc(flat.size() * sizeof(Chunk)));
   std::vector<size_t> gqn(groups.size());     // queue length per group
   {
@@ -1087,7 +1321,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       hipLaunchKernelGGL(G.kernel, dim3(G.blocks), dim3(kBlock), 0, ws, b_procs.as<ProcParams>(), dev.view, cq,
                          (int64_t)gqn[g], b_ints.as<IntegralDesc>(), b_grids.as<double>(),
                          b_active.as<int32_t>(), o.seed, ctl, b_heads.as<uint32_t>() + g, b_parts.as<double>(),
-                         neyman ? b_alloc.as<int64_t>() : nullptr);
+                         neyman ? b_alloc.as<int64_t>() : nullptr, hooks);
       HIP_TRY(hipGetLastError());
       if (time_kernels) HIP_TRY(hipEventRecord(tev->back(), ws));
     }
@@ -1141,6 +1375,12 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   // per integral in chunk order, so the results do not change.
   std::vector<int32_t> qhost(flat.begin(), flat.end());
   int64_t running_at_build = n_ev;
+  if (target_mode && resume && run_iters > 0) {
+    // events retired before the checkpoint leave the queue at once
+    int64_t running = 0;
+    for (int e = 0; e < n_ev; ++e) running += ck->done[e] == 0 ? 1 : 0;
+    if (running == 0) running_at_build = 0;
+  }
   auto compact = [&]() -> mem_status {
     std::vector<int32_t> dn(n_ev);
     HIP_TRY(hipMemcpy(dn.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1171,7 +1411,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     return use_graph ? capture() : MEM_OK;
   };
   auto wall0 = std::chrono::steady_clock::now();
-  for (int j = 0; j < iters; ++j) {
+  for (int j = 0; j < run_iters && running_at_build > 0; ++j) {
     if (use_graph) HIP_TRY(hipGraphLaunch(gexec, ws));
     else {
       mem_status es = enqueue_iteration(o.timing_out != nullptr, &tev);
@@ -1206,6 +1446,24 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   }
   // the work buffers are freed on return: wait for the stream
   HIP_TRY(hipStreamSynchronize(ws));
+  if (ck) {
+    // the final state into the handle
+    Control hc{};
+    std::vector<double> grids(grid_total), state((size_t)n_int * ST_SIZE);
+    std::vector<int32_t> act(n_int), dn(n_ev);
+    std::vector<int64_t> al(neyman ? n_int : 0);
+    HIP_TRY(hipMemcpy(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(grids.data(), b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(state.data(), b_state.p, state.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(act.data(), b_active.p, n_int * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dn.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (neyman) HIP_TRY(hipMemcpy(al.data(), b_alloc.p, n_int * sizeof(int64_t), hipMemcpyDeviceToHost));
+    ck->n_ev = n_ev; ck->n_int = n_int; ck->allocation = o.allocation; ck->seed = o.seed; ck->alpha = o.alpha;
+    ck->ev_key.swap(ev_key); ck->int_key.swap(int_key);
+    ck->iter = hc.iter;
+    ck->grids.swap(grids); ck->state.swap(state); ck->active.swap(act); ck->done.swap(dn); ck->alloc.swap(al);
+    ck->has = true;
+  }
   if (o.timing_out) {
     double ms = 0.0;
     for (size_t i = 0; i + 1 < tev.size(); i += 2) {
@@ -1893,7 +2151,7 @@ extern "C" mem_status mem_flow_train_step(mem_flow f, const float* ctx, const in
 // Flow-proposal integration (see mem_integrate_opts.flow).
 static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                  const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
-                                 double* p_out, double* err_out, int32_t* status_out)
+                                 double* p_out, double* err_out, int32_t* status_out, Workspace& work)
 {
   const int n_ev = ev->n_events;
   mem_flow fl = o.flow;
@@ -1964,11 +2222,10 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
   if (!s && want_graph) HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
   struct StreamGuard { hipStream_t& s; ~StreamGuard() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } } sg{own};
   hipStream_t ws = own ? own : s;
-  DevEvents dev;
+  DevEvents dev(&work);
   mem_status st = dev.make(ev, ws);
   if (st != MEM_OK) return st;
-  DevBuf b_procs, b_iproc, b_iev, b_iperm, b_ctx, b_cvec, b_ints, b_sch, b_wch, b_parts, b_state, b_active, b_evi0,
-      b_evnp, b_evnorm, b_done, b_ctl, b_x, b_lq, b_P, b_err, b_status;
+  DevBuf b_procs(&work), b_iproc(&work), b_iev(&work), b_iperm(&work), b_ctx(&work), b_cvec(&work), b_ints(&work), b_sch(&work), b_wch(&work), b_parts(&work), b_state(&work), b_active(&work), b_evi0(&work), b_evnp(&work), b_evnorm(&work), b_done(&work), b_ctl(&work), b_x(&work), b_lq(&work), b_P(&work), b_err(&work), b_status(&work);
   HIP_TRY(b_procs.alloc(ptab.size() * sizeof(ProcParams)));
   HIP_TRY(b_iproc.alloc(n_int * sizeof(int32_t)));
   HIP_TRY(b_iev.alloc(n_int * sizeof(int32_t)));
@@ -2113,7 +2370,8 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
     std::vector<double> hs((size_t)n_int * FS_SIZE);
     HIP_TRY(hipMemcpyAsync(hs.data(), b_state.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, ws));
     HIP_TRY(hipStreamSynchronize(ws));
-    for (int i = 0; i < n_int; ++i) n_evals += hs[(size_t)i * FS_SIZE + FS_N];
+    // the pooled points of every integral plus its pilot batch
+    for (int i = 0; i < n_int; ++i) n_evals += hs[(size_t)i * FS_SIZE + FS_N] + (double)ints[i].n_points;
   }
   // events below the ESS threshold: VEGAS on a compact copy
   std::vector<int32_t> done(n_ev);
@@ -2128,7 +2386,7 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
     const int nf = (int)fb.size();
     std::vector<int32_t> mask(n_ev, 0);
     for (int e : fb) mask[e] = 1;
-    DevBuf b_idx, b_fP, b_fE, b_fS, b_fN;
+    DevBuf b_idx(&work), b_fP(&work), b_fE(&work), b_fS(&work), b_fN(&work);
     HIP_TRY(b_idx.alloc(nf * sizeof(int32_t)));
     HIP_TRY(b_fP.alloc(n_ev * sizeof(double)));
     HIP_TRY(b_fE.alloc(n_ev * sizeof(double)));
@@ -2144,7 +2402,7 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
     o2.n_iter_out = b_fN.as<int32_t>();
     o2.timing_out = o.timing_out ? fb_timing : nullptr;
     st = integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o2, b_fP.as<double>(), b_fE.as<double>(),
-                         b_fS.as<int32_t>(), mask.data());
+                         b_fS.as<int32_t>(), mask.data(), work);
     if (st != MEM_OK) return st;
     hipLaunchKernelGGL(scatter_fallback_kernel, dim3((nf + 255) / 256), dim3(256), 0, ws, b_idx.as<int32_t>(), nf,
                        b_fP.as<double>(), b_fE.as<double>(), b_fS.as<int32_t>(), b_fN.as<int32_t>(), P, E, S,

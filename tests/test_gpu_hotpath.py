@@ -1,0 +1,256 @@
+"""The work-queue integrand kernel itself, point by point, against the FP64
+oracle.
+
+mem_integrate_events records, through its weights_out option, the weight
+w = f(x) J(x) of every point the persistent queue kernel evaluates for one
+integral.  The same u (Philox stream), the same grid and the oracle's
+integrand give the expected weight of each point.  The grid of iteration j
+is the one a j-iteration call leaves behind (every reduction runs in a
+fixed order, so a shorter call reproduces the longer call's grids bit for
+bit).
+
+Covered: the dilepton kernel's compacted path (per-wavefront LDS record and
+root queue, rounds with more than 64 roots) at the benchmark's launch shape
+(32 768 points per assignment and iteration = 8 chunks) and with a ragged
+tail, in FP32 and FP64; the same under Neyman allocation (chunks cut at the
+allocation); the per-lane path of launches that also carry t tbar H chunks;
+and every other process kind's chunk loop.  Bars: FP32 1e-5 relative and
+FP64 1e-9 (dilepton; the FP64 note in test_gpu_parity.py) on every point the
+oracle does not flag as ill-conditioned (its own value moves by more than
+1e-7 under 1-ulp changes of x), at most 1 % flagged; FP64 Drell-Yan 1e-11;
+equal solution counts are implied by the weights.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import events
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mem():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1407_7595_amd as m
+    m.lib()
+    return m
+
+
+def ill_conditioned(fn, x, f0, rel=1e-7):
+    for k in range(3):
+        xp = np.nextafter(x, 1.0) if k == 0 else np.nextafter(x, 0.0) if k == 1 else x * (1 + 2e-16)
+        xp = np.clip(xp, 0.0, 1.0 - 2 ** -53)
+        f1 = fn(xp)[0]
+        if abs(f1 - f0) > rel * max(abs(f0), 1e-300):
+            return True
+    return False
+
+
+def oracle_weights(fn, seed, it, event_index, perm, D, grid, n):
+    """for points 0..n-1 of one integral in iteration it on the given grid:
+    the weights w = f(x) J(x), the solution counts, the points x and f(x)"""
+    w = np.zeros(n)
+    f = np.zeros(n)
+    ns = np.zeros(n, dtype=np.int64)
+    xs = np.zeros((n, D))
+    for k in range(n):
+        u = oracle.uniforms(seed, k, it, event_index, perm, D)
+        x, jac, _ = oracle.vegas_map(grid, u)
+        f[k], ns[k] = fn(x)
+        w[k] = f[k] * jac
+        xs[k] = x
+    return w, ns, xs, f
+
+
+def compare(got, ref, fn, tol, what):
+    """element-wise bar with the oracle's ill-conditioning exclusion; ref is
+    oracle_weights' result"""
+    want, _, xs, fv = ref
+    assert np.all(np.isfinite(got)), what
+    both_zero = (got == 0.0) & (want == 0.0)
+    rel = np.where(both_zero, 0.0, np.abs(got - want) / np.maximum(np.abs(want), 1e-300))
+    flagged = 0
+    for k in np.nonzero(rel > tol)[0]:
+        if ill_conditioned(fn, xs[k], fv[k]):
+            flagged += 1
+            rel[k] = 0.0
+            continue
+        raise AssertionError(f"{what}: point {k}: gpu {got[k]!r} oracle {want[k]!r} rel {rel[k]:.3g}")
+    n_nz = int(np.sum(~both_zero))
+    say(f"{what}: {len(got)} points, {n_nz} nonzero, worst rel {rel.max():.3g} (unflagged), flagged {flagged}")
+    assert flagged <= 0.01 * max(n_nz, 1) + 2, what
+    return n_nz
+
+
+def wave_solution_counts(ns):
+    """accepted solutions per wavefront (64 consecutive points; chunks start
+    at multiples of 4096)"""
+    n = len(ns) // 64 * 64
+    return ns[:n].reshape(-1, 64).sum(axis=1)
+
+
+_TT_CACHE = {}
+
+
+def tt_oracle(d, e, perm, seed, it, grid, n):
+    key = (id(d), e, perm, seed, it, n, grid.tobytes())
+    if key not in _TT_CACHE:
+        po = oracle.tt_params()
+        fn = lambda x: oracle.tt_integrand(po, d["obs"][e], perm, x)     # noqa: E731
+        _TT_CACHE[key] = oracle_weights(fn, seed, it, e, perm, 8, grid, n)
+    return _TT_CACHE[key]
+
+
+TT_EVENTS = None
+
+
+def tt_events():
+    global TT_EVENTS
+    if TT_EVENTS is None:
+        TT_EVENTS = events.ttbar_dilepton(2, 0x5eed1)
+    return TT_EVENTS
+
+
+# event 0: the benchmark's 65 536 points per event (32 768 per assignment,
+# 8 chunks of 4096); event 1: 13 288 per assignment (3 chunks + a ragged
+# 1000-point tail that ends inside a wavefront)
+TT_BUDGETS = [65536, 26576]
+TT_ITERS = 4
+TT_SEED = 77
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-9)])
+@pytest.mark.parametrize("event,perm", [(0, 1), (1, 0)])
+def test_queue_weights_tt(mem, precision, tol, event, perm):
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=precision)
+    d = tt_events()
+    comps = mem.to_components(d["obs"]).cuda()
+    per = TT_BUDGETS[event] // 2
+    ig = 2 * event + perm
+    say(f"queue weights: tt precision={precision} integral {ig} ({per} points/iteration), {TT_ITERS} iterations")
+    wout = torch.full((TT_ITERS, per), float("nan"), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, p, TT_BUDGETS, TT_ITERS, seed=TT_SEED, weights_out=wout, weights_integral=ig)
+    grid3 = torch.zeros((4, 8, 65), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, p, TT_BUDGETS, 3, seed=TT_SEED, grid_out=grid3)
+    torch.cuda.synchronize()
+    got = wout.cpu().numpy()
+    assert not np.any(np.isnan(got)), "every point of every iteration is recorded"
+    po = oracle.tt_params()
+    fn = lambda x: oracle.tt_integrand(po, d["obs"][event], perm, x)     # noqa: E731
+    for it, grid in ((0, oracle.uniform_grid(8)), (3, grid3.cpu().numpy()[ig])):
+        ref = tt_oracle(d, event, perm, TT_SEED, it, grid, per)
+        n_nz = compare(got[it], ref, fn, tol, f"tt prec {precision} integral {ig} iteration {it}")
+        assert n_nz > 100
+        if it == 3 and event == 0:
+            waves = wave_solution_counts(ref[1])
+            say(f"  solutions per 64-point wavefront: max {waves.max()}, mean {waves.mean():.1f}")
+            assert waves.max() > 64, "some wavefront queues more than 64 roots"
+
+
+def test_queue_weights_tt_neyman(mem):
+    """Neyman allocation: chunks past an iteration's allocation are skipped
+    and the one across it is cut"""
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = tt_events()
+    comps = mem.to_components(d["obs"]).cuda()
+    budgets = [26576, 26576]
+    per = budgets[0] // 2
+    cover = 2 * per
+    say("queue weights: tt Neyman, integral 0, 4 iterations")
+    wout = torch.full((4, cover), float("nan"), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, p, budgets, 4, seed=5, weights_out=wout, weights_integral=0,
+                         allocation=mem.MEM_ALLOC_NEYMAN)
+    grid3 = torch.zeros((4, 8, 65), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, p, budgets, 3, seed=5, grid_out=grid3, allocation=mem.MEM_ALLOC_NEYMAN)
+    torch.cuda.synchronize()
+    got = wout.cpu().numpy()
+    assert not np.any(np.isnan(got[0, :per])) and np.all(np.isnan(got[0, per:])), "the first iteration splits equally"
+    n3 = int(np.sum(~np.isnan(got[3])))
+    assert n3 >= per // 8 and np.all(~np.isnan(got[3, :n3])) and np.all(np.isnan(got[3, n3:])), \
+        "an iteration evaluates a prefix of the point stream"
+    po = oracle.tt_params()
+    fn = lambda x: oracle.tt_integrand(po, d["obs"][0], 0, x)     # noqa: E731
+    ref = oracle_weights(fn, 5, 3, 0, 0, 8, grid3.cpu().numpy()[0], n3)
+    say(f"  iteration 3 allocation: {n3} of {cover} points")
+    compare(got[3, :n3], ref, fn, 1e-5, "tt Neyman iteration 3")
+
+
+def test_queue_weights_per_lane_path(mem):
+    """a launch that also carries t tbar H chunks runs the dilepton chunks
+    through the per-lane root loop (two waves per SIMD): same weights"""
+    tth = mem.Process(mem.MEM_TTH_SEMILEPTON, precision=mem.MEM_FP32)
+    tt = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    dh = events.ttbar_higgs(1, 0x5eed2)["obs"]
+    dt = tt_events()["obs"][:1]
+    obs = np.zeros((2, 7, 4))
+    obs[0] = dh[0, :7]
+    obs[1, :4] = dt[0, :4]
+    charge = np.array([int(dh[0, 7, 0]), 1], dtype=np.int32)
+    comps = mem.to_components(obs).cuda()
+    ch = torch.as_tensor(charge).cuda()
+    budgets = [24 * 256, 2 * 9000]
+    per = 9000
+    ig = 24 + 1              # the dilepton event's second assignment
+    say("queue weights: tt in a launch with t tbar H chunks, 3 iterations")
+    wout = torch.full((3, per), float("nan"), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, [tth, tt], budgets, 3, seed=9, charge=ch, weights_out=wout, weights_integral=ig)
+    grid2 = torch.zeros((26, 65 * 9), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, [tth, tt], budgets, 2, seed=9, charge=ch, grid_out=grid2)
+    torch.cuda.synchronize()
+    got = wout.cpu().numpy()
+    assert not np.any(np.isnan(got))
+    # grids are packed per integral: 9 x 65 for t tbar H, 8 x 65 for dilepton
+    flat = grid2.reshape(-1).cpu().numpy()
+    g_tt = flat[24 * 9 * 65 + 8 * 65: 24 * 9 * 65 + 2 * 8 * 65].reshape(8, 65)
+    po = oracle.tt_params()
+    fn = lambda x: oracle.tt_integrand(po, dt[0], 1, x)     # noqa: E731
+    for it, grid in ((0, oracle.uniform_grid(8)), (2, g_tt)):
+        ref = oracle_weights(fn, 9, it, 1, 1, 8, grid, per)
+        compare(got[it], ref, fn, 1e-5, f"tt per-lane iteration {it}")
+
+
+def test_queue_weights_other_kinds(mem):
+    """every other process kind's chunk loop (iteration 0, uniform grid)"""
+    cases = []
+    dy = events.drell_yan(1, 0x5eed3)["obs"]
+    cases.append(("dy", mem.MEM_DY_QQ_GAMMA_MUMU, mem.MEM_FP64, dy[:, :2], None, 2, 1, 5000, 1e-11,
+                  lambda e, pm, x: (oracle.dy_integrand(oracle.dy_params(), e, x), 0)))
+    sl = events.ttbar_semileptonic(1, 0x5eed4)["obs"]
+    cases.append(("sl", mem.MEM_TT_SEMILEPTON, mem.MEM_FP32, sl[:, :5], int(sl[0, 5, 0]), 7, 12, 12 * 1500, 1e-5,
+                  lambda e, pm, x: oracle.sl_integrand(oracle.sl_params(), e, pm, x)))
+    th = events.ttbar_higgs(1, 0x5eed5)["obs"]
+    cases.append(("tth", mem.MEM_TTH_SEMILEPTON, mem.MEM_FP32, th[:, :7], int(th[0, 7, 0]), 9, 24, 24 * 700, 1e-5,
+                  lambda e, pm, x: oracle.tth_integrand(oracle.tt_params(), e, pm, x)))
+    hl = events.ttbar_higgs_dilepton(1, 0x5eed6)["obs"]
+    cases.append(("tthll", mem.MEM_TTH_DILEPTON, mem.MEM_FP32, hl, None, 8, 12, 12 * 1200, 1e-5,
+                  lambda e, pm, x: oracle.tthll_integrand(oracle.tt_params(), e, pm, x)))
+    bb = events.ttbar_bbbar_dilepton(1, 0x5eed7)["obs"]
+    cases.append(("ttbbll", mem.MEM_TTBB_DILEPTON, mem.MEM_FP32, bb, None, 8, 24, 24 * 300, 1e-5,
+                  lambda e, pm, x: oracle.ttbbll_integrand(oracle.tt_params(), e, pm, x)))
+    for name, kind, prec, obs, charge, D, n_perm, budget, tol, fo in cases:
+        p = mem.Process(kind, precision=prec)
+        comps = mem.to_components(obs).cuda()
+        ch = torch.as_tensor(np.array([charge], dtype=np.int32)).cuda() if charge is not None else None
+        per = -(-budget // n_perm)
+        perm = n_perm - 1
+        say(f"queue weights: {name}, integral {perm} ({per} points), iteration 0 of 2")
+        wout = torch.full((2, per), float("nan"), dtype=torch.float64, device="cuda")
+        mem.integrate_events(comps, p, budget, 2, seed=3, charge=ch, weights_out=wout, weights_integral=perm)
+        torch.cuda.synchronize()
+        got = wout.cpu().numpy()
+        assert not np.any(np.isnan(got)), name
+        ev_rows = obs[0] if charge is None else {"sl": sl, "tth": th}[name][0]
+        fn = (lambda x, e=ev_rows, pm=perm, f=fo: f(e, pm, x))
+        ref = oracle_weights(fn, 3, 0, 0, perm, D, oracle.uniform_grid(D), per)
+        compare(got[0], ref, fn, tol, f"{name} iteration 0")
