@@ -194,16 +194,22 @@ typedef struct mem_flow_s* mem_flow;
  *                  the same u in either mode); estimates differ from equal
  *                  splitting by MC fluctuation only.  Other values:
  *                  MEM_EINVAL.
- *  weights_out     optional device pointer [iterations][weights_stride]
+ *  weights_out     optional device pointer [weights_rows][weights_stride]
  *                  doubles: the weight w = f(x) J(x) of every point the
  *                  integrand kernel evaluates for integral weights_integral
  *                  (integral index = sum of the earlier events'
  *                  permutation counts + permutation), at
- *                  [iteration][point index k].  Entries an iteration does
- *                  not evaluate are left as they were.  weights_stride must
- *                  be at least the integral's points per iteration (its
- *                  equal share, times min(n_perm, 4) under Neyman
- *                  allocation).  VEGAS only (MEM_EUNSUPPORTED with a flow).
+ *                  [iteration][point index k], iterations counted from the
+ *                  start of the integration (a resumed checkpoint's
+ *                  iterations included).  Entries an iteration does not
+ *                  evaluate are left as they were.  weights_stride must be
+ *                  at least the integral's points per iteration (its equal
+ *                  share, times min(n_perm, 4) under Neyman allocation) and
+ *                  weights_rows at least the last iteration index the call
+ *                  can reach plus one (n_iter, or max_iter in target mode,
+ *                  plus a resumed checkpoint's iterations in fixed mode);
+ *                  otherwise MEM_EINVAL before any launch.  VEGAS only
+ *                  (MEM_EUNSUPPORTED with a flow).
  *  hooks, hook_event  test hooks (MEM_HOOK_*; 0 = none)
  *  checkpoint      NULL, or a handle from mem_checkpoint_create (VEGAS only;
  *                  MEM_EUNSUPPORTED with a flow).  An empty handle: the
@@ -262,6 +268,7 @@ typedef struct {
   double* weights_out;
   int64_t weights_stride;
   int32_t weights_integral;
+  int32_t weights_rows;
   uint32_t hooks;
   int32_t hook_event;
   mem_checkpoint checkpoint;

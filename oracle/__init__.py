@@ -24,6 +24,11 @@ KIND_TT_SL = 4
 KIND_TTH = 5
 KIND_TTH_LL = 6
 KIND_TTBB_LL = 7
+# direct parametrisations of the t tbar, semileptonic and t tbar H dilepton
+# integrals (closure checks of the mapped ones)
+KIND_TT_DIRECT = 8
+KIND_TT_SL_DIRECT = 9
+KIND_TTH_LL_DIRECT = 10
 NBINS = 64
 
 
@@ -145,6 +150,7 @@ def _declare(L):
         "or_decay_w_factor": (D, [P, D]),
         "or_ps_volume": (D, [I, D, U64, I64, P]),
         "or_top_width": (D, [P, U64, I64, P]),
+        "or_tt_decayed_sigma": (D, [P, I, D, U64, I64, P]),
         "or_solve_dilepton": (I, [P, P, P, P, D, D, D, D, D, D, P, P, P]),
         "or_dilepton_residual": (None, [P, P, P, P, P, P, P]),
         "or_tt_me2_gg": (D, [P, P, P, P]),
@@ -260,6 +266,14 @@ def tt_integrand(p, ev, perm, x):
 def ps_volume(n, sqrt_s, seed, n_points):
     err = ctypes.c_double()
     v = lib().or_ps_volume(n, sqrt_s, seed, n_points, ctypes.byref(err))
+    return v, err.value
+
+
+def tt_decayed_sigma(p, channel, sqrt_shat, seed, n_points):
+    """partonic sigma(g g (0) / q qbar (1) -> t tbar -> b l nu b l nu) from
+    the decayed matrix element over six-body phase space; (value, error)"""
+    err = ctypes.c_double()
+    v = lib().or_tt_decayed_sigma(ctypes.byref(p), channel, sqrt_shat, seed, n_points, ctypes.byref(err))
     return v, err.value
 
 

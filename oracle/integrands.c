@@ -503,12 +503,14 @@ static void boost_transverse(const double* P, const double* in, double* out)
 
 int or_dims(int kind)
 {
-  return kind == OR_KIND_DY ? 2 : kind == OR_KIND_GENZ ? 4 : kind == OR_KIND_TT_SL ? 7 : kind == OR_KIND_TTH ? 9 : 8;
+  return kind == OR_KIND_DY ? 2 : kind == OR_KIND_GENZ ? 4
+       : (kind == OR_KIND_TT_SL || kind == OR_KIND_TT_SL_DIRECT) ? 7 : kind == OR_KIND_TTH ? 9 : 8;
 }
 int or_nperm(int kind)
 {
-  return kind == OR_KIND_TT ? 2 : kind == OR_KIND_TT_SL ? 12 : kind == OR_KIND_TTH ? 24
-       : kind == OR_KIND_TTH_LL ? 12 : kind == OR_KIND_TTBB_LL ? 24 : 1;
+  return (kind == OR_KIND_TT || kind == OR_KIND_TT_DIRECT) ? 2
+       : (kind == OR_KIND_TT_SL || kind == OR_KIND_TT_SL_DIRECT) ? 12 : kind == OR_KIND_TTH ? 24
+       : (kind == OR_KIND_TTH_LL || kind == OR_KIND_TTH_LL_DIRECT) ? 12 : kind == OR_KIND_TTBB_LL ? 24 : 1;
 }
 
 double or_genz_integrand(const double* x)
@@ -1010,8 +1012,10 @@ void or_f2_perm(int kind, int perm, int* rows)
  * transverse momenta add up to minus that of the visible objects (the
  * transverse momentum balance of Sec. 3; no recoil).  Only the gg initial
  * state. */
-static double f2_integrand(int kind, const or_params* p, const double* ev, int perm, const double* x,
-                           int* nsol_out)
+/* direct_e4: x7 is the r map of pair jet 2 for either kind (the direct
+ * parametrisation of the t tbar H integral, a closure check). */
+static double f2_integrand_me(int kind, int direct_e4, const or_params* p, const double* ev, int perm,
+                              const double* x, int* nsol_out)
 {
   const double S = p->sqrt_s * p->sqrt_s;
   int rows[4];
@@ -1036,7 +1040,7 @@ static double f2_integrand(int kind, const or_params* p, const double* ev, int p
     jac *= (rhi - rlo) * em[k] / (r * r);
   }
   double q2h = 0.0;
-  if (kind == OR_KIND_TTH_LL) {
+  if (kind == OR_KIND_TTH_LL && !direct_e4) {
     jac *= or_bw_map(x[7], p->m_h, p->w_h, 0.0, S, &q2h);
     double c12 = dir[2][0] * dir[3][0] + dir[2][1] * dir[3][1] + dir[2][2] * dir[3][2];
     if (!(1.0 - c12 > 0.0)) return 0.0;
@@ -1102,11 +1106,11 @@ static double f2_integrand(int kind, const or_params* p, const double* ev, int p
 
 double or_tthll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out)
 {
-  return f2_integrand(OR_KIND_TTH_LL, p, ev, perm, x, nsol_out);
+  return f2_integrand_me(OR_KIND_TTH_LL, 0, p, ev, perm, x, nsol_out);
 }
 double or_ttbbll_integrand(const or_params* p, const double* ev, int perm, const double* x, int* nsol_out)
 {
-  return f2_integrand(OR_KIND_TTBB_LL, p, ev, perm, x, nsol_out);
+  return f2_integrand_me(OR_KIND_TTBB_LL, 0, p, ev, perm, x, nsol_out);
 }
 
 /* Parton level for Sec. 4's processes (its Table 2 workload): the transfer
@@ -1151,4 +1155,166 @@ double or_f2_parton_weight(int kind, const or_params* p, const double* ev)
     sum += (2.0 / S) * (P[0] / Eh) * g1 * g2 * me / (2.0 * shat);
   }
   return sum / n;
+}
+
+/* ------------------------------------------- direct parametrisations -- */
+/* Eq. integrand written in the unmeasured momenta themselves: no
+ * propagator-aligned variables, no constraint solve, the Breit-Wigner
+ * factors left inside |M|^2.  They exist to check the mapped integrands
+ * above by closure (the two parametrisations of one integral must agree);
+ * the driver integrates them as kinds of their own.
+ *
+ * A momentum component p is drawn by the Cauchy map p = c + s tan(pi (x -
+ * 1/2)), dp/dx = pi s (1 + ((p - c)/s)^2). */
+static double cauchy_map(double x, double c, double s, double* jac)
+{
+  const double t = tan(M_PI * (x - 0.5));
+  *jac *= M_PI * s * (1.0 + t * t);
+  return c + s * t;
+}
+
+/* ttbar dilepton: x0, x1 jet energies and x6, x7 recoil exactly as in
+ * or_tt_integrand; x2..x5 -> (nu_x, nu_y, nu_z, nubar_z), nubar_T = MET -
+ * nu_T (the transverse delta function), measure d^3nu/(2E) d^3nubar/(2E)
+ * reduced by it to d^3nu dnubar_z / (2E 2E). */
+double or_tt_direct_integrand(const or_params* p, const double* ev, int perm, const double* x)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  const double* jet[2] = {ev + (perm ? 4 : 0), ev + (perm ? 0 : 4)};
+  const double* lp = ev + 8;
+  const double* lm = ev + 12;
+  double bq[2][4];
+  double jetf = 1.0;
+  for (int k = 0; k < 2; ++k) {
+    const double* m = jet[k];
+    double em = m[0], pm = norm3(m);
+    double r = p->r_lo + x[k] * (p->r_hi - p->r_lo);
+    double E = em / r;
+    double jac = (p->r_hi - p->r_lo) * em / (r * r);
+    bq[k][0] = E;
+    for (int i = 1; i < 4; ++i) bq[k][i] = m[i] / pm * E;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    jetf *= E * E * sin_th * or_gauss_tf(em, E, p->tf_sigma) / (2.0 * E) * jac;
+  }
+  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[6]));
+  double phi = 2.0 * M_PI * x[7];
+  double metx = rho * cos(phi) - (bq[0][1] + bq[1][1] + lp[1] + lm[1]);
+  double mety = rho * sin(phi) - (bq[0][2] + bq[1][2] + lp[2] + lm[2]);
+  double jnu = 1.0;
+  double v[4], vb[4];
+  v[1] = cauchy_map(x[2], 0.5 * metx, 60.0, &jnu);
+  v[2] = cauchy_map(x[3], 0.5 * mety, 60.0, &jnu);
+  v[3] = cauchy_map(x[4], 0.0, 100.0, &jnu);
+  vb[3] = cauchy_map(x[5], 0.0, 100.0, &jnu);
+  vb[1] = metx - v[1];
+  vb[2] = mety - v[2];
+  v[0] = norm3(v);
+  vb[0] = norm3(vb);
+  double lab[6][4];
+  memcpy(lab[0], bq[0], sizeof(lab[0])); memcpy(lab[1], lp, sizeof(lab[1]));
+  memcpy(lab[2], v, sizeof(lab[2]));     memcpy(lab[3], bq[1], sizeof(lab[3]));
+  memcpy(lab[4], lm, sizeof(lab[4]));    memcpy(lab[5], vb, sizeof(lab[5]));
+  double P[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 6; ++k) for (int i = 0; i < 4; ++i) P[i] += lab[k][i];
+  double hard[24];
+  for (int k = 0; k < 6; ++k) boost_transverse(P, lab[k], hard + 4 * k);
+  double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+  double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
+  double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+  double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+  const tt_lumi L = tt_lumis(p, x1, x2);
+  double me = L.gg * or_tt_me2_gg(p, k1, k2, hard)
+            + L.qq12 * or_tt_me2_qq(p, k1, k2, hard)
+            + L.qq21 * or_tt_me2_qq(p, k2, k1, hard);
+  double shat = x1 * x2 * S;
+  double f = (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat) / (2.0 * v[0] * 2.0 * vb[0]);
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
+  double lep = 1.0 / (2.0 * lp[0] * 2.0 * lm[0]);
+  return f * two_pi_pow * lep * jetf * jnu;
+}
+
+/* ttbar semileptonic: all four jet energies through their r maps (x0: light
+ * jet a, x1: light jet b, x2: b of the hadronic top, x3: b of the leptonic
+ * top, each over its TF window), x4, x5 recoil as in
+ * or_tt_semilep_integrand, x6 -> nu_z (nu_T = MET): the measure
+ * d^3nu/(2E) with the transverse delta function leaves dnu_z / (2E). */
+double or_tt_semilep_direct_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
+                                      const double* x)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  if (lep_charge == 0) lep_charge = ev[20] > 0 ? 1 : -1;
+  int ibl, ibh, ja, jb;
+  or_semilep_perm(perm, &ibl, &ibh, &ja, &jb);
+  const double* l = ev + 16;
+  double qa[4], qb[4], bh[4], bl[4];
+  const int idx[4] = {ja, jb, ibh, ibl};
+  double* dst[4] = {qa, qb, bh, bl};
+  double tf = 1.0, jac = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    const double* m = ev + 4 * idx[k];
+    const double lo = k < 2 ? p->lj_r_lo : p->r_lo, hi = k < 2 ? p->lj_r_hi : p->r_hi;
+    double r = lo + x[k] * (hi - lo);
+    double pm = norm3(m), E = m[0] / r;
+    jac *= (hi - lo) * m[0] / (r * r);
+    dst[k][0] = E;
+    for (int i = 0; i < 3; ++i) dst[k][i + 1] = E * m[i + 1] / pm;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    double T = k < 2 ? or_dgauss_tf(m[0], E, p->lj_core, p->lj_tail, p->lj_ftail)
+                     : or_gauss_tf(m[0], E, p->tf_sigma);
+    tf *= E * E * sin_th * T / (2.0 * E);
+  }
+  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
+  double phi = 2.0 * M_PI * x[5];
+  double nu[4];
+  nu[1] = rho * cos(phi) - (qa[1] + qb[1] + bh[1] + bl[1] + l[1]);
+  nu[2] = rho * sin(phi) - (qa[2] + qb[2] + bh[2] + bl[2] + l[2]);
+  nu[3] = cauchy_map(x[6], 0.0, 100.0, &jac);
+  nu[0] = norm3(nu);
+  double P[4];
+  for (int i = 0; i < 4; ++i) P[i] = qa[i] + qb[i] + bh[i] + bl[i] + l[i] + nu[i];
+  double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
+  double x1 = (Eh + P[3]) / p->sqrt_s, x2 = (Eh - P[3]) / p->sqrt_s;
+  if (!(x1 > 0.0 && x1 <= 1.0 && x2 > 0.0 && x2 <= 1.0)) return 0.0;
+  double k1[4] = {0.5 * x1 * p->sqrt_s, 0, 0, 0.5 * x1 * p->sqrt_s};
+  double k2[4] = {0.5 * x2 * p->sqrt_s, 0, 0, -0.5 * x2 * p->sqrt_s};
+  double hq[2][4], hbh[4], hbl[4], hl[4], hn[4];
+  boost_transverse(P, qa, hq[0]);
+  boost_transverse(P, qb, hq[1]);
+  boost_transverse(P, bh, hbh);
+  boost_transverse(P, bl, hbl);
+  boost_transverse(P, l, hl);
+  boost_transverse(P, nu, hn);
+  const tt_lumi L = tt_lumis(p, x1, x2);
+  double me = 0.0;
+  for (int o = 0; o < 2; ++o) {
+    const double* qk = hq[o];
+    const double* qbk = hq[1 - o];
+    double mom[24];
+    if (lep_charge > 0) {
+      memcpy(mom, hbl, 32); memcpy(mom + 4, hl, 32); memcpy(mom + 8, hn, 32);
+      memcpy(mom + 12, hbh, 32); memcpy(mom + 16, qk, 32); memcpy(mom + 20, qbk, 32);
+    } else {
+      memcpy(mom, hbh, 32); memcpy(mom + 4, qbk, 32); memcpy(mom + 8, qk, 32);
+      memcpy(mom + 12, hbl, 32); memcpy(mom + 16, hl, 32); memcpy(mom + 20, hn, 32);
+    }
+    me += L.gg * or_tt_me2_gg(p, k1, k2, mom) + L.qq12 * or_tt_me2_qq(p, k1, k2, mom)
+        + L.qq21 * or_tt_me2_qq(p, k2, k1, mom);
+  }
+  me *= 3.0 * 2.0;
+  double shat = x1 * x2 * S;
+  double f = (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat) / (2.0 * nu[0]);
+  double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
+  return f * two_pi_pow * tf * jac / (2.0 * l[0]);
+}
+
+/* t tbar H dilepton (Sec. 4): as or_tthll_integrand, but x7 is the r map of
+ * the second Higgs jet's energy (as for t tbar b bbar) instead of the Higgs
+ * virtuality of Eq. mhsolve; the Higgs Breit-Wigner factor stays in
+ * |M|^2. */
+double or_tthll_direct_integrand(const or_params* p, const double* ev, int perm, const double* x)
+{
+  /* the t tbar b bbar branch of f2_integrand maps x7 that way; only the
+   * matrix element differs */
+  return f2_integrand_me(OR_KIND_TTH_LL, 1, p, ev, perm, x, NULL);
 }

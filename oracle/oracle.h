@@ -136,6 +136,13 @@ double or_ps_volume(int n, double sqrt_s, uint64_t seed, int64_t n_points, doubl
  * or_top_decay_spinsum); writes the MC error to err. */
 double or_top_width(const or_params* p, uint64_t seed, int64_t n_points, double* err);
 
+/* Partonic cross section of g g (channel 0) or q qbar (channel 1) -> t tbar
+ * -> b l+ nu bbar l- nubar at fixed sqrt(shat) from the decayed matrix
+ * element over the full six-body phase space (MC, n_points Philox points);
+ * writes the MC error to err.  In units of GeV^-2. */
+double or_tt_decayed_sigma(const or_params* p, int channel, double sqrt_shat, uint64_t seed, int64_t n_points,
+                           double* err);
+
 /* Parton-level weight of a ttbar dilepton event whose six final-state
  * partons are all known (transfer functions are delta functions, Sec. 4's
  * parton-level timing).  ev = b, bbar, l+, l-, nu, nubar as 6 x
@@ -212,7 +219,18 @@ double or_flow_nll_grad(const double* params, int n, const double* x, const doub
 
 /* -------------------------------------------------------------- driver -- */
 enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_KIND_TTH = 5,
-       OR_KIND_TTH_LL = 6, OR_KIND_TTBB_LL = 7 };
+       OR_KIND_TTH_LL = 6, OR_KIND_TTBB_LL = 7,
+       /* the same integrals in direct parametrisations (closure checks) */
+       OR_KIND_TT_DIRECT = 8, OR_KIND_TT_SL_DIRECT = 9, OR_KIND_TTH_LL_DIRECT = 10 };
+/* Direct parametrisations of the t tbar dilepton, t tbar semileptonic and
+ * t tbar H dilepton integrands (integrands.c): the unmeasured momenta
+ * themselves as variables, no constraint solve, Breit-Wigner factors left
+ * in |M|^2.  Same events, assignments and dimensions as the mapped kinds;
+ * their integrals over [0,1]^D are the same numbers. */
+double or_tt_direct_integrand(const or_params* p, const double* ev, int perm, const double* x);
+double or_tt_semilep_direct_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
+                                      const double* x);
+double or_tthll_direct_integrand(const or_params* p, const double* ev, int perm, const double* x);
 /* t tbar H (H -> b bbar) and t tbar b bbar, both tops decaying to b l nu
  * (Sec. 4's analysis): events b-jets 0-3, l+, l- as 6 x {E,px,py,pz};
  * assignments and variables in integrands.c (or_f2_perm: the event rows of

@@ -118,3 +118,68 @@ double or_top_width(const or_params* p, uint64_t seed, int64_t n_points, double*
   if (err) *err = sqrt(fmax(0.0, s2 / N - I * I) / (N - 1.0));
   return I;
 }
+
+/* Partonic cross section of g g (channel 0) or q qbar (channel 1) ->
+ * t tbar -> b l+ nu bbar l- nubar at fixed sqrt(shat), beams along z:
+ *   sigma = (1 / (2 shat)) int dPhi_6 |M|^2,
+ * with |M|^2 the oracle's decayed matrix element (or_tt_me2_gg / _qq: spin
+ * and colour averaged, couplings and the four Breit-Wigner factors
+ * included).  dPhi_6 is generated by the exact recursion
+ *   dPhi_6 = dPhi_2(shat; t, tbar) (dq_t^2 / 2 pi) (dq_tbar^2 / 2 pi)
+ *            dPhi_2(t; b, W+) (dq_W+^2 / 2 pi) dPhi_2(W+; l+, nu) x (tbar side),
+ * each virtuality through the Breit-Wigner tan map of its propagator over
+ * its kinematic range, each direction uniformly; dPhi_2 = |p*| / (4 pi M)
+ * after the angular integration.  Points outside the kinematic limits
+ * weigh 0. */
+static double tan_map(double u, double m, double w, double hi, double* q2)
+{
+  const double mw = m * w;
+  const double t0 = atan(-m * m / mw), t1 = atan((hi - m * m) / mw);
+  const double th = t0 + u * (t1 - t0);
+  *q2 = m * m + mw * tan(th);
+  const double d = *q2 - m * m;
+  return (t1 - t0) * (d * d + mw * mw) / mw;     /* dq2 / du */
+}
+
+double or_tt_decayed_sigma(const or_params* p, int channel, double sqrt_shat, uint64_t seed, int64_t n_points,
+                           double* err)
+{
+  const double rs = sqrt_shat, shat = rs * rs;
+  const double k1[4] = {0.5 * rs, 0.0, 0.0, 0.5 * rs}, k2[4] = {0.5 * rs, 0.0, 0.0, -0.5 * rs};
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t k = 0; k < n_points; ++k) {
+    double u[16];
+    or_uniforms(seed, (uint32_t)k, 0u, 0u, 9u, 16, u);
+    double q2t, q2tb, q2wp, q2wm;
+    double jac = tan_map(u[0], p->m_t, p->w_t, shat, &q2t) * tan_map(u[1], p->m_t, p->w_t, shat, &q2tb);
+    const double mt1 = sqrt(fmax(q2t, 0.0)), mt2 = sqrt(fmax(q2tb, 0.0));
+    double w = 0.0;
+    if (q2t > 0.0 && q2tb > 0.0 && mt1 + mt2 < rs) {
+      jac *= tan_map(u[2], p->m_w, p->w_w, q2t, &q2wp) * tan_map(u[3], p->m_w, p->w_w, q2tb, &q2wm);
+      if (q2wp > 0.0 && q2wm > 0.0 && q2wp < q2t && q2wm < q2tb) {
+        /* t tbar in the partonic frame */
+        const double lam = (shat - (mt1 + mt2) * (mt1 + mt2)) * (shat - (mt1 - mt2) * (mt1 - mt2));
+        const double pst = sqrt(lam) / (2.0 * rs);
+        const double c = 2.0 * u[4] - 1.0, sn = sqrt(fmax(0.0, 1.0 - c * c)), phi = 2.0 * M_PI * u[5];
+        const double pt[4] = {sqrt(pst * pst + q2t), pst * sn * cos(phi), pst * sn * sin(phi), pst * c};
+        const double ptb[4] = {sqrt(pst * pst + q2tb), -pt[1], -pt[2], -pt[3]};
+        double mom[24], W[4], Wb[4];
+        const double mw1 = sqrt(q2wp), mw2 = sqrt(q2wm);
+        const double p1 = split(pt, mt1, mw1, 2.0 * u[6] - 1.0, 2.0 * M_PI * u[7], mom + 0, W);
+        const double p2 = split(W, mw1, 0.0, 2.0 * u[8] - 1.0, 2.0 * M_PI * u[9], mom + 4, mom + 8);
+        const double p3 = split(ptb, mt2, mw2, 2.0 * u[10] - 1.0, 2.0 * M_PI * u[11], mom + 12, Wb);
+        const double p4 = split(Wb, mw2, 0.0, 2.0 * u[12] - 1.0, 2.0 * M_PI * u[13], mom + 16, mom + 20);
+        const double phase = (pst / (4.0 * M_PI * rs)) * (p1 / (4.0 * M_PI * mt1)) * (p2 / (4.0 * M_PI * mw1))
+                           * (p3 / (4.0 * M_PI * mt2)) * (p4 / (4.0 * M_PI * mw2))
+                           * jac / pow(2.0 * M_PI, 4.0);
+        const double me = channel == 0 ? or_tt_me2_gg(p, k1, k2, mom) : or_tt_me2_qq(p, k1, k2, mom);
+        w = phase * me / (2.0 * shat);
+      }
+    }
+    s1 += w;
+    s2 += w * w;
+  }
+  const double N = (double)n_points, I = s1 / N;
+  if (err) *err = sqrt(fmax(0.0, s2 / N - I * I) / (N - 1.0));
+  return I;
+}

@@ -62,12 +62,13 @@ class IntegrateOpts(ctypes.Structure):
                 ("timing_out", ctypes.c_void_p), ("chunk_points", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("flow", ctypes.c_void_p), ("ess_threshold", ctypes.c_double), ("allocation", ctypes.c_int32),
                 ("weights_out", ctypes.c_void_p), ("weights_stride", ctypes.c_int64),
-                ("weights_integral", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
+                ("weights_integral", ctypes.c_int32), ("weights_rows", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
                 ("checkpoint", ctypes.c_void_p), ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p)]
 
 
 MEM_HOOK_NONFINITE = 1
+
 
 # allocator hook signatures (mem_alloc_fn, mem_free_fn)
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -266,6 +267,9 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
+    if weights_out is not None and not (weights_out.is_cuda and weights_out.dtype == torch.float64
+                                        and weights_out.dim() == 2 and weights_out.is_contiguous()):
+        raise ValueError("weights_out must be a contiguous float64 device tensor [rows, stride]")
     ev = events_struct(comps, charge)
     procs = processes if isinstance(processes, (list, tuple)) else [processes]
     handles = (ctypes.c_void_p * len(procs))(*[p.handle.value for p in procs])
@@ -286,7 +290,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         chunk_points, use_graph, flow.handle.value if flow is not None else None, ess_threshold,
                         allocation,
                         weights_out.data_ptr() if weights_out is not None else None,
-                        weights_out.shape[-1] if weights_out is not None else 0, weights_integral, hooks, hook_event,
+                        weights_out.shape[-1] if weights_out is not None else 0, weights_integral,
+                        weights_out.shape[0] if weights_out is not None else 0, hooks, hook_event,
                         checkpoint.handle.value if checkpoint is not None else None,
                         ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
                         ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None)
@@ -295,6 +300,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                                       ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
            "mem_integrate_events")
     return P, err, status
+
 
 
 class Checkpoint:

@@ -706,12 +706,16 @@ class Workspace {
   }
   bool arena() const { return arena_ != nullptr; }
   size_t used() const { return used_; }
+  size_t capacity() const { return cap_; }
+  // bytes the call has asked the arena for, the refused requests included
+  size_t requested() const { return need_; }
   hipError_t get(void** p, size_t bytes)
   {
     bytes = bytes ? (bytes + 255) / 256 * 256 : 256;
     *p = nullptr;
     if (arena_) {
-      if (used_ + bytes > cap_) return hipErrorOutOfMemory;
+      need_ += bytes;
+      if (need_ > cap_) return hipErrorOutOfMemory;
       *p = arena_ + used_;
       used_ += bytes;
       return hipSuccess;
@@ -735,7 +739,7 @@ class Workspace {
   void* user_ = nullptr;
   hipStream_t s_ = nullptr;
   char* arena_ = nullptr;
-  size_t cap_ = 0, used_ = 0;
+  size_t cap_ = 0, used_ = 0, need_ = 0;
   std::vector<std::pair<void*, size_t>> blocks_;
 };
 
@@ -1005,10 +1009,12 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                                   Workspace& work);
 
 // ---------------------------------------------------------- integrate ----
-extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
-                                           const int64_t* n_points, int32_t n_np, int32_t n_iter,
-                                           const mem_integrate_opts* opt, double* p_out, double* err_out,
-                                           int32_t* status_out)
+// arena: null (work buffers from hipMalloc or the caller's allocator), or
+// the no-allocation entry point's scratch of arena_bytes
+static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                  const int64_t* n_points, int32_t n_np, int32_t n_iter,
+                                  const mem_integrate_opts* opt, double* p_out, double* err_out,
+                                  int32_t* status_out, void* arena, size_t arena_bytes)
 {
   mem_status st = check_event_arrays(ev);
   if (st != MEM_OK) return st;
@@ -1039,9 +1045,28 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
   if (o.flow && (o.weights_out || o.checkpoint || o.hooks))
     return fail(MEM_EUNSUPPORTED, "weights_out, checkpoints and hooks are VEGAS-only");
   if (n_ev == 0) return MEM_OK;
+  if (arena) {
+    if (o.flow) return fail(MEM_EUNSUPPORTED, "the no-allocation entry point integrates with VEGAS only");
+    if (o.timing_out) return fail(MEM_EUNSUPPORTED, "timing_out creates events: not in the no-allocation entry point");
+    if (o.alloc_fn) return fail(MEM_EINVAL, "the no-allocation entry point takes no allocator");
+    if (!ev->on_device || !o.outputs_on_device)
+      return fail(MEM_EINVAL, "the no-allocation entry point needs events and outputs in device memory");
+    // direct launches on the caller's stream: no graph, no stream of its own
+    o.use_graph = 0;
+    Workspace work((char*)arena, arena_bytes);
+    return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr, work);
+  }
   Workspace work(o.alloc_fn, o.free_fn, o.alloc_user, (hipStream_t)o.stream);
   if (o.flow) return integrate_flow(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, work);
   return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr, work);
+}
+
+extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                           const int64_t* n_points, int32_t n_np, int32_t n_iter,
+                                           const mem_integrate_opts* opt, double* p_out, double* err_out,
+                                           int32_t* status_out)
+{
+  return integrate_entry(ev, hyp, n_hyp, n_points, n_np, n_iter, opt, p_out, err_out, status_out, nullptr, 0);
 }
 
 // VEGAS over every event, or over the events with ev_mask[e] != 0 (host
@@ -1168,6 +1193,9 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   const uint32_t iter0 = resume ? ck->iter : 0u;
   // iterations this call runs: n_iter more, or up to max_iter in total
   const int run_iters = target_mode ? std::max<int>(0, iters - (int)iter0) : iters;
+  // the queue kernel writes row `iteration index` of weights_out
+  if (o.weights_out && (int64_t)iter0 + run_iters > (int64_t)o.weights_rows)
+    return fail(MEM_EINVAL, "weights_rows below the iterations the call can reach");
   // launch groups by matrix-element precision; queue order longest first
   std::vector<Group> groups;
   auto group_of = [&](int prec) {
@@ -1206,31 +1234,49 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       b_heads(&work), b_P(&work), b_err(&work), b_status(&work), b_alloc(&work), b_cover(&work), b_nev(&work);
   size_t qtotal = 0;
   for (auto& G : groups) qtotal += G.queue.size();
-  HIP_TRY(b_procs.alloc(ptab.size() * sizeof(ProcParams)));
-  HIP_TRY(b_ints.alloc(ints.size() * sizeof(IntegralDesc)));
-  HIP_TRY(b_chunks.alloc(chunks.size() * sizeof(Chunk)));
-  HIP_TRY(b_queue.alloc(qtotal * sizeof(int32_t)));
-  HIP_TRY(b_grids.alloc(grid_total * sizeof(double)));
-  HIP_TRY(b_parts.alloc(part_total * sizeof(double)));
-  HIP_TRY(b_state.alloc((size_t)n_int * ST_SIZE * sizeof(double)));
-  HIP_TRY(b_active.alloc((size_t)n_int * sizeof(int32_t)));
-  HIP_TRY(b_evi0.alloc((size_t)n_ev * sizeof(int64_t)));
-  HIP_TRY(b_evnp.alloc((size_t)n_ev * sizeof(int32_t)));
-  HIP_TRY(b_evnorm.alloc((size_t)n_ev * sizeof(double)));
-  HIP_TRY(b_done.alloc((size_t)n_ev * sizeof(int32_t)));
-  HIP_TRY(b_ctl.alloc(sizeof(Control)));
-  HIP_TRY(b_heads.alloc(groups.size() * sizeof(uint32_t)));
-  HIP_TRY(b_nev.alloc(sizeof(double)));
-  if (neyman) {
-    HIP_TRY(b_alloc.alloc((size_t)n_int * sizeof(int64_t)));
-    HIP_TRY(b_cover.alloc((size_t)n_int * sizeof(int64_t)));
+  // every work buffer is taken before the first copy or launch; the chunk
+  // table in queue order (the queue kernel reads it instead of gathering
+  // through the queue) included
+  DevBuf b_chunks_q(&work);
+  {
+    hipError_t ae = hipSuccess;
+    auto A = [&](DevBuf& b, size_t bytes) {
+      hipError_t e = b.alloc(bytes);
+      if (ae == hipSuccess) ae = e;
+    };
+    A(b_procs, ptab.size() * sizeof(ProcParams));
+    A(b_ints, ints.size() * sizeof(IntegralDesc));
+    A(b_chunks, chunks.size() * sizeof(Chunk));
+    A(b_queue, qtotal * sizeof(int32_t));
+    A(b_grids, grid_total * sizeof(double));
+    A(b_parts, part_total * sizeof(double));
+    A(b_state, (size_t)n_int * ST_SIZE * sizeof(double));
+    A(b_active, (size_t)n_int * sizeof(int32_t));
+    A(b_evi0, (size_t)n_ev * sizeof(int64_t));
+    A(b_evnp, (size_t)n_ev * sizeof(int32_t));
+    A(b_evnorm, (size_t)n_ev * sizeof(double));
+    A(b_done, (size_t)n_ev * sizeof(int32_t));
+    A(b_ctl, sizeof(Control));
+    A(b_heads, groups.size() * sizeof(uint32_t));
+    A(b_nev, sizeof(double));
+    A(b_chunks_q, qtotal * sizeof(Chunk));
+    if (neyman) {
+      A(b_alloc, (size_t)n_int * sizeof(int64_t));
+      A(b_cover, (size_t)n_int * sizeof(int64_t));
+    }
+    if (o.outputs_on_device == 0) {
+      A(b_P, n_ev * sizeof(double));
+      A(b_err, n_ev * sizeof(double));
+      A(b_status, n_ev * sizeof(int32_t));
+    }
+    if (ae != hipSuccess && work.arena())
+      return fail(MEM_ENOMEM, "the work buffers of this call take " + std::to_string(work.requested()) +
+                                  " bytes, more than the " + std::to_string(work.capacity()) +
+                                  "-byte scratch of the no-allocation entry point: integrate fewer events, "
+                                  "assignments or points per call");
+    HIP_TRY(ae);
   }
   const bool out_dev = o.outputs_on_device != 0;
-  if (!out_dev) {
-    HIP_TRY(b_P.alloc(n_ev * sizeof(double)));
-    HIP_TRY(b_err.alloc(n_ev * sizeof(double)));
-    HIP_TRY(b_status.alloc(n_ev * sizeof(int32_t)));
-  }
   std::vector<int32_t> flat;
   std::vector<size_t> gq0;
   for (auto& G : groups) { gq0.push_back(flat.size()); flat.insert(flat.end(), G.queue.begin(), G.queue.end()); }
@@ -1254,6 +1300,9 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   {
     const int64_t ns = (int64_t)n_int * ST_SIZE;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, ws, b_state.as<double>(), ns, 0.0);
+    // chunk partials start at zero (the buffer may hold an earlier call's)
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((part_total + 255) / 256)), dim3(256), 0, ws,
+                       b_parts.as<double>(), part_total, 0.0);
     hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n_int + 255) / 256)), dim3(256), 0, ws,
                        b_active.as<int32_t>(), (int64_t)n_int, 1);
     hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n_ev + 255) / 256)), dim3(256), 0, ws,
@@ -1291,8 +1340,6 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   // chunk order through the queue: the kernel reads chunks[queue[c]]; the
   // queue kernel takes the chunk table permuted on the device instead
   // (one gather per call)
-  DevBuf b_chunks_q(&work);
-  HIP_TRY(b_chunks_q.alloc(flat.size() * sizeof(Chunk)));
   std::vector<size_t> gqn(groups.size());     // queue length per group
   {
     std::vector<Chunk> perm_chunks(flat.size());

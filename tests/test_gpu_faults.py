@@ -147,3 +147,20 @@ def test_torch_allocator(mem):
     assert torch.cuda.memory_allocated() == before
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
+
+
+def test_weights_out_shape_checked(mem):
+    """weights_out with fewer rows than the call's iterations, or a stride
+    below the integral's points, is refused before any launch"""
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    d = events.ttbar_dilepton(2, 49)
+    comps = mem.to_components(d["obs"]).cuda()
+    say("weights_out shape checks")
+    for rows, stride in ((2, 4096), (3, 4095)):
+        w = torch.zeros((rows, stride), dtype=torch.float64, device="cuda")
+        with pytest.raises(mem.MemError):
+            mem.integrate_events(comps, p, 8192, 3, weights_out=w, weights_integral=0)
+    w = torch.zeros((3, 4096), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, p, 8192, 3, weights_out=w, weights_integral=3)
+    torch.cuda.synchronize()
+    assert torch.any(w != 0.0), "the weights of the integral are recorded"

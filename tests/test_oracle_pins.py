@@ -147,6 +147,34 @@ def test_refine_matches_damped_rebinning_by_hand():
     assert np.allclose(got[1:64], want, rtol=0, atol=1e-13)
 
 
+def test_refine_converges_to_inverse_cdf():
+    """Iterated refinement on a separable product peak prod_d g_d(x_d),
+    g_d = a / (1 + a^2 (x - c_d)^2): each bin of the adapted grid ends up
+    holding an equal share of int |g_d| (the map's density follows |g_d|),
+    so the edges approach the inverse CDF
+        G_d^-1(k/64) = c_d + tan(k/64 (atan(a (1 - c_d)) + atan(a c_d)) - atan(a c_d)) / a,
+    to a fraction of the local bin width, and the weights' spread falls by
+    two orders of magnitude.  Lepage's damping only sets how fast the grid
+    gets there; a rule that misplaced the new edges (interpolation inside
+    the old bins, the cumulative importance, the smoothing's indices) ends
+    elsewhere."""
+    p = oracle.dy_params()
+    g0 = oracle.uniform_grid(4)
+    r, Is, Vs, g = oracle.integrate_one(oracle.KIND_GENZ, p, np.zeros(4), 0, 7, 0, 200000, 15, grid=g0)
+    a = 20.0
+    k = np.arange(65) / 64
+    for d in range(4):
+        c = 0.3 + 0.1 * d
+        tot = math.atan(a * (1 - c)) + math.atan(a * c)
+        inv = c + np.tan(k * tot - math.atan(a * c)) / a
+        w = np.diff(inv)
+        local = np.concatenate([[w[0]], np.minimum(w[:-1], w[1:]), [w[-1]]])
+        dev = np.abs(g[d] - inv) / local
+        assert dev.max() < 0.3, (d, dev.max())
+    rel = np.sqrt(Vs) / Is
+    assert rel[-1] < 0.02 * rel[0], rel
+
+
 def test_vegas_genz_product_peak():
     """VEGAS on a separable product peak: estimate within 3 sigma of the
     exact integral, and the adapted error far below plain MC."""
@@ -839,6 +867,42 @@ def test_top_width_from_decay_phase_space():
     v, err = oracle.top_width(p, 0x70b, 400000)
     assert abs(v - want) < 4 * err + 2e-3 * want, (v, want, err)
     assert err < 3e-3 * want
+
+
+@pytest.mark.parametrize("channel", [0, 1])
+def test_decayed_me_narrow_width_factorisation(channel):
+    """The decayed t tbar matrix element integrated over the full six-body
+    phase space, sigma = (1/(2 shat)) int dPhi_6 |M|^2 (or_tt_me2_gg / _qq),
+    tends for Gamma/M -> 0 to the on-shell production cross section times
+    the two decay branching fractions:
+      sigma -> sigma(ij -> t tbar) [Gamma(t -> bW) Gamma(W -> l nu) / (Gamma_W Gamma_t)]^2,
+    with Ellis-Stirling-Webber's closed forms
+      sigma_gg = pi a_s^2/(3 s) [(1 + rho + rho^2/16) ln((1+b)/(1-b)) - b (7/4 + 31 rho/16)],
+      sigma_qq = 8 pi a_s^2/(27 s) b (1 + rho/2),     rho = 4 m_t^2/s, b = sqrt(1 - rho),
+    and the decay widths' closed forms.  Every factor of the decayed matrix
+    element enters: couplings, the spin sums of production and decays, the
+    initial-state averages and the four Breit-Wigner factors.  Widths scaled
+    by 1e-2 put the off-shell corrections (O(Gamma/M)) below the MC error."""
+    eps = 1e-2
+    p = oracle.tt_params(w_t=1.4 * eps, w_w=2.1 * eps)
+    gf, mt, mw, a_s = p.g_fermi, p.m_t, p.m_w, p.alpha_s
+    r = mw * mw / (mt * mt)
+    g_tbw = gf * mt ** 3 / (8 * math.sqrt(2) * math.pi) * (1 - r) ** 2 * (1 + 2 * r)
+    g_wlnu = gf * mw ** 3 / (6 * math.sqrt(2) * math.pi)
+    br = g_tbw * g_wlnu / (p.w_t * p.w_w)
+    for rs in (400.0, 700.0):
+        s = rs * rs
+        rho = 4 * mt * mt / s
+        b = math.sqrt(1 - rho)
+        if channel == 0:
+            prod = math.pi * a_s ** 2 / (3 * s) * ((1 + rho + rho * rho / 16) * math.log((1 + b) / (1 - b))
+                                                   - b * (7 / 4 + 31 * rho / 16))
+        else:
+            prod = 8 * math.pi * a_s ** 2 / (27 * s) * b * (1 + rho / 2)
+        want = prod * br * br
+        v, err = oracle.tt_decayed_sigma(p, channel, rs, 0xa11 + channel, 60000)
+        assert err < 5e-3 * want
+        assert abs(v - want) < 4 * err + 5e-4 * want, (rs, v / want, err / want)
 
 
 # ----------------------------------------------------------- PDF grids ----
