@@ -358,6 +358,36 @@ mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, in
                                 const mem_integrate_opts* opt,
                                 double* p_out, double* err_out, int32_t* status_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mem_integrate_events with every work buffer (process table, work queue,
+ * grids, chunk partials, running state) placed in a fixed scratch array of
+ * MEM_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on, from the first call on that device until the process ends.  The call
+ * allocates no device memory, creates no stream, graph or event, and runs
+ * the iterations as direct launches on opt->stream (NULL: the null stream)
+ * of the current device.
+ *   Arguments and results as mem_integrate_events, with these limits: opt
+ *   is required, events (ev->on_device) and outputs (opt->outputs_on_device)
+ *   are device memory, VEGAS only (opt->flow: MEM_EUNSUPPORTED), no
+ *   timing_out (MEM_EUNSUPPORTED), no allocator hook (MEM_EINVAL).  A call
+ *   whose work buffers exceed the scratch returns MEM_ENOMEM before any copy
+ *   or launch, with the bytes it would need in mem_last_error (the buffers
+ *   grow with the number of integrals and of work-queue chunks: about
+ *   2 + 64 D doubles per chunk of chunk_points points, some 75 KB per
+ *   dilepton event at 65 536 points per iteration under the equal split
+ *   and twice that under Neyman allocation).
+ *   Every call on a device shares that device's scratch, which keeps the
+ *   last call's contents (the call initialises what it reads).  Calls that
+ *   overlap in time on one device (other host threads, other streams) race
+ *   on it: the caller serialises them.  Returns after opt->stream has
+ *   completed the call's work. */
+#define MEM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+mem_status mem_integrate_events_noalloc(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                        const int64_t* n_points, int32_t n_np, int32_t n_iter,
+                                        const mem_integrate_opts* opt, double* p_out, double* err_out,
+                                        int32_t* status_out);
+
 /* Checkpoints of VEGAS integrations (per-integral grids, cumulative sums,
  * iteration counter, retired events and allocations, held in host memory).
  * create: an empty handle.  save: write the state to a file (MEM_EINVAL for

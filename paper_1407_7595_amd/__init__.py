@@ -25,7 +25,7 @@ FLOW_CONTEXT = 24
 
 # every symbol include/mem.h declares
 EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_process",
-           "mem_process_shape", "mem_integrate_events", "mem_uniforms", "mem_eval_points",
+           "mem_process_shape", "mem_integrate_events", "mem_integrate_events_noalloc", "mem_uniforms", "mem_eval_points",
            "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
@@ -69,6 +69,8 @@ class IntegrateOpts(ctypes.Structure):
 
 MEM_HOOK_NONFINITE = 1
 
+# bytes of the per-device scratch of mem_integrate_events_noalloc
+MEM_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 # allocator hook signatures (mem_alloc_fn, mem_free_fn)
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -110,6 +112,7 @@ def lib():
             "mem_destroy_process": (None, [P]),
             "mem_process_shape": (I32, [P, P, P]),
             "mem_integrate_events": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
+            "mem_integrate_events_noalloc": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
             "mem_uniforms": (I32, [U64, U32, U32, U32, I32, I64, P, P]),
             "mem_eval_points": (I32, [P, P, I32, I32, P, I64, P, P, P]),
             "mem_discriminant": (I32, [P, P, I64, P, P]),
@@ -254,7 +257,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
                      allocation=0, weights_out=None, weights_integral=0, hooks=0, hook_event=0,
-                     checkpoint=None, allocator=None):
+                     checkpoint=None, allocator=None, _noalloc=False):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
@@ -295,12 +298,21 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         checkpoint.handle.value if checkpoint is not None else None,
                         ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
                         ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None)
-    _check(lib().mem_integrate_events(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
-                                      ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
-                                      ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
-           "mem_integrate_events")
+    entry = "mem_integrate_events_noalloc" if _noalloc else "mem_integrate_events"
+    _check(getattr(lib(), entry)(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
+                                 ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),
+                                 ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(status.data_ptr())),
+           entry)
     return P, err, status
 
+
+def integrate_events_noalloc(comps, processes, n_points, n_iter, outputs=None, **kw):
+    """mem_integrate_events_noalloc: integrate_events with every work buffer
+    in the library's fixed per-device scratch (no device allocation by the
+    library).  comps and the outputs must be device tensors; the returned
+    outputs are allocated here by torch unless `outputs` = (P, err, status)
+    is given.  VEGAS only; no timing, no allocator."""
+    return integrate_events(comps, processes, n_points, n_iter, outputs=outputs, _noalloc=True, **kw)
 
 
 class Checkpoint:

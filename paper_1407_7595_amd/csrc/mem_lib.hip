@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
@@ -1067,6 +1068,50 @@ extern "C" mem_status mem_integrate_events(const mem_events* ev, const mem_proce
                                            int32_t* status_out)
 {
   return integrate_entry(ev, hyp, n_hyp, n_points, n_np, n_iter, opt, p_out, err_out, status_out, nullptr, 0);
+}
+
+// ------------------------------------------------------- no allocation ----
+// The work buffers of mem_integrate_events_noalloc live in this array: one
+// copy per device, held until the process ends.  In host code its name is
+// not a device address; the address of the current device's copy comes
+// from hipGetSymbolAddress, once per device, and only that address is
+// handed to kernels and copies.
+static __device__ __align__(256) char scratch[MEM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+mem_status scratch_of_current_device(void** out)
+{
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(MEM_EDEVICE, "device number outside the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(MEM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MEM_OK;
+}
+}  // namespace
+
+extern "C" mem_status mem_integrate_events_noalloc(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
+                                                   const int64_t* n_points, int32_t n_np, int32_t n_iter,
+                                                   const mem_integrate_opts* opt, double* p_out, double* err_out,
+                                                   int32_t* status_out)
+{
+  if (!opt) return fail(MEM_EINVAL, "the no-allocation entry point needs options (device outputs, stream)");
+  void* base = nullptr;
+  const mem_status st = scratch_of_current_device(&base);
+  if (st != MEM_OK) return st;
+  return integrate_entry(ev, hyp, n_hyp, n_points, n_np, n_iter, opt, p_out, err_out, status_out, base,
+                         (size_t)MEM_NOALLOC_SCRATCH_BYTES);
 }
 
 // VEGAS over every event, or over the events with ev_mask[e] != 0 (host
