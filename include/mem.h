@@ -314,7 +314,11 @@ void mem_destroy_process(mem_process p);
  *          process returns MEM_EINVAL on another current device.  NULL
  *          restores the built-in toy densities.
  *  nx, nq  >= 2 each; nx * nq <= 2^22
- *  bounds  ln x and ln Q ranges (natural logarithms), increasing
+ *  bounds  ln x and ln Q ranges (natural logarithms), increasing; the
+ *          first and last nodes sit on them.  A table laid out for a reader
+ *          that steps by (max - min)/n (nodes at min + i (max - min)/n,
+ *          i < n, as the paper's interpolation listing does) is the same
+ *          grid with the upper bound min + (n - 1)(max - min)/n: pass that.
  * Outside the grid the edge cells extrapolate linearly.  Factorisation
  * scale (not stated in the paper): the muon pair mass for Drell-Yan, m_t
  * for the top processes.  Errors: MEM_EINVAL for a null process or bounds,

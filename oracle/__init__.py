@@ -191,6 +191,9 @@ def _declare(L):
         "or_colour_fabc": (D, [I, I, I]),
         "or_f2_perm": (None, [I, I, P]),
         "or_tthll_integrand": (D, [P, P, I, P, P]),
+        "or_tt_direct_integrand": (D, [P, P, I, P]),
+        "or_tt_semilep_direct_integrand": (D, [P, P, I, I, P, I]),
+        "or_tthll_direct_integrand": (D, [P, P, I, P]),
         "or_ttbbll_integrand": (D, [P, P, I, P, P]),
         "or_f2_parton_weight": (D, [I, P, P]),
         "or_flow_forward": (D, [P, P, P, P]),
@@ -523,6 +526,31 @@ def tthll_integrand(p, ev, perm, x):
     ns = ctypes.c_int(0)
     v = lib().or_tthll_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x), ctypes.byref(ns))
     return v, ns.value
+
+
+SL_DIRECT_EB = 1
+SL_DIRECT_NU = 2
+SL_DIRECT_EBH = 4
+
+
+def tt_direct_integrand(p, ev, perm, x):
+    """t tbar dilepton integrand in (nu_x, nu_y, nu_z, nubar_z) directly"""
+    ev, x = _f64(ev), _f64(x)
+    return lib().or_tt_direct_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x))
+
+
+def sl_direct_integrand(p, ev, perm, x, mode, charge=0):
+    """semileptonic integrand with the energy of light jet b (SL_DIRECT_EB),
+    of the hadronic top's b (SL_DIRECT_EBH) and/or nu_z (SL_DIRECT_NU) as
+    variables"""
+    ev, x = _f64(ev), _f64(x)
+    return lib().or_tt_semilep_direct_integrand(ctypes.byref(p), _ptr(ev), charge, perm, _ptr(x), mode)
+
+
+def tthll_direct_integrand(p, ev, perm, x):
+    """t tbar H dilepton integrand with x7 the second Higgs jet's r"""
+    ev, x = _f64(ev), _f64(x)
+    return lib().or_tthll_direct_integrand(ctypes.byref(p), _ptr(ev), perm, _ptr(x))
 
 
 def ttbbll_integrand(p, ev, perm, x):

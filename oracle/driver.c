@@ -25,7 +25,7 @@ static double integrand(int kind, const or_params* p, const double* ev, int perm
   if (kind == OR_KIND_TTH_LL) return or_tthll_integrand(p, ev, perm, x, NULL);
   if (kind == OR_KIND_TTBB_LL) return or_ttbbll_integrand(p, ev, perm, x, NULL);
   if (kind == OR_KIND_TT_DIRECT) return or_tt_direct_integrand(p, ev, perm, x);
-  if (kind == OR_KIND_TT_SL_DIRECT) return or_tt_semilep_direct_integrand(p, ev, 0, perm, x);
+  if (kind == OR_KIND_TT_SL_DIRECT) return or_tt_semilep_direct_integrand(p, ev, 0, perm, x, OR_SL_DIRECT_EB | OR_SL_DIRECT_EBH | OR_SL_DIRECT_NU);
   if (kind == OR_KIND_TTH_LL_DIRECT) return or_tthll_direct_integrand(p, ev, perm, x);
   return or_tt_integrand(p, ev, perm, x, NULL);
 }

@@ -1234,43 +1234,13 @@ double or_tt_direct_integrand(const or_params* p, const double* ev, int perm, co
   return f * two_pi_pow * lep * jetf * jnu;
 }
 
-/* ttbar semileptonic: all four jet energies through their r maps (x0: light
- * jet a, x1: light jet b, x2: b of the hadronic top, x3: b of the leptonic
- * top, each over its TF window), x4, x5 recoil as in
- * or_tt_semilep_integrand, x6 -> nu_z (nu_T = MET): the measure
- * d^3nu/(2E) with the transverse delta function leaves dnu_z / (2E). */
-double or_tt_semilep_direct_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
-                                      const double* x)
+/* ttbar semileptonic: (2/S)(E/E') sum |M|^2 x PDFs / (2 shat) of one
+ * configuration of the six final-state momenta (zero when x1 or x2 leaves
+ * (0, 1]); the body of or_tt_semilep_integrand's solution loop. */
+static double sl_config_weight(const or_params* p, int lep_charge, const double* qa, const double* qb,
+                               const double* bh, const double* bl, const double* l, const double* nu)
 {
   const double S = p->sqrt_s * p->sqrt_s;
-  if (lep_charge == 0) lep_charge = ev[20] > 0 ? 1 : -1;
-  int ibl, ibh, ja, jb;
-  or_semilep_perm(perm, &ibl, &ibh, &ja, &jb);
-  const double* l = ev + 16;
-  double qa[4], qb[4], bh[4], bl[4];
-  const int idx[4] = {ja, jb, ibh, ibl};
-  double* dst[4] = {qa, qb, bh, bl};
-  double tf = 1.0, jac = 1.0;
-  for (int k = 0; k < 4; ++k) {
-    const double* m = ev + 4 * idx[k];
-    const double lo = k < 2 ? p->lj_r_lo : p->r_lo, hi = k < 2 ? p->lj_r_hi : p->r_hi;
-    double r = lo + x[k] * (hi - lo);
-    double pm = norm3(m), E = m[0] / r;
-    jac *= (hi - lo) * m[0] / (r * r);
-    dst[k][0] = E;
-    for (int i = 0; i < 3; ++i) dst[k][i + 1] = E * m[i + 1] / pm;
-    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
-    double T = k < 2 ? or_dgauss_tf(m[0], E, p->lj_core, p->lj_tail, p->lj_ftail)
-                     : or_gauss_tf(m[0], E, p->tf_sigma);
-    tf *= E * E * sin_th * T / (2.0 * E);
-  }
-  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
-  double phi = 2.0 * M_PI * x[5];
-  double nu[4];
-  nu[1] = rho * cos(phi) - (qa[1] + qb[1] + bh[1] + bl[1] + l[1]);
-  nu[2] = rho * sin(phi) - (qa[2] + qb[2] + bh[2] + bl[2] + l[2]);
-  nu[3] = cauchy_map(x[6], 0.0, 100.0, &jac);
-  nu[0] = norm3(nu);
   double P[4];
   for (int i = 0; i < 4; ++i) P[i] = qa[i] + qb[i] + bh[i] + bl[i] + l[i] + nu[i];
   double Eh = sqrt(P[0] * P[0] - P[1] * P[1] - P[2] * P[2]);
@@ -1303,9 +1273,106 @@ double or_tt_semilep_direct_integrand(const or_params* p, const double* ev, int 
   }
   me *= 3.0 * 2.0;
   double shat = x1 * x2 * S;
-  double f = (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat) / (2.0 * nu[0]);
+  return (2.0 / S) * (P[0] / Eh) * me / (2.0 * shat);
+}
+
+/* ttbar semileptonic with parts of the parametrisation made direct.
+ * mode & OR_SL_DIRECT_EB: x1 is the r map of light jet b (over its TF
+ * window) instead of the hadronic W virtuality; mode & OR_SL_DIRECT_EBH: x2
+ * is the r map of the hadronic top's b instead of the hadronic top
+ * virtuality; mode & OR_SL_DIRECT_NU: x6 -> nu_z (Cauchy map; nu_T = MET,
+ * the measure d^3nu/(2E) with the transverse delta function leaving
+ * dnu_z/(2E)) instead of the leptonic W virtuality and the nu_z quadratic.
+ * x0, x3 (r maps of light jet a and of the leptonic top's b) and x4, x5
+ * (recoil) as in or_tt_semilep_integrand, which mode 0 reproduces. */
+double or_tt_semilep_direct_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
+                                      const double* x, int mode)
+{
+  const double S = p->sqrt_s * p->sqrt_s;
+  if (lep_charge == 0) lep_charge = ev[20] > 0 ? 1 : -1;
+  int ibl, ibh, ja, jb;
+  or_semilep_perm(perm, &ibl, &ibh, &ja, &jb);
+  const double* l = ev + 16;
+  const int idx[4] = {ja, jb, ibh, ibl};
+  double dir[4][3], em[4];
+  for (int k = 0; k < 4; ++k) {
+    const double* m = ev + 4 * idx[k];
+    const double pm = norm3(m);
+    em[k] = m[0];
+    for (int i = 0; i < 3; ++i) dir[k][i] = m[i + 1] / pm;
+  }
+  double E4[4], jac = 1.0;
+  /* r = E_meas / E over [lo, hi] */
+  #define R_MAP(k, xv, lo, hi) do { const double r_ = (lo) + (xv) * ((hi) - (lo)); \
+      E4[k] = em[k] / r_; jac *= ((hi) - (lo)) * em[k] / (r_ * r_); } while (0)
+  R_MAP(0, x[0], p->lj_r_lo, p->lj_r_hi);
+  R_MAP(3, x[3], p->r_lo, p->r_hi);
+  const double ca = dir[0][0] * dir[1][0] + dir[0][1] * dir[1][1] + dir[0][2] * dir[1][2];
+  if (!(1.0 - ca > 0.0)) return 0.0;
+  double q2wh;
+  if (mode & OR_SL_DIRECT_EB) {
+    R_MAP(1, x[1], p->lj_r_lo, p->lj_r_hi);
+    q2wh = 2.0 * E4[0] * E4[1] * (1.0 - ca);
+  } else {
+    jac *= or_bw_map(x[1], p->m_w, p->w_w, 0.0, S, &q2wh);
+    E4[1] = q2wh / (2.0 * E4[0] * (1.0 - ca));
+    jac *= 1.0 / (2.0 * E4[0] * (1.0 - ca));
+    const double rr = em[1] / E4[1];
+    if (rr < p->lj_r_lo || rr > p->lj_r_hi) return 0.0;
+  }
+  if (mode & OR_SL_DIRECT_EBH) {
+    R_MAP(2, x[2], p->r_lo, p->r_hi);
+  } else {
+    double q2th;
+    jac *= or_bw_map(x[2], p->m_t, p->w_t, 0.0, S, &q2th);
+    const double W[4] = {E4[0] + E4[1], E4[0] * dir[0][0] + E4[1] * dir[1][0],
+                         E4[0] * dir[0][1] + E4[1] * dir[1][1], E4[0] * dir[0][2] + E4[1] * dir[1][2]};
+    const double den = 2.0 * (W[0] - (dir[2][0] * W[1] + dir[2][1] * W[2] + dir[2][2] * W[3]));
+    if (!(den > 0.0)) return 0.0;
+    E4[2] = (q2th - q2wh) / den;
+    if (!(E4[2] > 0.0)) return 0.0;
+    jac *= 1.0 / den;
+    const double rr = em[2] / E4[2];
+    if (rr < p->r_lo || rr > p->r_hi) return 0.0;
+  }
+  #undef R_MAP
+  double qa[4], qb[4], bh[4], bl[4];
+  double* dst[4] = {qa, qb, bh, bl};
+  double tf = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    const double* m = ev + 4 * idx[k];
+    double pm = norm3(m), E = E4[k];
+    dst[k][0] = E;
+    for (int i = 0; i < 3; ++i) dst[k][i + 1] = E * m[i + 1] / pm;
+    double sin_th = sqrt(m[1] * m[1] + m[2] * m[2]) / pm;
+    double T = k < 2 ? or_dgauss_tf(m[0], E, p->lj_core, p->lj_tail, p->lj_ftail)
+                     : or_gauss_tf(m[0], E, p->tf_sigma);
+    tf *= E * E * sin_th * T / (2.0 * E);
+  }
+  double rho = p->sigma_k * sqrt(-2.0 * log(1.0 - x[4]));
+  double phi = 2.0 * M_PI * x[5];
+  double nx = rho * cos(phi) - (qa[1] + qb[1] + bh[1] + bl[1] + l[1]);
+  double ny = rho * sin(phi) - (qa[2] + qb[2] + bh[2] + bl[2] + l[2]);
+  double sum = 0.0;
+  if (mode & OR_SL_DIRECT_NU) {
+    double nu[4] = {0.0, nx, ny, 0.0};
+    nu[3] = cauchy_map(x[6], 0.0, 100.0, &jac);
+    nu[0] = norm3(nu);
+    sum = sl_config_weight(p, lep_charge, qa, qb, bh, bl, l, nu) / (2.0 * nu[0]);
+  } else {
+    double q2wl;
+    jac *= or_bw_map(x[6], p->m_w, p->w_w, 0.0, S, &q2wl);
+    double nzs[2];
+    int nroot = or_semilep_nu_z(l, nx, ny, q2wl, nzs);
+    for (int s = 0; s < nroot; ++s) {
+      double nu[4] = {sqrt(nx * nx + ny * ny + nzs[s] * nzs[s]), nx, ny, nzs[s]};
+      double dq = fabs(2.0 * (l[0] * nzs[s] / nu[0] - l[3]));
+      if (!(dq > 0.0)) continue;
+      sum += sl_config_weight(p, lep_charge, qa, qb, bh, bl, l, nu) / dq / (2.0 * nu[0]);
+    }
+  }
   double two_pi_pow = pow(2.0 * M_PI, 4.0 - 3.0 * 6.0);
-  return f * two_pi_pow * tf * jac / (2.0 * l[0]);
+  return sum * two_pi_pow * tf * jac / (2.0 * l[0]);
 }
 
 /* t tbar H dilepton (Sec. 4): as or_tthll_integrand, but x7 is the r map of

@@ -228,8 +228,9 @@ enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_K
  * in |M|^2.  Same events, assignments and dimensions as the mapped kinds;
  * their integrals over [0,1]^D are the same numbers. */
 double or_tt_direct_integrand(const or_params* p, const double* ev, int perm, const double* x);
+enum { OR_SL_DIRECT_EB = 1, OR_SL_DIRECT_NU = 2, OR_SL_DIRECT_EBH = 4 };
 double or_tt_semilep_direct_integrand(const or_params* p, const double* ev, int lep_charge, int perm,
-                                      const double* x);
+                                      const double* x, int mode);
 double or_tthll_direct_integrand(const or_params* p, const double* ev, int perm, const double* x);
 /* t tbar H (H -> b bbar) and t tbar b bbar, both tops decaying to b l nu
  * (Sec. 4's analysis): events b-jets 0-3, l+, l- as 6 x {E,px,py,pz};

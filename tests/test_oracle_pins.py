@@ -905,6 +905,124 @@ def test_decayed_me_narrow_width_factorisation(channel):
         assert abs(v - want) < 4 * err + 5e-4 * want, (rs, v / want, err / want)
 
 
+# ------------------------------------------- closure of the integrands ----
+# Eq. integrand is one integral over the unmeasured momenta; the mapped
+# integrands write it in propagator-aligned variables with the constraint
+# solves (Eq. dilepsolv, the nu_z quadratic, Eq. mhsolve) and their
+# Jacobians.  The same integral written directly in the momenta (the
+# oracle's direct kinds: no solve, no Breit-Wigner maps, the Breit-Wigner
+# factors left in |M|^2) must give the same number: any dropped or extra
+# factor of the change of variables (a Jacobian, its power, a 1/(2E), a
+# missing solution) breaks the equality.
+def test_closure_dilepton_direct_parametrisation():
+    """t tbar dilepton: the 8D mapped integral (Eq. dilepsolv solve) equals
+    the 8D integral over (nu_x, nu_y, nu_z, nubar_z) with the transverse
+    delta function, per (event, assignment), within the combined VEGAS
+    errors.  Widths of 20 (top) and 15 GeV (W) let plain VEGAS converge on
+    the direct side; the identity holds for any width."""
+    from concurrent.futures import ThreadPoolExecutor
+    p = oracle.tt_params(w_t=20.0, w_w=15.0)
+    obs = events.ttbar_dilepton(4, 0xc105e)["obs"]
+    jobs = [(e, pm) for e in range(4) for pm in (0, 1)]
+
+    def run(args):
+        kind, n, (e, pm) = args
+        r, _, _, _ = oracle.integrate_one(kind, p, obs[e], pm, 11, e, n, 8)
+        return r.I, r.sigma
+
+    with ThreadPoolExecutor(8) as ex:
+        mapped = list(ex.map(run, [(oracle.KIND_TT, 30000, j) for j in jobs]))
+        direct = list(ex.map(run, [(oracle.KIND_TT_DIRECT, 80000, j) for j in jobs]))
+    rel = []
+    for j, (a, sa), (b, sb) in zip(jobs, mapped, direct):
+        assert a > 0 and b > 0, j
+        pull = (a - b) / math.hypot(sa, sb)
+        assert abs(pull) < 4.0, (j, a, b, sa / a, sb / b)
+        rel.append((a - b) / b)
+    assert abs(np.mean(rel)) < 0.02, rel
+
+
+def _slices(fn_pairs, n_found, rng, draw, axis):
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        _slices_quad(fn_pairs, n_found, rng, draw, axis)
+
+
+def _slices_quad(fn_pairs, n_found, rng, draw, axis):
+    from scipy import integrate
+    done = 0
+    tries = 0
+    while done < n_found:
+        tries += 1
+        assert tries < 400
+        ev, perm, x = draw(rng)
+        fa, fb = fn_pairs(ev, perm)
+
+        def on(f):
+            def g(t):
+                y = x.copy()
+                y[axis] = t
+                return f(y)
+            return g
+
+        if max(on(fa)(t) for t in np.linspace(0.02, 0.98, 25)) == 0.0:
+            continue
+        a = integrate.quad(on(fa), 0, 1, limit=500, epsabs=0, epsrel=1e-10)[0]
+        b = integrate.quad(on(fb), 0, 1, limit=500, epsabs=0, epsrel=1e-10)[0]
+        assert abs(a - b) <= 1e-6 * abs(a), (axis, perm, a, b)
+        done += 1
+
+
+def test_closure_semileptonic_slices():
+    """t tbar semileptonic, one change of variables at a time, each checked
+    as a 1D integral at fixed values of the other variables (adaptive
+    quadrature to 1e-10):
+      nu_z:  the leptonic W virtuality with the nu_z quadratic (both roots,
+             Jacobian |d q^2 / d nu_z|) against nu_z itself;
+      E_bh:  the hadronic top virtuality against the hadronic b's energy
+             (at a fixed hadronic W virtuality);
+      E_b:   the hadronic W virtuality against light jet b's energy (at a
+             fixed hadronic b energy).
+    The three changes compose the semileptonic map; mode 0 of the direct
+    integrand is the mapped integrand itself."""
+    p = oracle.tt_params()
+    obs = events.ttbar_semileptonic(4, 0xc1060)["obs"]
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        e, perm, x = int(rng.integers(4)), int(rng.integers(12)), rng.random(7)
+        a = oracle.sl_integrand(p, obs[e], perm, x)[0]
+        b = oracle.sl_direct_integrand(p, obs[e], perm, x, 0)
+        assert abs(a - b) <= 1e-14 * abs(a)
+    E, N, H = oracle.SL_DIRECT_EB, oracle.SL_DIRECT_NU, oracle.SL_DIRECT_EBH
+
+    def draw(r):
+        return obs[int(r.integers(4))], int(r.integers(12)), r.random(7)
+
+    for axis, m1, m2 in ((6, 0, N), (2, 0, H), (1, H, E | H)):
+        pairs = (lambda ev, pm, m1=m1, m2=m2: (lambda y: oracle.sl_direct_integrand(p, ev, pm, y, m1),
+                                               lambda y: oracle.sl_direct_integrand(p, ev, pm, y, m2)))
+        _slices(pairs, 3, rng, draw, axis)
+
+
+def test_closure_tth_mhsolve_slices():
+    """t tbar H dilepton (Sec. 4): the Higgs virtuality of Eq. mhsolve (the
+    second Higgs jet's energy solved from it, Jacobian 1/(2 E_1 (1 -
+    cos w12))) against that jet's energy itself, as 1D integrals at fixed
+    values of the other seven variables.  Higgs width 1 GeV for the
+    quadrature; the identity holds for any width."""
+    p = oracle.tt_params(w_h=1.0)
+    obs = events.ttbar_higgs_dilepton(4, 0xc1061)["obs"]
+    rng = np.random.default_rng(6)
+
+    def draw(r):
+        return obs[int(r.integers(4))], int(r.integers(12)), r.random(8)
+
+    pairs = (lambda ev, pm: (lambda y: oracle.tthll_integrand(p, ev, pm, y)[0],
+                             lambda y: oracle.tthll_direct_integrand(p, ev, pm, y)))
+    _slices(pairs, 4, rng, draw, 7)
+
+
 # ----------------------------------------------------------- PDF grids ----
 PDF_BOUNDS = (math.log(1e-5), 0.0, math.log(10.0), math.log(13000.0))
 
@@ -952,6 +1070,43 @@ def test_pdf_grid_bilinear_exact():
         for j in (0, 2, 4):
             assert oracle.pdf_interp(g, 2, math.exp(lx[i]), math.exp(lq[j])) == pytest.approx(xf[j, i, 7], rel=1e-14)
     assert oracle.pdf_interp(g, 6, 0.1, 100.0) == 0.0 and oracle.pdf_interp(g, -6, 0.1, 100.0) == 0.0
+
+
+def test_pdf_grid_listing_spacing():
+    """The paper's interpolation listing (Sec. 4) steps the grid by
+    (max - min)/n, so its nodes sit at min + i (max - min)/n, i < n, and the
+    last one falls a step short of the stated maximum; outside the range it
+    continues the edge cell.  A table laid out for that reader is the
+    oracle's grid with the upper bound min + (n - 1)(max - min)/n: the
+    oracle's interpolation of it with that bound equals the listing's rule
+    (written here from its description: the cell index from the offset over
+    the step, clamped to [0, n - 2], bilinear weights over the cell area)
+    inside and outside the grid."""
+    nx, nq = 37, 9
+    lx0, lx1, lq0, lq1 = math.log(1e-4), 0.0, math.log(20.0), math.log(5000.0)
+    rng = np.random.default_rng(21)
+    xf = rng.random((nq, nx, 11)).astype(np.float32)
+    dx, dq = (lx1 - lx0) / nx, (lq1 - lq0) / nq
+    g = oracle.PdfGrid(xf, (lx0, lx0 + (nx - 1) * dx, lq0, lq0 + (nq - 1) * dq))
+
+    def listing(fl, x, Q):
+        lx, lq = math.log(x), math.log(Q)
+        ix = int((lx - lx0) / dx) if lx > lx0 else 0
+        ix = min(ix, nx - 2)
+        iq = int((lq - lq0) / dq) if lq > lq0 else 0
+        iq = min(iq, nq - 2)
+        c1x, c1q = lx0 + dx * ix, lq0 + dq * iq
+        c2x, c2q = lx0 + dx * (ix + 1), lq0 + dq * (iq + 1)
+        t = xf[:, :, fl + 5].astype(np.float64)
+        return (t[iq, ix] * (c2x - lx) * (c2q - lq) + t[iq, ix + 1] * (lx - c1x) * (c2q - lq)
+                + t[iq + 1, ix] * (c2x - lx) * (lq - c1q) + t[iq + 1, ix + 1] * (lx - c1x) * (lq - c1q)) / (dx * dq)
+
+    for _ in range(400):
+        x = math.exp(rng.uniform(lx0 - 0.5, lx1 + 0.3))
+        Q = math.exp(rng.uniform(lq0 - 0.3, lq1 + 0.3))
+        fl = int(rng.integers(-5, 6))
+        want = listing(fl, x, Q)
+        assert oracle.pdf_interp(g, fl, x, Q) == pytest.approx(want, rel=1e-9, abs=1e-9)
 
 
 def test_pdf_grid_toy_accuracy():
