@@ -158,9 +158,8 @@ __device__ __forceinline__ double f2_integrand(const ProcParams& pp, const F2Eve
     const v4 hbb = B.apply_me(j[1]), hlm = B.apply_me(ev.lm), hnb = B.apply_me(nb);
     const v4 h1 = B.apply_me(j[2]), h2 = B.apply_me(j[3]);
     const v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
-    const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
     drow<T> R, C;
-    decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
+    decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, tp, tm, mt, R, C);
     const double a = 0.5 * x1 * pp.sqrt_s * kMeScale, bm = 0.5 * x2 * pp.sqrt_s * kMeScale;
     double me;
     if constexpr (TTH)
@@ -208,9 +207,8 @@ __device__ __forceinline__ double f2_parton(const ProcParams& pp, const v4 (&o)[
     const v4 hbb = B.apply_me(b1), hlm = B.apply_me(o[5]), hnb = B.apply_me(o[7]);
     const v4 h1 = B.apply_me(q1), h2 = B.apply_me(q2);
     const v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
-    const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
     drow<T> R, C;
-    decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
+    decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, tp, tm, mt, R, C);
     const double a = 0.5 * x1 * pp.sqrt_s * kMeScale, bm = 0.5 * x2 * pp.sqrt_s * kMeScale;
     const v4 wp = add(o[4], o[6]), wm = add(o[5], o[7]), t = add(b0, wp), tb = add(b1, wm);
     double bw = bw_factor(mdot(t, t), pp.m_t, pp.w_t) * bw_factor(mdot(tb, tb), pp.m_t, pp.w_t)

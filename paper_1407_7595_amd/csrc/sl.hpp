@@ -169,10 +169,9 @@ __device__ __forceinline__ double sl_integrand(const ProcParams& pp, const SLEve
       const v4& af2 = lp ? qk : hl;       // fermion of the W-
       const v4& af2b = lp ? qbk : hn;     // antifermion of the W-
       const v4 tp = add(add(tb_, tf1b), tf1), tm = add(add(ab_, af2), af2b);
-      const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
       drow<T> R, C;
-      decay_rows<T>(tb_, tf1b, tf1, ab_, af2, af2b, pt, ptb, mt, R, C);
-      const T mgg = gg_sum<T>(R, C, pt, T(ak), T(bk), mt);
+      decay_rows<T>(tb_, tf1b, tf1, ab_, af2, af2b, tp, tm, mt, R, C);
+      const T mgg = gg_sum<T>(R, C, tp, ak, bk, mt);
       const T mqq = qq_beams<T>(R, C, T(ak), T(bk));
       me += gg * mgg * T(1.0 / 256.0) + (qq12 + qq21) * mqq * T(1.0 / 36.0);
     }

@@ -184,11 +184,10 @@ __device__ __forceinline__ bool tt_me_pdf(const ProcParams& pp, const v4& b0, co
   const v4 hb = B.apply_me(b0), hl = B.apply_me(lp), hn = B.apply_me(nu);
   const v4 hbb = B.apply_me(b1), hlm = B.apply_me(lm), hnb = B.apply_me(nb);
   const v4 tp = add(add(hb, hl), hn), tm = add(add(hbb, hlm), hnb);
-  const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
   drow<T> R, C;
-  decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, pt, ptb, mt, R, C);
+  decay_rows<T>(hb, hl, hn, hbb, hlm, hnb, tp, tm, mt, R, C);
   const double a = 0.5 * x1 * pp.sqrt_s * kMeScale, bm = 0.5 * x2 * pp.sqrt_s * kMeScale;
-  const T mgg = gg_sum<T>(R, C, pt, T(a), T(bm), mt);
+  const T mgg = gg_sum<T>(R, C, tp, a, bm, mt);
   // q qbar: the same |M|^2 for the quark from either beam
   const T mqq = qq_beams<T>(R, C, T(a), T(bm));
   const T me = gg * mgg * T(1.0 / 256.0) + (qq12 + qq21) * mqq * T(1.0 / 36.0);

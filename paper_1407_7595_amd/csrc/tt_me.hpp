@@ -85,15 +85,39 @@ __device__ __forceinline__ sp<T> psig_col(const mom<T>& p, sp<T> c)
 }
 // (p.sigma-bar) entries: [[p0+p3, p1 - i p2], [p1 + i p2, p0-p3]]
 
+// A momentum by its light-cone components p0 + p3, p0 - p3 and p1, p2,
+// formed in FP64 before the rounding to T: for a top far off its mass shell
+// p0 - p3 (or p0 + p3) is much smaller than p0, and forming it from
+// components already rounded to FP32 loses the digits the amplitudes need.
+template <class T> struct lcm { T p, m, x, y; };
+template <class T> __device__ __forceinline__ lcm<T> to_lc(const v4& v)
+{
+  return lcm<T>{T(v.e + v.z), T(v.e - v.z), T(v.x), T(v.y)};
+}
+template <class T>
+__device__ __forceinline__ sp<T> row_psig(sp<T> r, const lcm<T>& p)
+{
+  cx<T> m00{p.m, T(0)}, m01{-p.x, p.y}, m10{-p.x, -p.y}, m11{p.p, T(0)};
+  return sp<T>{r.a * m00 + r.b * m10, r.a * m01 + r.b * m11};
+}
+template <class T>
+__device__ __forceinline__ sp<T> psig_col(const lcm<T>& p, sp<T> c)
+{
+  cx<T> m00{p.m, T(0)}, m01{-p.x, p.y}, m10{-p.x, -p.y}, m11{p.p, T(0)};
+  return sp<T>{m00 * c.a + m01 * c.b, m10 * c.a + m11 * c.b};
+}
+
 // Dirac row / column in chiral blocks (L, R)
 template <class T> struct drow { sp<T> L, R; };
 
-// Decayed top row and antitop column (see header comment).
+// Decayed top row and antitop column (see header comment); pt, ptb: the
+// top and antitop momenta (FP64, matrix-element units).
 template <class T>
 __device__ __forceinline__ void decay_rows(const v4& b, const v4& lp, const v4& nu, const v4& bb,
-                                           const v4& lm, const v4& nub, const mom<T>& pt,
-                                           const mom<T>& ptb, T mt, drow<T>& R, drow<T>& C)
+                                           const v4& lm, const v4& nub, const v4& pt64,
+                                           const v4& ptb64, T mt, drow<T>& R, drow<T>& C)
 {
+  const lcm<T> pt = to_lc<T>(pt64), ptb = to_lc<T>(ptb64);
   sp<T> lb = lam<T>(b), ll = lam<T>(lp), ln = lam<T>(nu);
   sp<T> lbb = lam<T>(bb), llm = lam<T>(lm), lnb = lam<T>(nub);
   // r = 2 (lambda_b^dagger eps^T lambda_nu^*) (eps^T lambda_l)^T
@@ -119,7 +143,7 @@ template <class T> __device__ __forceinline__ cx<T> dot2(sp<T> r, sp<T> c) { ret
 // (h1 on the top side, h2 on the antitop side): R e1-slash (q-slash + m)
 // e2-slash C.  eps(+) = (0,1,i,0)/sqrt2, eps(-) = (0,1,-i,0)/sqrt2.
 template <class T>
-__device__ __forceinline__ cx<T> chain_amp(const drow<T>& R, const drow<T>& C, const mom<T>& q, T mt,
+__device__ __forceinline__ cx<T> chain_amp(const drow<T>& R, const drow<T>& C, const lcm<T>& q, T mt,
                                            int h1, int h2)
 {
   const T s2 = T(1.41421356237309504880);
@@ -136,10 +160,10 @@ __device__ __forceinline__ cx<T> chain_amp(const drow<T>& R, const drow<T>& C, c
   const int iu = (h2 == 0) ? 0 : 1;   // row of u
   // Q = q.sigma, Qbar = q.sigma-bar, entry [iw][iu]
   cx<T> Q, Qb;
-  if (iw == 0 && iu == 0) { Q = cx<T>{q.e - q.z, T(0)}; Qb = cx<T>{q.e + q.z, T(0)}; }
+  if (iw == 0 && iu == 0) { Q = cx<T>{q.m, T(0)}; Qb = cx<T>{q.p, T(0)}; }
   else if (iw == 0 && iu == 1) { Q = cx<T>{-q.x, q.y}; Qb = cx<T>{q.x, -q.y}; }
   else if (iw == 1 && iu == 0) { Q = cx<T>{-q.x, -q.y}; Qb = cx<T>{q.x, q.y}; }
-  else { Q = cx<T>{q.e + q.z, T(0)}; Qb = cx<T>{q.e - q.z, T(0)}; }
+  else { Q = cx<T>{q.p, T(0)}; Qb = cx<T>{q.m, T(0)}; }
   // w . (m u1 e_iu + Qbar[:,iu] u2): only component iw of the vector matters
   cx<T> v1 = (iw == iu) ? (mt * u1 + Qb * u2) : (Qb * u2);
   cx<T> v2 = (iw == iu) ? (Q * u1 + mt * u2) : (Q * u1);
@@ -147,21 +171,24 @@ __device__ __forceinline__ cx<T> chain_amp(const drow<T>& R, const drow<T>& C, c
 }
 
 // sum over gluon helicities and colours of |A|^2 for g(k1) g(k2) -> t tbar
-// (k1 = (a,0,0,a), k2 = (bm,0,0,-bm)); R, C from decay_rows.
+// (k1 = (a,0,0,a), k2 = (bm,0,0,-bm)); R, C from decay_rows; pt the top
+// momentum (FP64).  The internal top momenta p_t - k_i and their propagator
+// denominators (p_t - k_i)^2 - m^2 = (p_t^2 - m^2) - 2 p_t.k_i are formed in
+// FP64: far off the top's mass shell single diagrams grow while their sum
+// does not, and FP32 rounding of these inputs would show in the sum.
 template <class T>
-__device__ __forceinline__ T gg_sum(const drow<T>& R, const drow<T>& C, const mom<T>& pt, T a, T bm, T mt)
+__device__ __forceinline__ T gg_sum(const drow<T>& R, const drow<T>& C, const v4& pt, double a, double bm, T mt)
 {
-  mom<T> q1{pt.e - a, pt.x, pt.y, pt.z - a};     // p_t - k1
-  mom<T> q2{pt.e - bm, pt.x, pt.y, pt.z + bm};   // p_t - k2
-  T mt2 = mt * mt;
-  T Dt = (q1.e * q1.e - q1.x * q1.x - q1.y * q1.y - q1.z * q1.z) - mt2;
-  T Du = (q2.e * q2.e - q2.x * q2.x - q2.y * q2.y - q2.z * q2.z) - mt2;
-  const T iDt = rcp_t(Dt), iDu = rcp_t(Du);
-  T s = T(4) * a * bm;
+  const double pp = pt.e + pt.z, pm = pt.e - pt.z;
+  const lcm<T> q1{T(pp - 2.0 * a), T(pm), T(pt.x), T(pt.y)};     // p_t - k1
+  const lcm<T> q2{T(pp), T(pm - 2.0 * bm), T(pt.x), T(pt.y)};    // p_t - k2
+  const double off = mdot(pt, pt) - (double)mt * (double)mt;
+  const T iDt = rcp_t(T(off - 2.0 * a * pm)), iDu = rcp_t(T(off - 2.0 * bm * pp));
+  const T s = T(4.0 * a * bm);
   // R (k1-k2)-slash C = R_L (K.sigma) C_R + R_R (K.sigma-bar) C_L,
   // K.sigma = diag(-2bm, 2a), K.sigma-bar = diag(2a, -2bm)
-  cx<T> rkc = (T(-2) * bm) * (R.L.a * C.R.a) + (T(2) * a) * (R.L.b * C.R.b)
-            + (T(2) * a) * (R.R.a * C.L.a) + (T(-2) * bm) * (R.R.b * C.L.b);
+  const T a2 = T(2.0 * a), b2 = T(-2.0 * bm);
+  cx<T> rkc = b2 * (R.L.a * C.R.a) + a2 * (R.L.b * C.R.b) + a2 * (R.R.a * C.L.a) + b2 * (R.R.b * C.L.b);
   cx<T> sch = rcp_t(s) * rkc;
   T sum = T(0);
 #pragma unroll

@@ -177,9 +177,8 @@ __device__ __forceinline__ double tth_integrand(const ProcParams& pp, const TTHE
     const v4& af2 = lp ? qk : hl;
     const v4& af2b = lp ? qbk : hn;
     const v4 tp = add(add(tb_, tf1b), tf1), tm = add(add(ab_, af2), af2b);
-    const mom<T> pt{T(tp.e), T(tp.x), T(tp.y), T(tp.z)}, ptb{T(tm.e), T(tm.x), T(tm.y), T(tm.z)};
     drow<T> R, C;
-    decay_rows<T>(tb_, tf1b, tf1, ab_, af2, af2b, pt, ptb, mt, R, C);
+    decay_rows<T>(tb_, tf1b, tf1, ab_, af2, af2b, tp, tm, mt, R, C);
     const T me = g1 * g2 * gg_tth_sum<T>(R, C, tp, tm, hh, ak, bk, mt) * T(1.0 / 256.0);
     const double shat = x1 * x2 * pp.S;
     acc += (P.e / Eh) * (double)me * bwtl / (shat * x1 * x2 * dq * nu.e);

@@ -116,16 +116,20 @@ def tt_points(po, d, n, rng, i):
     return np.concatenate([near, far]), perm
 
 
-def ill_conditioned(po, ev, perm, x, f0, rel=1e-7):
-    """the oracle's own value moves by more than rel under 1-ulp input
+def ill_conditioned_fn(fn, x, f0, rel=1e-7):
+    """the oracle's own value fn(x) moves by more than rel under 1-ulp input
     perturbations: flag the point"""
     for k in range(3):
         xp = np.nextafter(x, 1.0) if k == 0 else np.nextafter(x, 0.0) if k == 1 else x * (1 + 2e-16)
         xp = np.clip(xp, 0.0, 1.0 - 2**-53)
-        f1 = oracle.tt_integrand(po, ev, perm, xp)[0]
+        f1 = fn(xp)
         if abs(f1 - f0) > rel * max(abs(f0), 1e-300):
             return True
     return False
+
+
+def ill_conditioned(po, ev, perm, x, f0, rel=1e-7):
+    return ill_conditioned_fn(lambda y: oracle.tt_integrand(po, ev, perm, y)[0], x, f0, rel)
 
 
 # FP64 mode: the GPU accepts a quartic-derived neutrino solution without the
@@ -213,9 +217,10 @@ def pulls(a, ea, b, eb):
 
 
 def test_dy_estimates_pull(mem):
-    """GPU estimates vs oracle estimates (same seed, same point stream;
-    identical up to the grid rounding) and the pull distribution of the
-    GPU estimate against brute-force quadrature"""
+    """GPU estimates vs oracle estimates on the same seed and point stream
+    (identical up to the grids' rounding, so far tighter than the MC
+    error); the oracle's own estimates are pinned against brute-force
+    quadrature by test_dy_vegas_vs_quadrature"""
     p = dy_process(mem)
     po = oracle.dy_params()
     d = events.drell_yan(64, 0x14077595)
@@ -359,10 +364,11 @@ def test_sl_integrand(mem, precision, tol):
 # momenta, then leaves the FP32 range unless it is formed in units of
 # 256 GeV.  Every value must be finite.  In this corner the single diagrams
 # of gg -> t tbar grow with the off-shell tops' energy while their sum does
-# not, and FP32 rounding of the diagrams shows in the sum: the dilepton
-# points reach a median of 1.6e-6 and a 99th percentile of 1.7e-5 (a host
-# model of the FP32 arithmetic shows the same), so the accuracy bars here are
-# percentiles ten times looser than on ordinary points.
+# not; the light-cone components of the top momenta and the top propagator
+# denominators are therefore formed in FP64 before the rounding to FP32, and
+# the bar is the ordinary one: 1e-5 on every point the oracle does not flag
+# as ill-conditioned (its own value moves by more than 1e-7 under 1-ulp
+# changes of x), at most 1 % flagged.
 @pytest.mark.parametrize("kind", ["tt", "sl"])
 def test_fp32_far_off_shell(mem, kind):
     rng = np.random.default_rng(31)
@@ -376,6 +382,7 @@ def test_fp32_far_off_shell(mem, kind):
         comps, charge = sl_split(d["obs"])
         comps, charge, D, perms = comps.cuda(), charge.cuda(), 7, (0, 5, 11)
     rel = []
+    flagged = 0
     for e in range(len(d["obs"])):
         for perm in perms:
             x = rng.random((4000 if kind == "tt" else 500, D))
@@ -398,12 +405,17 @@ def test_fp32_far_off_shell(mem, kind):
                 want = integ(po, d["obs"][e], perm, xi)[0]
                 if want == 0.0 and got[k] == 0.0:
                     continue
-                rel.append(abs(got[k] - want) / max(abs(want), 1e-300))
+                r = abs(got[k] - want) / max(abs(want), 1e-300)
+                if r > 1e-5 and ill_conditioned_fn(lambda y: integ(po, d["obs"][e], perm, y)[0], xi, want):
+                    flagged += 1
+                    continue
+                rel.append(r)
     rel = np.array(rel)
     say(f"{kind}: {len(rel)} nonzero points, median {np.median(rel):.3g}, p99 {np.quantile(rel, 0.99):.3g}, "
-        f"max {rel.max():.3g}")
+        f"max {rel.max():.3g} (unflagged), flagged {flagged}")
     assert len(rel) > (200 if kind == "tt" else 400)
-    assert np.median(rel) <= 1e-5 and np.quantile(rel, 0.99) <= 1e-4 and rel.max() <= 3e-4
+    assert rel.max() <= 1e-5
+    assert flagged <= 0.01 * len(rel)
 
 
 def test_sl_iteration0_sums(mem):

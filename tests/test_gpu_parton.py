@@ -1,11 +1,10 @@
 """Parton-level weights on the GPU (mem_parton_weights) against the FP64
-oracle: FP64 within 1e-10 relative on every event; FP32 within 1e-5 at the
-99.9th percentile and within 3e-5 on every event (device and host event
-arrays), the empty batch, and the error paths.  The FP32 tail: events whose
-gg amplitudes cancel strongly between the t-channel and s-channel diagrams
-lose log10 of that cancellation in digits to the FP32 rounding of the
-individual diagrams (1 event in 3000 at 1.4e-5 with the oracle's weight
-stable under 1-ulp input changes).  The FP64 bar:
+oracle: FP64 within 1e-10 relative on every event; FP32 within 1e-5 on
+every event (device and host event arrays), the empty batch, and the error
+paths.  Events whose gg amplitudes cancel strongly between the t-channel and
+s-channel diagrams are what the FP32 bar probes: the top momenta's
+light-cone components and the top propagator denominators are formed in
+FP64 before the amplitudes are assembled in FP32.  The FP64 bar:
 the GPU forms the top and W virtualities E^2 - p^2 from lab momenta, the
 oracle in the zero-transverse-momentum frame; near a Breit-Wigner pole
 (q^2 - m^2 ~ 10 GeV^2 against E^2 ~ 1e5 GeV^2) their rounding is amplified
@@ -57,10 +56,7 @@ def test_parton_weights_match_oracle(mem, precision, tol):
     rel = np.abs(got - want) / want
     q999 = np.quantile(rel, 0.999)
     say(f"  worst rel {rel.max():.3g}, 99.9 % {q999:.3g}, median {np.median(rel):.3g}")
-    if precision == 0:
-        assert rel.max() <= tol
-    else:
-        assert q999 <= tol and rel.max() <= 3 * tol
+    assert rel.max() <= tol
 
 
 def test_parton_weights_host_arrays_and_edges(mem):
