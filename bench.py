@@ -116,51 +116,23 @@ PEAK_BF16 = 2.5e15             # MI355X dense BF16 matrix peak, FLOP/s
 def flow_leg(mem, proc, comps, n_ev, args):
     """train the flow on VEGAS samples of fresh events, then integrate the
     benchmark events to 1 % with it (VEGAS fallback below ESS/N = 0.3)"""
-    import math
     import numpy as np
     import torch
     from synth import events
     n_tr = args.flow_train_events
     d = events.ttbar_dilepton(n_tr, SEED_TRAIN)
     ctr = mem.to_components(d["obs"]).cuda()
-    n_int = 2 * n_tr
+    n_s = 2 * n_tr * FLOW_CAPTURE
+    log(f"flow: training on {n_s} VEGAS samples of {n_tr} events, {FLOW_EPOCHS} epochs (mem_train_proposal)")
     t0 = time.perf_counter()
-    grids = torch.empty((n_int, 8, 65), dtype=torch.float64, device="cuda")
-    mem.integrate_events(ctr, proc, FLOW_TRAIN_PTS, FLOW_TRAIN_ITERS, seed=SEED_TRAIN, grid_out=grids)
-    ev_idx = torch.arange(n_tr, dtype=torch.int32, device="cuda").repeat_interleave(2)
-    pm_idx = torch.tensor([0, 1], dtype=torch.int32, device="cuda").repeat(n_tr)
-    x = torch.empty((n_int, FLOW_CAPTURE, 8), dtype=torch.float32, device="cuda")
-    w = torch.empty((n_int, FLOW_CAPTURE), dtype=torch.float32, device="cuda")
-    mem.vegas_capture(proc, ctr, ev_idx, pm_idx, grids, FLOW_CAPTURE, SEED_TRAIN, 99, x, w, normalise=1)
-    ctx = torch.empty((n_int, 24), dtype=torch.float32, device="cuda")
-    mem.flow_context(ctr, ev_idx, pm_idx, ctx)
-    torch.cuda.synchronize()
-    data_s = time.perf_counter() - t0
-    del grids
-    xs, ws = x.reshape(-1, 8), w.reshape(-1)
-    sint = torch.arange(n_int, dtype=torch.int32, device="cuda").repeat_interleave(FLOW_CAPTURE)
-    n_s = xs.shape[0]
-    n_b = n_s // FLOW_BATCH
-    f = mem.Flow(mem.MEM_FLOW_BF16)
-    rng = np.random.default_rng(7)
-    total = FLOW_EPOCHS * n_b
-    log(f"flow: {n_s} training samples from {n_tr} events ({data_s:.1f} s); {FLOW_EPOCHS} epochs x {n_b} steps")
-    t0 = time.perf_counter()
-    k = 0
-    losses = []
-    for ep in range(FLOW_EPOCHS):
-        for b in rng.permutation(n_b):
-            lr = FLOW_LR[1] + 0.5 * (FLOW_LR[0] - FLOW_LR[1]) * (1 + math.cos(math.pi * k / total))
-            sl = slice(int(b) * FLOW_BATCH, (int(b) + 1) * FLOW_BATCH)
-            want = (k % n_b == 0) or k == total - 1
-            L = f.train_step(ctx, sint[sl], xs[sl], ws[sl], lr=lr, want_loss=want)
-            if want:
-                losses.append(L / (FLOW_BATCH / FLOW_CAPTURE))
-                log(f"  epoch {ep} step {k}: loss per integral {losses[-1]:.4f}")
-            k += 1
+    f, losses = mem.train_proposal(proc, ctr, mode=mem.MEM_FLOW_BF16, vegas_points=FLOW_TRAIN_PTS,
+                                   vegas_iter=FLOW_TRAIN_ITERS, capture=FLOW_CAPTURE, batch=FLOW_BATCH,
+                                   epochs=FLOW_EPOCHS, lr_max=FLOW_LR[0], lr_min=FLOW_LR[1], seed=SEED_TRAIN,
+                                   losses=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    del x, w, xs, ws, sint, ctx, ctr
+    log(f"flow: trained in {train_s:.1f} s, loss per integral {losses[0]:.4f} -> {losses[-1]:.4f}")
+    del ctr
     torch.cuda.empty_cache()
     # the benchmark events to 1 % with the flow
     P = torch.empty(n_ev, dtype=torch.float64, device="cuda")
@@ -213,7 +185,7 @@ def flow_leg(mem, proc, comps, n_ev, args):
            "converged_fraction": float(np.mean((st == 0) | (st == 4))),
            "median_batches": float(np.median(nu_fb)),
            "train": {"events": n_tr, "samples": n_s, "epochs": FLOW_EPOCHS, "seconds": train_s,
-                     "data_seconds": data_s, "loss_first": losses[0], "loss_last": losses[-1]},
+                     "loss_first": losses[0], "loss_last": losses[-1]},
            "sample_kernel": {"ms": samp_ms, "launches": samp_n, "points": flow_pts,
                              "mfma_tflops": mfma / 1e12 if mfma else None,
                              "mfma_frac": mfma / PEAK_BF16 if mfma else None},

@@ -162,8 +162,10 @@ typedef struct mem_flow_s* mem_flow;
  *  use_graph       0: launch every iteration; 1 (default when the options
  *                  are NULL): capture one iteration as a hipGraph and
  *                  replay it
- *  flow            NULL: VEGAS (Sec. 2).  A flow: importance sampling from
- *                  it instead (ttbar dilepton events only).  Batch j of an
+ *  flow            NULL: the processes' proposal when they share one
+ *                  (mem_set_proposal), else VEGAS (Sec. 2).  A flow:
+ *                  importance sampling from it instead (ttbar dilepton
+ *                  events only).  Batch j of an
  *                  integral draws n_points/n_perm base points z from the
  *                  point stream (counter blocks perm*16 + 8 + d/2,
  *                  iteration j), maps them to x = T^-1(z; c) and weighs
@@ -373,7 +375,8 @@ mem_status mem_integrate_events(const mem_events* ev, const mem_process* hyp, in
  * of the current device.
  *   Arguments and results as mem_integrate_events, with these limits: opt
  *   is required, events (ev->on_device) and outputs (opt->outputs_on_device)
- *   are device memory, VEGAS only (opt->flow: MEM_EUNSUPPORTED), no
+ *   are device memory, VEGAS only (opt->flow or the processes' proposal:
+ *   MEM_EUNSUPPORTED), no
  *   timing_out (MEM_EUNSUPPORTED), no allocator hook (MEM_EINVAL).  A call
  *   whose work buffers exceed the scratch returns MEM_ENOMEM before any copy
  *   or launch, with the bytes it would need in mem_last_error (the buffers
@@ -561,6 +564,51 @@ mem_status mem_flow_log_prob(mem_flow f, const float* ctx, const int32_t* sint, 
  * are serialised by the caller. */
 mem_status mem_flow_train_step(mem_flow f, const float* ctx, const int32_t* sint, const float* x, const float* wt,
                                int64_t n, double lr, double* loss_out, float* grad_out, void* stream);
+
+/* Training of the proposal on one call (the learned importance sampling
+ * of the integrand; the method's own sampling idea is Sec. 2's importance
+ * sampling, the flow is this library's): VEGAS runs over the training
+ * events (vegas_iter iterations of vegas_points points per event), the
+ * adapted grids give `capture` samples (x, f(x) J(x) normalised per
+ * integral) of every (event, assignment) integral, and the flow is fitted
+ * to them by minimising -sum w log q(x|c) over shuffled minibatches of
+ * `batch` consecutive samples (whole integrals' samples), `epochs` passes,
+ * Adam with a cosine learning rate from lr_max to lr_min.  Zero fields take
+ * the defaults in brackets. */
+typedef struct {
+  int32_t mode;            /* MEM_FLOW_BF16 or MEM_FLOW_BF16X2 */
+  int32_t vegas_iter;      /* [4] adaptation iterations, >= 2 */
+  int64_t vegas_points;    /* [8192] VEGAS points per training event and iteration */
+  int32_t capture;         /* [168] samples per training integral */
+  int32_t batch;           /* [65536] samples per minibatch */
+  int32_t epochs;          /* [24] */
+  int32_t pad;
+  double lr_max, lr_min;   /* [2e-3, 1e-4] */
+  uint64_t seed;           /* point streams (VEGAS and capture) and minibatch order */
+  void* stream;            /* hipStream_t (NULL: the null stream) */
+  double* loss_out;        /* optional host [epochs]: the loss per integral of each epoch's first minibatch */
+} mem_flow_desc;
+
+/* Train a proposal for process p (MEM_TT_DILEPTON; other kinds
+ * MEM_EUNSUPPORTED) on the events `train` (host or device, as in
+ * mem_integrate_events); f: NULL for the defaults.  On MEM_OK *out is a new
+ * flow owned by the caller (mem_flow_destroy).  Deterministic for fixed
+ * inputs.  MEM_EINVAL: bad sizes (fewer samples than a batch, more than
+ * 2^31), unknown mode, lr_min > lr_max. */
+mem_status mem_train_proposal(mem_process p, const mem_events* train, const mem_flow_desc* f, mem_flow* out);
+
+/* Default proposal of integrations of process p: mem_integrate_events uses
+ * f when its options name no flow and every process of the call has the
+ * same proposal (NULL clears it: VEGAS).  The flow stays owned by the
+ * caller and must outlive its use.  MEM_EUNSUPPORTED for kinds other than
+ * MEM_TT_DILEPTON. */
+mem_status mem_set_proposal(mem_process p, mem_flow f);
+
+/* A flow to a file and back: parameters, Adam moments and step count
+ * (mode included).  save: MEM_EINVAL for an unwritable path.  load: a new
+ * flow (caller-owned); MEM_EINVAL for an unreadable or malformed file. */
+mem_status mem_flow_save(mem_flow f, const char* path);
+mem_status mem_flow_load(const char* path, mem_flow* out);
 
 const char* mem_status_string(mem_status s);
 /* Copies the message of the last failed call on this thread (may be empty). */

@@ -25,7 +25,8 @@ FLOW_CONTEXT = 24
 
 # every symbol include/mem.h declares
 EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_process",
-           "mem_process_shape", "mem_integrate_events", "mem_integrate_events_noalloc", "mem_uniforms", "mem_eval_points",
+           "mem_process_shape", "mem_integrate_events", "mem_integrate_events_noalloc", "mem_train_proposal", "mem_set_proposal",
+           "mem_flow_save", "mem_flow_load", "mem_uniforms", "mem_eval_points",
            "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
@@ -53,6 +54,13 @@ class Events(ctypes.Structure):
     _fields_ = [("n_events", ctypes.c_int32), ("n_obj", ctypes.c_int32), ("E", ctypes.c_void_p),
                 ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
                 ("charge", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class FlowDesc(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("vegas_iter", ctypes.c_int32), ("vegas_points", ctypes.c_int64),
+                ("capture", ctypes.c_int32), ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p), ("loss_out", ctypes.c_void_p)]
 
 
 class IntegrateOpts(ctypes.Structure):
@@ -113,6 +121,10 @@ def lib():
             "mem_process_shape": (I32, [P, P, P]),
             "mem_integrate_events": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
             "mem_integrate_events_noalloc": (I32, [P, P, I32, P, I32, I32, P, P, P, P]),
+            "mem_train_proposal": (I32, [P, P, P, P]),
+            "mem_set_proposal": (I32, [P, P]),
+            "mem_flow_save": (I32, [P, ctypes.c_char_p]),
+            "mem_flow_load": (I32, [ctypes.c_char_p, P]),
             "mem_uniforms": (I32, [U64, U32, U32, U32, I32, I64, P, P]),
             "mem_eval_points": (I32, [P, P, I32, I32, P, I64, P, P, P]),
             "mem_discriminant": (I32, [P, P, I64, P, P]),
@@ -211,6 +223,12 @@ class Process:
         _check(lib().mem_tuning_load(self.handle, table_path.encode(), arch.encode() if arch else None,
                                      ctypes.byref(found)), "mem_tuning_load")
         return bool(found.value)
+
+    def set_proposal(self, flow):
+        """mem_set_proposal: the default proposal of integrations of this
+        process (None: VEGAS); the Flow must outlive its use"""
+        _check(lib().mem_set_proposal(self.handle, flow.handle if flow is not None else None), "mem_set_proposal")
+        self._proposal = flow
 
     def chunk_points(self):
         c = ctypes.c_int32()
@@ -419,11 +437,23 @@ def vegas_capture(process, comps, event, perm, grids, n_per, seed, it, x_out, w_
 class Flow:
     """The learned proposal (mem_flow_*); released with the object."""
 
-    def __init__(self, mode=MEM_FLOW_BF16):
-        h = ctypes.c_void_p()
-        _check(lib().mem_flow_create(mode, ctypes.byref(h)), "mem_flow_create")
-        self.handle = h
+    def __init__(self, mode=MEM_FLOW_BF16, handle=None):
+        if handle is None:
+            handle = ctypes.c_void_p()
+            _check(lib().mem_flow_create(mode, ctypes.byref(handle)), "mem_flow_create")
+        self.handle = handle
         self.mode = mode
+
+    def save(self, path):
+        """mem_flow_save: parameters, Adam moments and step to a file"""
+        _check(lib().mem_flow_save(self.handle, os.fsencode(path)), "mem_flow_save")
+
+    @classmethod
+    def load(cls, path):
+        """mem_flow_load: a new flow from a file written by save"""
+        h = ctypes.c_void_p()
+        _check(lib().mem_flow_load(os.fsencode(path), ctypes.byref(h)), "mem_flow_load")
+        return cls(handle=h)
 
     def set_params(self, params):
         """params: float32 tensor [192552] (host or device)"""
@@ -463,6 +493,23 @@ class Flow:
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.mem_flow_destroy(self.handle)
             self.handle = None
+
+
+def train_proposal(process, comps, mode=MEM_FLOW_BF16, vegas_points=0, vegas_iter=0, capture=0, batch=0,
+                   epochs=0, lr_max=0.0, lr_min=0.0, seed=0x14077595, stream=None, losses=False):
+    """mem_train_proposal: a Flow trained on the events `comps` (VEGAS
+    samples of every (event, assignment) integral); zero arguments take the
+    library's defaults.  With losses=True returns (flow, per-epoch losses)."""
+    ev = events_struct(comps)
+    n_ep = epochs if epochs > 0 else 24
+    loss = (ctypes.c_double * n_ep)() if losses else None
+    d = FlowDesc(mode, vegas_iter, vegas_points, capture, batch, epochs, 0, lr_max, lr_min, seed,
+                 _stream_ptr(stream), ctypes.cast(loss, ctypes.c_void_p) if losses else None)
+    h = ctypes.c_void_p()
+    _check(lib().mem_train_proposal(process.handle, ctypes.byref(ev), ctypes.byref(d), ctypes.byref(h)),
+           "mem_train_proposal")
+    f = Flow(mode, handle=h)
+    return (f, list(loss)) if losses else f
 
 
 def flow_context(comps, event, perm, ctx_out, stream=None):

@@ -19,7 +19,7 @@
 //  * parameters per layer, row-major (out x in): W1[128][28], b1, W2, b2,
 //    W3[92][128], b3 (32 092 per layer).
 //
-// MFMA: v_mfma_f32_32x32x8bf16_1k.  A wave multiplies a 32-row tile of
+// MFMA: v_mfma_f32_32x32x16_bf16.  A wave multiplies a 32-row tile of
 // activations by a 32-column tile of weights; operands come from LDS (or
 // L2) in bf16 with k contiguous.
 #pragma once
@@ -38,7 +38,6 @@ constexpr int F_W1 = 0, F_B1 = FH * FIN, F_W2 = F_B1 + FH, F_B2 = F_W2 + FH * FH
 constexpr int FB_W2 = 0, FB_W2T = FH * FH, FB_W3 = 2 * FH * FH, FB_W3T = 2 * FH * FH + FOUTP * FH,
               FB_PER = 2 * FH * FH + 2 * FOUTP * FH;
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t f2bf(float v)
@@ -67,16 +66,22 @@ __device__ __forceinline__ int mfma_row(int r) { return 8 * (r >> 2) + 4 * ((thr
 __device__ __forceinline__ int mfma_col() { return threadIdx.x & 31; }
 
 // acc += A[m0.., 0..K) x B[0..K, n0..): A(m, k) = A[m * lda + k],
-// B(k, n) = Bt[n * ldb + k] (bf16, k contiguous, 8-byte aligned rows).
+// B(k, n) = Bt[n * ldb + k] (bf16, k contiguous), i.e.
+// acc += A[m0:m0+32][0:K] Bt[n0:n0+32][0:K]^T on v_mfma_f32_32x32x16_bf16
+// (K a multiple of 16, rows 16-byte aligned): lane i < 32 supplies row m0 + i
+// (n0 + i) with k in [k0, k0 + 8), lane 32 + i the same row with k in
+// [k0 + 8, k0 + 16).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void mfma_tile(const uint16_t* A, int lda, const uint16_t* Bt, int ldb, int m0, int n0,
                                           int K, f32x16& acc)
 {
   const int lane = threadIdx.x & 63;
-  const int i = lane & 31, kq = (lane >> 5) * 4;
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(A + (m0 + i) * lda + k0 + kq);
-    const bf16x4 b = *reinterpret_cast<const bf16x4*>(Bt + (n0 + i) * ldb + k0 + kq);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  const int i = lane & 31, kq = (lane >> 5) * 8;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x8_t a = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const short8_t*>(A + (m0 + i) * lda + k0 + kq));
+    const bf16x8_t b = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const short8_t*>(Bt + (n0 + i) * ldb + k0 + kq));
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
 }
 

@@ -541,42 +541,58 @@ __device__ __forceinline__ void spline_backward(const float* th, float x, float 
 
 // LDS of the backward kernel (phases reuse one region)
 constexpr int FHP = FH + 1;   // padded row of the first-layer gradient (bank spread)
+constexpr int FW1S = FIN + 1; // first-layer gradient terms per unit: W1 row and b1
 struct __align__(16) FlowBwdSmem {
   float gv[FP][8];          // dL/d(layer output vector)
   float gl[FP];             // dL/d(log q) per sample (= -weight)
   float ctx_in[FP][4];      // the layer's conditioning inputs
   float ctx[FP][FCTX];      // the samples' contexts
+  float gb2[FT / kWave][FH];  // per-wave partial sums of the second-layer bias gradient
   union {
     struct { uint16_t g[FP * FOUTP]; uint16_t gT[FOUTP * FP]; uint16_t h2T[FH * FP]; } a;   // 80 KB
     struct { uint16_t g[FP * FH]; uint16_t gT[FH * FP]; uint16_t h1T[FH * FP]; } b;         // 96 KB
-    float ga1[FP * FHP];                                                                 // 66 KB
+    struct { float ga1[FP * FHP]; float w1[FH * FW1S]; } c;                               // 81 KB
   } u;
 };
 
-__device__ __forceinline__ void atomic_tile(float* dst, int ld, int m0, int n0, int mmax, int nmax, const f32x16& acc)
+// The gradient slot of a workgroup is written by exactly one thread per
+// entry, in the same order on every run: plain stores on the workgroup's
+// first tile, additions on the later ones.
+__device__ __forceinline__ void slot_add(float* g, float v, bool first) { *g = first ? v : *g + v; }
+
+__device__ __forceinline__ void store_tile(float* dst, int ld, int m0, int n0, int mmax, int nmax, const f32x16& acc,
+                                           bool first)
 {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + mfma_row(r), n = n0 + mfma_col();
-    if (m < mmax && n < nmax) atomicAdd(dst + m * ld + n, acc[r]);
+    if (m < mmax && n < nmax) slot_add(dst + m * ld + n, acc[r], first);
   }
 }
 
 // Backward of L = -sum_i wt_i log q(x_i|c_i) through every layer (tape from
-// flow_train_fwd_kernel), accumulating the parameter gradient in grad.
+// flow_train_fwd_kernel).  Workgroup g takes the tiles of FP samples g,
+// g + G, g + 2G, ... (G = gridDim.x) and accumulates their parameter
+// gradient in its own slot part[g][FNP]; flow_grad_reduce_kernel then sums
+// the slots in slot order, so the gradient is the same on every run (no
+// atomics).
 __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restrict__ P,
                                                             const uint16_t* __restrict__ Wb,
                                                             const float* __restrict__ ctx,
                                                             const int32_t* __restrict__ sint,
                                                             const float* __restrict__ wt, int n,
                                                             const float* __restrict__ tape,
-                                                            float* __restrict__ grad)
+                                                            float* __restrict__ part)
 {
   __shared__ FlowBwdSmem S;
   const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * FP;
+  const int n_tiles = (n + FP - 1) / FP;
   const int64_t stride = (int64_t)FLAYERS * FTAPE;
   const int wv = t / kWave, m0 = 32 * wv;
+  float* slot = part + (int64_t)blockIdx.x * FNP;
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  const bool first = tile == (int)blockIdx.x;
+  const int64_t base = (int64_t)tile * FP;
   if (t < FP) {
 #pragma unroll
     for (int d = 0; d < 8; ++d) S.gv[t][d] = 0.0f;
@@ -592,7 +608,7 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
     flow_masks(l, A, B);
     const float* L = P + (int64_t)l * FPER;
     const uint16_t* W = Wb + (int64_t)l * FB_PER;
-    float* G = grad + (int64_t)l * FPER;
+    float* G = slot + (int64_t)l * FPER;
     const float* tp = tape + (base * FLAYERS + l) * FTAPE;
     // ---- spline backward: g theta (bf16, both layouts) and the input gradient
     for (int q = t; q < FP * FOUTP; q += FT) { S.u.a.g[q] = 0; }
@@ -629,15 +645,15 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
     if (t < FOUT) {
       float sb = 0.0f;
       for (int p = 0; p < FP; ++p) sb += bf2f(S.u.a.gT[t * FP + p]);
-      atomicAdd(&G[F_B3 + t], sb);
+      slot_add(&G[F_B3 + t], sb, first);
     }
     // ---- gW3[n][k] += sum_p g[p][n] h2[p][k]: 3 x 4 tiles over the 4 waves
-    for (int tile = wv; tile < 12; tile += 4) {
-      const int tm = tile / 4, tn = tile % 4;
+    for (int tile3 = wv; tile3 < 12; tile3 += 4) {
+      const int tm = tile3 / 4, tn = tile3 % 4;
       f32x16 acc;
       zero16(acc);
       mfma_tile(S.u.a.gT, FP, S.u.a.h2T, FP, 32 * tm, 32 * tn, FP, acc);
-      atomic_tile(G + F_W3, FH, 32 * tm, 32 * tn, FOUT, FH, acc);
+      store_tile(G + F_W3, FH, 32 * tm, 32 * tn, FOUT, FH, acc, first);
     }
     // ---- gh2[p][k] = sum_n g[p][n] W3[n][k]; ga2 = gh2 silu'(a2)
     f32x16 gh[4];
@@ -658,20 +674,22 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
         sb += ga;
       }
       sb += __shfl_xor(sb, 32, kWave);
-      if ((t & 63) < 32) atomicAdd(&G[F_B2 + 32 * tn + mfma_col()], sb);
+      if ((t & 63) < 32) S.gb2[wv][32 * tn + mfma_col()] = sb;
     }
     for (int q = t; q < FH * FP; q += FT) {
       const int k = q / FP, p = q % FP;
       S.u.b.h1T[q] = f2bf(silu(tp[p * stride + 8 + k]));
     }
     __syncthreads();
+    // gb2: the four waves' sums in wave order
+    if (t < FH) slot_add(&G[F_B2 + t], ((S.gb2[0][t] + S.gb2[1][t]) + S.gb2[2][t]) + S.gb2[3][t], first);
     // ---- gW2[o][k] += sum_p ga2[p][o] h1[p][k]: 4 x 4 tiles
-    for (int tile = wv; tile < 16; tile += 4) {
-      const int tm = tile / 4, tn = tile % 4;
+    for (int tile2 = wv; tile2 < 16; tile2 += 4) {
+      const int tm = tile2 / 4, tn = tile2 % 4;
       f32x16 acc;
       zero16(acc);
       mfma_tile(S.u.b.gT, FP, S.u.b.h1T, FP, 32 * tm, 32 * tn, FP, acc);
-      atomic_tile(G + F_W2, FH, 32 * tm, 32 * tn, FH, FH, acc);
+      store_tile(G + F_W2, FH, 32 * tm, 32 * tn, FH, FH, acc, first);
     }
     // ---- gh1[p][k] = sum_o ga2[p][o] W2[o][k]
 #pragma unroll
@@ -682,37 +700,46 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int p = m0 + mfma_row(r), k = 32 * tn + mfma_col();
-        S.u.ga1[p * FHP + k] = gh[tn][r] * dsilu(tp[p * stride + 8 + k]);
+        S.u.c.ga1[p * FHP + k] = gh[tn][r] * dsilu(tp[p * stride + 8 + k]);
       }
     if (t < FP) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) S.ctx_in[t][j] = tp[t * stride + B[j]];
     }
     __syncthreads();
-    // ---- first layer (VALU): gb1, gW1 and the conditioning-input gradient
+    // ---- first layer (VALU): gb1, gW1 (each unit's sums over the two
+    //      halves of the samples, added in half order) and the
+    //      conditioning-input gradient
     {
       const int o = t % FH, half = t / FH;
-      float sb = 0.0f, sw[4] = {0, 0, 0, 0};
+      float sb = 0.0f, sw[FIN];
+#pragma unroll
+      for (int j = 0; j < FIN; ++j) sw[j] = 0.0f;
       for (int p = half; p < FP; p += 2) {
-        const float g1 = S.u.ga1[p * FHP + o];
+        const float g1 = S.u.c.ga1[p * FHP + o];
         sb += g1;
 #pragma unroll
         for (int j = 0; j < 4; ++j) sw[j] += g1 * S.ctx_in[p][j];
-      }
-      atomicAdd(&G[F_B1 + o], sb);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) atomicAdd(&G[F_W1 + o * FIN + j], sw[j]);
-      for (int j = 0; j < FCTX; ++j) {
-        float s = 0.0f;
-        for (int p = half; p < FP; p += 2) s += S.u.ga1[p * FHP + o] * S.ctx[p][j];
-        atomicAdd(&G[F_W1 + o * FIN + 4 + j], s);
+        for (int j = 0; j < FCTX; ++j) sw[4 + j] += g1 * S.ctx[p][j];
+      }
+      if (half == 1) {
+#pragma unroll
+        for (int j = 0; j < FIN; ++j) S.u.c.w1[o * FW1S + j] = sw[j];
+        S.u.c.w1[o * FW1S + FIN] = sb;
+      }
+      __syncthreads();
+      if (half == 0) {
+#pragma unroll
+        for (int j = 0; j < FIN; ++j) slot_add(&G[F_W1 + o * FIN + j], sw[j] + S.u.c.w1[o * FW1S + j], first);
+        slot_add(&G[F_B1 + o], sb + S.u.c.w1[o * FW1S + FIN], first);
       }
     }
     if (t < FP) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float s = 0.0f;
-        for (int o = 0; o < FH; ++o) s += S.u.ga1[t * FHP + o] * L[F_W1 + o * FIN + j];
+        for (int o = 0; o < FH; ++o) s += S.u.c.ga1[t * FHP + o] * L[F_W1 + o * FIN + j];
         S.gv[t][B[j]] += s;
       }
     }
@@ -723,6 +750,18 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
     }
     __syncthreads();
   }
+  }
+}
+
+// grad[i] = sum over the workgroup slots g = 0, 1, ... of part[g][i], in
+// slot order.
+__global__ void flow_grad_reduce_kernel(const float* __restrict__ part, int n_slots, float* __restrict__ grad)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= FNP) return;
+  float s = 0.0f;
+  for (int g = 0; g < n_slots; ++g) s += part[(int64_t)g * FNP + i];
+  grad[i] = s;
 }
 
 // Adam on the FP32 master parameters (bias-corrected moments).

@@ -53,6 +53,8 @@ struct mem_process_s {
   int pdf_device = -1;        // the device that holds pdf_dev
   int32_t pdf_nx = 0, pdf_nq = 0;
   double pdf_bounds[4] = {0.0, 0.0, 0.0, 0.0};
+  // default learned proposal of integrations of this process (null: VEGAS)
+  mem_flow proposal = nullptr;
   ~mem_process_s() { if (pdf_dev) (void)hipFree(pdf_dev); }
 };
 
@@ -1043,6 +1045,13 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
   if (o.hooks & ~(uint32_t)MEM_HOOK_NONFINITE) return fail(MEM_EINVAL, "unknown hook");
   if ((o.hooks & MEM_HOOK_NONFINITE) && (o.hook_event < 0 || o.hook_event >= n_ev))
     return fail(MEM_EINVAL, "hook_event outside the events");
+  if (!o.flow && n_ev > 0) {
+    // the processes' own proposal (mem_set_proposal), when they share one
+    mem_flow pf = hyp[0] ? hyp[0]->proposal : nullptr;
+    for (int i = 1; i < n_hyp && pf; ++i)
+      if (!hyp[i] || hyp[i]->proposal != pf) pf = nullptr;
+    o.flow = pf;
+  }
   if (o.flow && (o.weights_out || o.checkpoint || o.hooks))
     return fail(MEM_EUNSUPPORTED, "weights_out, checkpoints and hooks are VEGAS-only");
   if (n_ev == 0) return MEM_OK;
@@ -1971,18 +1980,22 @@ struct mem_flow_s {
   float* lq = nullptr;      // log q of the training samples
   int64_t tape_cap = 0;
   double* loss_parts = nullptr;
+  float* part = nullptr;    // per-workgroup gradient slots of the backward pass
+  int part_slots = 0;
   int64_t step = 0;
   int32_t mode = MEM_FLOW_BF16;
   ~mem_flow_s()
   {
     for (void* q : {(void*)P, (void*)grad, (void*)m, (void*)v, (void*)Wb, (void*)Wf, (void*)tape, (void*)lq,
-                    (void*)loss_parts})
+                    (void*)loss_parts, (void*)part})
       if (q) (void)hipFree(q);
   }
 };
 
 namespace {
 constexpr int kLossBlocks = 256;
+// backward workgroups (and gradient slots) of a training step: one per CU
+constexpr unsigned kGradSlots = 256;
 
 __global__ void fill_f32_kernel(float* p, int64_t n, float v)
 {
@@ -2188,31 +2201,30 @@ extern "C" mem_status mem_flow_log_prob(mem_flow f, const float* ctx, const int3
   return MEM_OK;
 }
 
-extern "C" mem_status mem_flow_train_step(mem_flow f, const float* ctx, const int32_t* sint, const float* x,
-                                          const float* wt, int64_t n, double lr, double* loss_out, float* grad_out,
-                                          void* stream)
+// One training step once the arguments are checked: the minibatch's context
+// rows are [c_lo, c_lo + n_ctx); cvec holds n_ctx first-layer projections.
+// Enqueues on s; synchronises only for loss_out.
+static mem_status flow_train_core(mem_flow f, const float* ctx, const int32_t* sint, const float* x,
+                                  const float* wt, int64_t n, double lr, double* loss_out, float* grad_out,
+                                  hipStream_t s, int32_t c_lo, int n_ctx, float* cvec)
 {
-  if (!f || !ctx || !sint || !x || !wt) return fail(MEM_EINVAL, "null argument");
-  if (n < 1 || n > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "bad size");
-  if (!(lr >= 0.0)) return fail(MEM_EINVAL, "lr must be >= 0");
-  hipStream_t s = (hipStream_t)stream;
-  int32_t c_lo = 0, c_hi = 0;
-  mem_status st = sint_range(sint, n, s, &c_lo, &c_hi);
+  mem_status st = flow_tape(f, n);
   if (st != MEM_OK) return st;
-  const int n_ctx = c_hi - c_lo + 1;
-  st = flow_tape(f, n);
+  st = flow_cvec(f, ctx + (int64_t)c_lo * FCTX, n_ctx, cvec, s);
   if (st != MEM_OK) return st;
-  DevBuf b_cvec;
-  HIP_TRY(b_cvec.alloc((size_t)n_ctx * FLAYERS * FH * sizeof(float)));
-  st = flow_cvec(f, ctx + (int64_t)c_lo * FCTX, n_ctx, b_cvec.as<float>(), s);
-  if (st != MEM_OK) return st;
-  fill_f32(f->grad, FNP, 0.0f, s);
   const unsigned nb = (unsigned)((n + FP - 1) / FP);
+  // one gradient slot per backward workgroup, summed in slot order
+  const int slots = (int)std::min<unsigned>(nb, (unsigned)kGradSlots);
+  if (slots > f->part_slots) {
+    if (f->part) { (void)hipFree(f->part); f->part = nullptr; f->part_slots = 0; }
+    HIP_TRY(hipMalloc(&f->part, (size_t)slots * FNP * sizeof(float)));
+    f->part_slots = slots;
+  }
   hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_train_fwd_kernel<true> : flow_train_fwd_kernel<false>,
-                     dim3(nb), dim3(FT), 0, s, f->P, f->Wb, b_cvec.as<float>(), sint, c_lo, x, (int)n, f->tape,
-                     f->lq);
-  hipLaunchKernelGGL(flow_train_bwd_kernel, dim3(nb), dim3(FT), 0, s, f->P, f->Wb, ctx, sint, wt, (int)n, f->tape,
-                     f->grad);
+                     dim3(nb), dim3(FT), 0, s, f->P, f->Wb, cvec, sint, c_lo, x, (int)n, f->tape, f->lq);
+  hipLaunchKernelGGL(flow_train_bwd_kernel, dim3(slots), dim3(FT), 0, s, f->P, f->Wb, ctx, sint, wt, (int)n,
+                     f->tape, f->part);
+  hipLaunchKernelGGL(flow_grad_reduce_kernel, dim3((FNP + 255) / 256), dim3(256), 0, s, f->part, slots, f->grad);
   HIP_TRY(hipGetLastError());
   if (grad_out) HIP_TRY(hipMemcpyAsync(grad_out, f->grad, (size_t)FNP * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (loss_out) {
@@ -2236,7 +2248,220 @@ extern "C" mem_status mem_flow_train_step(mem_flow f, const float* ctx, const in
     st = flow_convert(f, s);
     if (st != MEM_OK) return st;
   }
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_train_step(mem_flow f, const float* ctx, const int32_t* sint, const float* x,
+                                          const float* wt, int64_t n, double lr, double* loss_out, float* grad_out,
+                                          void* stream)
+{
+  if (!f || !ctx || !sint || !x || !wt) return fail(MEM_EINVAL, "null argument");
+  if (n < 1 || n > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "bad size");
+  if (!(lr >= 0.0)) return fail(MEM_EINVAL, "lr must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t c_lo = 0, c_hi = 0;
+  mem_status st = sint_range(sint, n, s, &c_lo, &c_hi);
+  if (st != MEM_OK) return st;
+  const int n_ctx = c_hi - c_lo + 1;
+  DevBuf b_cvec;
+  HIP_TRY(b_cvec.alloc((size_t)n_ctx * FLAYERS * FH * sizeof(float)));
+  st = flow_train_core(f, ctx, sint, x, wt, n, lr, loss_out, grad_out, s, c_lo, n_ctx, b_cvec.as<float>());
+  if (st != MEM_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));   // the context projection is freed on return
+  return MEM_OK;
+}
+
+// ------------------------------------------------ proposal training ----
+namespace {
+__global__ void integral_of_sample_kernel(int32_t* sint, int64_t n, int32_t per)
+{
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) sint[i] = (int32_t)(i / per);
+}
+__global__ void event_perm_kernel(int32_t* ev, int32_t* pm, int32_t n_int)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_int) { ev[i] = i >> 1; pm[i] = i & 1; }
+}
+// splitmix64 (Steele, Lea, Flood, OOPSLA 2014): the minibatch order
+uint64_t splitmix64(uint64_t& st)
+{
+  uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+}  // namespace
+
+extern "C" mem_status mem_train_proposal(mem_process p, const mem_events* train, const mem_flow_desc* fd,
+                                         mem_flow* out)
+{
+  if (!p || !train || !out) return fail(MEM_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->desc.kind != MEM_TT_DILEPTON) return fail(MEM_EUNSUPPORTED, "the proposal is defined for ttbar dilepton");
+  mem_flow_desc d{};
+  d.mode = MEM_FLOW_BF16;
+  if (fd) d = *fd;
+  const int64_t vpts = d.vegas_points > 0 ? d.vegas_points : 8192;
+  const int32_t viter = d.vegas_iter > 0 ? d.vegas_iter : 4;
+  const int32_t cap = d.capture > 0 ? d.capture : 168;
+  const int32_t batch = d.batch > 0 ? d.batch : 65536;
+  const int32_t epochs = d.epochs > 0 ? d.epochs : 24;
+  const double lr_max = d.lr_max > 0.0 ? d.lr_max : 2e-3, lr_min = d.lr_min > 0.0 ? d.lr_min : 1e-4;
+  if (d.mode != MEM_FLOW_BF16 && d.mode != MEM_FLOW_BF16X2) return fail(MEM_EINVAL, "unknown flow mode");
+  if (viter < 2) return fail(MEM_EINVAL, "vegas_iter must be at least 2");
+  if (!(lr_min <= lr_max)) return fail(MEM_EINVAL, "lr_min above lr_max");
+  mem_status st = check_event_arrays(train);
+  if (st != MEM_OK) return st;
+  const int n_ev = train->n_events;
+  if (train->n_obj < 4) return fail(MEM_EINVAL, "n_obj too small for ttbar dilepton");
+  const int64_t n_int = 2 * (int64_t)n_ev;
+  const int64_t n_s = n_int * cap;
+  if (n_int < 1 || n_s > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "training set size out of range");
+  if (batch < 1 || batch > n_s) return fail(MEM_EINVAL, "batch must be between 1 and the number of samples");
+  hipStream_t s = (hipStream_t)d.stream;
+  // events on the device once (VEGAS, capture and context all read them)
+  DevEvents dev;
+  st = dev.make(train, s);
+  if (st != MEM_OK) return st;
+  mem_events ed = *train;
+  ed.E = dev.view.E; ed.px = dev.view.px; ed.py = dev.view.py; ed.pz = dev.view.pz;
+  ed.charge = dev.view.charge;
+  ed.on_device = 1;
+  // 1. VEGAS on the training events; their adapted grids
+  DevBuf b_grid, b_P, b_err, b_st, b_ev, b_pm;
+  HIP_TRY(b_grid.alloc((size_t)n_int * 8 * (kBins + 1) * sizeof(double)));
+  HIP_TRY(b_P.alloc((size_t)n_ev * sizeof(double)));
+  HIP_TRY(b_err.alloc((size_t)n_ev * sizeof(double)));
+  HIP_TRY(b_st.alloc((size_t)n_ev * sizeof(int32_t)));
+  HIP_TRY(b_ev.alloc((size_t)n_int * sizeof(int32_t)));
+  HIP_TRY(b_pm.alloc((size_t)n_int * sizeof(int32_t)));
+  {
+    mem_integrate_opts o{};
+    o.seed = d.seed;
+    o.alpha = 1.5;
+    o.max_iter = 64;
+    o.use_graph = 1;
+    o.stream = d.stream;
+    o.outputs_on_device = 1;
+    o.grid_out = b_grid.as<double>();
+    const mem_process hyp[1] = {p};
+    st = mem_integrate_events(&ed, hyp, 1, &vpts, 1, viter, &o, b_P.as<double>(), b_err.as<double>(),
+                              b_st.as<int32_t>());
+    if (st != MEM_OK) return st;
+  }
+  hipLaunchKernelGGL(event_perm_kernel, dim3((unsigned)((n_int + 255) / 256)), dim3(256), 0, s, b_ev.as<int32_t>(),
+                     b_pm.as<int32_t>(), (int32_t)n_int);
+  HIP_TRY(hipGetLastError());
+  // 2. samples of the adapted grids (x, f J normalised per integral) and contexts
+  DevBuf b_x, b_w, b_ctx, b_sint;
+  HIP_TRY(b_x.alloc((size_t)n_s * 8 * sizeof(float)));
+  HIP_TRY(b_w.alloc((size_t)n_s * sizeof(float)));
+  HIP_TRY(b_ctx.alloc((size_t)n_int * FCTX * sizeof(float)));
+  HIP_TRY(b_sint.alloc((size_t)n_s * sizeof(int32_t)));
+  st = mem_vegas_capture(p, &ed, b_ev.as<int32_t>(), b_pm.as<int32_t>(), (int32_t)n_int, b_grid.as<double>(), cap,
+                         d.seed, 99u, 1, b_x.as<float>(), b_w.as<float>(), d.stream);
+  if (st != MEM_OK) return st;
+  st = mem_flow_context(&ed, b_ev.as<int32_t>(), b_pm.as<int32_t>(), (int32_t)n_int, b_ctx.as<float>(), d.stream);
+  if (st != MEM_OK) return st;
+  hipLaunchKernelGGL(integral_of_sample_kernel, dim3((unsigned)((n_s + 255) / 256)), dim3(256), 0, s,
+                     b_sint.as<int32_t>(), n_s, cap);
+  HIP_TRY(hipGetLastError());
+  // 3. the flow, trained on shuffled minibatches (contiguous slices of the
+  //    samples: each holds whole integrals' samples), cosine learning rate
+  mem_flow f = nullptr;
+  st = mem_flow_create(d.mode, &f);
+  if (st != MEM_OK) return st;
+  struct FlowGuard { mem_flow& f; ~FlowGuard() { if (f) mem_flow_destroy(f); } } fg{f};
+  const int64_t n_b = n_s / batch;
+  const int max_ctx = (int)((batch + cap - 1) / cap) + 1;
+  DevBuf b_cvec;
+  HIP_TRY(b_cvec.alloc((size_t)max_ctx * FLAYERS * FH * sizeof(float)));
+  std::vector<int64_t> order(n_b);
+  uint64_t rs = d.seed ^ 0x5EEDF10Aull;
+  const int64_t total = (int64_t)epochs * n_b;
+  int64_t k = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t i = 0; i < n_b; ++i) order[i] = i;
+    for (int64_t i = n_b - 1; i > 0; --i) std::swap(order[i], order[(int64_t)(splitmix64(rs) % (uint64_t)(i + 1))]);
+    for (int64_t j = 0; j < n_b; ++j, ++k) {
+      const int64_t b = order[j];
+      const double lr = lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(M_PI * (double)k / (double)total));
+      const int64_t s0 = b * batch;
+      const int32_t c_lo = (int32_t)(s0 / cap), c_hi = (int32_t)((s0 + batch - 1) / cap);
+      double L = 0.0;
+      const bool want = d.loss_out != nullptr && j == 0;
+      st = flow_train_core(f, b_ctx.as<float>(), b_sint.as<int32_t>() + s0, b_x.as<float>() + s0 * 8,
+                           b_w.as<float>() + s0, batch, lr, want ? &L : nullptr, nullptr, s, c_lo,
+                           c_hi - c_lo + 1, b_cvec.as<float>());
+      if (st != MEM_OK) return st;
+      if (want) d.loss_out[ep] = L / ((double)batch / (double)cap);
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = f;
+  f = nullptr;
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_set_proposal(mem_process p, mem_flow f)
+{
+  if (!p) return fail(MEM_EINVAL, "null process");
+  if (f && p->desc.kind != MEM_TT_DILEPTON) return fail(MEM_EUNSUPPORTED, "the proposal is defined for ttbar dilepton");
+  p->proposal = f;
+  return MEM_OK;
+}
+
+// File layout of a saved flow: "MEMFLOW1", int32 mode, int32 0, int64 Adam
+// step, int64 parameter count, then the FP32 parameters and the two Adam
+// moments (little-endian, as in memory).
+extern "C" mem_status mem_flow_save(mem_flow f, const char* path)
+{
+  if (!f || !path) return fail(MEM_EINVAL, "null argument");
+  std::vector<float> h(3 * (size_t)FNP);
+  HIP_TRY(hipMemcpy(h.data(), f->P, (size_t)FNP * sizeof(float), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(h.data() + FNP, f->m, (size_t)FNP * sizeof(float), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(h.data() + 2 * (size_t)FNP, f->v, (size_t)FNP * sizeof(float), hipMemcpyDeviceToHost));
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(MEM_EINVAL, std::string("cannot write ") + path);
+  const int32_t hdr[2] = {f->mode, 0};
+  const int64_t nums[2] = {f->step, (int64_t)FNP};
+  bool ok = std::fwrite("MEMFLOW1", 1, 8, fp) == 8 && std::fwrite(hdr, sizeof(hdr), 1, fp) == 1 &&
+            std::fwrite(nums, sizeof(nums), 1, fp) == 1 && std::fwrite(h.data(), sizeof(float), h.size(), fp) == h.size();
+  ok = (std::fclose(fp) == 0) && ok;
+  if (!ok) return fail(MEM_EINVAL, std::string("write failed: ") + path);
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_flow_load(const char* path, mem_flow* out)
+{
+  if (!path || !out) return fail(MEM_EINVAL, "null argument");
+  *out = nullptr;
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(MEM_EINVAL, std::string("cannot read ") + path);
+  char magic[8];
+  int32_t hdr[2];
+  int64_t nums[2];
+  std::vector<float> h(3 * (size_t)FNP);
+  bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "MEMFLOW1", 8) == 0 &&
+            std::fread(hdr, sizeof(hdr), 1, fp) == 1 && std::fread(nums, sizeof(nums), 1, fp) == 1 &&
+            nums[1] == (int64_t)FNP && nums[0] >= 0 && std::fread(h.data(), sizeof(float), h.size(), fp) == h.size();
+  char extra;
+  ok = ok && std::fread(&extra, 1, 1, fp) == 0;
+  std::fclose(fp);
+  if (!ok) return fail(MEM_EINVAL, std::string("not a saved flow: ") + path);
+  mem_flow f = nullptr;
+  mem_status st = mem_flow_create(hdr[0], &f);
+  if (st != MEM_OK) return st;
+  st = mem_flow_set_params(f, h.data(), FNP, 0);
+  if (st == MEM_OK) {
+    if (hipMemcpy(f->m, h.data() + FNP, (size_t)FNP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(f->v, h.data() + 2 * (size_t)FNP, (size_t)FNP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+      st = fail(MEM_EDEVICE, "hipMemcpy of the Adam moments");
+  }
+  if (st != MEM_OK) { mem_flow_destroy(f); return st; }
+  f->step = nums[0];
+  *out = f;
   return MEM_OK;
 }
 
