@@ -179,7 +179,28 @@ def flow_leg(mem, proc, comps, n_ev, args):
     v_s = time.perf_counter() - t0
     vegas_same = {"events_per_s": n_ev / v_s, "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
                   "mean_iterations": float(np.mean(n_used.cpu().numpy()))}
+    # the flow seeding VEGAS's grids (MEM_FLOW_SEED_GRID) at the headline's
+    # points per iteration: every iteration enters the estimate
+    def run_seeded():
+        mem.integrate_events(comps, proc, PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
+                             n_iter_out=n_used, flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID,
+                             allocation=mem.MEM_ALLOC_NEYMAN)
+
+    run_seeded()
+    torch.cuda.synchronize()
+    st_times = []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        run_seeded()
+        torch.cuda.synchronize()
+        st_times.append(time.perf_counter() - t0)
+    seeded = {"events_per_s": n_ev * len(st_times) / sum(st_times), "points_per_iteration": PTS,
+              "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
+              "mean_iterations": float(np.mean(n_used.cpu().numpy())),
+              "median_iterations": float(np.median(n_used.cpu().numpy()))}
+    log(f"flow-seeded VEGAS grids: {seeded}")
     out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times), "flow_alone": alone,
+           "flow_seeded_grids": seeded,
            "vegas_same_points": vegas_same,
            "points_per_event_per_batch": FLOW_PTS, "fallback_fraction": float(np.mean(st == 4)),
            "converged_fraction": float(np.mean((st == 0) | (st == 4))),

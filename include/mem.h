@@ -228,8 +228,23 @@ typedef struct mem_flow_s* mem_flow;
  *                  call returns MEM_OK (unchanged otherwise).
  *  alloc_fn, free_fn, alloc_user  optional allocator for the call's
  *                  device work buffers (both or neither); NULL: hipMalloc
- *                  and hipFree.                                           */
+ *                  and hipFree.
+ *  flow_mode       how a flow (given or the processes' proposal) is used:
+ *                  MEM_FLOW_SAMPLE (0): importance sampling from it, as
+ *                  described under `flow`;
+ *                  MEM_FLOW_SEED_GRID: VEGAS whose grids start from the
+ *                  flow instead of uniform ones: 2048 flow samples of each
+ *                  integral (the flow's point stream at iteration
+ *                  0xFFFFFFF0) give, per dimension, edges at the quantiles
+ *                  k/64 of 0.8 x (sample CDF) + 0.2 x (uniform CDF); every
+ *                  iteration then enters the estimate (the first one too)
+ *                  and the stopping test runs from the second iteration.
+ *                  Each iteration is still VEGAS importance sampling on
+ *                  its own grid, so the estimate stays unbiased; ttbar
+ *                  dilepton processes only (MEM_EUNSUPPORTED), no
+ *                  ess_threshold.  Other values: MEM_EINVAL.           */
 enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
+enum { MEM_FLOW_SAMPLE = 0, MEM_FLOW_SEED_GRID = 1 };
 
 /* Per-integral state of a VEGAS integration, owned by the library (see
  * mem_checkpoint_create). */
@@ -277,6 +292,7 @@ typedef struct {
   mem_alloc_fn alloc_fn;
   mem_free_fn free_fn;
   void* alloc_user;
+  int32_t flow_mode;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */

@@ -29,6 +29,8 @@ KIND_TTBB_LL = 7
 KIND_TT_DIRECT = 8
 KIND_TT_SL_DIRECT = 9
 KIND_TTH_LL_DIRECT = 10
+# a lattice step function on [0,1]^2 (stratification check)
+KIND_STEP = 11
 NBINS = 64
 
 
@@ -160,6 +162,10 @@ def _declare(L):
         "or_gg_ttbar_ward": (D, [D, P, P, P, P]),
         "or_top_decay_spinsum": (D, [D, P, P, P, P]),
         "or_integrate_one": (None, [I, P, P, I, U64, U32, I64, I, D, P, P, P, P]),
+        "or_strat_ns": (I, [I, I64]),
+        "or_strat_allocate": (None, [I64, I64, P, I, P]),
+        "or_strat_iteration": (None, [I, P, P, I, U64, U32, U32, I64, P, I, P, P, P, P, P, P]),
+        "or_integrate_one_strat": (None, [I, P, P, I, U64, U32, I64, I, D, P, P, P]),
         "or_vegas_iteration": (None, [I, P, P, I, U64, U32, U32, I64, P, P, P, P]),
         "or_weight_at": (D, [I, P, P, I, P, P]),
         "or_integrate_events": (None, [I, P, P, I, I, U64, I64, I, D, D, P, P, P]),
@@ -348,6 +354,44 @@ def integrate_one(kind, p, ev, perm, seed, event_index, n_points, n_iter,
                            n_points, n_iter, alpha, None if g is None else _ptr(g),
                            _ptr(Is), _ptr(Vs), ctypes.byref(r))
     return r, Is, Vs, g
+
+
+STRAT_HMAX = 16384
+
+
+def strat_ns(D, N):
+    """hypercubes per dimension of adaptive stratified VEGAS"""
+    return lib().or_strat_ns(D, N)
+
+
+def strat_allocate(H, N, sig=None, first=False):
+    nh = np.zeros(H, dtype=np.int64)
+    sg = _f64(np.zeros(H) if sig is None else sig)
+    lib().or_strat_allocate(H, N, _ptr(sg), 1 if first else 0, nh.ctypes.data)
+    return nh
+
+
+def strat_iteration(kind, p, ev, perm, seed, event_index, it, N, grid, ns, nh):
+    """one stratified iteration: (I, var, per-hypercube deviations, bins,
+    every point's weight in iteration order)"""
+    ev, grid = _f64(ev), _f64(grid)
+    D = lib().or_dims(kind)
+    H = len(nh)
+    nh = np.ascontiguousarray(nh, dtype=np.int64)
+    I, var = ctypes.c_double(), ctypes.c_double()
+    sig, bins, w = np.zeros(H), np.zeros(D * 64), np.zeros(N)
+    lib().or_strat_iteration(kind, ctypes.byref(p), _ptr(ev), perm, seed, event_index, it, N, _ptr(grid), ns,
+                             nh.ctypes.data, ctypes.byref(I), ctypes.byref(var), _ptr(sig), _ptr(bins), _ptr(w))
+    return I.value, var.value, sig, bins, w
+
+
+def integrate_one_strat(kind, p, ev, perm, seed, event_index, n_points, n_iter, alpha=1.5):
+    ev = _f64(ev)
+    Is, Vs = np.zeros(n_iter), np.zeros(n_iter)
+    r = Result()
+    lib().or_integrate_one_strat(kind, ctypes.byref(p), _ptr(ev), perm, seed, event_index, n_points, n_iter,
+                                 alpha, _ptr(Is), _ptr(Vs), ctypes.byref(r))
+    return r, Is, Vs
 
 
 def vegas_iteration(kind, p, ev, perm, seed, event_index, it, n_points, grid):

@@ -503,7 +503,7 @@ static void boost_transverse(const double* P, const double* in, double* out)
 
 int or_dims(int kind)
 {
-  return kind == OR_KIND_DY ? 2 : kind == OR_KIND_GENZ ? 4
+  return (kind == OR_KIND_DY || kind == OR_KIND_STEP) ? 2 : kind == OR_KIND_GENZ ? 4
        : (kind == OR_KIND_TT_SL || kind == OR_KIND_TT_SL_DIRECT) ? 7 : kind == OR_KIND_TTH ? 9 : 8;
 }
 int or_nperm(int kind)

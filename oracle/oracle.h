@@ -221,7 +221,10 @@ double or_flow_nll_grad(const double* params, int n, const double* x, const doub
 enum { OR_KIND_DY = 1, OR_KIND_TT = 2, OR_KIND_GENZ = 3, OR_KIND_TT_SL = 4, OR_KIND_TTH = 5,
        OR_KIND_TTH_LL = 6, OR_KIND_TTBB_LL = 7,
        /* the same integrals in direct parametrisations (closure checks) */
-       OR_KIND_TT_DIRECT = 8, OR_KIND_TT_SL_DIRECT = 9, OR_KIND_TTH_LL_DIRECT = 10 };
+       OR_KIND_TT_DIRECT = 8, OR_KIND_TT_SL_DIRECT = 9, OR_KIND_TTH_LL_DIRECT = 10,
+       /* 1 + floor(4 x0) + 3 floor(4 x1) on [0,1]^2 (integral 7): constant on
+        * a 4 x 4 lattice, a check of stratified sampling */
+       OR_KIND_STEP = 11 };
 /* Direct parametrisations of the t tbar dilepton, t tbar semileptonic and
  * t tbar H dilepton integrands (integrands.c): the unmeasured momenta
  * themselves as variables, no constraint solve, Breit-Wigner factors left
@@ -274,6 +277,22 @@ void or_integrate_events_iters(int kind, const or_params* p, const double* event
                                int n_events, int n_obj, uint64_t seed, int64_t n_points,
                                int n_iter, const int32_t* n_iter_ev, double alpha, double sigma_norm,
                                double* P, double* err, int32_t* status);
+/* Adaptive stratified VEGAS (driver.c): hypercubes per dimension for D
+ * dimensions and N points, the allocation of N points over H hypercubes
+ * (first iteration, or from the per-hypercube standard deviations sig),
+ * one iteration (estimate, variance, per-hypercube deviations, per-bin
+ * sums, optionally every point's weight in iteration order), and a whole
+ * integration. */
+#define OR_STRAT_HMAX 16384
+int or_strat_ns(int D, int64_t N);
+void or_strat_allocate(int64_t H, int64_t N, const double* sig, int first, int64_t* nh);
+void or_strat_iteration(int kind, const or_params* p, const double* ev, int perm, uint64_t seed,
+                        uint32_t event_index, uint32_t iter, int64_t N, const double* grid, int ns,
+                        const int64_t* nh, double* I_out, double* var_out, double* sig_out, double* bins,
+                        double* w_out);
+void or_integrate_one_strat(int kind, const or_params* p, const double* ev, int perm, uint64_t seed,
+                            uint32_t event_index, int64_t N, int n_iter, double alpha, double* iter_I,
+                            double* iter_var, or_result* res);
 void or_set_threads(int n);
 int or_max_threads(void);
 int or_dims(int kind);

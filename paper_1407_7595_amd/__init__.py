@@ -72,10 +72,14 @@ class IntegrateOpts(ctypes.Structure):
                 ("weights_out", ctypes.c_void_p), ("weights_stride", ctypes.c_int64),
                 ("weights_integral", ctypes.c_int32), ("weights_rows", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
                 ("checkpoint", ctypes.c_void_p), ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
-                ("alloc_user", ctypes.c_void_p)]
+                ("alloc_user", ctypes.c_void_p), ("flow_mode", ctypes.c_int32)]
 
 
 MEM_HOOK_NONFINITE = 1
+
+# how a flow is used (mem_integrate_opts.flow_mode)
+MEM_FLOW_SAMPLE = 0
+MEM_FLOW_SEED_GRID = 1
 
 # bytes of the per-device scratch of mem_integrate_events_noalloc
 MEM_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
@@ -275,11 +279,12 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
                      allocation=0, weights_out=None, weights_integral=0, hooks=0, hook_event=0,
-                     checkpoint=None, allocator=None, _noalloc=False):
+                     checkpoint=None, allocator=None, flow_mode=0, _noalloc=False):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
-    flow: optional Flow (importance sampling from it, VEGAS fallback);
+    flow: optional Flow (importance sampling from it, VEGAS fallback; with
+    flow_mode=MEM_FLOW_SEED_GRID it seeds the VEGAS grids instead);
     allocation: MEM_ALLOC_EQUAL or MEM_ALLOC_NEYMAN across permutations;
     weights_out: optional float64 device tensor [iterations, stride] for
     the weights of integral weights_integral; hooks / hook_event: test
@@ -315,7 +320,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         weights_out.shape[0] if weights_out is not None else 0, hooks, hook_event,
                         checkpoint.handle.value if checkpoint is not None else None,
                         ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
-                        ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None)
+                        ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None,
+                        flow_mode)
     entry = "mem_integrate_events_noalloc" if _noalloc else "mem_integrate_events"
     _check(getattr(lib(), entry)(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                  ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),

@@ -138,7 +138,7 @@ __device__ __forceinline__ double f2_integrand(const ProcParams& pp, const F2Eve
   const double q2wm = pp.m_w * pp.m_w + mwg * tan_halfpi(pp.th0_w + x[5] * (pp.th1_w - pp.th0_w));
   const v4 vis = add(add(add(j[0], j[1]), add(j[2], j[3])), add(ev.lp, ev.lm));
   NuSet sols;
-  solve_dilepton(j[0], j[1], ev.lp, ev.lm, -vis.x, -vis.y, q2wp, q2t, q2wm, q2tb, sols);
+  solve_dilepton(j[0], j[1], ev.lp, ev.lm, -vis.x, -vis.y, q2wp, q2t, q2wm, q2tb, sols, polish_tol<T>());
   const int ns = sols.n;
   const T mt = T(pp.m_t * kMeScale);
   double acc = 0.0;

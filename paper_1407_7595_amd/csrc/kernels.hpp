@@ -119,19 +119,23 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
   }
 }
 
-// Dilepton chunk with the real roots of each wavefront compacted before
-// the per-root work.  Every lane maps its point and forms the resultant
-// quartic and its real roots (0 to 4); the lane's solve state goes to an
-// LDS record and its roots to an LDS queue (exclusive prefix sum of the
+// Dilepton chunk with the root searches and the per-root work of each
+// wavefront compacted.  Every lane maps its point, forms the resultant
+// quartic and isolates its real roots (0 to 4 sign-change intervals between
+// critical points); the lane's solve state and monic quartic go to an LDS
+// record and its intervals to an LDS queue (exclusive prefix sum of the
 // counts from three ballots).  Every lane then takes queue entries lane,
-// lane + 64, ...: it rebuilds the owner's geometry from the record, polishes
-// and tests the root (dilep_accept) and evaluates the matrix element stage
-// (tt_solution); each point sums its own entries in root order.  The
-// per-root work runs ceil(total / 64) times per wavefront instead of
-// max(roots) times, and every value equals tt_integrand's bit for bit (same
-// functions, same order; a rejected root adds +0).  ON = false compiles to
-// nothing (no LDS) for launches without dilepton chunks.
-constexpr int kTTRec = 30;       // DilepPoint (28 doubles) + the two jet energies
+// lane + 64, ...: first it runs the bracketed search of that interval
+// (the searches of a wavefront run in lockstep, so a lane no longer waits
+// for the slowest of its own up to four intervals), then, on the found
+// root, it rebuilds the owner's geometry from the record, polishes and
+// tests the root (dilep_accept) and evaluates the matrix element stage
+// (tt_solution); each point sums its own entries in root order.  Both
+// stages run ceil(total / 64) times per wavefront instead of max(roots)
+// times, and every value equals tt_integrand's bit for bit (same
+// functions, same inputs, same order; a rejected root adds +0).  ON = false
+// compiles to nothing (no LDS) for launches without dilepton chunks.
+constexpr int kTTRec = 34;       // DilepPoint (28 doubles), the two jet energies, the monic quartic c0..c3
 template <class T, bool ON>
 __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
                                                 double* sbins, double& s1, double& s2, double* wrec, bool poison,
@@ -140,11 +144,15 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
   if constexpr (ON) {
     __shared__ double srec[kBlock / kWave][kTTRec][kWave];
     __shared__ double spx[kBlock / kWave][4 * kWave];
+    __shared__ double slo[kBlock / kWave][4 * kWave];
+    __shared__ double shi[kBlock / kWave][4 * kWave];
     __shared__ double sres[kBlock / kWave][4 * kWave];
     __shared__ int sown[kBlock / kWave][4 * kWave];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     double (*rec)[kWave] = srec[wv];
     double* qpx = spx[wv];
+    double* qlo = slo[wv];
+    double* qhi = shi[wv];
     double* qres = sres[wv];
     int* qown = sown[wv];
     const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;     // lanes below this one
@@ -156,8 +164,8 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
       m.jetf = T(0);
       m.bq[0].e = m.bq[1].e = 0.0;
       DilepPoint s;
-      Four roots;
-      roots.n = 0;
+      QuartIso qi;
+      qi.lo.n = 0;
       double jac = 0.0;
       int bin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (live) {
@@ -168,19 +176,21 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
         double quart[5];
         if (dilep_prepare(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, s, quart)) {
           // the solve state goes to the lane's LDS record before the root
-          // search, so that it is not held in registers across it (the
+          // isolation, so that it is not held in registers across it (the
           // previous round's readers finished at its last wave_sync)
-          const double r[kTTRec] = {s.A1.e0, s.A1.e1, s.A1.e2, s.A1.z0, s.A1.z1, s.A1.z2,
-                                    s.A2.e0, s.A2.e1, s.A2.e2, s.A2.z0, s.A2.z1, s.A2.z2,
-                                    s.P0, s.P1, s.P2, s.Q0, s.Q1,
-                                    s.tq[0], s.tq[1], s.tq[2], s.tq[3], s.itq[0], s.itq[1], s.itq[2], s.itq[3],
-                                    s.lam, s.mx, s.my, m.bq[0].e, m.bq[1].e};
+          const double r[30] = {s.A1.e0, s.A1.e1, s.A1.e2, s.A1.z0, s.A1.z1, s.A1.z2,
+                                s.A2.e0, s.A2.e1, s.A2.e2, s.A2.z0, s.A2.z1, s.A2.z2,
+                                s.P0, s.P1, s.P2, s.Q0, s.Q1,
+                                s.tq[0], s.tq[1], s.tq[2], s.tq[3], s.itq[0], s.itq[1], s.itq[2], s.itq[3],
+                                s.lam, s.mx, s.my, m.bq[0].e, m.bq[1].e};
 #pragma unroll
-          for (int f = 0; f < kTTRec; ++f) rec[f][lane] = r[f];
-          quartic_real_roots(quart, roots);
+          for (int f = 0; f < 30; ++f) rec[f][lane] = r[f];
+          quartic_isolate(quart, qi);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) rec[30 + f][lane] = qi.c[f];
         }
       }
-      const int nr = roots.n;
+      const int nr = qi.lo.n;
       int off = 0, total = 0;
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
@@ -192,12 +202,22 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (j < nr) {
-            qpx[off + j] = roots.get(j);
+            qpx[off + j] = qi.x0.get(j);
+            qlo[off + j] = qi.lo.get(j);
+            qhi[off + j] = qi.hi.get(j);
             qown[off + j] = lane;
           }
         }
       }
       wave_sync();
+      // the wavefront's root searches, one interval per lane
+      for (int i = lane; i < total; i += kWave) {
+        const int o = qown[i];
+        const double c[5] = {rec[30][o], rec[31][o], rec[32][o], rec[33][o], 1.0};
+        qpx[i] = quartic_root(c, qlo[i], qhi[i], qpx[i]);
+      }
+      wave_sync();
+      // the roots' acceptance and matrix elements, one root per lane
       for (int i = lane; i < total; i += kWave) {
         const int o = qown[i];
         DilepPoint t;
@@ -211,7 +231,7 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
         DilepGeom g;
         dilep_geom(tt_jet(ev, 0, E0), tt_jet(ev, 1, E1), ev.lp, ev.lm, t, g);
         NuSol sol;
-        qres[i] = dilep_accept(t, g, qpx[i], sol) ? tt_solution<T>(pp, ev, E0, E1, sol) : 0.0;
+        qres[i] = dilep_accept(t, g, qpx[i], sol, polish_tol<T>()) ? tt_solution<T>(pp, ev, E0, E1, sol) : 0.0;
       }
       wave_sync();
       double acc = 0.0;

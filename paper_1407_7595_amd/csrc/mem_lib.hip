@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
                                                              double alpha, const Control* __restrict__ ctl,
                                                              int n_int, double* __restrict__ iter_out,
                                                              const int64_t* __restrict__ alloc,
-                                                             double* __restrict__ n_evals)
+                                                             double* __restrict__ n_evals, uint32_t first_kept)
 {
   __shared__ double sb[kMaxDims * kBins];
   __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
     if (var < 0.0) var = 0.0;
     double* st = state + (int64_t)ig * ST_SIZE;
     if (!isfinite(s1) || !isfinite(s2)) st[ST_NONFINITE] = 1.0;
-    if (iter >= 1) {
+    if (iter >= first_kept) {
       if (var > 0.0) { st[ST_WSUM] += 1.0 / var; st[ST_WISUM] += I / var; }
       st[ST_ISUM] += I;
       st[ST_NITER] += 1.0;
@@ -519,7 +519,7 @@ __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t*
                              const double* __restrict__ ev_norm, const double* __restrict__ state,
                              int32_t* __restrict__ active, int n_events, double target, Control* ctl,
                              int final_pass, double* P, double* err, int32_t* status, int32_t* n_iter_used,
-                             int32_t* ev_done)
+                             int32_t* ev_done, uint32_t first_kept)
 {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_events) return;
@@ -539,7 +539,7 @@ __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t*
   const double norm = ev_norm[e];
   const double p = norm * s / np, sd = norm * sqrt(v) / np;
   if (!final_pass) {
-    if (!ev_done[e] && iter >= 2 && (p > 0.0 && sd <= target * p)) {
+    if (!ev_done[e] && iter >= first_kept + 1 && (p > 0.0 && sd <= target * p)) {
       ev_done[e] = (int32_t)iter + 1;
       for (int k = 0; k < np; ++k) active[i0 + k] = 0;
     }
@@ -1009,7 +1009,10 @@ static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, i
 static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                   const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
                                   double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask,
-                                  Workspace& work);
+                                  Workspace& work, mem_flow seed_flow = nullptr);
+static mem_status seed_grids_from_flow(mem_flow f, const EventsView& view, const std::vector<IntegralDesc>& ints,
+                                       const IntegralDesc* d_ints, double* grids, uint64_t seed, Workspace& work,
+                                       hipStream_t s);
 
 // ---------------------------------------------------------- integrate ----
 // arena: null (work buffers from hipMalloc or the caller's allocator), or
@@ -1034,6 +1037,7 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
   if (opt) o = *opt;
   if (!(o.alpha > 0.0)) return fail(MEM_EINVAL, "alpha must be positive");
   if (o.allocation != MEM_ALLOC_EQUAL && o.allocation != MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "unknown allocation");
+  if (o.flow_mode != MEM_FLOW_SAMPLE && o.flow_mode != MEM_FLOW_SEED_GRID) return fail(MEM_EINVAL, "unknown flow_mode");
   const bool target_mode = o.target_rel_err > 0.0;
   const int iters = target_mode ? o.max_iter : n_iter;
   const bool resume = o.checkpoint && o.checkpoint->has;
@@ -1067,6 +1071,13 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
     return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr, work);
   }
   Workspace work(o.alloc_fn, o.free_fn, o.alloc_user, (hipStream_t)o.stream);
+  if (o.flow && o.flow_mode == MEM_FLOW_SEED_GRID) {
+    for (int i = 0; i < n_hyp; ++i)
+      if (!hyp[i] || hyp[i]->desc.kind != MEM_TT_DILEPTON)
+        return fail(MEM_EUNSUPPORTED, "flow-seeded grids cover ttbar dilepton only");
+    return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr, work,
+                           o.flow);
+  }
   if (o.flow) return integrate_flow(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, work);
   return integrate_vegas(ev, hyp, n_hyp, n_points, n_np, iters, o, p_out, err_out, status_out, nullptr, work);
 }
@@ -1125,11 +1136,15 @@ extern "C" mem_status mem_integrate_events_noalloc(const mem_events* ev, const m
 
 // VEGAS over every event, or over the events with ev_mask[e] != 0 (host
 // array; the others are skipped and their outputs are undefined).
+// seed_flow: the proposal whose samples seed every integral's grid (then
+// every iteration enters the estimate), or null (uniform grids, the first
+// iteration only adapts).
 static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                   const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
                                   double* p_out, double* err_out, int32_t* status_out, const int32_t* ev_mask,
-                                  Workspace& work)
+                                  Workspace& work, mem_flow seed_flow)
 {
+  const uint32_t first_kept = seed_flow ? 0u : 1u;
   mem_status st = MEM_OK;
   const int n_ev = ev->n_events;
   const bool target_mode = o.target_rel_err > 0.0;
@@ -1366,6 +1381,11 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                        b_ints.as<IntegralDesc>(), n_int);
     HIP_TRY(hipGetLastError());
   }
+  if (seed_flow) {
+    st = seed_grids_from_flow(seed_flow, dev.view, ints, b_ints.as<IntegralDesc>(), b_grids.as<double>(), o.seed,
+                              work, ws);
+    if (st != MEM_OK) return st;
+  }
   if (resume) {
     // the state of the earlier call; the host vectors live in the handle
     const Control ctlr{iter0, 0u, 0, 0u};
@@ -1429,11 +1449,12 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(),
                        b_chunks.as<Chunk>(), b_parts.as<double>(), b_grids.as<double>(), b_state.as<double>(),
                        b_active.as<int32_t>(), o.alpha, ctl, n_int, o.iter_out,
-                       neyman ? b_alloc.as<int64_t>() : nullptr, b_nev.as<double>());
+                       neyman ? b_alloc.as<int64_t>() : nullptr, b_nev.as<double>(), first_kept);
     if (target_mode)
       hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                          b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
-                         o.target_rel_err, ctl, 0, nullptr, nullptr, nullptr, nullptr, b_done.as<int32_t>());
+                         o.target_rel_err, ctl, 0, nullptr, nullptr, nullptr, nullptr, b_done.as<int32_t>(),
+                         first_kept);
     if (neyman)
       hipLaunchKernelGGL(neyman_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                          b_ints.as<IntegralDesc>(), b_state.as<double>(), b_active.as<int32_t>(),
@@ -1536,7 +1557,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   // the final pass reads ctl->iter == iterations run
   hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                      b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
-                     target_mode ? o.target_rel_err : 0.0, ctl, 1, P, E, S, o.n_iter_out, b_done.as<int32_t>());
+                     target_mode ? o.target_rel_err : 0.0, ctl, 1, P, E, S, o.n_iter_out, b_done.as<int32_t>(),
+                     first_kept);
   HIP_TRY(hipGetLastError());
   if (o.grid_out)
     HIP_TRY(hipMemcpyAsync(o.grid_out, b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToDevice, ws));
@@ -2466,6 +2488,104 @@ extern "C" mem_status mem_flow_load(const char* path, mem_flow* out)
 }
 
 // Flow-proposal integration (see mem_integrate_opts.flow).
+// ------------------------------------------------ flow-seeded grids ----
+namespace {
+constexpr int64_t kSeedPoints = 2048;        // proposal samples per integral
+constexpr int kSeedHist = 512;               // histogram bins per dimension
+constexpr double kSeedUniform = 0.2;         // share of the uniform density in the seeded grid
+constexpr uint32_t kSeedIter = 0xFFFFFFF0u;  // iteration index of the seeding draws
+
+// Grid of integral blockIdx.x from M proposal samples x[ig][M][8]: per
+// dimension the edges at the quantiles k/64 of the mixture
+// (1 - eps) F_samples + eps F_uniform, the sample CDF read from a
+// kSeedHist-bin histogram and linear inside a bin.  The uniform share keeps
+// every bin wider than eps / 64 of the unit interval, where the proposal
+// underweights the integrand.  One wavefront per dimension.
+__global__ __launch_bounds__(256) void seed_grids_kernel(const float* __restrict__ x, int64_t M,
+                                                         const IntegralDesc* __restrict__ ints,
+                                                         double* __restrict__ grids, double eps)
+{
+  __shared__ uint32_t hist[4][kSeedHist];
+  const int ig = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const IntegralDesc in = ints[ig];
+  for (int d0 = 0; d0 < 8; d0 += 4) {
+    const int d = d0 + w;
+    for (int b = lane; b < kSeedHist; b += 64) hist[w][b] = 0u;
+    __syncthreads();
+    for (int64_t k = lane; k < M; k += 64) {
+      const float v = x[((int64_t)ig * M + k) * 8 + d];
+      const int b = min(kSeedHist - 1, max(0, (int)(v * (float)kSeedHist)));
+      atomicAdd(&hist[w][b], 1u);
+    }
+    __syncthreads();
+    if (lane == 0 && d < in.dims) {
+      double* e = grids + in.grid_off + (int64_t)d * (kBins + 1);
+      const double inv = 1.0 / (double)M, hw = 1.0 / kSeedHist;
+      double cum = 0.0;
+      int b = 0;
+      e[0] = 0.0;
+      for (int k = 1; k < kBins; ++k) {
+        const double t = (double)k / kBins;
+        while (b < kSeedHist - 1 && (1.0 - eps) * (cum + hist[w][b] * inv) + eps * (b + 1) * hw < t) {
+          cum += hist[w][b] * inv;
+          ++b;
+        }
+        const double g0 = (1.0 - eps) * cum + eps * b * hw;
+        const double g1 = (1.0 - eps) * (cum + hist[w][b] * inv) + eps * (b + 1) * hw;
+        e[k] = fmin(1.0, (b + (t - g0) / (g1 - g0)) * hw);
+      }
+      e[kBins] = 1.0;
+    }
+    __syncthreads();
+  }
+}
+}  // namespace
+
+// Seed the grids of ttbar dilepton integrals from a proposal: kSeedPoints
+// samples of each integral (the flow's own point stream at iteration
+// kSeedIter, apart from VEGAS's), then seed_grids_kernel.
+static mem_status seed_grids_from_flow(mem_flow f, const EventsView& view, const std::vector<IntegralDesc>& ints,
+                                       const IntegralDesc* d_ints, double* grids, uint64_t seed, Workspace& work,
+                                       hipStream_t s)
+{
+  const int n_int = (int)ints.size();
+  std::vector<int32_t> iev(n_int), ipm(n_int);
+  std::vector<FlowChunk> sch;
+  for (int ig = 0; ig < n_int; ++ig) {
+    if (ints[ig].dims != 8) return fail(MEM_EUNSUPPORTED, "flow-seeded grids cover ttbar dilepton only");
+    iev[ig] = ints[ig].event;
+    ipm[ig] = ints[ig].perm;
+    for (int64_t s0 = 0; s0 < kSeedPoints; s0 += FP)
+      sch.push_back(FlowChunk{ig, iev[ig], ipm[ig], (int32_t)std::min<int64_t>(FP, kSeedPoints - s0), s0,
+                              (int64_t)ig * kSeedPoints + s0});
+  }
+  DevBuf b_ev(&work), b_pm(&work), b_ctx(&work), b_cvec(&work), b_sch(&work), b_x(&work), b_lq(&work);
+  HIP_TRY(b_ev.alloc(n_int * sizeof(int32_t)));
+  HIP_TRY(b_pm.alloc(n_int * sizeof(int32_t)));
+  HIP_TRY(b_ctx.alloc((size_t)n_int * FCTX * sizeof(float)));
+  HIP_TRY(b_cvec.alloc((size_t)n_int * FLAYERS * FH * sizeof(float)));
+  HIP_TRY(b_sch.alloc(sch.size() * sizeof(FlowChunk)));
+  HIP_TRY(b_x.alloc((size_t)n_int * kSeedPoints * 8 * sizeof(float)));
+  HIP_TRY(b_lq.alloc((size_t)n_int * kSeedPoints * sizeof(float)));
+  HIP_TRY(hipMemcpyAsync(b_ev.p, iev.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_pm.p, ipm.data(), n_int * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b_sch.p, sch.data(), sch.size() * sizeof(FlowChunk), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(flow_ctx_kernel, dim3((n_int + 255) / 256), dim3(256), 0, s, view, b_ev.as<int32_t>(),
+                     b_pm.as<int32_t>(), n_int, b_ctx.as<float>());
+  HIP_TRY(hipGetLastError());
+  mem_status st = flow_cvec(f, b_ctx.as<float>(), n_int, b_cvec.as<float>(), s);
+  if (st != MEM_OK) return st;
+  hipLaunchKernelGGL(f->mode == MEM_FLOW_BF16X2 ? flow_sample2_kernel<true> : flow_sample2_kernel<false>,
+                     dim3((unsigned)sch.size()), dim3(FT), 0, s, f->P, f->Wf, b_cvec.as<float>(),
+                     b_sch.as<FlowChunk>(), seed, kSeedIter, (const uint32_t*)nullptr, (const int32_t*)nullptr,
+                     b_x.as<float>(), b_lq.as<float>());
+  hipLaunchKernelGGL(seed_grids_kernel, dim3(n_int), dim3(256), 0, s, b_x.as<float>(), kSeedPoints, d_ints, grids,
+                     kSeedUniform);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));   // the samples are freed on return
+  return MEM_OK;
+}
+
 static mem_status integrate_flow(const mem_events* ev, const mem_process* hyp, int32_t n_hyp,
                                  const int64_t* n_points, int32_t n_np, int32_t iters, const mem_integrate_opts& o,
                                  double* p_out, double* err_out, int32_t* status_out, Workspace& work)

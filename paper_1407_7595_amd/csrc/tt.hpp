@@ -254,7 +254,7 @@ __device__ __forceinline__ double tt_integrand(const ProcParams& pp, const TTEve
   TTMaps<T> m;
   tt_maps<T>(pp, ev, x, m);
   NuSet sols;
-  solve_dilepton(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, sols);
+  solve_dilepton(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, sols, polish_tol<T>());
   const int ns = sols.n;
   double acc = 0.0;
   for (int k = 0; k < ns; ++k) acc += tt_solution<T>(pp, ev, m.bq[0].e, m.bq[1].e, sols.get(k));

@@ -148,11 +148,26 @@ __device__ __forceinline__ void cubic_estimates(double A, double B, double C, do
   }
 }
 
-// Real roots of a quartic (c4 != 0), ascending.
-__device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four& roots)
+// The real roots of a quartic (c4 != 0) in two steps.  quartic_isolate:
+// the monic coefficients and the intervals between consecutive critical
+// points (and the root bound) across which the quartic changes sign,
+// ascending, each with the starting point of its search (hi == lo: a root
+// exactly at lo).  quartic_root: the root of one such interval.  The work
+// queue kernel runs the second step on the intervals of a whole wavefront
+// gathered in LDS, so that the bracketed searches run in lockstep over
+// full lanes; quartic_real_roots runs both per lane.  Either way a root
+// comes out of the same function with the same inputs.
+struct QuartIso {
+  double c[5];        // monic coefficients
+  Four lo, hi, x0;    // the intervals (lo.n of them) and their starting points
+};
+
+__device__ __forceinline__ void quartic_isolate(const double (&c_in)[5], QuartIso& q)
 {
   const double inv = fast_rcp(c_in[4]);
   const double c[5] = {c_in[0] * inv, c_in[1] * inv, c_in[2] * inv, c_in[3] * inv, 1.0};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) q.c[i] = c[i];
   double bound = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) bound = fmax(bound, fabs(c[i]));
@@ -164,8 +179,8 @@ __device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four
   double s0 = -bound, s1 = -bound;
   const double disc = d2[1] * d2[1] - 4.0 * d2[2] * d2[0];
   if (disc > 0.0) {
-    const double q = -0.5 * (d2[1] + copysign(sqrt(disc), d2[1]));
-    const double a = q * (1.0 / 12.0), b = (q != 0.0) ? d2[0] * fast_rcp(q) : a;
+    const double qq = -0.5 * (d2[1] + copysign(sqrt(disc), d2[1]));
+    const double a = qq * (1.0 / 12.0), b = (qq != 0.0) ? d2[0] * fast_rcp(qq) : a;
     s0 = fmin(fmax(fmin(a, b), -bound), bound);
     s1 = fmin(fmax(fmax(a, b), -bound), bound);
   }
@@ -176,22 +191,66 @@ __device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four
   Four crit;
   crit.n = 0;
   const double p3[4] = {-bound, s0, s1, bound};
-  roots_on_intervals<3, 3, true>(d1, p3, crit, [&](int, double lo, double hi, double, double) {
-    return (est[0] > lo && est[0] < hi) ? est[0] : (est[1] > lo && est[1] < hi) ? est[1] : est[2];
-  });
+  // a closed-form estimate inside a derivative sign-change interval is its
+  // root to a few ulp away from double roots of p' (where the quartic is
+  // locally flat and its roots ill-conditioned anyway); only an interval
+  // without one runs the bracketed search
+  {
+    double fprev = horner<3>(d1, p3[0]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double lo = p3[i], hi = p3[i + 1];
+      const double fnext = horner<3>(d1, hi);
+      if (hi > lo) {
+        if (fprev == 0.0) crit.put(lo);
+        else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0) {
+          const bool in0 = est[0] > lo && est[0] < hi, in1 = est[1] > lo && est[1] < hi;
+          const bool in2 = est[2] > lo && est[2] < hi;
+          crit.put(in0 ? est[0] : in1 ? est[1] : in2 ? est[2]
+                                            : bracketed_root<3, true>(d1, lo, hi, fprev, 0.5 * (lo + hi)));
+        }
+      }
+      fprev = fnext;
+    }
+  }
   // the quartic is monotone between consecutive critical points; a root
   // starts from the quadratic model p(e) + p''(e) d^2 / 2 at the critical
   // end e with the smaller |p| (interior intervals have two)
   const double p4[5] = {-bound, crit.n > 0 ? crit.v0 : bound, crit.n > 1 ? crit.v1 : bound,
                         crit.n > 2 ? crit.v2 : bound, bound};
+  q.lo.n = q.hi.n = q.x0.n = 0;
+  double fprev = horner<4>(c, p4[0]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double lo = p4[i], hi = p4[i + 1];
+    const double fnext = horner<4>(c, hi);
+    if (hi > lo) {
+      if (fprev == 0.0) {
+        q.lo.put(lo); q.hi.put(lo); q.x0.put(lo);
+      } else if ((fprev < 0.0) != (fnext < 0.0) && fnext != 0.0) {
+        const bool lo_crit = i > 0, hi_crit = hi < bound;
+        const bool use_lo = lo_crit && (!hi_crit || fabs(fprev) <= fabs(fnext));
+        const double e = use_lo ? lo : hi, fe = use_lo ? fprev : fnext;
+        const double d = sqrt(fabs(2.0 * fe * fast_rcp(horner<2>(d2, e))));
+        q.lo.put(lo); q.hi.put(hi); q.x0.put(use_lo ? lo + d : hi - d);
+      }
+    }
+    fprev = fnext;
+  }
+}
+
+__device__ __forceinline__ double quartic_root(const double (&c)[5], double lo, double hi, double x0)
+{
+  return hi == lo ? lo : bracketed_root<4, false>(c, lo, hi, horner<4>(c, lo), x0);
+}
+
+// Real roots of a quartic (c4 != 0), ascending.
+__device__ __forceinline__ void quartic_real_roots(const double (&c_in)[5], Four& roots)
+{
+  QuartIso q;
+  quartic_isolate(c_in, q);
   roots.n = 0;
-  roots_on_intervals<4, 4, false>(c, p4, roots, [&](int i, double lo, double hi, double flo, double fhi) {
-    const bool lo_crit = i > 0, hi_crit = hi < bound;
-    const bool use_lo = lo_crit && (!hi_crit || fabs(flo) <= fabs(fhi));
-    const double e = use_lo ? lo : hi, fe = use_lo ? flo : fhi;
-    const double d = sqrt(fabs(2.0 * fe * fast_rcp(horner<2>(d2, e))));
-    return use_lo ? lo + d : hi - d;
-  });
+  for (int k = 0; k < q.lo.n; ++k) roots.put(quartic_root(q.c, q.lo.get(k), q.hi.get(k), q.x0.get(k)));
 }
 
 // Neutrino energy and p_z as affine functions of (p_x, p_y) from
@@ -290,6 +349,12 @@ __device__ __forceinline__ bool dilep_step(const DilepJac& J, const double (&r)[
   dv[3] = rb * fast_rcp(pb);
   return true;
 }
+
+// Relative constraint residual above which a root is polished by Newton on
+// the full system: near the FP64 rounding level when the matrix element
+// runs in FP64; 1e-10 when it runs in FP32, whose rounding (~1e-7) the
+// remaining solve error then stays far below.
+template <class T> constexpr double polish_tol() { return sizeof(T) == 4 ? 1e-10 : 1e-13; }
 
 // Accepted (nu, nubar) solutions of one point, held in four static slots
 // so that they stay in registers.
@@ -399,9 +464,11 @@ __device__ __forceinline__ void dilep_geom(const v4& b_in, const v4& bb_in, cons
 }
 
 // One real root px of the resultant: p_y from the conics, positive
-// energies, conditional Newton polish on the full system, residual test;
-// on acceptance the solution in lab units (GeV) with |det J| (GeV^4).
-__device__ __forceinline__ bool dilep_accept(const DilepPoint& s, const DilepGeom& g, double px, NuSol& out)
+// energies, conditional Newton polish on the full system (when the largest
+// relative residual exceeds polish_tol), residual test; on acceptance the
+// solution in lab units (GeV) with |det J| (GeV^4).
+__device__ __forceinline__ bool dilep_accept(const DilepPoint& s, const DilepGeom& g, double px, NuSol& out,
+                                             double polish_tol)
 {
   const Affine& A1 = s.A1;
   const Affine& A2 = s.A2;
@@ -421,7 +488,7 @@ __device__ __forceinline__ bool dilep_accept(const DilepPoint& s, const DilepGeo
   for (int i = 0; i < 4; ++i) worst = fmax(worst, fabs((F[i] - s.tq[i]) * s.itq[i]));
   // the resultant loses digits near degenerate configurations: polish by
   // Newton on the full system only where the residual shows it
-  for (int it = 0; it < 2 && worst > 1e-13; ++it) {
+  for (int it = 0; it < 2 && worst > polish_tol; ++it) {
     DilepJac J;
     dilep_J(g, nu, nb, J);
     double r[4] = {F[0] - s.tq[0], F[1] - s.tq[1], F[2] - s.tq[2], F[3] - s.tq[3]}, dv[4];
@@ -448,7 +515,7 @@ __device__ __forceinline__ bool dilep_accept(const DilepPoint& s, const DilepGeo
 // (GeV^4).  Inputs in GeV / GeV^2.
 __device__ __forceinline__ void solve_dilepton(const v4& b_in, const v4& bb_in, const v4& lp_in, const v4& lm_in,
                                                double metx, double mety, double q2wp, double q2t, double q2wm,
-                                               double q2tb, NuSet& out)
+                                               double q2tb, NuSet& out, double polish_tol)
 {
   out.n = 0;
   DilepPoint s;
@@ -460,7 +527,7 @@ __device__ __forceinline__ void solve_dilepton(const v4& b_in, const v4& bb_in, 
   dilep_geom(b_in, bb_in, lp_in, lm_in, s, g);
   for (int k = 0; k < roots.n; ++k) {
     NuSol sol;
-    if (dilep_accept(s, g, roots.get(k), sol)) out.put(sol);
+    if (dilep_accept(s, g, roots.get(k), sol, polish_tol)) out.put(sol);
   }
 }
 

@@ -132,3 +132,53 @@ def test_set_proposal(mem):
         mem.train_proposal(dy, tr)
     with pytest.raises(mem.MemError):
         mem.train_proposal(p, tr[:, :, :2].contiguous(), capture=16, batch=4096)
+
+
+def test_flow_seeded_grids(mem):
+    """MEM_FLOW_SEED_GRID: VEGAS starting from grids seeded by the flow's
+    samples, every iteration in the estimate.  The seeded first iteration
+    has a smaller variance than the uniform grid's; it is importance
+    sampling on a grid fixed before its points are drawn, so its estimate
+    is unbiased: the mean ratio to a high-statistics VEGAS reference over
+    the events is 1 within three standard errors.  (The combination over
+    iterations weights them by their estimated variances, as plain VEGAS
+    does; at low statistics that weighting pulls both low alike.)  The call
+    is deterministic; other kinds and unknown modes are refused."""
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    tr = mem.to_components(events.ttbar_dilepton(512, 0x76)["obs"]).cuda()
+    say("seeded grids: train on 512 events, 16 epochs")
+    f = mem.train_proposal(p, tr, seed=13, **dict(SMALL, epochs=16))
+    n_ev = 64
+    comps = mem.to_components(events.ttbar_dilepton(n_ev, 0x77)["obs"]).cuda()
+    n_int = 2 * n_ev
+    recs = {}
+    for name, kw in (("uniform", {}), ("seeded", dict(flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID))):
+        rec = torch.zeros((4, n_int, 2), dtype=torch.float64, device="cuda")
+        out = mem.integrate_events(comps, p, 16384, 4, seed=21, iter_out=rec, **kw)
+        torch.cuda.synchronize()
+        recs[name] = (rec.cpu().numpy(), [t.cpu().numpy() for t in out])
+    rel0 = {k: np.sqrt(v[0][0, :, 1]) / np.maximum(v[0][0, :, 0], 1e-300) for k, v in recs.items()}
+    say("first-iteration median relative error", {k: float(np.median(v)) for k, v in rel0.items()})
+    assert np.median(rel0["seeded"]) < 0.8 * np.median(rel0["uniform"])
+    again = mem.integrate_events(comps, p, 16384, 4, seed=21, flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID)
+    for a, b in zip(recs["seeded"][1], again):
+        assert np.array_equal(a, b.cpu().numpy())
+    say("seeded grids: VEGAS reference 262144 x 10")
+    Pr, Er, Sr = (t.cpu().numpy() for t in mem.integrate_events(comps, p, 262144, 10, seed=22))
+    assert np.all(Sr == 0) and np.median(Er / Pr) < 0.01 and np.all(Er < 0.03 * Pr)
+    P0 = recs["seeded"][0][0, :, 0].reshape(n_ev, 2).mean(axis=1)     # the first iteration alone
+    r = P0 / Pr
+    t = (r.mean() - 1.0) / (r.std(ddof=1) / np.sqrt(n_ev))
+    say(f"first-iteration ratio to the reference: mean {r.mean():.4f}, t {t:.2f}")
+    assert abs(t) < 3.0
+    Ps, Es, Ss = recs["seeded"][1]
+    assert np.all(Ss == 0)
+    pull = (Ps - Pr) / np.sqrt(Es ** 2 + Er ** 2)
+    say(f"combined pulls: mean {pull.mean():.2f}, std {pull.std():.2f}")
+    assert abs(pull.mean()) < 1.5 and pull.std() < 2.0
+    dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    dcomps = mem.to_components(events.drell_yan(2, 3)["obs"]).cuda()
+    with pytest.raises(mem.MemError):
+        mem.integrate_events(dcomps, dy, 4096, 2, flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID)
+    with pytest.raises(mem.MemError):
+        mem.integrate_events(comps, p, 4096, 2, flow=f, flow_mode=7)
