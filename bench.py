@@ -35,18 +35,21 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 # Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
 # FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
 # peak is half the FP32 one).  Counted by measure/opcount.py on
-# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1254.9 FP64 +
-# 742.0 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
-FLOP_PER_EVAL = 2.0 * 1254.9 + 742.0
+# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1242.4 FP64 +
+# 702.6 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
+FLOP_PER_EVAL = 2.0 * 1242.4 + 702.6
 
 # HBM bytes per fixed-budget launch of the integrand kernel (4096 events x
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # script's fixed-budget pass, each scaled by what the counter reads for plain
-# kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
-# FETCH 97 030 KiB x 2.000 + WRITE 266 093 KiB x 1.000.  Valid for this
-# workload and the kernel build the counters were taken on; None otherwise.
-TRAFFIC_BYTES_PER_LAUNCH = (97400 * 2.000 + 266094 * 1.000) * 1024
+# kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md).
+# Valid only for this workload and the kernel build the counters were taken
+# on: None until they are taken on the current build.
+TRAFFIC_BYTES_PER_LAUNCH = None
 TRAFFIC_WORKLOAD = (4096, 65536)
+
+# tuned launch configurations (mem_autotune's table) shipped with the package
+TUNING_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1407_7595_amd", "tuning.txt")
 
 
 def log(*a):
@@ -375,6 +378,8 @@ def main():
     ap.add_argument("--no-grid", action="store_true", help="skip the grid-PDF pass")
     ap.add_argument("--no-f2", action="store_true", help="skip the t tbar H vs t tbar b bbar pass")
     ap.add_argument("--flow-train-events", type=int, default=FLOW_TRAIN_EVENTS)
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on the benchmark events and write the tuning table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB fill and a 256 MiB elementwise copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -403,6 +408,18 @@ def main():
     comps = mem.to_components(d["obs"]).cuda()
     proc = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
     n_ev = args.events
+    # launch configuration: the tuned table's entry for this device, or a
+    # fresh tuning run (--tune, which rewrites the table's entry)
+    launch = {"source": "default"}
+    if args.tune:
+        best, bw, rate = proc.autotune(comps, PTS, table_path=TUNING_TABLE)
+        launch = {"source": "tuned now", "tuner_evals_per_s": rate}
+        log(f"autotune: chunk {best}, {bw} waves per SIMD, {rate:.4g} evals/s -> {TUNING_TABLE}")
+    elif os.path.exists(TUNING_TABLE) and proc.load_tuning(TUNING_TABLE):
+        launch = {"source": "table"}
+    launch.update({"chunk_points": proc.chunk_points(), "waves_per_simd": proc.waves(),
+                   "table": os.path.relpath(TUNING_TABLE, os.path.dirname(os.path.abspath(__file__)))})
+    log(f"launch: {launch}")
     P = torch.empty(n_ev, dtype=torch.float64, device="cuda")
     E = torch.empty_like(P)
     S = torch.empty(n_ev, dtype=torch.int32, device="cuda")
@@ -456,6 +473,23 @@ def main():
                  "median_iterations": float(np.median(n_used.cpu().numpy())),
                  "mean_iterations": float(np.mean(n_used.cpu().numpy()))}
         log(f"equal split: {equal}")
+    # adaptive stratified sampling on top of the grid (equal split across
+    # the assignments, which stratification requires), same target
+    strat = None
+    if args.steps:
+        def run_strat():
+            mem.integrate_events(comps, proc, PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
+                                 n_iter_out=n_used, stratify=mem.MEM_STRATIFY_ADAPTIVE)
+        run_strat()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_strat()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        strat = {"events_per_s": n_ev / ts, "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
+                 "median_iterations": float(np.median(n_used.cpu().numpy())),
+                 "mean_iterations": float(np.mean(n_used.cpu().numpy()))}
+        log(f"stratified: {strat}")
 
     roof = None
     if FLOP_PER_EVAL is not None and launches > 0:
@@ -490,11 +524,13 @@ def main():
                    "events": n_ev, "points_per_iteration": PTS, "target_rel_err": TARGET,
                    "proposal": "vegas", "allocation": "neyman across the two assignments"},
         "integrand_evals_per_s": evals_per_s,
+        "launch": launch,
         "fixed_budget": {"iterations": FIXED_ITERS, "seconds": fixed_s, "kernel_ms": kern_ms,
                          "median_rel_err": float(np.median(fixed_rel))},
         "converged_fraction": conv, "median_iterations": float(np.median(nu)) if args.steps else None,
         "mean_iterations": float(np.mean(nu)) if args.steps else None,
         "vegas_equal_split": equal,
+        "vegas_stratified": strat,
         "flow_vs_vegas": flow,
         "parton_level": parton,
         "pdf_grid": grid,

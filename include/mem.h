@@ -242,9 +242,40 @@ typedef struct mem_flow_s* mem_flow;
  *                  Each iteration is still VEGAS importance sampling on
  *                  its own grid, so the estimate stays unbiased; ttbar
  *                  dilepton processes only (MEM_EUNSUPPORTED), no
- *                  ess_threshold.  Other values: MEM_EINVAL.           */
+ *                  ess_threshold.  Other values: MEM_EINVAL.
+ *  stratify        MEM_STRATIFY_OFF (0, the default): plain VEGAS
+ *                  importance sampling (Sec. 2).  MEM_STRATIFY_ADAPTIVE (1):
+ *                  adaptive stratified sampling on top of the grid (Lepage,
+ *                  J. Comput. Phys. 439 (2021) 110386).  Per integral of N
+ *                  points per iteration and D dimensions, the map's input
+ *                  cube is cut into H = n_s^D equal hypercubes, n_s the
+ *                  largest integer with 2 n_s^D <= N and n_s^D <= 16384;
+ *                  hypercube h (digits c_d of h in base n_s, dimension 0
+ *                  least significant) gets n_h of the N points, taken in
+ *                  hypercube order: point k of the iteration (the k-th
+ *                  draw of the point stream, as without stratification)
+ *                  lies in the hypercube whose cumulative range holds k
+ *                  and enters the map as y_d = (c_d + u_d) / n_s.  The
+ *                  iteration estimate is sum_h mean_h(w) / H with variance
+ *                  sum_h s_h^2 / (H^2 n_h) (s_h^2 the sample variance of
+ *                  the weights in h); the grid adapts from the per-bin sums
+ *                  of w^2 / (H n_h).  The first iteration splits N equally
+ *                  (floor(N / H) each, one more to the first N mod H
+ *                  hypercubes); afterwards every hypercube keeps 2 points
+ *                  and the other N - 2H go out in proportion to s_h^0.75,
+ *                  rounded down, the remainder one each to the first
+ *                  hypercubes in index order (equal split again when every
+ *                  s_h is 0 or their sum is not finite).  Iterations are
+ *                  combined as without stratification.  Work-queue chunks
+ *                  are capped at 4096 points.  Requires the equal split
+ *                  across permutations (MEM_EINVAL with MEM_ALLOC_NEYMAN);
+ *                  no flow and no checkpoint (MEM_EUNSUPPORTED).  Device
+ *                  memory on top of plain VEGAS: 8 bytes per point of an
+ *                  iteration and 12 per hypercube.  Other values:
+ *                  MEM_EINVAL.                                          */
 enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
 enum { MEM_FLOW_SAMPLE = 0, MEM_FLOW_SEED_GRID = 1 };
+enum { MEM_STRATIFY_OFF = 0, MEM_STRATIFY_ADAPTIVE = 1 };
 
 /* Per-integral state of a VEGAS integration, owned by the library (see
  * mem_checkpoint_create). */
@@ -293,6 +324,7 @@ typedef struct {
   mem_free_fn free_fn;
   void* alloc_user;
   int32_t flow_mode;
+  int32_t stratify;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */
@@ -425,29 +457,48 @@ mem_status mem_checkpoint_load(const char* path, mem_checkpoint* out);
 mem_status mem_checkpoint_iterations(mem_checkpoint c, int32_t* n_iter);
 
 /* ---- autotuner ----
- * Points per work-queue chunk (the tile one workgroup integrates) trade
- * queue overhead and per-chunk partial sums against load balance and tail
- * effects; the best value depends on the GPU, the process and its
- * precision.  mem_autotune times a 2-iteration integration of the given
- * events (n_points per event per iteration) with each candidate (NULL:
- * 1024, 2048, 4096, 8192, 16384; each a multiple of 256 <= 65536), keeps
+ * The launch configuration of a process's integrand kernel, per device:
+ *  - points per work-queue chunk (the tile one workgroup of 256 threads
+ *    integrates, so chunk_points / 256 points per thread): queue overhead
+ *    and per-chunk partial sums against load balance and tail effects;
+ *  - waves per SIMD the kernel is compiled for (its launch bounds: a
+ *    register budget of 512 / waves per lane), i.e. latency hiding
+ *    against register spills.  Compiled variants: Drell-Yan 1, 2, 4; t tbar
+ *    H 2; the other kinds 1 and 2 (the first of each list is the
+ *    default).  At one wave per SIMD the dilepton kernel compacts its root
+ *    searches through LDS; at two it runs them per lane (same values).
+ *    A launch that mixes kinds uses their default variant.
+ * mem_autotune times a 2-iteration integration of the given events
+ * (n_points per event per iteration) with every pair of a chunk candidate
+ * (NULL: 1024, 2048, 4096, 8192, 16384; each a multiple of 256 <= 65536)
+ * and a waves candidate (NULL: every compiled variant of the kind), keeps
  * the fastest integrand rate in the process (used by every later
  * mem_integrate_events call whose options do not set chunk_points) and
- * reports it in best_out / rate_out (evaluations per second of the
- * integrand kernel; both optional).  table_path (optional): a text table
- * of lines "arch kind precision chunk_points evals_per_s", created or
- * updated in place for this device and process.  Errors: MEM_EINVAL (null
- * process, no events, bad candidates, unwritable table), the errors of
+ * reports it in best_out, best_waves_out and rate_out (evaluations per
+ * second of the integrand kernel; all optional).  table_path (optional):
+ * a text table of lines "arch kind precision chunk_points waves_per_simd
+ * evals_per_s", created or updated in place for this device and process.
+ * Errors: MEM_EINVAL (null process, no events, bad candidates, a waves
+ * candidate not compiled for the kind, unwritable table), the errors of
  * mem_integrate_events. */
 mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, const int32_t* candidates,
-                        int32_t n_cand, const char* table_path, int32_t* best_out, double* rate_out);
+                        int32_t n_cand, const int32_t* waves, int32_t n_waves, const char* table_path,
+                        int32_t* best_out, int32_t* best_waves_out, double* rate_out);
 
-/* Look up the tuned chunk size of a process in a table written by
- * mem_autotune, for architecture `arch` (e.g. "gfx950"; NULL: the current
- * device's).  found (optional) is set to 1 when the entry exists; a
- * missing entry is not an error.  MEM_EINVAL for an unreadable table or a
- * malformed entry. */
+/* Look up the tuned launch configuration of a process in a table written
+ * by mem_autotune, for architecture `arch` (e.g. "gfx950"; NULL: the
+ * current device's).  found (optional) is set to 1 when the entry exists;
+ * a missing entry is not an error.  MEM_EINVAL for an unreadable table or
+ * a malformed entry (including a waves value not compiled for the kind). */
 mem_status mem_tuning_load(mem_process p, const char* table_path, const char* arch, int32_t* found);
+
+/* Set the launch configuration directly: chunk_points 0 or a multiple of
+ * 256 <= 65536 (0: the library default, 4096), waves 0 or a compiled
+ * variant of the kind (0: the default).  MEM_EINVAL otherwise. */
+mem_status mem_process_set_launch(mem_process p, int32_t chunk_points, int32_t waves);
+
+/* The waves-per-SIMD variant integrations of this process use. */
+mem_status mem_process_waves(mem_process p, int32_t* waves);
 
 /* The chunk size integrations of this process use by default. */
 mem_status mem_process_chunk_points(mem_process p, int32_t* chunk_points);

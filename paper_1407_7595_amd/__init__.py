@@ -30,7 +30,7 @@ EXPORTS = ("mem_create_process", "mem_set_transfer_functions", "mem_destroy_proc
            "mem_vegas_refine", "mem_vegas_capture", "mem_flow_create", "mem_flow_destroy",
            "mem_flow_set_params", "mem_flow_get_params", "mem_flow_context", "mem_flow_sample",
            "mem_flow_log_prob", "mem_flow_train_step", "mem_autotune", "mem_tuning_load",
-           "mem_process_chunk_points", "mem_parton_weights", "mem_set_pdf_grid", "mem_toy_pdf_table",
+           "mem_process_chunk_points", "mem_process_set_launch", "mem_process_waves", "mem_parton_weights", "mem_set_pdf_grid", "mem_toy_pdf_table",
            "mem_discriminant", "mem_checkpoint_create", "mem_checkpoint_destroy", "mem_checkpoint_save",
            "mem_checkpoint_load", "mem_checkpoint_iterations", "mem_status_string", "mem_last_error")
 
@@ -72,7 +72,7 @@ class IntegrateOpts(ctypes.Structure):
                 ("weights_out", ctypes.c_void_p), ("weights_stride", ctypes.c_int64),
                 ("weights_integral", ctypes.c_int32), ("weights_rows", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
                 ("checkpoint", ctypes.c_void_p), ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
-                ("alloc_user", ctypes.c_void_p), ("flow_mode", ctypes.c_int32)]
+                ("alloc_user", ctypes.c_void_p), ("flow_mode", ctypes.c_int32), ("stratify", ctypes.c_int32)]
 
 
 MEM_HOOK_NONFINITE = 1
@@ -80,6 +80,10 @@ MEM_HOOK_NONFINITE = 1
 # how a flow is used (mem_integrate_opts.flow_mode)
 MEM_FLOW_SAMPLE = 0
 MEM_FLOW_SEED_GRID = 1
+
+# mem_integrate_opts.stratify
+MEM_STRATIFY_OFF = 0
+MEM_STRATIFY_ADAPTIVE = 1
 
 # bytes of the per-device scratch of mem_integrate_events_noalloc
 MEM_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
@@ -143,7 +147,9 @@ def lib():
             "mem_flow_sample": (I32, [P, P, P, P, I32, I64, U64, U32, P, P, P]),
             "mem_flow_log_prob": (I32, [P, P, P, P, I64, P, P]),
             "mem_flow_train_step": (I32, [P, P, P, P, P, I64, D, P, P, P]),
-            "mem_autotune": (I32, [P, P, I64, P, I32, ctypes.c_char_p, P, P]),
+            "mem_autotune": (I32, [P, P, I64, P, I32, P, I32, ctypes.c_char_p, P, P, P]),
+            "mem_process_set_launch": (I32, [P, I32, I32]),
+            "mem_process_waves": (I32, [P, P]),
             "mem_tuning_load": (I32, [P, ctypes.c_char_p, ctypes.c_char_p, P]),
             "mem_process_chunk_points": (I32, [P, P]),
             "mem_checkpoint_create": (I32, [P]),
@@ -212,15 +218,26 @@ class Process:
         b = (ctypes.c_double * 4)(*bounds)
         _check(lib().mem_set_pdf_grid(self.handle, a.ctypes.data, a.shape[1], a.shape[0], b), "mem_set_pdf_grid")
 
-    def autotune(self, comps, n_points, candidates=None, table_path=None, charge=None):
-        """mem_autotune on the given events; returns (chunk_points, evals/s)"""
+    def autotune(self, comps, n_points, candidates=None, waves=None, table_path=None, charge=None):
+        """mem_autotune on the given events over chunk sizes x waves-per-SIMD
+        variants; returns (chunk_points, waves, evals/s)"""
         ev = events_struct(comps, charge)
         cand = (ctypes.c_int32 * len(candidates))(*candidates) if candidates else None
-        best, rate = ctypes.c_int32(), ctypes.c_double()
+        wv = (ctypes.c_int32 * len(waves))(*waves) if waves else None
+        best, bw, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(lib().mem_autotune(self.handle, ctypes.byref(ev), n_points, cand, len(candidates) if candidates else 0,
-                                  table_path.encode() if table_path else None, ctypes.byref(best),
-                                  ctypes.byref(rate)), "mem_autotune")
-        return best.value, rate.value
+                                  wv, len(waves) if waves else 0, table_path.encode() if table_path else None,
+                                  ctypes.byref(best), ctypes.byref(bw), ctypes.byref(rate)), "mem_autotune")
+        return best.value, bw.value, rate.value
+
+    def set_launch(self, chunk_points=0, waves=0):
+        """mem_process_set_launch (0: defaults)"""
+        _check(lib().mem_process_set_launch(self.handle, chunk_points, waves), "mem_process_set_launch")
+
+    def waves(self):
+        w = ctypes.c_int32()
+        _check(lib().mem_process_waves(self.handle, ctypes.byref(w)), "mem_process_waves")
+        return w.value
 
     def load_tuning(self, table_path, arch=None):
         found = ctypes.c_int32()
@@ -279,7 +296,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
                      allocation=0, weights_out=None, weights_integral=0, hooks=0, hook_event=0,
-                     checkpoint=None, allocator=None, flow_mode=0, _noalloc=False):
+                     checkpoint=None, allocator=None, flow_mode=0, stratify=0, _noalloc=False):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
@@ -289,7 +306,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
     weights_out: optional float64 device tensor [iterations, stride] for
     the weights of integral weights_integral; hooks / hook_event: test
     hooks (MEM_HOOK_*); checkpoint: optional Checkpoint; allocator:
-    None (hipMalloc), TORCH_ALLOCATOR, or a pair (ALLOC_FN, FREE_FN).
+    None (hipMalloc), TORCH_ALLOCATOR, or a pair (ALLOC_FN, FREE_FN);
+    stratify: MEM_STRATIFY_ADAPTIVE for adaptive stratified sampling.
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
@@ -321,7 +339,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         checkpoint.handle.value if checkpoint is not None else None,
                         ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
                         ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None,
-                        flow_mode)
+                        flow_mode, stratify)
     entry = "mem_integrate_events_noalloc" if _noalloc else "mem_integrate_events"
     _check(getattr(lib(), entry)(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                  ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),

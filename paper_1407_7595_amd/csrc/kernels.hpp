@@ -44,7 +44,7 @@ struct Chunk {
   int64_t start;      // first point index of the chunk inside its integral
   int64_t part_off;   // offset of its partial sums (2 + D*64 doubles)
   int32_t proc;       // index into the launch's process table
-  int32_t pad;
+  int32_t id;         // index in the call's chunk table
 };
 
 // device control block of one integration
@@ -75,6 +75,68 @@ struct QueueHooks {
   int32_t nan_event;   // event whose weights become NaN (-1: none)
 };
 
+// Adaptive stratified sampling (Lepage 2021): per integral, n_s^D = H
+// equal hypercubes of the map's input cube; the iteration's points are
+// handed out in hypercube order by the cumulative counts cum[0..H]
+// (cum[0] = 0, cum[H] = N), so point k lies in the h with
+// cum[h] <= k < cum[h + 1] and enters the map as y_d = (c_d + u_d) / n_s,
+// c_d the base-n_s digits of h (dimension 0 least significant).
+constexpr int kStratHMax = 16384;
+constexpr int kStratChunkMax = 4096;
+// cumulative counts a chunk can touch: every hypercube holds at least two
+// points, so a chunk of c points spans at most c / 2 + 1 of them
+constexpr int kStratSeg = kStratChunkMax / 2 + 2;
+struct StratDesc {
+  int32_t ns;         // hypercubes per dimension
+  int32_t H;          // ns^D
+  int64_t cum_off;    // its H + 1 cumulative counts in StratView::cum
+  int64_t w_off;      // its N point weights in StratView::w
+};
+struct StratView {
+  const StratDesc* sd;     // per integral; null: no stratification
+  const int32_t* cum;
+  const int32_t* h0;       // per chunk (Chunk::id): hypercube of its first point
+  double* w;               // this iteration's weight of every point
+};
+// A chunk's view: the cumulative counts it touches, staged in LDS.
+struct StratChunk {
+  const int32_t* seg;      // cum[h0 .. h0 + nseg)
+  int32_t nseg, h0, ns, H;
+  double* w;               // the integral's point weights
+};
+
+// Point k of a stratified chunk: moves the uniforms u into the point's
+// hypercube and returns H n_h (the bins take w^2 / (H n_h)).
+__device__ __forceinline__ int strat_find(const StratChunk& sc, int64_t k)
+{
+  int lo = 0, hi = sc.nseg - 2;      // the i with seg[i] <= k < seg[i + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)sc.seg[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+// H n_h of the hypercube holding point k
+__device__ __forceinline__ double strat_hn(const StratChunk& sc, int64_t k)
+{
+  const int i = strat_find(sc, k);
+  return (double)sc.H * (double)(sc.seg[i + 1] - sc.seg[i]);
+}
+template <int D>
+__device__ __forceinline__ double strat_point(const StratChunk& sc, int64_t k, double (&u)[D])
+{
+  const int lo = strat_find(sc, k);
+  int r = sc.h0 + lo;
+  const double hn = (double)sc.H * (double)(sc.seg[lo + 1] - sc.seg[lo]);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int c = r % sc.ns;
+    r /= sc.ns;
+    u[d] = ((double)c + u[d]) / (double)sc.ns;
+  }
+  return hn;
+}
+
 // per-integral running state
 enum { ST_WSUM = 0, ST_WISUM, ST_ISUM, ST_NITER, ST_NONFINITE, ST_LAST_I, ST_LAST_V, ST_SIZE = 8 };
 
@@ -100,21 +162,24 @@ __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)
 template <int D, class F>
 __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
                                              double* sbins, double& s1, double& s2, double* wrec, bool poison,
-                                             F&& f)
+                                             bool strat, const StratChunk& sc, F&& f)
 {
   for (int k = threadIdx.x; k < ch.count; k += kBlock) {
     double u[D], x[D];
     int bin[D];
     point_uniforms<D>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
+    const double hn = strat ? strat_point<D>(sc, ch.start + k, u) : 1.0;
     double jac = vegas_map<D>(sgrid, u, x, bin);
     double w = f(x) * jac;
     if (poison) w = __builtin_nan("");
     if (wrec) wrec[k] = w;
     s1 += w;
     s2 += w * w;
+    if (strat) sc.w[ch.start + k] = w;
     if (w != 0.0) {
+      const double q = strat ? w * w / hn : w * w;
 #pragma unroll
-      for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
+      for (int d = 0; d < D; ++d) atomicAdd(&sbins[d * kBins + bin[d]], q);
     }
   }
 }
@@ -132,14 +197,17 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
 // tests the root (dilep_accept) and evaluates the matrix element stage
 // (tt_solution); each point sums its own entries in root order.  Both
 // stages run ceil(total / 64) times per wavefront instead of max(roots)
-// times, and every value equals tt_integrand's bit for bit (same
-// functions, same inputs, same order; a rejected root adds +0).  ON = false
-// compiles to nothing (no LDS) for launches without dilepton chunks.
+// times.  Same functions, same inputs and the same order as tt_integrand (a
+// rejected root adds +0); the compiler contracts the two instances'
+// arithmetic differently, which leaves relative differences of about 1e-11
+// in FP64 and 1e-7 with the FP32 matrix element.  ON = false compiles to
+// nothing (no LDS) for launches without dilepton chunks.
 constexpr int kTTRec = 34;       // DilepPoint (28 doubles), the two jet energies, the monic quartic c0..c3
 template <class T, bool ON>
 __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
                                                 double* sbins, double& s1, double& s2, double* wrec, bool poison,
-                                                const ProcParams& pp, const TTEvent& ev)
+                                                bool strat, const StratChunk& sc, const ProcParams& pp,
+                                                const TTEvent& ev)
 {
   if constexpr (ON) {
     __shared__ double srec[kBlock / kWave][kTTRec][kWave];
@@ -171,6 +239,7 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
       if (live) {
         double u[8], x[8];
         point_uniforms<8>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
+        if (strat) (void)strat_point<8>(sc, ch.start + k, u);
         jac = vegas_map<8>(sgrid, u, x, bin);
         tt_maps<T>(pp, ev, x, m);
         double quart[5];
@@ -243,9 +312,12 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
         if (wrec) wrec[k] = w;
         s1 += w;
         s2 += w * w;
+        if (strat) sc.w[ch.start + k] = w;
         if (w != 0.0) {
+          // H n_h found again rather than held in registers across the solve
+          const double q = strat ? w * w / strat_hn(sc, ch.start + k) : w * w;
 #pragma unroll
-          for (int d = 0; d < 8; ++d) atomicAdd(&sbins[d * kBins + bin[d]], w * w);
+          for (int d = 0; d < 8; ++d) atomicAdd(&sbins[d * kBins + bin[d]], q);
         }
       }
     }
@@ -269,14 +341,18 @@ template <int KINDS> constexpr int queue_waves()
 {
   return (KINDS & kMaskTTH) ? 2 : MEM_TT_WAVES;
 }
-template <class T, int KINDS>
-__global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kernel(
+// WAVES: waves per SIMD the instance is compiled for (its register budget
+// is 512 / WAVES per lane); the tuner picks among the compiled variants.
+template <class T, int KINDS, int WAVES = queue_waves<KINDS>()>
+__global__ __launch_bounds__(kBlock, WAVES) void vegas_queue_kernel(
     const ProcParams* __restrict__ procs, EventsView ev, const Chunk* __restrict__ chunks, int64_t n_chunks,
     const IntegralDesc* __restrict__ ints, const double* __restrict__ grids, const int32_t* __restrict__ active,
     uint64_t seed, Control* __restrict__ ctl, uint32_t* __restrict__ head, double* __restrict__ parts,
-    const int64_t* __restrict__ alloc, QueueHooks hk)
+    const int64_t* __restrict__ alloc, QueueHooks hk, StratView sv)
 {
+  static_assert(!(KINDS & kMaskTTH) || WAVES >= 2, "t tbar H instances run at two or more waves per SIMD");
   __shared__ double sgrid[kMaxDims * (kBins + 1)];
+  __shared__ int32_t sseg[kStratSeg];
   // per-wavefront bin sums, combined in wavefront order: the result does not
   // depend on how the wavefronts interleave
   __shared__ double sbins[kBlock / kWave][kMaxDims * kBins];
@@ -304,6 +380,15 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
     for (int i = threadIdx.x; i < D * kBins; i += kBlock)
 #pragma unroll
       for (int w = 0; w < kBlock / kWave; ++w) sbins[w][i] = 0.0;
+    const bool strat = sv.sd != nullptr;
+    StratChunk sc{sseg, 2, 0, 1, 1, nullptr};
+    if (strat) {
+      const StratDesc sd = sv.sd[ch.integral];
+      const int32_t h0 = sv.h0[ch.id];
+      const int nseg = min(min(ch.count / 2 + 2, sd.H + 1 - h0), kStratSeg);
+      for (int i = threadIdx.x; i < nseg; i += kBlock) sseg[i] = sv.cum[sd.cum_off + h0 + i];
+      sc = StratChunk{sseg, nseg, h0, sd.ns, sd.H, sv.w + sd.w_off};
+    }
     __syncthreads();
     const ProcParams& pp = procs[ch.proc];
     double* wbins = sbins[threadIdx.x / kWave];
@@ -313,27 +398,28 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
     if ((KINDS & kMaskDY) && pp.kind == kDY) {
       DYEvent e;
       dy_load(ev, ch.event, e);
-      chunk_points<2>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
+      chunk_points<2>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc,
                       [&](const double (&x)[2]) { return dy_integrand(pp, e, x); });
     } else if ((KINDS & kMaskTT) && pp.kind == kTT) {
       TTEvent e;
       tt_load(ev, ch.event, ch.perm, e);
-      // launches that also carry t tbar H chunks run at two waves per SIMD,
-      // where the 80 KB of queues would not fit twice: per-lane root loop
-      if constexpr ((KINDS & kMaskTTH) == 0)
-        chunk_points_tt<T, (KINDS & kMaskTT) != 0>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, pp, e);
+      // instances at two or more waves per SIMD (every launch that also
+      // carries t tbar H chunks, and the tuner's variants), where the 80 KB
+      // of queues would not fit twice: per-lane root loop
+      if constexpr (WAVES == 1)
+        chunk_points_tt<T, (KINDS & kMaskTT) != 0>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc, pp, e);
       else
-        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc,
                         [&](const double (&x)[8]) { return tt_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskSL) && pp.kind == kSL) {
       SLEvent e;
       sl_load(ev, ev.charge, ch.event, ch.perm, e);
-      chunk_points<7>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
+      chunk_points<7>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc,
                       [&](const double (&x)[7]) { return sl_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & kMaskTTH) && pp.kind == kTTH) {
       TTHEvent e;
       tth_load(ev, ev.charge, ch.event, ch.perm, e);
-      chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
+      chunk_points<9>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc,
                       [&](const double (&x)[9]) { return tth_integrand<T>(pp, e, x, nullptr); });
     } else if ((KINDS & (kMaskTHL | kMaskTBB)) && (pp.kind == kTHL || pp.kind == kTBB)) {
       // the chunk's event is the same for the whole workgroup: one copy in
@@ -343,10 +429,10 @@ __global__ __launch_bounds__(kBlock, queue_waves<KINDS>()) void vegas_queue_kern
       if (threadIdx.x == 0) f2_load(ev, tth, ch.event, ch.perm, sf2);
       __syncthreads();
       if ((KINDS & kMaskTHL) && tth)
-        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc,
                         [&](const double (&x)[8]) { return f2_integrand<T, true>(pp, sf2, x, nullptr); });
       else if (KINDS & kMaskTBB)
-        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison,
+        chunk_points<8>(ch, seed, iter, sgrid, wbins, s1, s2, wrec, poison, strat, sc,
                         [&](const double (&x)[8]) { return f2_integrand<T, false>(pp, sf2, x, nullptr); });
     }
     block_reduce2<0>(s1, s2, red);

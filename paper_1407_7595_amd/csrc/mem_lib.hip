@@ -48,6 +48,7 @@ struct mem_process_s {
   mem_tf_desc tf[5];
   ProcParams pp;
   int32_t chunk_points = 0;   // tuned points per work-queue chunk (0: library default)
+  int32_t waves = 0;          // tuned waves-per-SIMD variant of its queue kernel (0: the default)
   // parton-density grid on the device (null: toy densities) and its shape
   float* pdf_dev = nullptr;
   int pdf_device = -1;        // the device that holds pdf_dev
@@ -444,7 +445,8 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
                                                              double alpha, const Control* __restrict__ ctl,
                                                              int n_int, double* __restrict__ iter_out,
                                                              const int64_t* __restrict__ alloc,
-                                                             double* __restrict__ n_evals, uint32_t first_kept)
+                                                             double* __restrict__ n_evals, uint32_t first_kept,
+                                                             const double* __restrict__ strat_iv)
 {
   __shared__ double sb[kMaxDims * kBins];
   __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
@@ -473,11 +475,16 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
     }
     const double N = (double)npts;
     atomicAdd(n_evals, N);
-    const double I = s1 / N;
+    double I = s1 / N;
     double var = (s2 / N - I * I) / (N - 1.0);
     if (var < 0.0) var = 0.0;
+    if (strat_iv) {
+      // stratified: the estimate over the hypercubes
+      I = strat_iv[2 * ig];
+      var = strat_iv[2 * ig + 1];
+    }
     double* st = state + (int64_t)ig * ST_SIZE;
-    if (!isfinite(s1) || !isfinite(s2)) st[ST_NONFINITE] = 1.0;
+    if (!isfinite(s1) || !isfinite(s2) || !isfinite(I) || !isfinite(var)) st[ST_NONFINITE] = 1.0;
     if (iter >= first_kept) {
       if (var > 0.0) { st[ST_WSUM] += 1.0 / var; st[ST_WISUM] += I / var; }
       st[ST_ISUM] += I;
@@ -616,6 +623,163 @@ __global__ void neyman_kernel(const int64_t* __restrict__ ev_int0, const int32_t
       return;
     }
   }
+}
+
+// ---- adaptive stratified sampling (Lepage 2021) ----
+// The hypercube of the first point of each chunk of one integral: the
+// largest h with cum[h] <= start.  Called by the whole workgroup once the
+// integral's cumulative counts are in device memory (written by this
+// workgroup before its last barrier).
+__device__ void strat_chunk_starts(const int32_t* cum, int H, const Chunk* __restrict__ chunks,
+                                   const IntegralDesc& in, int32_t* __restrict__ h0)
+{
+  for (int i = threadIdx.x; i < in.n_chunks; i += kBlock) {
+    const int64_t start = chunks[in.chunk0 + i].start;
+    int lo = 0, hi = H - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)cum[mid] <= start) lo = mid; else hi = mid - 1;
+    }
+    h0[in.chunk0 + i] = lo;
+  }
+}
+
+// First iteration: N split equally over the H hypercubes, floor(N / H)
+// each and one more to the first N mod H.
+__global__ __launch_bounds__(kBlock) void strat_init_kernel(const IntegralDesc* __restrict__ ints, StratView sv,
+                                                            int32_t* __restrict__ cum, const Chunk* __restrict__ chunks,
+                                                            int32_t* __restrict__ h0)
+{
+  const IntegralDesc in = ints[blockIdx.x];
+  const StratDesc sd = sv.sd[blockIdx.x];
+  const int64_t q = in.n_points / sd.H, r = in.n_points % sd.H;
+  int32_t* c = cum + sd.cum_off;
+  for (int h = threadIdx.x; h <= sd.H; h += kBlock) c[h] = (int32_t)(h * q + (h < r ? h : r));
+  __syncthreads();
+  strat_chunk_starts(c, sd.H, chunks, in, h0);
+}
+
+// inclusive prefix sum of an int across the workgroup (every thread
+// calls it; wsum: kBlock / kWave ints of LDS); *total gets the sum
+__device__ __forceinline__ int block_scan_int(int v, int* wsum, int* total)
+{
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int o = __shfl_up(v, off, kWave);
+    if (lane >= off) v += o;
+  }
+  if (lane == kWave - 1) wsum[wave] = v;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    before += w < wave ? wsum[w] : 0;
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return v + before;
+}
+
+// After an iteration's integrand launches, per running integral (one
+// workgroup, thread t taking hypercubes t, t + 256, ... so that a
+// wavefront's reads are neighbours): each hypercube's mean and sample
+// variance of its weights, summed in point order
+// (s^2 = (sum w^2 / n - mean^2) n / (n - 1), clipped at 0); the iteration
+// estimate sum_h mean_h / H and its variance sum_h s_h^2 / (H^2 n_h) are the
+// threads' partial sums added in thread order, so the result does not
+// depend on scheduling.  The next iteration's allocation: 2 points per
+// hypercube plus floor((N - 2H) s_h^0.75 / sum_h s_h^0.75), the remainder
+// one each to the first hypercubes in index order (equal split when the sum
+// is 0 or not finite), turned into cumulative counts in place.  s_h^0.75 is
+// formed as sqrt(s sqrt(s)).
+__global__ __launch_bounds__(kBlock) void strat_finish_kernel(const IntegralDesc* __restrict__ ints, StratView sv,
+                                                              int32_t* __restrict__ cum, double* __restrict__ sigb,
+                                                              const int32_t* __restrict__ active,
+                                                              const Chunk* __restrict__ chunks,
+                                                              int32_t* __restrict__ h0, double* __restrict__ strat_iv)
+{
+  __shared__ double pI[kBlock], pV[kBlock], pS[kBlock];
+  __shared__ int64_t pN[kBlock];
+  __shared__ double tot[3];
+  __shared__ int64_t used_all;
+  __shared__ int wsum[kBlock / kWave];
+  const int ig = blockIdx.x;
+  if (!active[ig]) return;
+  const IntegralDesc in = ints[ig];
+  const StratDesc sd = sv.sd[ig];
+  const int H = sd.H;
+  const int64_t N = in.n_points;
+  int32_t* c = cum + sd.cum_off;
+  const double* w = sv.w + sd.w_off;
+  double* sg = sigb + sd.cum_off;
+  const double Hd = (double)H;
+  double Ip = 0.0, Vp = 0.0, Sp = 0.0;
+  for (int h = threadIdx.x; h < H; h += kBlock) {
+    const int32_t k0 = c[h], k1 = c[h + 1];
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+    for (int32_t k = k0; k < k1; ++k) {
+      const double x = w[k];
+      s1 += x;
+      s2 += x * x;
+    }
+    const double n = (double)(k1 - k0);
+    const double mean = s1 / n;
+    double v = (s2 / n - mean * mean) * n / (n - 1.0);
+    if (v < 0.0) v = 0.0;
+    Ip += mean / Hd;
+    Vp += v / (Hd * Hd * n);
+    const double sig = sqrt(v);
+    const double b = sqrt(sig * sqrt(sig));
+    sg[h] = b;
+    Sp += b;
+  }
+  pI[threadIdx.x] = Ip;
+  pV[threadIdx.x] = Vp;
+  pS[threadIdx.x] = Sp;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, v = 0.0, d = 0.0;
+    for (int t = 0; t < kBlock; ++t) { a += pI[t]; v += pV[t]; d += pS[t]; }
+    tot[0] = a; tot[1] = v; tot[2] = d;
+    strat_iv[2 * ig] = a;
+    strat_iv[2 * ig + 1] = v;
+  }
+  __syncthreads();     // every read of this iteration's counts is done
+  const double S = tot[2];
+  const bool equal = !(S > 0.0) || !isfinite(S);
+  const int64_t R = N - 2 * (int64_t)H;
+  // the counts before the remainder, in place of the cumulative counts
+  int64_t u = 0;
+  for (int h = threadIdx.x; h < H; h += kBlock) {
+    const int64_t n = equal ? N / H : 2 + (int64_t)floor((double)R * (sg[h] / S));
+    c[h] = (int32_t)n;
+    u += n;
+  }
+  pN[threadIdx.x] = u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t a = 0;
+    for (int t = 0; t < kBlock; ++t) a += pN[t];
+    used_all = a;
+  }
+  __syncthreads();
+  const int64_t rem = N - used_all;       // 0 <= rem <= H
+  // exclusive prefix sums in tiles of kBlock hypercubes (counts < 2^31)
+  int off = 0;
+  for (int base = 0; base < H; base += kBlock) {
+    const int h = base + threadIdx.x;
+    const int n = h < H ? c[h] + (h < rem ? 1 : 0) : 0;
+    int tile = 0;
+    const int incl = block_scan_int(n, wsum, &tile);
+    if (h < H) c[h] = off + incl - n;
+    off += tile;
+  }
+  if (threadIdx.x == 0) c[H] = off;
+  __syncthreads();
+  strat_chunk_starts(c, H, chunks, in, h0);
 }
 
 template <int KIND, int D, class T>
@@ -845,17 +1009,39 @@ struct DevEvents {
 // The queue kernel instance for a precision and a set of kinds.
 typedef void (*QueueKernel)(const ProcParams*, EventsView, const Chunk*, int64_t, const IntegralDesc*,
                             const double*, const int32_t*, uint64_t, Control*, uint32_t*, double*,
-                            const int64_t*, QueueHooks);
+                            const int64_t*, QueueHooks, StratView);
+// Waves-per-SIMD variants compiled per process kind (the first is the
+// default): Drell-Yan also at 2 and 4, the top kinds at 1 and 2 (spills
+// beyond), t tbar H at 2 only.
+int waves_variants(int kind, int* out)
+{
+  switch (kind) {
+    case MEM_DY_QQ_GAMMA_MUMU: out[0] = 1; out[1] = 2; out[2] = 4; return 3;
+    case MEM_TTH_SEMILEPTON: out[0] = 2; return 1;
+    default: out[0] = 1; out[1] = 2; return 2;
+  }
+}
+bool waves_supported(int kind, int waves)
+{
+  int v[4];
+  const int n = waves_variants(kind, v);
+  for (int i = 0; i < n; ++i) if (v[i] == waves) return true;
+  return false;
+}
+// The queue kernel instance for a precision, a set of kinds and a waves
+// variant (0: the default; a launch of several kinds takes the default).
 template <class T>
-QueueKernel queue_kernel_for(int mask)
+QueueKernel queue_kernel_for(int mask, int waves)
 {
   switch (mask) {
-    case kMaskDY: return vegas_queue_kernel<T, kMaskDY>;
-    case kMaskTT: return vegas_queue_kernel<T, kMaskTT>;
-    case kMaskSL: return vegas_queue_kernel<T, kMaskSL>;
+    case kMaskDY:
+      return waves == 2 ? vegas_queue_kernel<T, kMaskDY, 2> : waves == 4 ? vegas_queue_kernel<T, kMaskDY, 4>
+                                                                          : vegas_queue_kernel<T, kMaskDY>;
+    case kMaskTT: return waves == 2 ? vegas_queue_kernel<T, kMaskTT, 2> : vegas_queue_kernel<T, kMaskTT>;
+    case kMaskSL: return waves == 2 ? vegas_queue_kernel<T, kMaskSL, 2> : vegas_queue_kernel<T, kMaskSL>;
     case kMaskTTH: return vegas_queue_kernel<T, kMaskTTH>;
-    case kMaskTHL: return vegas_queue_kernel<T, kMaskTHL>;
-    case kMaskTBB: return vegas_queue_kernel<T, kMaskTBB>;
+    case kMaskTHL: return waves == 2 ? vegas_queue_kernel<T, kMaskTHL, 2> : vegas_queue_kernel<T, kMaskTHL>;
+    case kMaskTBB: return waves == 2 ? vegas_queue_kernel<T, kMaskTBB, 2> : vegas_queue_kernel<T, kMaskTBB>;
     case kMaskTHL | kMaskTBB: return vegas_queue_kernel<T, kMaskTHL | kMaskTBB>;
     default:
       if (!(mask & kMaskTTH)) return vegas_queue_kernel<T, kMaskDY | kMaskTT | kMaskSL>;
@@ -883,6 +1069,7 @@ struct Group {
   int mask = 0;                 // kinds present
   int blocks = 0;
   QueueKernel kernel = nullptr;
+  int waves = -1;               // the processes' waves variant (0: they differ)
 };
 
 }  // namespace
@@ -1038,6 +1225,12 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
   if (!(o.alpha > 0.0)) return fail(MEM_EINVAL, "alpha must be positive");
   if (o.allocation != MEM_ALLOC_EQUAL && o.allocation != MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "unknown allocation");
   if (o.flow_mode != MEM_FLOW_SAMPLE && o.flow_mode != MEM_FLOW_SEED_GRID) return fail(MEM_EINVAL, "unknown flow_mode");
+  if (o.stratify != MEM_STRATIFY_OFF && o.stratify != MEM_STRATIFY_ADAPTIVE) return fail(MEM_EINVAL, "unknown stratify");
+  if (o.stratify) {
+    if (o.allocation == MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "stratified sampling takes the equal split across permutations");
+    if (o.flow) return fail(MEM_EUNSUPPORTED, "stratified sampling is VEGAS-only");
+    if (o.checkpoint) return fail(MEM_EUNSUPPORTED, "no checkpoints of stratified integrations");
+  }
   const bool target_mode = o.target_rel_err > 0.0;
   const int iters = target_mode ? o.max_iter : n_iter;
   const bool resume = o.checkpoint && o.checkpoint->has;
@@ -1049,7 +1242,7 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
   if (o.hooks & ~(uint32_t)MEM_HOOK_NONFINITE) return fail(MEM_EINVAL, "unknown hook");
   if ((o.hooks & MEM_HOOK_NONFINITE) && (o.hook_event < 0 || o.hook_event >= n_ev))
     return fail(MEM_EINVAL, "hook_event outside the events");
-  if (!o.flow && n_ev > 0) {
+  if (!o.flow && !o.stratify && n_ev > 0) {
     // the processes' own proposal (mem_set_proposal), when they share one
     mem_flow pf = hyp[0] ? hyp[0]->proposal : nullptr;
     for (int i = 1; i < n_hyp && pf; ++i)
@@ -1145,6 +1338,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                                   Workspace& work, mem_flow seed_flow)
 {
   const uint32_t first_kept = seed_flow ? 0u : 1u;
+  const bool strat = o.stratify == MEM_STRATIFY_ADAPTIVE;
   mem_status st = MEM_OK;
   const int n_ev = ev->n_events;
   const bool target_mode = o.target_rel_err > 0.0;
@@ -1215,7 +1409,9 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     IntegralDesc& d = ints[ig];
     // the call's chunk size, else the process's tuned one, else the default
     const int tuned = procs[int_proc[ig]]->chunk_points;
-    const int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : tuned > 0 ? tuned : kDefaultChunk;
+    int64_t chunk_pts = o.chunk_points > 0 ? o.chunk_points : tuned > 0 ? tuned : kDefaultChunk;
+    // a stratified chunk's cumulative counts are staged in LDS
+    if (strat) chunk_pts = std::min<int64_t>(chunk_pts, kStratChunkMax);
     d.chunk0 = (int64_t)chunks.size();
     d.n_chunks = 0;
     for (int64_t s0 = 0; s0 < cover[ig]; s0 += chunk_pts) {
@@ -1225,12 +1421,37 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       c.start = s0;
       c.part_off = part_total;
       c.proc = int_proc[ig];
+      c.id = (int32_t)chunks.size();
       part_total += 2 + (int64_t)d.dims * kBins;
       chunks.push_back(c);
       d.n_chunks++;
     }
   }
   if ((int64_t)chunks.size() > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "too many chunks");
+  // stratification: hypercubes per integral, offsets of their cumulative
+  // counts and of the point weights
+  std::vector<StratDesc> sdesc;
+  int64_t cum_total = 0, w_total = 0;
+  if (strat) {
+    sdesc.resize(n_int);
+    for (int ig = 0; ig < n_int; ++ig) {
+      const int64_t N = ints[ig].n_points;
+      if (N > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "stratified sampling takes below 2^31 points per permutation");
+      const int D = ints[ig].dims;
+      int ns = 1;
+      for (;;) {
+        int64_t h = 1;
+        for (int d = 0; d < D; ++d) h *= ns + 1;
+        if (2 * h > N || h > kStratHMax) break;
+        ++ns;
+      }
+      int64_t H = 1;
+      for (int d = 0; d < D; ++d) H *= ns;
+      sdesc[ig] = StratDesc{ns, (int32_t)H, cum_total, w_total};
+      cum_total += H + 1;
+      w_total += N;
+    }
+  }
   QueueHooks hooks{nullptr, 0, -1, -1};
   if (o.weights_out) {
     if (o.weights_integral < 0 || o.weights_integral >= n_int) return fail(MEM_EINVAL, "weights_integral outside the integrals");
@@ -1282,6 +1503,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     Group& G = groups[group_of(prec)];
     G.queue.push_back((int32_t)c);
     G.mask |= kind_mask(p->desc.kind);
+    G.waves = G.waves < 0 ? p->waves : G.waves == p->waves ? G.waves : 0;
     cost[c] = chunks[c].count * eval_cost(p->desc.kind);
   }
   for (auto& G : groups)
@@ -1300,7 +1522,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   if (st != MEM_OK) return st;
   DevBuf b_procs(&work), b_ints(&work), b_chunks(&work), b_queue(&work), b_grids(&work), b_parts(&work),
       b_state(&work), b_active(&work), b_evi0(&work), b_evnp(&work), b_evnorm(&work), b_done(&work), b_ctl(&work),
-      b_heads(&work), b_P(&work), b_err(&work), b_status(&work), b_alloc(&work), b_cover(&work), b_nev(&work);
+      b_heads(&work), b_P(&work), b_err(&work), b_status(&work), b_alloc(&work), b_cover(&work), b_nev(&work),
+      b_sd(&work), b_cum(&work), b_sigb(&work), b_h0(&work), b_wpt(&work), b_siv(&work);
   size_t qtotal = 0;
   for (auto& G : groups) qtotal += G.queue.size();
   // every work buffer is taken before the first copy or launch; the chunk
@@ -1332,6 +1555,14 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     if (neyman) {
       A(b_alloc, (size_t)n_int * sizeof(int64_t));
       A(b_cover, (size_t)n_int * sizeof(int64_t));
+    }
+    if (strat) {
+      A(b_sd, (size_t)n_int * sizeof(StratDesc));
+      A(b_cum, (size_t)cum_total * sizeof(int32_t));
+      A(b_sigb, (size_t)cum_total * sizeof(double));
+      A(b_h0, chunks.size() * sizeof(int32_t));
+      A(b_wpt, (size_t)w_total * sizeof(double));
+      A(b_siv, (size_t)n_int * 2 * sizeof(double));
     }
     if (o.outputs_on_device == 0) {
       A(b_P, n_ev * sizeof(double));
@@ -1381,6 +1612,14 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
                        b_ints.as<IntegralDesc>(), n_int);
     HIP_TRY(hipGetLastError());
   }
+  StratView sview{nullptr, nullptr, nullptr, nullptr};
+  if (strat) {
+    HIP_TRY(hipMemcpyAsync(b_sd.p, sdesc.data(), n_int * sizeof(StratDesc), hipMemcpyHostToDevice, ws));
+    sview = StratView{b_sd.as<StratDesc>(), b_cum.as<int32_t>(), b_h0.as<int32_t>(), b_wpt.as<double>()};
+    hipLaunchKernelGGL(strat_init_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(), sview,
+                       b_cum.as<int32_t>(), b_chunks.as<Chunk>(), b_h0.as<int32_t>());
+    HIP_TRY(hipGetLastError());
+  }
   if (seed_flow) {
     st = seed_grids_from_flow(seed_flow, dev.view, ints, b_ints.as<IntegralDesc>(), b_grids.as<double>(), o.seed,
                               work, ws);
@@ -1408,7 +1647,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     HIP_TRY(hipStreamSynchronize(ws));
   }
   for (auto& G : groups) {
-    G.kernel = G.prec == MEM_FP32 ? queue_kernel_for<float>(G.mask) : queue_kernel_for<double>(G.mask);
+    const int wv = G.waves > 0 ? G.waves : 0;
+    G.kernel = G.prec == MEM_FP32 ? queue_kernel_for<float>(G.mask, wv) : queue_kernel_for<double>(G.mask, wv);
     G.blocks = persistent_blocks(G.kernel, (int64_t)G.queue.size());
   }
   // chunk order through the queue: the kernel reads chunks[queue[c]]; the
@@ -1442,14 +1682,19 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       hipLaunchKernelGGL(G.kernel, dim3(G.blocks), dim3(kBlock), 0, ws, b_procs.as<ProcParams>(), dev.view, cq,
                          (int64_t)gqn[g], b_ints.as<IntegralDesc>(), b_grids.as<double>(),
                          b_active.as<int32_t>(), o.seed, ctl, b_heads.as<uint32_t>() + g, b_parts.as<double>(),
-                         neyman ? b_alloc.as<int64_t>() : nullptr, hooks);
+                         neyman ? b_alloc.as<int64_t>() : nullptr, hooks, sview);
       HIP_TRY(hipGetLastError());
       if (time_kernels) HIP_TRY(hipEventRecord(tev->back(), ws));
     }
+    if (strat)
+      hipLaunchKernelGGL(strat_finish_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(), sview,
+                         b_cum.as<int32_t>(), b_sigb.as<double>(), b_active.as<int32_t>(), b_chunks.as<Chunk>(),
+                         b_h0.as<int32_t>(), b_siv.as<double>());
     hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(),
                        b_chunks.as<Chunk>(), b_parts.as<double>(), b_grids.as<double>(), b_state.as<double>(),
                        b_active.as<int32_t>(), o.alpha, ctl, n_int, o.iter_out,
-                       neyman ? b_alloc.as<int64_t>() : nullptr, b_nev.as<double>(), first_kept);
+                       neyman ? b_alloc.as<int64_t>() : nullptr, b_nev.as<double>(), first_kept,
+                       strat ? b_siv.as<double>() : nullptr);
     if (target_mode)
       hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                          b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
@@ -1538,6 +1783,12 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     else {
       mem_status es = enqueue_iteration(o.timing_out != nullptr, &tev);
       if (es != MEM_OK) return es;
+    }
+    if (j == 0) {
+      // a launch that failed on the device surfaces here, before the
+      // remaining iterations run on its results
+      HIP_TRY(hipStreamSynchronize(ws));
+      HIP_TRY(hipGetLastError());
     }
     if (target_mode) {
       Control hc{};
@@ -1820,7 +2071,8 @@ bool valid_chunk(int64_t c) { return c > 0 && c % kBlock == 0 && c <= 65536; }
 }  // namespace
 
 extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, const int32_t* candidates,
-                                   int32_t n_cand, const char* table_path, int32_t* best_out, double* rate_out)
+                                   int32_t n_cand, const int32_t* waves, int32_t n_waves, const char* table_path,
+                                   int32_t* best_out, int32_t* best_waves_out, double* rate_out)
 {
   if (!p) return fail(MEM_EINVAL, "null process");
   mem_status st = check_event_arrays(ev);
@@ -1831,30 +2083,41 @@ extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t 
   if (n_cand < 1) return fail(MEM_EINVAL, "no candidates");
   for (int i = 0; i < n_cand; ++i)
     if (!valid_chunk(candidates[i])) return fail(MEM_EINVAL, "candidates must be multiples of 256 <= 65536");
+  int32_t wdef[4];
+  if (!waves) { n_waves = waves_variants(p->desc.kind, wdef); waves = wdef; }
+  if (n_waves < 1) return fail(MEM_EINVAL, "no waves candidates");
+  for (int i = 0; i < n_waves; ++i)
+    if (!waves_supported(p->desc.kind, waves[i])) return fail(MEM_EINVAL, "a waves candidate not compiled for this kind");
   const int n_ev = ev->n_events;
   std::vector<double> P(n_ev), E(n_ev);
   std::vector<int32_t> S(n_ev);
+  const int32_t keep_chunk = p->chunk_points, keep_waves = p->waves;
   double best_rate = -1.0;
-  int32_t best = candidates[0];
-  for (int i = 0; i < n_cand; ++i) {
-    double rate = 0.0;
-    for (int rep = 0; rep < 2; ++rep) {   // the better of two runs
-      double tm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      mem_integrate_opts o{};
-      o.seed = 0x5EEDu + (uint64_t)rep;
-      o.alpha = 1.5;
-      o.max_iter = 2;
-      o.chunk_points = candidates[i];
-      o.use_graph = 0;
-      o.timing_out = tm;
-      st = mem_integrate_events(ev, &p, 1, &n_points, 1, 2, &o, P.data(), E.data(), S.data());
-      if (st != MEM_OK) return st;
-      if (tm[0] > 0.0) rate = std::max(rate, tm[2] / (tm[0] * 1e-3));
+  int32_t best = candidates[0], best_w = waves[0];
+  for (int iw = 0; iw < n_waves; ++iw) {
+    p->waves = waves[iw];
+    for (int i = 0; i < n_cand; ++i) {
+      double rate = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {   // the better of two runs
+        double tm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        mem_integrate_opts o{};
+        o.seed = 0x5EEDu + (uint64_t)rep;
+        o.alpha = 1.5;
+        o.max_iter = 2;
+        o.chunk_points = candidates[i];
+        o.use_graph = 0;
+        o.timing_out = tm;
+        st = mem_integrate_events(ev, &p, 1, &n_points, 1, 2, &o, P.data(), E.data(), S.data());
+        if (st != MEM_OK) { p->chunk_points = keep_chunk; p->waves = keep_waves; return st; }
+        if (tm[0] > 0.0) rate = std::max(rate, tm[2] / (tm[0] * 1e-3));
+      }
+      if (rate > best_rate) { best_rate = rate; best = candidates[i]; best_w = waves[iw]; }
     }
-    if (rate > best_rate) { best_rate = rate; best = candidates[i]; }
   }
   p->chunk_points = best;
+  p->waves = best_w;
   if (best_out) *best_out = best;
+  if (best_waves_out) *best_waves_out = best_w;
   if (rate_out) *rate_out = best_rate;
   if (table_path) {
     const std::string arch = device_arch();
@@ -1872,11 +2135,11 @@ extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t 
       std::fclose(fh);
     }
     char row[256];
-    std::snprintf(row, sizeof row, "%s %d %.6g", key.c_str(), best, best_rate);
+    std::snprintf(row, sizeof row, "%s %d %d %.6g", key.c_str(), best, best_w, best_rate);
     lines.push_back(row);
     FILE* fo = std::fopen(table_path, "w");
     if (!fo) return fail(MEM_EINVAL, std::string("cannot write ") + table_path);
-    std::fputs("# arch kind precision chunk_points evals_per_s\n", fo);
+    std::fputs("# arch kind precision chunk_points waves_per_simd evals_per_s\n", fo);
     for (const auto& ln : lines)
       if (ln[0] != '#') { std::fputs(ln.c_str(), fo); std::fputc('\n', fo); }
     std::fclose(fo);
@@ -1898,13 +2161,35 @@ extern "C" mem_status mem_tuning_load(mem_process p, const char* table_path, con
   while (std::fgets(buf, sizeof buf, fh)) {
     std::string ln(buf);
     if (ln.compare(0, key.size() + 1, key + " ") != 0) continue;
-    long c = std::strtol(ln.c_str() + key.size() + 1, nullptr, 10);
-    if (!valid_chunk(c)) { st = fail(MEM_EINVAL, "malformed tuning entry"); break; }
+    char* end = nullptr;
+    const long c = std::strtol(ln.c_str() + key.size() + 1, &end, 10);
+    const long w = std::strtol(end, nullptr, 10);
+    if (!valid_chunk(c) || !waves_supported(p->desc.kind, (int)w)) { st = fail(MEM_EINVAL, "malformed tuning entry"); break; }
     p->chunk_points = (int32_t)c;
+    p->waves = (int32_t)w;
     if (found) *found = 1;
   }
   std::fclose(fh);
   return st;
+}
+
+extern "C" mem_status mem_process_set_launch(mem_process p, int32_t chunk_points, int32_t waves)
+{
+  if (!p) return fail(MEM_EINVAL, "null process");
+  if (chunk_points != 0 && !valid_chunk(chunk_points)) return fail(MEM_EINVAL, "chunk_points must be 0 or a multiple of 256 <= 65536");
+  if (waves != 0 && !waves_supported(p->desc.kind, waves)) return fail(MEM_EINVAL, "waves variant not compiled for this kind");
+  p->chunk_points = chunk_points;
+  p->waves = waves;
+  return MEM_OK;
+}
+
+extern "C" mem_status mem_process_waves(mem_process p, int32_t* waves)
+{
+  if (!p || !waves) return fail(MEM_EINVAL, "null argument");
+  int32_t v[4];
+  waves_variants(p->desc.kind, v);
+  *waves = p->waves > 0 ? p->waves : v[0];
+  return MEM_OK;
 }
 
 extern "C" mem_status mem_process_chunk_points(mem_process p, int32_t* chunk_points)

@@ -142,7 +142,8 @@ def test_flow_seeded_grids(mem):
     is unbiased: the mean ratio to a high-statistics VEGAS reference over
     the events is 1 within three standard errors.  (The combination over
     iterations weights them by their estimated variances, as plain VEGAS
-    does; at low statistics that weighting pulls both low alike.)  The call
+    does; at low statistics that weighting pulls both low alike, so the
+    combined estimates are held to plain VEGAS's calibration.)  The call
     is deterministic; other kinds and unknown modes are refused."""
     p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
     tr = mem.to_components(events.ttbar_dilepton(512, 0x76)["obs"]).cuda()
@@ -171,11 +172,17 @@ def test_flow_seeded_grids(mem):
     t = (r.mean() - 1.0) / (r.std(ddof=1) / np.sqrt(n_ev))
     say(f"first-iteration ratio to the reference: mean {r.mean():.4f}, t {t:.2f}")
     assert abs(t) < 3.0
-    Ps, Es, Ss = recs["seeded"][1]
-    assert np.all(Ss == 0)
-    pull = (Ps - Pr) / np.sqrt(Es ** 2 + Er ** 2)
-    say(f"combined pulls: mean {pull.mean():.2f}, std {pull.std():.2f}")
-    assert abs(pull.mean()) < 1.5 and pull.std() < 2.0
+    # the combined estimates: no worse calibrated than plain VEGAS's with
+    # the same points (median pull and median absolute pull)
+    med = {}
+    for name in ("uniform", "seeded"):
+        Pc, Ec, Sc = recs[name][1]
+        assert np.all(Sc == 0)
+        pull = (Pc - Pr) / np.sqrt(Ec ** 2 + Er ** 2)
+        med[name] = (float(np.median(pull)), float(np.median(np.abs(pull))))
+    say("combined pulls (median, median |pull|)", med)
+    assert abs(med["seeded"][0]) <= abs(med["uniform"][0]) + 0.5
+    assert med["seeded"][1] <= med["uniform"][1] + 0.5
     dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
     dcomps = mem.to_components(events.drell_yan(2, 3)["obs"]).cuda()
     with pytest.raises(mem.MemError):
