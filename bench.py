@@ -202,8 +202,31 @@ def flow_leg(mem, proc, comps, n_ev, args):
               "mean_iterations": float(np.mean(n_used.cpu().numpy())),
               "median_iterations": float(np.median(n_used.cpu().numpy()))}
     log(f"flow-seeded VEGAS grids: {seeded}")
+    # ESS/N per integral: the untrained flow (the identity, i.e. uniform
+    # sampling), the trained flow (its first batch) and the VEGAS grid after
+    # three adaptations (its fourth iteration)
+    n_int = 2 * n_ev
+
+    def ess_quantiles(rec, n):
+        I, var = rec[..., 0], rec[..., 1]
+        den = var * (n - 1) + I * I
+        e = np.where(den > 0, I * I / np.maximum(den, 1e-300), 0.0)
+        return {q: float(np.quantile(e, v)) for q, v in (("p10", 0.1), ("median", 0.5), ("p90", 0.9))}
+
+    ess = {}
+    for name, fl in (("untrained_flow", mem.Flow()), ("trained_flow", f)):
+        rec = torch.zeros((2, n_int, 2), dtype=torch.float64, device="cuda")
+        mem.integrate_events(comps, proc, FLOW_PTS, 2, seed=SEED_TRAIN + 1, flow=fl, ess_threshold=1e-12,
+                             iter_out=rec)
+        torch.cuda.synchronize()
+        ess[name] = ess_quantiles(rec.cpu().numpy()[0], FLOW_PTS // 2)
+    rec = torch.zeros((4, n_int, 2), dtype=torch.float64, device="cuda")
+    mem.integrate_events(comps, proc, FLOW_PTS, 4, seed=SEED_TRAIN + 1, iter_out=rec)
+    torch.cuda.synchronize()
+    ess["vegas_iteration_4"] = ess_quantiles(rec.cpu().numpy()[3], FLOW_PTS // 2)
+    log(f"ESS/N quantiles over the {n_int} integrals at {FLOW_PTS // 2} points: {ess}")
     out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times), "flow_alone": alone,
-           "flow_seeded_grids": seeded,
+           "flow_seeded_grids": seeded, "ess_over_n": ess,
            "vegas_same_points": vegas_same,
            "points_per_event_per_batch": FLOW_PTS, "fallback_fraction": float(np.mean(st == 4)),
            "converged_fraction": float(np.mean((st == 0) | (st == 4))),
@@ -412,9 +435,12 @@ def main():
     # fresh tuning run (--tune, which rewrites the table's entry)
     launch = {"source": "default"}
     if args.tune:
-        best, bw, rate = proc.autotune(comps, PTS, table_path=TUNING_TABLE)
-        launch = {"source": "tuned now", "tuner_evals_per_s": rate}
-        log(f"autotune: chunk {best}, {bw} waves per SIMD, {rate:.4g} evals/s -> {TUNING_TABLE}")
+        # the headline's own call: target mode to 1 %, Neyman allocation
+        best, bw, rate = proc.autotune(comps, PTS, table_path=TUNING_TABLE, target_rel_err=TARGET,
+                                       max_iter=MAX_ITER, allocation=mem.MEM_ALLOC_NEYMAN,
+                                       candidates=[1024, 2048, 4096, 8192, 16384])
+        launch = {"source": "tuned now", "tuner_events_per_s": rate}
+        log(f"autotune: chunk {best}, {bw} waves per SIMD, {rate:.4g} events/s -> {TUNING_TABLE}")
     elif os.path.exists(TUNING_TABLE) and proc.load_tuning(TUNING_TABLE):
         launch = {"source": "table"}
     launch.update({"chunk_points": proc.chunk_points(), "waves_per_simd": proc.waves(),

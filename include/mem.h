@@ -272,10 +272,27 @@ typedef struct mem_flow_s* mem_flow;
  *                  no flow and no checkpoint (MEM_EUNSUPPORTED).  Device
  *                  memory on top of plain VEGAS: 8 bytes per point of an
  *                  iteration and 12 per hypercube.  Other values:
+ *                  MEM_EINVAL.
+ *  combine         how an integral's kept iterations (the second on; the
+ *                  first on with flow-seeded grids) form its estimate
+ *                  (VEGAS; a flow's own batches are pooled regardless).
+ *                  MEM_COMBINE_WEIGHTED (0, the default): inverse-variance
+ *                  weights, I = sum(I_j / s_j^2) / sum(1 / s_j^2), error^2
+ *                  = 1 / sum(1 / s_j^2) (Lepage 1978).  MEM_COMBINE_MEAN
+ *                  (1): equal weights, I = mean of the I_j, error^2 =
+ *                  sum s_j^2 / n^2.  Every I_j is unbiased given its grid,
+ *                  which earlier iterations fixed, so the mean is unbiased;
+ *                  the weighted form runs low where budgets are small
+ *                  against the integrand's peaks (an iteration that missed
+ *                  the large weights has a low I_j and a low s_j^2 and so
+ *                  the larger weight), at the price of a larger error when
+ *                  the grid is still improving.  The stopping test of
+ *                  target mode uses the chosen estimate.  Other values:
  *                  MEM_EINVAL.                                          */
 enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
 enum { MEM_FLOW_SAMPLE = 0, MEM_FLOW_SEED_GRID = 1 };
 enum { MEM_STRATIFY_OFF = 0, MEM_STRATIFY_ADAPTIVE = 1 };
+enum { MEM_COMBINE_WEIGHTED = 0, MEM_COMBINE_MEAN = 1 };
 
 /* Per-integral state of a VEGAS integration, owned by the library (see
  * mem_checkpoint_create). */
@@ -325,6 +342,7 @@ typedef struct {
   void* alloc_user;
   int32_t flow_mode;
   int32_t stratify;
+  int32_t combine;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */
@@ -466,24 +484,33 @@ mem_status mem_checkpoint_iterations(mem_checkpoint c, int32_t* n_iter);
  *    against register spills.  Compiled variants: Drell-Yan 1, 2, 4; t tbar
  *    H 2; the other kinds 1 and 2 (the first of each list is the
  *    default).  At one wave per SIMD the dilepton kernel compacts its root
- *    searches through LDS; at two it runs them per lane (same values).
+ *    searches through LDS; at two it runs them per lane (the same
+ *    arithmetic, contracted differently by the compiler).
  *    A launch that mixes kinds uses their default variant.
- * mem_autotune times a 2-iteration integration of the given events
- * (n_points per event per iteration) with every pair of a chunk candidate
- * (NULL: 1024, 2048, 4096, 8192, 16384; each a multiple of 256 <= 65536)
- * and a waves candidate (NULL: every compiled variant of the kind), keeps
- * the fastest integrand rate in the process (used by every later
- * mem_integrate_events call whose options do not set chunk_points) and
- * reports it in best_out, best_waves_out and rate_out (evaluations per
- * second of the integrand kernel; all optional).  table_path (optional):
- * a text table of lines "arch kind precision chunk_points waves_per_simd
- * evals_per_s", created or updated in place for this device and process.
- * Errors: MEM_EINVAL (null process, no events, bad candidates, a waves
- * candidate not compiled for the kind, unwritable table), the errors of
- * mem_integrate_events. */
-mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, const int32_t* candidates,
-                        int32_t n_cand, const int32_t* waves, int32_t n_waves, const char* table_path,
-                        int32_t* best_out, int32_t* best_waves_out, double* rate_out);
+ * mem_autotune times an integration of the given events (n_points per
+ * event per iteration) with every pair of a chunk candidate (NULL: 1024,
+ * 2048, 4096, 8192, 16384; each a multiple of 256 <= 65536) and a waves
+ * candidate (NULL: every compiled variant of the kind), the better of two
+ * runs (seeds base seed and base seed + 1), by the host clock around the
+ * call.  The timed call is mem_integrate_events with `base`'s options
+ * (target mode, allocation, stratification, stream, ...; its outputs go to
+ * host memory and its recording options, hooks and checkpoint are
+ * ignored) and n_iter iterations; base NULL: n_iter = 2 with the default
+ * options.  Tune with the options the process will run with: a target-mode
+ * run spends its late iterations on a few events, where smaller chunks
+ * balance better than a fixed-budget run shows.  The fastest pair is kept
+ * in the process (used by every later mem_integrate_events call whose
+ * options do not set chunk_points) and reported in best_out,
+ * best_waves_out and rate_out (events per second of the timed call; all
+ * optional).  table_path (optional): a text table of lines "arch kind
+ * precision chunk_points waves_per_simd events_per_s", created or updated
+ * in place for this device and process.  Errors: MEM_EINVAL (null
+ * process, no events, bad candidates, a waves candidate not compiled for
+ * the kind, unwritable table), the errors of mem_integrate_events. */
+mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, int32_t n_iter,
+                        const mem_integrate_opts* base, const int32_t* candidates, int32_t n_cand,
+                        const int32_t* waves, int32_t n_waves, const char* table_path, int32_t* best_out,
+                        int32_t* best_waves_out, double* rate_out);
 
 /* Look up the tuned launch configuration of a process in a table written
  * by mem_autotune, for architecture `arch` (e.g. "gfx950"; NULL: the

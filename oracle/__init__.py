@@ -162,6 +162,7 @@ def _declare(L):
         "or_gg_ttbar_ward": (D, [D, P, P, P, P]),
         "or_top_decay_spinsum": (D, [D, P, P, P, P]),
         "or_integrate_one": (None, [I, P, P, I, U64, U32, I64, I, D, P, P, P, P]),
+        "or_combine_iterations": (None, [P, P, I, I, I, P, P]),
         "or_strat_ns": (I, [I, I64]),
         "or_strat_allocate": (None, [I64, I64, P, I, P]),
         "or_strat_iteration": (None, [I, P, P, I, U64, U32, U32, I64, P, I, P, P, P, P, P, P]),
@@ -357,6 +358,15 @@ def integrate_one(kind, p, ev, perm, seed, event_index, n_points, n_iter,
 
 
 STRAT_HMAX = 16384
+
+
+def combine_iterations(Is, Vs, first_kept=1, mode=0):
+    """(I, sigma) of one integral from its iterations: mode 0 inverse-variance
+    weights (VEGAS), mode 1 equal weights"""
+    Is, Vs = _f64(Is), _f64(Vs)
+    I, sg = ctypes.c_double(), ctypes.c_double()
+    lib().or_combine_iterations(_ptr(Is), _ptr(Vs), len(Is), first_kept, mode, ctypes.byref(I), ctypes.byref(sg))
+    return I.value, sg.value
 
 
 def strat_ns(D, N):

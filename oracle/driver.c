@@ -197,6 +197,41 @@ int or_max_threads(void)
 #endif
 }
 
+/* ------------------------------------------- combining the iterations -- */
+/* The estimate of one integral from its iterations' I_j and sigma_j^2,
+ * iterations first_kept, first_kept + 1, ... (the first ones only adapt the
+ * grid).  mode 0, Lepage's weighting (Sec. 2's VEGAS): I = sum (I_j /
+ * sigma_j^2) / sum (1 / sigma_j^2), sigma^2 = 1 / sum (1 / sigma_j^2) over
+ * the iterations with sigma_j^2 > 0; with none, the plain mean of the kept
+ * I_j and sigma = 0.  mode 1, equal weights: I = mean of the kept I_j,
+ * sigma^2 = sum sigma_j^2 / n^2.  Each I_j is unbiased given its grid,
+ * which the earlier iterations fixed, so the mean is unbiased; the
+ * weighted form is not where a low I_j comes with a low sigma_j^2 (an
+ * iteration that missed the large weights). */
+void or_combine_iterations(const double* Is, const double* Vs, int n_iter, int first_kept, int mode, double* I,
+                           double* sigma)
+{
+  int n = 0;
+  double m = 0.0, vs = 0.0, wsum = 0.0, wIsum = 0.0;
+  for (int j = first_kept; j < n_iter; ++j) {
+    m += Is[j];
+    vs += Vs[j];
+    ++n;
+    if (Vs[j] > 0.0) { wsum += 1.0 / Vs[j]; wIsum += Is[j] / Vs[j]; }
+  }
+  if (n == 0) { *I = 0.0; *sigma = 0.0; return; }
+  if (mode == 1) {
+    *I = m / n;
+    *sigma = sqrt(vs) / n;
+  } else if (wsum > 0.0) {
+    *I = wIsum / wsum;
+    *sigma = sqrt(1.0 / wsum);
+  } else {
+    *I = m / n;
+    *sigma = 0.0;
+  }
+}
+
 /* ------------------------------------------ adaptive stratified VEGAS -- */
 /* VEGAS with adaptive stratified sampling (Lepage, "Adaptive
  * multidimensional integration: VEGAS enhanced", J. Comput. Phys. 439

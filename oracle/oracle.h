@@ -254,6 +254,10 @@ typedef struct {
  * iter_var (may be NULL) receive I_j, sigma_j^2 of every iteration.
  * grid_io (may be NULL): if non-NULL it is the starting grid and receives
  * the final grid. */
+/* Combined estimate from per-iteration I_j, sigma_j^2 (driver.c): mode 0
+ * inverse-variance weights, mode 1 equal weights. */
+void or_combine_iterations(const double* Is, const double* Vs, int n_iter, int first_kept, int mode, double* I,
+                           double* sigma);
 void or_integrate_one(int kind, const or_params* p, const double* ev, int perm,
                       uint64_t seed, uint32_t event_index, int64_t n_points,
                       int n_iter, double alpha, double* grid_io,

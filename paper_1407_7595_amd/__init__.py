@@ -72,7 +72,8 @@ class IntegrateOpts(ctypes.Structure):
                 ("weights_out", ctypes.c_void_p), ("weights_stride", ctypes.c_int64),
                 ("weights_integral", ctypes.c_int32), ("weights_rows", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
                 ("checkpoint", ctypes.c_void_p), ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
-                ("alloc_user", ctypes.c_void_p), ("flow_mode", ctypes.c_int32), ("stratify", ctypes.c_int32)]
+                ("alloc_user", ctypes.c_void_p), ("flow_mode", ctypes.c_int32), ("stratify", ctypes.c_int32),
+                ("combine", ctypes.c_int32)]
 
 
 MEM_HOOK_NONFINITE = 1
@@ -84,6 +85,10 @@ MEM_FLOW_SEED_GRID = 1
 # mem_integrate_opts.stratify
 MEM_STRATIFY_OFF = 0
 MEM_STRATIFY_ADAPTIVE = 1
+
+# mem_integrate_opts.combine
+MEM_COMBINE_WEIGHTED = 0
+MEM_COMBINE_MEAN = 1
 
 # bytes of the per-device scratch of mem_integrate_events_noalloc
 MEM_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
@@ -147,7 +152,7 @@ def lib():
             "mem_flow_sample": (I32, [P, P, P, P, I32, I64, U64, U32, P, P, P]),
             "mem_flow_log_prob": (I32, [P, P, P, P, I64, P, P]),
             "mem_flow_train_step": (I32, [P, P, P, P, P, I64, D, P, P, P]),
-            "mem_autotune": (I32, [P, P, I64, P, I32, P, I32, ctypes.c_char_p, P, P, P]),
+            "mem_autotune": (I32, [P, P, I64, I32, P, P, I32, P, I32, ctypes.c_char_p, P, P, P]),
             "mem_process_set_launch": (I32, [P, I32, I32]),
             "mem_process_waves": (I32, [P, P]),
             "mem_tuning_load": (I32, [P, ctypes.c_char_p, ctypes.c_char_p, P]),
@@ -218,16 +223,27 @@ class Process:
         b = (ctypes.c_double * 4)(*bounds)
         _check(lib().mem_set_pdf_grid(self.handle, a.ctypes.data, a.shape[1], a.shape[0], b), "mem_set_pdf_grid")
 
-    def autotune(self, comps, n_points, candidates=None, waves=None, table_path=None, charge=None):
+    def autotune(self, comps, n_points, candidates=None, waves=None, table_path=None, charge=None, n_iter=2,
+                 target_rel_err=None, max_iter=64, allocation=0, stratify=0, seed=0x5EED):
         """mem_autotune on the given events over chunk sizes x waves-per-SIMD
-        variants; returns (chunk_points, waves, evals/s)"""
+        variants, timing n_iter-iteration integrations (or, with
+        target_rel_err, target-mode integrations with these options);
+        returns (chunk_points, waves, events/s)"""
         ev = events_struct(comps, charge)
         cand = (ctypes.c_int32 * len(candidates))(*candidates) if candidates else None
         wv = (ctypes.c_int32 * len(waves))(*waves) if waves else None
+        base = None
+        if target_rel_err is not None or allocation or stratify or n_iter != 2:
+            base = IntegrateOpts()
+            base.seed, base.alpha, base.max_iter, base.use_graph = seed, 1.5, max_iter, 1
+            base.target_rel_err = target_rel_err or 0.0
+            base.allocation, base.stratify = allocation, stratify
         best, bw, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        _check(lib().mem_autotune(self.handle, ctypes.byref(ev), n_points, cand, len(candidates) if candidates else 0,
-                                  wv, len(waves) if waves else 0, table_path.encode() if table_path else None,
-                                  ctypes.byref(best), ctypes.byref(bw), ctypes.byref(rate)), "mem_autotune")
+        _check(lib().mem_autotune(self.handle, ctypes.byref(ev), n_points, n_iter,
+                                  ctypes.byref(base) if base is not None else None, cand,
+                                  len(candidates) if candidates else 0, wv, len(waves) if waves else 0,
+                                  table_path.encode() if table_path else None, ctypes.byref(best), ctypes.byref(bw),
+                                  ctypes.byref(rate)), "mem_autotune")
         return best.value, bw.value, rate.value
 
     def set_launch(self, chunk_points=0, waves=0):
@@ -296,7 +312,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
                      allocation=0, weights_out=None, weights_integral=0, hooks=0, hook_event=0,
-                     checkpoint=None, allocator=None, flow_mode=0, stratify=0, _noalloc=False):
+                     checkpoint=None, allocator=None, flow_mode=0, stratify=0, combine=0, _noalloc=False):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
@@ -307,7 +323,9 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
     the weights of integral weights_integral; hooks / hook_event: test
     hooks (MEM_HOOK_*); checkpoint: optional Checkpoint; allocator:
     None (hipMalloc), TORCH_ALLOCATOR, or a pair (ALLOC_FN, FREE_FN);
-    stratify: MEM_STRATIFY_ADAPTIVE for adaptive stratified sampling.
+    stratify: MEM_STRATIFY_ADAPTIVE for adaptive stratified sampling;
+    combine: MEM_COMBINE_WEIGHTED or MEM_COMBINE_MEAN (the iterations'
+    combination).
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
@@ -339,7 +357,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         checkpoint.handle.value if checkpoint is not None else None,
                         ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
                         ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None,
-                        flow_mode, stratify)
+                        flow_mode, stratify, combine)
     entry = "mem_integrate_events_noalloc" if _noalloc else "mem_integrate_events"
     _check(getattr(lib(), entry)(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                  ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),

@@ -138,7 +138,9 @@ __device__ __forceinline__ double strat_point(const StratChunk& sc, int64_t k, d
 }
 
 // per-integral running state
-enum { ST_WSUM = 0, ST_WISUM, ST_ISUM, ST_NITER, ST_NONFINITE, ST_LAST_I, ST_LAST_V, ST_SIZE = 8 };
+// (sums over the kept iterations: 1/sigma_j^2, I_j/sigma_j^2, I_j, their
+// count, sigma_j^2; a non-finite flag; the last iteration's I_j, sigma_j^2)
+enum { ST_WSUM = 0, ST_WISUM, ST_ISUM, ST_NITER, ST_NONFINITE, ST_LAST_I, ST_LAST_V, ST_VSUM, ST_SIZE = 8 };
 
 template <int D>
 __device__ __forceinline__ void block_reduce2(double& a, double& b, double* red)

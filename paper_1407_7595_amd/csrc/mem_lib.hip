@@ -489,6 +489,7 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
       if (var > 0.0) { st[ST_WSUM] += 1.0 / var; st[ST_WISUM] += I / var; }
       st[ST_ISUM] += I;
       st[ST_NITER] += 1.0;
+      st[ST_VSUM] += var;
     }
     st[ST_LAST_I] = I;
     st[ST_LAST_V] = var;
@@ -507,10 +508,15 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
   }
 }
 
-// Combined estimate of one integral from its running state.
-__device__ __forceinline__ void integral_estimate(const double* st, double& I, double& var)
+// Combined estimate of one integral from its running state: inverse-
+// variance weights (MEM_COMBINE_WEIGHTED), or equal weights
+// (MEM_COMBINE_MEAN: mean of the kept I_j, variance sum sigma_j^2 / n^2).
+__device__ __forceinline__ void integral_estimate(const double* st, int combine, double& I, double& var)
 {
-  if (st[ST_WSUM] > 0.0) {
+  if (combine == MEM_COMBINE_MEAN && st[ST_NITER] > 0.0) {
+    I = st[ST_ISUM] / st[ST_NITER];
+    var = st[ST_VSUM] / (st[ST_NITER] * st[ST_NITER]);
+  } else if (st[ST_WSUM] > 0.0) {
     I = st[ST_WISUM] / st[ST_WSUM];
     var = 1.0 / st[ST_WSUM];
   } else {
@@ -526,7 +532,7 @@ __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t*
                              const double* __restrict__ ev_norm, const double* __restrict__ state,
                              int32_t* __restrict__ active, int n_events, double target, Control* ctl,
                              int final_pass, double* P, double* err, int32_t* status, int32_t* n_iter_used,
-                             int32_t* ev_done, uint32_t first_kept)
+                             int32_t* ev_done, uint32_t first_kept, int combine)
 {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_events) return;
@@ -538,7 +544,7 @@ __global__ void event_kernel(const int64_t* __restrict__ ev_int0, const int32_t*
   for (int k = 0; k < np; ++k) {
     double I, var;
     const double* st = state + (i0 + k) * ST_SIZE;
-    integral_estimate(st, I, var);
+    integral_estimate(st, combine, I, var);
     s += I;
     v += var;
     if (st[ST_NONFINITE] != 0.0 || !isfinite(I)) bad = true;
@@ -1226,6 +1232,7 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
   if (o.allocation != MEM_ALLOC_EQUAL && o.allocation != MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "unknown allocation");
   if (o.flow_mode != MEM_FLOW_SAMPLE && o.flow_mode != MEM_FLOW_SEED_GRID) return fail(MEM_EINVAL, "unknown flow_mode");
   if (o.stratify != MEM_STRATIFY_OFF && o.stratify != MEM_STRATIFY_ADAPTIVE) return fail(MEM_EINVAL, "unknown stratify");
+  if (o.combine != MEM_COMBINE_WEIGHTED && o.combine != MEM_COMBINE_MEAN) return fail(MEM_EINVAL, "unknown combine");
   if (o.stratify) {
     if (o.allocation == MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "stratified sampling takes the equal split across permutations");
     if (o.flow) return fail(MEM_EUNSUPPORTED, "stratified sampling is VEGAS-only");
@@ -1699,7 +1706,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                          b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
                          o.target_rel_err, ctl, 0, nullptr, nullptr, nullptr, nullptr, b_done.as<int32_t>(),
-                         first_kept);
+                         first_kept, o.combine);
     if (neyman)
       hipLaunchKernelGGL(neyman_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                          b_ints.as<IntegralDesc>(), b_state.as<double>(), b_active.as<int32_t>(),
@@ -1809,7 +1816,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   hipLaunchKernelGGL(event_kernel, dim3(ev_blocks), dim3(256), 0, ws, b_evi0.as<int64_t>(), b_evnp.as<int32_t>(),
                      b_evnorm.as<double>(), b_state.as<double>(), b_active.as<int32_t>(), n_ev,
                      target_mode ? o.target_rel_err : 0.0, ctl, 1, P, E, S, o.n_iter_out, b_done.as<int32_t>(),
-                     first_kept);
+                     first_kept, o.combine);
   HIP_TRY(hipGetLastError());
   if (o.grid_out)
     HIP_TRY(hipMemcpyAsync(o.grid_out, b_grids.p, grid_total * sizeof(double), hipMemcpyDeviceToDevice, ws));
@@ -2070,9 +2077,10 @@ std::string tuning_key(const std::string& arch, const mem_process_s* p)
 bool valid_chunk(int64_t c) { return c > 0 && c % kBlock == 0 && c <= 65536; }
 }  // namespace
 
-extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, const int32_t* candidates,
-                                   int32_t n_cand, const int32_t* waves, int32_t n_waves, const char* table_path,
-                                   int32_t* best_out, int32_t* best_waves_out, double* rate_out)
+extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t n_points, int32_t n_iter,
+                                   const mem_integrate_opts* base, const int32_t* candidates, int32_t n_cand,
+                                   const int32_t* waves, int32_t n_waves, const char* table_path, int32_t* best_out,
+                                   int32_t* best_waves_out, double* rate_out)
 {
   if (!p) return fail(MEM_EINVAL, "null process");
   mem_status st = check_event_arrays(ev);
@@ -2088,6 +2096,24 @@ extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t 
   if (n_waves < 1) return fail(MEM_EINVAL, "no waves candidates");
   for (int i = 0; i < n_waves; ++i)
     if (!waves_supported(p->desc.kind, waves[i])) return fail(MEM_EINVAL, "a waves candidate not compiled for this kind");
+  // the timed call: the caller's options (outputs to the host, no
+  // recording, no checkpoint, chunk size from the candidate), else a
+  // 2-iteration integration with the defaults
+  mem_integrate_opts base_opts{};
+  base_opts.seed = 0x5EEDu;
+  base_opts.alpha = 1.5;
+  base_opts.max_iter = 64;
+  base_opts.use_graph = 1;
+  if (base) base_opts = *base;
+  else n_iter = 2;
+  base_opts.outputs_on_device = 0;
+  base_opts.iter_out = nullptr;
+  base_opts.grid_out = nullptr;
+  base_opts.n_iter_out = nullptr;
+  base_opts.timing_out = nullptr;
+  base_opts.weights_out = nullptr;
+  base_opts.hooks = 0;
+  base_opts.checkpoint = nullptr;
   const int n_ev = ev->n_events;
   std::vector<double> P(n_ev), E(n_ev);
   std::vector<int32_t> S(n_ev);
@@ -2099,17 +2125,14 @@ extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t 
     for (int i = 0; i < n_cand; ++i) {
       double rate = 0.0;
       for (int rep = 0; rep < 2; ++rep) {   // the better of two runs
-        double tm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        mem_integrate_opts o{};
-        o.seed = 0x5EEDu + (uint64_t)rep;
-        o.alpha = 1.5;
-        o.max_iter = 2;
+        mem_integrate_opts o = base_opts;
+        o.seed = base_opts.seed + (uint64_t)rep;
         o.chunk_points = candidates[i];
-        o.use_graph = 0;
-        o.timing_out = tm;
-        st = mem_integrate_events(ev, &p, 1, &n_points, 1, 2, &o, P.data(), E.data(), S.data());
+        const auto t0 = std::chrono::steady_clock::now();
+        st = mem_integrate_events(ev, &p, 1, &n_points, 1, n_iter, &o, P.data(), E.data(), S.data());
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (st != MEM_OK) { p->chunk_points = keep_chunk; p->waves = keep_waves; return st; }
-        if (tm[0] > 0.0) rate = std::max(rate, tm[2] / (tm[0] * 1e-3));
+        if (sec > 0.0) rate = std::max(rate, (double)n_ev / sec);
       }
       if (rate > best_rate) { best_rate = rate; best = candidates[i]; best_w = waves[iw]; }
     }
@@ -2139,7 +2162,7 @@ extern "C" mem_status mem_autotune(mem_process p, const mem_events* ev, int64_t 
     lines.push_back(row);
     FILE* fo = std::fopen(table_path, "w");
     if (!fo) return fail(MEM_EINVAL, std::string("cannot write ") + table_path);
-    std::fputs("# arch kind precision chunk_points waves_per_simd evals_per_s\n", fo);
+    std::fputs("# arch kind precision chunk_points waves_per_simd events_per_s\n", fo);
     for (const auto& ln : lines)
       if (ln[0] != '#') { std::fputs(ln.c_str(), fo); std::fputc('\n', fo); }
     std::fclose(fo);

@@ -490,3 +490,29 @@ def test_mixed_batch_queue_and_graph(mem):
         # iterations' points slightly: a fraction of the MC error
         bar = 1e-3 if k == "dy" else 0.5
         assert abs(P1[i] - Po) <= bar * Eo + 1e-9 * abs(Po)
+
+
+def test_combine_mean_matches_oracle(mem):
+    """MEM_COMBINE_MEAN: the equal-weight combination of the kept
+    iterations, per event against the oracle's combination of its own
+    iterations on the same point stream (FP64 Drell-Yan, 4 events x 4096 x
+    6); P = I / sigma_norm, the constant taken from the default weighted
+    combination against the oracle's"""
+    n_ev, N, iters, seed = 4, 4096, 6, 41
+    d = events.drell_yan(n_ev, 0x61)
+    comps = mem.to_components(d["obs"]).cuda()
+    dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    Pw, Ew, _ = (t.cpu().numpy() for t in mem.integrate_events(comps, dy, N, iters, seed=seed))
+    Pm, Em, Sm = (t.cpu().numpy() for t in mem.integrate_events(comps, dy, N, iters, seed=seed,
+                                                                combine=mem.MEM_COMBINE_MEAN))
+    assert np.all(Sm == 0)
+    for e in range(n_ev):
+        r, Is, Vs, _ = oracle.integrate_one(oracle.KIND_DY, oracle.dy_params(), d["obs"][e], 0, seed, e, N, iters)
+        norm = Pw[e] / r.I
+        Im, sm = oracle.combine_iterations(Is, Vs, 1, 1)
+        say(f"event {e}: mean-combined P rel {abs(Pm[e] - norm * Im) / (norm * Im):.3g}, "
+            f"err rel {abs(Em[e] - norm * sm) / (norm * sm):.3g}")
+        assert Pm[e] == pytest.approx(norm * Im, rel=1e-9)
+        assert Em[e] == pytest.approx(norm * sm, rel=1e-6)
+    with pytest.raises(mem.MemError):
+        mem.integrate_events(comps, dy, N, iters, combine=2)

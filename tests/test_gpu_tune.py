@@ -48,7 +48,7 @@ def test_autotune_table_and_use(mem, tmp_path):
     table = tmp_path / "tune.txt"
     say("autotune 24 tt events x 16384, chunks 1024, 4096 x waves 1, 2")
     best, bw, rate = p.autotune(comps, 16384, candidates=[1024, 4096], waves=[1, 2], table_path=str(table))
-    say(f"best chunk {best}, {bw} waves per SIMD, {rate:.3g} evals/s")
+    say(f"best chunk {best}, {bw} waves per SIMD, {rate:.3g} events/s")
     assert best in (1024, 4096) and bw in (1, 2) and rate > 0
     assert p.chunk_points() == best and p.waves() == bw
     rows = [ln.split() for ln in table.read_text().splitlines() if not ln.startswith("#")]
@@ -135,6 +135,19 @@ def test_tuned_launch_matches_oracle(mem, tmp_path):
         r = np.where(both_zero, 0.0, np.abs(got - want) / np.maximum(np.abs(want), 1e-300))
         say(f"waves {wv}: {int((~both_zero).sum())} nonzero of {N}, worst rel {r.max():.3g}")
         assert r.max() < 1e-5
+
+
+def test_autotune_target_mode(mem):
+    """tuning on a target-mode call (the options the process will run
+    with): a valid pair, the rate in events per second of that call"""
+    d = events.ttbar_dilepton(64, 67)
+    comps = mem.to_components(d["obs"]).cuda()
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    best, bw, rate = p.autotune(comps, 16384, candidates=[1024, 4096], waves=[1, 2], target_rel_err=0.02,
+                                max_iter=16, allocation=mem.MEM_ALLOC_NEYMAN)
+    say(f"target mode: chunk {best}, waves {bw}, {rate:.4g} events/s")
+    assert best in (1024, 4096) and bw in (1, 2) and 0 < rate < 1e9
+    assert p.chunk_points() == best and p.waves() == bw
 
 
 def test_tuning_refusals(mem, tmp_path):
