@@ -42,11 +42,12 @@ FLOP_PER_EVAL = 2.0 * 1242.4 + 702.6
 # HBM bytes per fixed-budget launch of the integrand kernel (4096 events x
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # script's fixed-budget pass, each scaled by what the counter reads for plain
-# kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md).
-# Valid only for this workload and the kernel build the counters were taken
-# on: None until they are taken on the current build.
-TRAFFIC_BYTES_PER_LAUNCH = None
-TRAFFIC_WORKLOAD = (4096, 65536)
+# kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
+# FETCH 95 640 KiB x 2.000 + WRITE 266 096 KiB x 1.000.  Valid only for this
+# workload and the kernel build the counters were taken on (set to None when
+# the kernel changes, until they are taken again).
+TRAFFIC_BYTES_PER_LAUNCH = (95640 * 2.000 + 266096 * 1.000) * 1024
+TRAFFIC_WORKLOAD = (4096, 65536, 4096, 1)     # events, points, chunk points, waves per SIMD
 
 # tuned launch configurations (mem_autotune's table) shipped with the package
 TUNING_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1407_7595_amd", "tuning.txt")
@@ -521,7 +522,8 @@ def main():
     if FLOP_PER_EVAL is not None and launches > 0:
         per_launch = FLOP_PER_EVAL * n_evals / launches
         achieved = per_launch / (kern_ms / launches * 1e-3)
-        traffic = TRAFFIC_BYTES_PER_LAUNCH if (n_ev, PTS) == TRAFFIC_WORKLOAD else None
+        traffic = (TRAFFIC_BYTES_PER_LAUNCH
+                   if (n_ev, PTS, proc.chunk_points(), proc.waves()) == TRAFFIC_WORKLOAD else None)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": traffic}
     parton = parton_leg(mem, proc)
