@@ -542,6 +542,10 @@ __device__ __forceinline__ void spline_backward(const float* th, float x, float 
 // LDS of the backward kernel (phases reuse one region)
 constexpr int FHP = FH + 1;   // padded row of the first-layer gradient (bank spread)
 constexpr int FW1S = FIN + 1; // first-layer gradient terms per unit: W1 row and b1
+// row of the transposed activations h1T, h2T [unit][sample]: padded by 8 so
+// that the transposing writes (consecutive units, one sample) spread over
+// the banks while rows stay 16-byte aligned for the matrix-core loads
+constexpr int FPT = FP + 8;
 struct __align__(16) FlowBwdSmem {
   float gv[FP][8];          // dL/d(layer output vector)
   float gl[FP];             // dL/d(log q) per sample (= -weight)
@@ -549,11 +553,34 @@ struct __align__(16) FlowBwdSmem {
   float ctx[FP][FCTX];      // the samples' contexts
   float gb2[FT / kWave][FH];  // per-wave partial sums of the second-layer bias gradient
   union {
-    struct { uint16_t g[FP * FOUTP]; uint16_t gT[FOUTP * FP]; uint16_t h2T[FH * FP]; } a;   // 80 KB
-    struct { uint16_t g[FP * FH]; uint16_t gT[FH * FP]; uint16_t h1T[FH * FP]; } b;         // 96 KB
+    struct { uint16_t g[FP * FOUTP]; uint16_t gT[FOUTP * FP]; uint16_t h2T[FH * FPT]; } a;  // 82 KB
+    struct { uint16_t g[FP * FH]; uint16_t gT[FH * FP]; uint16_t h1T[FH * FPT]; } b;        // 98 KB
     struct { float ga1[FP * FHP]; float w1[FH * FW1S]; } c;                               // 81 KB
   } u;
 };
+
+// hT[k][p] = bf16(silu(a[p][k])) for the tile's FP samples and FH units,
+// a[p][k] = src[p * stride + k] in the tape.  Consecutive threads read one
+// sample's consecutive units (coalesced); each thread first issues eight
+// independent loads, then converts and stores them, so that one wave
+// waits for the memory once per eight values.
+__device__ __forceinline__ void transpose_act(const float* __restrict__ src, int64_t stride, uint16_t* hT)
+{
+  static_assert((FH * FP) % (8 * FT) == 0, "whole rounds of eight loads per thread");
+  for (int q0 = threadIdx.x; q0 < FH * FP; q0 += 8 * FT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * FT, p = q / FH, k = q % FH;
+      v[u] = src[p * stride + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * FT, p = q / FH, k = q % FH;
+      hT[k * FPT + p] = f2bf(silu(v[u]));
+    }
+  }
+}
 
 // The gradient slot of a workgroup is written by exactly one thread per
 // entry, in the same order on every run: plain stores on the workgroup's
@@ -635,11 +662,9 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) S.gv[p][A[j0 + jj]] = gin[jj];
     }
-    // h2 transposed (bf16) from the tape
-    for (int q = t; q < FH * FP; q += FT) {
-      const int k = q / FP, p = q % FP;
-      S.u.a.h2T[q] = f2bf(silu(tp[p * stride + 8 + FH + k]));
-    }
+    // h2 transposed (bf16) from the tape: consecutive threads read one
+    // sample's consecutive units (coalesced) and write a column of h2T
+    transpose_act(tp + 8 + FH, stride, S.u.a.h2T);
     __syncthreads();
     // gb3[n] = sum_p g[p][n] (rows of the transposed copy)
     if (t < FOUT) {
@@ -652,7 +677,7 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
       const int tm = tile3 / 4, tn = tile3 % 4;
       f32x16 acc;
       zero16(acc);
-      mfma_tile(S.u.a.gT, FP, S.u.a.h2T, FP, 32 * tm, 32 * tn, FP, acc);
+      mfma_tile(S.u.a.gT, FP, S.u.a.h2T, FPT, 32 * tm, 32 * tn, FP, acc);
       store_tile(G + F_W3, FH, 32 * tm, 32 * tn, FOUT, FH, acc, first);
     }
     // ---- gh2[p][k] = sum_n g[p][n] W3[n][k]; ga2 = gh2 silu'(a2)
@@ -676,10 +701,7 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
       sb += __shfl_xor(sb, 32, kWave);
       if ((t & 63) < 32) S.gb2[wv][32 * tn + mfma_col()] = sb;
     }
-    for (int q = t; q < FH * FP; q += FT) {
-      const int k = q / FP, p = q % FP;
-      S.u.b.h1T[q] = f2bf(silu(tp[p * stride + 8 + k]));
-    }
+    transpose_act(tp + 8, stride, S.u.b.h1T);
     __syncthreads();
     // gb2: the four waves' sums in wave order
     if (t < FH) slot_add(&G[F_B2 + t], ((S.gb2[0][t] + S.gb2[1][t]) + S.gb2[2][t]) + S.gb2[3][t], first);
@@ -688,7 +710,7 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
       const int tm = tile2 / 4, tn = tile2 % 4;
       f32x16 acc;
       zero16(acc);
-      mfma_tile(S.u.b.gT, FP, S.u.b.h1T, FP, 32 * tm, 32 * tn, FP, acc);
+      mfma_tile(S.u.b.gT, FP, S.u.b.h1T, FPT, 32 * tm, 32 * tn, FP, acc);
       store_tile(G + F_W2, FH, 32 * tm, 32 * tn, FH, FH, acc, first);
     }
     // ---- gh1[p][k] = sum_o ga2[p][o] W2[o][k]
@@ -739,6 +761,7 @@ __global__ __launch_bounds__(FT) void flow_train_bwd_kernel(const float* __restr
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float s = 0.0f;
+#pragma unroll 8
         for (int o = 0; o < FH; ++o) s += S.u.c.ga1[t * FHP + o] * L[F_W1 + o * FIN + j];
         S.gv[t][B[j]] += s;
       }
