@@ -537,7 +537,11 @@ def main():
     if not args.no_flow:
         flow = flow_leg(mem, proc, comps, n_ev, args)
         if value:
+            # both uses of the trained proposal against the VEGAS headline
+            # (same events, same 1 % target): sampling from it with the
+            # VEGAS fallback, and seeding VEGAS's grids from it
             flow["vs_vegas"] = flow["events_per_s"] / value
+            flow["flow_seeded_grids"]["vs_vegas"] = flow["flow_seeded_grids"]["events_per_s"] / value
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle)")
