@@ -192,14 +192,20 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-class Process:
-    """A hypothesis (mem_create_process); released with the object."""
-
-    def __init__(self, kind, precision=MEM_FP32, sqrt_s=13000.0, m_top=172.5, w_top=1.4, m_w=80.4, w_w=2.1,
+def process_desc(kind, precision=MEM_FP32, sqrt_s=13000.0, m_top=172.5, w_top=1.4, m_w=80.4, w_w=2.1,
                  m_h=125.0, w_h=0.00407, alpha=1.0 / 137.0, alpha_s=0.118, g_fermi=1.1663787e-5,
                  sigma_k=20.0, m_lo=60.0, m_hi=120.0, sigma_norm=0.0, m_b=4.18):
-        d = ProcessDesc(kind, precision, sqrt_s, m_top, w_top, m_w, w_w, m_h, w_h, alpha, alpha_s, g_fermi,
-                        sigma_k, m_lo, m_hi, sigma_norm, m_b)
+    """mem_process_desc with the configurations' parameters as defaults"""
+    return ProcessDesc(kind, precision, sqrt_s, m_top, w_top, m_w, w_w, m_h, w_h, alpha, alpha_s, g_fermi,
+                       sigma_k, m_lo, m_hi, sigma_norm, m_b)
+
+
+class Process:
+    """A hypothesis (mem_create_process); released with the object.
+    Keyword arguments as process_desc."""
+
+    def __init__(self, kind, precision=MEM_FP32, **kw):
+        d = process_desc(kind, precision, **kw)
         h = ctypes.c_void_p()
         _check(lib().mem_create_process(ctypes.byref(d), ctypes.byref(h)), "mem_create_process")
         self.handle = h

@@ -5,7 +5,7 @@
 // Philox4x32-10 point stream (Salmon et al., SC'11) mapped through a VEGAS
 // grid (Lepage 1978).  Points are generated in registers, never stored.
 #pragma once
-#ifndef MEM_HOST_COUNT
+#if !defined(MEM_HOST_COUNT) && !defined(MEM_HOST_EMU)
 #include <hip/hip_runtime.h>
 #endif
 #include <stdint.h>

@@ -181,3 +181,51 @@ def test_strat_refused(mem):
         mem.integrate_events(comps, tt, 4096, 2, stratify=1, flow=mem.Flow())
     with pytest.raises(mem.MemError):
         mem.integrate_events(comps, tt, 4096, 2, stratify=1, checkpoint=mem.Checkpoint())
+
+
+def test_strat_mixed_batch_and_noalloc(mem):
+    """one call with Drell-Yan (2D, FP64) and dilepton (8D, FP64) events and
+    uneven budgets, so integrals of different dimensions and hypercube
+    counts share the work queue: every integral's I_j and sigma_j^2 against
+    the oracle's stratified driver (event index = position in the batch);
+    the no-allocation entry point gives the same outputs bit for bit"""
+    dy = mem.Process(mem.MEM_DY_QQ_GAMMA_MUMU, precision=mem.MEM_FP64)
+    tt = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP64)
+    dd = events.drell_yan(2, 0x56)["obs"]
+    dt = events.ttbar_dilepton(2, 0x57)["obs"]
+    kinds = ["dy", "tt", "dy", "tt"]
+    src = {"dy": iter(dd), "tt": iter(dt)}
+    full, obs = [], np.zeros((len(kinds), 4, 4))
+    for i, k in enumerate(kinds):
+        o = next(src[k])
+        full.append(o)
+        n = 2 if k == "dy" else 4
+        obs[i, :n] = o[:n]
+    budgets = [4096, 8192 + 1400, 2500, 8192]
+    procs = [dy if k == "dy" else tt for k in kinds]
+    comps = mem.to_components(obs).cuda()
+    iters, seed = 4, 29
+    n_int = 1 + 2 + 1 + 2
+    rec = torch.zeros((iters, n_int, 2), dtype=torch.float64, device="cuda")
+    out = mem.integrate_events(comps, procs, budgets, iters, seed=seed, iter_out=rec,
+                               stratify=mem.MEM_STRATIFY_ADAPTIVE)
+    rec = rec.cpu().numpy()
+    out = [t.cpu().numpy() for t in out]
+    assert np.all(out[2] == 0)
+    ig = 0
+    for i, k in enumerate(kinds):
+        kind, po, npm = (oracle.KIND_DY, oracle.dy_params(), 1) if k == "dy" else (oracle.KIND_TT, oracle.tt_params(), 2)
+        N = -(-budgets[i] // npm)
+        for perm in range(npm):
+            _, Is, Vs = oracle.integrate_one_strat(kind, po, full[i], perm, seed, i, N, iters)
+            ri, rv = rel(rec[:, ig, 0], Is).max(), rel(rec[:, ig, 1], Vs).max()
+            say(f"mixed event {i} ({k}) perm {perm}, N={N}: I_j rel {ri:.3g}, var_j rel {rv:.3g}")
+            bar_i, bar_v = (1e-9, 1e-6) if k == "dy" else (1e-6, 1e-4)
+            assert ri < bar_i and rv < bar_v
+            ig += 1
+    outs = (torch.empty(4, dtype=torch.float64, device="cuda"), torch.empty(4, dtype=torch.float64, device="cuda"),
+            torch.empty(4, dtype=torch.int32, device="cuda"))
+    na = mem.integrate_events_noalloc(comps, procs, budgets, iters, outputs=outs, seed=seed,
+                                      stratify=mem.MEM_STRATIFY_ADAPTIVE)
+    for a, b in zip(out, na):
+        assert np.array_equal(a, b.cpu().numpy())
