@@ -5,8 +5,11 @@
 // chunk partials summed in chunk order), for comparison with the oracle's
 // iteration on the same point stream.
 //
-//   host_queue DESC_FILE EVENTS_FILE VARIANT N_POINTS SEED CHUNK BLOCKS
+//   host_queue DESC_FILE EVENTS_FILE VARIANT N_POINTS SEED CHUNK BLOCKS [NS]
 //
+// With NS (hypercubes per dimension), the iteration is stratified with the
+// first iteration's equal split of N_POINTS over NS^D hypercubes, and each
+// integral's line carries its N_POINTS point weights after the bin sums.
 // DESC_FILE: a mem_process_desc as bytes.  EVENTS_FILE: int32 n_events,
 // int32 n_obj, then E, px, py, pz planes [n_obj][n_events] of doubles,
 // optionally followed by one int32 lepton charge per event.  VARIANT: tt1f,
@@ -57,10 +60,11 @@ static std::vector<char> slurp(const char* path)
 
 int main(int argc, char** argv)
 {
-  if (argc != 8) {
-    std::fprintf(stderr, "usage: host_queue DESC EVENTS VARIANT N_POINTS SEED CHUNK BLOCKS\n");
+  if (argc != 8 && argc != 9) {
+    std::fprintf(stderr, "usage: host_queue DESC EVENTS VARIANT N_POINTS SEED CHUNK BLOCKS [NS]\n");
     return 2;
   }
+  const int ns = argc == 9 ? std::atoi(argv[8]) : 0;
   const std::vector<char> db = slurp(argv[1]), eb = slurp(argv[2]);
   Kernel kern = pick(argv[3]);
   const int64_t N = std::atoll(argv[4]);
@@ -123,7 +127,34 @@ int main(int argc, char** argv)
   Control ctl{0u, 0u, 0, 0u};
   uint32_t head = 0;
   const QueueHooks hk{nullptr, 0, -1, -1};
-  const StratView sv{nullptr, nullptr, nullptr, nullptr};
+  // stratification: every integral's equal split and each chunk's first
+  // hypercube, as the library's first iteration sets them
+  std::vector<StratDesc> sd;
+  std::vector<int32_t> cum, h0(chunks.size(), 0);
+  std::vector<double> wpt;
+  if (ns > 0) {
+    int64_t H = 1;
+    for (int dd = 0; dd < D; ++dd) H *= ns;
+    if (2 * H > N || H > kStratHMax || chunk > kStratChunkMax) {
+      std::fprintf(stderr, "bad stratification\n");
+      return 2;
+    }
+    const int64_t q = N / H, r = N % H;
+    for (size_t ig = 0; ig < ints.size(); ++ig) {
+      sd.push_back(StratDesc{ns, (int32_t)H, (int64_t)cum.size(), (int64_t)(ig * N)});
+      const int64_t base = (int64_t)cum.size();
+      for (int64_t h = 0; h <= H; ++h) cum.push_back((int32_t)(h * q + (h < r ? h : r)));
+      for (int c = 0; c < ints[ig].n_chunks; ++c) {
+        const int64_t start = chunks[ints[ig].chunk0 + c].start;
+        int64_t h = 0;
+        while (h + 1 < H && cum[base + h + 1] <= start) ++h;
+        h0[ints[ig].chunk0 + c] = (int32_t)h;
+      }
+    }
+    wpt.assign(ints.size() * N, 0.0);
+  }
+  const StratView sv = ns > 0 ? StratView{sd.data(), cum.data(), h0.data(), wpt.data()}
+                              : StratView{nullptr, nullptr, nullptr, nullptr};
   emu::launch(blocks, [&] {
     kern(&pp, ev, chunks.data(), (int64_t)chunks.size(), ints.data(), grids.data(), active.data(), seed, &ctl, &head,
          parts.data(), nullptr, hk, sv);
@@ -139,6 +170,10 @@ int main(int argc, char** argv)
     }
     std::printf("%d %d %.17g %.17g", in.event, in.perm, s1, s2);
     for (double b : bins) std::printf(" %.17g", b);
+    if (ns > 0) {
+      const double* w = wpt.data() + (size_t)(&in - ints.data()) * N;
+      for (int64_t k = 0; k < N; ++k) std::printf(" %.17g", w[k]);
+    }
     std::printf("\n");
   }
   return 0;

@@ -54,10 +54,10 @@ def write_inputs(tmp, desc, obs, charge=None):
     return dpath, epath
 
 
-def run(exe, dpath, epath, variant, n, seed, chunk, blocks):
+def run(exe, dpath, epath, variant, n, seed, chunk, blocks, ns=0):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", TSAN_OPTIONS="halt_on_error=1")
-    out = subprocess.run([exe, dpath, epath, variant, str(n), str(seed), str(chunk), str(blocks)],
-                         capture_output=True, text=True, env=env, timeout=900)
+    args = [exe, dpath, epath, variant, str(n), str(seed), str(chunk), str(blocks)] + ([str(ns)] if ns else [])
+    out = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
     assert out.returncode == 0, out.stderr[-4000:]
     rows = [list(map(float, ln.split())) for ln in out.stdout.splitlines() if ln.strip()]
     return [(int(r[0]), int(r[1]), r[2], r[3], np.array(r[4:])) for r in rows]
@@ -119,6 +119,39 @@ def test_queue_kernel_host_asan_ubsan_semileptonic_and_tth(tmp_path):
     rows = run(exe, dpath, epath, "tth2f", 512, 13, 256, 2)
     assert len(rows) == 24
     compare(rows, oracle.KIND_TTH, oracle.tt_params(), th, 512, 13, 9, 1e-5)
+
+
+def test_queue_kernel_host_stratified(tmp_path):
+    """the stratified point mapping (hypercube search in the chunk's staged
+    counts, digits, shifted uniforms, weights stored per point) in the
+    first iteration's equal split, under AddressSanitizer and
+    UndefinedBehaviorSanitizer: every point's weight against the oracle's
+    stratified iteration (FP64 dilepton, 1e-9; Drell-Yan 1e-11), with a
+    ragged chunk and unequal hypercube counts"""
+    tmp = str(tmp_path)
+    exe = build(tmp, "address,undefined")
+    for kind, ok, po, D, obs, prec, n, ns, tol in (
+            ("tt1d", oracle.KIND_TT, oracle.tt_params(), 8, events.ttbar_dilepton(2, 0x86)["obs"], mem.MEM_FP64,
+             1100, 2, 1e-9),
+            ("dy", oracle.KIND_DY, oracle.dy_params(), 2, events.drell_yan(2, 0x87)["obs"], mem.MEM_FP64, 1000, 20,
+             1e-11)):
+        pk = mem.MEM_TT_DILEPTON if kind.startswith("tt") else mem.MEM_DY_QQ_GAMMA_MUMU
+        dpath, epath = write_inputs(tmp, mem.process_desc(pk, prec), obs)
+        rows = run(exe, dpath, epath, kind, n, 0x77, 512, 2, ns)
+        H = ns ** D
+        nh = oracle.strat_allocate(H, n, first=True)
+        n_nz = 0
+        for e, perm, s1, s2, rest in rows:
+            w = rest[D * 64:]
+            assert len(w) == n
+            _, _, _, _, want = oracle.strat_iteration(ok, po, obs[e], perm, 0x77, e, 0, n, oracle.uniform_grid(D),
+                                                      ns, nh)
+            both_zero = (w == 0) & (want == 0)
+            r = np.where(both_zero, 0.0, np.abs(w - want) / np.maximum(np.abs(want), 1e-300))
+            assert r.max() <= tol, (kind, e, perm, r.max())
+            assert abs(s1 - w.sum()) <= 1e-12 * max(abs(s1), 1e-300)
+            n_nz += int(np.sum(~both_zero))
+        assert n_nz > 0
 
 
 def test_queue_kernel_host_tsan(tmp_path):
