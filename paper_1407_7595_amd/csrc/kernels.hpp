@@ -187,7 +187,7 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
 }
 
 // Dilepton chunk with the root searches and the per-root work of each
-// wavefront compacted.  Every lane maps its point, forms the resultant
+// wavefront compacted.  Every lane maps a point, forms the resultant
 // quartic and isolates its real roots (0 to 4 sign-change intervals between
 // critical points); the lane's solve state and monic quartic go to an LDS
 // record and its intervals to an LDS queue (exclusive prefix sum of the
@@ -198,13 +198,30 @@ __device__ __forceinline__ void chunk_points(const Chunk& ch, uint64_t seed, uin
 // root, it rebuilds the owner's geometry from the record, polishes and
 // tests the root (dilep_accept) and evaluates the matrix element stage
 // (tt_solution); each point sums its own entries in root order.  Both
-// stages run ceil(total / 64) times per wavefront instead of max(roots)
-// times.  Same functions, same inputs and the same order as tt_integrand (a
-// rejected root adds +0); the compiler contracts the two instances'
+// stages run in rounds of 64 entries instead of max(roots) times.
+//
+// Rounds on few lanes are put off: after the whole rounds of a batch, a
+// remainder of at most kTTDefer entries stays at the front of the queue
+// for the next batch.  The lanes that own those entries keep their point
+// (record, Jacobian, bins, partial sum) and take no new point in that
+// batch; the other lanes take the wavefront's next points (its 64-point
+// segment of every 256-point block, the same points as a fixed lane per
+// point, handed out in order).  Once the wavefront's points are handed out
+// the queue is drained.  Each root still runs the same functions on the
+// same inputs and a point adds its solutions in root order, so its weight
+// does not depend on the batching; the order in which finished points
+// enter s1 and s2 does.  Same functions, inputs and order as tt_integrand
+// (a rejected root adds +0); the compiler contracts the two instances'
 // arithmetic differently, which leaves relative differences of about 1e-11
 // in FP64 and 1e-7 with the FP32 matrix element.  ON = false compiles to
 // nothing (no LDS) for launches without dilepton chunks.
 constexpr int kTTRec = 34;       // DilepPoint (28 doubles), the two jet energies, the monic quartic c0..c3
+#ifndef MEM_TT_DEFER
+#define MEM_TT_DEFER 32
+#endif
+constexpr int kTTDefer = MEM_TT_DEFER;               // largest remainder put off to the next batch
+static_assert(kTTDefer >= 0 && kTTDefer < kWave, "a remainder is below one round");
+constexpr int kTTQueue = 4 * kWave + kTTDefer;        // entries: the deferred ones and up to 4 per lane
 template <class T, bool ON>
 __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, uint32_t iter, const double* sgrid,
                                                 double* sbins, double& s1, double& s2, double* wrec, bool poison,
@@ -213,11 +230,11 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
 {
   if constexpr (ON) {
     __shared__ double srec[kBlock / kWave][kTTRec][kWave];
-    __shared__ double spx[kBlock / kWave][4 * kWave];
-    __shared__ double slo[kBlock / kWave][4 * kWave];
-    __shared__ double shi[kBlock / kWave][4 * kWave];
-    __shared__ double sres[kBlock / kWave][4 * kWave];
-    __shared__ int sown[kBlock / kWave][4 * kWave];
+    __shared__ double spx[kBlock / kWave][kTTQueue];
+    __shared__ double slo[kBlock / kWave][kTTQueue];
+    __shared__ double shi[kBlock / kWave][kTTQueue];
+    __shared__ double sres[kBlock / kWave][kTTQueue];
+    __shared__ int sown[kBlock / kWave][kTTQueue];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     double (*rec)[kWave] = srec[wv];
     double* qpx = spx[wv];
@@ -226,34 +243,53 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
     double* qres = sres[wv];
     int* qown = sown[wv];
     const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;     // lanes below this one
-    // wave-uniform trip count: lanes past the chunk's end idle
-    for (int kb = threadIdx.x - lane; kb < ch.count; kb += kBlock) {
-      const int k = kb + lane;
-      const bool live = k < ch.count;
-      TTMaps<T> m;
-      m.jetf = T(0);
-      m.bq[0].e = m.bq[1].e = 0.0;
-      DilepPoint s;
+    // the wavefront's points: 64 of every 256-point block, and its share of
+    // a ragged last block
+    const int n_wave = (ch.count / kBlock) * kWave + min(max(ch.count % kBlock - wv * kWave, 0), kWave);
+    int t = 0;         // the wavefront's points handed out so far
+    int ndef = 0;      // deferred entries at the front of the queue
+    // the lane's point while entries of it are queued (busy)
+    bool busy = false;
+    int k = 0, off = 0, left = 0;
+    double jac = 0.0, acc = 0.0;
+    T jetf = T(0);
+    uint32_t bins0 = 0, bins1 = 0;    // the point's 8 bin indices, 6 bits each
+    // wavefront-uniform control: every decision below comes from ballots
+    for (;;) {
+      const int avail = n_wave - t;
+      if (avail <= 0 && ndef == 0) break;
+      const uint64_t freem = __ballot(!busy);
+      const int rank = __popcll(freem & lt);
+      const bool take = !busy && rank < avail;
       QuartIso qi;
       qi.lo.n = 0;
-      double jac = 0.0;
-      int bin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (live) {
+      if (take) {
+        const int s = t + rank;
+        k = (s / kWave) * kBlock + wv * kWave + (s & (kWave - 1));
         double u[8], x[8];
         point_uniforms<8>(seed, (uint32_t)(ch.start + k), iter, (uint32_t)ch.event, (uint32_t)ch.perm, u);
         if (strat) (void)strat_point<8>(sc, ch.start + k, u);
+        int bin[8];
         jac = vegas_map<8>(sgrid, u, x, bin);
+        static_assert(kBins <= 64, "bin indices are packed in 6 bits");
+        bins0 = (uint32_t)bin[0] | (uint32_t)bin[1] << 6 | (uint32_t)bin[2] << 12 | (uint32_t)bin[3] << 18 |
+                (uint32_t)bin[4] << 24;
+        bins1 = (uint32_t)bin[5] | (uint32_t)bin[6] << 6 | (uint32_t)bin[7] << 12;
+        TTMaps<T> m;
         tt_maps<T>(pp, ev, x, m);
+        jetf = m.jetf;
+        acc = 0.0;
+        DilepPoint sp;
         double quart[5];
-        if (dilep_prepare(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, s, quart)) {
+        if (dilep_prepare(m.bq[0], m.bq[1], ev.lp, ev.lm, m.metx, m.mety, m.q2wp, m.q2t, m.q2wm, m.q2tb, sp, quart)) {
           // the solve state goes to the lane's LDS record before the root
-          // isolation, so that it is not held in registers across it (the
-          // previous round's readers finished at its last wave_sync)
-          const double r[30] = {s.A1.e0, s.A1.e1, s.A1.e2, s.A1.z0, s.A1.z1, s.A1.z2,
-                                s.A2.e0, s.A2.e1, s.A2.e2, s.A2.z0, s.A2.z1, s.A2.z2,
-                                s.P0, s.P1, s.P2, s.Q0, s.Q1,
-                                s.tq[0], s.tq[1], s.tq[2], s.tq[3], s.itq[0], s.itq[1], s.itq[2], s.itq[3],
-                                s.lam, s.mx, s.my, m.bq[0].e, m.bq[1].e};
+          // isolation, so that it is not held in registers across it (its
+          // last reader finished before the previous batch's last wave_sync)
+          const double r[30] = {sp.A1.e0, sp.A1.e1, sp.A1.e2, sp.A1.z0, sp.A1.z1, sp.A1.z2,
+                                sp.A2.e0, sp.A2.e1, sp.A2.e2, sp.A2.z0, sp.A2.z1, sp.A2.z2,
+                                sp.P0, sp.P1, sp.P2, sp.Q0, sp.Q1,
+                                sp.tq[0], sp.tq[1], sp.tq[2], sp.tq[3], sp.itq[0], sp.itq[1], sp.itq[2], sp.itq[3],
+                                sp.lam, sp.mx, sp.my, m.bq[0].e, m.bq[1].e};
 #pragma unroll
           for (int f = 0; f < 30; ++f) rec[f][lane] = r[f];
           quartic_isolate(quart, qi);
@@ -261,67 +297,96 @@ __device__ __forceinline__ void chunk_points_tt(const Chunk& ch, uint64_t seed, 
           for (int f = 0; f < 4; ++f) rec[30 + f][lane] = qi.c[f];
         }
       }
+      t += min(__popcll(freem), max(avail, 0));
+      // the new entries go after the deferred ones, in lane order
       const int nr = qi.lo.n;
-      int off = 0, total = 0;
+      int o = 0, total = ndef;
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         const uint64_t msk = __ballot((nr >> b) & 1);
-        off += __popcll(msk & lt) << b;
+        o += __popcll(msk & lt) << b;
         total += __popcll(msk) << b;
       }
+      o += ndef;
       if (nr > 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (j < nr) {
-            qpx[off + j] = qi.x0.get(j);
-            qlo[off + j] = qi.lo.get(j);
-            qhi[off + j] = qi.hi.get(j);
-            qown[off + j] = lane;
+            qpx[o + j] = qi.x0.get(j);
+            qlo[o + j] = qi.lo.get(j);
+            qhi[o + j] = qi.hi.get(j);
+            qown[o + j] = lane;
           }
         }
       }
+      if (take) {
+        busy = true;
+        off = o;
+        left = nr;
+      }
       wave_sync();
-      // the wavefront's root searches, one interval per lane
-      for (int i = lane; i < total; i += kWave) {
-        const int o = qown[i];
-        const double c[5] = {rec[30][o], rec[31][o], rec[32][o], rec[33][o], 1.0};
+      // entries run in this batch: whole rounds, and the remainder when it
+      // exceeds kTTDefer or the wavefront has no points left to hand out
+      int done = total;
+      if (t < n_wave && total % kWave <= kTTDefer) done = total - total % kWave;
+      // the root searches, one interval per lane
+      for (int i = lane; i < done; i += kWave) {
+        const int ow = qown[i];
+        const double c[5] = {rec[30][ow], rec[31][ow], rec[32][ow], rec[33][ow], 1.0};
         qpx[i] = quartic_root(c, qlo[i], qhi[i], qpx[i]);
       }
       wave_sync();
       // the roots' acceptance and matrix elements, one root per lane
-      for (int i = lane; i < total; i += kWave) {
-        const int o = qown[i];
-        DilepPoint t;
-        t.A1 = Affine{rec[0][o], rec[1][o], rec[2][o], rec[3][o], rec[4][o], rec[5][o]};
-        t.A2 = Affine{rec[6][o], rec[7][o], rec[8][o], rec[9][o], rec[10][o], rec[11][o]};
-        t.P0 = rec[12][o]; t.P1 = rec[13][o]; t.P2 = rec[14][o]; t.Q0 = rec[15][o]; t.Q1 = rec[16][o];
+      for (int i = lane; i < done; i += kWave) {
+        const int ow = qown[i];
+        DilepPoint sp;
+        sp.A1 = Affine{rec[0][ow], rec[1][ow], rec[2][ow], rec[3][ow], rec[4][ow], rec[5][ow]};
+        sp.A2 = Affine{rec[6][ow], rec[7][ow], rec[8][ow], rec[9][ow], rec[10][ow], rec[11][ow]};
+        sp.P0 = rec[12][ow]; sp.P1 = rec[13][ow]; sp.P2 = rec[14][ow]; sp.Q0 = rec[15][ow]; sp.Q1 = rec[16][ow];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) { t.tq[c] = rec[17 + c][o]; t.itq[c] = rec[21 + c][o]; }
-        t.lam = rec[25][o]; t.mx = rec[26][o]; t.my = rec[27][o];
-        const double E0 = rec[28][o], E1 = rec[29][o];
+        for (int c = 0; c < 4; ++c) { sp.tq[c] = rec[17 + c][ow]; sp.itq[c] = rec[21 + c][ow]; }
+        sp.lam = rec[25][ow]; sp.mx = rec[26][ow]; sp.my = rec[27][ow];
+        const double E0 = rec[28][ow], E1 = rec[29][ow];
         DilepGeom g;
-        dilep_geom(tt_jet(ev, 0, E0), tt_jet(ev, 1, E1), ev.lp, ev.lm, t, g);
+        dilep_geom(tt_jet(ev, 0, E0), tt_jet(ev, 1, E1), ev.lp, ev.lm, sp, g);
         NuSol sol;
-        qres[i] = dilep_accept(t, g, qpx[i], sol, polish_tol<T>()) ? tt_solution<T>(pp, ev, E0, E1, sol) : 0.0;
+        qres[i] = dilep_accept(sp, g, qpx[i], sol, polish_tol<T>()) ? tt_solution<T>(pp, ev, E0, E1, sol) : 0.0;
       }
       wave_sync();
-      double acc = 0.0;
-      for (int j = 0; j < nr; ++j) acc += qres[off + j];
-      wave_sync();     // the next round overwrites the queue
-      if (live) {
-        double w = tt_point<T>(pp, ev, acc, m.jetf) * jac;
-        if (poison) w = __builtin_nan("");
-        if (wrec) wrec[k] = w;
-        s1 += w;
-        s2 += w * w;
-        if (strat) sc.w[ch.start + k] = w;
-        if (w != 0.0) {
-          // H n_h found again rather than held in registers across the solve
-          const double q = strat ? w * w / strat_hn(sc, ch.start + k) : w * w;
+      if (busy) {
+        // this batch's entries of the lane's point, in root order
+        const int p = min(max(done - off, 0), left);
+        for (int j = 0; j < p; ++j) acc += qres[off + j];
+        left -= p;
+        off += p - done;
+        if (left == 0) {
+          busy = false;
+          double w = tt_point<T>(pp, ev, acc, jetf) * jac;
+          if (poison) w = __builtin_nan("");
+          if (wrec) wrec[k] = w;
+          s1 += w;
+          s2 += w * w;
+          if (strat) sc.w[ch.start + k] = w;
+          if (w != 0.0) {
+            // H n_h found again rather than held in registers across the solve
+            const double q = strat ? w * w / strat_hn(sc, ch.start + k) : w * w;
 #pragma unroll
-          for (int d = 0; d < 8; ++d) atomicAdd(&sbins[d * kBins + bin[d]], q);
+            for (int d = 0; d < 8; ++d)
+              atomicAdd(&sbins[d * kBins + (int)(((d < 5 ? bins0 : bins1) >> (6 * (d < 5 ? d : d - 5))) & 63u)], q);
+          }
         }
       }
+      // the deferred entries to the front of the queue (at most one per lane)
+      const int nd = total - done;
+      if (done > 0 && nd > 0) {
+        double dpx = 0.0, dlo = 0.0, dhi = 0.0;
+        int down = 0;
+        if (lane < nd) { dpx = qpx[done + lane]; dlo = qlo[done + lane]; dhi = qhi[done + lane]; down = qown[done + lane]; }
+        wave_sync();
+        if (lane < nd) { qpx[lane] = dpx; qlo[lane] = dlo; qhi[lane] = dhi; qown[lane] = down; }
+      }
+      wave_sync();     // the next batch appends to the queue
+      ndef = nd;
     }
   }
 }
