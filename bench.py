@@ -34,19 +34,20 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 
 # Algorithmic FLOP per integrand evaluation of the ttbar dilepton path,
 # FP32-equivalent (an FP64 operation counts twice: the MI355X FP64 vector
-# peak is half the FP32 one).  Counted by measure/opcount.py on
-# 8 events x 2 assignments x 8 VEGAS iterations x 4096 points: 1242.4 FP64 +
-# 702.6 FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
-FLOP_PER_EVAL = 2.0 * 1242.4 + 702.6
+# peak is half the FP32 one).  Counted by measure/opcount.py on this
+# benchmark's own fixed-budget workload: its 4096 events x 2 assignments x 8
+# VEGAS iterations x 32 768 points (65 536 per event): 1160.68 FP64 + 623.83
+# FP32 FLOP per evaluation (profiles/flop_count_ttbar_dilepton.md).
+FLOP_PER_EVAL = 2.0 * 1160.68 + 623.83
 
 # HBM bytes per fixed-budget launch of the integrand kernel (4096 events x
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # script's fixed-budget pass, each scaled by what the counter reads for plain
 # kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
-# FETCH 95 640 KiB x 2.000 + WRITE 266 096 KiB x 1.000.  Valid only for this
+# FETCH 95 542 KiB x 2.000 + WRITE 266 097 KiB x 1.000.  Valid only for this
 # workload and the kernel build the counters were taken on (set to None when
 # the kernel changes, until they are taken again).
-TRAFFIC_BYTES_PER_LAUNCH = (95640 * 2.000 + 266096 * 1.000) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (95541.6 * 2.000 + 266097 * 1.000) * 1024
 TRAFFIC_WORKLOAD = (4096, 65536, 4096, 1)     # events, points, chunk points, waves per SIMD
 
 # tuned launch configurations (mem_autotune's table) shipped with the package

@@ -156,10 +156,12 @@ static void refine(const std::vector<double>& d, double alpha, double* e)
 
 int main(int argc, char** argv)
 {
-  if (argc < 4) { std::fprintf(stderr, "usage: opcount n_points n_iter n_events < events.bin\n"); return 2; }
+  if (argc < 4) { std::fprintf(stderr, "usage: opcount n_points n_iter n_events [first_event] < events.bin\n"); return 2; }
   const long npts = std::atol(argv[1]);
   const int nit = std::atoi(argv[2]);
   int nuse = std::atoi(argv[3]);
+  // index of the first event in the whole sample (the point stream's event counter)
+  const int e0 = argc > 4 ? std::atoi(argv[4]) : 0;
   int32_t n_ev = 0;
   if (std::fread(&n_ev, 4, 1, stdin) != 1) return 3;
   std::vector<double> ev((size_t)n_ev * 16);
@@ -201,7 +203,7 @@ int main(int argc, char** argv)
         for (long k = 0; k < npts; ++k) {
           CD u[8], x[8];
           int bin[8];
-          point_uniforms<8>(0x14077595ull, (uint32_t)k, (uint32_t)j, (uint32_t)e, (uint32_t)perm, u);
+          point_uniforms<8>(0x14077595ull, (uint32_t)k, (uint32_t)j, (uint32_t)(e0 + e), (uint32_t)perm, u);
           CD jac = vegas_map<8>(cg.data(), u, x, bin);
           int ns = 0;
           CD f = tt_integrand<CF>(pp, tev, x, &ns);
@@ -234,13 +236,13 @@ int main(int argc, char** argv)
     const Tally& a = g_t;
     double flops = a.add[p] + a.mul[p] + 2 * a.fma[p] + a.div[p] + a.sqr[p] + a.trans[p];
     (p == 0 ? tot64 : tot32) = flops / n_evals;
-    std::printf(", \"%s\": {\"add\": %.2f, \"mul\": %.2f, \"fma\": %.2f, \"div\": %.2f, \"sqrt\": %.2f, "
-                "\"transcendental\": %.2f, \"flop\": %.2f}",
+    std::printf(", \"%s\": {\"add\": %.4f, \"mul\": %.4f, \"fma\": %.4f, \"div\": %.4f, \"sqrt\": %.4f, "
+                "\"transcendental\": %.4f, \"flop\": %.4f}",
                 nm[p], a.add[p] / n_evals, a.mul[p] / n_evals, a.fma[p] / n_evals, a.div[p] / n_evals,
                 a.sqr[p] / n_evals, a.trans[p] / n_evals, flops / n_evals);
   }
-  std::printf(", \"flop_fp32_equivalent\": %.2f, \"per_iteration_flop\": [", tot32 + 2 * tot64);
-  for (int j = 0; j < nit; ++j) std::printf("%s%.1f", j ? ", " : "", per_iter_flops[j] / (nuse * 2.0 * npts));
+  std::printf(", \"flop_fp32_equivalent\": %.4f, \"per_iteration_flop\": [", tot32 + 2 * tot64);
+  for (int j = 0; j < nit; ++j) std::printf("%s%.4f", j ? ", " : "", per_iter_flops[j] / (nuse * 2.0 * npts));
   std::printf("]}\n");
   return 0;
 }
