@@ -186,24 +186,31 @@ def flow_leg(mem, proc, comps, n_ev, args):
                   "mean_iterations": float(np.mean(n_used.cpu().numpy()))}
     # the flow seeding VEGAS's grids (MEM_FLOW_SEED_GRID) at the headline's
     # points per iteration: every iteration enters the estimate
-    def run_seeded():
-        mem.integrate_events(comps, proc, PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
-                             n_iter_out=n_used, flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID,
-                             allocation=mem.MEM_ALLOC_NEYMAN)
+    # (the headline's 65 536, and the flow leg's 16 384 against VEGAS at 16 384)
+    def seeded_run(pts):
+        def run_seeded():
+            mem.integrate_events(comps, proc, pts, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
+                                 n_iter_out=n_used, flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID,
+                                 allocation=mem.MEM_ALLOC_NEYMAN)
 
-    run_seeded()
-    torch.cuda.synchronize()
-    st_times = []
-    for _ in range(max(1, args.steps)):
-        t0 = time.perf_counter()
         run_seeded()
         torch.cuda.synchronize()
-        st_times.append(time.perf_counter() - t0)
-    seeded = {"events_per_s": n_ev * len(st_times) / sum(st_times), "points_per_iteration": PTS,
-              "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
-              "mean_iterations": float(np.mean(n_used.cpu().numpy())),
-              "median_iterations": float(np.median(n_used.cpu().numpy()))}
+        st_times = []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            run_seeded()
+            torch.cuda.synchronize()
+            st_times.append(time.perf_counter() - t0)
+        return {"events_per_s": n_ev * len(st_times) / sum(st_times), "points_per_iteration": pts,
+                "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
+                "mean_iterations": float(np.mean(n_used.cpu().numpy())),
+                "median_iterations": float(np.median(n_used.cpu().numpy()))}
+
+    seeded = seeded_run(PTS)
     log(f"flow-seeded VEGAS grids: {seeded}")
+    seeded_small = seeded_run(FLOW_PTS)
+    seeded_small["vs_vegas_same_points"] = seeded_small["events_per_s"] / vegas_same["events_per_s"]
+    log(f"flow-seeded VEGAS grids at {FLOW_PTS} points: {seeded_small}")
     # ESS/N per integral: the untrained flow (the identity, i.e. uniform
     # sampling), the trained flow (its first batch) and the VEGAS grid after
     # three adaptations (its fourth iteration)
@@ -228,7 +235,7 @@ def flow_leg(mem, proc, comps, n_ev, args):
     ess["vegas_iteration_4"] = ess_quantiles(rec.cpu().numpy()[3], FLOW_PTS // 2)
     log(f"ESS/N quantiles over the {n_int} integrals at {FLOW_PTS // 2} points: {ess}")
     out = {"events_per_s": value, "seconds_per_step": sum(times) / len(times), "flow_alone": alone,
-           "flow_seeded_grids": seeded, "ess_over_n": ess,
+           "flow_seeded_grids": seeded, "flow_seeded_grids_same_points": seeded_small, "ess_over_n": ess,
            "vegas_same_points": vegas_same,
            "points_per_event_per_batch": FLOW_PTS, "fallback_fraction": float(np.mean(st == 4)),
            "converged_fraction": float(np.mean((st == 0) | (st == 4))),

@@ -233,7 +233,7 @@ typedef struct mem_flow_s* mem_flow;
  *                  MEM_FLOW_SAMPLE (0): importance sampling from it, as
  *                  described under `flow`;
  *                  MEM_FLOW_SEED_GRID: VEGAS whose grids start from the
- *                  flow instead of uniform ones: 2048 flow samples of each
+ *                  flow instead of uniform ones: 1024 flow samples of each
  *                  integral (the flow's point stream at iteration
  *                  0xFFFFFFF0) give, per dimension, edges at the quantiles
  *                  k/64 of 0.8 x (sample CDF) + 0.2 x (uniform CDF); every

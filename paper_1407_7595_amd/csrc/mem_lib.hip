@@ -2702,7 +2702,7 @@ extern "C" mem_status mem_flow_load(const char* path, mem_flow* out)
 // Flow-proposal integration (see mem_integrate_opts.flow).
 // ------------------------------------------------ flow-seeded grids ----
 namespace {
-constexpr int64_t kSeedPoints = 2048;        // proposal samples per integral
+constexpr int64_t kSeedPoints = 1024;        // proposal samples per integral
 constexpr int kSeedHist = 512;               // histogram bins per dimension
 constexpr double kSeedUniform = 0.2;         // share of the uniform density in the seeded grid
 constexpr uint32_t kSeedIter = 0xFFFFFFF0u;  // iteration index of the seeding draws
