@@ -44,11 +44,11 @@ FLOP_PER_EVAL = 2.0 * 1160.68 + 623.83
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # script's fixed-budget pass, each scaled by what the counter reads for plain
 # kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
-# FETCH 95 542 KiB x 2.000 + WRITE 266 097 KiB x 1.000.  Valid only for this
+# FETCH 61 563 KiB x 2.000 + WRITE 133 054 KiB x 1.000.  Valid only for this
 # workload and the kernel build the counters were taken on (set to None when
 # the kernel changes, until they are taken again).
-TRAFFIC_BYTES_PER_LAUNCH = (95541.6 * 2.000 + 266097 * 1.000) * 1024
-TRAFFIC_WORKLOAD = (4096, 65536, 4096, 1)     # events, points, chunk points, waves per SIMD
+TRAFFIC_BYTES_PER_LAUNCH = (61562.7 * 2.000 + 133054 * 1.000) * 1024
+TRAFFIC_WORKLOAD = (4096, 65536, 8192, 1)     # events, points, chunk points, waves per SIMD
 
 # tuned launch configurations (mem_autotune's table) shipped with the package
 TUNING_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1407_7595_amd", "tuning.txt")
