@@ -11,8 +11,9 @@ bit).
 
 Covered: the dilepton kernel's compacted path (per-wavefront LDS record and
 root queue, rounds with more than 64 roots) at the benchmark's launch shape
-(32 768 points per assignment and iteration = 8 chunks) and with a ragged
-tail, in FP32 and FP64; the same under Neyman allocation (chunks cut at the
+(32 768 points per assignment and iteration), at the library's default
+chunk of 4096 points and at the shipped tuning table's, with a ragged tail,
+in FP32 and FP64; the same under Neyman allocation (chunks cut at the
 allocation); the per-lane path of launches that also carry t tbar H chunks;
 and every other process kind's chunk loop.  Bars: FP32 1e-5 relative and
 FP64 1e-9 (dilepton; the FP64 note in test_gpu_parity.py) on every point the
@@ -20,6 +21,7 @@ oracle does not flag as ill-conditioned (its own value moves by more than
 1e-7 under 1-ulp changes of x), at most 1 % flagged; FP64 Drell-Yan 1e-11;
 equal solution counts are implied by the weights.
 """
+import os
 import sys
 
 import numpy as np
@@ -126,6 +128,8 @@ def tt_events():
 # 8 chunks of 4096); event 1: 13 288 per assignment (3 chunks + a ragged
 # 1000-point tail that ends inside a wavefront)
 TT_BUDGETS = [65536, 26576]
+TUNING_TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1407_7595_amd",
+                            "tuning.txt")
 TT_ITERS = 6
 TT_SEED = 77
 
@@ -133,7 +137,22 @@ TT_SEED = 77
 @pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-9)])
 @pytest.mark.parametrize("event,perm", [(0, 1), (1, 0)])
 def test_queue_weights_tt(mem, precision, tol, event, perm):
-    p = mem.Process(mem.MEM_TT_DILEPTON, precision=precision)
+    check_queue_weights_tt(mem, mem.Process(mem.MEM_TT_DILEPTON, precision=precision), precision, tol, event, perm)
+
+
+@pytest.mark.parametrize("event,perm", [(0, 0), (1, 1)])
+def test_queue_weights_tt_tuned_launch(mem, event, perm):
+    """the benchmark's launch configuration: the shipped tuning table's
+    entry for this GPU (8192 points per chunk, one wave per SIMD for the
+    FP32 dilepton process on gfx950), every point of the first and last
+    iterations against the oracle"""
+    p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
+    assert p.load_tuning(TUNING_TABLE), "the shipped table has an entry for this GPU"
+    say(f"tuned launch: {p.chunk_points()} points per chunk, {p.waves()} waves per SIMD")
+    check_queue_weights_tt(mem, p, 1, 1e-5, event, perm)
+
+
+def check_queue_weights_tt(mem, p, precision, tol, event, perm):
     d = tt_events()
     comps = mem.to_components(d["obs"]).cuda()
     per = TT_BUDGETS[event] // 2
