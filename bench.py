@@ -50,6 +50,13 @@ FLOP_PER_EVAL = 2.0 * 1160.68 + 623.83
 TRAFFIC_BYTES_PER_LAUNCH = (61562.7 * 2.000 + 133054 * 1.000) * 1024
 TRAFFIC_WORKLOAD = (4096, 65536, 8192, 1)     # events, points, chunk points, waves per SIMD
 
+# chunks of the late iterations (mem_integrate_opts.tail_chunk_points /
+# tail_iter): from the eighth iteration on, when few events still run, 2048
+# points per chunk spread them over more of the GPU (measured on this
+# workload: 2048 from iteration 6, 8 or 10 within 0.5 % of each other; 1024
+# slower than none)
+TAIL = dict(tail_chunk_points=2048, tail_iter=8)
+
 # tuned launch configurations (mem_autotune's table) shipped with the package
 TUNING_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1407_7595_amd", "tuning.txt")
 
@@ -149,7 +156,7 @@ def flow_leg(mem, proc, comps, n_ev, args):
     def run(tm=None, thr=0.3):
         mem.integrate_events(comps, proc, FLOW_PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER,
                              outputs=(P, E, S), n_iter_out=n_used, flow=f, ess_threshold=thr, timing=tm,
-                             allocation=mem.MEM_ALLOC_NEYMAN)
+                             allocation=mem.MEM_ALLOC_NEYMAN, **TAIL)
 
     run()
     torch.cuda.synchronize()
@@ -179,7 +186,7 @@ def flow_leg(mem, proc, comps, n_ev, args):
     # setting): the like-for-like reference for the proposal
     t0 = time.perf_counter()
     mem.integrate_events(comps, proc, FLOW_PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER,
-                         outputs=(P, E, S), n_iter_out=n_used, allocation=mem.MEM_ALLOC_NEYMAN)
+                         outputs=(P, E, S), n_iter_out=n_used, allocation=mem.MEM_ALLOC_NEYMAN, **TAIL)
     torch.cuda.synchronize()
     v_s = time.perf_counter() - t0
     vegas_same = {"events_per_s": n_ev / v_s, "converged_fraction": float(np.mean(S.cpu().numpy() == 0)),
@@ -191,7 +198,7 @@ def flow_leg(mem, proc, comps, n_ev, args):
         def run_seeded():
             mem.integrate_events(comps, proc, pts, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
                                  n_iter_out=n_used, flow=f, flow_mode=mem.MEM_FLOW_SEED_GRID,
-                                 allocation=mem.MEM_ALLOC_NEYMAN)
+                                 allocation=mem.MEM_ALLOC_NEYMAN, **TAIL)
 
         run_seeded()
         torch.cuda.synchronize()
@@ -447,13 +454,13 @@ def main():
         # the headline's own call: target mode to 1 %, Neyman allocation
         best, bw, rate = proc.autotune(comps, PTS, table_path=TUNING_TABLE, target_rel_err=TARGET,
                                        max_iter=MAX_ITER, allocation=mem.MEM_ALLOC_NEYMAN,
-                                       candidates=[1024, 2048, 4096, 8192, 16384])
+                                       candidates=[1024, 2048, 4096, 8192, 16384], **TAIL)
         launch = {"source": "tuned now", "tuner_events_per_s": rate}
         log(f"autotune: chunk {best}, {bw} waves per SIMD, {rate:.4g} events/s -> {TUNING_TABLE}")
     elif os.path.exists(TUNING_TABLE) and proc.load_tuning(TUNING_TABLE):
         launch = {"source": "table"}
     launch.update({"chunk_points": proc.chunk_points(), "waves_per_simd": proc.waves(),
-                   "table": os.path.relpath(TUNING_TABLE, os.path.dirname(os.path.abspath(__file__)))})
+                   "table": os.path.relpath(TUNING_TABLE, os.path.dirname(os.path.abspath(__file__))), **TAIL})
     log(f"launch: {launch}")
     P = torch.empty(n_ev, dtype=torch.float64, device="cuda")
     E = torch.empty_like(P)
@@ -476,7 +483,7 @@ def main():
 
     def step(alloc=mem.MEM_ALLOC_NEYMAN):
         mem.integrate_events(comps, proc, PTS, 0, target_rel_err=TARGET, max_iter=MAX_ITER, outputs=(P, E, S),
-                             n_iter_out=n_used, allocation=alloc)
+                             n_iter_out=n_used, allocation=alloc, **TAIL)
 
     for w in range(args.warmup):
         log(f"warmup step {w}")

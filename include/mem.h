@@ -288,7 +288,24 @@ typedef struct mem_flow_s* mem_flow;
  *                  the larger weight), at the price of a larger error when
  *                  the grid is still improving.  The stopping test of
  *                  target mode uses the chosen estimate.  Other values:
- *                  MEM_EINVAL.                                          */
+ *                  MEM_EINVAL.
+ *  tail_chunk_points, tail_iter
+ *                  work-queue chunks of the late iterations: 0 (the
+ *                  default) keeps every iteration at the call's chunk size;
+ *                  otherwise, from iteration tail_iter (>= 1, counted from
+ *                  the integration's start, a resumed checkpoint's
+ *                  iterations included) on, every integral's points are cut
+ *                  into chunks of tail_chunk_points (a multiple of 256, at
+ *                  most 65536) instead.  In target mode the late iterations
+ *                  carry few events, whose few long chunks leave most of
+ *                  the GPU idle; shorter chunks spread them.  The chunking
+ *                  of an iteration depends only on its index, so a target-
+ *                  mode event equals a fixed run with the same options bit
+ *                  for bit; a different chunking changes the order of the
+ *                  partial sums, hence the last bits of the grids and the
+ *                  points drawn after them.  Work buffers grow by the tail
+ *                  table (chunk table and partials).  Not with stratify
+ *                  (MEM_EUNSUPPORTED).  Invalid values: MEM_EINVAL.     */
 enum { MEM_ALLOC_EQUAL = 0, MEM_ALLOC_NEYMAN = 1 };
 enum { MEM_FLOW_SAMPLE = 0, MEM_FLOW_SEED_GRID = 1 };
 enum { MEM_STRATIFY_OFF = 0, MEM_STRATIFY_ADAPTIVE = 1 };
@@ -343,6 +360,8 @@ typedef struct {
   int32_t flow_mode;
   int32_t stratify;
   int32_t combine;
+  int32_t tail_chunk_points;
+  int32_t tail_iter;
 } mem_integrate_opts;
 
 /* Per-event status codes written to status_out. */

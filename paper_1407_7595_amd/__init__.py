@@ -73,7 +73,7 @@ class IntegrateOpts(ctypes.Structure):
                 ("weights_integral", ctypes.c_int32), ("weights_rows", ctypes.c_int32), ("hooks", ctypes.c_uint32), ("hook_event", ctypes.c_int32),
                 ("checkpoint", ctypes.c_void_p), ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p), ("flow_mode", ctypes.c_int32), ("stratify", ctypes.c_int32),
-                ("combine", ctypes.c_int32)]
+                ("combine", ctypes.c_int32), ("tail_chunk_points", ctypes.c_int32), ("tail_iter", ctypes.c_int32)]
 
 
 MEM_HOOK_NONFINITE = 1
@@ -230,7 +230,8 @@ class Process:
         _check(lib().mem_set_pdf_grid(self.handle, a.ctypes.data, a.shape[1], a.shape[0], b), "mem_set_pdf_grid")
 
     def autotune(self, comps, n_points, candidates=None, waves=None, table_path=None, charge=None, n_iter=2,
-                 target_rel_err=None, max_iter=64, allocation=0, stratify=0, seed=0x5EED):
+                 target_rel_err=None, max_iter=64, allocation=0, stratify=0, seed=0x5EED, tail_chunk_points=0,
+                 tail_iter=0):
         """mem_autotune on the given events over chunk sizes x waves-per-SIMD
         variants, timing n_iter-iteration integrations (or, with
         target_rel_err, target-mode integrations with these options);
@@ -239,11 +240,12 @@ class Process:
         cand = (ctypes.c_int32 * len(candidates))(*candidates) if candidates else None
         wv = (ctypes.c_int32 * len(waves))(*waves) if waves else None
         base = None
-        if target_rel_err is not None or allocation or stratify or n_iter != 2:
+        if target_rel_err is not None or allocation or stratify or tail_chunk_points or n_iter != 2:
             base = IntegrateOpts()
             base.seed, base.alpha, base.max_iter, base.use_graph = seed, 1.5, max_iter, 1
             base.target_rel_err = target_rel_err or 0.0
             base.allocation, base.stratify = allocation, stratify
+            base.tail_chunk_points, base.tail_iter = tail_chunk_points, tail_iter
         best, bw, rate = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(lib().mem_autotune(self.handle, ctypes.byref(ev), n_points, n_iter,
                                   ctypes.byref(base) if base is not None else None, cand,
@@ -318,7 +320,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                      max_iter=64, stream=None, iter_out=None, grid_out=None, n_iter_out=None, outputs=None,
                      timing=None, charge=None, chunk_points=0, use_graph=1, flow=None, ess_threshold=0.0,
                      allocation=0, weights_out=None, weights_integral=0, hooks=0, hook_event=0,
-                     checkpoint=None, allocator=None, flow_mode=0, stratify=0, combine=0, _noalloc=False):
+                     checkpoint=None, allocator=None, flow_mode=0, stratify=0, combine=0, tail_chunk_points=0,
+                     tail_iter=0, _noalloc=False):
     """mem_integrate_events.  comps: [4, n_obj, n_events] float64 (device
     or host); processes: one Process or a list (one per event); n_points:
     int or a list per event; timing: optional ctypes (c_double * 8) array;
@@ -331,7 +334,8 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
     None (hipMalloc), TORCH_ALLOCATOR, or a pair (ALLOC_FN, FREE_FN);
     stratify: MEM_STRATIFY_ADAPTIVE for adaptive stratified sampling;
     combine: MEM_COMBINE_WEIGHTED or MEM_COMBINE_MEAN (the iterations'
-    combination).
+    combination); tail_chunk_points / tail_iter: chunks of that many points
+    from that iteration on (0: the call's chunk size throughout).
     Returns (P, err, status) as torch tensors on the device of `comps`
     (or writes into `outputs`)."""
     import torch
@@ -363,7 +367,7 @@ def integrate_events(comps, processes, n_points, n_iter, seed=0x14077595, alpha=
                         checkpoint.handle.value if checkpoint is not None else None,
                         ctypes.cast(allocator[0], ctypes.c_void_p) if allocator is not None else None,
                         ctypes.cast(allocator[1], ctypes.c_void_p) if allocator is not None else None, None,
-                        flow_mode, stratify, combine)
+                        flow_mode, stratify, combine, tail_chunk_points, tail_iter)
     entry = "mem_integrate_events_noalloc" if _noalloc else "mem_integrate_events"
     _check(getattr(lib(), entry)(ctypes.byref(ev), handles, len(procs), npts_arr, len(npts), n_iter,
                                  ctypes.byref(opt), ctypes.c_void_p(P.data_ptr()),

@@ -1137,6 +1137,12 @@ static mem_status integrate_entry(const mem_events* ev, const mem_process* hyp, 
   if (o.flow_mode != MEM_FLOW_SAMPLE && o.flow_mode != MEM_FLOW_SEED_GRID) return fail(MEM_EINVAL, "unknown flow_mode");
   if (o.stratify != MEM_STRATIFY_OFF && o.stratify != MEM_STRATIFY_ADAPTIVE) return fail(MEM_EINVAL, "unknown stratify");
   if (o.combine != MEM_COMBINE_WEIGHTED && o.combine != MEM_COMBINE_MEAN) return fail(MEM_EINVAL, "unknown combine");
+  if (o.tail_chunk_points != 0) {
+    if (o.tail_chunk_points < 0 || o.tail_chunk_points % kBlock != 0 || o.tail_chunk_points > 65536)
+      return fail(MEM_EINVAL, "tail_chunk_points must be 0 or a multiple of 256 <= 65536");
+    if (o.tail_iter < 1) return fail(MEM_EINVAL, "tail_iter must be at least 1");
+    if (o.stratify) return fail(MEM_EUNSUPPORTED, "tail chunking of stratified integrations");
+  }
   if (o.stratify) {
     if (o.allocation == MEM_ALLOC_NEYMAN) return fail(MEM_EINVAL, "stratified sampling takes the equal split across permutations");
     if (o.flow) return fail(MEM_EUNSUPPORTED, "stratified sampling is VEGAS-only");
@@ -1397,6 +1403,33 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   // the queue kernel writes row `iteration index` of weights_out
   if (o.weights_out && (int64_t)iter0 + run_iters > (int64_t)o.weights_rows)
     return fail(MEM_EINVAL, "weights_rows below the iterations the call can reach");
+  // tail chunking: a second chunk table (chunks of tail_chunk_points, their
+  // own partial slots after the first table's) that the iterations from
+  // tail_iter on use; built only when the call can reach tail_iter
+  const size_t n_main = chunks.size();
+  const bool tail = o.tail_chunk_points > 0 && (int64_t)iter0 + run_iters > (int64_t)o.tail_iter;
+  std::vector<IntegralDesc> ints_tail;
+  if (tail) {
+    ints_tail = ints;
+    for (int ig = 0; ig < n_int; ++ig) {
+      IntegralDesc& d = ints_tail[ig];
+      d.chunk0 = (int64_t)chunks.size();
+      d.n_chunks = 0;
+      for (int64_t s0 = 0; s0 < cover[ig]; s0 += o.tail_chunk_points) {
+        Chunk c{};
+        c.integral = ig; c.event = d.event; c.perm = d.perm;
+        c.count = (int32_t)std::min<int64_t>(o.tail_chunk_points, cover[ig] - s0);
+        c.start = s0;
+        c.part_off = part_total;
+        c.proc = int_proc[ig];
+        c.id = (int32_t)chunks.size();
+        part_total += 2 + (int64_t)d.dims * kBins;
+        chunks.push_back(c);
+        d.n_chunks++;
+      }
+    }
+    if ((int64_t)chunks.size() > (int64_t)0x7FFFFFFF) return fail(MEM_EINVAL, "too many chunks");
+  }
   // launch groups by matrix-element precision; queue order longest first
   std::vector<Group> groups;
   auto group_of = [&](int prec) {
@@ -1408,14 +1441,18 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   for (const auto* p : procs) if (p->desc.kind != MEM_DY_QQ_GAMMA_MUMU) { first_prec = p->desc.precision; break; }
   if (first_prec < 0) first_prec = MEM_FP64;
   std::vector<double> cost(chunks.size());
-  for (size_t c = 0; c < chunks.size(); ++c) {
+  std::vector<int> int_group(n_int, 0);
+  for (size_t c = 0; c < chunks.size(); ++c)
+    cost[c] = chunks[c].count * eval_cost(procs[chunks[c].proc]->desc.kind);
+  for (size_t c = 0; c < n_main; ++c) {
     const mem_process_s* p = procs[chunks[c].proc];
     int prec = p->desc.kind == MEM_DY_QQ_GAMMA_MUMU ? first_prec : p->desc.precision;
-    Group& G = groups[group_of(prec)];
+    const int gi = group_of(prec);
+    int_group[chunks[c].integral] = gi;
+    Group& G = groups[gi];
     G.queue.push_back((int32_t)c);
     G.mask |= kind_mask(p->desc.kind);
     G.waves = G.waves < 0 ? p->waves : G.waves == p->waves ? G.waves : 0;
-    cost[c] = chunks[c].count * eval_cost(p->desc.kind);
   }
   for (auto& G : groups)
     std::stable_sort(G.queue.begin(), G.queue.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
@@ -1462,7 +1499,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     A(b_ctl, sizeof(Control));
     A(b_heads, groups.size() * sizeof(uint32_t));
     A(b_nev, sizeof(double));
-    A(b_chunks_q, qtotal * sizeof(Chunk));
+    A(b_chunks_q, std::max(qtotal, chunks.size() - n_main) * sizeof(Chunk));
     if (neyman) {
       A(b_alloc, (size_t)n_int * sizeof(int64_t));
       A(b_cover, (size_t)n_int * sizeof(int64_t));
@@ -1688,8 +1725,44 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     qhost.swap(nq);
     return use_graph ? capture() : MEM_OK;
   };
+  // tail chunking: before iteration tail_iter the running integrals move to
+  // the tail table (their chunk table entries and partial slots), the queue
+  // is rebuilt from it and the iteration graph recaptured
+  bool tail_pending = tail;
+  auto switch_to_tail = [&]() -> mem_status {
+    HIP_TRY(hipStreamSynchronize(ws));
+    std::vector<int32_t> dn(n_ev);
+    HIP_TRY(hipMemcpy(dn.data(), b_done.p, n_ev * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(b_ints.p, ints_tail.data(), n_int * sizeof(IntegralDesc), hipMemcpyHostToDevice));
+    std::vector<std::vector<int32_t>> q(groups.size());
+    for (size_t c = n_main; c < chunks.size(); ++c)
+      if (!dn[chunks[c].event]) q[int_group[chunks[c].integral]].push_back((int32_t)c);
+    std::vector<int32_t> nq;
+    int64_t running = 0;
+    for (int e = 0; e < n_ev; ++e) running += dn[e] == 0 ? 1 : 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+      std::stable_sort(q[g].begin(), q[g].end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+      gq0[g] = nq.size();
+      gqn[g] = q[g].size();
+      nq.insert(nq.end(), q[g].begin(), q[g].end());
+      groups[g].blocks = persistent_blocks(groups[g].kernel, (int64_t)q[g].size());
+    }
+    std::vector<Chunk> pc(nq.size());
+    for (size_t i = 0; i < nq.size(); ++i) pc[i] = chunks[nq[i]];
+    if (!pc.empty())
+      HIP_TRY(hipMemcpy(b_chunks_q.p, pc.data(), pc.size() * sizeof(Chunk), hipMemcpyHostToDevice));
+    qhost.swap(nq);
+    if (target_mode) running_at_build = running;
+    return use_graph ? capture() : MEM_OK;
+  };
   auto wall0 = std::chrono::steady_clock::now();
   for (int j = 0; j < run_iters && running_at_build > 0; ++j) {
+    if (tail_pending && (int64_t)iter0 + j >= (int64_t)o.tail_iter) {
+      tail_pending = false;
+      mem_status ts = switch_to_tail();
+      if (ts != MEM_OK) return ts;
+      if (running_at_build == 0) break;     // target mode: every event retired
+    }
     if (use_graph) HIP_TRY(hipGraphLaunch(gexec, ws));
     else {
       mem_status es = enqueue_iteration(o.timing_out != nullptr, &tev);
