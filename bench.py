@@ -44,11 +44,11 @@ FLOP_PER_EVAL = 2.0 * 1160.68 + 623.83
 # 65 536 points), from rocprofv3 FETCH_SIZE / WRITE_SIZE passes over this
 # script's fixed-budget pass, each scaled by what the counter reads for plain
 # kernels of known size (profiles/hbm_counters_ttbar_dilepton_4096ev.md):
-# FETCH 61 563 KiB x 2.000 + WRITE 133 054 KiB x 1.000.  Valid only for this
+# FETCH 36 303 KiB x 2.000 + WRITE 66 532 KiB x 1.000.  Valid only for this
 # workload and the kernel build the counters were taken on (set to None when
 # the kernel changes, until they are taken again).
-TRAFFIC_BYTES_PER_LAUNCH = (61562.7 * 2.000 + 133054 * 1.000) * 1024
-TRAFFIC_WORKLOAD = (4096, 65536, 8192, 1)     # events, points, chunk points, waves per SIMD
+TRAFFIC_BYTES_PER_LAUNCH = (36303.2 * 2.000 + 66531.6 * 1.000) * 1024
+TRAFFIC_WORKLOAD = (4096, 65536, 16384, 1)    # events, points, chunk points, waves per SIMD
 
 # chunks of the late iterations (mem_integrate_opts.tail_chunk_points /
 # tail_iter): from the eighth iteration on, when few events still run, 2048
