@@ -339,8 +339,11 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v)
 
 // Sum the chunk partials of each integral in chunk order, form the
 // iteration estimate and its variance, fold it into the inverse-variance
-// combination (iterations >= 1) and refine the grid.
-__global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc* __restrict__ ints,
+// combination (iterations >= 1) and refine the grid.  One workgroup per
+// integral: integral blockIdx.x, or ig_list[blockIdx.x] once the host has
+// listed the running events' integrals (late iterations of target mode).
+__global__ __launch_bounds__(kBlock) void finish_iter_kernel(const int32_t* __restrict__ ig_list,
+                                                             const IntegralDesc* __restrict__ ints,
                                                              const Chunk* __restrict__ chunks,
                                                              const double* __restrict__ parts,
                                                              double* __restrict__ grids,
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void finish_iter_kernel(const IntegralDesc*
 {
   __shared__ double sb[kMaxDims * kBins];
   __shared__ double scratch[kBlock / kWave][3 * (kBins + 1)];
-  const int ig = blockIdx.x;
+  const int ig = ig_list ? ig_list[blockIdx.x] : (int)blockIdx.x;
   if (!active[ig]) return;
   const uint32_t iter = ctl->iter;
   const IntegralDesc in = ints[ig];
@@ -1471,7 +1474,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
   DevBuf b_procs(&work), b_ints(&work), b_chunks(&work), b_queue(&work), b_grids(&work), b_parts(&work),
       b_state(&work), b_active(&work), b_evi0(&work), b_evnp(&work), b_evnorm(&work), b_done(&work), b_ctl(&work),
       b_heads(&work), b_P(&work), b_err(&work), b_status(&work), b_alloc(&work), b_cover(&work), b_nev(&work),
-      b_sd(&work), b_cum(&work), b_sigb(&work), b_h0(&work), b_wpt(&work), b_siv(&work);
+      b_sd(&work), b_cum(&work), b_sigb(&work), b_h0(&work), b_wpt(&work), b_siv(&work), b_finlist(&work);
   size_t qtotal = 0;
   for (auto& G : groups) qtotal += G.queue.size();
   // every work buffer is taken before the first copy or launch; the chunk
@@ -1500,6 +1503,7 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
     A(b_heads, groups.size() * sizeof(uint32_t));
     A(b_nev, sizeof(double));
     A(b_chunks_q, std::max(qtotal, chunks.size() - n_main) * sizeof(Chunk));
+    A(b_finlist, (size_t)n_int * sizeof(int32_t));
     if (neyman) {
       A(b_alloc, (size_t)n_int * sizeof(int64_t));
       A(b_cover, (size_t)n_int * sizeof(int64_t));
@@ -1613,6 +1617,21 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
 
   const int ev_blocks = (n_ev + 255) / 256;
   Control* ctl = b_ctl.as<Control>();
+  // the integrals the finish step visits: every one, until a queue rebuild
+  // lists the running events' integrals
+  int n_fin = n_int;
+  bool fin_list = false;
+  auto list_running = [&](const std::vector<int32_t>& dn) -> mem_status {
+    std::vector<int32_t> l;
+    for (int e = 0; e < n_ev; ++e)
+      if (!dn[e])
+        for (int k = 0; k < ev_np[e]; ++k) l.push_back((int32_t)(ev_int0[e] + k));
+    if (l.empty()) return MEM_OK;     // nothing runs: the full grid, every workgroup returns at once
+    HIP_TRY(hipMemcpy(b_finlist.p, l.data(), l.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    n_fin = (int)l.size();
+    fin_list = true;
+    return MEM_OK;
+  };
   // one iteration: begin -> queue kernel(s) -> finish -> [events] -> end
   auto enqueue_iteration = [&](bool time_kernels, std::vector<hipEvent_t>* tev) -> mem_status {
     hipLaunchKernelGGL(iter_begin_kernel, dim3(1), dim3(64), 0, ws, ctl, b_heads.as<uint32_t>(), (int)groups.size());
@@ -1638,7 +1657,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       hipLaunchKernelGGL(strat_finish_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(), sview,
                          b_cum.as<int32_t>(), b_sigb.as<double>(), b_active.as<int32_t>(), b_chunks.as<Chunk>(),
                          b_h0.as<int32_t>(), b_siv.as<double>());
-    hipLaunchKernelGGL(finish_iter_kernel, dim3(n_int), dim3(kBlock), 0, ws, b_ints.as<IntegralDesc>(),
+    hipLaunchKernelGGL(finish_iter_kernel, dim3(n_fin), dim3(kBlock), 0, ws, fin_list ? b_finlist.as<int32_t>() : nullptr,
+                       b_ints.as<IntegralDesc>(),
                        b_chunks.as<Chunk>(), b_parts.as<double>(), b_grids.as<double>(), b_state.as<double>(),
                        b_active.as<int32_t>(), o.alpha, ctl, n_int, o.iter_out,
                        neyman ? b_alloc.as<int64_t>() : nullptr, b_nev.as<double>(), first_kept,
@@ -1723,6 +1743,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       groups[g].blocks = persistent_blocks(groups[g].kernel, (int64_t)ng[g]);
     }
     qhost.swap(nq);
+    mem_status ls = list_running(dn);
+    if (ls != MEM_OK) return ls;
     return use_graph ? capture() : MEM_OK;
   };
   // tail chunking: before iteration tail_iter the running integrals move to
@@ -1753,6 +1775,8 @@ static mem_status integrate_vegas(const mem_events* ev, const mem_process* hyp, 
       HIP_TRY(hipMemcpy(b_chunks_q.p, pc.data(), pc.size() * sizeof(Chunk), hipMemcpyHostToDevice));
     qhost.swap(nq);
     if (target_mode) running_at_build = running;
+    mem_status ls = list_running(dn);
+    if (ls != MEM_OK) return ls;
     return use_graph ? capture() : MEM_OK;
   };
   auto wall0 = std::chrono::steady_clock::now();
