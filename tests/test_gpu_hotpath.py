@@ -143,9 +143,9 @@ def test_queue_weights_tt(mem, precision, tol, event, perm):
 @pytest.mark.parametrize("event,perm", [(0, 0), (1, 1)])
 def test_queue_weights_tt_tuned_launch(mem, event, perm):
     """the benchmark's launch configuration: the shipped tuning table's
-    entry for this GPU (8192 points per chunk, one wave per SIMD for the
-    FP32 dilepton process on gfx950), every point of the first and last
-    iterations against the oracle"""
+    entry for this GPU and the FP32 dilepton process (its chunk size and
+    waves per SIMD), every point of the first and last iterations against
+    the oracle"""
     p = mem.Process(mem.MEM_TT_DILEPTON, precision=mem.MEM_FP32)
     assert p.load_tuning(TUNING_TABLE), "the shipped table has an entry for this GPU"
     say(f"tuned launch: {p.chunk_points()} points per chunk, {p.waves()} waves per SIMD")
